@@ -1,0 +1,198 @@
+"""Plain CPU oracle for the SCMF hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product library never loads it, and
+it imports nothing from the product package: the two sides implement the same
+written specification independently and share only the seeded input generators
+in ``synth``.
+
+Contents
+  * ``soma_oracle.c`` -- the method step by step in plain C (FP64 energies on
+    the FP32 state), wrapped here with ctypes;
+  * ``philox_py``     -- a second, independent Philox4x32-10 in Python integers;
+  * ``references``    -- closed forms and brute-force references that pin the
+    oracle (ideal-chain acceptance, 3-bead Boltzmann marginals, ...).
+
+Paper: arXiv:1711.03828 (SCMF simulation of soft coarse-grained polymers).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "soma_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+MOVE_LOCAL = 0
+MOVE_SMC = 1
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (no fast-math, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math",
+               "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        u32, u64, f32, f64, i32 = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float,
+                                   ctypes.c_double, ctypes.c_int)
+        L.orc_philox_batch.argtypes = [u64, P, P, P]
+        L.orc_u01.argtypes = [u32]
+        L.orc_u01.restype = f32
+        L.orc_v11.argtypes = [u32]
+        L.orc_v11.restype = f32
+        L.orc_density_hist.argtypes = [P, u32, P, P, P, u32, u32, u32, P]
+        L.orc_field_f64.argtypes = [P, u64, f64, f64, f64, P]
+        L.orc_field_f32.argtypes = [P, u64, f32, f32, f32, P]
+        L.orc_h_nb.argtypes = [P, u64, f64, f64, f64, u32]
+        L.orc_h_nb.restype = f64
+        L.orc_mc_sweep.argtypes = [P, u32, u32, u32, f32, u32, P, u32, u32, u32, u32,
+                                   f32, u64, u32, u32, u32, u32, P, i32]
+        L.orc_mc_sweep.restype = u64
+        L.orc_brick_cell_batch.argtypes = [u64, P, u32, u32, u32, P]
+        L.orc_init_chains.argtypes = [P, u32, u32, f32, u32, u32, u32, u64, u32, u32,
+                                      u32, u32]
+        L.orc_chain_observables.argtypes = [P, u32, u32, P, P, P]
+        L.orc_field_energy.argtypes = [P, u32, u32, u32, P, u32, u32, u32, u32]
+        L.orc_field_energy.restype = f64
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# --------------------------------------------------------------------------
+# Thin wrappers (argument marshalling only; all arithmetic is in the C file)
+# --------------------------------------------------------------------------
+def philox(ctr: np.ndarray, key: np.ndarray) -> np.ndarray:
+    ctr = _c(ctr, np.uint32).reshape(-1, 4)
+    key = _c(np.broadcast_to(key, (ctr.shape[0], 2)), np.uint32)
+    out = np.empty_like(ctr)
+    lib().orc_philox_batch(ctr.shape[0], _ptr(ctr), _ptr(key), _ptr(out))
+    return out
+
+
+def u01(x: int) -> float:
+    return lib().orc_u01(int(x))
+
+
+def v11(x: int) -> float:
+    return lib().orc_v11(int(x))
+
+
+@dataclass
+class Species:
+    n_chains: int
+    n: int          # beads per chain
+    n_a: int        # leading A beads
+
+
+def density_hist(pos: np.ndarray, species: list[Species], grid) -> np.ndarray:
+    """Counts as uint32 array [2, n_cells] (type A plane, type B plane)."""
+    nx, ny, nz = grid
+    pos = _c(pos, np.float32)
+    counts = np.zeros((2, nx * ny * nz), np.uint32)
+    nc = _c([s.n_chains for s in species], np.uint32)
+    nn = _c([s.n for s in species], np.uint32)
+    na = _c([s.n_a for s in species], np.uint32)
+    lib().orc_density_hist(_ptr(pos), len(species), _ptr(nc), _ptr(nn), _ptr(na),
+                           nx, ny, nz, _ptr(counts))
+    return counts
+
+
+def field_f64(counts: np.ndarray, inv_rho: float, chi_n: float, kappa_n: float) -> np.ndarray:
+    counts = _c(counts, np.uint32)
+    n_cells = counts.shape[-1]
+    om = np.empty((2, n_cells), np.float64)
+    lib().orc_field_f64(_ptr(counts), n_cells, inv_rho, chi_n, kappa_n, _ptr(om))
+    return om
+
+
+def field_f32(counts: np.ndarray, inv_rho, chi_n, kappa_n) -> np.ndarray:
+    counts = _c(counts, np.uint32)
+    n_cells = counts.shape[-1]
+    om = np.empty((2, n_cells), np.float32)
+    lib().orc_field_f32(_ptr(counts), n_cells, float(np.float32(inv_rho)),
+                        float(np.float32(chi_n)), float(np.float32(kappa_n)), _ptr(om))
+    return om
+
+
+def h_nb(counts, inv_rho, chi_n, kappa_n, n_ref) -> float:
+    counts = _c(counts, np.uint32)
+    return lib().orc_h_nb(_ptr(counts), counts.shape[-1], inv_rho, chi_n, kappa_n, n_ref)
+
+
+def mc_sweep(pos: np.ndarray, sp: Species, omega: np.ndarray, grid, *, k0, n_ref,
+             move_kind=MOVE_LOCAL, step, seed, sweep, replica=0, chain_base=0,
+             set_order=0, want_flags=False, threads=1):
+    """In-place sweep of one species' chains (pos is that species' slice).
+
+    Returns (n_accepted, flags or None)."""
+    assert pos.dtype == np.float32 and pos.flags.c_contiguous
+    assert pos.size == sp.n_chains * sp.n * 3
+    nx, ny, nz = grid
+    omega = _c(omega, np.float32)
+    assert omega.size == 2 * nx * ny * nz
+    flags = np.zeros(sp.n_chains * sp.n, np.uint8) if want_flags else None
+    acc = lib().orc_mc_sweep(_ptr(pos), sp.n_chains, sp.n, sp.n_a, float(np.float32(k0)),
+                             n_ref, _ptr(omega), nx, ny, nz, move_kind,
+                             float(np.float32(step)), seed, sweep, replica, chain_base,
+                             set_order, _ptr(flags) if flags is not None else None,
+                             threads)
+    return acc, flags
+
+
+def brick_cell(k: np.ndarray, grid) -> np.ndarray:
+    k = _c(k, np.uint64)
+    out = np.empty((k.size, 3), np.uint64)
+    lib().orc_brick_cell_batch(k.size, _ptr(k), *grid, _ptr(out))
+    return out
+
+
+def init_chains(sp: Species, grid, *, bond_sigma, seed, replica=0, chain_base=0,
+                total_chains=None, origin_mode=1) -> np.ndarray:
+    pos = np.empty((sp.n_chains * sp.n, 3), np.float32)
+    total = sp.n_chains if total_chains is None else total_chains
+    lib().orc_init_chains(_ptr(pos), sp.n_chains, sp.n, float(np.float32(bond_sigma)),
+                          *grid, seed, replica, chain_base, total, origin_mode)
+    return pos
+
+
+def chain_observables(pos: np.ndarray, n_chains: int, n: int):
+    pos = _c(pos, np.float32)
+    re2 = np.empty(n_chains)
+    rg2 = np.empty(n_chains)
+    b2 = np.empty(n_chains)
+    lib().orc_chain_observables(_ptr(pos), n_chains, n, _ptr(re2), _ptr(rg2), _ptr(b2))
+    return re2, rg2, b2
+
+
+def field_energy(pos, sp: Species, omega, grid, n_ref) -> float:
+    pos = _c(pos, np.float32)
+    omega = _c(omega, np.float32)
+    return lib().orc_field_energy(_ptr(pos), sp.n_chains, sp.n, sp.n_a, _ptr(omega),
+                                  *grid, n_ref)

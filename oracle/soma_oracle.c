@@ -1,0 +1,522 @@
+/*
+ * soma_oracle.c -- plain, slow CPU oracle for the SCMF hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code, header, table or constant generator
+ * with the HIP path: both sides implement the same written specification
+ * independently.
+ *
+ * Paper: L. Schneider and M. Mueller, "Multi-Architecture Monte-Carlo (MC)
+ * Simulation of Soft Coarse-Grained Polymeric Materials: SOft coarse grained
+ * Monte-carlo Acceleration (SOMA)", arXiv:1711.03828.
+ *
+ * Every function cites the passage it follows.  Conventions (readings of the
+ * paper that it leaves open) are the ones documented with the project:
+ *   - lengths in grid units (Delta L = 1); positions FP32, unwrapped;
+ *   - a cell is the half-open unit cube [i, i+1), the index is floor(x) mod n;
+ *   - two bead types A (0) and B (1); a linear species A_{NA} B_{N-NA};
+ *   - counts held as one uint32 plane per type, omega as one FP32 plane per
+ *     type, planes ordered A then B; a cell's linear index is (z*ny + y)*nx + x;
+ *   - energies, forces and the Metropolis / Metropolis-Hastings ratio are
+ *     evaluated in FP64 from the FP32 state.
+ *
+ * Parity status: every function below is pinned by a CPU test
+ * (tests/test_oracle_*.py) except where its header says "parity unpinned".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_TYPE_A 0u
+#define ORC_TYPE_B 1u
+
+#define ORC_MOVE_LOCAL 0u
+#define ORC_MOVE_SMC 1u
+
+#define ORC_PURPOSE_MOVE_A 0u
+#define ORC_PURPOSE_MOVE_B 1u
+#define ORC_PURPOSE_INIT 4u
+
+#define ORC_SWEEP_INIT 0xFFFFFFFFu
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10, from its published definition (Salmon, Moraes, Dror, Shaw,  */
+/* "Parallel random numbers: as easy as 1, 2, 3", SC'11).  The paper itself   */
+/* stores a PCG state per thread (Sec. 3.2.3); a stateless counter-based      */
+/* generator replaces it here so that no generator state lives in memory.     */
+/* ------------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2],
+                       uint32_t out[4]) {
+  uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+  uint32_t k0 = key_in[0], k1 = key_in[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u; /* golden ratio Weyl increment */
+      k1 += 0xBB67AE85u; /* sqrt(3)-1 Weyl increment */
+    }
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Batch form for the tests. */
+void orc_philox_batch(uint64_t n, const uint32_t *ctr, const uint32_t *key,
+                      uint32_t *out) {
+  for (uint64_t i = 0; i < n; ++i)
+    orc_philox4x32_10(ctr + 4 * i, key + 2 * i, out + 4 * i);
+}
+
+static void orc_draw(uint64_t seed, uint32_t chain, uint32_t bead,
+                     uint32_t purpose, uint32_t sweep, uint32_t replica,
+                     uint32_t out[4]) {
+  uint32_t ctr[4] = {chain, bead | (purpose << 16), sweep, replica};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  orc_philox4x32_10(ctr, key, out);
+}
+
+/* Uniform on the open interval (0,1): the top 23 bits k of a word give
+ * u = (2k+1) / 2^24, which FP32 holds exactly and which is symmetric about
+ * 1/2.  v = 2u - 1 lies in (-1,1), is exact and never 0. */
+float orc_u01(uint32_t x) { return (float)(2u * (x >> 9) + 1u) * 0x1p-24f; }
+float orc_v11(uint32_t x) {
+  return (float)((int32_t)(2u * (x >> 9) + 1u) - (int32_t)(1u << 23)) * 0x1p-23f;
+}
+
+/* Box-Muller in FP64 from two FP32 uniforms. */
+static void orc_box_muller(uint32_t w0, uint32_t w1, double *n0, double *n1) {
+  double u1 = (double)orc_u01(w0), u2 = (double)orc_u01(w1);
+  double r = sqrt(-2.0 * log(u1));
+  double ang = 2.0 * M_PI * u2;
+  *n0 = r * cos(ang);
+  *n1 = r * sin(ang);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Grid geometry: cubic collocation grid with spacing Delta L (Sec. 2.1,      */
+/* Eq. (4) and the characteristic function of a cell that follows it).        */
+/* ------------------------------------------------------------------------- */
+static int64_t orc_wrap(double x, uint32_t n) {
+  double f = floor(x);
+  int64_t i = (int64_t)f;
+  int64_t m = i % (int64_t)n;
+  if (m < 0) m += n;
+  return m;
+}
+
+static uint64_t orc_cell(const float *r, uint32_t nx, uint32_t ny,
+                         uint32_t nz) {
+  int64_t cx = orc_wrap((double)r[0], nx);
+  int64_t cy = orc_wrap((double)r[1], ny);
+  int64_t cz = orc_wrap((double)r[2], nz);
+  return ((uint64_t)cz * ny + (uint64_t)cy) * nx + (uint64_t)cx;
+}
+
+static uint64_t orc_cell_shift(const float *r, int dim, int s, uint32_t nx,
+                               uint32_t ny, uint32_t nz) {
+  int64_t c[3] = {orc_wrap((double)r[0], nx), orc_wrap((double)r[1], ny),
+                  orc_wrap((double)r[2], nz)};
+  int64_t n[3] = {nx, ny, nz};
+  c[dim] = ((c[dim] + s) % n[dim] + n[dim]) % n[dim];
+  return ((uint64_t)c[2] * ny + (uint64_t)c[1]) * nx + (uint64_t)c[0];
+}
+
+/* Bead type inside a linear species A_{NA} B_{N-NA} (Sec. 2.1: every bead
+ * has one of n_t types; here n_t = 2). */
+static uint32_t orc_type(uint32_t i, uint32_t n_a) {
+  return i < n_a ? ORC_TYPE_A : ORC_TYPE_B;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Density histogram: occupation numbers n_i(c) of every type in every cell,   */
+/* Eq. (4) with the characteristic-function assignment; counted once per MC   */
+/* step (Sec. 3.1.1).  counts[t * n_cells + c] is zeroed here.                 */
+/* ------------------------------------------------------------------------- */
+void orc_density_hist(const float *pos, uint32_t n_species,
+                      const uint32_t *n_chains, const uint32_t *n_per_chain,
+                      const uint32_t *n_a, uint32_t nx, uint32_t ny,
+                      uint32_t nz, uint32_t *counts) {
+  uint64_t n_cells = (uint64_t)nx * ny * nz;
+  memset(counts, 0, 2 * n_cells * sizeof(uint32_t));
+  uint64_t bead = 0;
+  for (uint32_t s = 0; s < n_species; ++s)
+    for (uint32_t c = 0; c < n_chains[s]; ++c)
+      for (uint32_t i = 0; i < n_per_chain[s]; ++i, ++bead) {
+        uint64_t cell = orc_cell(pos + 3 * bead, nx, ny, nz);
+        counts[orc_type(i, n_a[s]) * n_cells + cell] += 1u;
+      }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Quasi-instantaneous fields, Eq. (12), K^1 form of the interaction (Eq. (8)) */
+/* for two types:                                                              */
+/*   phi_t = n_t / (rho0 dL^3),   omega_A = kappaN (phi_A+phi_B-1) + chiN phi_B */
+/*                                omega_B = kappaN (phi_A+phi_B-1) + chiN phi_A */
+/* omega is the per-chain (xN) field; the energy of one bead is omega/N with   */
+/* N the reference chain length (Sec. 2.1, the paragraph on N-invariance).     */
+/* inv_rho = 1/(rho0 dL^3) = n_cells / n_beads.                                */
+/* ------------------------------------------------------------------------- */
+void orc_field_f64(const uint32_t *counts, uint64_t n_cells, double inv_rho,
+                   double chi_n, double kappa_n, double *omega) {
+  for (uint64_t c = 0; c < n_cells; ++c) {
+    double phi_a = counts[c] * inv_rho;
+    double phi_b = counts[n_cells + c] * inv_rho;
+    double incompress = kappa_n * (phi_a + phi_b - 1.0);
+    omega[c] = incompress + chi_n * phi_b;
+    omega[n_cells + c] = incompress + chi_n * phi_a;
+  }
+}
+
+/* The same field in a fixed FP32 operation order (products and sums rounded
+ * one by one, the chi term fused), used to hold the device result to
+ * bit equality.  Compiled with -ffp-contract=off so the order is the one
+ * written. */
+void orc_field_f32(const uint32_t *counts, uint64_t n_cells, float inv_rho,
+                   float chi_n, float kappa_n, float *omega) {
+  for (uint64_t c = 0; c < n_cells; ++c) {
+    float phi_a = (float)counts[c] * inv_rho;
+    float phi_b = (float)counts[n_cells + c] * inv_rho;
+    float s = (phi_a + phi_b) - 1.0f;
+    float t = kappa_n * s;
+    omega[c] = fmaf(chi_n, phi_b, t);
+    omega[n_cells + c] = fmaf(chi_n, phi_a, t);
+  }
+}
+
+/* Non-bonded energy on the grid, Eqs. (5), (6), (8), in units of kT:
+ *   H_nb = (rho0 dL^3 / N) sum_c [ kappaN/2 (phi_A+phi_B-1)^2 + chiN phi_A phi_B ]
+ * (the i != j sum of Eq. (8) read over unordered pairs, which is the reading
+ * that reproduces the field of Eq. (12) as its derivative). */
+double orc_h_nb(const uint32_t *counts, uint64_t n_cells, double inv_rho,
+                double chi_n, double kappa_n, uint32_t n_ref) {
+  double sum = 0.0;
+  for (uint64_t c = 0; c < n_cells; ++c) {
+    double phi_a = counts[c] * inv_rho;
+    double phi_b = counts[n_cells + c] * inv_rho;
+    double dev = phi_a + phi_b - 1.0;
+    sum += 0.5 * kappa_n * dev * dev + chi_n * phi_a * phi_b;
+  }
+  return sum / (inv_rho * (double)n_ref);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Bonded energy of one bead with its chain neighbours, Eqs. (1)-(2):          */
+/* V = (k0/2) r^2 per bond.                                                    */
+/* ------------------------------------------------------------------------- */
+static double orc_bond_energy(const float *r, const float *chain, uint32_t i,
+                              uint32_t n, double k0) {
+  double e = 0.0;
+  for (int nb = -1; nb <= 1; nb += 2) {
+    int64_t j = (int64_t)i + nb;
+    if (j < 0 || j >= (int64_t)n) continue;
+    const float *rj = chain + 3 * j;
+    for (int d = 0; d < 3; ++d) {
+      double dx = (double)r[d] - (double)rj[d];
+      e += 0.5 * k0 * dx * dx;
+    }
+  }
+  return e;
+}
+
+/* Force on a bead used by the force-biased proposal (Sec. 2.2, smart MC):
+ * the bonded force -dH_b/dr plus the grid-field force -(1/N) grad omega_t,
+ * with the gradient taken as the central difference of omega between the two
+ * neighbouring cells of the cell that holds r (piecewise constant in a cell). */
+static void orc_force(const float *r, const float *chain, uint32_t i,
+                      uint32_t n, double k0, const float *omega_t,
+                      uint32_t nx, uint32_t ny, uint32_t nz, uint32_t n_ref,
+                      double f[3]) {
+  f[0] = f[1] = f[2] = 0.0;
+  for (int nb = -1; nb <= 1; nb += 2) {
+    int64_t j = (int64_t)i + nb;
+    if (j < 0 || j >= (int64_t)n) continue;
+    const float *rj = chain + 3 * j;
+    for (int d = 0; d < 3; ++d) f[d] += k0 * ((double)rj[d] - (double)r[d]);
+  }
+  if (omega_t) {
+    for (int d = 0; d < 3; ++d) {
+      double up = omega_t[orc_cell_shift(r, d, +1, nx, ny, nz)];
+      double dn = omega_t[orc_cell_shift(r, d, -1, nx, ny, nz)];
+      f[d] -= 0.5 * (up - dn) / (double)n_ref;
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* One MC sweep of one linear species with the fields held fixed (stage 2 of   */
+/* the SCMF cycle, Sec. 2.2).                                                  */
+/*                                                                             */
+/* Order of attempts: the "SET" scheme of Sec. 3.1.2 -- for a linear chain the */
+/* even and the odd beads are the two independent sets; per chain and sweep    */
+/* the order of the two sets is random (bit 0 of the first word of bead 0's   */
+/* move draw), or even-first when set_order == 1.  Inside a set the moves do  */
+/* not interact, so doing them one after another equals doing them at once.   */
+/*                                                                             */
+/* LOCAL (Sec. 2.2, move (i)): trial displacement uniform in [-a,a] per        */
+/* Cartesian direction, r' = fmaf(a, v, r) in FP32; Metropolis acceptance      */
+/* min(1, exp(-dE)) with dE = dE_bond + (omega_t(c') - omega_t(c))/N           */
+/* (the non-bonded change of Eq. (15), per bead).                              */
+/*                                                                             */
+/* SMC (Sec. 2.2, move (ii), force-biased): r' = r + A F(r) + sqrt(2A) xi,     */
+/* xi ~ N(0,1)^3, accepted by Metropolis-Hastings with the ratio of the        */
+/* Gaussian proposal densities q(r|r') / q(r'|r).                              */
+/*                                                                             */
+/* Random numbers: Philox4x32-10, key = seed, counter = (chain_base + chain,   */
+/* bead | purpose << 16, sweep, replica).  LOCAL uses one block (words 0-2:    */
+/* displacement, word 3: acceptance).  SMC uses block A (purpose 0) for four   */
+/* normals and block B (purpose 1), word 0, for acceptance.                    */
+/*                                                                             */
+/* accept_flags (n_chains * N bytes, may be NULL) records 1 for an accepted    */
+/* move.  Returns the number of accepted moves.                                */
+/* ------------------------------------------------------------------------- */
+static int orc_move_local(float *chain, uint32_t c_id, uint32_t i, uint32_t n,
+                          uint32_t n_a, double k0, const float *omega,
+                          uint64_t n_cells, uint32_t nx, uint32_t ny,
+                          uint32_t nz, uint32_t n_ref, float a, uint64_t seed,
+                          uint32_t sweep, uint32_t replica) {
+  uint32_t w[4];
+  orc_draw(seed, c_id, i, ORC_PURPOSE_MOVE_A, sweep, replica, w);
+  float *r = chain + 3 * i;
+  float trial[3];
+  for (int d = 0; d < 3; ++d) trial[d] = fmaf(a, orc_v11(w[d]), r[d]);
+  double d_bond = orc_bond_energy(trial, chain, i, n, k0) -
+                  orc_bond_energy(r, chain, i, n, k0);
+  const float *om = omega + (uint64_t)orc_type(i, n_a) * n_cells;
+  double d_field = ((double)om[orc_cell(trial, nx, ny, nz)] -
+                    (double)om[orc_cell(r, nx, ny, nz)]) /
+                   (double)n_ref;
+  double d_e = d_bond + d_field;
+  double u = (double)orc_u01(w[3]);
+  int accept = (d_e <= 0.0) || (u < exp(-d_e));
+  if (accept) memcpy(r, trial, sizeof trial);
+  return accept;
+}
+
+static int orc_move_smc(float *chain, uint32_t c_id, uint32_t i, uint32_t n,
+                        uint32_t n_a, double k0, const float *omega,
+                        uint64_t n_cells, uint32_t nx, uint32_t ny,
+                        uint32_t nz, uint32_t n_ref, float a_smc,
+                        uint64_t seed, uint32_t sweep, uint32_t replica) {
+  uint32_t wa[4], wb[4];
+  orc_draw(seed, c_id, i, ORC_PURPOSE_MOVE_A, sweep, replica, wa);
+  orc_draw(seed, c_id, i, ORC_PURPOSE_MOVE_B, sweep, replica, wb);
+  double xi[4];
+  orc_box_muller(wa[0], wa[1], &xi[0], &xi[1]);
+  orc_box_muller(wa[2], wa[3], &xi[2], &xi[3]);
+  const float *om = omega + (uint64_t)orc_type(i, n_a) * n_cells;
+  double A = (double)a_smc;
+  float *r = chain + 3 * i;
+  double f_old[3], f_new[3];
+  orc_force(r, chain, i, n, k0, om, nx, ny, nz, n_ref, f_old);
+  float trial[3];
+  for (int d = 0; d < 3; ++d)
+    trial[d] = (float)((double)r[d] + A * f_old[d] + sqrt(2.0 * A) * xi[d]);
+  orc_force(trial, chain, i, n, k0, om, nx, ny, nz, n_ref, f_new);
+  double log_fwd = 0.0, log_rev = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    double x_f = (double)trial[d] - (double)r[d] - A * f_old[d];
+    double x_r = (double)r[d] - (double)trial[d] - A * f_new[d];
+    log_fwd -= x_f * x_f / (4.0 * A);
+    log_rev -= x_r * x_r / (4.0 * A);
+  }
+  double d_bond = orc_bond_energy(trial, chain, i, n, k0) -
+                  orc_bond_energy(r, chain, i, n, k0);
+  double d_field = ((double)om[orc_cell(trial, nx, ny, nz)] -
+                    (double)om[orc_cell(r, nx, ny, nz)]) /
+                   (double)n_ref;
+  double log_ratio = -(d_bond + d_field) + log_rev - log_fwd;
+  double u = (double)orc_u01(wb[0]);
+  int accept = (log_ratio >= 0.0) || (u < exp(log_ratio));
+  if (accept) memcpy(r, trial, sizeof trial);
+  return accept;
+}
+
+uint64_t orc_mc_sweep(float *pos, uint32_t n_chains, uint32_t n,
+                      uint32_t n_a, float k0, uint32_t n_ref,
+                      const float *omega, uint32_t nx, uint32_t ny,
+                      uint32_t nz, uint32_t move_kind, float step,
+                      uint64_t seed, uint32_t sweep, uint32_t replica,
+                      uint32_t chain_base, uint32_t set_order,
+                      uint8_t *accept_flags, int n_threads) {
+  uint64_t n_cells = (uint64_t)nx * ny * nz;
+  uint64_t accepted = 0;
+  (void)n_threads;
+#pragma omp parallel for schedule(static) reduction(+ : accepted) num_threads(n_threads > 0 ? n_threads : 1)
+  for (int64_t c = 0; c < (int64_t)n_chains; ++c) {
+    float *chain = pos + (uint64_t)c * n * 3;
+    uint32_t c_id = chain_base + (uint32_t)c;
+    uint32_t first = 0;
+    if (set_order == 0) {
+      uint32_t w[4];
+      orc_draw(seed, c_id, 0, ORC_PURPOSE_MOVE_A, sweep, replica, w);
+      first = w[0] & 1u;
+    }
+    for (uint32_t pass = 0; pass < 2; ++pass) {
+      uint32_t parity = pass == 0 ? first : 1u - first;
+      for (uint32_t i = parity; i < n; i += 2) {
+        int acc;
+        if (move_kind == ORC_MOVE_SMC)
+          acc = orc_move_smc(chain, c_id, i, n, n_a, (double)k0, omega,
+                             n_cells, nx, ny, nz, n_ref, step, seed, sweep,
+                             replica);
+        else
+          acc = orc_move_local(chain, c_id, i, n, n_a, (double)k0, omega,
+                               n_cells, nx, ny, nz, n_ref, step, seed, sweep,
+                               replica);
+        accepted += (uint64_t)acc;
+        if (accept_flags) accept_flags[(uint64_t)c * n + i] = (uint8_t)acc;
+      }
+    }
+  }
+  return accepted;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Initial configuration (the paper does not prescribe one): every chain is a */
+/* Gaussian random walk -- the ideal chain of the harmonic bond model, bond   */
+/* components i.i.d. N(0, 1/k0), so that b0^2 = 3/k0 (Sec. 2.1, after Eq. (9)) */
+/* -- started from an origin uniform in the box.                               */
+/*                                                                             */
+/* origin_mode 0: origin i.i.d. uniform in the box, r0_d = u_d * n_d.          */
+/* origin_mode 1: stratified uniform -- chain g of G falls in the cell of rank */
+/*   k = floor(n_cells (g + u_3) / G) along the bricked cell order below, at a */
+/*   uniform point of that cell; neighbouring chain numbers are then           */
+/*   neighbours in space.                                                      */
+/* Bricked order: bricks of 8 cells per side (the last brick along a direction */
+/* takes the remainder), bricks row-major in (z, y, x), cells row-major in     */
+/* (z, y, x) inside a brick.                                                   */
+/* Draws: block (g, j | 4 << 16, 0xFFFFFFFF, replica) for bead j; bead 0 gives  */
+/* the origin, bead j >= 1 the bond j via Box-Muller (words 0,1 -> x,y;        */
+/* words 2,3 -> z from the cosine branch).                                     */
+/* ------------------------------------------------------------------------- */
+static void orc_brick_cell(uint64_t k, uint32_t nx, uint32_t ny, uint32_t nz,
+                           uint64_t out[3]) {
+  const uint64_t B = 8;
+  uint64_t nbx = nx / B ? nx / B : 1, nby = ny / B ? ny / B : 1,
+           nbz = nz / B ? nz / B : 1;
+#define ORC_W(b, nb, n) ((b) + 1 < (nb) ? B : (n) - B * ((nb) - 1))
+  uint64_t slab = B * (uint64_t)nx * ny;
+  uint64_t bz = k / slab;
+  if (bz > nbz - 1) bz = nbz - 1;
+  k -= bz * slab;
+  uint64_t wz = ORC_W(bz, nbz, nz);
+  uint64_t row = wz * B * nx;
+  uint64_t by = k / row;
+  if (by > nby - 1) by = nby - 1;
+  k -= by * row;
+  uint64_t wy = ORC_W(by, nby, ny);
+  uint64_t brick = wz * wy * B;
+  uint64_t bx = k / brick;
+  if (bx > nbx - 1) bx = nbx - 1;
+  k -= bx * brick;
+  uint64_t wx = ORC_W(bx, nbx, nx);
+#undef ORC_W
+  uint64_t z = k / (wy * wx);
+  uint64_t rem = k % (wy * wx);
+  out[0] = bx * B + rem % wx;
+  out[1] = by * B + rem / wx;
+  out[2] = bz * B + z;
+}
+
+void orc_brick_cell_batch(uint64_t n, const uint64_t *k, uint32_t nx,
+                          uint32_t ny, uint32_t nz, uint64_t *out) {
+  for (uint64_t i = 0; i < n; ++i) orc_brick_cell(k[i], nx, ny, nz, out + 3 * i);
+}
+
+void orc_init_chains(float *pos, uint32_t n_chains, uint32_t n,
+                     float bond_sigma, uint32_t nx, uint32_t ny, uint32_t nz,
+                     uint64_t seed, uint32_t replica, uint32_t chain_base,
+                     uint32_t total_chains, uint32_t origin_mode) {
+  uint64_t n_cells = (uint64_t)nx * ny * nz;
+  for (uint32_t c = 0; c < n_chains; ++c) {
+    uint32_t g = chain_base + c;
+    float *chain = pos + (uint64_t)c * n * 3;
+    uint32_t w[4];
+    orc_draw(seed, g, 0, ORC_PURPOSE_INIT, ORC_SWEEP_INIT, replica, w);
+    if (origin_mode == 1) {
+      /* k = floor(n_cells * (g + (2m+1)/2^24) / G), exact in 128-bit ints */
+      unsigned __int128 num =
+          (unsigned __int128)n_cells *
+          (((unsigned __int128)g << 24) + 2u * (w[3] >> 9) + 1u);
+      unsigned __int128 den = (unsigned __int128)total_chains << 24;
+      uint64_t k = (uint64_t)(num / den);
+      uint64_t cell[3];
+      orc_brick_cell(k, nx, ny, nz, cell);
+      for (int d = 0; d < 3; ++d) chain[d] = (float)cell[d] + orc_u01(w[d]);
+    } else {
+      float dims[3] = {(float)nx, (float)ny, (float)nz};
+      for (int d = 0; d < 3; ++d) chain[d] = orc_u01(w[d]) * dims[d];
+    }
+    for (uint32_t j = 1; j < n; ++j) {
+      orc_draw(seed, g, j, ORC_PURPOSE_INIT, ORC_SWEEP_INIT, replica, w);
+      double xi[4];
+      orc_box_muller(w[0], w[1], &xi[0], &xi[1]);
+      orc_box_muller(w[2], w[3], &xi[2], &xi[3]);
+      for (int d = 0; d < 3; ++d)
+        chain[3 * j + d] =
+            (float)((double)chain[3 * (j - 1) + d] + (double)bond_sigma * xi[d]);
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Chain observables (Sec. 5.5 uses <Re^2>; Rg and the bond length follow the  */
+/* same ideal-chain definitions of Sec. 2.1): per chain, with unwrapped         */
+/* positions,                                                                  */
+/*   Re^2 = |r_{N-1} - r_0|^2,  Rg^2 = (1/N) sum_i |r_i - r_cm|^2,              */
+/*   b2   = sum over bonds |r_{i+1} - r_i|^2,   E_b = (k0/2) b2.               */
+/* Outputs are per-chain FP64 arrays (any may be NULL).                         */
+/* ------------------------------------------------------------------------- */
+void orc_chain_observables(const float *pos, uint32_t n_chains, uint32_t n,
+                           double *re2, double *rg2, double *b2) {
+  for (uint32_t c = 0; c < n_chains; ++c) {
+    const float *ch = pos + (uint64_t)c * n * 3;
+    double cm[3] = {0, 0, 0};
+    for (uint32_t i = 0; i < n; ++i)
+      for (int d = 0; d < 3; ++d) cm[d] += ch[3 * i + d];
+    for (int d = 0; d < 3; ++d) cm[d] /= n;
+    double e = 0, g = 0, b = 0;
+    for (int d = 0; d < 3; ++d) {
+      double x = (double)ch[3 * (n - 1) + d] - (double)ch[d];
+      e += x * x;
+    }
+    for (uint32_t i = 0; i < n; ++i)
+      for (int d = 0; d < 3; ++d) {
+        double x = (double)ch[3 * i + d] - cm[d];
+        g += x * x;
+      }
+    for (uint32_t i = 0; i + 1 < n; ++i)
+      for (int d = 0; d < 3; ++d) {
+        double x = (double)ch[3 * (i + 1) + d] - (double)ch[3 * i + d];
+        b += x * x;
+      }
+    if (re2) re2[c] = e;
+    if (rg2) rg2[c] = g / n;
+    if (b2) b2[c] = b;
+  }
+}
+
+/* Field energy of the beads in their cells, the right-hand side of Eq. (13)
+ * divided by N: sum_j omega_type(j)(c_j) / N. */
+double orc_field_energy(const float *pos, uint32_t n_chains, uint32_t n,
+                        uint32_t n_a, const float *omega, uint32_t nx,
+                        uint32_t ny, uint32_t nz, uint32_t n_ref) {
+  uint64_t n_cells = (uint64_t)nx * ny * nz;
+  double e = 0.0;
+  for (uint32_t c = 0; c < n_chains; ++c)
+    for (uint32_t i = 0; i < n; ++i) {
+      const float *r = pos + ((uint64_t)c * n + i) * 3;
+      e += (double)omega[(uint64_t)orc_type(i, n_a) * n_cells +
+                         orc_cell(r, nx, ny, nz)];
+    }
+  return e / (double)n_ref;
+}

@@ -1,0 +1,111 @@
+"""Seeded synthetic inputs shared by the device path's tests and the oracle.
+
+This module draws random inputs and describes workloads; it holds none of the
+method's arithmetic (no energies, fields, moves or histograms).  Both sides of
+a parity test start from the arrays made here.
+
+Workloads follow the melts of arXiv:1711.03828 (Secs. 5.1-5.6): linear AB
+diblock chains, grid spacing Re0/6, bonds Gaussian with the ideal-chain
+statistics of the harmonic model.  No dataset is involved anywhere.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+MASTER_SEED = 20171110
+
+
+@dataclass(frozen=True)
+class SpeciesSpec:
+    n_chains: int
+    n: int        # beads per chain
+    n_a: int      # leading A beads
+
+
+@dataclass(frozen=True)
+class Workload:
+    """A melt: box in grid cells, Re0 in cells, interaction strengths, moves."""
+    name: str
+    grid: tuple            # (nx, ny, nz) cells
+    species: tuple         # SpeciesSpec, ...
+    re_cells: float        # Re0 in grid units
+    n_ref: int             # reference chain length N of chiN, kappaN
+    chi_n: float
+    kappa_n: float
+    count_width: int       # 16 or 32 bit per-type occupation counts
+    a_frac: float = 0.1    # local move half-width in units of b0 = Re0/sqrt(Nref-1)
+    smc_frac: float = 0.05 # smart-MC step A in units of Re0^2 / Nref
+    sweeps: int = 100
+    seed: int = MASTER_SEED
+
+    @property
+    def n_cells(self):
+        nx, ny, nz = self.grid
+        return nx * ny * nz
+
+    @property
+    def n_beads(self):
+        return sum(s.n_chains * s.n for s in self.species)
+
+    @property
+    def n_chains(self):
+        return sum(s.n_chains for s in self.species)
+
+
+# Plain SCMF, AB diblock melt: 1024 A16B16 chains, 4x4x4 Re0 box, 24^3 grid.
+C1_SMALL = Workload("diblock_1k_N32_grid24", (24, 24, 24),
+                    (SpeciesSpec(1024, 32, 16),), 6.0, 32, 30.0, 50.0, 16, sweeps=100)
+# Plain SCMF at scale: 4,194,304 A16B16 chains (134M beads), 64x64x32 Re0 box,
+# 384x384x192 grid, u32 counts, local plus force-biased moves, 1000 sweeps.
+C2_LARGE = Workload("diblock_4M_N32_grid384x384x192", (384, 384, 192),
+                    (SpeciesSpec(4194304, 32, 16),), 6.0, 32, 20.0, 50.0, 32, sweeps=1000)
+# Single melt of the learned-proposal study: 262,144 A16B16 chains, 96^3 grid.
+C4_MEDIUM = Workload("diblock_256k_N32_grid96", (96, 96, 96),
+                     (SpeciesSpec(262144, 32, 16),), 6.0, 32, 25.0, 50.0, 16, sweeps=100)
+
+WORKLOADS = {w.name: w for w in (C1_SMALL, C2_LARGE, C4_MEDIUM)}
+
+
+def scaled(w: Workload, n_chains: int, grid) -> Workload:
+    """Same chemistry, different size (for tests)."""
+    sp = tuple(SpeciesSpec(n_chains, s.n, s.n_a) for s in w.species)
+    return Workload(w.name + f"_scaled{n_chains}", tuple(grid), sp, w.re_cells, w.n_ref,
+                    w.chi_n, w.kappa_n, w.count_width, w.a_frac, w.smc_frac, w.sweeps,
+                    w.seed)
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def gaussian_walks(seed: int, n_chains: int, n: int, grid, bond_sigma: float,
+                   origin_spread=None) -> np.ndarray:
+    """Chains as random walks with N(0, bond_sigma^2) bond components and origins
+    uniform in the box (or in [0, origin_spread) per axis); float32 [n_chains*n, 3],
+    chain-major, unwrapped."""
+    g = rng(seed)
+    box = np.asarray(grid if origin_spread is None else origin_spread, np.float64)
+    origin = g.random((n_chains, 1, 3)) * box
+    bonds = g.standard_normal((n_chains, n - 1, 3)) * bond_sigma
+    walk = np.concatenate([np.zeros((n_chains, 1, 3)), np.cumsum(bonds, axis=1)], axis=1)
+    return (origin + walk).astype(np.float32).reshape(-1, 3)
+
+
+def uniform_field(seed: int, n_cells: int, lo: float, hi: float) -> np.ndarray:
+    """Random per-type fields, float32 [2, n_cells]."""
+    return rng(seed).uniform(lo, hi, size=(2, n_cells)).astype(np.float32)
+
+
+def boundary_positions(grid) -> np.ndarray:
+    """Hand-picked positions on and near cell faces, box faces and negative
+    coordinates (float32 [k, 3])."""
+    nx, ny, nz = grid
+    eps = np.float32(1e-6)
+    vals_x = [0.0, 0.5, 1.0, -0.0, -0.5, -1.0, nx, nx - eps, nx + 0.25, -nx, -nx - 0.5,
+              2.0 * nx + 1.0, 3.999999, 1e4 + 0.5, -1e4 - 0.25]
+    out = []
+    for i, x in enumerate(vals_x):
+        out.append([x, (x * 0.5 + i) % (2 * ny) - ny / 2, -x + 0.25 * i])
+    return np.asarray(out, np.float32)
