@@ -1,0 +1,201 @@
+/*
+ * soma.h -- C ABI of the MI355X (gfx950) SCMF hot path.
+ *
+ * The library advances soft, coarse-grained polymer melts with the
+ * single-chain-in-mean-field (SCMF) Monte Carlo method of
+ *   L. Schneider, M. Mueller, "Multi-Architecture Monte-Carlo (MC) Simulation
+ *   of Soft Coarse-Grained Polymeric Materials: SOMA", arXiv:1711.03828.
+ * One SCMF cycle (Sec. 2.2) is: MC moves of every bead with the fields held
+ * fixed (stage 2), then the per-type occupation histogram of the grid cells
+ * (Eq. (4)) and the quasi-instantaneous fields computed from it (Eq. (12),
+ * K^1 form of Eq. (8); stage 1).
+ *
+ * Conventions shared by every call
+ *   - Lengths are in grid units (cell side Delta L = 1).  The box has
+ *     nx*ny*nz cells and is periodic; a cell is the half-open unit cube and a
+ *     position x belongs to cell floor(x) mod n along each axis.  The linear
+ *     cell index is (z*ny + y)*nx + x.
+ *   - Two bead types, A (0) and B (1).  A species is a linear chain of n beads
+ *     whose first n_a beads are A; bead i is bonded to i-1 and i+1 (Eqs. (1),
+ *     (2), harmonic springs of constant k0).
+ *   - Positions: FP32 [n_beads][3], unwrapped, chain-major; species follow
+ *     each other in the order of soma_config.species.
+ *   - Counts: per cell one packed word holding both types: with
+ *     count_width 16 a uint32 (A in bits 0-15, B in bits 16-31); with
+ *     count_width 32 a uint64 (A in bits 0-31, B in bits 32-63).
+ *   - Fields omega: FP32 planes [2][n_cells] (A plane, then B plane), in
+ *     units of kT per chain; a bead of type t in cell c has energy
+ *     omega_t(c) / n_ref (Eq. (13)).
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = seed,
+ *     counter = (global chain index, bead | purpose << 16, sweep, replica).
+ *     Results therefore depend only on the configuration, the seed and the
+ *     sweep index -- not on launch geometry.
+ *
+ * Memory ownership: the caller owns every device buffer (positions, counts,
+ * omega, workspace) and keeps it alive for the life of the handle.  The
+ * library never allocates or frees device memory.  The handle owns only host
+ * memory.
+ *
+ * Streams: every call takes a HIP stream (hipStream_t passed as void*; NULL is
+ * the default stream) and only enqueues work on it, except where a call is
+ * marked BLOCKING.
+ *
+ * Errors: every call returns a soma_status; on failure soma_last_error()
+ * returns a message for the calling thread.  No call aborts or throws.  A
+ * handle must not be used from two threads at once.
+ */
+#ifndef SOMA_H
+#define SOMA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum soma_status {
+  SOMA_OK = 0,
+  SOMA_E_INVAL = -1,        /* invalid argument or configuration */
+  SOMA_E_HIP = -2,          /* a HIP runtime call or kernel launch failed */
+  SOMA_E_SIZE = -3,         /* a caller buffer is smaller than required */
+  SOMA_E_UNSUPPORTED = -4,  /* valid request this build does not support */
+  SOMA_E_DEVICE_FLAG = -5   /* a kernel raised the device error word */
+} soma_status;
+
+/* Move kinds (Sec. 2.2). */
+#define SOMA_MOVE_LOCAL 0u /* uniform trial displacement in [-a,a]^3, Metropolis */
+#define SOMA_MOVE_SMC 1u   /* force-biased (smart MC) proposal, Metropolis-Hastings */
+
+/* Device error word bits (returned by soma_check / soma_observables). */
+#define SOMA_FLAG_POSITION 1u /* a position became non-finite or |x| >= 2^22 */
+
+#define SOMA_MAX_SPECIES 8
+#define SOMA_MAX_BEADS_PER_CHAIN 128
+
+typedef struct soma_species {
+  uint32_t n_chains; /* chains of this species */
+  uint32_t n;        /* beads per chain, 1..SOMA_MAX_BEADS_PER_CHAIN */
+  uint32_t n_a;      /* leading beads of type A, 0..n */
+  float k0;          /* harmonic bond constant, kT per cell^2 (Eq. (2)) */
+} soma_species;
+
+typedef struct soma_config {
+  uint32_t nx, ny, nz;   /* cells per axis */
+  uint32_t n_species;    /* 1..SOMA_MAX_SPECIES */
+  soma_species species[SOMA_MAX_SPECIES];
+  uint32_t n_ref;        /* reference chain length N of omega/N, chiN, kappaN */
+  float chi_n;           /* chi_AB N (Eq. (8)) */
+  float kappa_n;         /* kappa N (Eq. (6)) */
+  float local_a;         /* half-width a of the local move, cells */
+  float smc_a;           /* step A of the smart-MC move, cells^2: r' = r + A F + sqrt(2A) xi */
+  uint64_t seed;         /* Philox key */
+  uint32_t replica;      /* fourth Philox counter word */
+  uint32_t count_width;  /* 16 or 32 (bits per type per cell) */
+  uint32_t set_order;    /* 0: random even/odd order per chain and sweep; 1: even first */
+  uint32_t origin_mode;  /* initial origins: 0 i.i.d. uniform, 1 stratified in bricked order */
+} soma_config;
+
+typedef struct soma_buffers {
+  float *pos;          uint64_t pos_bytes;       /* >= 12 * n_beads */
+  void *counts;        uint64_t counts_bytes;    /* >= (4 or 8) * n_cells */
+  float *omega;        uint64_t omega_bytes;     /* >= 8 * n_cells */
+  void *workspace;     uint64_t workspace_bytes; /* >= soma_workspace_size() */
+} soma_buffers;
+
+typedef struct soma_obs {
+  uint64_t sweeps;        /* sweeps done since init (the next sweep index) */
+  uint64_t n_beads, n_chains;
+  uint64_t count_a;       /* sum of A counts of the last field update */
+  uint64_t count_b;       /* sum of B counts of the last field update */
+  uint64_t accepted[2];   /* accepted moves per move kind since init */
+  uint64_t attempted[2];  /* attempted moves per move kind since init */
+  double re2_sum;         /* sum over chains of |r_{N-1} - r_0|^2 */
+  double rg2_sum;         /* sum over chains of (1/N) sum_i |r_i - r_cm|^2 */
+  double b2_sum;          /* sum over bonds of |r_{i+1} - r_i|^2 */
+  double e_bond;          /* H_b / kT, Eqs. (1)-(2) */
+  double e_field;         /* sum_j omega_type(j)(c_j) / n_ref at the current fields, Eq. (13) */
+  double h_nb;            /* H_nb / kT of the last field update, Eqs. (5), (6), (8) */
+  uint32_t error_flags;   /* device error word (SOMA_FLAG_*) */
+  uint32_t counts_conserved; /* 1 if count_a/count_b equal the bead totals per type */
+} soma_obs;
+
+typedef struct soma_system soma_system;
+
+/* Sizes in bytes of the caller buffers for a configuration.
+ * Returns SOMA_E_INVAL for an invalid configuration.  Any output may be NULL. */
+int32_t soma_buffer_sizes(const soma_config *cfg, uint64_t *pos_bytes,
+                          uint64_t *counts_bytes, uint64_t *omega_bytes,
+                          uint64_t *workspace_bytes);
+
+/* Workspace bytes (acceptance slots, reduction partials, error word). */
+int32_t soma_workspace_size(const soma_config *cfg, uint64_t *bytes);
+
+/* Creates a handle for the configuration and the caller buffers.
+ * If init_positions != 0, fills buf->pos with Gaussian-walk chains: bonds
+ * N(0, 1/k0) per component (the ideal chain of Eq. (2), b0^2 = 3/k0, Sec. 2.1)
+ * from origins placed per origin_mode; otherwise buf->pos must already hold
+ * positions.  Then computes the histogram and the fields once (stage 1 of
+ * Sec. 2.2), so that omega matches the positions; counts are left zero.
+ * Asynchronous on `stream` except for argument validation.  On success *out
+ * receives the handle. */
+int32_t soma_init_system(const soma_config *cfg, const soma_buffers *buf,
+                         uint32_t init_positions, void *stream,
+                         soma_system **out);
+
+/* Performs n_sweeps MC sweeps (stage 2 of Sec. 2.2) with the fields held
+ * fixed: each sweep attempts one move of every bead, the even and the odd
+ * beads of a chain forming the two independent sets of Sec. 3.1.2, moved set
+ * after set in a random order per chain and sweep.  move_kind is
+ * SOMA_MOVE_LOCAL or SOMA_MOVE_SMC.  The last sweep of the call also builds
+ * the occupation histogram of the final positions into buf->counts (fused;
+ * counts are cleared first if they still hold an older histogram).
+ * Asynchronous. */
+int32_t soma_mc_sweep(soma_system *sys, uint32_t n_sweeps, uint32_t move_kind,
+                      void *stream);
+
+/* Stage 1 of Sec. 2.2: omega from the current histogram (Eq. (12)), counts
+ * cleared to zero in the same pass, and the count sums and H_nb of this
+ * histogram kept for soma_observables.  If no histogram is pending (no
+ * sweep since the last update) it is first rebuilt from the positions.
+ * Asynchronous. */
+int32_t soma_update_fields(soma_system *sys, void *stream);
+
+/* BLOCKING.  Chain observables in FP64 (Re^2, Rg^2, bond lengths, bond and
+ * field energies), acceptance counters, the count sums and H_nb of the last
+ * field update, and the device error word.  Synchronizes `stream`.
+ * Returns SOMA_E_DEVICE_FLAG (with *out filled) if the error word is set. */
+int32_t soma_observables(soma_system *sys, soma_obs *out, void *stream);
+
+/* BLOCKING.  Reads the device error word; SOMA_E_DEVICE_FLAG if set. */
+int32_t soma_check(soma_system *sys, uint32_t *flags, void *stream);
+
+/* Sweep index of the next sweep (Philox counter word 2); set it to resume a
+ * run from saved positions bit-exactly. */
+int32_t soma_get_sweep(const soma_system *sys, uint64_t *sweep);
+int32_t soma_set_sweep(soma_system *sys, uint64_t sweep);
+
+/* Stand-alone occupation histogram (Eq. (4)) of `pos` into `counts`
+ * (cleared first), in the packed layout of cfg->count_width.  Both are device
+ * pointers sized as by soma_buffer_sizes.  Asynchronous. */
+int32_t soma_density_hist(const soma_config *cfg, const float *pos,
+                           void *counts, void *stream);
+
+/* Stand-alone fields (Eq. (12)) from packed `counts` into `omega` without
+ * clearing the counts.  inv_rho = n_cells / n_beads.  Asynchronous. */
+int32_t soma_field_from_counts(const soma_config *cfg, const void *counts,
+                               float *omega, void *stream);
+
+/* Stand-alone initial positions as in soma_init_system.  Asynchronous. */
+int32_t soma_init_positions(const soma_config *cfg, float *pos, void *stream);
+
+/* Releases the handle (host memory only). */
+void soma_destroy(soma_system *sys);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *soma_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SOMA_H */

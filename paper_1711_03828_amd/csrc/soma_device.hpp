@@ -1,0 +1,115 @@
+// soma_device.hpp -- device helpers of the SCMF hot path for gfx950:
+// counter-based random numbers, uniform conversions, periodic cell indices.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace soma {
+
+constexpr uint32_t kPurposeMoveA = 0u;
+constexpr uint32_t kPurposeMoveB = 1u;
+constexpr uint32_t kPurposeInit = 4u;
+constexpr uint32_t kSweepInit = 0xFFFFFFFFu;
+constexpr uint32_t kAccSlots = 1024u;  // acceptance counter slots per move kind
+constexpr float kMaxCoord = 4194304.0f;  // 2^22: cell arithmetic stays exact below
+
+struct Rand4 {
+  uint32_t x, y, z, w;
+};
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  The paper keeps a PCG
+// state per thread in memory (Sec. 3.2.3); a counter-based generator needs no
+// state at all, so the draws cost ALU work only.  The key schedule is
+// wave-uniform and lands in scalar registers.
+__device__ __forceinline__ Rand4 philox(uint32_t c0, uint32_t c1, uint32_t c2,
+                                        uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = c0 * 0xD2511F53u;
+    const uint32_t hi0 = __umulhi(c0, 0xD2511F53u);
+    const uint32_t lo1 = c2 * 0xCD9E8D57u;
+    const uint32_t hi1 = __umulhi(c2, 0xCD9E8D57u);
+    c0 = hi1 ^ c1 ^ k0;
+    c1 = lo1;
+    c2 = hi0 ^ c3 ^ k1;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return {c0, c1, c2, c3};
+}
+
+// u = (2k+1) 2^-24 from the top 23 bits k: exact in FP32, in (0,1), symmetric.
+__device__ __forceinline__ float uniform01(uint32_t x) {
+  return (float)(2u * (x >> 9) + 1u) * 0x1p-24f;
+}
+// v = 2u - 1 in (-1,1), exact (one rounding of an exact value).
+__device__ __forceinline__ float uniform11(uint32_t x) {
+  return fmaf(2.0f, uniform01(x), -1.0f);
+}
+
+// Two standard normals from two words (Box-Muller).
+__device__ __forceinline__ void box_muller(uint32_t w0, uint32_t w1, float &n0,
+                                           float &n1) {
+  const float rad = sqrtf(-2.0f * logf(uniform01(w0)));
+  float s, c;
+  sincospif(2.0f * uniform01(w1), &s, &c);
+  n0 = rad * c;
+  n1 = rad * s;
+}
+
+// floor(x) mod n, exact for |x| < 2^22; NaN and larger values are clamped
+// first so the index is always inside [0, n).
+__device__ __forceinline__ uint32_t wrap_cell(float x, int n, float inv_n) {
+  float f = floorf(x);
+  f = fminf(fmaxf(f, -kMaxCoord), kMaxCoord);
+  const int i = (int)f;
+  const int q = (int)floorf(f * inv_n);  // floor(i/n) up to +-1
+  int r = i - q * n;
+  r = r >= n ? r - n : r;
+  r = r < 0 ? r + n : r;
+  return (uint32_t)r;
+}
+
+struct Grid {
+  int nx, ny, nz;
+  float inv_nx, inv_ny, inv_nz;
+  uint32_t n_cells;
+};
+
+__device__ __forceinline__ void cell3(const Grid &g, float x, float y, float z,
+                                      uint32_t &cx, uint32_t &cy,
+                                      uint32_t &cz) {
+  cx = wrap_cell(x, g.nx, g.inv_nx);
+  cy = wrap_cell(y, g.ny, g.inv_ny);
+  cz = wrap_cell(z, g.nz, g.inv_nz);
+}
+
+__device__ __forceinline__ uint32_t cell_index(const Grid &g, uint32_t cx,
+                                               uint32_t cy, uint32_t cz) {
+  return (cz * (uint32_t)g.ny + cy) * (uint32_t)g.nx + cx;
+}
+
+__device__ __forceinline__ uint32_t cell_of(const Grid &g, float x, float y,
+                                            float z) {
+  uint32_t cx, cy, cz;
+  cell3(g, x, y, z, cx, cy, cz);
+  return cell_index(g, cx, cy, cz);
+}
+
+__device__ __forceinline__ bool coord_ok(float x) {
+  return fabsf(x) < kMaxCoord;  // false for NaN and +-inf
+}
+
+// Consecutive logical tiles on one XCD: the hardware deals workgroups to the
+// eight XCDs round-robin, so tile t runs on XCD t % 8.  Remapping gives XCD x
+// the contiguous range [x n/8, (x+1) n/8) and keeps neighbouring chains (which
+// share grid cells) in one L2.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t n) {
+  const uint32_t n8 = n & ~7u;
+  if (b >= n8) return b;
+  return (b & 7u) * (n8 >> 3) + (b >> 3);
+}
+
+}  // namespace soma

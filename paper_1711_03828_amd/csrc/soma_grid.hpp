@@ -1,0 +1,276 @@
+// soma_grid.hpp -- stage 1 of the SCMF cycle (Sec. 2.2): the per-type
+// occupation histogram of the grid cells (Eq. (4)) and the quasi-instantaneous
+// fields (Eq. (12), K^1 form), plus the initial Gaussian-walk configuration.
+#pragma once
+
+#include "soma_device.hpp"
+
+namespace soma {
+
+constexpr uint32_t kFieldBlocks = 1024u;  // fixed grid of the field kernel
+
+struct FieldPartial {
+  unsigned long long sum_a, sum_b;
+  double h_nb;
+  double pad;
+};
+
+// ---------------------------------------------------------------------------
+// Stand-alone histogram: one thread per bead, one packed atomic per bead.
+// ---------------------------------------------------------------------------
+template <bool COUNT64>
+__global__ __launch_bounds__(256) void density_hist_kernel(
+    const float *pos, uint64_t n_beads, uint32_t n, uint32_t n_a, Grid g,
+    void *counts) {
+  const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_beads) return;
+  const float *r = pos + 3 * b;
+  const uint32_t cell = cell_of(g, r[0], r[1], r[2]);
+  const uint32_t i = (uint32_t)(b % n);
+  if (COUNT64) {
+    const unsigned long long inc = 1ull << (i < n_a ? 0u : 32u);
+    atomicAdd(reinterpret_cast<unsigned long long *>(counts) + cell, inc);
+  } else {
+    const unsigned int inc = 1u << (i < n_a ? 0u : 16u);
+    atomicAdd(reinterpret_cast<unsigned int *>(counts) + cell, inc);
+  }
+}
+
+// Fill a buffer of n_words 32-bit words with zeros (a kernel, not a memset
+// node, so that it can live inside a captured graph).
+__global__ __launch_bounds__(256) void zero_kernel(uint32_t *p, uint64_t n_words) {
+  const uint64_t n4 = n_words >> 2;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint4 *p4 = reinterpret_cast<uint4 *>(p);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
+    p4[i] = make_uint4(0u, 0u, 0u, 0u);
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < (n_words & 3u)) p[n4 * 4 + t] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Fields from counts, Eq. (12) with Eq. (8):
+//   phi_t = n_t * inv_rho,  s = (phi_A + phi_B) - 1,  t = kappaN * s,
+//   omega_A = fma(chiN, phi_B, t),  omega_B = fma(chiN, phi_A, t)
+// in this FP32 order (the library is built without FP contraction).
+// Optionally clears the counts in the same pass and accumulates the count
+// sums and H_nb (Eqs. (5), (6), (8), FP64) per block.
+// ---------------------------------------------------------------------------
+struct FieldArgs {
+  void *counts;
+  float *omega;
+  uint32_t n_cells;
+  float inv_rho, chi_n, kappa_n;
+  double inv_rho_d, chi_n_d, kappa_n_d;
+  FieldPartial *partials;  // may be null
+  int clear;
+};
+
+__device__ __forceinline__ void field_cell(uint32_t na, uint32_t nb,
+                                           const FieldArgs &a, float &oa,
+                                           float &ob) {
+  const float phi_a = (float)na * a.inv_rho;
+  const float phi_b = (float)nb * a.inv_rho;
+  const float s = (phi_a + phi_b) - 1.0f;
+  const float t = a.kappa_n * s;
+  oa = fmaf(a.chi_n, phi_b, t);
+  ob = fmaf(a.chi_n, phi_a, t);
+}
+
+__device__ __forceinline__ double hnb_cell(uint32_t na, uint32_t nb,
+                                           const FieldArgs &a) {
+  const double pa = (double)na * a.inv_rho_d, pb = (double)nb * a.inv_rho_d;
+  const double dev = pa + pb - 1.0;
+  return 0.5 * a.kappa_n_d * dev * dev + a.chi_n_d * pa * pb;
+}
+
+template <bool COUNT64>
+__device__ __forceinline__ void load4(const void *counts, uint32_t q,
+                                      uint32_t na[4], uint32_t nb[4]) {
+  if (COUNT64) {
+    const ulonglong2 *c = reinterpret_cast<const ulonglong2 *>(counts) + 2 * (size_t)q;
+    const ulonglong2 v0 = c[0], v1 = c[1];
+    const unsigned long long w[4] = {v0.x, v0.y, v1.x, v1.y};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) { na[j] = (uint32_t)w[j]; nb[j] = (uint32_t)(w[j] >> 32); }
+  } else {
+    const uint4 v = reinterpret_cast<const uint4 *>(counts)[q];
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) { na[j] = w[j] & 0xFFFFu; nb[j] = w[j] >> 16; }
+  }
+}
+
+template <bool COUNT64>
+__global__ __launch_bounds__(256) void field_update_kernel(const FieldArgs a) {
+  __shared__ unsigned long long s_a[4], s_b[4];
+  __shared__ double s_h[4];
+  const uint32_t n4 = a.n_cells >> 2;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long sum_a = 0, sum_b = 0;
+  double h = 0.0;
+  const bool stats = a.partials != nullptr;
+  float4 *oa4 = reinterpret_cast<float4 *>(a.omega);
+  const bool b_aligned = (a.n_cells & 3u) == 0u;
+  float4 *ob4 = reinterpret_cast<float4 *>(a.omega + (b_aligned ? a.n_cells : 0u));
+  for (uint32_t q = tid; q < n4; q += stride) {
+    uint32_t na[4], nb[4];
+    load4<COUNT64>(a.counts, q, na, nb);
+    float va[4], vb[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      field_cell(na[j], nb[j], a, va[j], vb[j]);
+      if (stats) { sum_a += na[j]; sum_b += nb[j]; h += hnb_cell(na[j], nb[j], a); }
+    }
+    oa4[q] = make_float4(va[0], va[1], va[2], va[3]);
+    if (b_aligned) {
+      ob4[q] = make_float4(vb[0], vb[1], vb[2], vb[3]);
+    } else {  // the B plane starts n_cells floats in: 16-byte stores only if n_cells % 4 == 0
+      float *ob = a.omega + a.n_cells + 4 * (size_t)q;
+      ob[0] = vb[0]; ob[1] = vb[1]; ob[2] = vb[2]; ob[3] = vb[3];
+    }
+    if (a.clear) {
+      if (COUNT64) {
+        ulonglong2 *c = reinterpret_cast<ulonglong2 *>(a.counts) + 2 * (size_t)q;
+        c[0] = make_ulonglong2(0ull, 0ull);
+        c[1] = make_ulonglong2(0ull, 0ull);
+      } else {
+        reinterpret_cast<uint4 *>(a.counts)[q] = make_uint4(0u, 0u, 0u, 0u);
+      }
+    }
+  }
+  // ragged tail (n_cells not a multiple of 4)
+  const uint32_t tail = a.n_cells & 3u;
+  if (tid < tail) {
+    const uint32_t c = n4 * 4 + tid;
+    uint32_t na, nb;
+    if (COUNT64) {
+      const unsigned long long w = reinterpret_cast<const unsigned long long *>(a.counts)[c];
+      na = (uint32_t)w; nb = (uint32_t)(w >> 32);
+      if (a.clear) reinterpret_cast<unsigned long long *>(a.counts)[c] = 0ull;
+    } else {
+      const uint32_t w = reinterpret_cast<const uint32_t *>(a.counts)[c];
+      na = w & 0xFFFFu; nb = w >> 16;
+      if (a.clear) reinterpret_cast<uint32_t *>(a.counts)[c] = 0u;
+    }
+    float va, vb;
+    field_cell(na, nb, a, va, vb);
+    a.omega[c] = va;
+    a.omega[a.n_cells + c] = vb;
+    if (stats) { sum_a += na; sum_b += nb; h += hnb_cell(na, nb, a); }
+  }
+  if (!stats) return;
+  // block reduction: wave shuffles, then four waves through LDS
+  for (int off = 32; off > 0; off >>= 1) {
+    sum_a += __shfl_down(sum_a, off, 64);
+    sum_b += __shfl_down(sum_b, off, 64);
+    h += __shfl_down(h, off, 64);
+  }
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  if (lane == 0) { s_a[wv] = sum_a; s_b[wv] = sum_b; s_h[wv] = h; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    FieldPartial p;
+    p.sum_a = s_a[0] + s_a[1] + s_a[2] + s_a[3];
+    p.sum_b = s_b[0] + s_b[1] + s_b[2] + s_b[3];
+    p.h_nb = ((s_h[0] + s_h[1]) + s_h[2]) + s_h[3];
+    p.pad = 0.0;
+    a.partials[blockIdx.x] = p;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initial configuration: Gaussian random walks, bonds N(0, sigma^2) per
+// component with sigma^2 = 1/k0 (the ideal chain of Eq. (2); b0^2 = 3/k0,
+// Sec. 2.1).  One thread per chain.  Origins:
+//   mode 0: uniform in the box, r0_d = u_d * n_d;
+//   mode 1: stratified -- chain g of G sits in the cell of rank
+//           floor(n_cells (g + u_3) / G) of the bricked order (bricks of 8^3
+//           cells row-major in z,y,x, the last brick per axis taking the
+//           remainder; cells row-major in z,y,x inside a brick), at a uniform
+//           point inside it.
+// Draws: Philox block (g, j | 4 << 16, 0xFFFFFFFF, replica) for bead j.
+// ---------------------------------------------------------------------------
+struct InitArgs {
+  float *pos;
+  uint32_t n_chains, n;
+  uint32_t chain_base, total_chains;
+  float sigma;
+  Grid grid;
+  uint32_t seed_lo, seed_hi, replica, origin_mode;
+};
+
+// floor((hi:lo) / d) for a 128-bit dividend whose quotient fits in 64 bits.
+__device__ inline uint64_t div128_64(uint64_t hi, uint64_t lo, uint64_t d) {
+  uint64_t q = 0;
+  for (int i = 63; i >= 0; --i) {
+    // shift (hi:lo) left by one into hi, remainder kept in hi
+    const uint64_t top = hi >> 63;
+    hi = (hi << 1) | (lo >> 63);
+    lo <<= 1;
+    if (top || hi >= d) { hi -= d; q |= 1ull << i; }
+  }
+  return q;
+}
+
+__device__ inline void brick_cell(uint64_t k, const Grid &g, uint32_t &x,
+                                  uint32_t &y, uint32_t &z) {
+  const uint64_t B = 8, nx = g.nx, ny = g.ny, nz = g.nz;
+  const uint64_t nbx = nx >= B ? nx / B : 1, nby = ny >= B ? ny / B : 1,
+                 nbz = nz >= B ? nz / B : 1;
+  uint64_t bz = k / (B * nx * ny);
+  bz = bz < nbz - 1 ? bz : nbz - 1;
+  k -= bz * B * nx * ny;
+  const uint64_t wz = bz + 1 < nbz ? B : nz - B * (nbz - 1);
+  uint64_t by = k / (wz * B * nx);
+  by = by < nby - 1 ? by : nby - 1;
+  k -= by * wz * B * nx;
+  const uint64_t wy = by + 1 < nby ? B : ny - B * (nby - 1);
+  uint64_t bx = k / (wz * wy * B);
+  bx = bx < nbx - 1 ? bx : nbx - 1;
+  k -= bx * wz * wy * B;
+  const uint64_t wx = bx + 1 < nbx ? B : nx - B * (nbx - 1);
+  const uint64_t inner = k % (wy * wx);
+  x = (uint32_t)(bx * B + inner % wx);
+  y = (uint32_t)(by * B + inner / wx);
+  z = (uint32_t)(bz * B + k / (wy * wx));
+}
+
+__global__ __launch_bounds__(256) void init_chains_kernel(const InitArgs a) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.n_chains) return;
+  const uint32_t g = a.chain_base + c;
+  float *p = a.pos + (size_t)c * a.n * 3;
+  Rand4 w = philox(g, kPurposeInit << 16, kSweepInit, a.replica, a.seed_lo, a.seed_hi);
+  float x, y, z;
+  if (a.origin_mode == 1) {
+    const uint64_t num = ((uint64_t)g << 24) + 2ull * (w.w >> 9) + 1ull;
+    const uint64_t nc = a.grid.n_cells;
+    const uint64_t lo = nc * num;
+    const uint64_t hi = __umul64hi(nc, num);
+    const uint64_t k = div128_64(hi, lo, (uint64_t)a.total_chains << 24);
+    uint32_t cx, cy, cz;
+    brick_cell(k, a.grid, cx, cy, cz);
+    x = (float)cx + uniform01(w.x);
+    y = (float)cy + uniform01(w.y);
+    z = (float)cz + uniform01(w.z);
+  } else {
+    x = uniform01(w.x) * (float)a.grid.nx;
+    y = uniform01(w.y) * (float)a.grid.ny;
+    z = uniform01(w.z) * (float)a.grid.nz;
+  }
+  p[0] = x; p[1] = y; p[2] = z;
+  for (uint32_t j = 1; j < a.n; ++j) {
+    w = philox(g, j | (kPurposeInit << 16), kSweepInit, a.replica, a.seed_lo, a.seed_hi);
+    float n0, n1, n2, n3;
+    box_muller(w.x, w.y, n0, n1);
+    box_muller(w.z, w.w, n2, n3);
+    x = fmaf(a.sigma, n0, x);
+    y = fmaf(a.sigma, n1, y);
+    z = fmaf(a.sigma, n2, z);
+    p[3 * j] = x; p[3 * j + 1] = y; p[3 * j + 2] = z;
+  }
+}
+
+}  // namespace soma

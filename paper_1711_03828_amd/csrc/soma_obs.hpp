@@ -1,0 +1,131 @@
+// soma_obs.hpp -- FP64 global reductions: chain observables, energies,
+// acceptance counters and the count sums of the last field update.
+#pragma once
+
+#include "soma_grid.hpp"
+
+namespace soma {
+
+struct ObsPartial {
+  double re2, rg2, b2, e_bond, e_field, pad;
+};
+
+struct Totals {
+  unsigned long long accepted[2];
+  unsigned long long sum_a, sum_b;
+  double re2, rg2, b2, e_bond, e_field, h_nb;
+  uint32_t err, pad;
+};
+
+struct ObsArgs {
+  const float *pos;
+  const float *omega;
+  uint32_t n_chains, n, n_a;
+  double half_k0;
+  double inv_nref;
+  Grid grid;
+  ObsPartial *partials;
+};
+
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (*s)[NV]) {
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] += __shfl_down(v[j], off, 64);
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) s[wv][j] = v[j];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = ((s[0][j] + s[1][j]) + s[2][j]) + s[3][j];
+}
+
+// One thread per chain: Re^2 = |r_{N-1} - r_0|^2, Rg^2 = (1/N) sum |r_i - r_cm|^2,
+// sum of squared bond lengths, bond energy (k0/2) sum b^2 (Eqs. (1)-(2)) and
+// field energy sum_i omega_t(c_i) / N (Eq. (13)); partial sums per block.
+__global__ __launch_bounds__(256) void chain_obs_kernel(const ObsArgs a) {
+  __shared__ double s[4][5];
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  double v[5] = {0, 0, 0, 0, 0};
+  if (c < a.n_chains) {
+    const float *p = a.pos + (size_t)c * a.n * 3;
+    double cx = 0, cy = 0, cz = 0, b2 = 0, ef = 0;
+    for (uint32_t i = 0; i < a.n; ++i) {
+      const float x = p[3 * i], y = p[3 * i + 1], z = p[3 * i + 2];
+      cx += x; cy += y; cz += z;
+      if (i > 0) {
+        const double dx = (double)x - p[3 * i - 3], dy = (double)y - p[3 * i - 2],
+                     dz = (double)z - p[3 * i - 1];
+        b2 += dx * dx + dy * dy + dz * dz;
+      }
+      const uint32_t cell = cell_of(a.grid, x, y, z);
+      ef += (double)a.omega[(i < a.n_a ? 0u : a.grid.n_cells) + cell];
+    }
+    const double inv_n = 1.0 / (double)a.n;
+    cx *= inv_n; cy *= inv_n; cz *= inv_n;
+    double rg = 0;
+    for (uint32_t i = 0; i < a.n; ++i) {
+      const double dx = p[3 * i] - cx, dy = p[3 * i + 1] - cy, dz = p[3 * i + 2] - cz;
+      rg += dx * dx + dy * dy + dz * dz;
+    }
+    const float *q = p + 3 * (a.n - 1);
+    const double ex = (double)q[0] - p[0], ey = (double)q[1] - p[1], ez = (double)q[2] - p[2];
+    v[0] = ex * ex + ey * ey + ez * ez;
+    v[1] = rg * inv_n;
+    v[2] = b2;
+    v[3] = a.half_k0 * b2;
+    v[4] = ef * a.inv_nref;
+  }
+  block_sum<5>(v, s);
+  if (threadIdx.x == 0) {
+    ObsPartial o;
+    o.re2 = v[0]; o.rg2 = v[1]; o.b2 = v[2]; o.e_bond = v[3]; o.e_field = v[4]; o.pad = 0;
+    a.partials[blockIdx.x] = o;
+  }
+}
+
+// Single block: fixed-order reduction of all partials into one Totals record.
+__global__ __launch_bounds__(256) void reduce_totals_kernel(
+    const ObsPartial *op, uint32_t n_op, const FieldPartial *fp, uint32_t n_fp,
+    const unsigned long long *acc_slots, const uint32_t *err, Totals *out) {
+  __shared__ double s[4][6];
+  __shared__ unsigned long long su[4][4];
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  unsigned long long u[4] = {0, 0, 0, 0};
+  for (uint32_t i = threadIdx.x; i < n_op; i += blockDim.x) {
+    v[0] += op[i].re2; v[1] += op[i].rg2; v[2] += op[i].b2;
+    v[3] += op[i].e_bond; v[4] += op[i].e_field;
+  }
+  for (uint32_t i = threadIdx.x; i < n_fp; i += blockDim.x) {
+    u[2] += fp[i].sum_a; u[3] += fp[i].sum_b; v[5] += fp[i].h_nb;
+  }
+  for (uint32_t i = threadIdx.x; i < kAccSlots; i += blockDim.x) {
+    u[0] += acc_slots[i];
+    u[1] += acc_slots[kAccSlots + i];
+  }
+  block_sum<6>(v, s);
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) u[j] += __shfl_down(u[j], off, 64);
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) su[wv][j] = u[j];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Totals t;
+    t.accepted[0] = su[0][0] + su[1][0] + su[2][0] + su[3][0];
+    t.accepted[1] = su[0][1] + su[1][1] + su[2][1] + su[3][1];
+    t.sum_a = su[0][2] + su[1][2] + su[2][2] + su[3][2];
+    t.sum_b = su[0][3] + su[1][3] + su[2][3] + su[3][3];
+    t.re2 = v[0]; t.rg2 = v[1]; t.b2 = v[2]; t.e_bond = v[3]; t.e_field = v[4];
+    t.h_nb = v[5];
+    t.err = *err;
+    t.pad = 0;
+    *out = t;
+  }
+}
+
+}  // namespace soma

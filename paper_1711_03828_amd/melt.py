@@ -1,0 +1,113 @@
+"""A melt on one GPU: torch tensors own the device buffers, the C ABI does the work.
+
+``Melt`` derives the model constants from a workload description (Re0 in grid
+units, chain lengths, chiN, kappaN) and holds the buffers and the handle:
+
+* k0 = 3 (N_ref - 1) / Re0^2, so that the ideal chain has b0^2 = 3/k0 =
+  Re0^2/(N_ref - 1) (Sec. 2.1, after Eq. (9));
+* local half-width a = a_frac * b0; smart-MC step A = smc_frac * Re0^2 / N_ref.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import soma as C
+
+
+def make_config(w, *, seed=None, replica=0, set_order=0, origin_mode=1) -> C.soma_config:
+    cfg = C.soma_config()
+    cfg.nx, cfg.ny, cfg.nz = (int(v) for v in w.grid)
+    cfg.n_species = len(w.species)
+    for i, s in enumerate(w.species):
+        cfg.species[i].n_chains = s.n_chains
+        cfg.species[i].n = s.n
+        cfg.species[i].n_a = s.n_a
+        cfg.species[i].k0 = float(np.float32(3.0 * (w.n_ref - 1) / w.re_cells ** 2))
+    cfg.n_ref = w.n_ref
+    cfg.chi_n = w.chi_n
+    cfg.kappa_n = w.kappa_n
+    b0 = w.re_cells / math.sqrt(w.n_ref - 1)
+    cfg.local_a = float(np.float32(w.a_frac * b0))
+    cfg.smc_a = float(np.float32(w.smc_frac * w.re_cells ** 2 / w.n_ref))
+    cfg.seed = w.seed if seed is None else seed
+    cfg.replica = replica
+    cfg.count_width = w.count_width
+    cfg.set_order = set_order
+    cfg.origin_mode = origin_mode
+    return cfg
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+class Melt:
+    """Buffers + handle for one melt on one device."""
+
+    def __init__(self, cfg: C.soma_config, positions: torch.Tensor | None = None,
+                 device="cuda", stream=None):
+        self.cfg = cfg
+        pos_b, cnt_b, om_b, ws_b = C.soma_buffer_sizes(cfg)
+        self.n_beads = pos_b // 12
+        self.n_cells = cfg.nx * cfg.ny * cfg.nz
+        if positions is None:
+            self.pos = torch.empty((self.n_beads, 3), dtype=torch.float32, device=device)
+        else:
+            assert positions.shape == (self.n_beads, 3) and positions.dtype == torch.float32
+            self.pos = positions.to(device).contiguous()
+        cdt = torch.int32 if cfg.count_width == 16 else torch.int64
+        self.counts = torch.empty(self.n_cells, dtype=cdt, device=device)
+        self.omega = torch.empty((2, self.n_cells), dtype=torch.float32, device=device)
+        self.workspace = torch.empty(ws_b, dtype=torch.uint8, device=device)
+        self.buf = C.soma_buffers(self.pos.data_ptr(), pos_b, self.counts.data_ptr(), cnt_b,
+                                  self.omega.data_ptr(), om_b, self.workspace.data_ptr(), ws_b)
+        self.handle = C.soma_init_system(cfg, self.buf, positions is None, _stream(stream))
+
+    def sweep(self, n_sweeps=1, move_kind=C.SOMA_MOVE_LOCAL, stream=None):
+        C.soma_mc_sweep(self.handle, n_sweeps, move_kind, _stream(stream))
+
+    def update_fields(self, stream=None):
+        C.soma_update_fields(self.handle, _stream(stream))
+
+    def cycle(self, n=1, move_kind=C.SOMA_MOVE_LOCAL, stream=None):
+        """n SCMF cycles: one sweep, then the field refresh."""
+        s = _stream(stream)
+        for _ in range(n):
+            C.soma_mc_sweep(self.handle, 1, move_kind, s)
+            C.soma_update_fields(self.handle, s)
+
+    def observables(self, stream=None, raise_on_flag=True) -> C.soma_obs:
+        return C.soma_observables(self.handle, _stream(stream), raise_on_flag)
+
+    @property
+    def sweep_index(self) -> int:
+        return C.soma_get_sweep(self.handle)
+
+    @sweep_index.setter
+    def sweep_index(self, v: int):
+        C.soma_set_sweep(self.handle, v)
+
+    def counts_planes(self) -> np.ndarray:
+        """Unpack the packed counts to uint32 [2, n_cells] on the host."""
+        c = self.counts.cpu().numpy()
+        if self.cfg.count_width == 16:
+            u = c.view(np.uint32)
+            return np.stack([u & 0xFFFF, u >> 16]).astype(np.uint32)
+        u = c.view(np.uint64)
+        return np.stack([u & 0xFFFFFFFF, u >> 32]).astype(np.uint32)
+
+    def close(self):
+        if self.handle:
+            C.soma_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

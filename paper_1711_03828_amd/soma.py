@@ -1,0 +1,184 @@
+"""ctypes binding of the C ABI in ``include/soma.h`` (argument marshalling only).
+
+Every function here has the name of the C entry point it calls; all work runs
+in the HIP library ``libsoma_hip.so``.  Device memory comes from PyTorch
+tensors (``tensor.data_ptr()``); streams are HIP streams
+(``torch.cuda.current_stream().cuda_stream``).  If the library has not been
+built this module raises on import -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsoma_hip.so")
+
+SOMA_OK = 0
+SOMA_E_INVAL = -1
+SOMA_E_HIP = -2
+SOMA_E_SIZE = -3
+SOMA_E_UNSUPPORTED = -4
+SOMA_E_DEVICE_FLAG = -5
+
+SOMA_MOVE_LOCAL = 0
+SOMA_MOVE_SMC = 1
+SOMA_FLAG_POSITION = 1
+SOMA_MAX_SPECIES = 8
+SOMA_MAX_BEADS_PER_CHAIN = 128
+
+
+class soma_species(ctypes.Structure):
+    _fields_ = [("n_chains", ctypes.c_uint32), ("n", ctypes.c_uint32),
+                ("n_a", ctypes.c_uint32), ("k0", ctypes.c_float)]
+
+
+class soma_config(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_uint32), ("ny", ctypes.c_uint32), ("nz", ctypes.c_uint32),
+                ("n_species", ctypes.c_uint32),
+                ("species", soma_species * SOMA_MAX_SPECIES),
+                ("n_ref", ctypes.c_uint32), ("chi_n", ctypes.c_float),
+                ("kappa_n", ctypes.c_float), ("local_a", ctypes.c_float),
+                ("smc_a", ctypes.c_float), ("seed", ctypes.c_uint64),
+                ("replica", ctypes.c_uint32), ("count_width", ctypes.c_uint32),
+                ("set_order", ctypes.c_uint32), ("origin_mode", ctypes.c_uint32)]
+
+
+class soma_buffers(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("pos_bytes", ctypes.c_uint64),
+                ("counts", ctypes.c_void_p), ("counts_bytes", ctypes.c_uint64),
+                ("omega", ctypes.c_void_p), ("omega_bytes", ctypes.c_uint64),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64)]
+
+
+class soma_obs(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_uint64), ("n_beads", ctypes.c_uint64),
+                ("n_chains", ctypes.c_uint64), ("count_a", ctypes.c_uint64),
+                ("count_b", ctypes.c_uint64), ("accepted", ctypes.c_uint64 * 2),
+                ("attempted", ctypes.c_uint64 * 2), ("re2_sum", ctypes.c_double),
+                ("rg2_sum", ctypes.c_double), ("b2_sum", ctypes.c_double),
+                ("e_bond", ctypes.c_double), ("e_field", ctypes.c_double),
+                ("h_nb", ctypes.c_double), ("error_flags", ctypes.c_uint32),
+                ("counts_conserved", ctypes.c_uint32)]
+
+
+class SomaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"soma error {code}: {msg}")
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing; build it with "
+                      "`python -m paper_1711_03828_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P = ctypes.c_void_p
+_u32, _u64, _i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
+_pu64 = ctypes.POINTER(ctypes.c_uint64)
+_pu32 = ctypes.POINTER(ctypes.c_uint32)
+
+_SIGS = {
+    "soma_buffer_sizes": ([ctypes.POINTER(soma_config), _pu64, _pu64, _pu64, _pu64], _i32),
+    "soma_workspace_size": ([ctypes.POINTER(soma_config), _pu64], _i32),
+    "soma_init_system": ([ctypes.POINTER(soma_config), ctypes.POINTER(soma_buffers), _u32, _P,
+                          ctypes.POINTER(_P)], _i32),
+    "soma_mc_sweep": ([_P, _u32, _u32, _P], _i32),
+    "soma_update_fields": ([_P, _P], _i32),
+    "soma_observables": ([_P, ctypes.POINTER(soma_obs), _P], _i32),
+    "soma_check": ([_P, _pu32, _P], _i32),
+    "soma_get_sweep": ([_P, _pu64], _i32),
+    "soma_set_sweep": ([_P, _u64], _i32),
+    "soma_density_hist": ([ctypes.POINTER(soma_config), _P, _P, _P], _i32),
+    "soma_field_from_counts": ([ctypes.POINTER(soma_config), _P, _P, _P], _i32),
+    "soma_init_positions": ([ctypes.POINTER(soma_config), _P, _P], _i32),
+    "soma_destroy": ([_P], None),
+    "soma_last_error": ([], ctypes.c_char_p),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+def soma_last_error() -> str:
+    return _lib.soma_last_error().decode()
+
+
+def _check(rc: int) -> int:
+    if rc != SOMA_OK:
+        raise SomaError(rc, soma_last_error())
+    return rc
+
+
+def soma_buffer_sizes(cfg: soma_config):
+    v = [ctypes.c_uint64() for _ in range(4)]
+    _check(_lib.soma_buffer_sizes(ctypes.byref(cfg), *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def soma_workspace_size(cfg: soma_config) -> int:
+    v = ctypes.c_uint64()
+    _check(_lib.soma_workspace_size(ctypes.byref(cfg), ctypes.byref(v)))
+    return v.value
+
+
+def soma_init_system(cfg: soma_config, buf: soma_buffers, init_positions: bool, stream: int):
+    h = ctypes.c_void_p()
+    _check(_lib.soma_init_system(ctypes.byref(cfg), ctypes.byref(buf), int(init_positions),
+                                 ctypes.c_void_p(stream), ctypes.byref(h)))
+    return h
+
+
+def soma_mc_sweep(h, n_sweeps: int, move_kind: int, stream: int) -> None:
+    _check(_lib.soma_mc_sweep(h, n_sweeps, move_kind, ctypes.c_void_p(stream)))
+
+
+def soma_update_fields(h, stream: int) -> None:
+    _check(_lib.soma_update_fields(h, ctypes.c_void_p(stream)))
+
+
+def soma_observables(h, stream: int, raise_on_flag: bool = True) -> soma_obs:
+    out = soma_obs()
+    rc = _lib.soma_observables(h, ctypes.byref(out), ctypes.c_void_p(stream))
+    if rc != SOMA_OK and (raise_on_flag or rc != SOMA_E_DEVICE_FLAG):
+        raise SomaError(rc, soma_last_error())
+    return out
+
+
+def soma_check(h, stream: int) -> int:
+    f = ctypes.c_uint32()
+    rc = _lib.soma_check(h, ctypes.byref(f), ctypes.c_void_p(stream))
+    if rc not in (SOMA_OK, SOMA_E_DEVICE_FLAG):
+        raise SomaError(rc, soma_last_error())
+    return f.value
+
+
+def soma_get_sweep(h) -> int:
+    v = ctypes.c_uint64()
+    _check(_lib.soma_get_sweep(h, ctypes.byref(v)))
+    return v.value
+
+
+def soma_set_sweep(h, sweep: int) -> None:
+    _check(_lib.soma_set_sweep(h, sweep))
+
+
+def soma_density_hist(cfg: soma_config, pos_ptr: int, counts_ptr: int, stream: int) -> None:
+    _check(_lib.soma_density_hist(ctypes.byref(cfg), ctypes.c_void_p(pos_ptr),
+                                  ctypes.c_void_p(counts_ptr), ctypes.c_void_p(stream)))
+
+
+def soma_field_from_counts(cfg: soma_config, counts_ptr: int, omega_ptr: int, stream: int) -> None:
+    _check(_lib.soma_field_from_counts(ctypes.byref(cfg), ctypes.c_void_p(counts_ptr),
+                                       ctypes.c_void_p(omega_ptr), ctypes.c_void_p(stream)))
+
+
+def soma_init_positions(cfg: soma_config, pos_ptr: int, stream: int) -> None:
+    _check(_lib.soma_init_positions(ctypes.byref(cfg), ctypes.c_void_p(pos_ptr),
+                                    ctypes.c_void_p(stream)))
+
+
+def soma_destroy(h) -> None:
+    if h:
+        _lib.soma_destroy(h)

@@ -1,0 +1,71 @@
+"""Shared set-up for the GPU parity tests: configurations on both sides.
+
+The device side gets a ``soma_config`` through the package; the oracle side
+gets the same numbers as plain arguments.  Model constants are derived once
+here from the workload description (they are configuration, not method).
+"""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+
+import synth
+
+
+def flush(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def constants(w):
+    k0 = np.float32(3.0 * (w.n_ref - 1) / w.re_cells ** 2)
+    a = np.float32(w.a_frac * w.re_cells / math.sqrt(w.n_ref - 1))
+    A = np.float32(w.smc_frac * w.re_cells ** 2 / w.n_ref)
+    inv_rho = np.float32(w.n_cells / w.n_beads)
+    return k0, a, A, inv_rho
+
+
+def device_config(w, **kw):
+    from paper_1711_03828_amd.melt import make_config
+    return make_config(w, **kw)
+
+
+def custom_config(grid, species, *, k0, n_ref, chi_n=0.0, kappa_n=0.0, local_a=0.1,
+                  smc_a=0.05, seed=1, count_width=16, set_order=0, origin_mode=1, replica=0):
+    from paper_1711_03828_amd import soma as C
+    cfg = C.soma_config()
+    cfg.nx, cfg.ny, cfg.nz = grid
+    cfg.n_species = len(species)
+    for i, s in enumerate(species):
+        cfg.species[i].n_chains = s.n_chains
+        cfg.species[i].n = s.n
+        cfg.species[i].n_a = s.n_a
+        cfg.species[i].k0 = float(np.float32(k0))
+    cfg.n_ref = n_ref
+    cfg.chi_n = chi_n
+    cfg.kappa_n = kappa_n
+    cfg.local_a = float(np.float32(local_a))
+    cfg.smc_a = float(np.float32(smc_a))
+    cfg.seed = seed
+    cfg.replica = replica
+    cfg.count_width = count_width
+    cfg.set_order = set_order
+    cfg.origin_mode = origin_mode
+    return cfg
+
+
+def walks_for(w, seed):
+    k0 = constants(w)[0]
+    parts = [synth.gaussian_walks(seed + i, s.n_chains, s.n, w.grid, 1.0 / math.sqrt(float(k0)))
+             for i, s in enumerate(w.species)]
+    return np.concatenate(parts) if parts else np.zeros((0, 3), np.float32)
+
+
+def unpack_counts(c: np.ndarray, width: int) -> np.ndarray:
+    if width == 16:
+        u = c.view(np.uint32)
+        return np.stack([u & 0xFFFF, u >> 16]).astype(np.uint32)
+    u = c.view(np.uint64)
+    return np.stack([u & 0xFFFFFFFF, u >> 32]).astype(np.uint32)
