@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--move", default="local", choices=["local", "smc"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the SCMF path here runs on a single "
@@ -111,6 +113,12 @@ def main():
     w = {"c1": synth.C1_SMALL, "c2": synth.C2_LARGE, "c4": synth.C4_MEDIUM}[args.workload]
     move = C.SOMA_MOVE_LOCAL if args.move == "local" else C.SOMA_MOVE_SMC
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     melt = Melt(make_config(w))            # device-side Gaussian-walk init + fields
     torch.cuda.synchronize()
     print(f"# initialised {w.name}: {w.n_beads} beads, {w.n_cells} cells", file=sys.stderr,

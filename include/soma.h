@@ -134,8 +134,9 @@ int32_t soma_workspace_size(const soma_config *cfg, uint64_t *bytes);
  * If init_positions != 0, fills buf->pos with Gaussian-walk chains: bonds
  * N(0, 1/k0) per component (the ideal chain of Eq. (2), b0^2 = 3/k0, Sec. 2.1)
  * from origins placed per origin_mode; otherwise buf->pos must already hold
- * positions.  Then computes the histogram and the fields once (stage 1 of
- * Sec. 2.2), so that omega matches the positions; counts are left zero.
+ * positions.  Then builds the occupation histogram (Eq. (4)) into buf->counts
+ * and the fields from it (stage 1 of Sec. 2.2).  From then on the library keeps
+ * buf->counts equal to the histogram of the current positions.
  * Asynchronous on `stream` except for argument validation.  On success *out
  * receives the handle. */
 int32_t soma_init_system(const soma_config *cfg, const soma_buffers *buf,
@@ -146,19 +147,21 @@ int32_t soma_init_system(const soma_config *cfg, const soma_buffers *buf,
  * fixed: each sweep attempts one move of every bead, the even and the odd
  * beads of a chain forming the two independent sets of Sec. 3.1.2, moved set
  * after set in a random order per chain and sweep.  move_kind is
- * SOMA_MOVE_LOCAL or SOMA_MOVE_SMC.  The last sweep of the call also builds
- * the occupation histogram of the final positions into buf->counts (fused;
- * counts are cleared first if they still hold an older histogram).
- * Asynchronous. */
+ * SOMA_MOVE_LOCAL or SOMA_MOVE_SMC.  The histogram in buf->counts is updated
+ * in the same pass (a bead that changes cell is moved from its old to its new
+ * cell), so after the call it equals the histogram of the final positions,
+ * bit for bit.  Asynchronous. */
 int32_t soma_mc_sweep(soma_system *sys, uint32_t n_sweeps, uint32_t move_kind,
                       void *stream);
 
-/* Stage 1 of Sec. 2.2: omega from the current histogram (Eq. (12)), counts
- * cleared to zero in the same pass, and the count sums and H_nb of this
- * histogram kept for soma_observables.  If no histogram is pending (no
- * sweep since the last update) it is first rebuilt from the positions.
- * Asynchronous. */
+/* Stage 1 of Sec. 2.2: omega from the current histogram (Eq. (12)); the count
+ * sums and H_nb of this histogram are kept for soma_observables.  The counts
+ * are left unchanged.  Asynchronous. */
 int32_t soma_update_fields(soma_system *sys, void *stream);
+
+/* Recounts buf->counts from buf->pos (cleared first).  Needed only after the
+ * caller has changed positions outside the library.  Asynchronous. */
+int32_t soma_rebuild_histogram(soma_system *sys, void *stream);
 
 /* BLOCKING.  Chain observables in FP64 (Re^2, Rg^2, bond lengths, bond and
  * field energies), acceptance counters, the count sums and H_nb of the last

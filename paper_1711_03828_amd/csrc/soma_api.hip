@@ -202,7 +202,6 @@ struct soma_system {
   soma::Grid grid;
   uint64_t sweep = 0;
   uint64_t attempted[2] = {0, 0};
-  bool counts_hold_hist = false;
   unsigned char *ws = nullptr;
   uint32_t *err() { return reinterpret_cast<uint32_t *>(ws + d.off_err); }
   unsigned long long *acc() { return reinterpret_cast<unsigned long long *>(ws + d.off_acc); }
@@ -213,15 +212,15 @@ struct soma_system {
 
 namespace {
 
-template <bool SMC, bool C64, bool V2>
-void launch_sweep_t(bool hist, dim3 grid, hipStream_t s, const soma::SweepArgs &a) {
-  if (hist)
-    hipLaunchKernelGGL((soma::mc_sweep_kernel<SMC, C64, V2, true>), grid, dim3(256), 0, s, a);
+template <bool C64, bool V2>
+void launch_sweep_t(uint32_t kind, dim3 grid, hipStream_t s, const soma::SweepArgs &a) {
+  if (kind == SOMA_MOVE_SMC)
+    hipLaunchKernelGGL((soma::mc_sweep_smc_kernel<C64, V2>), grid, dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((soma::mc_sweep_kernel<SMC, C64, V2, false>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((soma::mc_sweep_local_kernel<C64, V2>), grid, dim3(256), 0, s, a);
 }
 
-int32_t launch_sweep(soma_system *sys, uint32_t kind, bool hist, hipStream_t s) {
+int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s) {
   const soma_config *c = &sys->cfg;
   for (uint32_t sp = 0; sp < c->n_species; ++sp) {
     const soma_species &S = c->species[sp];
@@ -255,12 +254,10 @@ int32_t launch_sweep(soma_system *sys, uint32_t kind, bool hist, hipStream_t s) 
     const bool v2 = (S.n % 2 == 0) && (sys->d.bead_off[sp] % 2 == 0) && aligned(a.pos, 8);
     const bool c64 = c->count_width == 32;
     const dim3 grid((uint32_t)blocks);
-    if (kind == SOMA_MOVE_SMC) {
-      if (c64) { if (v2) launch_sweep_t<true, true, true>(hist, grid, s, a); else launch_sweep_t<true, true, false>(hist, grid, s, a); }
-      else     { if (v2) launch_sweep_t<true, false, true>(hist, grid, s, a); else launch_sweep_t<true, false, false>(hist, grid, s, a); }
+    if (c64) {
+      if (v2) launch_sweep_t<true, true>(kind, grid, s, a); else launch_sweep_t<true, false>(kind, grid, s, a);
     } else {
-      if (c64) { if (v2) launch_sweep_t<false, true, true>(hist, grid, s, a); else launch_sweep_t<false, true, false>(hist, grid, s, a); }
-      else     { if (v2) launch_sweep_t<false, false, true>(hist, grid, s, a); else launch_sweep_t<false, false, false>(hist, grid, s, a); }
+      if (v2) launch_sweep_t<false, true>(kind, grid, s, a); else launch_sweep_t<false, false>(kind, grid, s, a);
     }
     LAUNCH_TRY();
   }
@@ -328,12 +325,11 @@ int32_t soma_init_system(const soma_config *cfg, const soma_buffers *buf, uint32
   rc = launch_zero(sys->ws, d.ws_bytes, s);
   if (!rc && init_positions) rc = launch_init(cfg, d, buf->pos, s);
   if (!rc) rc = launch_hist(cfg, d, buf->pos, buf->counts, s);
-  if (!rc) rc = launch_field(cfg, d, buf->counts, buf->omega, sys->fpart(), 1, s);
+  if (!rc) rc = launch_field(cfg, d, buf->counts, buf->omega, sys->fpart(), 0, s);
   if (rc) {
     delete sys;
     return rc;
   }
-  sys->counts_hold_hist = false;
   *out = sys;
   return SOMA_OK;
 }
@@ -344,31 +340,26 @@ int32_t soma_mc_sweep(soma_system *sys, uint32_t n_sweeps, uint32_t move_kind, v
     return fail(SOMA_E_UNSUPPORTED, "move kind %u", move_kind);
   if (move_kind == SOMA_MOVE_SMC && !(sys->cfg.smc_a > 0.f))
     return fail(SOMA_E_INVAL, "smart-MC moves need smc_a > 0");
-  if (n_sweeps == 0) return SOMA_OK;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (sys->counts_hold_hist) {
-    const int32_t rc = launch_zero(sys->buf.counts, sys->d.counts_bytes, s);
-    if (rc) return rc;
-  }
   for (uint32_t i = 0; i < n_sweeps; ++i) {
-    const int32_t rc = launch_sweep(sys, move_kind, i + 1 == n_sweeps, s);
+    const int32_t rc = launch_sweep(sys, move_kind, s);
     if (rc) return rc;
     sys->sweep += 1;
   }
   sys->attempted[move_kind] += (uint64_t)n_sweeps * sys->d.n_beads;
-  sys->counts_hold_hist = true;
   return SOMA_OK;
+}
+
+int32_t soma_rebuild_histogram(soma_system *sys, void *stream) {
+  if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
+  return launch_hist(&sys->cfg, sys->d, sys->buf.pos, sys->buf.counts,
+                     reinterpret_cast<hipStream_t>(stream));
 }
 
 int32_t soma_update_fields(soma_system *sys, void *stream) {
   if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  int32_t rc = SOMA_OK;
-  if (!sys->counts_hold_hist) rc = launch_hist(&sys->cfg, sys->d, sys->buf.pos, sys->buf.counts, s);
-  if (!rc) rc = launch_field(&sys->cfg, sys->d, sys->buf.counts, sys->buf.omega, sys->fpart(), 1, s);
-  if (rc) return rc;
-  sys->counts_hold_hist = false;
-  return SOMA_OK;
+  return launch_field(&sys->cfg, sys->d, sys->buf.counts, sys->buf.omega, sys->fpart(), 0,
+                      reinterpret_cast<hipStream_t>(stream));
 }
 
 int32_t soma_observables(soma_system *sys, soma_obs *out, void *stream) {

@@ -26,14 +26,13 @@ __device__ __forceinline__ Rand4 philox(uint32_t c0, uint32_t c1, uint32_t c2,
                                         uint32_t c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = c0 * 0xD2511F53u;
-    const uint32_t hi0 = __umulhi(c0, 0xD2511F53u);
-    const uint32_t lo1 = c2 * 0xCD9E8D57u;
-    const uint32_t hi1 = __umulhi(c2, 0xCD9E8D57u);
-    c0 = hi1 ^ c1 ^ k0;
-    c1 = lo1;
-    c2 = hi0 ^ c3 ^ k1;
-    c3 = lo0;
+    // one v_mad_u64_u32 per product gives both halves
+    const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
+    const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
+    c0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    c1 = (uint32_t)p1;
+    c2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c3 = (uint32_t)p0;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -41,12 +40,15 @@ __device__ __forceinline__ Rand4 philox(uint32_t c0, uint32_t c1, uint32_t c2,
 }
 
 // u = (2k+1) 2^-24 from the top 23 bits k: exact in FP32, in (0,1), symmetric.
+// Built from the bit pattern 1 + k 2^-23 of [1,2): (f - 1) + 2^-24, both exact.
 __device__ __forceinline__ float uniform01(uint32_t x) {
-  return (float)(2u * (x >> 9) + 1u) * 0x1p-24f;
+  const float f = __uint_as_float((x >> 9) | 0x3F800000u);
+  return (f - 1.0f) + 0x1p-24f;
 }
-// v = 2u - 1 in (-1,1), exact (one rounding of an exact value).
+// v = 2u - 1 = (2f - 3) + 2^-23 in (-1,1), both steps exact.
 __device__ __forceinline__ float uniform11(uint32_t x) {
-  return fmaf(2.0f, uniform01(x), -1.0f);
+  const float f = __uint_as_float((x >> 9) | 0x3F800000u);
+  return fmaf(2.0f, f, -3.0f) + 0x1p-23f;
 }
 
 // Two standard normals from two words (Box-Muller).
@@ -60,16 +62,16 @@ __device__ __forceinline__ void box_muller(uint32_t w0, uint32_t w1, float &n0,
 }
 
 // floor(x) mod n, exact for |x| < 2^22; NaN and larger values are clamped
-// first so the index is always inside [0, n).
+// first so the index is always inside [0, n).  The quotient estimate
+// floor(f/n) may be off by one; the two unsigned minima fix either case.
 __device__ __forceinline__ uint32_t wrap_cell(float x, int n, float inv_n) {
-  float f = floorf(x);
-  f = fminf(fmaxf(f, -kMaxCoord), kMaxCoord);
-  const int i = (int)f;
-  const int q = (int)floorf(f * inv_n);  // floor(i/n) up to +-1
-  int r = i - q * n;
-  r = r >= n ? r - n : r;
-  r = r < 0 ? r + n : r;
-  return (uint32_t)r;
+  const float f = fminf(fmaxf(floorf(x), -kMaxCoord), kMaxCoord);
+  const float q = floorf(f * inv_n);
+  const int r = (int)fmaf(-q, (float)n, f);  // exact: integers below 2^24
+  uint32_t u = (uint32_t)r;
+  u = min(u, u + (uint32_t)n);               // r in [-n, 0)  -> r + n
+  u = min(u, u - (uint32_t)n);               // r in [n, 2n)  -> r - n
+  return u;
 }
 
 struct Grid {
@@ -86,9 +88,10 @@ __device__ __forceinline__ void cell3(const Grid &g, float x, float y, float z,
   cz = wrap_cell(z, g.nz, g.inv_nz);
 }
 
+// (z ny + y) nx + x with 24-bit multiplies (every factor is below 2^24).
 __device__ __forceinline__ uint32_t cell_index(const Grid &g, uint32_t cx,
                                                uint32_t cy, uint32_t cz) {
-  return (cz * (uint32_t)g.ny + cy) * (uint32_t)g.nx + cx;
+  return __umul24(__umul24(cz, (uint32_t)g.ny) + cy, (uint32_t)g.nx) + cx;
 }
 
 __device__ __forceinline__ uint32_t cell_of(const Grid &g, float x, float y,

@@ -1,5 +1,5 @@
-// soma_sweep.hpp -- the MC sweep kernel (stage 2 of the SCMF cycle, Sec. 2.2)
-// with the occupation histogram of the final positions fused as its epilogue.
+// soma_sweep.hpp -- the MC sweep kernels (stage 2 of the SCMF cycle, Sec. 2.2)
+// with the occupation histogram kept current in the same pass.
 //
 // Work decomposition (the "SET" scheme of Sec. 3.1.2 mapped on wave64):
 // a chain of N beads occupies ceil(N/2) consecutive lanes of one wavefront;
@@ -7,8 +7,15 @@
 // whole sweep.  The two sets are moved one after the other in a random order
 // per chain; within a set every lane moves its bead at once, since the beads
 // of one set are not bonded to each other.  The neighbour a moving bead needs
-// from the adjacent lane is exchanged through the cross-lane network, so each
-// bead is read from and written to HBM exactly once per sweep.
+// from the adjacent lane comes through the cross-lane network, so each bead is
+// read from and written to HBM exactly once per sweep.
+//
+// Histogram: the counts always hold the occupation numbers of the current
+// positions (Eq. (4)).  A sweep moves every bead once, so the histogram of the
+// final positions is the old one minus each bead at its old cell plus each
+// bead at its new cell; only beads that changed cell need the two integer
+// atomics.  Integer addition is exact and order-independent, so the result is
+// bit-identical to counting the final positions from scratch.
 #pragma once
 
 #include "soma_device.hpp"
@@ -33,20 +40,191 @@ struct SweepArgs {
   uint32_t set_order;              // 0 random per chain and sweep, 1 even first
 };
 
-struct F3 {
-  float x, y, z;
-};
+// Three-component vector kept in registers (a native vector type, so that
+// selects between vectors never go through private memory).
+typedef float F3 __attribute__((ext_vector_type(3)));
 
-__device__ __forceinline__ F3 sel(bool c, F3 a, F3 b) {
-  return {c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z};
-}
+__device__ __forceinline__ F3 sel(bool c, F3 a, F3 b) { return c ? a : b; }
 
 __device__ __forceinline__ float shfl_f(float v, int src) {
   return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
 }
 
-// Central-difference gradient of one field plane at cell (cx,cy,cz), the
-// force of the grid field on a bead being -(1/N) grad omega.
+// Lane geometry of one wave: which chain and which bead pair a lane holds.
+struct LaneMap {
+  int lane;
+  uint32_t k;           // pair index in the chain
+  uint32_t chain;       // chain index within the species
+  bool has0, has1;      // beads 2k and 2k+1 exist
+  uint32_t tile;
+  uint32_t wib;
+};
+
+__device__ __forceinline__ LaneMap lane_map(const SweepArgs &a) {
+  LaneMap m;
+  m.lane = (int)(threadIdx.x & 63u);
+  m.wib = threadIdx.x >> 6;
+  m.tile = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t L = a.lanes_per_chain;
+  const uint32_t slot = (uint32_t)m.lane / L;
+  m.k = (uint32_t)m.lane - slot * L;
+  m.chain = (m.tile * 4u + m.wib) * a.chains_per_wave + slot;
+  const bool active = slot < a.chains_per_wave && m.chain < a.n_chains;
+  m.has0 = active;  // 2k < N for every k < ceil(N/2)
+  m.has1 = active && 2u * m.k + 1u < a.n;
+  return m;
+}
+
+template <bool VEC2>
+__device__ __forceinline__ void load_pair(const float *cp, const LaneMap &m, F3 &r0, F3 &r1) {
+  r0 = F3{0.f, 0.f, 0.f};
+  r1 = F3{0.f, 0.f, 0.f};
+  if (VEC2) {
+    if (m.has0) {
+      const float2 p0 = reinterpret_cast<const float2 *>(cp)[0];
+      const float2 p1 = reinterpret_cast<const float2 *>(cp)[1];
+      const float2 p2 = reinterpret_cast<const float2 *>(cp)[2];
+      r0 = F3{p0.x, p0.y, p1.x};
+      r1 = F3{p1.y, p2.x, p2.y};
+    }
+  } else {
+    if (m.has0) r0 = F3{cp[0], cp[1], cp[2]};
+    if (m.has1) r1 = F3{cp[3], cp[4], cp[5]};
+  }
+}
+
+template <bool VEC2>
+__device__ __forceinline__ void store_pair(float *cp, const LaneMap &m, F3 r0, F3 r1) {
+  if (VEC2) {
+    if (m.has0) {
+      reinterpret_cast<float2 *>(cp)[0] = make_float2(r0.x, r0.y);
+      reinterpret_cast<float2 *>(cp)[1] = make_float2(r0.z, r1.x);
+      reinterpret_cast<float2 *>(cp)[2] = make_float2(r1.y, r1.z);
+    }
+  } else {
+    if (m.has0) { cp[0] = r0.x; cp[1] = r0.y; cp[2] = r0.z; }
+    if (m.has1) { cp[3] = r1.x; cp[4] = r1.y; cp[5] = r1.z; }
+  }
+}
+
+// Move one bead's unit from cell `from` to cell `to` in the packed counts.
+template <bool COUNT64>
+__device__ __forceinline__ void move_count(void *counts, uint32_t from, uint32_t to, bool is_b) {
+  if (COUNT64) {
+    unsigned long long *c = reinterpret_cast<unsigned long long *>(counts);
+    const unsigned long long inc = is_b ? (1ull << 32) : 1ull;
+    atomicAdd(c + from, (unsigned long long)(0ull - inc));
+    atomicAdd(c + to, inc);
+  } else {
+    unsigned int *c = reinterpret_cast<unsigned int *>(counts);
+    const unsigned int inc = is_b ? (1u << 16) : 1u;
+    atomicAdd(c + from, 0u - inc);
+    atomicAdd(c + to, inc);
+  }
+}
+
+__device__ __forceinline__ void finish_wave(const SweepArgs &a, const LaneMap &m, uint32_t n_acc,
+                                            F3 r0, F3 r1) {
+  __shared__ uint32_t s_acc[4];
+  const bool bad = (m.has0 && !(coord_ok(r0.x) && coord_ok(r0.y) && coord_ok(r0.z))) ||
+                   (m.has1 && !(coord_ok(r1.x) && coord_ok(r1.y) && coord_ok(r1.z)));
+  if (__ballot(bad) != 0ull && m.lane == 0) atomicOr(a.err, 1u);
+  if (m.lane == 0) s_acc[m.wib] = n_acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t tot = s_acc[0] + s_acc[1] + s_acc[2] + s_acc[3];
+    if (tot) atomicAdd(a.acc_slots + (m.tile & (kAccSlots - 1u)), (unsigned long long)tot);
+  }
+}
+
+// Order of the two sets for this chain and sweep: bit 0 of the first word of
+// bead 0's draw, broadcast from the chain's first lane (the displacement uses
+// only bits 9..31 of that word).
+__device__ __forceinline__ uint32_t set_order_bit(const SweepArgs &a, const LaneMap &m,
+                                                  uint32_t w0x) {
+  if (a.set_order != 0) return 0u;
+  const int src = m.lane - (int)m.k;
+  return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)(w0x & 1u));
+}
+
+// ---------------------------------------------------------------------------
+// Local moves (Sec. 2.2, move (i)): uniform trial displacement in [-a,a] per
+// Cartesian direction, Metropolis acceptance of
+//   dE = (k0/2) sum_bonds (|r'-r_j|^2 - |r-r_j|^2) + (omega_t(c') - omega_t(c))/N.
+// A trial position depends only on the bead itself, so both trial positions of
+// a lane and the four field values they need are fetched before either set
+// moves; only the bond term waits for the other set.
+// ---------------------------------------------------------------------------
+template <bool COUNT64, bool VEC2>
+__global__ __launch_bounds__(256) void mc_sweep_local_kernel(const SweepArgs a) {
+  const LaneMap m = lane_map(a);
+  const uint32_t N = a.n;
+  const uint32_t i0 = 2u * m.k, i1 = i0 + 1u;
+  float *cp = a.pos + (size_t)(m.has0 ? m.chain : 0u) * N * 3u + 6u * m.k;
+  F3 r0, r1;
+  load_pair<VEC2>(cp, m, r0, r1);
+
+  const uint32_t gchain = a.chain_base + m.chain;
+  const Rand4 w0 = philox(gchain, i0 | (kPurposeMoveA << 16), a.sweep, a.replica, a.seed_lo, a.seed_hi);
+  const Rand4 w1 = philox(gchain, i1 | (kPurposeMoveA << 16), a.sweep, a.replica, a.seed_lo, a.seed_hi);
+  const uint32_t first = set_order_bit(a, m, w0.x);
+
+  const F3 t0 = {fmaf(a.step, uniform11(w0.x), r0.x), fmaf(a.step, uniform11(w0.y), r0.y),
+                 fmaf(a.step, uniform11(w0.z), r0.z)};
+  const F3 t1 = {fmaf(a.step, uniform11(w1.x), r1.x), fmaf(a.step, uniform11(w1.y), r1.y),
+                 fmaf(a.step, uniform11(w1.z), r1.z)};
+  const uint32_t c0 = cell_of(a.grid, r0.x, r0.y, r0.z);
+  const uint32_t c1 = cell_of(a.grid, r1.x, r1.y, r1.z);
+  const uint32_t n0 = cell_of(a.grid, t0.x, t0.y, t0.z);
+  const uint32_t n1 = cell_of(a.grid, t1.x, t1.y, t1.z);
+  const bool b0 = i0 >= a.n_a, b1 = i1 >= a.n_a;
+  const float *om0 = a.omega + (b0 ? a.grid.n_cells : 0u);
+  const float *om1 = a.omega + (b1 ? a.grid.n_cells : 0u);
+  // per-bead field change, in units of kT per bead
+  const float df0 = (om0[n0] - om0[c0]) * a.inv_nref;
+  const float df1 = (om1[n1] - om1[c1]) * a.inv_nref;
+  const float u0 = uniform01(w0.w), u1 = uniform01(w1.w);
+
+  bool acc0 = false, acc1 = false;
+  uint32_t n_acc = 0;
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool odd = (first ^ (uint32_t)pass) != 0u;
+    // even set needs bead 2k-1 (odd bead of lane k-1); odd set needs bead
+    // 2k+2 (even bead of lane k+1)
+    const F3 send = sel(odd, r0, r1);
+    const int src = odd ? (m.lane < 63 ? m.lane + 1 : m.lane) : (m.lane > 0 ? m.lane - 1 : m.lane);
+    const F3 nb = {shfl_f(send.x, src), shfl_f(send.y, src), shfl_f(send.z, src)};
+    const F3 left = sel(odd, r0, nb);
+    const F3 right = sel(odd, nb, r1);
+    const bool moving = odd ? m.has1 : m.has0;
+    const float wl = (odd || m.k > 0) ? 1.0f : 0.0f;
+    const float wr = (odd ? (i1 + 1u < N) : m.has1) ? 1.0f : 0.0f;
+    const F3 r = sel(odd, r1, r0);
+    const F3 t = sel(odd, t1, t0);
+    const F3 d = {t.x - r.x, t.y - r.y, t.z - r.z};
+    const F3 el = {r.x - left.x, r.y - left.y, r.z - left.z};
+    const F3 er = {r.x - right.x, r.y - right.y, r.z - right.z};
+    // sum_j d.(2 (r - r_j) + d) over the existing bonded neighbours
+    const float qx = wl * (2.0f * el.x + d.x) + wr * (2.0f * er.x + d.x);
+    const float qy = wl * (2.0f * el.y + d.y) + wr * (2.0f * er.y + d.y);
+    const float qz = wl * (2.0f * el.z + d.z) + wr * (2.0f * er.z + d.z);
+    const float d_e = a.half_k0 * (d.x * qx + d.y * qy + d.z * qz) + (odd ? df1 : df0);
+    const float u = odd ? u1 : u0;
+    const bool acc = moving && (d_e <= 0.0f || u < __expf(-d_e));
+    if (odd) { acc1 = acc; r1 = acc ? t1 : r1; }
+    else     { acc0 = acc; r0 = acc ? t0 : r0; }
+    n_acc += (uint32_t)__popcll(__ballot(acc));
+  }
+
+  store_pair<VEC2>(cp, m, r0, r1);
+  if (acc0 && n0 != c0) move_count<COUNT64>(a.counts, c0, n0, b0);
+  if (acc1 && n1 != c1) move_count<COUNT64>(a.counts, c1, n1, b1);
+  finish_wave(a, m, n_acc, r0, r1);
+}
+
+// Central-difference gradient of one field plane at cell (cx,cy,cz); the
+// force of the grid field on a bead is -(1/N) grad omega.
 __device__ __forceinline__ F3 field_grad(const Grid &g, const float *om,
                                          uint32_t cx, uint32_t cy,
                                          uint32_t cz) {
@@ -63,186 +241,102 @@ __device__ __forceinline__ F3 field_grad(const Grid &g, const float *om,
   return r;
 }
 
-template <bool SMC, bool COUNT64, bool VEC2, bool HIST>
-__global__ __launch_bounds__(256) void mc_sweep_kernel(const SweepArgs a) {
-  __shared__ uint32_t s_acc[4];
-  const int lane = (int)(threadIdx.x & 63u);
-  const uint32_t wib = threadIdx.x >> 6;
-  const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
-  const uint32_t L = a.lanes_per_chain;
-  const uint32_t slot = (uint32_t)lane / L;
-  const uint32_t k = (uint32_t)lane - slot * L;
-  const uint32_t chain = (tile * 4u + wib) * a.chains_per_wave + slot;
-  const bool active = slot < a.chains_per_wave && chain < a.n_chains;
+// ---------------------------------------------------------------------------
+// Smart-MC moves (Sec. 2.2, move (ii)): r' = r + A F(r) + sqrt(2A) xi with the
+// bonded force plus the grid-field force -(1/N) grad omega; accepted with
+// min(1, exp(-dE) q(r|r')/q(r'|r)), q the Gaussian proposal density.  The
+// trial position of the second set depends on the first set's outcome through
+// the bonded force, so the sets are handled one after the other.
+// ---------------------------------------------------------------------------
+template <bool COUNT64, bool VEC2>
+__global__ __launch_bounds__(256) void mc_sweep_smc_kernel(const SweepArgs a) {
+  const LaneMap m = lane_map(a);
   const uint32_t N = a.n;
-  const uint32_t i0 = 2u * k, i1 = 2u * k + 1u;
-  const bool has0 = active;            // 2k < N for every k < ceil(N/2)
-  const bool has1 = active && i1 < N;
-  float *cp = a.pos + (size_t)(active ? chain : 0u) * N * 3u + 6u * k;
+  const uint32_t i0 = 2u * m.k, i1 = i0 + 1u;
+  float *cp = a.pos + (size_t)(m.has0 ? m.chain : 0u) * N * 3u + 6u * m.k;
+  F3 r0, r1;
+  load_pair<VEC2>(cp, m, r0, r1);
 
-  F3 r0 = {0.f, 0.f, 0.f}, r1 = {0.f, 0.f, 0.f};
-  if (VEC2) {
-    if (has0) {
-      const float2 p0 = reinterpret_cast<const float2 *>(cp)[0];
-      const float2 p1 = reinterpret_cast<const float2 *>(cp)[1];
-      const float2 p2 = reinterpret_cast<const float2 *>(cp)[2];
-      r0 = {p0.x, p0.y, p1.x};
-      r1 = {p1.y, p2.x, p2.y};
-    }
-  } else {
-    if (has0) r0 = {cp[0], cp[1], cp[2]};
-    if (has1) r1 = {cp[3], cp[4], cp[5]};
-  }
-
-  const uint32_t gchain = a.chain_base + chain;
+  const uint32_t gchain = a.chain_base + m.chain;
   const Rand4 wa0 = philox(gchain, i0 | (kPurposeMoveA << 16), a.sweep, a.replica, a.seed_lo, a.seed_hi);
   const Rand4 wa1 = philox(gchain, i1 | (kPurposeMoveA << 16), a.sweep, a.replica, a.seed_lo, a.seed_hi);
-  Rand4 wb0 = {0, 0, 0, 0}, wb1 = {0, 0, 0, 0};
-  if (SMC) {
-    wb0 = philox(gchain, i0 | (kPurposeMoveB << 16), a.sweep, a.replica, a.seed_lo, a.seed_hi);
-    wb1 = philox(gchain, i1 | (kPurposeMoveB << 16), a.sweep, a.replica, a.seed_lo, a.seed_hi);
-  }
-  // Set order: bit 0 of the first word of bead 0's draw, broadcast from the
-  // chain's first lane (the displacement uses only bits 9..31 of that word).
-  uint32_t first = 0;
-  if (a.set_order == 0) {
-    const int src = lane - (int)k;
-    first = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)(wa0.x & 1u));
-  }
+  const Rand4 wb0 = philox(gchain, i0 | (kPurposeMoveB << 16), a.sweep, a.replica, a.seed_lo, a.seed_hi);
+  const Rand4 wb1 = philox(gchain, i1 | (kPurposeMoveB << 16), a.sweep, a.replica, a.seed_lo, a.seed_hi);
+  const uint32_t first = set_order_bit(a, m, wa0.x);
+  const bool b0 = i0 >= a.n_a, b1 = i1 >= a.n_a;
 
-  uint32_t cell0 = 0, cell1 = 0;
+  uint32_t from0 = 0, to0 = 0, from1 = 0, to1 = 0;
+  bool moved0 = false, moved1 = false;
   uint32_t n_acc = 0;
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
-    const bool odd = (pass == 0 ? first : first ^ 1u) != 0u;
-    // neighbour from the adjacent lane: even pass needs bead 2k-1 (odd bead of
-    // lane k-1), odd pass needs bead 2k+2 (even bead of lane k+1)
+    const bool odd = (first ^ (uint32_t)pass) != 0u;
     const F3 send = sel(odd, r0, r1);
-    const int src = odd ? (lane < 63 ? lane + 1 : lane) : (lane > 0 ? lane - 1 : lane);
+    const int src = odd ? (m.lane < 63 ? m.lane + 1 : m.lane) : (m.lane > 0 ? m.lane - 1 : m.lane);
     const F3 nb = {shfl_f(send.x, src), shfl_f(send.y, src), shfl_f(send.z, src)};
     const F3 left = sel(odd, r0, nb);
     const F3 right = sel(odd, nb, r1);
-    const bool moving = odd ? has1 : has0;
-    const float wl = (odd || k > 0) ? 1.0f : 0.0f;
-    const float wr = (odd ? (i1 + 1u < N) : (i1 < N)) ? 1.0f : 0.0f;
-    const uint32_t mi = odd ? i1 : i0;
+    const bool moving = odd ? m.has1 : m.has0;
+    const float wl = (odd || m.k > 0) ? 1.0f : 0.0f;
+    const float wr = (odd ? (i1 + 1u < N) : m.has1) ? 1.0f : 0.0f;
     const F3 r = sel(odd, r1, r0);
     const Rand4 w = odd ? wa1 : wa0;
-    const float *om = a.omega + (mi < a.n_a ? 0u : a.grid.n_cells);
+    const float u = uniform01(odd ? wb1.x : wb0.x);
+    const float *om = a.omega + ((odd ? b1 : b0) ? a.grid.n_cells : 0u);
 
     bool acc = false;
-    uint32_t cell_final = 0;
+    uint32_t co = 0, cn = 0;
+    F3 rn = r;
     if (moving) {
       uint32_t ox, oy, oz;
       cell3(a.grid, r.x, r.y, r.z, ox, oy, oz);
-      const uint32_t co = cell_index(a.grid, ox, oy, oz);
+      co = cell_index(a.grid, ox, oy, oz);
       const F3 el = {r.x - left.x, r.y - left.y, r.z - left.z};
       const F3 er = {r.x - right.x, r.y - right.y, r.z - right.z};
-      F3 rn;
-      float log_q = 0.0f;
-      float u;
-      F3 f_old = {0.f, 0.f, 0.f}, g_old = {0.f, 0.f, 0.f};
-      if (!SMC) {
-        rn = {fmaf(a.step, uniform11(w.x), r.x), fmaf(a.step, uniform11(w.y), r.y),
-              fmaf(a.step, uniform11(w.z), r.z)};
-        u = uniform01(w.w);
-      } else {
-        const Rand4 wb = odd ? wb1 : wb0;
-        float xi0, xi1, xi2, xi3;
-        box_muller(w.x, w.y, xi0, xi1);
-        box_muller(w.z, w.w, xi2, xi3);
-        g_old = field_grad(a.grid, om, ox, oy, oz);
-        f_old = {-a.k0 * (wl * el.x + wr * er.x) - a.inv_nref * g_old.x,
-                 -a.k0 * (wl * el.y + wr * er.y) - a.inv_nref * g_old.y,
-                 -a.k0 * (wl * el.z + wr * er.z) - a.inv_nref * g_old.z};
-        rn = {fmaf(a.sqrt_2a, xi0, fmaf(a.step, f_old.x, r.x)),
-              fmaf(a.sqrt_2a, xi1, fmaf(a.step, f_old.y, r.y)),
-              fmaf(a.sqrt_2a, xi2, fmaf(a.step, f_old.z, r.z))};
-        u = uniform01(wb.x);
-      }
+      float xi0, xi1, xi2, xi3;
+      box_muller(w.x, w.y, xi0, xi1);
+      box_muller(w.z, w.w, xi2, xi3);
+      const F3 g_old = field_grad(a.grid, om, ox, oy, oz);
+      const F3 f_old = {-a.k0 * (wl * el.x + wr * er.x) - a.inv_nref * g_old.x,
+                        -a.k0 * (wl * el.y + wr * er.y) - a.inv_nref * g_old.y,
+                        -a.k0 * (wl * el.z + wr * er.z) - a.inv_nref * g_old.z};
+      rn = {fmaf(a.sqrt_2a, xi0, fmaf(a.step, f_old.x, r.x)),
+            fmaf(a.sqrt_2a, xi1, fmaf(a.step, f_old.y, r.y)),
+            fmaf(a.sqrt_2a, xi2, fmaf(a.step, f_old.z, r.z))};
       uint32_t nx_, ny_, nz_;
       cell3(a.grid, rn.x, rn.y, rn.z, nx_, ny_, nz_);
-      const uint32_t cn = cell_index(a.grid, nx_, ny_, nz_);
+      cn = cell_index(a.grid, nx_, ny_, nz_);
+      // force at the trial position with the same bonded neighbours; the
+      // field gradient is constant inside a cell
+      const F3 g_new = cn == co ? g_old : field_grad(a.grid, om, nx_, ny_, nz_);
       const F3 d = {rn.x - r.x, rn.y - r.y, rn.z - r.z};
-      if (SMC) {
-        // force at the trial position with the same bonded neighbours; the
-        // field gradient is constant inside a cell
-        const F3 g_new = cn == co ? g_old : field_grad(a.grid, om, nx_, ny_, nz_);
-        const F3 nl = {rn.x - left.x, rn.y - left.y, rn.z - left.z};
-        const F3 nr = {rn.x - right.x, rn.y - right.y, rn.z - right.z};
-        const F3 f_new = {-a.k0 * (wl * nl.x + wr * nr.x) - a.inv_nref * g_new.x,
-                          -a.k0 * (wl * nl.y + wr * nr.y) - a.inv_nref * g_new.y,
-                          -a.k0 * (wl * nl.z + wr * nr.z) - a.inv_nref * g_new.z};
-        const F3 fw = {d.x - a.step * f_old.x, d.y - a.step * f_old.y, d.z - a.step * f_old.z};
-        const F3 rv = {-d.x - a.step * f_new.x, -d.y - a.step * f_new.y, -d.z - a.step * f_new.z};
-        const float fw2 = fw.x * fw.x + fw.y * fw.y + fw.z * fw.z;
-        const float rv2 = rv.x * rv.x + rv.y * rv.y + rv.z * rv.z;
-        log_q = (fw2 - rv2) * a.inv_4a;  // log q(r|r') - log q(r'|r)
-      }
-      // bond energy change in the difference form: sum_j d.(2 (r - r_j) + d)
+      const F3 nl = {rn.x - left.x, rn.y - left.y, rn.z - left.z};
+      const F3 nr = {rn.x - right.x, rn.y - right.y, rn.z - right.z};
+      const F3 f_new = {-a.k0 * (wl * nl.x + wr * nr.x) - a.inv_nref * g_new.x,
+                        -a.k0 * (wl * nl.y + wr * nr.y) - a.inv_nref * g_new.y,
+                        -a.k0 * (wl * nl.z + wr * nr.z) - a.inv_nref * g_new.z};
+      const F3 fw = {d.x - a.step * f_old.x, d.y - a.step * f_old.y, d.z - a.step * f_old.z};
+      const F3 rv = {-d.x - a.step * f_new.x, -d.y - a.step * f_new.y, -d.z - a.step * f_new.z};
+      const float log_q = ((fw.x * fw.x + fw.y * fw.y + fw.z * fw.z) -
+                           (rv.x * rv.x + rv.y * rv.y + rv.z * rv.z)) * a.inv_4a;
       const float qx = wl * (2.0f * el.x + d.x) + wr * (2.0f * er.x + d.x);
       const float qy = wl * (2.0f * el.y + d.y) + wr * (2.0f * er.y + d.y);
       const float qz = wl * (2.0f * el.z + d.z) + wr * (2.0f * er.z + d.z);
-      const float d_bond = a.half_k0 * (d.x * qx + d.y * qy + d.z * qz);
       const float w_old = om[co];
       const float w_new = cn == co ? w_old : om[cn];
-      const float d_e = d_bond + (w_new - w_old) * a.inv_nref;
-      if (!SMC) {
-        acc = d_e <= 0.0f || u < __expf(-d_e);
-      } else {
-        const float lr = log_q - d_e;
-        acc = lr >= 0.0f || u < __expf(lr);
-      }
-      cell_final = acc ? cn : co;
-      if (acc) {
-        if (odd) r1 = rn; else r0 = rn;
-      }
+      const float d_e = a.half_k0 * (d.x * qx + d.y * qy + d.z * qz) + (w_new - w_old) * a.inv_nref;
+      const float lr = log_q - d_e;
+      acc = lr >= 0.0f || u < __expf(lr);
     }
-    if (odd) cell1 = cell_final; else cell0 = cell_final;
+    if (odd) { r1 = acc ? rn : r1; moved1 = acc && cn != co; from1 = co; to1 = cn; }
+    else     { r0 = acc ? rn : r0; moved0 = acc && cn != co; from0 = co; to0 = cn; }
     n_acc += (uint32_t)__popcll(__ballot(acc));
   }
 
-  if (VEC2) {
-    if (has0) {
-      reinterpret_cast<float2 *>(cp)[0] = make_float2(r0.x, r0.y);
-      reinterpret_cast<float2 *>(cp)[1] = make_float2(r0.z, r1.x);
-      reinterpret_cast<float2 *>(cp)[2] = make_float2(r1.y, r1.z);
-    }
-  } else {
-    if (has0) { cp[0] = r0.x; cp[1] = r0.y; cp[2] = r0.z; }
-    if (has1) { cp[3] = r1.x; cp[4] = r1.y; cp[5] = r1.z; }
-  }
-
-  const bool bad = (has0 && !(coord_ok(r0.x) && coord_ok(r0.y) && coord_ok(r0.z))) ||
-                   (has1 && !(coord_ok(r1.x) && coord_ok(r1.y) && coord_ok(r1.z)));
-  if (__ballot(bad) != 0ull && lane == 0) atomicOr(a.err, 1u);
-
-  if (HIST) {
-    // packed increment: one unit in the A or the B half of the cell word
-    const unsigned shift = COUNT64 ? 32u : 16u;
-    const unsigned long long inc0 = 1ull << (i0 < a.n_a ? 0u : shift);
-    const unsigned long long inc1 = has1 ? 1ull << (i1 < a.n_a ? 0u : shift) : 0ull;
-    if (has0) {
-      const bool same = has1 && cell1 == cell0;
-      const unsigned long long first_inc = same ? inc0 + inc1 : inc0;
-      if (COUNT64) {
-        unsigned long long *c = reinterpret_cast<unsigned long long *>(a.counts);
-        atomicAdd(c + cell0, first_inc);
-        if (has1 && !same) atomicAdd(c + cell1, inc1);
-      } else {
-        unsigned int *c = reinterpret_cast<unsigned int *>(a.counts);
-        atomicAdd(c + cell0, (unsigned int)first_inc);
-        if (has1 && !same) atomicAdd(c + cell1, (unsigned int)inc1);
-      }
-    }
-  }
-
-  if (lane == 0) s_acc[wib] = n_acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t tot = s_acc[0] + s_acc[1] + s_acc[2] + s_acc[3];
-    if (tot) atomicAdd(a.acc_slots + (tile & (kAccSlots - 1u)), (unsigned long long)tot);
-  }
+  store_pair<VEC2>(cp, m, r0, r1);
+  if (moved0) move_count<COUNT64>(a.counts, from0, to0, b0);
+  if (moved1) move_count<COUNT64>(a.counts, from1, to1, b1);
+  finish_wave(a, m, n_acc, r0, r1);
 }
 
 }  // namespace soma

@@ -74,6 +74,9 @@ class Melt:
     def update_fields(self, stream=None):
         C.soma_update_fields(self.handle, _stream(stream))
 
+    def rebuild_histogram(self, stream=None):
+        C.soma_rebuild_histogram(self.handle, _stream(stream))
+
     def cycle(self, n=1, move_kind=C.SOMA_MOVE_LOCAL, stream=None):
         """n SCMF cycles: one sweep, then the field refresh."""
         s = _stream(stream)

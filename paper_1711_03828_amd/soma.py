@@ -85,6 +85,7 @@ _SIGS = {
                           ctypes.POINTER(_P)], _i32),
     "soma_mc_sweep": ([_P, _u32, _u32, _P], _i32),
     "soma_update_fields": ([_P, _P], _i32),
+    "soma_rebuild_histogram": ([_P, _P], _i32),
     "soma_observables": ([_P, ctypes.POINTER(soma_obs), _P], _i32),
     "soma_check": ([_P, _pu32, _P], _i32),
     "soma_get_sweep": ([_P, _pu64], _i32),
@@ -136,6 +137,10 @@ def soma_mc_sweep(h, n_sweeps: int, move_kind: int, stream: int) -> None:
 
 def soma_update_fields(h, stream: int) -> None:
     _check(_lib.soma_update_fields(h, ctypes.c_void_p(stream)))
+
+
+def soma_rebuild_histogram(h, stream: int) -> None:
+    _check(_lib.soma_rebuild_histogram(h, ctypes.c_void_p(stream)))
 
 
 def soma_observables(h, stream: int, raise_on_flag: bool = True) -> soma_obs:

@@ -119,7 +119,7 @@ def test_init_fields_bit_exact(C, orc):
     melt, pos, omega, sp, _ = _both_sides(C, orc, w, 41)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(melt.omega.cpu().numpy(), omega)
-    assert not melt.counts.cpu().numpy().any()       # cleared by the field pass
+    np.testing.assert_array_equal(melt.counts_planes(), orc.density_hist(pos, sp, w.grid))
     obs = melt.observables()
     assert obs.counts_conserved == 1 and obs.error_flags == 0
     assert obs.h_nb == pytest.approx(orc.h_nb(orc.density_hist(pos, sp, w.grid),
@@ -172,6 +172,19 @@ def test_one_sweep_parity(C, orc, kind, wname):
     allowed = math.ceil(1e-6 * moves)
     flush("mismatched chains", bad_chains, "allowed", allowed, "moves", moves)
     assert bad_chains <= allowed
+    # the histogram kept by the sweep is the histogram of the final positions
+    # (exactly, counted by the oracle from the device positions) ...
+    hist_gpu = melt.counts_planes()
+    np.testing.assert_array_equal(hist_gpu, orc.density_hist(got, sp, w.grid))
+    # ... and differs from the oracle's own histogram only where a bead sits in a
+    # different cell on the two sides (none for local moves without mismatches;
+    # for smart MC a bead within 1e-5 Re0 of a cell face)
+    hist_ref = orc.density_hist(pos, sp, w.grid)
+    cells_differ = int((np.floor(got.astype(np.float64)) != np.floor(pos.astype(np.float64)))
+                       .any(axis=1).sum())
+    if kind == "local" and bad_chains == 0:
+        assert cells_differ == 0
+    assert int((hist_gpu != hist_ref).sum()) <= 2 * cells_differ
     obs = melt.observables()
     kidx = 0 if kind == "local" else 1
     assert obs.attempted[kidx] == moves
