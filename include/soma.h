@@ -67,7 +67,7 @@ typedef enum soma_status {
 #define SOMA_MOVE_SMC 1u   /* force-biased (smart MC) proposal, Metropolis-Hastings */
 
 /* Device error word bits (returned by soma_check / soma_observables). */
-#define SOMA_FLAG_POSITION 1u /* a position became non-finite or |x| >= 2^22 */
+#define SOMA_FLAG_POSITION 1u /* soma_observables found a position non-finite or |x| >= 2^22 */
 
 #define SOMA_MAX_SPECIES 8
 #define SOMA_MAX_BEADS_PER_CHAIN 128
@@ -86,7 +86,7 @@ typedef struct soma_config {
   uint32_t n_ref;        /* reference chain length N of omega/N, chiN, kappaN */
   float chi_n;           /* chi_AB N (Eq. (8)) */
   float kappa_n;         /* kappa N (Eq. (6)) */
-  float local_a;         /* half-width a of the local move, cells */
+  float local_a;         /* half-width a of the local move, cells; local moves need a < 1 */
   float smc_a;           /* step A of the smart-MC move, cells^2: r' = r + A F + sqrt(2A) xi */
   uint64_t seed;         /* Philox key */
   uint32_t replica;      /* fourth Philox counter word */

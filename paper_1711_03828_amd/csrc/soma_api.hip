@@ -230,7 +230,6 @@ int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s) {
     a.omega = sys->buf.omega;
     a.counts = sys->buf.counts;
     a.acc_slots = sys->acc() + (kind == SOMA_MOVE_SMC ? soma::kAccSlots : 0u);
-    a.err = sys->err();
     a.grid = sys->grid;
     a.n_chains = S.n_chains;
     a.n = S.n;
@@ -340,6 +339,8 @@ int32_t soma_mc_sweep(soma_system *sys, uint32_t n_sweeps, uint32_t move_kind, v
     return fail(SOMA_E_UNSUPPORTED, "move kind %u", move_kind);
   if (move_kind == SOMA_MOVE_SMC && !(sys->cfg.smc_a > 0.f))
     return fail(SOMA_E_INVAL, "smart-MC moves need smc_a > 0");
+  if (move_kind == SOMA_MOVE_LOCAL && !(sys->cfg.local_a < 1.f))
+    return fail(SOMA_E_UNSUPPORTED, "local moves need a half-width below one cell");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   for (uint32_t i = 0; i < n_sweeps; ++i) {
     const int32_t rc = launch_sweep(sys, move_kind, s);
@@ -379,6 +380,7 @@ int32_t soma_observables(soma_system *sys, soma_obs *out, void *stream) {
     a.inv_nref = 1.0 / (double)c->n_ref;
     a.grid = sys->grid;
     a.partials = sys->opart() + sys->d.obs_block_off[sp];
+    a.err = sys->err();
     hipLaunchKernelGGL(soma::chain_obs_kernel, dim3((S.n_chains + 255) / 256), dim3(256), 0, s, a);
     LAUNCH_TRY();
   }

@@ -29,9 +29,10 @@ __device__ __forceinline__ Rand4 philox(uint32_t c0, uint32_t c1, uint32_t c2,
     // one v_mad_u64_u32 per product gives both halves
     const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
     const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
-    c0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    // three-input XOR in one v_bitop3_b32 (truth table 0x96)
+    c0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
     c1 = (uint32_t)p1;
-    c2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
     c3 = (uint32_t)p0;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
@@ -71,6 +72,16 @@ __device__ __forceinline__ uint32_t wrap_cell(float x, int n, float inv_n) {
   uint32_t u = (uint32_t)r;
   u = min(u, u + (uint32_t)n);               // r in [-n, 0)  -> r + n
   u = min(u, u - (uint32_t)n);               // r in [n, 2n)  -> r - n
+  return u;
+}
+
+// Cell coordinate of x' given the cell coordinate c of x and |x' - x| < 1:
+// floor moves by -1, 0 or +1, then wraps at the box faces.
+__device__ __forceinline__ uint32_t shift_cell(uint32_t c, float x, float xn, int n) {
+  const int d = (int)(floorf(xn) - floorf(x));
+  uint32_t u = c + (uint32_t)d;
+  u = min(u, u + (uint32_t)n);  // -1 -> n-1
+  u = min(u, u - (uint32_t)n);  // n  -> 0
   return u;
 }
 

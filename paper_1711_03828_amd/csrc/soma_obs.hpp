@@ -6,6 +6,8 @@
 
 namespace soma {
 
+constexpr uint32_t SOMA_FLAG_POSITION_BIT = 1u;  // a position non-finite or |x| >= 2^22
+
 struct ObsPartial {
   double re2, rg2, b2, e_bond, e_field, pad;
 };
@@ -25,6 +27,7 @@ struct ObsArgs {
   double inv_nref;
   Grid grid;
   ObsPartial *partials;
+  uint32_t *err;
 };
 
 template <int NV>
@@ -52,8 +55,10 @@ __global__ __launch_bounds__(256) void chain_obs_kernel(const ObsArgs a) {
   if (c < a.n_chains) {
     const float *p = a.pos + (size_t)c * a.n * 3;
     double cx = 0, cy = 0, cz = 0, b2 = 0, ef = 0;
+    bool bad = false;
     for (uint32_t i = 0; i < a.n; ++i) {
       const float x = p[3 * i], y = p[3 * i + 1], z = p[3 * i + 2];
+      bad |= !(coord_ok(x) && coord_ok(y) && coord_ok(z));
       cx += x; cy += y; cz += z;
       if (i > 0) {
         const double dx = (double)x - p[3 * i - 3], dy = (double)y - p[3 * i - 2],
@@ -63,6 +68,7 @@ __global__ __launch_bounds__(256) void chain_obs_kernel(const ObsArgs a) {
       const uint32_t cell = cell_of(a.grid, x, y, z);
       ef += (double)a.omega[(i < a.n_a ? 0u : a.grid.n_cells) + cell];
     }
+    if (bad) atomicOr(a.err, SOMA_FLAG_POSITION_BIT);
     const double inv_n = 1.0 / (double)a.n;
     cx *= inv_n; cy *= inv_n; cz *= inv_n;
     double rg = 0;

@@ -27,7 +27,6 @@ struct SweepArgs {
   const float *omega;              // [2][n_cells]
   void *counts;                    // packed per-cell counts
   unsigned long long *acc_slots;   // [kAccSlots] accepted-move counters
-  uint32_t *err;                   // device error word
   Grid grid;
   uint32_t n_chains, n, n_a;
   uint32_t lanes_per_chain, chains_per_wave;
@@ -123,12 +122,8 @@ __device__ __forceinline__ void move_count(void *counts, uint32_t from, uint32_t
   }
 }
 
-__device__ __forceinline__ void finish_wave(const SweepArgs &a, const LaneMap &m, uint32_t n_acc,
-                                            F3 r0, F3 r1) {
+__device__ __forceinline__ void finish_wave(const SweepArgs &a, const LaneMap &m, uint32_t n_acc) {
   __shared__ uint32_t s_acc[4];
-  const bool bad = (m.has0 && !(coord_ok(r0.x) && coord_ok(r0.y) && coord_ok(r0.z))) ||
-                   (m.has1 && !(coord_ok(r1.x) && coord_ok(r1.y) && coord_ok(r1.z)));
-  if (__ballot(bad) != 0ull && m.lane == 0) atomicOr(a.err, 1u);
   if (m.lane == 0) s_acc[m.wib] = n_acc;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -152,8 +147,11 @@ __device__ __forceinline__ uint32_t set_order_bit(const SweepArgs &a, const Lane
 // Cartesian direction, Metropolis acceptance of
 //   dE = (k0/2) sum_bonds (|r'-r_j|^2 - |r-r_j|^2) + (omega_t(c') - omega_t(c))/N.
 // A trial position depends only on the bead itself, so both trial positions of
-// a lane and the four field values they need are fetched before either set
-// moves; only the bond term waits for the other set.
+// a lane and the field values they need are fetched before either set moves;
+// only the bond term waits for the other set.  Per lane the two beads are
+// relabelled once by the chain's set order ("a" moves first, "b" second), so
+// the passes need no per-pass selection.  Requires a < 1 cell (host-checked):
+// a trial position is then at most one cell away along each axis.
 // ---------------------------------------------------------------------------
 template <bool COUNT64, bool VEC2>
 __global__ __launch_bounds__(256) void mc_sweep_local_kernel(const SweepArgs a) {
@@ -167,60 +165,78 @@ __global__ __launch_bounds__(256) void mc_sweep_local_kernel(const SweepArgs a) 
   const uint32_t gchain = a.chain_base + m.chain;
   const Rand4 w0 = philox(gchain, i0 | (kPurposeMoveA << 16), a.sweep, a.replica, a.seed_lo, a.seed_hi);
   const Rand4 w1 = philox(gchain, i1 | (kPurposeMoveA << 16), a.sweep, a.replica, a.seed_lo, a.seed_hi);
-  const uint32_t first = set_order_bit(a, m, w0.x);
+  const bool odd_first = set_order_bit(a, m, w0.x) != 0u;
 
+  // trial positions r' = fma(a, v, r)
   const F3 t0 = {fmaf(a.step, uniform11(w0.x), r0.x), fmaf(a.step, uniform11(w0.y), r0.y),
                  fmaf(a.step, uniform11(w0.z), r0.z)};
   const F3 t1 = {fmaf(a.step, uniform11(w1.x), r1.x), fmaf(a.step, uniform11(w1.y), r1.y),
                  fmaf(a.step, uniform11(w1.z), r1.z)};
-  const uint32_t c0 = cell_of(a.grid, r0.x, r0.y, r0.z);
-  const uint32_t c1 = cell_of(a.grid, r1.x, r1.y, r1.z);
-  const uint32_t n0 = cell_of(a.grid, t0.x, t0.y, t0.z);
-  const uint32_t n1 = cell_of(a.grid, t1.x, t1.y, t1.z);
+  // old and trial cells
+  uint32_t x0, y0, z0, x1, y1, z1;
+  cell3(a.grid, r0.x, r0.y, r0.z, x0, y0, z0);
+  cell3(a.grid, r1.x, r1.y, r1.z, x1, y1, z1);
+  const uint32_t c0 = cell_index(a.grid, x0, y0, z0);
+  const uint32_t c1 = cell_index(a.grid, x1, y1, z1);
+  const uint32_t n0 = cell_index(a.grid, shift_cell(x0, r0.x, t0.x, a.grid.nx),
+                                 shift_cell(y0, r0.y, t0.y, a.grid.ny),
+                                 shift_cell(z0, r0.z, t0.z, a.grid.nz));
+  const uint32_t n1 = cell_index(a.grid, shift_cell(x1, r1.x, t1.x, a.grid.nx),
+                                 shift_cell(y1, r1.y, t1.y, a.grid.ny),
+                                 shift_cell(z1, r1.z, t1.z, a.grid.nz));
   const bool b0 = i0 >= a.n_a, b1 = i1 >= a.n_a;
   const float *om0 = a.omega + (b0 ? a.grid.n_cells : 0u);
   const float *om1 = a.omega + (b1 ? a.grid.n_cells : 0u);
-  // per-bead field change, in units of kT per bead
-  const float df0 = (om0[n0] - om0[c0]) * a.inv_nref;
-  const float df1 = (om1[n1] - om1[c1]) * a.inv_nref;
-  const float u0 = uniform01(w0.w), u1 = uniform01(w1.w);
+  const float wo0 = om0[c0], wo1 = om1[c1];
+  float wn0 = wo0, wn1 = wo1;
+  if (n0 != c0) wn0 = om0[n0];
+  if (n1 != c1) wn1 = om1[n1];
 
-  bool acc0 = false, acc1 = false;
-  uint32_t n_acc = 0;
-#pragma unroll
-  for (int pass = 0; pass < 2; ++pass) {
-    const bool odd = (first ^ (uint32_t)pass) != 0u;
-    // even set needs bead 2k-1 (odd bead of lane k-1); odd set needs bead
-    // 2k+2 (even bead of lane k+1)
-    const F3 send = sel(odd, r0, r1);
-    const int src = odd ? (m.lane < 63 ? m.lane + 1 : m.lane) : (m.lane > 0 ? m.lane - 1 : m.lane);
-    const F3 nb = {shfl_f(send.x, src), shfl_f(send.y, src), shfl_f(send.z, src)};
-    const F3 left = sel(odd, r0, nb);
-    const F3 right = sel(odd, nb, r1);
-    const bool moving = odd ? m.has1 : m.has0;
-    const float wl = (odd || m.k > 0) ? 1.0f : 0.0f;
-    const float wr = (odd ? (i1 + 1u < N) : m.has1) ? 1.0f : 0.0f;
-    const F3 r = sel(odd, r1, r0);
-    const F3 t = sel(odd, t1, t0);
-    const F3 d = {t.x - r.x, t.y - r.y, t.z - r.z};
-    const F3 el = {r.x - left.x, r.y - left.y, r.z - left.z};
-    const F3 er = {r.x - right.x, r.y - right.y, r.z - right.z};
-    // sum_j d.(2 (r - r_j) + d) over the existing bonded neighbours
-    const float qx = wl * (2.0f * el.x + d.x) + wr * (2.0f * er.x + d.x);
-    const float qy = wl * (2.0f * el.y + d.y) + wr * (2.0f * er.y + d.y);
-    const float qz = wl * (2.0f * el.z + d.z) + wr * (2.0f * er.z + d.z);
-    const float d_e = a.half_k0 * (d.x * qx + d.y * qy + d.z * qz) + (odd ? df1 : df0);
-    const float u = odd ? u1 : u0;
-    const bool acc = moving && (d_e <= 0.0f || u < __expf(-d_e));
-    if (odd) { acc1 = acc; r1 = acc ? t1 : r1; }
-    else     { acc0 = acc; r0 = acc ? t0 : r0; }
-    n_acc += (uint32_t)__popcll(__ballot(acc));
+  // relabel by set order: a moves first, b second
+  const F3 ra0 = sel(odd_first, r1, r0), rb0 = sel(odd_first, r0, r1);
+  const F3 ta = sel(odd_first, t1, t0), tb = sel(odd_first, t0, t1);
+  const Rand4 wa = odd_first ? w1 : w0, wb = odd_first ? w0 : w1;
+  const bool has_a = odd_first ? m.has1 : m.has0, has_b = odd_first ? m.has0 : m.has1;
+  const float dfa = ((odd_first ? wn1 : wn0) - (odd_first ? wo1 : wo0)) * a.inv_nref;
+  const float dfb = ((odd_first ? wn0 : wn1) - (odd_first ? wo0 : wo1)) * a.inv_nref;
+  // bonded neighbours of a: own b and b of the adjacent lane (lane k-1 if a is
+  // even, lane k+1 if a is odd); of b: own a and a of the other adjacent lane
+  const int up = m.lane < 63 ? m.lane + 1 : m.lane, dn = m.lane > 0 ? m.lane - 1 : m.lane;
+  const int src_a = odd_first ? up : dn, src_b = odd_first ? dn : up;
+  const bool lo_ok = m.k > 0, hi_ok = i1 + 1u < N;   // beads 2k-1 and 2k+2 exist
+  const float wadj_a = (odd_first ? hi_ok : lo_ok) ? 1.0f : 0.0f;
+  const float wadj_b = (odd_first ? lo_ok : hi_ok) ? 1.0f : 0.0f;
+  const float wown_a = has_b ? 1.0f : 0.0f, wown_b = has_a ? 1.0f : 0.0f;
+
+  // pass 1: set of a
+  F3 ra = ra0;
+  bool acc_a;
+  {
+    const F3 nb = {shfl_f(rb0.x, src_a), shfl_f(rb0.y, src_a), shfl_f(rb0.z, src_a)};
+    const F3 d = ta - ra;
+    const F3 q = wown_a * (2.0f * (ra - rb0) + d) + wadj_a * (2.0f * (ra - nb) + d);
+    const float d_e = a.half_k0 * (d.x * q.x + d.y * q.y + d.z * q.z) + dfa;
+    acc_a = has_a && (d_e <= 0.0f || uniform01(wa.w) < __expf(-d_e));
+    ra = acc_a ? ta : ra;
   }
+  // pass 2: set of b, against the updated a beads
+  F3 rb = rb0;
+  bool acc_b;
+  {
+    const F3 nb = {shfl_f(ra.x, src_b), shfl_f(ra.y, src_b), shfl_f(ra.z, src_b)};
+    const F3 d = tb - rb;
+    const F3 q = wown_b * (2.0f * (rb - ra) + d) + wadj_b * (2.0f * (rb - nb) + d);
+    const float d_e = a.half_k0 * (d.x * q.x + d.y * q.y + d.z * q.z) + dfb;
+    acc_b = has_b && (d_e <= 0.0f || uniform01(wb.w) < __expf(-d_e));
+    rb = acc_b ? tb : rb;
+  }
+  const uint32_t n_acc = (uint32_t)(__popcll(__ballot(acc_a)) + __popcll(__ballot(acc_b)));
 
-  store_pair<VEC2>(cp, m, r0, r1);
+  store_pair<VEC2>(cp, m, sel(odd_first, rb, ra), sel(odd_first, ra, rb));
+  const bool acc0 = odd_first ? acc_b : acc_a, acc1 = odd_first ? acc_a : acc_b;
   if (acc0 && n0 != c0) move_count<COUNT64>(a.counts, c0, n0, b0);
   if (acc1 && n1 != c1) move_count<COUNT64>(a.counts, c1, n1, b1);
-  finish_wave(a, m, n_acc, r0, r1);
+  finish_wave(a, m, n_acc);
 }
 
 // Central-difference gradient of one field plane at cell (cx,cy,cz); the
@@ -336,7 +352,7 @@ __global__ __launch_bounds__(256) void mc_sweep_smc_kernel(const SweepArgs a) {
   store_pair<VEC2>(cp, m, r0, r1);
   if (moved0) move_count<COUNT64>(a.counts, from0, to0, b0);
   if (moved1) move_count<COUNT64>(a.counts, from1, to1, b1);
-  finish_wave(a, m, n_acc, r0, r1);
+  finish_wave(a, m, n_acc);
 }
 
 }  // namespace soma

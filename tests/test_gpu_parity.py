@@ -276,9 +276,12 @@ def test_nonfinite_position_raises_flag(C):
     pos[5] = [np.nan, 1.0, 2.0]
     m = Melt(device_config(w), positions=torch.from_numpy(pos))
     m.sweep(1)
-    assert C.soma_check(m.handle, _stream()) & C.SOMA_FLAG_POSITION
-    with pytest.raises(C.SomaError):
+    with pytest.raises(C.SomaError) as e:
         m.observables()
+    assert e.value.code == C.SOMA_E_DEVICE_FLAG
+    assert C.soma_check(m.handle, _stream()) & C.SOMA_FLAG_POSITION
+    # the NaN bead is never moved, so the histogram stays that of the positions
+    np.testing.assert_array_equal(m.counts_planes()[:, :].sum(), w.n_beads)
 
 
 def test_invalid_configs_rejected(C):
