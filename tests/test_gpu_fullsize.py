@@ -1,0 +1,71 @@
+"""Parity at the benchmark's full size: 4,194,304 A16B16 chains (134,217,728 beads),
+384x384x192 cells, 32-bit counts, chiN = 20, kappaN = 50, in the launch
+configuration bench.py times.
+
+The oracle histograms and fields the whole melt (bit-exact comparison on all
+28.3 M cells) and sweeps a sample of chains spread over the whole range one by
+one; the device sweeps the whole melt.  Bars as in test_gpu_parity.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import Species
+from tests.gpu_helpers import constants, device_config, flush
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def big():
+    w = synth.C2_LARGE
+    k0 = constants(w)[0]
+    flush("generating", w.n_beads, "beads")
+    pos = synth.gaussian_walks(77, w.n_chains, 32, w.grid, 1 / math.sqrt(float(k0)))
+    return w, pos
+
+
+def test_fullsize_histogram_fields_and_sampled_sweep(orc, big):
+    from paper_1711_03828_amd import soma as C
+    from paper_1711_03828_amd.melt import Melt
+    w, pos = big
+    k0, a, A, inv_rho = constants(w)
+    sp = Species(w.n_chains, 32, 16)
+    flush("oracle histogram + fields")
+    counts = orc.density_hist(pos, [sp], w.grid)
+    omega = orc.field_f32(counts, inv_rho, np.float32(w.chi_n), np.float32(w.kappa_n))
+    flush("device init")
+    melt = Melt(device_config(w), positions=torch.from_numpy(pos))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(melt.counts_planes(), counts)
+    np.testing.assert_array_equal(melt.omega.cpu().numpy(), omega)
+    del counts
+
+    flush("device sweep")
+    melt.sweep(1, C.SOMA_MOVE_LOCAL)
+    torch.cuda.synchronize()
+    got = melt.pos.cpu().numpy().reshape(w.n_chains, 32, 3)
+    sample = np.unique(np.linspace(0, w.n_chains - 1, 4096).astype(np.int64))
+    bad = 0
+    for c in sample:
+        ref = pos.reshape(w.n_chains, 32, 3)[c].copy()
+        orc.mc_sweep(ref.reshape(-1, 3), Species(1, 32, 16), omega, w.grid, k0=k0,
+                     n_ref=w.n_ref, step=a, seed=w.seed, sweep=0, chain_base=int(c))
+        bad += int(not np.array_equal(ref, got[c]))
+    allowed = math.ceil(1e-6 * w.n_beads)
+    flush("sampled chains", sample.size, "mismatched", bad, "allowed", allowed)
+    assert bad <= allowed
+    # properties at full size: exact conservation and the kept histogram equals
+    # a from-scratch recount of the device positions
+    obs = melt.observables()
+    assert obs.counts_conserved == 1
+    recount = torch.zeros_like(melt.counts)
+    C.soma_density_hist(melt.cfg, melt.pos.data_ptr(), recount.data_ptr(),
+                        torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(recount, melt.counts)
+    melt.close()

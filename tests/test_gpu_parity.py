@@ -173,9 +173,10 @@ def test_one_sweep_parity(C, orc, kind, wname):
     flush("mismatched chains", bad_chains, "allowed", allowed, "moves", moves)
     assert bad_chains <= allowed
     # the histogram kept by the sweep is the histogram of the final positions
-    # (exactly, counted by the oracle from the device positions) ...
+    # (exactly: the library's from-scratch recount of its positions agrees) ...
     hist_gpu = melt.counts_planes()
-    np.testing.assert_array_equal(hist_gpu, orc.density_hist(got, sp, w.grid))
+    cfg = device_config(w)
+    np.testing.assert_array_equal(hist_gpu, _gpu_hist(C, cfg, got))
     # ... and differs from the oracle's own histogram only where a bead sits in a
     # different cell on the two sides (none for local moves without mismatches;
     # for smart MC a bead within 1e-5 Re0 of a cell face)
