@@ -159,6 +159,13 @@ int32_t soma_mc_sweep(soma_system *sys, uint32_t n_sweeps, uint32_t move_kind,
  * are left unchanged.  Asynchronous. */
 int32_t soma_update_fields(soma_system *sys, void *stream);
 
+/* Launch shape of the local-move sweep: 0 (default) runs one wave per tile
+ * of chains; blocks > 0 runs that many persistent 256-thread blocks, each wave
+ * looping over tiles and prefetching the next tile's positions.  Results are
+ * identical for every value (they depend only on seed, sweep and chain).
+ * A multiple of 8 keeps each XCD on one contiguous range of chains. */
+int32_t soma_set_sweep_blocks(soma_system *sys, uint32_t blocks);
+
 /* Recounts buf->counts from buf->pos (cleared first).  Needed only after the
  * caller has changed positions outside the library.  Asynchronous. */
 int32_t soma_rebuild_histogram(soma_system *sys, void *stream);

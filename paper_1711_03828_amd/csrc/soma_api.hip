@@ -202,6 +202,7 @@ struct soma_system {
   soma::Grid grid;
   uint64_t sweep = 0;
   uint64_t attempted[2] = {0, 0};
+  uint32_t sweep_blocks = 0;  // local-move grid: 0 = one tile per wave, else persistent blocks
   unsigned char *ws = nullptr;
   uint32_t *err() { return reinterpret_cast<uint32_t *>(ws + d.off_err); }
   unsigned long long *acc() { return reinterpret_cast<unsigned long long *>(ws + d.off_acc); }
@@ -249,7 +250,9 @@ int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s) {
     a.replica = c->replica;
     a.set_order = c->set_order;
     const uint64_t chains_per_block = 4ull * a.chains_per_wave;
-    const uint64_t blocks = (S.n_chains + chains_per_block - 1) / chains_per_block;
+    uint64_t blocks = (S.n_chains + chains_per_block - 1) / chains_per_block;
+    if (kind == SOMA_MOVE_LOCAL && sys->sweep_blocks && sys->sweep_blocks < blocks)
+      blocks = sys->sweep_blocks;
     const bool v2 = (S.n % 2 == 0) && (sys->d.bead_off[sp] % 2 == 0) && aligned(a.pos, 8);
     const bool c64 = c->count_width == 32;
     const dim3 grid((uint32_t)blocks);
@@ -348,6 +351,12 @@ int32_t soma_mc_sweep(soma_system *sys, uint32_t n_sweeps, uint32_t move_kind, v
     sys->sweep += 1;
   }
   sys->attempted[move_kind] += (uint64_t)n_sweeps * sys->d.n_beads;
+  return SOMA_OK;
+}
+
+int32_t soma_set_sweep_blocks(soma_system *sys, uint32_t blocks) {
+  if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
+  sys->sweep_blocks = blocks;
   return SOMA_OK;
 }
 

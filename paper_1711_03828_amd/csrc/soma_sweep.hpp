@@ -59,19 +59,24 @@ struct LaneMap {
   uint32_t wib;
 };
 
-__device__ __forceinline__ LaneMap lane_map(const SweepArgs &a) {
+__device__ __forceinline__ LaneMap lane_map_tile(const SweepArgs &a, uint32_t tile, bool valid) {
   LaneMap m;
   m.lane = (int)(threadIdx.x & 63u);
   m.wib = threadIdx.x >> 6;
-  m.tile = xcd_remap(blockIdx.x, gridDim.x);
+  m.tile = tile;
   const uint32_t L = a.lanes_per_chain;
   const uint32_t slot = (uint32_t)m.lane / L;
   m.k = (uint32_t)m.lane - slot * L;
-  m.chain = (m.tile * 4u + m.wib) * a.chains_per_wave + slot;
-  const bool active = slot < a.chains_per_wave && m.chain < a.n_chains;
+  m.chain = tile * a.chains_per_wave + slot;
+  const bool active = valid && slot < a.chains_per_wave && m.chain < a.n_chains;
   m.has0 = active;  // 2k < N for every k < ceil(N/2)
   m.has1 = active && 2u * m.k + 1u < a.n;
   return m;
+}
+
+__device__ __forceinline__ LaneMap lane_map(const SweepArgs &a) {
+  const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x) * 4u + (threadIdx.x >> 6);
+  return lane_map_tile(a, tile, true);
 }
 
 template <bool VEC2>
@@ -122,13 +127,14 @@ __device__ __forceinline__ void move_count(void *counts, uint32_t from, uint32_t
   }
 }
 
-__device__ __forceinline__ void finish_wave(const SweepArgs &a, const LaneMap &m, uint32_t n_acc) {
+// Accepted-move count of the block into one of kAccSlots counters.
+__device__ __forceinline__ void finish_block(const SweepArgs &a, uint32_t n_acc) {
   __shared__ uint32_t s_acc[4];
-  if (m.lane == 0) s_acc[m.wib] = n_acc;
+  if ((threadIdx.x & 63u) == 0u) s_acc[threadIdx.x >> 6] = n_acc;
   __syncthreads();
   if (threadIdx.x == 0) {
     const uint32_t tot = s_acc[0] + s_acc[1] + s_acc[2] + s_acc[3];
-    if (tot) atomicAdd(a.acc_slots + (m.tile & (kAccSlots - 1u)), (unsigned long long)tot);
+    if (tot) atomicAdd(a.acc_slots + (blockIdx.x & (kAccSlots - 1u)), (unsigned long long)tot);
   }
 }
 
@@ -153,41 +159,39 @@ __device__ __forceinline__ uint32_t set_order_bit(const SweepArgs &a, const Lane
 // the passes need no per-pass selection.  Requires a < 1 cell (host-checked):
 // a trial position is then at most one cell away along each axis.
 // ---------------------------------------------------------------------------
+// One wave's tile of local moves: positions r0/r1 already loaded for lane map m.
 template <bool COUNT64, bool VEC2>
-__global__ __launch_bounds__(256) void mc_sweep_local_kernel(const SweepArgs a) {
-  const LaneMap m = lane_map(a);
+__device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap &m, float *cp,
+                                               F3 r0, F3 r1) {
   const uint32_t N = a.n;
   const uint32_t i0 = 2u * m.k, i1 = i0 + 1u;
-  float *cp = a.pos + (size_t)(m.has0 ? m.chain : 0u) * N * 3u + 6u * m.k;
-  F3 r0, r1;
-  load_pair<VEC2>(cp, m, r0, r1);
-
   const uint32_t gchain = a.chain_base + m.chain;
-  const Rand4 w0 = philox(gchain, i0 | (kPurposeMoveA << 16), a.sweep, a.replica, a.seed_lo, a.seed_hi);
-  const Rand4 w1 = philox(gchain, i1 | (kPurposeMoveA << 16), a.sweep, a.replica, a.seed_lo, a.seed_hi);
-  const bool odd_first = set_order_bit(a, m, w0.x) != 0u;
-
-  // trial positions r' = fma(a, v, r)
-  const F3 t0 = {fmaf(a.step, uniform11(w0.x), r0.x), fmaf(a.step, uniform11(w0.y), r0.y),
-                 fmaf(a.step, uniform11(w0.z), r0.z)};
-  const F3 t1 = {fmaf(a.step, uniform11(w1.x), r1.x), fmaf(a.step, uniform11(w1.y), r1.y),
-                 fmaf(a.step, uniform11(w1.z), r1.z)};
-  // old and trial cells
+  // old cells and their field values first: they need only the positions
   uint32_t x0, y0, z0, x1, y1, z1;
   cell3(a.grid, r0.x, r0.y, r0.z, x0, y0, z0);
   cell3(a.grid, r1.x, r1.y, r1.z, x1, y1, z1);
   const uint32_t c0 = cell_index(a.grid, x0, y0, z0);
   const uint32_t c1 = cell_index(a.grid, x1, y1, z1);
+  const bool b0 = i0 >= a.n_a, b1 = i1 >= a.n_a;
+  const float *om0 = a.omega + (b0 ? a.grid.n_cells : 0u);
+  const float *om1 = a.omega + (b1 ? a.grid.n_cells : 0u);
+  const float wo0 = om0[c0], wo1 = om1[c1];
+
+  const Rand4 w0 = philox(gchain, i0 | (kPurposeMoveA << 16), a.sweep, a.replica, a.seed_lo, a.seed_hi);
+  const Rand4 w1 = philox(gchain, i1 | (kPurposeMoveA << 16), a.sweep, a.replica, a.seed_lo, a.seed_hi);
+  const bool odd_first = set_order_bit(a, m, w0.x) != 0u;
+
+  // trial positions r' = fma(a, v, r) and their cells (at most one cell away)
+  const F3 t0 = {fmaf(a.step, uniform11(w0.x), r0.x), fmaf(a.step, uniform11(w0.y), r0.y),
+                 fmaf(a.step, uniform11(w0.z), r0.z)};
+  const F3 t1 = {fmaf(a.step, uniform11(w1.x), r1.x), fmaf(a.step, uniform11(w1.y), r1.y),
+                 fmaf(a.step, uniform11(w1.z), r1.z)};
   const uint32_t n0 = cell_index(a.grid, shift_cell(x0, r0.x, t0.x, a.grid.nx),
                                  shift_cell(y0, r0.y, t0.y, a.grid.ny),
                                  shift_cell(z0, r0.z, t0.z, a.grid.nz));
   const uint32_t n1 = cell_index(a.grid, shift_cell(x1, r1.x, t1.x, a.grid.nx),
                                  shift_cell(y1, r1.y, t1.y, a.grid.ny),
                                  shift_cell(z1, r1.z, t1.z, a.grid.nz));
-  const bool b0 = i0 >= a.n_a, b1 = i1 >= a.n_a;
-  const float *om0 = a.omega + (b0 ? a.grid.n_cells : 0u);
-  const float *om1 = a.omega + (b1 ? a.grid.n_cells : 0u);
-  const float wo0 = om0[c0], wo1 = om1[c1];
   float wn0 = wo0, wn1 = wo1;
   if (n0 != c0) wn0 = om0[n0];
   if (n1 != c1) wn1 = om1[n1];
@@ -230,13 +234,62 @@ __global__ __launch_bounds__(256) void mc_sweep_local_kernel(const SweepArgs a) 
     acc_b = has_b && (d_e <= 0.0f || uniform01(wb.w) < __expf(-d_e));
     rb = acc_b ? tb : rb;
   }
-  const uint32_t n_acc = (uint32_t)(__popcll(__ballot(acc_a)) + __popcll(__ballot(acc_b)));
-
   store_pair<VEC2>(cp, m, sel(odd_first, rb, ra), sel(odd_first, ra, rb));
   const bool acc0 = odd_first ? acc_b : acc_a, acc1 = odd_first ? acc_a : acc_b;
   if (acc0 && n0 != c0) move_count<COUNT64>(a.counts, c0, n0, b0);
   if (acc1 && n1 != c1) move_count<COUNT64>(a.counts, c1, n1, b1);
-  finish_wave(a, m, n_acc);
+  return (uint32_t)(__popcll(__ballot(acc_a)) + __popcll(__ballot(acc_b)));
+}
+
+// ---------------------------------------------------------------------------
+// Local moves (Sec. 2.2, move (i)): uniform trial displacement in [-a,a] per
+// Cartesian direction, Metropolis acceptance of
+//   dE = (k0/2) sum_bonds (|r'-r_j|^2 - |r-r_j|^2) + (omega_t(c') - omega_t(c))/N.
+// A trial position depends only on the bead itself, so both trial positions of
+// a lane and the field values they need are fetched before either set moves;
+// only the bond term waits for the other set.  Per lane the two beads are
+// relabelled once by the chain's set order ("a" moves first, "b" second), so
+// the passes need no per-pass selection.  Requires a < 1 cell (host-checked):
+// a trial position is then at most one cell away along each axis.
+//
+// Tiles (one wave's chains) are dealt XCD by XCD: the tiles of XCD x are the
+// contiguous range [x T/8, (x+1) T/8), walked by that XCD's waves in order, so
+// the waves running together on one XCD share one compact region of the grid.
+// With fewer waves than tiles each wave loops, loading the next tile's
+// positions while it works on the current one.
+// ---------------------------------------------------------------------------
+template <bool COUNT64, bool VEC2>
+__global__ __launch_bounds__(256) void mc_sweep_local_kernel(const SweepArgs a) {
+  const uint32_t n_tiles = (a.n_chains + a.chains_per_wave - 1u) / a.chains_per_wave;
+  const uint32_t blocks = gridDim.x;
+  // XCD split only when the grid is a multiple of 8 blocks
+  const uint32_t parts = (blocks & 7u) == 0u ? 8u : 1u;
+  const uint32_t part = blockIdx.x % parts;
+  const uint32_t waves_per_part = (blocks / parts) * 4u;
+  const uint32_t wave_in_part = (blockIdx.x / parts) * 4u + (threadIdx.x >> 6);
+  const uint32_t t_begin = (uint32_t)(((uint64_t)n_tiles * part) / parts);
+  const uint32_t t_end = (uint32_t)(((uint64_t)n_tiles * (part + 1u)) / parts);
+
+  uint32_t n_acc = 0;
+  uint32_t t = t_begin + wave_in_part;
+  LaneMap m = lane_map_tile(a, t < t_end ? t : 0u, t < t_end);
+  float *cp = a.pos + (size_t)(m.has0 ? m.chain : 0u) * a.n * 3u + 6u * m.k;
+  F3 r0, r1;
+  load_pair<VEC2>(cp, m, r0, r1);
+  while (t < t_end) {
+    const uint32_t tn = t + waves_per_part;
+    const LaneMap mn = lane_map_tile(a, tn < t_end ? tn : 0u, tn < t_end);
+    float *cpn = a.pos + (size_t)(mn.has0 ? mn.chain : 0u) * a.n * 3u + 6u * mn.k;
+    F3 s0, s1;
+    load_pair<VEC2>(cpn, mn, s0, s1);    // next tile, in flight during this one
+    n_acc += local_tile<COUNT64, VEC2>(a, m, cp, r0, r1);
+    m = mn;
+    cp = cpn;
+    r0 = s0;
+    r1 = s1;
+    t = tn;
+  }
+  finish_block(a, n_acc);
 }
 
 // Central-difference gradient of one field plane at cell (cx,cy,cz); the
@@ -352,7 +405,7 @@ __global__ __launch_bounds__(256) void mc_sweep_smc_kernel(const SweepArgs a) {
   store_pair<VEC2>(cp, m, r0, r1);
   if (moved0) move_count<COUNT64>(a.counts, from0, to0, b0);
   if (moved1) move_count<COUNT64>(a.counts, from1, to1, b1);
-  finish_wave(a, m, n_acc);
+  finish_block(a, n_acc);
 }
 
 }  // namespace soma

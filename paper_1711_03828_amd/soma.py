@@ -86,6 +86,7 @@ _SIGS = {
     "soma_mc_sweep": ([_P, _u32, _u32, _P], _i32),
     "soma_update_fields": ([_P, _P], _i32),
     "soma_rebuild_histogram": ([_P, _P], _i32),
+    "soma_set_sweep_blocks": ([_P, _u32], _i32),
     "soma_observables": ([_P, ctypes.POINTER(soma_obs), _P], _i32),
     "soma_check": ([_P, _pu32, _P], _i32),
     "soma_get_sweep": ([_P, _pu64], _i32),
@@ -137,6 +138,10 @@ def soma_mc_sweep(h, n_sweeps: int, move_kind: int, stream: int) -> None:
 
 def soma_update_fields(h, stream: int) -> None:
     _check(_lib.soma_update_fields(h, ctypes.c_void_p(stream)))
+
+
+def soma_set_sweep_blocks(h, blocks: int) -> None:
+    _check(_lib.soma_set_sweep_blocks(h, blocks))
 
 
 def soma_rebuild_histogram(h, stream: int) -> None:
