@@ -196,3 +196,108 @@ def field_energy(pos, sp: Species, omega, grid, n_ref) -> float:
     omega = _c(omega, np.float32)
     return lib().orc_field_energy(_ptr(pos), sp.n_chains, sp.n, sp.n_a, _ptr(omega),
                                   *grid, n_ref)
+
+
+# --------------------------------------------------------------------------
+# Learned proposal (network, loss, features, mixed sweep)
+# --------------------------------------------------------------------------
+MOVE_MIXED = 2
+NF, NH, NO = 60, 64, 6
+
+
+def _lib_mlp():
+    L = lib()
+    if getattr(L, "_mlp_ready", False):
+        return L
+    P = ctypes.c_void_p
+    u32, u64, f32, f64, i32 = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float,
+                               ctypes.c_double, ctypes.c_int)
+    L.orc_param_layout.argtypes = [u32]
+    L.orc_param_layout.restype = u32
+    L.orc_bf16.argtypes = [f32]
+    L.orc_bf16.restype = f32
+    L.orc_mlp_forward.argtypes = [P, P, i32, P, P]
+    L.orc_mlp_backward.argtypes = [P, P, P, i32, P]
+    L.orc_nll.argtypes = [P, P, f64, f64, f64, P]
+    L.orc_nll.restype = f64
+    L.orc_nll_batch.argtypes = [P, u64, P, P, f64, f64, f64, i32, P, P]
+    L.orc_nll_batch.restype = f64
+    L.orc_features_batch.argtypes = [P, u32, u32, u32, P, P, u32, u32, u32, P]
+    L.orc_mc_sweep_mixed.argtypes = [P, u32, u32, u32, f32, u32, P, u32, u32, u32, f32, f32,
+                                     P, f32, f32, f32, i32, u64, u32, u32, u32, u32, P, P, P,
+                                     P, i32]
+    L.orc_mc_sweep_mixed.restype = u64
+    L._mlp_ready = True
+    return L
+
+
+def param_layout():
+    L = _lib_mlp()
+    names = ["shift", "scale", "w1", "b1", "w2", "b2", "w3", "b3", "size"]
+    return {n: int(L.orc_param_layout(i)) for i, n in enumerate(names)}
+
+
+def bf16(x: float) -> float:
+    return _lib_mlp().orc_bf16(float(x))
+
+
+def mlp_forward(params: np.ndarray, features: np.ndarray, bf16_mode=False):
+    """z [n, 6] for features [n, 60]."""
+    L = _lib_mlp()
+    params = _c(params, np.float32)
+    f = _c(features, np.float64).reshape(-1, NF)
+    z = np.empty((f.shape[0], NO))
+    for s in range(f.shape[0]):
+        zs = np.empty(NO)
+        L.orc_mlp_forward(_ptr(params), _ptr(f[s]), int(bf16_mode), _ptr(zs), None)
+        z[s] = zs
+    return z
+
+
+def nll_batch(params, features, targets, *, m_max, lo, hi, bf16_mode=False):
+    """(mean NLL, gradient [P], z [n, 6])."""
+    L = _lib_mlp()
+    params = _c(params, np.float32)
+    f = _c(features, np.float64).reshape(-1, NF)
+    t = _c(targets, np.float64).reshape(-1, 3)
+    grad = np.zeros(param_layout()["size"])
+    z = np.empty((f.shape[0], NO))
+    loss = L.orc_nll_batch(_ptr(params), f.shape[0], _ptr(f), _ptr(t), m_max, lo, hi,
+                           int(bf16_mode), _ptr(grad), _ptr(z))
+    return loss, grad, z
+
+
+def features(pos, sp: Species, beads, omega, grid):
+    """Features of bead beads[c] of chain c, [n_chains, 60]."""
+    L = _lib_mlp()
+    pos = _c(pos, np.float32)
+    b = _c(beads, np.uint32)
+    omega = _c(omega, np.float32)
+    out = np.empty((sp.n_chains, NF))
+    L.orc_features_batch(_ptr(pos), sp.n_chains, sp.n, sp.n_a, _ptr(b), _ptr(omega), *grid,
+                         _ptr(out))
+    return out
+
+
+def mc_sweep_mixed(pos, sp: Species, omega, grid, *, k0, n_ref, local_a, p_learn, params,
+                   m_max, lo, hi, bf16_mode=True, seed, sweep, replica=0, chain_base=0,
+                   set_order=0, want_flags=False, threads=1):
+    """In-place mixed (local / learned) sweep.  Returns (accepted, accepted_learned,
+    bad_net, kind_flags, accept_flags)."""
+    L = _lib_mlp()
+    assert pos.dtype == np.float32 and pos.flags.c_contiguous
+    params = _c(params, np.float32)
+    omega = _c(omega, np.float32)
+    kf = np.zeros(sp.n_chains * sp.n, np.uint8) if want_flags else None
+    af = np.zeros(sp.n_chains * sp.n, np.uint8) if want_flags else None
+    acc_l = ctypes.c_uint64()
+    bad = ctypes.c_uint32()
+    acc = L.orc_mc_sweep_mixed(_ptr(pos), sp.n_chains, sp.n, sp.n_a, float(np.float32(k0)), n_ref,
+                               _ptr(omega), *grid, float(np.float32(local_a)),
+                               float(np.float32(p_learn)), _ptr(params), float(np.float32(m_max)),
+                               float(np.float32(lo)), float(np.float32(hi)), int(bf16_mode), seed,
+                               sweep, replica, chain_base, set_order,
+                               _ptr(kf) if kf is not None else None,
+                               _ptr(af) if af is not None else None,
+                               ctypes.byref(acc_l), ctypes.byref(bad), threads)
+    return acc, acc_l.value, bad.value, kf, af

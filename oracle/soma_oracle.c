@@ -520,3 +520,317 @@ double orc_field_energy(const float *pos, uint32_t n_chains, uint32_t n,
     }
   return e / (double)n_ref;
 }
+
+/* ========================================================================= */
+/* Learned proposal (not part of the paper: an addition to its local and     */
+/* smart-MC moves, Sec. 2.2, that keeps the sampled distribution exact by     */
+/* Metropolis-Hastings with the proposal ratio).                              */
+/*                                                                            */
+/* Features of bead i at position r (60): the per-chain fields of the bead's  */
+/* own type at the 27 cells around its cell, then those of the other type    */
+/* (cells in (dz, dy, dx) order, each -1..1, periodic), then the bond vectors */
+/* r_{i-1} - r and r_{i+1} - r (zero where the neighbour does not exist).     */
+/* Standardised per feature: (f - shift) * scale.                             */
+/* Network: h1 = silu(W1 x + b1), h2 = silu(W2 h1 + b2), z = W3 h2 + b3       */
+/* (60 -> 64 -> 64 -> 6).  Head: mu_d = m tanh(z_d / m),                      */
+/* log sigma_d = lo + (hi - lo) sigmoid(z_{3+d}).                             */
+/* Proposal: r' = r + mu(r) + sigma(r) xi, xi ~ N(0,1)^3.                     */
+/* BF16 mode rounds the standardised input, every weight and each hidden      */
+/* activation to bfloat16 (round to nearest even) at the points the device    */
+/* does, accumulating in FP64.                                                */
+/* ========================================================================= */
+#define ORC_NF 60
+#define ORC_NH 64
+#define ORC_NO 6
+#define ORC_P_SHIFT 0
+#define ORC_P_SCALE 60
+#define ORC_P_W1 120
+#define ORC_P_B1 3960
+#define ORC_P_W2 4024
+#define ORC_P_B2 8120
+#define ORC_P_W3 8184
+#define ORC_P_B3 8568
+#define ORC_P_SIZE 8576
+#define ORC_MOVE_MIXED 2u
+#define ORC_PURPOSE_MIX 1u
+
+uint32_t orc_param_layout(uint32_t which) {
+  const uint32_t v[] = {ORC_P_SHIFT, ORC_P_SCALE, ORC_P_W1, ORC_P_B1, ORC_P_W2,
+                        ORC_P_B2, ORC_P_W3, ORC_P_B3, ORC_P_SIZE};
+  return which < 9 ? v[which] : 0u;
+}
+
+/* float -> bfloat16 -> float, round to nearest even */
+float orc_bf16(float x) {
+  uint32_t u;
+  memcpy(&u, &x, 4);
+  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return x; /* NaN unchanged */
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  u &= 0xFFFF0000u;
+  memcpy(&x, &u, 4);
+  return x;
+}
+
+static double orc_silu(double a) { return a / (1.0 + exp(-a)); }
+static double orc_dsilu(double a) {
+  double s = 1.0 / (1.0 + exp(-a));
+  return s * (1.0 + a * (1.0 - s));
+}
+
+/* cache layout: x[60] a1[64] h1[64] a2[64] h2[64] */
+void orc_mlp_forward(const float *p, const double *f, int bf16, double *z,
+                     double *cache) {
+  double x[ORC_NF], a1[ORC_NH], h1[ORC_NH], a2[ORC_NH], h2[ORC_NH];
+  for (int k = 0; k < ORC_NF; ++k) {
+    float s = ((float)f[k] - p[ORC_P_SHIFT + k]) * p[ORC_P_SCALE + k];
+    x[k] = bf16 ? (double)orc_bf16(s) : (f[k] - p[ORC_P_SHIFT + k]) * p[ORC_P_SCALE + k];
+  }
+#define ORC_W(off, idx) (bf16 ? (double)orc_bf16(p[(off) + (idx)]) : (double)p[(off) + (idx)])
+  for (int m = 0; m < ORC_NH; ++m) {
+    double acc = 0.0;
+    for (int k = 0; k < ORC_NF; ++k) acc += ORC_W(ORC_P_W1, m * ORC_NF + k) * x[k];
+    a1[m] = acc + p[ORC_P_B1 + m];
+    h1[m] = orc_silu(a1[m]);
+    if (bf16) h1[m] = orc_bf16((float)h1[m]);
+  }
+  for (int m = 0; m < ORC_NH; ++m) {
+    double acc = 0.0;
+    for (int k = 0; k < ORC_NH; ++k) acc += ORC_W(ORC_P_W2, m * ORC_NH + k) * h1[k];
+    a2[m] = acc + p[ORC_P_B2 + m];
+    h2[m] = orc_silu(a2[m]);
+    if (bf16) h2[m] = orc_bf16((float)h2[m]);
+  }
+  for (int o = 0; o < ORC_NO; ++o) {
+    double acc = 0.0;
+    for (int k = 0; k < ORC_NH; ++k) acc += ORC_W(ORC_P_W3, o * ORC_NH + k) * h2[k];
+    z[o] = acc + p[ORC_P_B3 + o];
+  }
+#undef ORC_W
+  if (cache) {
+    memcpy(cache, x, sizeof x);
+    memcpy(cache + ORC_NF, a1, sizeof a1);
+    memcpy(cache + ORC_NF + ORC_NH, h1, sizeof h1);
+    memcpy(cache + ORC_NF + 2 * ORC_NH, a2, sizeof a2);
+    memcpy(cache + ORC_NF + 3 * ORC_NH, h2, sizeof h2);
+  }
+}
+
+/* Back-propagation of dL/dz through the network (plain chain rule), adding
+ * dL/dparam into grad (ORC_P_SIZE doubles; standardisation constants get no
+ * gradient).  Uses the same (possibly bf16-rounded) weights and activations as
+ * the forward pass that filled `cache`. */
+void orc_mlp_backward(const float *p, const double *cache, const double *dz,
+                      int bf16, double *grad) {
+  const double *x = cache, *a1 = cache + ORC_NF, *h1 = cache + ORC_NF + ORC_NH,
+               *a2 = cache + ORC_NF + 2 * ORC_NH, *h2 = cache + ORC_NF + 3 * ORC_NH;
+#define ORC_W(off, idx) (bf16 ? (double)orc_bf16(p[(off) + (idx)]) : (double)p[(off) + (idx)])
+  double d2[ORC_NH], d1[ORC_NH];
+  for (int o = 0; o < ORC_NO; ++o) {
+    grad[ORC_P_B3 + o] += dz[o];
+    for (int k = 0; k < ORC_NH; ++k) grad[ORC_P_W3 + o * ORC_NH + k] += dz[o] * h2[k];
+  }
+  for (int k = 0; k < ORC_NH; ++k) {
+    double s = 0.0;
+    for (int o = 0; o < ORC_NO; ++o) s += ORC_W(ORC_P_W3, o * ORC_NH + k) * dz[o];
+    d2[k] = s * orc_dsilu(a2[k]);
+  }
+  for (int m = 0; m < ORC_NH; ++m) {
+    grad[ORC_P_B2 + m] += d2[m];
+    for (int k = 0; k < ORC_NH; ++k) grad[ORC_P_W2 + m * ORC_NH + k] += d2[m] * h1[k];
+  }
+  for (int k = 0; k < ORC_NH; ++k) {
+    double s = 0.0;
+    for (int m = 0; m < ORC_NH; ++m) s += ORC_W(ORC_P_W2, m * ORC_NH + k) * d2[m];
+    d1[k] = s * orc_dsilu(a1[k]);
+  }
+  for (int m = 0; m < ORC_NH; ++m) {
+    grad[ORC_P_B1 + m] += d1[m];
+    for (int k = 0; k < ORC_NF; ++k) grad[ORC_P_W1 + m * ORC_NF + k] += d1[m] * x[k];
+  }
+#undef ORC_W
+}
+
+/* Gaussian head: mu, sigma, log sigma from z. */
+static void orc_head(const double *z, double m_max, double lo, double hi,
+                     double *mu, double *sig, double *lsig) {
+  for (int d = 0; d < 3; ++d) {
+    mu[d] = m_max * tanh(z[d] / m_max);
+    double sg = 1.0 / (1.0 + exp(-z[3 + d]));
+    lsig[d] = lo + (hi - lo) * sg;
+    sig[d] = exp(lsig[d]);
+  }
+}
+
+/* Negative log-likelihood (without the constant 3/2 log 2 pi) of a
+ * displacement dr under the head's Gaussian, and dL/dz. */
+double orc_nll(const double *z, const double *dr, double m_max, double lo,
+               double hi, double *dz) {
+  double loss = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    double mu = m_max * tanh(z[d] / m_max);
+    double sg = 1.0 / (1.0 + exp(-z[3 + d]));
+    double ls = lo + (hi - lo) * sg;
+    double inv_var = exp(-2.0 * ls);
+    double e = dr[d] - mu;
+    loss += 0.5 * e * e * inv_var + ls;
+    double dmu = -e * inv_var;
+    double dls = 1.0 - e * e * inv_var;
+    dz[d] = dmu * (1.0 - (mu / m_max) * (mu / m_max));
+    dz[3 + d] = dls * (hi - lo) * sg * (1.0 - sg);
+  }
+  return loss;
+}
+
+/* Mean NLL over a batch and its gradient (grad: ORC_P_SIZE doubles,
+ * overwritten).  features [n][60], targets [n][3]. */
+double orc_nll_batch(const float *p, uint64_t n, const double *features,
+                     const double *targets, double m_max, double lo, double hi,
+                     int bf16, double *grad, double *z_out) {
+  double cache[ORC_NF + 4 * ORC_NH], z[ORC_NO], dz[ORC_NO];
+  memset(grad, 0, ORC_P_SIZE * sizeof(double));
+  double total = 0.0;
+  for (uint64_t s = 0; s < n; ++s) {
+    orc_mlp_forward(p, features + s * ORC_NF, bf16, z, cache);
+    if (z_out) memcpy(z_out + s * ORC_NO, z, sizeof z);
+    total += orc_nll(z, targets + 3 * s, m_max, lo, hi, dz);
+    for (int o = 0; o < ORC_NO; ++o) dz[o] /= (double)n;
+    orc_mlp_backward(p, cache, dz, bf16, grad);
+  }
+  return total / (double)n;
+}
+
+void orc_features(const float *chain, uint32_t i, uint32_t n, uint32_t n_a,
+                  const float *omega, uint32_t nx, uint32_t ny, uint32_t nz,
+                  const float *r, double *f) {
+  uint64_t n_cells = (uint64_t)nx * ny * nz;
+  uint32_t own = orc_type(i, n_a);
+  const float *om_own = omega + (uint64_t)own * n_cells;
+  const float *om_oth = omega + (uint64_t)(1u - own) * n_cells;
+  int64_t c[3] = {orc_wrap((double)r[0], nx), orc_wrap((double)r[1], ny),
+                  orc_wrap((double)r[2], nz)};
+  int j = 0;
+  for (int dz_ = -1; dz_ <= 1; ++dz_)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx, ++j) {
+        int64_t x = ((c[0] + dx) % nx + nx) % nx;
+        int64_t y = ((c[1] + dy) % ny + ny) % ny;
+        int64_t zz = ((c[2] + dz_) % nz + nz) % nz;
+        uint64_t cell = ((uint64_t)zz * ny + (uint64_t)y) * nx + (uint64_t)x;
+        f[j] = om_own[cell];
+        f[27 + j] = om_oth[cell];
+      }
+  for (int d = 0; d < 3; ++d) {
+    f[54 + d] = i > 0 ? (double)chain[3 * (i - 1) + d] - (double)r[d] : 0.0;
+    f[57 + d] = i + 1 < n ? (double)chain[3 * (i + 1) + d] - (double)r[d] : 0.0;
+  }
+}
+
+/* Features of bead `bead` of every chain of a species (for the training data
+ * and the tests): out [n_chains][60]. */
+void orc_features_batch(const float *pos, uint32_t n_chains, uint32_t n, uint32_t n_a,
+                        const uint32_t *beads, const float *omega, uint32_t nx,
+                        uint32_t ny, uint32_t nz, double *out) {
+  for (uint32_t c = 0; c < n_chains; ++c) {
+    const float *chain = pos + (uint64_t)c * n * 3;
+    orc_features(chain, beads[c], n, n_a, omega, nx, ny, nz, chain + 3 * beads[c],
+                 out + (uint64_t)c * ORC_NF);
+  }
+}
+
+/* Mixed sweep: each bead makes the learned move with probability p_learn
+ * (uniform from word 1 of its purpose-1 draw, independent of the state) and
+ * the local move otherwise.  A learned move draws xi by Box-Muller from the
+ * purpose-0 block and accepts with word 0 of the purpose-1 block; a network
+ * output that is not finite at r or r' rejects the move (q = 0). */
+static int orc_move_learned(float *chain, uint32_t c_id, uint32_t i, uint32_t n,
+                            uint32_t n_a, double k0, const float *omega,
+                            uint64_t n_cells, uint32_t nx, uint32_t ny, uint32_t nz,
+                            uint32_t n_ref, const float *params, double m_max,
+                            double lo, double hi, int bf16, uint64_t seed,
+                            uint32_t sweep, uint32_t replica, uint32_t *bad_net) {
+  uint32_t wa[4], wb[4];
+  orc_draw(seed, c_id, i, ORC_PURPOSE_MOVE_A, sweep, replica, wa);
+  orc_draw(seed, c_id, i, ORC_PURPOSE_MOVE_B, sweep, replica, wb);
+  double xi[4];
+  orc_box_muller(wa[0], wa[1], &xi[0], &xi[1]);
+  orc_box_muller(wa[2], wa[3], &xi[2], &xi[3]);
+  float *r = chain + 3 * i;
+  double f[ORC_NF], z[ORC_NO], mu[3], sig[3], lsig[3];
+  orc_features(chain, i, n, n_a, omega, nx, ny, nz, r, f);
+  orc_mlp_forward(params, f, bf16, z, NULL);
+  orc_head(z, m_max, lo, hi, mu, sig, lsig);
+  float trial[3];
+  for (int d = 0; d < 3; ++d)
+    trial[d] = (float)((double)r[d] + mu[d] + sig[d] * xi[d]);
+  double fn[ORC_NF], zn[ORC_NO], mun[3], sign[3], lsign[3];
+  orc_features(chain, i, n, n_a, omega, nx, ny, nz, trial, fn);
+  orc_mlp_forward(params, fn, bf16, zn, NULL);
+  orc_head(zn, m_max, lo, hi, mun, sign, lsign);
+  for (int d = 0; d < 6; ++d)
+    if (!isfinite(z[d]) || !isfinite(zn[d])) { (*bad_net)++; return 0; }
+  double log_fwd = 0.0, log_rev = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    double ef = (double)trial[d] - (double)r[d] - mu[d];
+    double er = (double)r[d] - (double)trial[d] - mun[d];
+    log_fwd -= ef * ef / (2.0 * sig[d] * sig[d]) + lsig[d];
+    log_rev -= er * er / (2.0 * sign[d] * sign[d]) + lsign[d];
+  }
+  double d_bond = orc_bond_energy(trial, chain, i, n, k0) - orc_bond_energy(r, chain, i, n, k0);
+  const float *om = omega + (uint64_t)orc_type(i, n_a) * n_cells;
+  double d_field = ((double)om[orc_cell(trial, nx, ny, nz)] -
+                    (double)om[orc_cell(r, nx, ny, nz)]) / (double)n_ref;
+  double log_ratio = -(d_bond + d_field) + log_rev - log_fwd;
+  double u = (double)orc_u01(wb[0]);
+  int accept = (log_ratio >= 0.0) || (u < exp(log_ratio));
+  if (accept) memcpy(r, trial, sizeof trial);
+  return accept;
+}
+
+uint64_t orc_mc_sweep_mixed(float *pos, uint32_t n_chains, uint32_t n, uint32_t n_a,
+                            float k0, uint32_t n_ref, const float *omega, uint32_t nx,
+                            uint32_t ny, uint32_t nz, float local_a, float p_learn,
+                            const float *params, float m_max, float lo, float hi, int bf16,
+                            uint64_t seed, uint32_t sweep, uint32_t replica,
+                            uint32_t chain_base, uint32_t set_order, uint8_t *kind_flags,
+                            uint8_t *accept_flags, uint64_t *accepted_learned,
+                            uint32_t *bad_net, int n_threads) {
+  uint64_t n_cells = (uint64_t)nx * ny * nz;
+  uint64_t acc_total = 0, acc_l = 0;
+  uint32_t bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : acc_total, acc_l, bad) num_threads(n_threads > 0 ? n_threads : 1)
+  for (int64_t c = 0; c < (int64_t)n_chains; ++c) {
+    float *chain = pos + (uint64_t)c * n * 3;
+    uint32_t c_id = chain_base + (uint32_t)c;
+    uint32_t first = 0;
+    if (set_order == 0) {
+      uint32_t w[4];
+      orc_draw(seed, c_id, 0, ORC_PURPOSE_MOVE_A, sweep, replica, w);
+      first = w[0] & 1u;
+    }
+    for (uint32_t pass = 0; pass < 2; ++pass) {
+      uint32_t parity = pass == 0 ? first : 1u - first;
+      for (uint32_t i = parity; i < n; i += 2) {
+        uint32_t wb[4];
+        orc_draw(seed, c_id, i, ORC_PURPOSE_MOVE_B, sweep, replica, wb);
+        int learned = (double)orc_u01(wb[1]) < (double)p_learn;
+        int acc;
+        uint32_t b = 0;
+        if (learned)
+          acc = orc_move_learned(chain, c_id, i, n, n_a, (double)k0, omega, n_cells, nx, ny,
+                                 nz, n_ref, params, m_max, lo, hi, bf16, seed, sweep,
+                                 replica, &b);
+        else
+          acc = orc_move_local(chain, c_id, i, n, n_a, (double)k0, omega, n_cells, nx, ny,
+                               nz, n_ref, local_a, seed, sweep, replica);
+        bad += b;
+        acc_total += (uint64_t)acc;
+        if (learned) acc_l += (uint64_t)acc;
+        if (kind_flags) kind_flags[(uint64_t)c * n + i] = (uint8_t)learned;
+        if (accept_flags) accept_flags[(uint64_t)c * n + i] = (uint8_t)acc;
+      }
+    }
+  }
+  if (accepted_learned) *accepted_learned = acc_l;
+  if (bad_net) *bad_net = bad;
+  return acc_total;
+}

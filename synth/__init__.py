@@ -109,3 +109,28 @@ def boundary_positions(grid) -> np.ndarray:
     for i, x in enumerate(vals_x):
         out.append([x, (x * 0.5 + i) % (2 * ny) - ny / 2, -x + 0.25 * i])
     return np.asarray(out, np.float32)
+
+
+# Parameter blob of the learned proposal's network (FP32, flat).  This is an
+# interface format shared by every consumer: per-feature standardisation
+# (shift[60], scale[60]), then W1[64][60], b1[64], W2[64][64], b2[64],
+# W3[6][64], b3[6], padded to 8576 floats.
+MLP_LAYOUT = {"shift": 0, "scale": 60, "w1": 120, "b1": 3960, "w2": 4024, "b2": 8120,
+              "w3": 8184, "b3": 8568, "size": 8576}
+
+
+def mlp_params(seed: int, *, shift=None, scale=None, weight_gain=1.0, out_gain=0.1) -> np.ndarray:
+    """Random network weights (He-like scaling), standardisation constants given
+    or identity; output layer scaled by out_gain."""
+    g = rng(seed)
+    L = MLP_LAYOUT
+    p = np.zeros(L["size"], np.float32)
+    p[L["shift"]:L["shift"] + 60] = 0.0 if shift is None else shift
+    p[L["scale"]:L["scale"] + 60] = 1.0 if scale is None else scale
+    p[L["w1"]:L["w1"] + 3840] = g.standard_normal(3840) * weight_gain / np.sqrt(60)
+    p[L["b1"]:L["b1"] + 64] = g.standard_normal(64) * 0.1
+    p[L["w2"]:L["w2"] + 4096] = g.standard_normal(4096) * weight_gain / np.sqrt(64)
+    p[L["b2"]:L["b2"] + 64] = g.standard_normal(64) * 0.1
+    p[L["w3"]:L["w3"] + 384] = g.standard_normal(384) * out_gain / np.sqrt(64)
+    p[L["b3"]:L["b3"] + 6] = g.standard_normal(6) * out_gain
+    return p

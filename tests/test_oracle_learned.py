@@ -1,0 +1,139 @@
+"""Pins of the oracle's learned proposal (network, loss, features, mixed move).
+
+* back-propagation equals central finite differences of the FP64 loss
+  (relative error < 1e-6 on every parameter group);
+* bfloat16 rounding equals the library converter (torch, round to nearest even);
+* BF16-emulating forward stays close to FP64 (rounding only);
+* features: hand-checked own/other field blocks, cell order and bond vectors;
+* exactness of Metropolis-Hastings: 3-bead chain in a frozen random field with
+  random (untrained) network weights, pure learned and 50/50 mixed moves,
+  matches the exact Boltzmann distribution (MH exactness does not depend on
+  training).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import Species, references
+
+HEAD = dict(m_max=1.0, lo=math.log(0.02), hi=math.log(1.0))
+
+
+def _batch(n, seed):
+    g = np.random.default_rng(seed)
+    f = g.standard_normal((n, 60))
+    t = g.standard_normal((n, 3)) * 0.3
+    return f, t
+
+
+def test_gradient_matches_finite_differences(orc):
+    p = synth.mlp_params(3, weight_gain=1.3, out_gain=0.8).astype(np.float64)
+    f, t = _batch(16, 4)
+    loss, grad, _ = orc.nll_batch(p.astype(np.float32), f, t, **HEAD)
+    L = synth.MLP_LAYOUT
+    g = np.random.default_rng(5)
+    # parameters are stored as float32, so perturb by a step that float32 holds
+    for name, size in (("w1", 3840), ("b1", 64), ("w2", 4096), ("b2", 64), ("w3", 384),
+                       ("b3", 6)):
+        for idx in g.choice(size, min(size, 6), replace=False):
+            k = L[name] + int(idx)
+            h = 2.0 ** -10
+            pp = p.copy(); pp[k] += h
+            pm = p.copy(); pm[k] -= h
+            lp, _, _ = orc.nll_batch(pp.astype(np.float32), f, t, **HEAD)
+            lm, _, _ = orc.nll_batch(pm.astype(np.float32), f, t, **HEAD)
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - grad[k]) <= 1e-6 * max(1.0, abs(grad[k])) + 2e-7, (name, idx, fd, grad[k])
+    assert np.all(grad[:120] == 0.0)        # no gradient for the standardisation constants
+
+
+def test_bf16_rounding_matches_library(orc):
+    g = np.random.default_rng(6)
+    xs = np.concatenate([g.standard_normal(3000) * 10.0 ** g.integers(-8, 8, 3000),
+                         [0.0, -0.0, 1.0, 1.00390625, 1.005859375, 3.4e38, 1e-40]]).astype(np.float32)
+    lib = torch.from_numpy(xs).to(torch.bfloat16).to(torch.float32).numpy()
+    ours = np.array([orc.bf16(float(x)) for x in xs], np.float32)
+    np.testing.assert_array_equal(ours, lib)
+
+
+def test_bf16_forward_close_to_fp64(orc):
+    p = synth.mlp_params(7)
+    f, _ = _batch(50, 8)
+    z64 = orc.mlp_forward(p, f, bf16_mode=False)
+    z16 = orc.mlp_forward(p, f, bf16_mode=True)
+    assert np.abs(z16 - z64).max() < 0.05 * (1 + np.abs(z64).max())
+
+
+def test_features_hand_checked(orc):
+    grid = (5, 4, 3)
+    n_cells = 60
+    omega = np.zeros((2, n_cells), np.float32)
+    omega[0] = np.arange(n_cells)            # A field: cell index
+    omega[1] = 1000 + np.arange(n_cells)     # B field: 1000 + cell index
+    # one chain of 3 beads, types A B B (n_a = 1)
+    pos = np.array([[0.5, 0.5, 0.5], [1.25, 3.5, 2.75], [2.0, 0.25, 2.5]], np.float32)
+    sp = Species(1, 3, 1)
+    fa = orc.features(pos, sp, [0], omega, grid)[0]
+    fb = orc.features(pos, sp, [1], omega, grid)[0]
+    # bead 0 is A in cell (0,0,0): own block = A field; (dz,dy,dx)=(-1,-1,-1) ->
+    # cell (4, 3, 2) -> index (2*4+3)*5+4 = 59; centre = cell 0
+    assert fa[0] == 59 and fa[13] == 0 and fa[27 + 13] == 1000
+    np.testing.assert_array_equal(fa[54:57], 0.0)                     # no previous bead
+    np.testing.assert_allclose(fa[57:60], pos[1] - pos[0])
+    # bead 1 is B in cell (1,3,2) -> centre index (2*4+3)*5+1 = 56; own block = B field
+    assert fb[13] == 1056 and fb[27 + 13] == 56
+    # (dz,dy,dx) = (+1,+1,+1) wraps to cell (2,0,0) -> index 2
+    assert fb[26] == 1002
+    np.testing.assert_allclose(fb[54:57], pos[0] - pos[1])
+    np.testing.assert_allclose(fb[57:60], pos[2] - pos[1])
+
+
+def _three_bead_mixed(orc, p_learn, params, n_chains=8192, equil=150, sweeps=200):
+    """Equilibrate with local moves, then continue with the mixed move: exact
+    Metropolis-Hastings keeps the Boltzmann distribution stationary."""
+    L, k0 = 4, np.float32(3.0)
+    grid = (L, L, L)
+    omega = synth.uniform_field(21, L ** 3, -2.0, 2.0)
+    pos = synth.gaussian_walks(24, n_chains, 3, grid, 1.0 / math.sqrt(3.0))
+    acc_l = 0
+    for sweep in range(equil + sweeps):
+        pl = 0.0 if sweep < equil else p_learn
+        _, al, bad, _, _ = orc.mc_sweep_mixed(pos, Species(n_chains, 3, 2), omega, grid, k0=k0,
+                                              n_ref=1, local_a=0.7, p_learn=pl,
+                                              params=params, **HEAD, seed=5, sweep=sweep,
+                                              threads=8)
+        acc_l += al
+        assert bad == 0
+    cells = np.floor(pos.astype(np.float64)).astype(np.int64) % L
+    lin = ((cells[:, 2] * L + cells[:, 1]) * L + cells[:, 0]).reshape(n_chains, 3)
+    return lin, omega, acc_l
+
+
+def drifting_params(seed):
+    """Random weights with a position-dependent drift of ~0.1 cell and sigma
+    ~0.5 cell: far from a symmetric proposal, so the proposal ratio matters."""
+    params = synth.mlp_params(seed, out_gain=0.1)
+    b3 = synth.MLP_LAYOUT["b3"]
+    params[b3 + 3:b3 + 6] = 1.5
+    return params
+
+
+@pytest.mark.parametrize("p_learn", [1.0, 0.5])
+def test_mixed_move_is_exact_with_random_weights(orc, p_learn):
+    # random weights give a position-dependent drift of about 0.1 cell: the
+    # proposal is far from symmetric, so a wrong proposal ratio would bias the
+    # sampled distribution
+    params = drifting_params(9)
+    lin, omega, acc_l = _three_bead_mixed(orc, p_learn, params)
+    assert acc_l > 0
+    p = references.three_bead_cell_distribution(omega[0], omega[1], 3.0, 4)
+    marg = [p.sum(axis=(1, 2)), p.sum(axis=(0, 2)), p.sum(axis=(0, 1))]
+    for b in range(3):
+        pval, stat, dof = references.chi2_pvalue(np.bincount(lin[:, b], minlength=64), marg[b])
+        assert pval > 1e-4, (b, stat, dof)
+    obs = np.bincount(lin[:, 0] * 64 + lin[:, 2], minlength=4096)
+    pval, stat, dof = references.chi2_pvalue(obs, p.sum(axis=1).ravel())
+    assert pval > 1e-4, (stat, dof)
