@@ -65,9 +65,11 @@ typedef enum soma_status {
 /* Move kinds (Sec. 2.2). */
 #define SOMA_MOVE_LOCAL 0u /* uniform trial displacement in [-a,a]^3, Metropolis */
 #define SOMA_MOVE_SMC 1u   /* force-biased (smart MC) proposal, Metropolis-Hastings */
+#define SOMA_MOVE_MIXED 2u /* learned proposal with probability p_learn, else local; MH */
 
 /* Device error word bits (returned by soma_check / soma_observables). */
 #define SOMA_FLAG_POSITION 1u /* soma_observables found a position non-finite or |x| >= 2^22 */
+#define SOMA_FLAG_NETWORK 2u  /* a learned move met a non-finite network output (rejected) */
 
 #define SOMA_MAX_SPECIES 8
 #define SOMA_MAX_BEADS_PER_CHAIN 128
@@ -93,6 +95,12 @@ typedef struct soma_config {
   uint32_t count_width;  /* 16 or 32 (bits per type per cell) */
   uint32_t set_order;    /* 0: random even/odd order per chain and sweep; 1: even first */
   uint32_t origin_mode;  /* initial origins: 0 i.i.d. uniform, 1 stratified in bricked order */
+  /* learned proposal (SOMA_MOVE_MIXED): probability of the learned move per
+   * bead, and the bounds of its Gaussian head: mu = mu_max tanh(z/mu_max),
+   * log sigma = log_sigma_min + (log_sigma_max - log_sigma_min) sigmoid(z) */
+  float p_learn;
+  float mu_max;
+  float log_sigma_min, log_sigma_max;
 } soma_config;
 
 typedef struct soma_buffers {
@@ -107,8 +115,8 @@ typedef struct soma_obs {
   uint64_t n_beads, n_chains;
   uint64_t count_a;       /* sum of A counts of the last field update */
   uint64_t count_b;       /* sum of B counts of the last field update */
-  uint64_t accepted[2];   /* accepted moves per move kind since init */
-  uint64_t attempted[2];  /* attempted moves per move kind since init */
+  uint64_t accepted[3];   /* accepted moves since init: local, smart-MC, learned */
+  uint64_t attempted[3];  /* attempted moves since init: local, smart-MC, learned */
   double re2_sum;         /* sum over chains of |r_{N-1} - r_0|^2 */
   double rg2_sum;         /* sum over chains of (1/N) sum_i |r_i - r_cm|^2 */
   double b2_sum;          /* sum over bonds of |r_{i+1} - r_i|^2 */
@@ -197,6 +205,39 @@ int32_t soma_field_from_counts(const soma_config *cfg, const void *counts,
 
 /* Stand-alone initial positions as in soma_init_system.  Asynchronous. */
 int32_t soma_init_positions(const soma_config *cfg, float *pos, void *stream);
+
+/* ---- Learned proposal --------------------------------------------------
+ * Network parameters are an FP32 blob (device memory, caller-owned) of 8576
+ * floats: shift[60] scale[60] (feature standardisation (f - shift) * scale),
+ * W1[64][60] b1[64] W2[64][64] b2[64] W3[6][64] b3[6] (row-major, [out][in]).
+ * Features of a bead: its own type's field at the 27 cells around its cell
+ * ((dz,dy,dx) in -1..1, dz slowest), the other type's field at the same cells,
+ * then the bond vectors r_{i-1} - r and r_{i+1} - r (zero where absent).
+ * Network: SiLU, 60 -> 64 -> 64 -> 6, evaluated with BF16 inputs and weights
+ * and FP32 accumulation on the matrix cores. */
+
+/* Bytes of a prepared network (see soma_prepare_net). */
+uint64_t soma_net_bytes(void);
+
+/* Converts an FP32 parameter blob into the device layout the kernels use
+ * (`net`: soma_net_bytes() bytes of device memory, 16-byte aligned).
+ * Asynchronous. */
+int32_t soma_prepare_net(const float *params, void *net, void *stream);
+
+/* Installs the network of the mixed move into the handle's workspace (a copy:
+ * `params` may be freed or changed afterwards).  Asynchronous. */
+int32_t soma_set_proposal(soma_system *sys, const float *params, void *stream);
+
+/* Network outputs z [n][6] (FP32) for raw features [n][60] (FP32), both device
+ * memory, with a prepared network.  Asynchronous. */
+int32_t soma_mlp_forward(const void *net, const float *features, uint32_t n,
+                         float *z, void *stream);
+
+/* Raw features [n][60] (FP32, device) of bead beads[s] of global chain
+ * chains[s] at the current positions and fields (training data).
+ * Asynchronous. */
+int32_t soma_features(soma_system *sys, const uint32_t *chains,
+                      const uint32_t *beads, uint32_t n, float *out, void *stream);
 
 /* Releases the handle (host memory only). */
 void soma_destroy(soma_system *sys);

@@ -47,7 +47,8 @@ struct Derived {
   uint64_t obs_block_off[SOMA_MAX_SPECIES] = {};
   uint64_t pos_bytes = 0, counts_bytes = 0, omega_bytes = 0;
   // workspace layout
-  uint64_t off_err = 0, off_acc = 0, off_fpart = 0, off_totals = 0, off_opart = 0;
+  uint64_t off_err = 0, off_acc = 0, off_att = 0, off_net = 0, off_fpart = 0, off_totals = 0,
+           off_opart = 0;
   uint64_t ws_bytes = 0;
 };
 
@@ -64,6 +65,11 @@ int32_t derive(const soma_config *c, Derived *d) {
   if (c->n_ref == 0) return fail(SOMA_E_INVAL, "n_ref must be positive");
   if (c->set_order > 1) return fail(SOMA_E_INVAL, "set_order must be 0 or 1");
   if (c->origin_mode > 1) return fail(SOMA_E_INVAL, "origin_mode must be 0 or 1");
+  if (!(c->p_learn >= 0.f && c->p_learn <= 1.f) || !(c->mu_max > 0.f) ||
+      !std::isfinite(c->log_sigma_min) || !std::isfinite(c->log_sigma_max) ||
+      !(c->log_sigma_min <= c->log_sigma_max))
+    return fail(SOMA_E_INVAL, "learned proposal: need 0 <= p_learn <= 1, mu_max > 0, "
+                              "finite log_sigma_min <= log_sigma_max");
   if (!std::isfinite(c->chi_n) || !std::isfinite(c->kappa_n) || !std::isfinite(c->local_a) ||
       !std::isfinite(c->smc_a) || c->local_a < 0.f || c->smc_a < 0.f)
     return fail(SOMA_E_INVAL, "chi_n, kappa_n, local_a, smc_a must be finite (steps >= 0)");
@@ -92,7 +98,9 @@ int32_t derive(const soma_config *c, Derived *d) {
   d->omega_bytes = 8ull * n_cells;
   d->off_err = 0;
   d->off_acc = align_up(d->off_err + 16);
-  d->off_fpart = align_up(d->off_acc + 2ull * soma::kAccSlots * 8ull);
+  d->off_att = align_up(d->off_acc + 3ull * soma::kAccSlots * 8ull);
+  d->off_net = align_up(d->off_att + soma::kAccSlots * 8ull);
+  d->off_fpart = align_up(d->off_net + sizeof(soma::NetDev));
   d->off_totals = align_up(d->off_fpart + soma::kFieldBlocks * sizeof(soma::FieldPartial));
   d->off_opart = align_up(d->off_totals + sizeof(soma::Totals));
   d->ws_bytes = align_up(d->off_opart + (d->obs_blocks ? d->obs_blocks : 1) * sizeof(soma::ObsPartial));
@@ -203,19 +211,26 @@ struct soma_system {
   uint64_t sweep = 0;
   uint64_t attempted[2] = {0, 0};
   uint32_t sweep_blocks = 0;  // local-move grid: 0 = one tile per wave, else persistent blocks
+  uint64_t mixed_moves = 0;   // bead moves made by mixed sweeps (local or learned)
+  bool has_net = false;
   unsigned char *ws = nullptr;
   uint32_t *err() { return reinterpret_cast<uint32_t *>(ws + d.off_err); }
   unsigned long long *acc() { return reinterpret_cast<unsigned long long *>(ws + d.off_acc); }
   soma::FieldPartial *fpart() { return reinterpret_cast<soma::FieldPartial *>(ws + d.off_fpart); }
   soma::Totals *totals() { return reinterpret_cast<soma::Totals *>(ws + d.off_totals); }
   soma::ObsPartial *opart() { return reinterpret_cast<soma::ObsPartial *>(ws + d.off_opart); }
+  unsigned long long *att() { return reinterpret_cast<unsigned long long *>(ws + d.off_att); }
+  soma::NetDev *net() { return reinterpret_cast<soma::NetDev *>(ws + d.off_net); }
 };
 
 namespace {
 
 template <bool C64, bool V2>
-void launch_sweep_t(uint32_t kind, dim3 grid, hipStream_t s, const soma::SweepArgs &a) {
-  if (kind == SOMA_MOVE_SMC)
+void launch_sweep_t(uint32_t kind, dim3 grid, hipStream_t s, const soma::SweepArgs &a,
+                    const soma::MixArgs &mx, uint32_t *err) {
+  if (kind == SOMA_MOVE_MIXED)
+    hipLaunchKernelGGL((soma::mc_sweep_mixed_kernel<C64, V2>), grid, dim3(256), 0, s, a, mx, err);
+  else if (kind == SOMA_MOVE_SMC)
     hipLaunchKernelGGL((soma::mc_sweep_smc_kernel<C64, V2>), grid, dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL((soma::mc_sweep_local_kernel<C64, V2>), grid, dim3(256), 0, s, a);
@@ -231,6 +246,13 @@ int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s) {
     a.omega = sys->buf.omega;
     a.counts = sys->buf.counts;
     a.acc_slots = sys->acc() + (kind == SOMA_MOVE_SMC ? soma::kAccSlots : 0u);
+    soma::MixArgs mx;
+    mx.net = sys->net();
+    mx.head.m_max = c->mu_max;
+    mx.head.lo = c->log_sigma_min;
+    mx.head.hi = c->log_sigma_max;
+    mx.p_learn = c->p_learn;
+    mx.att_slots = sys->att();
     a.grid = sys->grid;
     a.n_chains = S.n_chains;
     a.n = S.n;
@@ -240,7 +262,7 @@ int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s) {
     a.chain_base = (uint32_t)sys->d.chain_off[sp];
     a.k0 = S.k0;
     a.half_k0 = 0.5f * S.k0;
-    a.step = kind == SOMA_MOVE_SMC ? c->smc_a : c->local_a;
+    a.step = kind == SOMA_MOVE_SMC ? c->smc_a : c->local_a;  // mixed: local half-width
     a.sqrt_2a = (float)std::sqrt(2.0 * (double)c->smc_a);
     a.inv_4a = c->smc_a > 0.f ? (float)(1.0 / (4.0 * (double)c->smc_a)) : 0.f;
     a.inv_nref = (float)(1.0 / (double)c->n_ref);
@@ -257,9 +279,11 @@ int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s) {
     const bool c64 = c->count_width == 32;
     const dim3 grid((uint32_t)blocks);
     if (c64) {
-      if (v2) launch_sweep_t<true, true>(kind, grid, s, a); else launch_sweep_t<true, false>(kind, grid, s, a);
+      if (v2) launch_sweep_t<true, true>(kind, grid, s, a, mx, sys->err());
+      else launch_sweep_t<true, false>(kind, grid, s, a, mx, sys->err());
     } else {
-      if (v2) launch_sweep_t<false, true>(kind, grid, s, a); else launch_sweep_t<false, false>(kind, grid, s, a);
+      if (v2) launch_sweep_t<false, true>(kind, grid, s, a, mx, sys->err());
+      else launch_sweep_t<false, false>(kind, grid, s, a, mx, sys->err());
     }
     LAUNCH_TRY();
   }
@@ -338,11 +362,13 @@ int32_t soma_init_system(const soma_config *cfg, const soma_buffers *buf, uint32
 
 int32_t soma_mc_sweep(soma_system *sys, uint32_t n_sweeps, uint32_t move_kind, void *stream) {
   if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
-  if (move_kind != SOMA_MOVE_LOCAL && move_kind != SOMA_MOVE_SMC)
+  if (move_kind != SOMA_MOVE_LOCAL && move_kind != SOMA_MOVE_SMC && move_kind != SOMA_MOVE_MIXED)
     return fail(SOMA_E_UNSUPPORTED, "move kind %u", move_kind);
+  if (move_kind == SOMA_MOVE_MIXED && !sys->has_net && sys->cfg.p_learn > 0.f)
+    return fail(SOMA_E_INVAL, "mixed moves need a network (soma_set_proposal)");
   if (move_kind == SOMA_MOVE_SMC && !(sys->cfg.smc_a > 0.f))
     return fail(SOMA_E_INVAL, "smart-MC moves need smc_a > 0");
-  if (move_kind == SOMA_MOVE_LOCAL && !(sys->cfg.local_a < 1.f))
+  if (move_kind != SOMA_MOVE_SMC && !(sys->cfg.local_a < 1.f))
     return fail(SOMA_E_UNSUPPORTED, "local moves need a half-width below one cell");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   for (uint32_t i = 0; i < n_sweeps; ++i) {
@@ -350,7 +376,8 @@ int32_t soma_mc_sweep(soma_system *sys, uint32_t n_sweeps, uint32_t move_kind, v
     if (rc) return rc;
     sys->sweep += 1;
   }
-  sys->attempted[move_kind] += (uint64_t)n_sweeps * sys->d.n_beads;
+  if (move_kind == SOMA_MOVE_MIXED) sys->mixed_moves += (uint64_t)n_sweeps * sys->d.n_beads;
+  else sys->attempted[move_kind] += (uint64_t)n_sweeps * sys->d.n_beads;
   return SOMA_OK;
 }
 
@@ -395,7 +422,7 @@ int32_t soma_observables(soma_system *sys, soma_obs *out, void *stream) {
   }
   hipLaunchKernelGGL(soma::reduce_totals_kernel, dim3(1), dim3(256), 0, s, sys->opart(),
                      (uint32_t)sys->d.obs_blocks, sys->fpart(), soma::kFieldBlocks, sys->acc(),
-                     sys->err(), sys->totals());
+                     sys->att(), sys->err(), sys->totals());
   LAUNCH_TRY();
   soma::Totals t;
   HIP_TRY(hipMemcpyAsync(&t, sys->totals(), sizeof t, hipMemcpyDeviceToHost, s));
@@ -406,10 +433,10 @@ int32_t soma_observables(soma_system *sys, soma_obs *out, void *stream) {
   out->n_chains = sys->d.n_chains;
   out->count_a = t.sum_a;
   out->count_b = t.sum_b;
-  out->accepted[0] = t.accepted[0];
-  out->accepted[1] = t.accepted[1];
-  out->attempted[0] = sys->attempted[0];
+  for (int k = 0; k < 3; ++k) out->accepted[k] = t.accepted[k];
+  out->attempted[0] = sys->attempted[0] + (sys->mixed_moves - t.attempted_learned);
   out->attempted[1] = sys->attempted[1];
+  out->attempted[2] = t.attempted_learned;
   out->re2_sum = t.re2;
   out->rg2_sum = t.rg2;
   out->b2_sum = t.b2;
@@ -473,6 +500,58 @@ int32_t soma_init_positions(const soma_config *cfg, float *pos, void *stream) {
   if (rc) return rc;
   if (!pos) return fail(SOMA_E_INVAL, "NULL buffer");
   return launch_init(cfg, d, pos, reinterpret_cast<hipStream_t>(stream));
+}
+
+uint64_t soma_net_bytes(void) { return sizeof(soma::NetDev); }
+
+int32_t soma_prepare_net(const float *params, void *net, void *stream) {
+  if (!params || !net) return fail(SOMA_E_INVAL, "NULL buffer");
+  if (!aligned(net, 16)) return fail(SOMA_E_INVAL, "net buffer must be 16-byte aligned");
+  hipLaunchKernelGGL(soma::net_prepare_kernel, dim3(1), dim3(256), 0,
+                     reinterpret_cast<hipStream_t>(stream), params,
+                     reinterpret_cast<soma::NetDev *>(net));
+  LAUNCH_TRY();
+  return SOMA_OK;
+}
+
+int32_t soma_set_proposal(soma_system *sys, const float *params, void *stream) {
+  if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
+  const int32_t rc = soma_prepare_net(params, sys->net(), stream);
+  if (rc) return rc;
+  sys->has_net = true;
+  return SOMA_OK;
+}
+
+int32_t soma_mlp_forward(const void *net, const float *features, uint32_t n, float *z,
+                         void *stream) {
+  if (!net || !features || !z) return fail(SOMA_E_INVAL, "NULL buffer");
+  if (n == 0) return SOMA_OK;
+  hipLaunchKernelGGL(soma::mlp_forward_kernel, dim3((n + 255) / 256), dim3(256), 0,
+                     reinterpret_cast<hipStream_t>(stream),
+                     reinterpret_cast<const soma::NetDev *>(net), features, n, z);
+  LAUNCH_TRY();
+  return SOMA_OK;
+}
+
+int32_t soma_features(soma_system *sys, const uint32_t *chains, const uint32_t *beads,
+                      uint32_t n, float *out, void *stream) {
+  if (!sys || !chains || !beads || !out) return fail(SOMA_E_INVAL, "NULL argument");
+  if (n == 0) return SOMA_OK;
+  soma::SpeciesTable st;
+  st.n_species = sys->cfg.n_species;
+  st.total_chains = (uint32_t)sys->d.n_chains;
+  for (uint32_t k = 0; k < 8; ++k) {
+    const bool ok = k < sys->cfg.n_species;
+    st.chain_off[k] = ok ? (uint32_t)sys->d.chain_off[k] : 0u;
+    st.bead_off[k] = ok ? sys->d.bead_off[k] : 0u;
+    st.n[k] = ok ? sys->cfg.species[k].n : 1u;
+    st.n_a[k] = ok ? sys->cfg.species[k].n_a : 0u;
+  }
+  hipLaunchKernelGGL(soma::features_kernel, dim3((n + 255) / 256), dim3(256), 0,
+                     reinterpret_cast<hipStream_t>(stream), sys->buf.pos, sys->buf.omega,
+                     sys->grid, st, chains, beads, n, out);
+  LAUNCH_TRY();
+  return SOMA_OK;
 }
 
 void soma_destroy(soma_system *sys) { delete sys; }

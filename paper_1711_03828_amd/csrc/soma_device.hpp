@@ -14,6 +14,10 @@ constexpr uint32_t kSweepInit = 0xFFFFFFFFu;
 constexpr uint32_t kAccSlots = 1024u;  // acceptance counter slots per move kind
 constexpr float kMaxCoord = 4194304.0f;  // 2^22: cell arithmetic stays exact below
 
+// Three-component vector kept in registers (a native vector type, so that
+// selects between vectors never go through private memory).
+typedef float F3 __attribute__((ext_vector_type(3)));
+
 struct Rand4 {
   uint32_t x, y, z, w;
 };

@@ -1,0 +1,282 @@
+// soma_mlp.hpp -- the learned proposal's network on the gfx950 matrix cores.
+//
+// A learned move proposes r' = r + mu(r) + sigma(r) xi from a small network
+// (60 -> 64 -> 64 -> 6, SiLU) fed with the fields around the bead and its two
+// bond vectors, and is accepted by Metropolis-Hastings with the exact ratio
+// of the Gaussian proposal densities, so the sampled distribution of the
+// method (Sec. 2.2) is unchanged; the move is an addition to the paper's local
+// and smart-MC moves.
+//
+// One wavefront evaluates the network for 64 samples (its 64 lanes) with
+// v_mfma_f32_16x16x32_bf16: activations are the B operand (K = units, N =
+// samples), weights the A operand (M = output units); BF16 inputs, FP32
+// accumulation.  Activations pass between layers through a per-wave LDS
+// tile [64 samples][72] bf16 in natural unit order.
+#pragma once
+
+#include "soma_device.hpp"
+
+namespace soma {
+
+constexpr int kNF = 60, kNH = 64, kNO = 6;
+// FP32 parameter blob (interface format): shift[60] scale[60] W1[64][60] b1[64]
+// W2[64][64] b2[64] W3[6][64] b3[6], padded to 8576 floats.
+constexpr int kPShift = 0, kPScale = 60, kPW1 = 120, kPB1 = 3960, kPW2 = 4024, kPB2 = 8120,
+              kPW3 = 8184, kPB3 = 8568, kPSize = 8576;
+constexpr int kActStride = 72;  // bf16 per LDS row: 64 units + 8 padding
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Device copy of the network, ready for the MFMA tiles.
+struct NetDev {
+  float shift[64], scale[64];  // entries 60..63: shift 0, scale 0 (feature 0)
+  float b1[64], b2[64], b3[16];
+  __bf16 w1[64 * 64];          // [out][in], in >= 60 zero
+  __bf16 w2[64 * 64];          // [out][in]
+  __bf16 w3[16 * 64];          // rows >= 6 zero
+  __bf16 w2t[64 * 64];         // W2 transposed: [in][out]
+  __bf16 w3t[64 * 32];         // [hidden][k]: W3[k][hidden] for k < 6, else 0
+};
+
+struct HeadArgs {
+  float m_max, lo, hi;         // mu = m tanh(z/m); log sigma = lo + (hi-lo) sigmoid(z)
+};
+
+__global__ __launch_bounds__(256) void net_prepare_kernel(const float *__restrict__ p,
+                                                          NetDev *__restrict__ net) {
+  for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+    net->shift[i] = i < kNF ? p[kPShift + i] : 0.0f;
+    net->scale[i] = i < kNF ? p[kPScale + i] : 0.0f;
+    net->b1[i] = p[kPB1 + i];
+    net->b2[i] = p[kPB2 + i];
+    if (i < 16) net->b3[i] = i < kNO ? p[kPB3 + i] : 0.0f;
+  }
+  for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) {
+    const int o = i >> 6, k = i & 63;
+    net->w1[i] = (__bf16)(k < kNF ? p[kPW1 + o * kNF + k] : 0.0f);
+    net->w2[i] = (__bf16)p[kPW2 + o * kNH + k];
+    net->w2t[i] = (__bf16)p[kPW2 + k * kNH + o];
+    if (o < 16) net->w3[i] = (__bf16)(o < kNO ? p[kPW3 + o * kNH + k] : 0.0f);
+  }
+  for (int i = threadIdx.x; i < 64 * 32; i += blockDim.x) {
+    const int h = i >> 5, k = i & 31;
+    net->w3t[i] = (__bf16)(k < kNO ? p[kPW3 + k * kNH + h] : 0.0f);
+  }
+}
+
+__device__ __forceinline__ float silu(float a) { return a / (1.0f + __expf(-a)); }
+
+__device__ __forceinline__ bf16x8 lds_b8(const __bf16 *p) {
+  return *reinterpret_cast<const bf16x8 *>(p);
+}
+
+// One fully connected layer of 64 outputs with SiLU, for the wave's 64
+// samples: reads the inputs from `act`, overwrites `act` with the outputs.
+__device__ __forceinline__ void hidden_layer(const __bf16 *__restrict__ w,
+                                             const float *__restrict__ bias, __bf16 *act) {
+  const int lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb) {
+    bf16x8 b[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) b[t] = lds_b8(act + (16 * t + col) * kActStride + 32 * kb + 8 * g);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      const bf16x8 av = *reinterpret_cast<const bf16x8 *>(w + (16 * mt + col) * 64 + 32 * kb + 8 * g);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[t], acc[mt][t], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int unit = 16 * mt + 4 * g;
+      typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+      bf16x4 v;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = (__bf16)silu(acc[mt][t][r] + bias[unit + r]);
+      *reinterpret_cast<bf16x4 *>(act + (16 * t + col) * kActStride + unit) = v;
+    }
+}
+
+// Network output z (6 per sample) for the 64 samples whose standardised
+// inputs are in `act` (row = lane); z of sample s lands in zout[8 s .. 8 s + 5].
+__device__ __forceinline__ void wave_forward(const NetDev *__restrict__ net, __bf16 *act,
+                                             float *zout) {
+  hidden_layer(net->w1, net->b1, act);
+  hidden_layer(net->w2, net->b2, act);
+  const int lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+  f32x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb) {
+    const bf16x8 av = *reinterpret_cast<const bf16x8 *>(net->w3 + col * 64 + 32 * kb + 8 * g);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const bf16x8 b = lds_b8(act + (16 * t + col) * kActStride + 32 * kb + 8 * g);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, acc[t], 0, 0, 0);
+    }
+  }
+  if (g < 2) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) zout[(16 * t + col) * 8 + 4 * g + r] = acc[t][r] + net->b3[4 * g + r];
+  }
+}
+
+// Cell-neighbourhood addressing of a bead: the 3 x 3 x 3 cells around the
+// cell that holds r, as 9 row bases (dz, dy) and 3 column offsets (dx).
+struct Neighbourhood {
+  uint32_t base[9];
+  uint32_t xs[3];
+  uint32_t centre;
+};
+
+__device__ __forceinline__ Neighbourhood neighbourhood(const Grid &g, F3 r) {
+  uint32_t cx, cy, cz;
+  cell3(g, r.x, r.y, r.z, cx, cy, cz);
+  Neighbourhood nb;
+  nb.xs[0] = cx == 0 ? g.nx - 1u : cx - 1u;
+  nb.xs[1] = cx;
+  nb.xs[2] = cx + 1 == (uint32_t)g.nx ? 0u : cx + 1u;
+  const uint32_t ys[3] = {cy == 0 ? g.ny - 1u : cy - 1u, cy, cy + 1 == (uint32_t)g.ny ? 0u : cy + 1u};
+  const uint32_t zs[3] = {cz == 0 ? g.nz - 1u : cz - 1u, cz, cz + 1 == (uint32_t)g.nz ? 0u : cz + 1u};
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+      nb.base[3 * dz + dy] = __umul24(__umul24(zs[dz], (uint32_t)g.ny) + ys[dy], (uint32_t)g.nx);
+  nb.centre = nb.base[4] + cx;
+  return nb;
+}
+
+// Raw feature k (0..59) of a bead: fields of its own type at the 27 cells
+// around its cell ((dz, dy, dx) order, periodic), then the other type's, then
+// the bond vectors to the previous and next bead (zero where absent).
+__device__ __forceinline__ float raw_feature(int k, const Neighbourhood &nb, const float *own,
+                                             const float *oth, F3 bp, F3 bn) {
+  if (k < 27) return own[nb.base[k / 3] + nb.xs[k % 3]];
+  if (k < 54) return oth[nb.base[(k - 27) / 3] + nb.xs[(k - 27) % 3]];
+  const int d = (k - 54) % 3;
+  const F3 v = k < 57 ? bp : bn;
+  return d == 0 ? v.x : (d == 1 ? v.y : v.z);
+}
+
+// Gathers, standardises and stores the 60 features of a bead at r into one
+// LDS row of bf16 (entries 60..63 zero), 8 at a time.  Returns the bead's own
+// field in its cell; `cell` receives that cell's index.
+__device__ __forceinline__ float features_to_row(const Grid &g, const float *__restrict__ omega,
+                                                 bool is_b, F3 r, F3 bp, F3 bn,
+                                                 const NetDev *__restrict__ net, __bf16 *row,
+                                                 uint32_t &cell) {
+  const Neighbourhood nb = neighbourhood(g, r);
+  const float *own = omega + (is_b ? g.n_cells : 0u);
+  const float *oth = omega + (is_b ? 0u : g.n_cells);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    bf16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 8 * c + j;
+      v[j] = k < kNF ? (__bf16)((raw_feature(k, nb, own, oth, bp, bn) - net->shift[k]) * net->scale[k])
+                     : (__bf16)0.0f;
+    }
+    *reinterpret_cast<bf16x8 *>(row + 8 * c) = v;
+  }
+  cell = nb.centre;
+  return own[nb.centre];
+}
+
+// Gaussian head of one sample: mean, sigma and log sigma.
+__device__ __forceinline__ void head(const float *z, const HeadArgs &h, float (&mu)[3],
+                                     float (&sig)[3], float (&lsig)[3]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    mu[d] = h.m_max * tanhf(z[d] / h.m_max);
+    const float s = 1.0f / (1.0f + __expf(-z[3 + d]));
+    lsig[d] = h.lo + (h.hi - h.lo) * s;
+    sig[d] = __expf(lsig[d]);
+  }
+}
+
+// Stand-alone forward pass: raw features [n][60] -> z [n][6]; one wave per 64 samples.
+__global__ __launch_bounds__(256) void mlp_forward_kernel(const NetDev *__restrict__ net,
+                                                          const float *__restrict__ feat,
+                                                          uint32_t n, float *__restrict__ z) {
+  __shared__ __bf16 s_act[4][64 * kActStride];
+  __shared__ float s_z[4][64 * 8];
+  const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  const uint32_t s = (blockIdx.x * 4u + wv) * 64u + lane;
+  __bf16 *row = &s_act[wv][lane * kActStride];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    bf16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 8 * c + j;
+      const float x = (k < kNF && s < n) ? feat[(size_t)s * kNF + (k < kNF ? k : 0)] : 0.0f;
+      v[j] = k < kNF ? (__bf16)((x - net->shift[k]) * net->scale[k]) : (__bf16)0.0f;
+    }
+    *reinterpret_cast<bf16x8 *>(row + 8 * c) = v;
+  }
+  wave_forward(net, s_act[wv], s_z[wv]);
+  if (s < n)
+#pragma unroll
+    for (int o = 0; o < kNO; ++o) z[(size_t)s * kNO + o] = s_z[wv][lane * 8 + o];
+}
+
+}  // namespace soma
+
+namespace soma {
+
+// Species table for kernels that address beads by (global chain, bead).
+struct SpeciesTable {
+  uint32_t n_species, total_chains;
+  uint32_t chain_off[8], n[8], n_a[8];
+  uint64_t bead_off[8];
+};
+
+// Raw features (FP32) of bead `beads[s]` of global chain `chains[s]` at the
+// current positions, for training data: out [n][60].  One thread per sample.
+__global__ __launch_bounds__(256) void features_kernel(const float *__restrict__ pos,
+                                                       const float *__restrict__ omega, Grid g,
+                                                       SpeciesTable st,
+                                                       const uint32_t *__restrict__ chains,
+                                                       const uint32_t *__restrict__ beads,
+                                                       uint32_t n, float *__restrict__ out) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const uint32_t c = chains[s];
+  if (c >= st.total_chains) {  // out of range: zeros, never a stray read
+    for (int k = 0; k < kNF; ++k) out[(size_t)s * kNF + k] = 0.0f;
+    return;
+  }
+  uint32_t sp = 0;
+  for (uint32_t k = 1; k < st.n_species; ++k)
+    if (c >= st.chain_off[k]) sp = k;
+  const uint32_t nn = st.n[sp];
+  const uint32_t i = min(beads[s], nn - 1u);
+  const float *chain = pos + 3 * (st.bead_off[sp] + (uint64_t)(c - st.chain_off[sp]) * nn);
+  const F3 r = {chain[3 * i], chain[3 * i + 1], chain[3 * i + 2]};
+  const F3 zero3 = F3{0.f, 0.f, 0.f};
+  const F3 bp = i > 0 ? F3{chain[3 * i - 3], chain[3 * i - 2], chain[3 * i - 1]} - r : zero3;
+  const F3 bn = i + 1 < nn ? F3{chain[3 * i + 3], chain[3 * i + 4], chain[3 * i + 5]} - r : zero3;
+  const Neighbourhood nb = neighbourhood(g, r);
+  const bool is_b = i >= st.n_a[sp];
+  const float *own = omega + (is_b ? g.n_cells : 0u);
+  const float *oth = omega + (is_b ? 0u : g.n_cells);
+#pragma unroll
+  for (int k = 0; k < kNF; ++k) out[(size_t)s * kNF + k] = raw_feature(k, nb, own, oth, bp, bn);
+}
+
+}  // namespace soma

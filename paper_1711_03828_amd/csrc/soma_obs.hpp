@@ -13,7 +13,8 @@ struct ObsPartial {
 };
 
 struct Totals {
-  unsigned long long accepted[2];
+  unsigned long long accepted[3];
+  unsigned long long attempted_learned;
   unsigned long long sum_a, sum_b;
   double re2, rg2, b2, e_bond, e_field, h_nb;
   uint32_t err, pad;
@@ -93,39 +94,45 @@ __global__ __launch_bounds__(256) void chain_obs_kernel(const ObsArgs a) {
 }
 
 // Single block: fixed-order reduction of all partials into one Totals record.
+// acc_slots holds kAccSlots counters for each of local, smart-MC and learned
+// moves; att_slots the attempted learned moves.
 __global__ __launch_bounds__(256) void reduce_totals_kernel(
     const ObsPartial *op, uint32_t n_op, const FieldPartial *fp, uint32_t n_fp,
-    const unsigned long long *acc_slots, const uint32_t *err, Totals *out) {
+    const unsigned long long *acc_slots, const unsigned long long *att_slots,
+    const uint32_t *err, Totals *out) {
   __shared__ double s[4][6];
-  __shared__ unsigned long long su[4][4];
+  __shared__ unsigned long long su[4][6];
   double v[6] = {0, 0, 0, 0, 0, 0};
-  unsigned long long u[4] = {0, 0, 0, 0};
+  unsigned long long u[6] = {0, 0, 0, 0, 0, 0};
   for (uint32_t i = threadIdx.x; i < n_op; i += blockDim.x) {
     v[0] += op[i].re2; v[1] += op[i].rg2; v[2] += op[i].b2;
     v[3] += op[i].e_bond; v[4] += op[i].e_field;
   }
   for (uint32_t i = threadIdx.x; i < n_fp; i += blockDim.x) {
-    u[2] += fp[i].sum_a; u[3] += fp[i].sum_b; v[5] += fp[i].h_nb;
+    u[3] += fp[i].sum_a; u[4] += fp[i].sum_b; v[5] += fp[i].h_nb;
   }
   for (uint32_t i = threadIdx.x; i < kAccSlots; i += blockDim.x) {
     u[0] += acc_slots[i];
     u[1] += acc_slots[kAccSlots + i];
+    u[2] += acc_slots[2 * kAccSlots + i];
+    u[5] += att_slots[i];
   }
   block_sum<6>(v, s);
   for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) u[j] += __shfl_down(u[j], off, 64);
+    for (int j = 0; j < 6; ++j) u[j] += __shfl_down(u[j], off, 64);
   const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
   if (lane == 0)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) su[wv][j] = u[j];
+    for (int j = 0; j < 6; ++j) su[wv][j] = u[j];
   __syncthreads();
   if (threadIdx.x == 0) {
     Totals t;
-    t.accepted[0] = su[0][0] + su[1][0] + su[2][0] + su[3][0];
-    t.accepted[1] = su[0][1] + su[1][1] + su[2][1] + su[3][1];
-    t.sum_a = su[0][2] + su[1][2] + su[2][2] + su[3][2];
-    t.sum_b = su[0][3] + su[1][3] + su[2][3] + su[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) t.accepted[j] = su[0][j] + su[1][j] + su[2][j] + su[3][j];
+    t.sum_a = su[0][3] + su[1][3] + su[2][3] + su[3][3];
+    t.sum_b = su[0][4] + su[1][4] + su[2][4] + su[3][4];
+    t.attempted_learned = su[0][5] + su[1][5] + su[2][5] + su[3][5];
     t.re2 = v[0]; t.rg2 = v[1]; t.b2 = v[2]; t.e_bond = v[3]; t.e_field = v[4];
     t.h_nb = v[5];
     t.err = *err;

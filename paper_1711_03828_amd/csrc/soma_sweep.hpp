@@ -19,6 +19,7 @@
 #pragma once
 
 #include "soma_device.hpp"
+#include "soma_mlp.hpp"
 
 namespace soma {
 
@@ -38,10 +39,6 @@ struct SweepArgs {
   uint32_t seed_lo, seed_hi, sweep, replica;
   uint32_t set_order;              // 0 random per chain and sweep, 1 even first
 };
-
-// Three-component vector kept in registers (a native vector type, so that
-// selects between vectors never go through private memory).
-typedef float F3 __attribute__((ext_vector_type(3)));
 
 __device__ __forceinline__ F3 sel(bool c, F3 a, F3 b) { return c ? a : b; }
 
@@ -406,6 +403,153 @@ __global__ __launch_bounds__(256) void mc_sweep_smc_kernel(const SweepArgs a) {
   if (moved0) move_count<COUNT64>(a.counts, from0, to0, b0);
   if (moved1) move_count<COUNT64>(a.counts, from1, to1, b1);
   finish_block(a, n_acc);
+}
+
+}  // namespace soma
+
+namespace soma {
+
+// Extra arguments of the mixed local / learned sweep.
+struct MixArgs {
+  const NetDev *net;
+  HeadArgs head;
+  float p_learn;                   // probability of the learned move (state-independent)
+  unsigned long long *att_slots;   // [kAccSlots] attempted learned moves
+};
+
+// ---------------------------------------------------------------------------
+// Mixed moves: each bead makes the learned move with probability p_learn
+// (word 1 of its purpose-1 draw, independent of the configuration) and the
+// local move otherwise.  A learned move draws xi by Box-Muller from the
+// purpose-0 block, proposes r' = r + mu(r) + sigma(r) xi and accepts with
+// min(1, exp(-dE) q(r|r')/q(r'|r)) (word 0 of the purpose-1 block); a
+// non-finite network output rejects it and raises error bit 2.  The network
+// needs the bond vectors, so the two sets are handled one after the other.
+// ---------------------------------------------------------------------------
+template <bool COUNT64, bool VEC2>
+__global__ __launch_bounds__(256) void mc_sweep_mixed_kernel(const SweepArgs a, const MixArgs mx,
+                                                             uint32_t *err) {
+  __shared__ __bf16 s_act[4][64 * kActStride];
+  __shared__ float s_z[4][64 * 8];
+  const LaneMap m = lane_map(a);
+  __bf16 *act = s_act[m.wib];
+  float *zb = s_z[m.wib];
+  __bf16 *row = act + m.lane * kActStride;
+  const uint32_t N = a.n;
+  const uint32_t i0 = 2u * m.k, i1 = i0 + 1u;
+  float *cp = a.pos + (size_t)(m.has0 ? m.chain : 0u) * N * 3u + 6u * m.k;
+  F3 r0, r1;
+  load_pair<VEC2>(cp, m, r0, r1);
+
+  const uint32_t gchain = a.chain_base + m.chain;
+  const Rand4 wa0 = philox(gchain, i0 | (kPurposeMoveA << 16), a.sweep, a.replica, a.seed_lo, a.seed_hi);
+  const Rand4 wa1 = philox(gchain, i1 | (kPurposeMoveA << 16), a.sweep, a.replica, a.seed_lo, a.seed_hi);
+  const Rand4 wb0 = philox(gchain, i0 | (kPurposeMoveB << 16), a.sweep, a.replica, a.seed_lo, a.seed_hi);
+  const Rand4 wb1 = philox(gchain, i1 | (kPurposeMoveB << 16), a.sweep, a.replica, a.seed_lo, a.seed_hi);
+  const uint32_t first = set_order_bit(a, m, wa0.x);
+  const bool b0 = i0 >= a.n_a, b1 = i1 >= a.n_a;
+
+  uint32_t from0 = 0, to0 = 0, from1 = 0, to1 = 0;
+  bool moved0 = false, moved1 = false;
+  uint32_t n_acc = 0, n_acc_l = 0, n_att_l = 0;
+  bool net_bad_any = false;
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool odd = (first ^ (uint32_t)pass) != 0u;
+    const F3 send = sel(odd, r0, r1);
+    const int src = odd ? (m.lane < 63 ? m.lane + 1 : m.lane) : (m.lane > 0 ? m.lane - 1 : m.lane);
+    const F3 nb = {shfl_f(send.x, src), shfl_f(send.y, src), shfl_f(send.z, src)};
+    const F3 left = sel(odd, r0, nb);     // bead i-1
+    const F3 right = sel(odd, nb, r1);    // bead i+1
+    const bool moving = odd ? m.has1 : m.has0;
+    const bool has_l = odd || m.k > 0;
+    const bool has_r = odd ? (i1 + 1u < N) : m.has1;
+    const float wl = has_l ? 1.0f : 0.0f, wr = has_r ? 1.0f : 0.0f;
+    const F3 r = sel(odd, r1, r0);
+    const Rand4 w = odd ? wa1 : wa0;
+    const Rand4 wb = odd ? wb1 : wb0;
+    const bool is_b = odd ? b1 : b0;
+    const bool learned = moving && uniform01(wb.y) < mx.p_learn;
+    const float *om = a.omega + (is_b ? a.grid.n_cells : 0u);
+    const F3 zero3 = F3{0.f, 0.f, 0.f};
+
+    F3 rn;
+    uint32_t co, cn;
+    float w_old, w_new, log_q = 0.0f;
+    bool net_bad = false;
+    if (__ballot(learned) != 0ull) {
+      w_old = features_to_row(a.grid, a.omega, is_b, r, has_l ? left - r : zero3,
+                              has_r ? right - r : zero3, mx.net, row, co);
+      wave_forward(mx.net, act, zb);
+      float mu[3], sig[3], lsig[3];
+      head(zb + m.lane * 8, mx.head, mu, sig, lsig);
+      float xi0, xi1, xi2, xi3;
+      box_muller(w.x, w.y, xi0, xi1);
+      box_muller(w.z, w.w, xi2, xi3);
+      const F3 tl = {r.x + fmaf(sig[0], xi0, mu[0]), r.y + fmaf(sig[1], xi1, mu[1]),
+                     r.z + fmaf(sig[2], xi2, mu[2])};
+      const F3 tp = {fmaf(a.step, uniform11(w.x), r.x), fmaf(a.step, uniform11(w.y), r.y),
+                     fmaf(a.step, uniform11(w.z), r.z)};
+      rn = sel(learned, tl, tp);
+      w_new = features_to_row(a.grid, a.omega, is_b, rn, has_l ? left - rn : zero3,
+                              has_r ? right - rn : zero3, mx.net, row, cn);
+      wave_forward(mx.net, act, zb);
+      float mun[3], sign[3], lsign[3];
+      head(zb + m.lane * 8, mx.head, mun, sign, lsign);
+      float lq = 0.0f;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const float rd = d == 0 ? r.x : (d == 1 ? r.y : r.z);
+        const float td = d == 0 ? rn.x : (d == 1 ? rn.y : rn.z);
+        const float ef = td - rd - mu[d];
+        const float er = rd - td - mun[d];
+        lq += 0.5f * ef * ef / (sig[d] * sig[d]) + lsig[d] - 0.5f * er * er / (sign[d] * sign[d]) - lsign[d];
+        net_bad |= !(isfinite(mu[d]) && isfinite(sig[d]) && isfinite(mun[d]) && isfinite(sign[d]));
+      }
+      log_q = lq;   // log q(r|r') - log q(r'|r)
+      net_bad = net_bad && learned;
+    } else {
+      rn = F3{fmaf(a.step, uniform11(w.x), r.x), fmaf(a.step, uniform11(w.y), r.y),
+              fmaf(a.step, uniform11(w.z), r.z)};
+      co = cell_of(a.grid, r.x, r.y, r.z);
+      cn = cell_of(a.grid, rn.x, rn.y, rn.z);
+      w_old = om[co];
+      w_new = cn == co ? w_old : om[cn];
+    }
+    const F3 d = rn - r;
+    const F3 q = wl * (2.0f * (r - left) + d) + wr * (2.0f * (r - right) + d);
+    const float d_e = a.half_k0 * (d.x * q.x + d.y * q.y + d.z * q.z) + (w_new - w_old) * a.inv_nref;
+    bool acc;
+    if (learned) {
+      const float lr = log_q - d_e;
+      acc = !net_bad && (lr >= 0.0f || uniform01(wb.x) < __expf(lr));
+    } else {
+      acc = moving && (d_e <= 0.0f || uniform01(w.w) < __expf(-d_e));
+    }
+    net_bad_any |= net_bad;
+    if (odd) { r1 = acc ? rn : r1; moved1 = acc && cn != co; from1 = co; to1 = cn; }
+    else     { r0 = acc ? rn : r0; moved0 = acc && cn != co; from0 = co; to0 = cn; }
+    n_acc += (uint32_t)__popcll(__ballot(acc));
+    n_acc_l += (uint32_t)__popcll(__ballot(acc && learned));
+    n_att_l += (uint32_t)__popcll(__ballot(learned));
+  }
+  store_pair<VEC2>(cp, m, r0, r1);
+  if (moved0) move_count<COUNT64>(a.counts, from0, to0, b0);
+  if (moved1) move_count<COUNT64>(a.counts, from1, to1, b1);
+  if (__ballot(net_bad_any) != 0ull && m.lane == 0) atomicOr(err, 2u);
+  // local and learned acceptances go to separate slot arrays
+  __shared__ uint32_t s_cnt[4][3];
+  if (m.lane == 0) { s_cnt[m.wib][0] = n_acc - n_acc_l; s_cnt[m.wib][1] = n_acc_l; s_cnt[m.wib][2] = n_att_l; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t slot = blockIdx.x & (kAccSlots - 1u);
+    const uint32_t loc = s_cnt[0][0] + s_cnt[1][0] + s_cnt[2][0] + s_cnt[3][0];
+    const uint32_t lrn = s_cnt[0][1] + s_cnt[1][1] + s_cnt[2][1] + s_cnt[3][1];
+    const uint32_t att = s_cnt[0][2] + s_cnt[1][2] + s_cnt[2][2] + s_cnt[3][2];
+    if (loc) atomicAdd(a.acc_slots + slot, (unsigned long long)loc);
+    if (lrn) atomicAdd(a.acc_slots + 2u * kAccSlots + slot, (unsigned long long)lrn);
+    if (att) atomicAdd(mx.att_slots + slot, (unsigned long long)att);
+  }
 }
 
 }  // namespace soma

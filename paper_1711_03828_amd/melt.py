@@ -17,7 +17,8 @@ import torch
 from . import soma as C
 
 
-def make_config(w, *, seed=None, replica=0, set_order=0, origin_mode=1) -> C.soma_config:
+def make_config(w, *, seed=None, replica=0, set_order=0, origin_mode=1, p_learn=0.0,
+                mu_max=1.0, sigma_min=0.02, sigma_max=1.0) -> C.soma_config:
     cfg = C.soma_config()
     cfg.nx, cfg.ny, cfg.nz = (int(v) for v in w.grid)
     cfg.n_species = len(w.species)
@@ -37,6 +38,10 @@ def make_config(w, *, seed=None, replica=0, set_order=0, origin_mode=1) -> C.som
     cfg.count_width = w.count_width
     cfg.set_order = set_order
     cfg.origin_mode = origin_mode
+    cfg.p_learn = p_learn
+    cfg.mu_max = mu_max
+    cfg.log_sigma_min = math.log(sigma_min)
+    cfg.log_sigma_max = math.log(sigma_max)
     return cfg
 
 
@@ -70,6 +75,11 @@ class Melt:
 
     def sweep(self, n_sweeps=1, move_kind=C.SOMA_MOVE_LOCAL, stream=None):
         C.soma_mc_sweep(self.handle, n_sweeps, move_kind, _stream(stream))
+
+    def set_proposal(self, params: torch.Tensor, stream=None):
+        """Install the learned proposal's FP32 parameter blob (a device tensor)."""
+        assert params.dtype == torch.float32 and params.numel() == C.NET_PARAMS
+        C.soma_set_proposal(self.handle, params.contiguous().data_ptr(), _stream(stream))
 
     def update_fields(self, stream=None):
         C.soma_update_fields(self.handle, _stream(stream))

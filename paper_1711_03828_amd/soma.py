@@ -23,7 +23,10 @@ SOMA_E_DEVICE_FLAG = -5
 
 SOMA_MOVE_LOCAL = 0
 SOMA_MOVE_SMC = 1
+SOMA_MOVE_MIXED = 2
 SOMA_FLAG_POSITION = 1
+SOMA_FLAG_NETWORK = 2
+NET_PARAMS = 8576
 SOMA_MAX_SPECIES = 8
 SOMA_MAX_BEADS_PER_CHAIN = 128
 
@@ -41,7 +44,9 @@ class soma_config(ctypes.Structure):
                 ("kappa_n", ctypes.c_float), ("local_a", ctypes.c_float),
                 ("smc_a", ctypes.c_float), ("seed", ctypes.c_uint64),
                 ("replica", ctypes.c_uint32), ("count_width", ctypes.c_uint32),
-                ("set_order", ctypes.c_uint32), ("origin_mode", ctypes.c_uint32)]
+                ("set_order", ctypes.c_uint32), ("origin_mode", ctypes.c_uint32),
+                ("p_learn", ctypes.c_float), ("mu_max", ctypes.c_float),
+                ("log_sigma_min", ctypes.c_float), ("log_sigma_max", ctypes.c_float)]
 
 
 class soma_buffers(ctypes.Structure):
@@ -54,8 +59,8 @@ class soma_buffers(ctypes.Structure):
 class soma_obs(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_uint64), ("n_beads", ctypes.c_uint64),
                 ("n_chains", ctypes.c_uint64), ("count_a", ctypes.c_uint64),
-                ("count_b", ctypes.c_uint64), ("accepted", ctypes.c_uint64 * 2),
-                ("attempted", ctypes.c_uint64 * 2), ("re2_sum", ctypes.c_double),
+                ("count_b", ctypes.c_uint64), ("accepted", ctypes.c_uint64 * 3),
+                ("attempted", ctypes.c_uint64 * 3), ("re2_sum", ctypes.c_double),
                 ("rg2_sum", ctypes.c_double), ("b2_sum", ctypes.c_double),
                 ("e_bond", ctypes.c_double), ("e_field", ctypes.c_double),
                 ("h_nb", ctypes.c_double), ("error_flags", ctypes.c_uint32),
@@ -94,6 +99,11 @@ _SIGS = {
     "soma_density_hist": ([ctypes.POINTER(soma_config), _P, _P, _P], _i32),
     "soma_field_from_counts": ([ctypes.POINTER(soma_config), _P, _P, _P], _i32),
     "soma_init_positions": ([ctypes.POINTER(soma_config), _P, _P], _i32),
+    "soma_net_bytes": ([], ctypes.c_uint64),
+    "soma_prepare_net": ([_P, _P, _P], _i32),
+    "soma_set_proposal": ([_P, _P, _P], _i32),
+    "soma_mlp_forward": ([_P, _P, _u32, _P, _P], _i32),
+    "soma_features": ([_P, _P, _P, _u32, _P, _P], _i32),
     "soma_destroy": ([_P], None),
     "soma_last_error": ([], ctypes.c_char_p),
 }
@@ -187,6 +197,29 @@ def soma_field_from_counts(cfg: soma_config, counts_ptr: int, omega_ptr: int, st
 def soma_init_positions(cfg: soma_config, pos_ptr: int, stream: int) -> None:
     _check(_lib.soma_init_positions(ctypes.byref(cfg), ctypes.c_void_p(pos_ptr),
                                     ctypes.c_void_p(stream)))
+
+
+def soma_net_bytes() -> int:
+    return int(_lib.soma_net_bytes())
+
+
+def soma_prepare_net(params_ptr: int, net_ptr: int, stream: int) -> None:
+    _check(_lib.soma_prepare_net(ctypes.c_void_p(params_ptr), ctypes.c_void_p(net_ptr),
+                                 ctypes.c_void_p(stream)))
+
+
+def soma_set_proposal(h, params_ptr: int, stream: int) -> None:
+    _check(_lib.soma_set_proposal(h, ctypes.c_void_p(params_ptr), ctypes.c_void_p(stream)))
+
+
+def soma_mlp_forward(net_ptr: int, features_ptr: int, n: int, z_ptr: int, stream: int) -> None:
+    _check(_lib.soma_mlp_forward(ctypes.c_void_p(net_ptr), ctypes.c_void_p(features_ptr), n,
+                                 ctypes.c_void_p(z_ptr), ctypes.c_void_p(stream)))
+
+
+def soma_features(h, chains_ptr: int, beads_ptr: int, n: int, out_ptr: int, stream: int) -> None:
+    _check(_lib.soma_features(h, ctypes.c_void_p(chains_ptr), ctypes.c_void_p(beads_ptr), n,
+                              ctypes.c_void_p(out_ptr), ctypes.c_void_p(stream)))
 
 
 def soma_destroy(h) -> None:

@@ -33,7 +33,8 @@ def device_config(w, **kw):
 
 
 def custom_config(grid, species, *, k0, n_ref, chi_n=0.0, kappa_n=0.0, local_a=0.1,
-                  smc_a=0.05, seed=1, count_width=16, set_order=0, origin_mode=1, replica=0):
+                  smc_a=0.05, seed=1, count_width=16, set_order=0, origin_mode=1, replica=0,
+                  p_learn=0.0, mu_max=1.0, sigma_min=0.02, sigma_max=1.0):
     from paper_1711_03828_amd import soma as C
     cfg = C.soma_config()
     cfg.nx, cfg.ny, cfg.nz = grid
@@ -53,6 +54,10 @@ def custom_config(grid, species, *, k0, n_ref, chi_n=0.0, kappa_n=0.0, local_a=0
     cfg.count_width = count_width
     cfg.set_order = set_order
     cfg.origin_mode = origin_mode
+    cfg.p_learn = p_learn
+    cfg.mu_max = mu_max
+    cfg.log_sigma_min = math.log(sigma_min)
+    cfg.log_sigma_max = math.log(sigma_max)
     return cfg
 
 
