@@ -239,6 +239,33 @@ int32_t soma_mlp_forward(const void *net, const float *features, uint32_t n,
 int32_t soma_features(soma_system *sys, const uint32_t *chains,
                       const uint32_t *beads, uint32_t n, float *out, void *stream);
 
+/* Options of one training step of the network. */
+typedef struct soma_train_opts {
+  float lr, beta1, beta2, eps;  /* Adam */
+  float mu_max, log_sigma_min, log_sigma_max;  /* head bounds (as in soma_config) */
+  uint32_t apply;               /* 0: gradient and loss only; 1: also the Adam update */
+  uint32_t max_waves;           /* parallel partial gradients (0: one per 64 samples) */
+} soma_train_opts;
+
+/* Device workspace bytes of soma_train_step for up to max_waves partials. */
+uint64_t soma_train_workspace_bytes(uint32_t max_waves);
+
+/* One training step on a batch of n samples (device memory): features
+ * [n][60] raw features at time t, targets [n][3] the displacements of the
+ * same beads between t and a later time.  Loss: mean Gaussian negative
+ * log-likelihood of the targets under the head, without the constant.
+ * Computes the mean gradient with BF16 MFMA forward and back-propagation (FP32
+ * accumulation); with opts->apply, updates params (FP32 master blob, in
+ * place) by Adam with moments adam_m, adam_v ([8576] FP32, zero before the
+ * first step) at step `step` (1-based).  grad_out ([8576]) and loss_out (one
+ * float) may be NULL.  workspace: soma_train_workspace_bytes(waves) bytes,
+ * 256-byte aligned.  Asynchronous. */
+int32_t soma_train_step(const float *features, const float *targets, uint32_t n,
+                        float *params, float *adam_m, float *adam_v, uint32_t step,
+                        const soma_train_opts *opts, void *workspace,
+                        uint64_t workspace_bytes, float *grad_out, float *loss_out,
+                        void *stream);
+
 /* Releases the handle (host memory only). */
 void soma_destroy(soma_system *sys);
 

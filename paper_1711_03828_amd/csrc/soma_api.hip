@@ -13,6 +13,7 @@
 #include "soma_grid.hpp"
 #include "soma_obs.hpp"
 #include "soma_sweep.hpp"
+#include "soma_train.hpp"
 
 namespace {
 
@@ -550,6 +551,72 @@ int32_t soma_features(soma_system *sys, const uint32_t *chains, const uint32_t *
   hipLaunchKernelGGL(soma::features_kernel, dim3((n + 255) / 256), dim3(256), 0,
                      reinterpret_cast<hipStream_t>(stream), sys->buf.pos, sys->buf.omega,
                      sys->grid, st, chains, beads, n, out);
+  LAUNCH_TRY();
+  return SOMA_OK;
+}
+
+uint64_t soma_train_workspace_bytes(uint32_t max_waves) {
+  if (max_waves == 0) max_waves = 1;
+  return align_up(sizeof(soma::NetDev)) + align_up((uint64_t)max_waves * soma::kPSize * 4ull) +
+         align_up((uint64_t)max_waves * 4ull);
+}
+
+int32_t soma_train_step(const float *features, const float *targets, uint32_t n, float *params,
+                        float *adam_m, float *adam_v, uint32_t step, const soma_train_opts *o,
+                        void *workspace, uint64_t workspace_bytes, float *grad_out,
+                        float *loss_out, void *stream) {
+  if (!features || !targets || !params || !o || !workspace)
+    return fail(SOMA_E_INVAL, "NULL argument");
+  if (n == 0) return fail(SOMA_E_INVAL, "empty batch");
+  if (o->apply && (!adam_m || !adam_v || step == 0))
+    return fail(SOMA_E_INVAL, "an update needs Adam moments and step >= 1");
+  if (!(o->mu_max > 0.f) || !(o->log_sigma_min <= o->log_sigma_max))
+    return fail(SOMA_E_INVAL, "head bounds");
+  if (!aligned(workspace, 256)) return fail(SOMA_E_INVAL, "workspace must be 256-byte aligned");
+  const uint32_t chunks = (n + 63u) / 64u;
+  const uint32_t waves = o->max_waves ? (chunks < o->max_waves ? chunks : o->max_waves) : chunks;
+  if (workspace_bytes < soma_train_workspace_bytes(waves))
+    return fail(SOMA_E_SIZE, "train workspace: %llu < %llu bytes",
+                (unsigned long long)workspace_bytes,
+                (unsigned long long)soma_train_workspace_bytes(waves));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  unsigned char *ws = reinterpret_cast<unsigned char *>(workspace);
+  soma::NetDev *net = reinterpret_cast<soma::NetDev *>(ws);
+  float *partials = reinterpret_cast<float *>(ws + align_up(sizeof(soma::NetDev)));
+  float *lossp = reinterpret_cast<float *>(ws + align_up(sizeof(soma::NetDev)) +
+                                           align_up((uint64_t)waves * soma::kPSize * 4ull));
+  hipLaunchKernelGGL(soma::net_prepare_kernel, dim3(1), dim3(256), 0, s, params, net);
+  LAUNCH_TRY();
+  soma::TrainArgs ta;
+  ta.net = net;
+  ta.feat = features;
+  ta.target = targets;
+  ta.n = n;
+  ta.head.m_max = o->mu_max;
+  ta.head.lo = o->log_sigma_min;
+  ta.head.hi = o->log_sigma_max;
+  ta.partials = partials;
+  ta.loss_partials = lossp;
+  hipLaunchKernelGGL(soma::mlp_grad_kernel, dim3(waves), dim3(64), 0, s, ta);
+  LAUNCH_TRY();
+  soma::AdamArgs aa;
+  aa.partials = partials;
+  aa.loss_partials = lossp;
+  aa.waves = waves;
+  aa.n = n;
+  aa.params = params;
+  aa.m = adam_m;
+  aa.v = adam_v;
+  aa.lr = o->lr;
+  aa.beta1 = o->beta1;
+  aa.beta2 = o->beta2;
+  aa.eps = o->eps;
+  aa.bc1 = 1.0f - std::pow(o->beta1, (float)(step ? step : 1));
+  aa.bc2 = 1.0f - std::pow(o->beta2, (float)(step ? step : 1));
+  aa.apply = o->apply ? 1 : 0;
+  aa.grad_out = grad_out;
+  aa.loss_out = loss_out;
+  hipLaunchKernelGGL(soma::mlp_adam_kernel, dim3((soma::kPSize + 255) / 256), dim3(256), 0, s, aa);
   LAUNCH_TRY();
   return SOMA_OK;
 }

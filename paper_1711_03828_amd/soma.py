@@ -67,6 +67,13 @@ class soma_obs(ctypes.Structure):
                 ("counts_conserved", ctypes.c_uint32)]
 
 
+class soma_train_opts(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("mu_max", ctypes.c_float),
+                ("log_sigma_min", ctypes.c_float), ("log_sigma_max", ctypes.c_float),
+                ("apply", ctypes.c_uint32), ("max_waves", ctypes.c_uint32)]
+
+
 class SomaError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"soma error {code}: {msg}")
@@ -104,6 +111,9 @@ _SIGS = {
     "soma_set_proposal": ([_P, _P, _P], _i32),
     "soma_mlp_forward": ([_P, _P, _u32, _P, _P], _i32),
     "soma_features": ([_P, _P, _P, _u32, _P, _P], _i32),
+    "soma_train_workspace_bytes": ([_u32], ctypes.c_uint64),
+    "soma_train_step": ([_P, _P, _u32, _P, _P, _P, _u32, ctypes.POINTER(soma_train_opts), _P,
+                         _u64, _P, _P, _P], _i32),
     "soma_destroy": ([_P], None),
     "soma_last_error": ([], ctypes.c_char_p),
 }
@@ -220,6 +230,18 @@ def soma_mlp_forward(net_ptr: int, features_ptr: int, n: int, z_ptr: int, stream
 def soma_features(h, chains_ptr: int, beads_ptr: int, n: int, out_ptr: int, stream: int) -> None:
     _check(_lib.soma_features(h, ctypes.c_void_p(chains_ptr), ctypes.c_void_p(beads_ptr), n,
                               ctypes.c_void_p(out_ptr), ctypes.c_void_p(stream)))
+
+
+def soma_train_workspace_bytes(max_waves: int) -> int:
+    return int(_lib.soma_train_workspace_bytes(max_waves))
+
+
+def soma_train_step(features_ptr, targets_ptr, n, params_ptr, m_ptr, v_ptr, step,
+                    opts: soma_train_opts, ws_ptr, ws_bytes, grad_ptr, loss_ptr, stream) -> None:
+    vp = lambda x: ctypes.c_void_p(x) if x else None
+    _check(_lib.soma_train_step(vp(features_ptr), vp(targets_ptr), n, vp(params_ptr), vp(m_ptr),
+                                vp(v_ptr), step, ctypes.byref(opts), vp(ws_ptr), ws_bytes,
+                                vp(grad_ptr), vp(loss_ptr), ctypes.c_void_p(stream)))
 
 
 def soma_destroy(h) -> None:
