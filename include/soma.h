@@ -155,7 +155,7 @@ int32_t soma_init_system(const soma_config *cfg, const soma_buffers *buf,
  * fixed: each sweep attempts one move of every bead, the even and the odd
  * beads of a chain forming the two independent sets of Sec. 3.1.2, moved set
  * after set in a random order per chain and sweep.  move_kind is
- * SOMA_MOVE_LOCAL or SOMA_MOVE_SMC.  The histogram in buf->counts is updated
+ * SOMA_MOVE_LOCAL, SOMA_MOVE_SMC or SOMA_MOVE_MIXED.  The histogram in buf->counts is updated
  * in the same pass (a bead that changes cell is moved from its old to its new
  * cell), so after the call it equals the histogram of the final positions,
  * bit for bit.  Asynchronous. */
@@ -188,9 +188,74 @@ int32_t soma_observables(soma_system *sys, soma_obs *out, void *stream);
 int32_t soma_check(soma_system *sys, uint32_t *flags, void *stream);
 
 /* Sweep index of the next sweep (Philox counter word 2); set it to resume a
- * run from saved positions bit-exactly. */
+ * run from saved positions bit-exactly.  The index lives in the workspace
+ * (a device counter that every sweep call, graph replay or batch advances),
+ * so setting it is a tiny kernel on `stream` (asynchronous). */
 int32_t soma_get_sweep(const soma_system *sys, uint64_t *sweep);
-int32_t soma_set_sweep(soma_system *sys, uint64_t sweep);
+int32_t soma_set_sweep(soma_system *sys, uint64_t sweep, void *stream);
+
+/* ---- Captured SCMF cycles ----------------------------------------------
+ * soma_capture_cycle records `cycles` SCMF cycles of the system (MC sweep of
+ * move_kind, then the field refresh of stage 1, Sec. 2.2), followed by the
+ * advance of the device sweep counter, into a HIP graph; soma_run_cycle
+ * replays it n_launches times on `stream` (asynchronous).  A replay gives the
+ * same bits as the same cycles called one by one.  The graph holds the launch
+ * shape and buffers of capture time: capture again after
+ * soma_set_sweep_blocks.  The graph contains kernel nodes only. */
+int32_t soma_capture_cycle(soma_system *sys, uint32_t cycles, uint32_t move_kind);
+int32_t soma_run_cycle(soma_system *sys, uint32_t n_launches, void *stream);
+
+/* ---- Autotuning ----------------------------------------------------------
+ * Times candidate launch shapes over real SCMF cycles and keeps the fastest.
+ * Launch shapes never change results, so the trajectory is bit-identical to
+ * running the same number of cycles untuned: each candidate runs 1 + cycles
+ * SCMF cycles of move_kind (out->cycles_run in total; the sweep index and the
+ * acceptance counters advance accordingly).  With a cache file (may be NULL)
+ * a stored choice for the same sizes and move kind is applied without running
+ * anything (out->from_cache = 1); a new choice is appended to the file (text,
+ * one line per key; an unwritable file is ignored).  BLOCKING. */
+typedef struct soma_tune {
+  uint32_t mode;          /* batches: 0 XCD ranges, 1 round-robin items */
+  uint32_t grid_blocks;   /* 0: one block per tile group; else persistent blocks */
+  float ms_per_cycle;     /* measured time of the chosen shape (0 on a cache hit) */
+  uint32_t candidates;    /* shapes timed */
+  uint32_t cycles_run;    /* SCMF cycles run while tuning */
+  uint32_t from_cache;
+} soma_tune;
+int32_t soma_autotune(soma_system *sys, uint32_t cycles, uint32_t move_kind,
+                      const char *cache_path, void *stream, soma_tune *out);
+
+/* ---- Batches of systems ----------------------------------------------------
+ * Several systems (replicas of different sizes, chain lengths, interaction
+ * parameters; each created by soma_init_system with its own buffers) swept by
+ * one kernel launch per sweep and refreshed by one launch per field update,
+ * so that small systems together fill the GPU (Sec. 4).  Chain tiles of all
+ * systems form one work list, largest system first, cut into one contiguous
+ * range per XCD.  Every bead draws the Philox numbers of its own system, so a
+ * batched sweep equals the unbatched sweeps of the systems bit for bit.
+ * All systems need the same count_width.  The batch keeps pointers to the
+ * systems (they must outlive it) and its tables in a caller workspace of
+ * soma_batch_workspace_size bytes (256-byte aligned, device memory).
+ * soma_batch_create copies the tables and waits for the copy (blocking). */
+typedef struct soma_batch soma_batch;
+int32_t soma_batch_workspace_size(soma_system *const *systems, uint32_t n, uint64_t *bytes);
+int32_t soma_batch_create(soma_system *const *systems, uint32_t n, void *workspace,
+                          uint64_t workspace_bytes, void *stream, soma_batch **out);
+/* Launch shape: mode 0 (XCD ranges, default) or 1 (round-robin items);
+ * grid_blocks 0 (one block per item, default) or a persistent grid. */
+int32_t soma_batch_set_launch(soma_batch *b, uint32_t mode, uint32_t grid_blocks);
+/* n_sweeps sweeps of every system with fields fixed (asynchronous). */
+int32_t soma_batch_sweep(soma_batch *b, uint32_t n_sweeps, uint32_t move_kind, void *stream);
+/* Field refresh of every system (asynchronous). */
+int32_t soma_batch_update_fields(soma_batch *b, void *stream);
+/* Captured cycles of the whole batch, as soma_capture_cycle / soma_run_cycle. */
+int32_t soma_batch_capture_cycle(soma_batch *b, uint32_t cycles, uint32_t move_kind);
+int32_t soma_batch_run_cycle(soma_batch *b, uint32_t n_launches, void *stream);
+/* Autotuning of the batch's launch shape, as soma_autotune. */
+int32_t soma_batch_autotune(soma_batch *b, uint32_t cycles, uint32_t move_kind,
+                            const char *cache_path, void *stream, soma_tune *out);
+/* Releases the batch (host memory; the graph). */
+void soma_batch_destroy(soma_batch *b);
 
 /* Stand-alone occupation histogram (Eq. (4)) of `pos` into `counts`
  * (cleared first), in the packed layout of cfg->count_width.  Both are device
@@ -224,9 +289,14 @@ uint64_t soma_net_bytes(void);
  * Asynchronous. */
 int32_t soma_prepare_net(const float *params, void *net, void *stream);
 
-/* Installs the network of the mixed move into the handle's workspace (a copy:
- * `params` may be freed or changed afterwards).  Asynchronous. */
-int32_t soma_set_proposal(soma_system *sys, const float *params, void *stream);
+/* Installs the network of the mixed move for one species (or for every species
+ * with species = SOMA_ALL_SPECIES) into the handle's workspace; a copy:
+ * `params` may be freed or changed afterwards.  Mixed sweeps with p_learn > 0
+ * need a network for every species that has chains.  Asynchronous.
+ * SOMA_E_INVAL for a species index out of range. */
+#define SOMA_ALL_SPECIES 0xFFFFFFFFu
+int32_t soma_set_proposal(soma_system *sys, uint32_t species, const float *params,
+                          void *stream);
 
 /* Network outputs z [n][6] (FP32) for raw features [n][60] (FP32), both device
  * memory, with a prepared network.  Asynchronous. */
@@ -238,6 +308,21 @@ int32_t soma_mlp_forward(const void *net, const float *features, uint32_t n,
  * Asynchronous. */
 int32_t soma_features(soma_system *sys, const uint32_t *chains,
                       const uint32_t *beads, uint32_t n, float *out, void *stream);
+
+/* Training samples from the running melt (plain-sampler trajectories).
+ * Sample s (0 <= s < n) of round `round` is bead i of global chain c with
+ * c = floor(w0 * n_chains / 2^32), i = floor(w1 * n_species_beads / 2^32),
+ * where (w0, w1, ...) is the Philox4x32-10 block of counter
+ * (s, 5 << 16, round, replica) and the system's key.
+ *   phase 0: writes r0 [n][3] = its position, features [n][60] (if not NULL)
+ *            and picked [n][2] = (c, i) (if not NULL);
+ *   phase 1: writes dr [n][3] = position now - r0 (same samples: same round).
+ * Call phase 0, run K SCMF cycles, call phase 1: (features, dr) is one batch
+ * of (input, target) pairs for soma_train_step.  All buffers device memory,
+ * caller-owned.  Asynchronous. */
+int32_t soma_collect_training(soma_system *sys, uint32_t n, uint32_t round, uint32_t phase,
+                              float *features, float *r0, float *dr, uint32_t *picked,
+                              void *stream);
 
 /* Options of one training step of the network. */
 typedef struct soma_train_opts {
@@ -266,7 +351,7 @@ int32_t soma_train_step(const float *features, const float *targets, uint32_t n,
                         uint64_t workspace_bytes, float *grad_out, float *loss_out,
                         void *stream);
 
-/* Releases the handle (host memory only). */
+/* Releases the handle (host memory and a captured graph). */
 void soma_destroy(soma_system *sys);
 
 /* Message of the last failed call on this thread ("" if none). */

@@ -6,7 +6,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
+#include <string>
+#include <vector>
 
 #include "soma.h"
 #include "soma_device.hpp"
@@ -14,6 +17,7 @@
 #include "soma_obs.hpp"
 #include "soma_sweep.hpp"
 #include "soma_train.hpp"
+#include "soma_batch.hpp"
 
 namespace {
 
@@ -51,6 +55,7 @@ struct Derived {
   uint64_t off_err = 0, off_acc = 0, off_att = 0, off_net = 0, off_fpart = 0, off_totals = 0,
            off_opart = 0;
   uint64_t ws_bytes = 0;
+  uint32_t field_blocks = 1;  // blocks of the field update (and its FP64 partial sums)
 };
 
 int32_t derive(const soma_config *c, Derived *d) {
@@ -75,6 +80,10 @@ int32_t derive(const soma_config *c, Derived *d) {
       !std::isfinite(c->smc_a) || c->local_a < 0.f || c->smc_a < 0.f)
     return fail(SOMA_E_INVAL, "chi_n, kappa_n, local_a, smc_a must be finite (steps >= 0)");
   d->n_cells = n_cells;
+  {
+    const uint64_t fb = (n_cells + 4095) / 4096;
+    d->field_blocks = (uint32_t)(fb < soma::kFieldBlocks ? fb : soma::kFieldBlocks);
+  }
   d->n_beads = d->n_chains = d->n_a_total = d->obs_blocks = 0;
   for (uint32_t s = 0; s < c->n_species; ++s) {
     const soma_species &sp = c->species[s];
@@ -101,7 +110,7 @@ int32_t derive(const soma_config *c, Derived *d) {
   d->off_acc = align_up(d->off_err + 16);
   d->off_att = align_up(d->off_acc + 3ull * soma::kAccSlots * 8ull);
   d->off_net = align_up(d->off_att + soma::kAccSlots * 8ull);
-  d->off_fpart = align_up(d->off_net + sizeof(soma::NetDev));
+  d->off_fpart = align_up(d->off_net + SOMA_MAX_SPECIES * align_up(sizeof(soma::NetDev)));
   d->off_totals = align_up(d->off_fpart + soma::kFieldBlocks * sizeof(soma::FieldPartial));
   d->off_opart = align_up(d->off_totals + sizeof(soma::Totals));
   d->ws_bytes = align_up(d->off_opart + (d->obs_blocks ? d->obs_blocks : 1) * sizeof(soma::ObsPartial));
@@ -153,8 +162,8 @@ int32_t launch_hist(const soma_config *c, const Derived &d, const float *pos, vo
   return SOMA_OK;
 }
 
-int32_t launch_field(const soma_config *c, const Derived &d, void *counts, float *omega,
-                     soma::FieldPartial *partials, int clear, hipStream_t s) {
+soma::FieldArgs field_args(const soma_config *c, const Derived &d, void *counts, float *omega,
+                           soma::FieldPartial *partials) {
   soma::FieldArgs a;
   a.counts = counts;
   a.omega = omega;
@@ -166,8 +175,14 @@ int32_t launch_field(const soma_config *c, const Derived &d, void *counts, float
   a.chi_n_d = (double)c->chi_n;
   a.kappa_n_d = (double)c->kappa_n;
   a.partials = partials;
-  a.clear = clear;
-  const uint32_t blocks = soma::kFieldBlocks;
+  a.clear = 0;
+  return a;
+}
+
+int32_t launch_field(const soma_config *c, const Derived &d, void *counts, float *omega,
+                     soma::FieldPartial *partials, hipStream_t s) {
+  const soma::FieldArgs a = field_args(c, d, counts, omega, partials);
+  const uint32_t blocks = d.field_blocks;
   if (c->count_width == 32)
     hipLaunchKernelGGL(soma::field_update_kernel<true>, dim3(blocks), dim3(256), 0, s, a);
   else
@@ -204,6 +219,21 @@ bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p
 
 }  // namespace
 
+// An instantiated graph of SCMF cycles (sweep, field refresh) x cycles, then
+// the advance of the device sweep counters.
+struct CycleGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint32_t cycles = 0, kind = 0;
+  void release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    cycles = 0;
+  }
+};
+
 struct soma_system {
   soma_config cfg;
   soma_buffers buf;
@@ -213,81 +243,166 @@ struct soma_system {
   uint64_t attempted[2] = {0, 0};
   uint32_t sweep_blocks = 0;  // local-move grid: 0 = one tile per wave, else persistent blocks
   uint64_t mixed_moves = 0;   // bead moves made by mixed sweeps (local or learned)
-  bool has_net = false;
+  uint32_t net_mask = 0;      // species with an installed network (bit per species)
   unsigned char *ws = nullptr;
+  CycleGraph graph;
+  ~soma_system() { graph.release(); }
   uint32_t *err() { return reinterpret_cast<uint32_t *>(ws + d.off_err); }
+  uint32_t *sweep_ctr() { return reinterpret_cast<uint32_t *>(ws + d.off_err) + 1; }
+  void count_sweeps(uint32_t kind, uint64_t n) {
+    sweep += n;
+    if (kind == SOMA_MOVE_MIXED) mixed_moves += n * d.n_beads;
+    else attempted[kind] += n * d.n_beads;
+  }
   unsigned long long *acc() { return reinterpret_cast<unsigned long long *>(ws + d.off_acc); }
   soma::FieldPartial *fpart() { return reinterpret_cast<soma::FieldPartial *>(ws + d.off_fpart); }
   soma::Totals *totals() { return reinterpret_cast<soma::Totals *>(ws + d.off_totals); }
   soma::ObsPartial *opart() { return reinterpret_cast<soma::ObsPartial *>(ws + d.off_opart); }
   unsigned long long *att() { return reinterpret_cast<unsigned long long *>(ws + d.off_att); }
-  soma::NetDev *net() { return reinterpret_cast<soma::NetDev *>(ws + d.off_net); }
+  soma::NetDev *net(uint32_t sp) {
+    return reinterpret_cast<soma::NetDev *>(ws + d.off_net + sp * align_up(sizeof(soma::NetDev)));
+  }
+  bool nets_ready() const {
+    for (uint32_t sp = 0; sp < cfg.n_species; ++sp)
+      if (cfg.species[sp].n_chains && !(net_mask >> sp & 1u)) return false;
+    return true;
+  }
 };
 
 namespace {
 
 template <bool C64, bool V2>
 void launch_sweep_t(uint32_t kind, dim3 grid, hipStream_t s, const soma::SweepArgs &a,
-                    const soma::MixArgs &mx, uint32_t *err) {
+                    const soma::MixArgs &mx) {
   if (kind == SOMA_MOVE_MIXED)
-    hipLaunchKernelGGL((soma::mc_sweep_mixed_kernel<C64, V2>), grid, dim3(256), 0, s, a, mx, err);
+    hipLaunchKernelGGL((soma::mc_sweep_mixed_kernel<C64, V2>), grid, dim3(256), 0, s, a, mx);
   else if (kind == SOMA_MOVE_SMC)
     hipLaunchKernelGGL((soma::mc_sweep_smc_kernel<C64, V2>), grid, dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL((soma::mc_sweep_local_kernel<C64, V2>), grid, dim3(256), 0, s, a);
 }
 
-int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s) {
+// Arguments of species sp's sweep of kind `kind` (sweep offset 0).
+void sweep_args(soma_system *sys, uint32_t sp, uint32_t kind, soma::SweepArgs &a,
+                soma::MixArgs &mx) {
+  const soma_config *c = &sys->cfg;
+  const soma_species &S = c->species[sp];
+  a.pos = sys->buf.pos + 3 * sys->d.bead_off[sp];
+  a.omega = sys->buf.omega;
+  a.counts = sys->buf.counts;
+  a.acc_slots = sys->acc() + (kind == SOMA_MOVE_SMC ? soma::kAccSlots : 0u);
+  a.grid = sys->grid;
+  a.n_chains = S.n_chains;
+  a.n = S.n;
+  a.n_a = S.n_a;
+  a.lanes_per_chain = (S.n + 1) / 2;
+  a.chains_per_wave = 64u / a.lanes_per_chain;
+  a.chain_base = (uint32_t)sys->d.chain_off[sp];
+  a.k0 = S.k0;
+  a.half_k0 = 0.5f * S.k0;
+  a.step = kind == SOMA_MOVE_SMC ? c->smc_a : c->local_a;  // mixed: local half-width
+  a.sqrt_2a = (float)std::sqrt(2.0 * (double)c->smc_a);
+  a.inv_4a = c->smc_a > 0.f ? (float)(1.0 / (4.0 * (double)c->smc_a)) : 0.f;
+  a.inv_nref = (float)(1.0 / (double)c->n_ref);
+  a.seed_lo = (uint32_t)c->seed;
+  a.seed_hi = (uint32_t)(c->seed >> 32);
+  a.sweep = 0;
+  a.replica = c->replica;
+  a.set_order = c->set_order;
+  a.sweep_ctr = sys->sweep_ctr();
+  mx.net = sys->net(sp);
+  mx.head.m_max = c->mu_max;
+  mx.head.lo = c->log_sigma_min;
+  mx.head.hi = c->log_sigma_max;
+  mx.p_learn = c->p_learn;
+  mx.att_slots = sys->att();
+  mx.err = sys->err();
+}
+
+bool species_vec2(const soma_system *sys, uint32_t sp) {
+  const uint64_t off = sys->d.bead_off[sp];
+  return (sys->cfg.species[sp].n % 2 == 0) && (off % 2 == 0) &&
+         aligned(sys->buf.pos + 3 * off, 8);
+}
+
+// One sweep of every species; `off` is added to the device sweep counter.
+int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s, uint32_t off) {
   const soma_config *c = &sys->cfg;
   for (uint32_t sp = 0; sp < c->n_species; ++sp) {
     const soma_species &S = c->species[sp];
     if (!S.n_chains) continue;
     soma::SweepArgs a;
-    a.pos = sys->buf.pos + 3 * sys->d.bead_off[sp];
-    a.omega = sys->buf.omega;
-    a.counts = sys->buf.counts;
-    a.acc_slots = sys->acc() + (kind == SOMA_MOVE_SMC ? soma::kAccSlots : 0u);
     soma::MixArgs mx;
-    mx.net = sys->net();
-    mx.head.m_max = c->mu_max;
-    mx.head.lo = c->log_sigma_min;
-    mx.head.hi = c->log_sigma_max;
-    mx.p_learn = c->p_learn;
-    mx.att_slots = sys->att();
-    a.grid = sys->grid;
-    a.n_chains = S.n_chains;
-    a.n = S.n;
-    a.n_a = S.n_a;
-    a.lanes_per_chain = (S.n + 1) / 2;
-    a.chains_per_wave = 64u / a.lanes_per_chain;
-    a.chain_base = (uint32_t)sys->d.chain_off[sp];
-    a.k0 = S.k0;
-    a.half_k0 = 0.5f * S.k0;
-    a.step = kind == SOMA_MOVE_SMC ? c->smc_a : c->local_a;  // mixed: local half-width
-    a.sqrt_2a = (float)std::sqrt(2.0 * (double)c->smc_a);
-    a.inv_4a = c->smc_a > 0.f ? (float)(1.0 / (4.0 * (double)c->smc_a)) : 0.f;
-    a.inv_nref = (float)(1.0 / (double)c->n_ref);
-    a.seed_lo = (uint32_t)c->seed;
-    a.seed_hi = (uint32_t)(c->seed >> 32);
-    a.sweep = (uint32_t)sys->sweep;
-    a.replica = c->replica;
-    a.set_order = c->set_order;
+    sweep_args(sys, sp, kind, a, mx);
+    a.sweep = off;
     const uint64_t chains_per_block = 4ull * a.chains_per_wave;
     uint64_t blocks = (S.n_chains + chains_per_block - 1) / chains_per_block;
     if (kind == SOMA_MOVE_LOCAL && sys->sweep_blocks && sys->sweep_blocks < blocks)
       blocks = sys->sweep_blocks;
-    const bool v2 = (S.n % 2 == 0) && (sys->d.bead_off[sp] % 2 == 0) && aligned(a.pos, 8);
+    const bool v2 = species_vec2(sys, sp);
     const bool c64 = c->count_width == 32;
     const dim3 grid((uint32_t)blocks);
     if (c64) {
-      if (v2) launch_sweep_t<true, true>(kind, grid, s, a, mx, sys->err());
-      else launch_sweep_t<true, false>(kind, grid, s, a, mx, sys->err());
+      if (v2) launch_sweep_t<true, true>(kind, grid, s, a, mx);
+      else launch_sweep_t<true, false>(kind, grid, s, a, mx);
     } else {
-      if (v2) launch_sweep_t<false, true>(kind, grid, s, a, mx, sys->err());
-      else launch_sweep_t<false, false>(kind, grid, s, a, mx, sys->err());
+      if (v2) launch_sweep_t<false, true>(kind, grid, s, a, mx);
+      else launch_sweep_t<false, false>(kind, grid, s, a, mx);
     }
     LAUNCH_TRY();
   }
+  return SOMA_OK;
+}
+
+int32_t launch_counter(uint32_t *ctr, uint32_t by, uint32_t set, uint32_t value, hipStream_t s) {
+  hipLaunchKernelGGL(soma::sweep_counter_one_kernel, dim3(1), dim3(64), 0, s, ctr, by, set, value);
+  LAUNCH_TRY();
+  return SOMA_OK;
+}
+
+int32_t check_kind(soma_system *sys, uint32_t move_kind) {
+  if (move_kind != SOMA_MOVE_LOCAL && move_kind != SOMA_MOVE_SMC && move_kind != SOMA_MOVE_MIXED)
+    return fail(SOMA_E_UNSUPPORTED, "move kind %u", move_kind);
+  if (move_kind == SOMA_MOVE_MIXED && sys->cfg.p_learn > 0.f && !sys->nets_ready())
+    return fail(SOMA_E_INVAL, "mixed moves need a network for every species (soma_set_proposal)");
+  if (move_kind == SOMA_MOVE_SMC && !(sys->cfg.smc_a > 0.f))
+    return fail(SOMA_E_INVAL, "smart-MC moves need smc_a > 0");
+  if (move_kind != SOMA_MOVE_SMC && !(sys->cfg.local_a < 1.f))
+    return fail(SOMA_E_UNSUPPORTED, "local moves need a half-width below one cell");
+  return SOMA_OK;
+}
+
+// Records what `enqueue(stream)` launches into a graph and instantiates it.
+// Capture runs on a private stream, so nothing executes while recording.
+template <class F>
+int32_t capture_graph(CycleGraph &g, uint32_t cycles, uint32_t kind, F enqueue) {
+  hipStream_t cs = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return fail(SOMA_E_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  }
+  const int32_t rc = enqueue(cs);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cs, &graph);
+  (void)hipStreamDestroy(cs);
+  if (rc || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc) return rc;
+    return fail(SOMA_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(SOMA_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  g.release();
+  g.graph = graph;
+  g.exec = exec;
+  g.cycles = cycles;
+  g.kind = kind;
   return SOMA_OK;
 }
 
@@ -352,7 +467,7 @@ int32_t soma_init_system(const soma_config *cfg, const soma_buffers *buf, uint32
   rc = launch_zero(sys->ws, d.ws_bytes, s);
   if (!rc && init_positions) rc = launch_init(cfg, d, buf->pos, s);
   if (!rc) rc = launch_hist(cfg, d, buf->pos, buf->counts, s);
-  if (!rc) rc = launch_field(cfg, d, buf->counts, buf->omega, sys->fpart(), 0, s);
+  if (!rc) rc = launch_field(cfg, d, buf->counts, buf->omega, sys->fpart(), s);
   if (rc) {
     delete sys;
     return rc;
@@ -363,22 +478,43 @@ int32_t soma_init_system(const soma_config *cfg, const soma_buffers *buf, uint32
 
 int32_t soma_mc_sweep(soma_system *sys, uint32_t n_sweeps, uint32_t move_kind, void *stream) {
   if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
-  if (move_kind != SOMA_MOVE_LOCAL && move_kind != SOMA_MOVE_SMC && move_kind != SOMA_MOVE_MIXED)
-    return fail(SOMA_E_UNSUPPORTED, "move kind %u", move_kind);
-  if (move_kind == SOMA_MOVE_MIXED && !sys->has_net && sys->cfg.p_learn > 0.f)
-    return fail(SOMA_E_INVAL, "mixed moves need a network (soma_set_proposal)");
-  if (move_kind == SOMA_MOVE_SMC && !(sys->cfg.smc_a > 0.f))
-    return fail(SOMA_E_INVAL, "smart-MC moves need smc_a > 0");
-  if (move_kind != SOMA_MOVE_SMC && !(sys->cfg.local_a < 1.f))
-    return fail(SOMA_E_UNSUPPORTED, "local moves need a half-width below one cell");
+  int32_t rc = check_kind(sys, move_kind);
+  if (rc) return rc;
+  if (n_sweeps == 0) return SOMA_OK;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   for (uint32_t i = 0; i < n_sweeps; ++i) {
-    const int32_t rc = launch_sweep(sys, move_kind, s);
+    rc = launch_sweep(sys, move_kind, s, i);
     if (rc) return rc;
-    sys->sweep += 1;
   }
-  if (move_kind == SOMA_MOVE_MIXED) sys->mixed_moves += (uint64_t)n_sweeps * sys->d.n_beads;
-  else sys->attempted[move_kind] += (uint64_t)n_sweeps * sys->d.n_beads;
+  rc = launch_counter(sys->sweep_ctr(), n_sweeps, 0, 0, s);
+  if (rc) return rc;
+  sys->count_sweeps(move_kind, n_sweeps);
+  return SOMA_OK;
+}
+
+int32_t soma_capture_cycle(soma_system *sys, uint32_t cycles, uint32_t move_kind) {
+  if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
+  if (cycles == 0) return fail(SOMA_E_INVAL, "cycles must be positive");
+  int32_t rc = check_kind(sys, move_kind);
+  if (rc) return rc;
+  return capture_graph(sys->graph, cycles, move_kind, [&](hipStream_t cs) -> int32_t {
+    for (uint32_t i = 0; i < cycles; ++i) {
+      int32_t r = launch_sweep(sys, move_kind, cs, i);
+      if (!r) r = launch_field(&sys->cfg, sys->d, sys->buf.counts, sys->buf.omega, sys->fpart(), cs);
+      if (r) return r;
+    }
+    return launch_counter(sys->sweep_ctr(), cycles, 0, 0, cs);
+  });
+}
+
+int32_t soma_run_cycle(soma_system *sys, uint32_t n_launches, void *stream) {
+  if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
+  if (!sys->graph.exec) return fail(SOMA_E_INVAL, "no captured cycle (soma_capture_cycle)");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (uint32_t i = 0; i < n_launches; ++i) {
+    HIP_TRY(hipGraphLaunch(sys->graph.exec, s));
+    sys->count_sweeps(sys->graph.kind, sys->graph.cycles);
+  }
   return SOMA_OK;
 }
 
@@ -396,7 +532,7 @@ int32_t soma_rebuild_histogram(soma_system *sys, void *stream) {
 
 int32_t soma_update_fields(soma_system *sys, void *stream) {
   if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
-  return launch_field(&sys->cfg, sys->d, sys->buf.counts, sys->buf.omega, sys->fpart(), 0,
+  return launch_field(&sys->cfg, sys->d, sys->buf.counts, sys->buf.omega, sys->fpart(),
                       reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -422,7 +558,7 @@ int32_t soma_observables(soma_system *sys, soma_obs *out, void *stream) {
     LAUNCH_TRY();
   }
   hipLaunchKernelGGL(soma::reduce_totals_kernel, dim3(1), dim3(256), 0, s, sys->opart(),
-                     (uint32_t)sys->d.obs_blocks, sys->fpart(), soma::kFieldBlocks, sys->acc(),
+                     (uint32_t)sys->d.obs_blocks, sys->fpart(), sys->d.field_blocks, sys->acc(),
                      sys->att(), sys->err(), sys->totals());
   LAUNCH_TRY();
   soma::Totals t;
@@ -468,8 +604,11 @@ int32_t soma_get_sweep(const soma_system *sys, uint64_t *sweep) {
   return SOMA_OK;
 }
 
-int32_t soma_set_sweep(soma_system *sys, uint64_t sweep) {
+int32_t soma_set_sweep(soma_system *sys, uint64_t sweep, void *stream) {
   if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
+  const int32_t rc = launch_counter(sys->sweep_ctr(), 0, 1, (uint32_t)sweep,
+                                    reinterpret_cast<hipStream_t>(stream));
+  if (rc) return rc;
   sys->sweep = sweep;
   return SOMA_OK;
 }
@@ -491,7 +630,7 @@ int32_t soma_field_from_counts(const soma_config *cfg, const void *counts, float
   if (!counts || !omega) return fail(SOMA_E_INVAL, "NULL buffer");
   if (!aligned(counts, 16) || !aligned(omega, 16))
     return fail(SOMA_E_INVAL, "counts and omega must be 16-byte aligned");
-  return launch_field(cfg, d, const_cast<void *>(counts), omega, nullptr, 0,
+  return launch_field(cfg, d, const_cast<void *>(counts), omega, nullptr,
                       reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -515,11 +654,19 @@ int32_t soma_prepare_net(const float *params, void *net, void *stream) {
   return SOMA_OK;
 }
 
-int32_t soma_set_proposal(soma_system *sys, const float *params, void *stream) {
+int32_t soma_set_proposal(soma_system *sys, uint32_t species, const float *params,
+                          void *stream) {
   if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
-  const int32_t rc = soma_prepare_net(params, sys->net(), stream);
-  if (rc) return rc;
-  sys->has_net = true;
+  const uint32_t n_sp = sys->cfg.n_species;
+  if (species != SOMA_ALL_SPECIES && species >= n_sp)
+    return fail(SOMA_E_INVAL, "species %u of %u", species, n_sp);
+  const uint32_t lo = species == SOMA_ALL_SPECIES ? 0u : species;
+  const uint32_t hi = species == SOMA_ALL_SPECIES ? n_sp : species + 1u;
+  for (uint32_t sp = lo; sp < hi; ++sp) {
+    const int32_t rc = soma_prepare_net(params, sys->net(sp), stream);
+    if (rc) return rc;
+    sys->net_mask |= 1u << sp;
+  }
   return SOMA_OK;
 }
 
@@ -534,10 +681,8 @@ int32_t soma_mlp_forward(const void *net, const float *features, uint32_t n, flo
   return SOMA_OK;
 }
 
-int32_t soma_features(soma_system *sys, const uint32_t *chains, const uint32_t *beads,
-                      uint32_t n, float *out, void *stream) {
-  if (!sys || !chains || !beads || !out) return fail(SOMA_E_INVAL, "NULL argument");
-  if (n == 0) return SOMA_OK;
+namespace {
+soma::SpeciesTable species_table(const soma_system *sys) {
   soma::SpeciesTable st;
   st.n_species = sys->cfg.n_species;
   st.total_chains = (uint32_t)sys->d.n_chains;
@@ -548,9 +693,45 @@ int32_t soma_features(soma_system *sys, const uint32_t *chains, const uint32_t *
     st.n[k] = ok ? sys->cfg.species[k].n : 1u;
     st.n_a[k] = ok ? sys->cfg.species[k].n_a : 0u;
   }
+  return st;
+}
+}  // namespace
+
+int32_t soma_features(soma_system *sys, const uint32_t *chains, const uint32_t *beads,
+                      uint32_t n, float *out, void *stream) {
+  if (!sys || !chains || !beads || !out) return fail(SOMA_E_INVAL, "NULL argument");
+  if (n == 0) return SOMA_OK;
   hipLaunchKernelGGL(soma::features_kernel, dim3((n + 255) / 256), dim3(256), 0,
                      reinterpret_cast<hipStream_t>(stream), sys->buf.pos, sys->buf.omega,
-                     sys->grid, st, chains, beads, n, out);
+                     sys->grid, species_table(sys), chains, beads, n, out);
+  LAUNCH_TRY();
+  return SOMA_OK;
+}
+
+int32_t soma_collect_training(soma_system *sys, uint32_t n, uint32_t round, uint32_t phase,
+                              float *features, float *r0, float *dr, uint32_t *picked,
+                              void *stream) {
+  if (!sys || !r0) return fail(SOMA_E_INVAL, "NULL argument");
+  if (phase > 1) return fail(SOMA_E_INVAL, "phase %u", phase);
+  if (phase == 1 && !dr) return fail(SOMA_E_INVAL, "phase 1 needs dr");
+  if (n == 0) return SOMA_OK;
+  soma::CollectArgs a;
+  a.pos = sys->buf.pos;
+  a.omega = sys->buf.omega;
+  a.grid = sys->grid;
+  a.st = species_table(sys);
+  a.seed_lo = (uint32_t)sys->cfg.seed;
+  a.seed_hi = (uint32_t)(sys->cfg.seed >> 32);
+  a.replica = sys->cfg.replica;
+  a.round = round;
+  a.n = n;
+  a.phase = phase;
+  a.features = features;
+  a.r0 = r0;
+  a.dr = dr;
+  a.picked = picked;
+  hipLaunchKernelGGL(soma::collect_kernel, dim3((n + 255) / 256), dim3(256), 0,
+                     reinterpret_cast<hipStream_t>(stream), a);
   LAUNCH_TRY();
   return SOMA_OK;
 }
@@ -620,6 +801,456 @@ int32_t soma_train_step(const float *features, const float *targets, uint32_t n,
   LAUNCH_TRY();
   return SOMA_OK;
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches: one launch per sweep (and per field refresh) for many systems.
+// ---------------------------------------------------------------------------
+struct soma_batch {
+  std::vector<soma_system *> sys;
+  // host copies of the device tables (kept for the batch's lifetime)
+  std::vector<soma::BatchSeg> segs[3];
+  std::vector<uint32_t> seg_first;
+  std::vector<soma::FieldArgs> fargs;
+  std::vector<uint32_t> fb_first;
+  std::vector<uint32_t *> ctrs;
+  soma::BatchSeg *d_segs[3] = {nullptr, nullptr, nullptr};
+  uint32_t *d_seg_first = nullptr, *d_fb_first = nullptr;
+  soma::FieldArgs *d_fargs = nullptr;
+  uint32_t **d_ctrs = nullptr;
+  uint32_t n_items = 0, c64 = 0, v2 = 1;
+  uint32_t mode = 0, grid_blocks = 0;  // launch shape (results do not depend on it)
+  CycleGraph graph;
+  ~soma_batch() { graph.release(); }
+};
+
+namespace {
+
+struct BatchLayout {
+  uint64_t segs[3], seg_first, fargs, fb_first, ctrs, total;
+};
+
+BatchLayout batch_layout(uint64_t n_segs, uint64_t n_sys) {
+  BatchLayout L;
+  uint64_t o = 0;
+  for (int k = 0; k < 3; ++k) {
+    L.segs[k] = o;
+    o = align_up(o + n_segs * sizeof(soma::BatchSeg));
+  }
+  L.seg_first = o;
+  o = align_up(o + (n_segs + 1) * 4);
+  L.fargs = o;
+  o = align_up(o + n_sys * sizeof(soma::FieldArgs));
+  L.fb_first = o;
+  o = align_up(o + (n_sys + 1) * 4);
+  L.ctrs = o;
+  o = align_up(o + n_sys * 8);
+  L.total = o;
+  return L;
+}
+
+int32_t batch_segments(soma_system *const *systems, uint32_t n, uint64_t *n_segs) {
+  if (!systems || n == 0) return fail(SOMA_E_INVAL, "empty batch");
+  uint64_t k = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    if (!systems[i]) return fail(SOMA_E_INVAL, "system %u is NULL", i);
+    for (uint32_t sp = 0; sp < systems[i]->cfg.n_species; ++sp)
+      if (systems[i]->cfg.species[sp].n_chains) ++k;
+    if (systems[i]->cfg.count_width != systems[0]->cfg.count_width)
+      return fail(SOMA_E_UNSUPPORTED, "all systems of a batch need the same count_width");
+  }
+  *n_segs = k;
+  return SOMA_OK;
+}
+
+uint32_t items_of(const soma::SweepArgs &a) {
+  const uint32_t per = 4u * a.chains_per_wave;
+  return (a.n_chains + per - 1u) / per;
+}
+
+template <bool C64, bool V2>
+void launch_batch_t(uint32_t kind, dim3 grid, hipStream_t s, const soma::BatchLaunch &L) {
+  if (kind == SOMA_MOVE_MIXED)
+    hipLaunchKernelGGL((soma::batched_sweep_kernel<C64, V2, 2>), grid, dim3(256), 0, s, L);
+  else if (kind == SOMA_MOVE_SMC)
+    hipLaunchKernelGGL((soma::batched_sweep_kernel<C64, V2, 1>), grid, dim3(256), 0, s, L);
+  else
+    hipLaunchKernelGGL((soma::batched_sweep_kernel<C64, V2, 0>), grid, dim3(256), 0, s, L);
+}
+
+int32_t launch_batch_sweep(soma_batch *b, uint32_t kind, hipStream_t s, uint32_t off) {
+  soma::BatchLaunch L;
+  L.segs = b->d_segs[kind];
+  L.seg_first = b->d_seg_first;
+  L.n_segs = (uint32_t)b->seg_first.size() - 1u;
+  L.n_items = b->n_items;
+  L.per_xcd = (b->n_items + 7u) / 8u;
+  L.mode = b->mode;
+  L.sweep_off = off;
+  uint32_t blocks;
+  if (b->mode == 0) {
+    blocks = 8u * L.per_xcd;
+    if (b->grid_blocks && b->grid_blocks < blocks) blocks = (b->grid_blocks + 7u) / 8u * 8u;
+  } else {
+    blocks = b->n_items;
+    if (b->grid_blocks && b->grid_blocks < blocks) blocks = b->grid_blocks;
+  }
+  const dim3 grid(blocks);
+  if (b->c64) {
+    if (b->v2) launch_batch_t<true, true>(kind, grid, s, L);
+    else launch_batch_t<true, false>(kind, grid, s, L);
+  } else {
+    if (b->v2) launch_batch_t<false, true>(kind, grid, s, L);
+    else launch_batch_t<false, false>(kind, grid, s, L);
+  }
+  LAUNCH_TRY();
+  return SOMA_OK;
+}
+
+int32_t launch_batch_field(soma_batch *b, hipStream_t s) {
+  const uint32_t n_sys = (uint32_t)b->sys.size();
+  const dim3 grid(b->fb_first[n_sys]);
+  if (b->c64)
+    hipLaunchKernelGGL(soma::batched_field_kernel<true>, grid, dim3(256), 0, s, b->d_fargs,
+                       b->d_fb_first, n_sys);
+  else
+    hipLaunchKernelGGL(soma::batched_field_kernel<false>, grid, dim3(256), 0, s, b->d_fargs,
+                       b->d_fb_first, n_sys);
+  LAUNCH_TRY();
+  return SOMA_OK;
+}
+
+int32_t launch_batch_counter(soma_batch *b, uint32_t by, hipStream_t s) {
+  const uint32_t n_sys = (uint32_t)b->sys.size();
+  hipLaunchKernelGGL(soma::sweep_counter_kernel, dim3((n_sys + 63) / 64), dim3(64), 0, s,
+                     b->d_ctrs, n_sys, by, 0u, 0u);
+  LAUNCH_TRY();
+  return SOMA_OK;
+}
+
+int32_t batch_check_kind(soma_batch *b, uint32_t kind) {
+  for (soma_system *x : b->sys) {
+    const int32_t rc = check_kind(x, kind);
+    if (rc) return rc;
+  }
+  return SOMA_OK;
+}
+
+void batch_count(soma_batch *b, uint32_t kind, uint64_t n) {
+  for (soma_system *x : b->sys) x->count_sweeps(kind, n);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t soma_batch_workspace_size(soma_system *const *systems, uint32_t n, uint64_t *bytes) {
+  if (!bytes) return fail(SOMA_E_INVAL, "bytes is NULL");
+  uint64_t n_segs = 0;
+  const int32_t rc = batch_segments(systems, n, &n_segs);
+  if (rc) return rc;
+  *bytes = batch_layout(n_segs, n).total;
+  return SOMA_OK;
+}
+
+int32_t soma_batch_create(soma_system *const *systems, uint32_t n, void *workspace,
+                          uint64_t workspace_bytes, void *stream, soma_batch **out) {
+  if (!out) return fail(SOMA_E_INVAL, "out is NULL");
+  *out = nullptr;
+  uint64_t n_segs = 0;
+  int32_t rc = batch_segments(systems, n, &n_segs);
+  if (rc) return rc;
+  const BatchLayout lay = batch_layout(n_segs, n);
+  if (!workspace) return fail(SOMA_E_INVAL, "workspace is NULL");
+  if (!aligned(workspace, 256)) return fail(SOMA_E_INVAL, "workspace must be 256-byte aligned");
+  if (workspace_bytes < lay.total)
+    return fail(SOMA_E_SIZE, "batch workspace: %llu < %llu bytes",
+                (unsigned long long)workspace_bytes, (unsigned long long)lay.total);
+  soma_batch *b = new (std::nothrow) soma_batch();
+  if (!b) return fail(SOMA_E_INVAL, "out of host memory");
+  b->sys.assign(systems, systems + n);
+  b->c64 = systems[0]->cfg.count_width == 32 ? 1u : 0u;
+  // segments, largest first (equal sizes keep their order)
+  struct Ref { uint32_t s, sp; uint64_t beads; };
+  std::vector<Ref> refs;
+  for (uint32_t i = 0; i < n; ++i)
+    for (uint32_t sp = 0; sp < systems[i]->cfg.n_species; ++sp) {
+      const soma_species &S = systems[i]->cfg.species[sp];
+      if (S.n_chains) refs.push_back({i, sp, (uint64_t)S.n_chains * S.n});
+    }
+  std::stable_sort(refs.begin(), refs.end(),
+                   [](const Ref &x, const Ref &y) { return x.beads > y.beads; });
+  uint64_t items = 0;
+  b->seg_first.push_back(0);
+  for (const Ref &r : refs) {
+    soma::BatchSeg seg[3];
+    for (uint32_t k = 0; k < 3; ++k) sweep_args(systems[r.s], r.sp, k, seg[k].a, seg[k].mx);
+    for (uint32_t k = 0; k < 3; ++k) b->segs[k].push_back(seg[k]);
+    if (!species_vec2(systems[r.s], r.sp)) b->v2 = 0;
+    items += items_of(seg[0].a);
+    if (items >= (1ull << 31)) {
+      delete b;
+      return fail(SOMA_E_UNSUPPORTED, "batch too large");
+    }
+    b->seg_first.push_back((uint32_t)items);
+  }
+  b->n_items = (uint32_t)items;
+  b->fb_first.push_back(0);
+  for (uint32_t i = 0; i < n; ++i) {
+    soma_system *x = systems[i];
+    b->fargs.push_back(field_args(&x->cfg, x->d, x->buf.counts, x->buf.omega, x->fpart()));
+    b->fb_first.push_back(b->fb_first.back() + x->d.field_blocks);
+    b->ctrs.push_back(x->sweep_ctr());
+  }
+  unsigned char *ws = reinterpret_cast<unsigned char *>(workspace);
+  for (int k = 0; k < 3; ++k) b->d_segs[k] = reinterpret_cast<soma::BatchSeg *>(ws + lay.segs[k]);
+  b->d_seg_first = reinterpret_cast<uint32_t *>(ws + lay.seg_first);
+  b->d_fargs = reinterpret_cast<soma::FieldArgs *>(ws + lay.fargs);
+  b->d_fb_first = reinterpret_cast<uint32_t *>(ws + lay.fb_first);
+  b->d_ctrs = reinterpret_cast<uint32_t **>(ws + lay.ctrs);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  auto put = [&](void *dst, const void *src, size_t bytes) -> int32_t {
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+    return SOMA_OK;
+  };
+  for (int k = 0; k < 3 && !rc; ++k)
+    rc = put(b->d_segs[k], b->segs[k].data(), b->segs[k].size() * sizeof(soma::BatchSeg));
+  if (!rc) rc = put(b->d_seg_first, b->seg_first.data(), b->seg_first.size() * 4);
+  if (!rc) rc = put(b->d_fargs, b->fargs.data(), b->fargs.size() * sizeof(soma::FieldArgs));
+  if (!rc) rc = put(b->d_fb_first, b->fb_first.data(), b->fb_first.size() * 4);
+  if (!rc) rc = put(b->d_ctrs, b->ctrs.data(), b->ctrs.size() * 8);
+  if (!rc) {  // the host tables must outlive the copies
+    const hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = fail(SOMA_E_HIP, "batch tables: %s", hipGetErrorString(e));
+  }
+  if (rc) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return SOMA_OK;
+}
+
+int32_t soma_batch_set_launch(soma_batch *b, uint32_t mode, uint32_t grid_blocks) {
+  if (!b) return fail(SOMA_E_INVAL, "batch is NULL");
+  if (mode > 1) return fail(SOMA_E_INVAL, "mode must be 0 or 1");
+  b->mode = mode;
+  b->grid_blocks = grid_blocks;
+  return SOMA_OK;
+}
+
+int32_t soma_batch_sweep(soma_batch *b, uint32_t n_sweeps, uint32_t move_kind, void *stream) {
+  if (!b) return fail(SOMA_E_INVAL, "batch is NULL");
+  int32_t rc = batch_check_kind(b, move_kind);
+  if (rc || n_sweeps == 0) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (uint32_t i = 0; i < n_sweeps; ++i) {
+    rc = launch_batch_sweep(b, move_kind, s, i);
+    if (rc) return rc;
+  }
+  rc = launch_batch_counter(b, n_sweeps, s);
+  if (rc) return rc;
+  batch_count(b, move_kind, n_sweeps);
+  return SOMA_OK;
+}
+
+int32_t soma_batch_update_fields(soma_batch *b, void *stream) {
+  if (!b) return fail(SOMA_E_INVAL, "batch is NULL");
+  return launch_batch_field(b, reinterpret_cast<hipStream_t>(stream));
+}
+
+int32_t soma_batch_capture_cycle(soma_batch *b, uint32_t cycles, uint32_t move_kind) {
+  if (!b) return fail(SOMA_E_INVAL, "batch is NULL");
+  if (cycles == 0) return fail(SOMA_E_INVAL, "cycles must be positive");
+  const int32_t rc = batch_check_kind(b, move_kind);
+  if (rc) return rc;
+  return capture_graph(b->graph, cycles, move_kind, [&](hipStream_t cs) -> int32_t {
+    for (uint32_t i = 0; i < cycles; ++i) {
+      int32_t r = launch_batch_sweep(b, move_kind, cs, i);
+      if (!r) r = launch_batch_field(b, cs);
+      if (r) return r;
+    }
+    return launch_batch_counter(b, cycles, cs);
+  });
+}
+
+int32_t soma_batch_run_cycle(soma_batch *b, uint32_t n_launches, void *stream) {
+  if (!b) return fail(SOMA_E_INVAL, "batch is NULL");
+  if (!b->graph.exec) return fail(SOMA_E_INVAL, "no captured cycle (soma_batch_capture_cycle)");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (uint32_t i = 0; i < n_launches; ++i) {
+    HIP_TRY(hipGraphLaunch(b->graph.exec, s));
+    batch_count(b, b->graph.kind, b->graph.cycles);
+  }
+  return SOMA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+std::string system_key(const soma_system *x) {
+  char buf[128];
+  std::string k;
+  std::snprintf(buf, sizeof buf, "%ux%ux%u/c%u", x->cfg.nx, x->cfg.ny, x->cfg.nz,
+                x->cfg.count_width);
+  k += buf;
+  for (uint32_t sp = 0; sp < x->cfg.n_species; ++sp) {
+    const soma_species &S = x->cfg.species[sp];
+    std::snprintf(buf, sizeof buf, ",%u:%u:%u", S.n_chains, S.n, S.n_a);
+    k += buf;
+  }
+  return k;
+}
+
+bool cache_lookup(const char *path, const std::string &key, uint32_t *mode, uint32_t *grid) {
+  if (!path) return false;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return false;
+  bool found = false;
+  char line[8192];
+  while (std::fgets(line, sizeof line, f)) {
+    char *tab = std::strchr(line, '\t');
+    if (!tab) continue;
+    *tab = '\0';
+    unsigned m = 0, g = 0;
+    if (key == line && std::sscanf(tab + 1, "%u %u", &m, &g) == 2 && m <= 1) {
+      *mode = m;
+      *grid = g;
+      found = true;  // the last matching line wins
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const char *path, const std::string &key, uint32_t mode, uint32_t grid,
+                 float ms) {
+  if (!path) return;
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s\t%u %u %.6f\n", key.c_str(), mode, grid, ms);
+  std::fclose(f);
+}
+
+// Runs one warm-up cycle, then times `cycles` cycles (ms per cycle).
+template <class Cycle>
+int32_t time_cycles(hipStream_t s, uint32_t cycles, Cycle cycle, float *ms) {
+  int32_t rc = cycle();
+  if (rc) return rc;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(SOMA_E_HIP, "hipEventCreate: %s", hipGetErrorString(e));
+  }
+  e = hipEventRecord(e0, s);
+  for (uint32_t i = 0; i < cycles && !rc && e == hipSuccess; ++i) rc = cycle();
+  if (!rc && e == hipSuccess) e = hipEventRecord(e1, s);
+  if (!rc && e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (!rc && e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  if (e != hipSuccess) return fail(SOMA_E_HIP, "timing: %s", hipGetErrorString(e));
+  *ms = t / (float)(cycles ? cycles : 1);
+  return SOMA_OK;
+}
+
+struct Shape {
+  uint32_t mode, grid;
+};
+
+// Tries each shape (apply, then time cycles), keeps the fastest.
+template <class Apply, class Cycle>
+int32_t tune(const Shape *shapes, uint32_t n_shapes, uint32_t cycles, const char *cache_path,
+             const std::string &key, hipStream_t s, Apply apply, Cycle cycle, soma_tune *out) {
+  std::memset(out, 0, sizeof *out);
+  uint32_t mode = 0, grid = 0;
+  if (cache_lookup(cache_path, key, &mode, &grid)) {
+    apply(mode, grid);
+    out->mode = mode;
+    out->grid_blocks = grid;
+    out->from_cache = 1;
+    return SOMA_OK;
+  }
+  float best = 0.f;
+  uint32_t best_i = 0;
+  for (uint32_t i = 0; i < n_shapes; ++i) {
+    apply(shapes[i].mode, shapes[i].grid);
+    float ms = 0.f;
+    const int32_t rc = time_cycles(s, cycles, cycle, &ms);
+    if (rc) return rc;
+    out->cycles_run += 1 + cycles;
+    out->candidates += 1;
+    if (i == 0 || ms < best) {
+      best = ms;
+      best_i = i;
+    }
+  }
+  apply(shapes[best_i].mode, shapes[best_i].grid);
+  out->mode = shapes[best_i].mode;
+  out->grid_blocks = shapes[best_i].grid;
+  out->ms_per_cycle = best;
+  cache_store(cache_path, key, out->mode, out->grid_blocks, best);
+  return SOMA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t soma_autotune(soma_system *sys, uint32_t cycles, uint32_t move_kind,
+                      const char *cache_path, void *stream, soma_tune *out) {
+  if (!sys || !out) return fail(SOMA_E_INVAL, "system or out is NULL");
+  if (cycles == 0) return fail(SOMA_E_INVAL, "cycles must be positive");
+  const int32_t rc = check_kind(sys, move_kind);
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // only the local-move kernel has a second launch shape (persistent blocks)
+  static const Shape local_shapes[] = {{0, 0}, {0, 1024}, {0, 2048}, {0, 4096}};
+  const uint32_t n_shapes = move_kind == SOMA_MOVE_LOCAL ? 4u : 1u;
+  char kind_s[16];
+  std::snprintf(kind_s, sizeof kind_s, "sys/k%u/", move_kind);
+  return tune(local_shapes, n_shapes, cycles, cache_path, kind_s + system_key(sys), s,
+              [&](uint32_t, uint32_t grid) { sys->sweep_blocks = grid; },
+              [&]() -> int32_t {
+                int32_t r = soma_mc_sweep(sys, 1, move_kind, stream);
+                if (!r) r = soma_update_fields(sys, stream);
+                return r;
+              },
+              out);
+}
+
+int32_t soma_batch_autotune(soma_batch *b, uint32_t cycles, uint32_t move_kind,
+                            const char *cache_path, void *stream, soma_tune *out) {
+  if (!b || !out) return fail(SOMA_E_INVAL, "batch or out is NULL");
+  if (cycles == 0) return fail(SOMA_E_INVAL, "cycles must be positive");
+  const int32_t rc = batch_check_kind(b, move_kind);
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  static const Shape shapes[] = {{0, 0}, {1, 0}, {0, 2048}, {0, 8192}};
+  char kind_s[16];
+  std::snprintf(kind_s, sizeof kind_s, "batch/k%u", move_kind);
+  std::string key = kind_s;
+  for (soma_system *x : b->sys) key += "/" + system_key(x);
+  return tune(shapes, 4u, cycles, cache_path, key, s,
+              [&](uint32_t mode, uint32_t grid) {
+                b->mode = mode;
+                b->grid_blocks = grid;
+              },
+              [&]() -> int32_t {
+                int32_t r = soma_batch_sweep(b, 1, move_kind, stream);
+                if (!r) r = soma_batch_update_fields(b, stream);
+                return r;
+              },
+              out);
+}
+
+void soma_batch_destroy(soma_batch *b) { delete b; }
 
 void soma_destroy(soma_system *sys) { delete sys; }
 

@@ -10,6 +10,7 @@ namespace soma {
 constexpr uint32_t kPurposeMoveA = 0u;
 constexpr uint32_t kPurposeMoveB = 1u;
 constexpr uint32_t kPurposeInit = 4u;
+constexpr uint32_t kPurposeCollect = 5u;
 constexpr uint32_t kSweepInit = 0xFFFFFFFFu;
 constexpr uint32_t kAccSlots = 1024u;  // acceptance counter slots per move kind
 constexpr float kMaxCoord = 4194304.0f;  // 2^22: cell arithmetic stays exact below

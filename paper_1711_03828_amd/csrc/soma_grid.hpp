@@ -101,13 +101,15 @@ __device__ __forceinline__ void load4(const void *counts, uint32_t q,
   }
 }
 
+// Block `blk` of the `nblk` blocks that serve one grid: a grid-stride loop
+// over groups of four cells, then the block's partial sums (FP64 H_nb).
 template <bool COUNT64>
-__global__ __launch_bounds__(256) void field_update_kernel(const FieldArgs a) {
+__device__ __forceinline__ void field_body(const FieldArgs &a, uint32_t blk, uint32_t nblk) {
   __shared__ unsigned long long s_a[4], s_b[4];
   __shared__ double s_h[4];
   const uint32_t n4 = a.n_cells >> 2;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t stride = nblk * blockDim.x;
+  const uint32_t tid = blk * blockDim.x + threadIdx.x;
   unsigned long long sum_a = 0, sum_b = 0;
   double h = 0.0;
   const bool stats = a.partials != nullptr;
@@ -176,8 +178,47 @@ __global__ __launch_bounds__(256) void field_update_kernel(const FieldArgs a) {
     p.sum_b = s_b[0] + s_b[1] + s_b[2] + s_b[3];
     p.h_nb = ((s_h[0] + s_h[1]) + s_h[2]) + s_h[3];
     p.pad = 0.0;
-    a.partials[blockIdx.x] = p;
+    a.partials[blk] = p;
   }
+}
+
+template <bool COUNT64>
+__global__ __launch_bounds__(256) void field_update_kernel(const FieldArgs a) {
+  field_body<COUNT64>(a, blockIdx.x, gridDim.x);
+}
+
+// Blocks of the grid-field update for a number of systems are given out in
+// contiguous ranges: system s owns blocks [first[s], first[s+1]).
+__device__ __forceinline__ uint32_t range_of(const uint32_t *first, uint32_t n, uint32_t x) {
+  uint32_t lo = 0, hi = n;  // first[lo] <= x < first[hi]
+  while (hi - lo > 1u) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (first[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <bool COUNT64>
+__global__ __launch_bounds__(256) void batched_field_kernel(const FieldArgs *fa,
+                                                            const uint32_t *first, uint32_t n_sys) {
+  const uint32_t s = range_of(first, n_sys, blockIdx.x);
+  field_body<COUNT64>(fa[s], blockIdx.x - first[s], first[s + 1] - first[s]);
+}
+
+// Device sweep counters: add `by` to each (or set them to `value`).
+__global__ __launch_bounds__(64) void sweep_counter_kernel(uint32_t *const *ctrs, uint32_t n,
+                                                           uint32_t by, uint32_t set,
+                                                           uint32_t value) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t *c = ctrs[i];
+  c[0] = set ? value : c[0] + by;
+}
+
+__global__ __launch_bounds__(64) void sweep_counter_one_kernel(uint32_t *ctr, uint32_t by,
+                                                               uint32_t set, uint32_t value) {
+  if (threadIdx.x == 0) ctr[0] = set ? value : ctr[0] + by;
 }
 
 // ---------------------------------------------------------------------------

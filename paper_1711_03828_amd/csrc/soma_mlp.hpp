@@ -246,6 +246,33 @@ struct SpeciesTable {
   uint64_t bead_off[8];
 };
 
+// Species of global chain c and the chain's first bead (c < total_chains).
+__device__ __forceinline__ const float *chain_start(const float *pos, const SpeciesTable &st,
+                                                    uint32_t c, uint32_t *sp_out) {
+  uint32_t sp = 0;
+  for (uint32_t k = 1; k < st.n_species; ++k)
+    if (c >= st.chain_off[k]) sp = k;
+  *sp_out = sp;
+  return pos + 3 * (st.bead_off[sp] + (uint64_t)(c - st.chain_off[sp]) * st.n[sp]);
+}
+
+// Raw features (FP32) of bead i of a chain of species sp starting at `chain`.
+__device__ __forceinline__ void bead_features(const float *chain, const float *omega,
+                                              const Grid &g, const SpeciesTable &st, uint32_t sp,
+                                              uint32_t i, float *row) {
+  const uint32_t nn = st.n[sp];
+  const F3 r = {chain[3 * i], chain[3 * i + 1], chain[3 * i + 2]};
+  const F3 zero3 = F3{0.f, 0.f, 0.f};
+  const F3 bp = i > 0 ? F3{chain[3 * i - 3], chain[3 * i - 2], chain[3 * i - 1]} - r : zero3;
+  const F3 bn = i + 1 < nn ? F3{chain[3 * i + 3], chain[3 * i + 4], chain[3 * i + 5]} - r : zero3;
+  const Neighbourhood nb = neighbourhood(g, r);
+  const bool is_b = i >= st.n_a[sp];
+  const float *own = omega + (is_b ? g.n_cells : 0u);
+  const float *oth = omega + (is_b ? 0u : g.n_cells);
+#pragma unroll
+  for (int k = 0; k < kNF; ++k) row[k] = raw_feature(k, nb, own, oth, bp, bn);
+}
+
 // Raw features (FP32) of bead `beads[s]` of global chain `chains[s]` at the
 // current positions, for training data: out [n][60].  One thread per sample.
 __global__ __launch_bounds__(256) void features_kernel(const float *__restrict__ pos,
@@ -257,26 +284,57 @@ __global__ __launch_bounds__(256) void features_kernel(const float *__restrict__
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const uint32_t c = chains[s];
+  float *row = out + (size_t)s * kNF;
   if (c >= st.total_chains) {  // out of range: zeros, never a stray read
-    for (int k = 0; k < kNF; ++k) out[(size_t)s * kNF + k] = 0.0f;
+    for (int k = 0; k < kNF; ++k) row[k] = 0.0f;
     return;
   }
-  uint32_t sp = 0;
-  for (uint32_t k = 1; k < st.n_species; ++k)
-    if (c >= st.chain_off[k]) sp = k;
-  const uint32_t nn = st.n[sp];
-  const uint32_t i = min(beads[s], nn - 1u);
-  const float *chain = pos + 3 * (st.bead_off[sp] + (uint64_t)(c - st.chain_off[sp]) * nn);
-  const F3 r = {chain[3 * i], chain[3 * i + 1], chain[3 * i + 2]};
-  const F3 zero3 = F3{0.f, 0.f, 0.f};
-  const F3 bp = i > 0 ? F3{chain[3 * i - 3], chain[3 * i - 2], chain[3 * i - 1]} - r : zero3;
-  const F3 bn = i + 1 < nn ? F3{chain[3 * i + 3], chain[3 * i + 4], chain[3 * i + 5]} - r : zero3;
-  const Neighbourhood nb = neighbourhood(g, r);
-  const bool is_b = i >= st.n_a[sp];
-  const float *own = omega + (is_b ? g.n_cells : 0u);
-  const float *oth = omega + (is_b ? 0u : g.n_cells);
-#pragma unroll
-  for (int k = 0; k < kNF; ++k) out[(size_t)s * kNF + k] = raw_feature(k, nb, own, oth, bp, bn);
+  uint32_t sp;
+  const float *chain = chain_start(pos, st, c, &sp);
+  bead_features(chain, omega, g, st, sp, min(beads[s], st.n[sp] - 1u), row);
+}
+
+// Training samples drawn from the running melt.  Sample s of a round picks a
+// chain uniformly among all chains and a bead uniformly along it, from the
+// Philox block (s, purpose 5, round, replica).  Phase 0 records the bead's
+// features (optional) and position; phase 1, later in the run, the
+// displacement from that recorded position.
+struct CollectArgs {
+  const float *pos;
+  const float *omega;
+  Grid grid;
+  SpeciesTable st;
+  uint32_t seed_lo, seed_hi, replica, round, n, phase;
+  float *features;   // [n][60] or null (phase 0)
+  float *r0;         // [n][3]
+  float *dr;         // [n][3] (phase 1)
+  uint32_t *picked;  // [n][2] (chain, bead) or null (phase 0)
+};
+
+__global__ __launch_bounds__(256) void collect_kernel(const CollectArgs a) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n) return;
+  const Rand4 q = philox(s, kPurposeCollect << 16, a.round, a.replica, a.seed_lo, a.seed_hi);
+  const uint32_t c = __umulhi(q.x, a.st.total_chains);
+  uint32_t sp;
+  const float *chain = chain_start(a.pos, a.st, c, &sp);
+  const uint32_t i = __umulhi(q.y, a.st.n[sp]);
+  const float *r = chain + 3 * i;
+  const size_t o = 3 * (size_t)s;
+  if (a.phase == 0) {
+    if (a.features) bead_features(chain, a.omega, a.grid, a.st, sp, i, a.features + (size_t)s * kNF);
+    a.r0[o] = r[0];
+    a.r0[o + 1] = r[1];
+    a.r0[o + 2] = r[2];
+    if (a.picked) {
+      a.picked[2 * (size_t)s] = c;
+      a.picked[2 * (size_t)s + 1] = i;
+    }
+  } else {
+    a.dr[o] = r[0] - a.r0[o];
+    a.dr[o + 1] = r[1] - a.r0[o + 1];
+    a.dr[o + 2] = r[2] - a.r0[o + 2];
+  }
 }
 
 }  // namespace soma

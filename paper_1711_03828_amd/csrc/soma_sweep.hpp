@@ -36,9 +36,21 @@ struct SweepArgs {
   float step;                      // local: a; smart MC: A
   float sqrt_2a, inv_4a;           // smart MC only
   float inv_nref;
-  uint32_t seed_lo, seed_hi, sweep, replica;
+  uint32_t seed_lo, seed_hi;
+  uint32_t sweep;                  // offset added to the device sweep counter
+  uint32_t replica;
   uint32_t set_order;              // 0 random per chain and sweep, 1 even first
+  const uint32_t *sweep_ctr;       // device sweep counter of the system
 };
+
+// Arguments with the Philox sweep word resolved: the system's device counter
+// plus the launch's offset, so that a launch recorded once (a captured graph)
+// still draws fresh numbers on every replay.
+__device__ __forceinline__ SweepArgs resolve_sweep(const SweepArgs &in, uint32_t extra) {
+  SweepArgs a = in;
+  a.sweep = in.sweep + extra + *in.sweep_ctr;
+  return a;
+}
 
 __device__ __forceinline__ F3 sel(bool c, F3 a, F3 b) { return c ? a : b; }
 
@@ -133,6 +145,7 @@ __device__ __forceinline__ void finish_block(const SweepArgs &a, uint32_t n_acc)
     const uint32_t tot = s_acc[0] + s_acc[1] + s_acc[2] + s_acc[3];
     if (tot) atomicAdd(a.acc_slots + (blockIdx.x & (kAccSlots - 1u)), (unsigned long long)tot);
   }
+  __syncthreads();
 }
 
 // Order of the two sets for this chain and sweep: bit 0 of the first word of
@@ -256,7 +269,8 @@ __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap
 // positions while it works on the current one.
 // ---------------------------------------------------------------------------
 template <bool COUNT64, bool VEC2>
-__global__ __launch_bounds__(256) void mc_sweep_local_kernel(const SweepArgs a) {
+__global__ __launch_bounds__(256) void mc_sweep_local_kernel(const SweepArgs a_in) {
+  const SweepArgs a = resolve_sweep(a_in, 0u);
   const uint32_t n_tiles = (a.n_chains + a.chains_per_wave - 1u) / a.chains_per_wave;
   const uint32_t blocks = gridDim.x;
   // XCD split only when the grid is a multiple of 8 blocks
@@ -315,8 +329,7 @@ __device__ __forceinline__ F3 field_grad(const Grid &g, const float *om,
 // the bonded force, so the sets are handled one after the other.
 // ---------------------------------------------------------------------------
 template <bool COUNT64, bool VEC2>
-__global__ __launch_bounds__(256) void mc_sweep_smc_kernel(const SweepArgs a) {
-  const LaneMap m = lane_map(a);
+__device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &m) {
   const uint32_t N = a.n;
   const uint32_t i0 = 2u * m.k, i1 = i0 + 1u;
   float *cp = a.pos + (size_t)(m.has0 ? m.chain : 0u) * N * 3u + 6u * m.k;
@@ -402,7 +415,14 @@ __global__ __launch_bounds__(256) void mc_sweep_smc_kernel(const SweepArgs a) {
   store_pair<VEC2>(cp, m, r0, r1);
   if (moved0) move_count<COUNT64>(a.counts, from0, to0, b0);
   if (moved1) move_count<COUNT64>(a.counts, from1, to1, b1);
-  finish_block(a, n_acc);
+  return n_acc;
+}
+
+template <bool COUNT64, bool VEC2>
+__global__ __launch_bounds__(256) void mc_sweep_smc_kernel(const SweepArgs a_in) {
+  const SweepArgs a = resolve_sweep(a_in, 0u);
+  const LaneMap m = lane_map(a);
+  finish_block(a, smc_wave<COUNT64, VEC2>(a, m));
 }
 
 }  // namespace soma
@@ -415,6 +435,7 @@ struct MixArgs {
   HeadArgs head;
   float p_learn;                   // probability of the learned move (state-independent)
   unsigned long long *att_slots;   // [kAccSlots] attempted learned moves
+  uint32_t *err;                   // device error word (bit 2: non-finite network output)
 };
 
 // ---------------------------------------------------------------------------
@@ -426,14 +447,11 @@ struct MixArgs {
 // non-finite network output rejects it and raises error bit 2.  The network
 // needs the bond vectors, so the two sets are handled one after the other.
 // ---------------------------------------------------------------------------
+// One wave's chains; act/zb are the wave's LDS tiles.  Returns through cnt the
+// wave's accepted local moves, accepted learned moves and learned attempts.
 template <bool COUNT64, bool VEC2>
-__global__ __launch_bounds__(256) void mc_sweep_mixed_kernel(const SweepArgs a, const MixArgs mx,
-                                                             uint32_t *err) {
-  __shared__ __bf16 s_act[4][64 * kActStride];
-  __shared__ float s_z[4][64 * 8];
-  const LaneMap m = lane_map(a);
-  __bf16 *act = s_act[m.wib];
-  float *zb = s_z[m.wib];
+__device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx, const LaneMap &m,
+                                           __bf16 *act, float *zb, uint32_t cnt[3]) {
   __bf16 *row = act + m.lane * kActStride;
   const uint32_t N = a.n;
   const uint32_t i0 = 2u * m.k, i1 = i0 + 1u;
@@ -536,10 +554,19 @@ __global__ __launch_bounds__(256) void mc_sweep_mixed_kernel(const SweepArgs a, 
   store_pair<VEC2>(cp, m, r0, r1);
   if (moved0) move_count<COUNT64>(a.counts, from0, to0, b0);
   if (moved1) move_count<COUNT64>(a.counts, from1, to1, b1);
-  if (__ballot(net_bad_any) != 0ull && m.lane == 0) atomicOr(err, 2u);
-  // local and learned acceptances go to separate slot arrays
+  if (__ballot(net_bad_any) != 0ull && m.lane == 0) atomicOr(mx.err, 2u);
+  cnt[0] = n_acc - n_acc_l;
+  cnt[1] = n_acc_l;
+  cnt[2] = n_att_l;
+}
+
+// Block totals of the mixed sweep: local and learned acceptances go to separate
+// slot arrays, learned attempts to their own.
+__device__ __forceinline__ void mixed_finish(const SweepArgs &a, const MixArgs &mx,
+                                             const uint32_t cnt[3]) {
   __shared__ uint32_t s_cnt[4][3];
-  if (m.lane == 0) { s_cnt[m.wib][0] = n_acc - n_acc_l; s_cnt[m.wib][1] = n_acc_l; s_cnt[m.wib][2] = n_att_l; }
+  const uint32_t wib = threadIdx.x >> 6;
+  if ((threadIdx.x & 63u) == 0u) { s_cnt[wib][0] = cnt[0]; s_cnt[wib][1] = cnt[1]; s_cnt[wib][2] = cnt[2]; }
   __syncthreads();
   if (threadIdx.x == 0) {
     const uint32_t slot = blockIdx.x & (kAccSlots - 1u);
@@ -550,6 +577,19 @@ __global__ __launch_bounds__(256) void mc_sweep_mixed_kernel(const SweepArgs a, 
     if (lrn) atomicAdd(a.acc_slots + 2u * kAccSlots + slot, (unsigned long long)lrn);
     if (att) atomicAdd(mx.att_slots + slot, (unsigned long long)att);
   }
+  __syncthreads();
+}
+
+template <bool COUNT64, bool VEC2>
+__global__ __launch_bounds__(256) void mc_sweep_mixed_kernel(const SweepArgs a_in,
+                                                             const MixArgs mx) {
+  __shared__ __bf16 s_act[4][64 * kActStride];
+  __shared__ float s_z[4][64 * 8];
+  const SweepArgs a = resolve_sweep(a_in, 0u);
+  const LaneMap m = lane_map(a);
+  uint32_t cnt[3];
+  mixed_wave<COUNT64, VEC2>(a, mx, m, s_act[m.wib], s_z[m.wib], cnt);
+  mixed_finish(a, mx, cnt);
 }
 
 }  // namespace soma

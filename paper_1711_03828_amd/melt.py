@@ -76,10 +76,12 @@ class Melt:
     def sweep(self, n_sweeps=1, move_kind=C.SOMA_MOVE_LOCAL, stream=None):
         C.soma_mc_sweep(self.handle, n_sweeps, move_kind, _stream(stream))
 
-    def set_proposal(self, params: torch.Tensor, stream=None):
-        """Install the learned proposal's FP32 parameter blob (a device tensor)."""
+    def set_proposal(self, params: torch.Tensor, species=C.SOMA_ALL_SPECIES, stream=None):
+        """Install the learned proposal's FP32 parameter blob (a device tensor) for
+        one species or all."""
         assert params.dtype == torch.float32 and params.numel() == C.NET_PARAMS
-        C.soma_set_proposal(self.handle, params.contiguous().data_ptr(), _stream(stream))
+        C.soma_set_proposal(self.handle, params.contiguous().data_ptr(), _stream(stream),
+                            species)
 
     def update_fields(self, stream=None):
         C.soma_update_fields(self.handle, _stream(stream))
@@ -103,7 +105,17 @@ class Melt:
 
     @sweep_index.setter
     def sweep_index(self, v: int):
-        C.soma_set_sweep(self.handle, v)
+        C.soma_set_sweep(self.handle, v, _stream(None))
+
+    def capture_cycle(self, cycles: int, move_kind=C.SOMA_MOVE_LOCAL):
+        """Record `cycles` SCMF cycles into a HIP graph (replayed by run_cycle)."""
+        C.soma_capture_cycle(self.handle, cycles, move_kind)
+
+    def run_cycle(self, n_launches: int = 1, stream=None):
+        C.soma_run_cycle(self.handle, n_launches, _stream(stream))
+
+    def autotune(self, cycles: int, move_kind=C.SOMA_MOVE_LOCAL, cache_path=None, stream=None):
+        return C.soma_autotune(self.handle, cycles, move_kind, cache_path, _stream(stream))
 
     def counts_planes(self) -> np.ndarray:
         """Unpack the packed counts to uint32 [2, n_cells] on the host."""
@@ -117,6 +129,53 @@ class Melt:
     def close(self):
         if self.handle:
             C.soma_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several melts swept by one launch per sweep (and per field refresh)."""
+
+    def __init__(self, melts, stream=None):
+        self.melts = list(melts)   # the melts must outlive the batch
+        handles = [m.handle for m in self.melts]
+        ws_b = C.soma_batch_workspace_size(handles)
+        self.workspace = torch.empty(ws_b, dtype=torch.uint8, device=self.melts[0].pos.device)
+        self.handle = C.soma_batch_create(handles, self.workspace.data_ptr(), ws_b,
+                                          _stream(stream))
+
+    def set_launch(self, mode: int, grid_blocks: int = 0):
+        C.soma_batch_set_launch(self.handle, mode, grid_blocks)
+
+    def sweep(self, n_sweeps=1, move_kind=C.SOMA_MOVE_LOCAL, stream=None):
+        C.soma_batch_sweep(self.handle, n_sweeps, move_kind, _stream(stream))
+
+    def update_fields(self, stream=None):
+        C.soma_batch_update_fields(self.handle, _stream(stream))
+
+    def cycle(self, n=1, move_kind=C.SOMA_MOVE_LOCAL, stream=None):
+        s = _stream(stream)
+        for _ in range(n):
+            C.soma_batch_sweep(self.handle, 1, move_kind, s)
+            C.soma_batch_update_fields(self.handle, s)
+
+    def capture_cycle(self, cycles: int, move_kind=C.SOMA_MOVE_LOCAL):
+        C.soma_batch_capture_cycle(self.handle, cycles, move_kind)
+
+    def run_cycle(self, n_launches: int = 1, stream=None):
+        C.soma_batch_run_cycle(self.handle, n_launches, _stream(stream))
+
+    def autotune(self, cycles: int, move_kind=C.SOMA_MOVE_LOCAL, cache_path=None, stream=None):
+        return C.soma_batch_autotune(self.handle, cycles, move_kind, cache_path, _stream(stream))
+
+    def close(self):
+        if self.handle:
+            C.soma_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -26,6 +26,7 @@ SOMA_MOVE_SMC = 1
 SOMA_MOVE_MIXED = 2
 SOMA_FLAG_POSITION = 1
 SOMA_FLAG_NETWORK = 2
+SOMA_ALL_SPECIES = 0xFFFFFFFF
 NET_PARAMS = 8576
 SOMA_MAX_SPECIES = 8
 SOMA_MAX_BEADS_PER_CHAIN = 128
@@ -74,6 +75,12 @@ class soma_train_opts(ctypes.Structure):
                 ("apply", ctypes.c_uint32), ("max_waves", ctypes.c_uint32)]
 
 
+class soma_tune(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_uint32), ("grid_blocks", ctypes.c_uint32),
+                ("ms_per_cycle", ctypes.c_float), ("candidates", ctypes.c_uint32),
+                ("cycles_run", ctypes.c_uint32), ("from_cache", ctypes.c_uint32)]
+
+
 class SomaError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"soma error {code}: {msg}")
@@ -102,15 +109,29 @@ _SIGS = {
     "soma_observables": ([_P, ctypes.POINTER(soma_obs), _P], _i32),
     "soma_check": ([_P, _pu32, _P], _i32),
     "soma_get_sweep": ([_P, _pu64], _i32),
-    "soma_set_sweep": ([_P, _u64], _i32),
+    "soma_set_sweep": ([_P, _u64, _P], _i32),
+    "soma_capture_cycle": ([_P, _u32, _u32], _i32),
+    "soma_run_cycle": ([_P, _u32, _P], _i32),
+    "soma_autotune": ([_P, _u32, _u32, ctypes.c_char_p, _P, ctypes.POINTER(soma_tune)], _i32),
+    "soma_batch_workspace_size": ([ctypes.POINTER(_P), _u32, _pu64], _i32),
+    "soma_batch_create": ([ctypes.POINTER(_P), _u32, _P, _u64, _P, ctypes.POINTER(_P)], _i32),
+    "soma_batch_set_launch": ([_P, _u32, _u32], _i32),
+    "soma_batch_sweep": ([_P, _u32, _u32, _P], _i32),
+    "soma_batch_update_fields": ([_P, _P], _i32),
+    "soma_batch_capture_cycle": ([_P, _u32, _u32], _i32),
+    "soma_batch_run_cycle": ([_P, _u32, _P], _i32),
+    "soma_batch_autotune": ([_P, _u32, _u32, ctypes.c_char_p, _P, ctypes.POINTER(soma_tune)],
+                            _i32),
+    "soma_batch_destroy": ([_P], None),
     "soma_density_hist": ([ctypes.POINTER(soma_config), _P, _P, _P], _i32),
     "soma_field_from_counts": ([ctypes.POINTER(soma_config), _P, _P, _P], _i32),
     "soma_init_positions": ([ctypes.POINTER(soma_config), _P, _P], _i32),
     "soma_net_bytes": ([], ctypes.c_uint64),
     "soma_prepare_net": ([_P, _P, _P], _i32),
-    "soma_set_proposal": ([_P, _P, _P], _i32),
+    "soma_set_proposal": ([_P, _u32, _P, _P], _i32),
     "soma_mlp_forward": ([_P, _P, _u32, _P, _P], _i32),
     "soma_features": ([_P, _P, _P, _u32, _P, _P], _i32),
+    "soma_collect_training": ([_P, _u32, _u32, _u32, _P, _P, _P, _P, _P], _i32),
     "soma_train_workspace_bytes": ([_u32], ctypes.c_uint64),
     "soma_train_step": ([_P, _P, _u32, _P, _P, _P, _u32, ctypes.POINTER(soma_train_opts), _P,
                          _u64, _P, _P, _P], _i32),
@@ -190,8 +211,78 @@ def soma_get_sweep(h) -> int:
     return v.value
 
 
-def soma_set_sweep(h, sweep: int) -> None:
-    _check(_lib.soma_set_sweep(h, sweep))
+def soma_set_sweep(h, sweep: int, stream: int = 0) -> None:
+    _check(_lib.soma_set_sweep(h, sweep, ctypes.c_void_p(stream)))
+
+
+def soma_capture_cycle(h, cycles: int, move_kind: int) -> None:
+    _check(_lib.soma_capture_cycle(h, cycles, move_kind))
+
+
+def soma_run_cycle(h, n_launches: int, stream: int) -> None:
+    _check(_lib.soma_run_cycle(h, n_launches, ctypes.c_void_p(stream)))
+
+
+def _path(p):
+    return None if p is None else os.fsencode(p)
+
+
+def soma_autotune(h, cycles: int, move_kind: int, cache_path, stream: int) -> soma_tune:
+    out = soma_tune()
+    _check(_lib.soma_autotune(h, cycles, move_kind, _path(cache_path), ctypes.c_void_p(stream),
+                              ctypes.byref(out)))
+    return out
+
+
+def _handles(handles):
+    arr = (_P * len(handles))(*[h.value if isinstance(h, ctypes.c_void_p) else h
+                                for h in handles])
+    return arr
+
+
+def soma_batch_workspace_size(handles) -> int:
+    v = ctypes.c_uint64()
+    _check(_lib.soma_batch_workspace_size(_handles(handles), len(handles), ctypes.byref(v)))
+    return v.value
+
+
+def soma_batch_create(handles, ws_ptr: int, ws_bytes: int, stream: int):
+    b = ctypes.c_void_p()
+    _check(_lib.soma_batch_create(_handles(handles), len(handles), ctypes.c_void_p(ws_ptr),
+                                  ws_bytes, ctypes.c_void_p(stream), ctypes.byref(b)))
+    return b
+
+
+def soma_batch_set_launch(b, mode: int, grid_blocks: int) -> None:
+    _check(_lib.soma_batch_set_launch(b, mode, grid_blocks))
+
+
+def soma_batch_sweep(b, n_sweeps: int, move_kind: int, stream: int) -> None:
+    _check(_lib.soma_batch_sweep(b, n_sweeps, move_kind, ctypes.c_void_p(stream)))
+
+
+def soma_batch_update_fields(b, stream: int) -> None:
+    _check(_lib.soma_batch_update_fields(b, ctypes.c_void_p(stream)))
+
+
+def soma_batch_capture_cycle(b, cycles: int, move_kind: int) -> None:
+    _check(_lib.soma_batch_capture_cycle(b, cycles, move_kind))
+
+
+def soma_batch_run_cycle(b, n_launches: int, stream: int) -> None:
+    _check(_lib.soma_batch_run_cycle(b, n_launches, ctypes.c_void_p(stream)))
+
+
+def soma_batch_autotune(b, cycles: int, move_kind: int, cache_path, stream: int) -> soma_tune:
+    out = soma_tune()
+    _check(_lib.soma_batch_autotune(b, cycles, move_kind, _path(cache_path),
+                                    ctypes.c_void_p(stream), ctypes.byref(out)))
+    return out
+
+
+def soma_batch_destroy(b) -> None:
+    if b:
+        _lib.soma_batch_destroy(b)
 
 
 def soma_density_hist(cfg: soma_config, pos_ptr: int, counts_ptr: int, stream: int) -> None:
@@ -218,8 +309,8 @@ def soma_prepare_net(params_ptr: int, net_ptr: int, stream: int) -> None:
                                  ctypes.c_void_p(stream)))
 
 
-def soma_set_proposal(h, params_ptr: int, stream: int) -> None:
-    _check(_lib.soma_set_proposal(h, ctypes.c_void_p(params_ptr), ctypes.c_void_p(stream)))
+def soma_set_proposal(h, params_ptr: int, stream: int, species: int = SOMA_ALL_SPECIES) -> None:
+    _check(_lib.soma_set_proposal(h, species, ctypes.c_void_p(params_ptr), ctypes.c_void_p(stream)))
 
 
 def soma_mlp_forward(net_ptr: int, features_ptr: int, n: int, z_ptr: int, stream: int) -> None:
@@ -230,6 +321,13 @@ def soma_mlp_forward(net_ptr: int, features_ptr: int, n: int, z_ptr: int, stream
 def soma_features(h, chains_ptr: int, beads_ptr: int, n: int, out_ptr: int, stream: int) -> None:
     _check(_lib.soma_features(h, ctypes.c_void_p(chains_ptr), ctypes.c_void_p(beads_ptr), n,
                               ctypes.c_void_p(out_ptr), ctypes.c_void_p(stream)))
+
+
+def soma_collect_training(h, n: int, round_: int, phase: int, features_ptr: int, r0_ptr: int,
+                          dr_ptr: int, picked_ptr: int, stream: int) -> None:
+    vp = lambda x: ctypes.c_void_p(x) if x else None
+    _check(_lib.soma_collect_training(h, n, round_, phase, vp(features_ptr), vp(r0_ptr),
+                                      vp(dr_ptr), vp(picked_ptr), ctypes.c_void_p(stream)))
 
 
 def soma_train_workspace_bytes(max_waves: int) -> int:

@@ -134,3 +134,54 @@ def mlp_params(seed: int, *, shift=None, scale=None, weight_gain=1.0, out_gain=0
     p[L["w3"]:L["w3"] + 384] = g.standard_normal(384) * out_gain / np.sqrt(64)
     p[L["b3"]:L["b3"] + 6] = g.standard_normal(6) * out_gain
     return p
+
+
+def splitmix64(x: int) -> int:
+    """SplitMix64 output for state x (Steele, Lea, Flood 2014): per-replica seeds."""
+    z = (x + 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & 0xFFFFFFFFFFFFFFFF
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & 0xFFFFFFFFFFFFFFFF
+    return z ^ (z >> 31)
+
+
+def _cube_side(volume_re3: float, re_cells: float) -> int:
+    return max(2, int(round(re_cells * volume_re3 ** (1.0 / 3.0))))
+
+
+def c3_replicas(n_rep: int = 64, master: int = MASTER_SEED, scale: float = 1.0):
+    """Replica ensemble of the batched study: chains log-uniform on [2048, 262144]
+    (times `scale`), N in {16, 32, 64}, A fraction in {0.3, 0.5}, chiN from 10 to 40
+    over the replicas, kappaN 50; volume 4 Re0^3 per 1024 chains, a cube at grid
+    spacing Re0/6.  Replica r has seed SplitMix64(master + r)."""
+    g = rng(master + 3)
+    out = []
+    for r in range(n_rep):
+        n_chains = max(1, int(round(np.exp(g.uniform(np.log(2048), np.log(262144))) * scale)))
+        n = int(g.choice([16, 32, 64]))
+        f = float(g.choice([0.3, 0.5]))
+        chi = 10.0 + 30.0 * r / max(1, n_rep - 1)
+        side = _cube_side(4.0 * n_chains / 1024.0, 6.0)
+        out.append(Workload(f"c3_r{r}", (side, side, side),
+                            (SpeciesSpec(n_chains, n, int(round(f * n))),), 6.0, n, chi, 50.0,
+                            16, seed=splitmix64(master + r)))
+    return out
+
+
+def c5_replicas(n_rep: int = 32, master: int = MASTER_SEED, scale: float = 1.0):
+    """Blend replicas: chains log-uniform on [16384, 131072] (times `scale`), beads
+    70% A16B16 diblocks, 15% A16 and 15% B16 homopolymers (chains 1 : 0.4286 :
+    0.4286), chiN from 15 to 35 over the replicas, kappaN 50, reference N 32,
+    the bead density of a 1024-chain N=32 melt in 4 Re0^3."""
+    g = rng(master + 5)
+    out = []
+    for r in range(n_rep):
+        n_total = np.exp(g.uniform(np.log(16384), np.log(131072))) * scale
+        n_d = max(1, int(round(n_total / (1.0 + 2 * 0.15 / 0.70 * 2))))
+        n_h = max(1, int(round(n_d * 0.15 / 0.70 * 2)))
+        beads = 32 * n_d + 16 * 2 * n_h
+        side = _cube_side(beads / (1024.0 * 32 / 4.0), 6.0)
+        chi = 15.0 + 20.0 * r / max(1, n_rep - 1)
+        sp = (SpeciesSpec(n_d, 32, 16), SpeciesSpec(n_h, 16, 16), SpeciesSpec(n_h, 16, 0))
+        out.append(Workload(f"c5_r{r}", (side, side, side), sp, 6.0, 32, chi, 50.0, 16,
+                            seed=splitmix64(master + 1000 + r)))
+    return out
