@@ -332,6 +332,28 @@ typedef struct soma_train_opts {
   uint32_t max_waves;           /* parallel partial gradients (0: one per 64 samples) */
 } soma_train_opts;
 
+/* ---- Structure factor (Sec. 5.6) ---------------------------------------
+ * S(q) = N^2 rho0 / (4 V) |F[phi_A - phi_B](q)|^2, F the grid Fourier
+ * transform dL^3 sum_c (.) exp(-i q.r_c), on every reciprocal-lattice vector
+ * q = 2 pi (mx/nx, my/ny, mz/nz) (grid units); with phi = n/(rho0 dL^3) this
+ * is N^2 |G(q)|^2 / (4 n_beads), G the transform of the count difference
+ * n_A - n_B, N = n_ref.  Computed from the current counts in FP64 (three 1-D
+ * transforms) into sq [n_cells] (device, cell order: index (mz*ny + my)*nx
+ * + mx, m the non-negative lattice index).  Workspace (device, 256-byte
+ * aligned): soma_sq_workspace_bytes(sys).  Asynchronous. */
+uint64_t soma_sq_workspace_bytes(const soma_system *sys);
+int32_t soma_structure_factor(soma_system *sys, void *workspace, uint64_t workspace_bytes,
+                              double *sq, void *stream);
+
+/* Host-side shell average of S(q) (host array `sq` as above): shell
+ * k = round(|q| / dq), dq = 2 pi / min(nx, ny, nz), for k < n_shells;
+ * s_avg[k] the mean over the shell, count[k] its size, q_mid[k] = k dq (may
+ * be NULL); *peak (may be NULL) the shell k >= 1 of largest mean (first on
+ * ties).  Runs on the calling thread. */
+int32_t soma_sq_shells(const double *sq, uint32_t nx, uint32_t ny, uint32_t nz,
+                       uint32_t n_shells, double *q_mid, double *s_avg, uint64_t *count,
+                       uint32_t *peak);
+
 /* Device workspace bytes of soma_train_step for up to max_waves partials. */
 uint64_t soma_train_workspace_bytes(uint32_t max_waves);
 

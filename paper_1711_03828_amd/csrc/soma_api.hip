@@ -18,6 +18,7 @@
 #include "soma_sweep.hpp"
 #include "soma_train.hpp"
 #include "soma_batch.hpp"
+#include "soma_sq.hpp"
 
 namespace {
 
@@ -733,6 +734,96 @@ int32_t soma_collect_training(soma_system *sys, uint32_t n, uint32_t round, uint
   hipLaunchKernelGGL(soma::collect_kernel, dim3((n + 255) / 256), dim3(256), 0,
                      reinterpret_cast<hipStream_t>(stream), a);
   LAUNCH_TRY();
+  return SOMA_OK;
+}
+
+uint64_t soma_sq_workspace_bytes(const soma_system *sys) {
+  if (!sys) return 0;
+  const uint64_t n = sys->d.n_cells;
+  return align_up(16 * n) * 2 + align_up(16ull * (sys->cfg.nx + sys->cfg.ny + sys->cfg.nz));
+}
+
+int32_t soma_structure_factor(soma_system *sys, void *workspace, uint64_t workspace_bytes,
+                              double *sq, void *stream) {
+  if (!sys || !workspace || !sq) return fail(SOMA_E_INVAL, "NULL argument");
+  if (!aligned(workspace, 256) || !aligned(sq, 8))
+    return fail(SOMA_E_INVAL, "workspace must be 256-byte aligned, sq 8-byte aligned");
+  const uint64_t need = soma_sq_workspace_bytes(sys);
+  if (workspace_bytes < need)
+    return fail(SOMA_E_SIZE, "structure-factor workspace: %llu < %llu bytes",
+                (unsigned long long)workspace_bytes, (unsigned long long)need);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const uint64_t n = sys->d.n_cells;
+  unsigned char *ws = reinterpret_cast<unsigned char *>(workspace);
+  soma::SqArgs a;
+  a.counts = sys->buf.counts;
+  a.count64 = sys->cfg.count_width == 32;
+  a.nx = sys->cfg.nx;
+  a.ny = sys->cfg.ny;
+  a.nz = sys->cfg.nz;
+  a.a = reinterpret_cast<double2 *>(ws);
+  a.b = reinterpret_cast<double2 *>(ws + align_up(16 * n));
+  double2 *tw = reinterpret_cast<double2 *>(ws + 2 * align_up(16 * n));
+  const uint32_t len[3] = {a.nx, a.ny, a.nz};
+  uint32_t off = 0;
+  for (int k = 0; k < 3; ++k) {
+    hipLaunchKernelGGL(soma::sq_twiddle_kernel, dim3((len[k] + 255) / 256), dim3(256), 0, s,
+                       tw + off, len[k]);
+    LAUNCH_TRY();
+    a.tw[k] = tw + off;
+    off += len[k];
+  }
+  const dim3 grid((uint32_t)((n + 255) / 256));
+  hipLaunchKernelGGL(soma::sq_dft_x_kernel, grid, dim3(256), 0, s, a);
+  LAUNCH_TRY();
+  hipLaunchKernelGGL(soma::sq_dft_axis_kernel, grid, dim3(256), 0, s, a.a, a.b, a.tw[1], a.nx,
+                     a.ny, a.nz, 1);
+  LAUNCH_TRY();
+  hipLaunchKernelGGL(soma::sq_dft_axis_kernel, grid, dim3(256), 0, s, a.b, a.a, a.tw[2], a.nx,
+                     a.ny, a.nz, 2);
+  LAUNCH_TRY();
+  const double nn = (double)sys->cfg.n_ref;
+  hipLaunchKernelGGL(soma::sq_power_kernel, grid, dim3(256), 0, s, a.a, sq, n,
+                     nn * nn / (4.0 * (double)sys->d.n_beads));
+  LAUNCH_TRY();
+  return SOMA_OK;
+}
+
+int32_t soma_sq_shells(const double *sq, uint32_t nx, uint32_t ny, uint32_t nz,
+                       uint32_t n_shells, double *q_mid, double *s_avg, uint64_t *count,
+                       uint32_t *peak) {
+  if (!sq || !s_avg || !count || n_shells == 0) return fail(SOMA_E_INVAL, "NULL argument");
+  if (nx == 0 || ny == 0 || nz == 0) return fail(SOMA_E_INVAL, "empty grid");
+  const double two_pi = 6.283185307179586476925286766559;
+  const uint32_t lmin = std::min(nx, std::min(ny, nz));
+  const double dq = two_pi / (double)lmin;
+  for (uint32_t k = 0; k < n_shells; ++k) {
+    s_avg[k] = 0.0;
+    count[k] = 0;
+    if (q_mid) q_mid[k] = dq * k;
+  }
+  auto wave = [](uint32_t m, uint32_t n) { return (double)(m <= n / 2 ? (int64_t)m : (int64_t)m - n) / n; };
+  uint64_t c = 0;
+  for (uint32_t z = 0; z < nz; ++z) {
+    const double fz = wave(z, nz);
+    for (uint32_t y = 0; y < ny; ++y) {
+      const double fy = wave(y, ny);
+      for (uint32_t x = 0; x < nx; ++x, ++c) {
+        const double fx = wave(x, nx);
+        const double q = two_pi * std::sqrt(fx * fx + fy * fy + fz * fz);
+        const uint64_t k = (uint64_t)std::floor(q / dq + 0.5);
+        if (k >= n_shells) continue;
+        s_avg[k] += sq[c];
+        count[k] += 1;
+      }
+    }
+  }
+  uint32_t best = 0;
+  for (uint32_t k = 0; k < n_shells; ++k) {
+    if (count[k]) s_avg[k] /= (double)count[k];
+    if (k >= 1 && count[k] && (best == 0 || s_avg[k] > s_avg[best])) best = k;
+  }
+  if (peak) *peak = best;
   return SOMA_OK;
 }
 

@@ -135,6 +135,9 @@ _SIGS = {
     "soma_train_workspace_bytes": ([_u32], ctypes.c_uint64),
     "soma_train_step": ([_P, _P, _u32, _P, _P, _P, _u32, ctypes.POINTER(soma_train_opts), _P,
                          _u64, _P, _P, _P], _i32),
+    "soma_sq_workspace_bytes": ([_P], ctypes.c_uint64),
+    "soma_structure_factor": ([_P, _P, _u64, _P, _P], _i32),
+    "soma_sq_shells": ([_P, _u32, _u32, _u32, _u32, _P, _P, _P, _pu32], _i32),
     "soma_destroy": ([_P], None),
     "soma_last_error": ([], ctypes.c_char_p),
 }
@@ -328,6 +331,30 @@ def soma_collect_training(h, n: int, round_: int, phase: int, features_ptr: int,
     vp = lambda x: ctypes.c_void_p(x) if x else None
     _check(_lib.soma_collect_training(h, n, round_, phase, vp(features_ptr), vp(r0_ptr),
                                       vp(dr_ptr), vp(picked_ptr), ctypes.c_void_p(stream)))
+
+
+def soma_sq_workspace_bytes(h) -> int:
+    return int(_lib.soma_sq_workspace_bytes(h))
+
+
+def soma_structure_factor(h, ws_ptr: int, ws_bytes: int, sq_ptr: int, stream: int) -> None:
+    _check(_lib.soma_structure_factor(h, ctypes.c_void_p(ws_ptr), ws_bytes,
+                                      ctypes.c_void_p(sq_ptr), ctypes.c_void_p(stream)))
+
+
+def soma_sq_shells(sq_host, grid, n_shells: int):
+    """Shell average of a host float64 array (C-contiguous, n_cells):
+    (q_mid, s_avg, count, peak) as numpy arrays and an int."""
+    import numpy as np
+    sq_host = np.ascontiguousarray(sq_host, dtype=np.float64)
+    q = np.zeros(n_shells)
+    s = np.zeros(n_shells)
+    c = np.zeros(n_shells, np.uint64)
+    peak = ctypes.c_uint32()
+    nx, ny, nz = (int(v) for v in grid)
+    _check(_lib.soma_sq_shells(sq_host.ctypes.data, nx, ny, nz, n_shells, q.ctypes.data,
+                               s.ctypes.data, c.ctypes.data, ctypes.byref(peak)))
+    return q, s, c, peak.value
 
 
 def soma_train_workspace_bytes(max_waves: int) -> int:
