@@ -113,6 +113,142 @@ def cpu_baseline(w, seconds: float):
                        f"{sample.n_beads} beads, same density/chiN/kappaN")}
 
 
+def _re_vectors(melt, n):
+    x = melt.pos.view(-1, n, 3)
+    return (x[:, -1] - x[:, 0]).double()
+
+
+def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: int):
+    """Plain vs learned proposal on the 262,144-chain melt (96^3 cells, chiN 25).
+
+    1. Training data from the plain sampler: 10 rounds of 2^20 random beads,
+       features at cycle t and displacement after 128 further plain cycles
+       (10,485,760 samples), collected and trained on the device.
+    2. Bead-moves/s of both samplers on the full melt (HIP events, graph-replayed
+       SCMF cycles).
+    3. tau_int of the end-to-end vectors (Sokal window) on a 4096-chain melt of the
+       same density and chemistry (24^3 cells), from frames every `frame_cycles`
+       cycles (plain: plain_mult times as many), after equilibration with the
+       learned sampler; uncorrelated
+       samples/s = n_chains * cycles/s / (2 tau_int), cycles/s from step 2.
+    """
+    import torch
+
+    from paper_1711_03828_amd import analysis, learned
+    from paper_1711_03828_amd import soma as C
+    from paper_1711_03828_amd.melt import Melt, make_config
+
+    w = synth.C4_MEDIUM
+    t0 = time.perf_counter()
+    melt = Melt(make_config(w, p_learn=p_learn))
+    melt.cycle(50)
+    feats, disp = learned.collect(melt, 1 << 20, 128, 10)
+    params = learned.init_params(feats, seed=1)
+    tr = learned.Trainer(params, lr=3e-3)
+    losses = tr.run(feats, disp, steps=3000, batch=8192, loss_every=500)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    n_samples = int(feats.shape[0])
+    del feats, disp
+    melt.set_proposal(params)
+    stream = torch.cuda.current_stream()
+    out = {"workload": w.name, "p_learn": p_learn,
+           "training": {"samples": n_samples, "lag_cycles": 128, "adam_steps": 3000,
+                        "batch": 8192, "loss_first": losses[0], "loss_last": losses[-1],
+                        "seconds_collect_and_train": t_train}}
+    rates = {}
+    for name, kind in (("plain", C.SOMA_MOVE_LOCAL), ("learned", C.SOMA_MOVE_MIXED)):
+        melt.capture_cycle(10, kind)
+        melt.run_cycle(2)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        melt.run_cycle(5)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 50
+        rates[name] = 1e3 / ms
+        out[name] = {"ms_per_cycle": ms, "bead_moves_per_s": w.n_beads * 1e3 / ms}
+    obs = melt.observables()
+    out["learned"]["acceptance"] = obs.accepted[2] / max(1, obs.attempted[2])
+    out["plain"]["acceptance"] = obs.accepted[0] / max(1, obs.attempted[0])
+    melt.close()
+
+    sub_w = synth.scaled(w, 4096, (24, 24, 24))
+    sub = Melt(make_config(sub_w, p_learn=p_learn))
+    sub.set_proposal(params)
+    sub.capture_cycle(frame_cycles, C.SOMA_MOVE_MIXED)
+    sub.run_cycle(max(1, 20000 // frame_cycles))       # equilibrate (learned sampler)
+    for name, kind, mult in (("learned", C.SOMA_MOVE_MIXED, 1),
+                             ("plain", C.SOMA_MOVE_LOCAL, plain_mult)):
+        sub.capture_cycle(frame_cycles * mult, kind)
+        n_frames = sub_frames
+        re = torch.empty((n_frames, sub_w.n_chains, 3), dtype=torch.float64, device="cuda")
+        for f in range(n_frames):
+            sub.run_cycle(1)
+            re[f] = _re_vectors(sub, 32)
+        series = re.reshape(n_frames, -1).cpu().numpy()
+        tau_frames, window = analysis.tau_int(series)
+        step = frame_cycles * mult
+        tau = tau_frames * step
+        re2 = float((re ** 2).sum(-1).mean()) / w.re_cells ** 2
+        out[name].update({"tau_int_cycles": tau, "window_frames": window,
+                          "frames": n_frames, "cycles_per_frame": step,
+                          "re2_over_re02": re2,
+                          "uncorrelated_samples_per_s":
+                              w.n_chains * rates[name] / (2.0 * tau)})
+        print(f"# {name}: tau_int {tau:.1f} cycles (window {window} frames), "
+              f"<Re^2>/Re0^2 {re2:.4f}", file=sys.stderr, flush=True)
+    sub.close()
+    out["gain_uncorrelated_samples_per_s"] = (out["learned"]["uncorrelated_samples_per_s"] /
+                                              out["plain"]["uncorrelated_samples_per_s"])
+    return out
+
+
+def batched_leg(cycles: int):
+    """64 uneven replicas (chains log-uniform on 2048..262144, N in {16, 32, 64},
+    chiN 10..40): autotuned batched launch, graph-replayed SCMF cycles, against
+    the same cycles run melt by melt."""
+    import torch
+
+    from paper_1711_03828_amd import soma as C
+    from paper_1711_03828_amd.melt import Batch, Melt, make_config
+
+    reps = synth.c3_replicas()
+    melts = [Melt(make_config(w, replica=i)) for i, w in enumerate(reps)]
+    n_beads = sum(w.n_beads for w in reps)
+    batch = Batch(melts)
+    tune = batch.autotune(3, C.SOMA_MOVE_LOCAL)
+    batch.capture_cycle(10, C.SOMA_MOVE_LOCAL)
+    batch.run_cycle(1)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    batch.run_cycle(cycles // 10)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / (cycles // 10 * 10)
+    # the same cycles melt by melt (one launch per melt and kernel)
+    e0.record(stream)
+    for m in melts:
+        m.cycle(10)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_single = e0.elapsed_time(e1) / 10
+    obs = [m.observables() for m in melts]
+    acc = sum(o.accepted[0] for o in obs) / max(1, sum(o.attempted[0] for o in obs))
+    batch.close()
+    for m in melts:
+        m.close()
+    return {"workload": f"{len(reps)} replicas, {n_beads} beads, "
+                        f"{sum(w.n_cells for w in reps)} cells",
+            "ms_per_cycle": ms, "bead_moves_per_s": n_beads * 1e3 / ms,
+            "ms_per_cycle_unbatched": ms_single,
+            "speedup_vs_unbatched": ms_single / ms,
+            "tuned": {"mode": tune.mode, "grid_blocks": tune.grid_blocks,
+                      "candidates": tune.candidates, "cycles_run": tune.cycles_run},
+            "acceptance": acc}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +258,16 @@ def main():
     ap.add_argument("--move", default="local", choices=["local", "smc"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the plain-vs-learned proposal comparison")
+    ap.add_argument("--p-learn", type=float, default=0.9)
+    ap.add_argument("--tau-frames", type=int, default=400, help="frames per tau_int run")
+    ap.add_argument("--frame-cycles", type=int, default=50,
+                    help="cycles between frames of the learned run")
+    ap.add_argument("--plain-frame-mult", type=int, default=16,
+                    help="the plain run's frames are this many times further apart")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 64-replica batched measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -206,6 +352,11 @@ def main():
         "acceptance": acc,
     }
     melt.close()
+    if not args.no_learned:
+        result["learned_proposal"] = learned_leg(args.p_learn, args.tau_frames,
+                                                 args.frame_cycles, args.plain_frame_mult)
+    if not args.no_batched:
+        result["batched"] = batched_leg(50)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(result), flush=True)
