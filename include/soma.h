@@ -311,18 +311,19 @@ int32_t soma_features(soma_system *sys, const uint32_t *chains,
 
 /* Training samples from the running melt (plain-sampler trajectories).
  * Sample s (0 <= s < n) of round `round` is bead i of global chain c with
- * c = floor(w0 * n_chains / 2^32), i = floor(w1 * n_species_beads / 2^32),
- * where (w0, w1, ...) is the Philox4x32-10 block of counter
- * (s, 5 << 16, round, replica) and the system's key.
+ * c = c0 + floor(w0 * nc / 2^32), i = floor(w1 * N / 2^32), where (w0, w1, ...)
+ * is the Philox4x32-10 block of counter (s, 5 << 16, round, replica) and the
+ * system's key, [c0, c0 + nc) the chains of `species` (all chains for
+ * SOMA_ALL_SPECIES) and N the beads per chain of c's species.
  *   phase 0: writes r0 [n][3] = its position, features [n][60] (if not NULL)
  *            and picked [n][2] = (c, i) (if not NULL);
  *   phase 1: writes dr [n][3] = position now - r0 (same samples: same round).
  * Call phase 0, run K SCMF cycles, call phase 1: (features, dr) is one batch
  * of (input, target) pairs for soma_train_step.  All buffers device memory,
  * caller-owned.  Asynchronous. */
-int32_t soma_collect_training(soma_system *sys, uint32_t n, uint32_t round, uint32_t phase,
-                              float *features, float *r0, float *dr, uint32_t *picked,
-                              void *stream);
+int32_t soma_collect_training(soma_system *sys, uint32_t species, uint32_t n, uint32_t round,
+                              uint32_t phase, float *features, float *r0, float *dr,
+                              uint32_t *picked, void *stream);
 
 /* Options of one training step of the network. */
 typedef struct soma_train_opts {

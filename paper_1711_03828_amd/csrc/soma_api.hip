@@ -709,11 +709,14 @@ int32_t soma_features(soma_system *sys, const uint32_t *chains, const uint32_t *
   return SOMA_OK;
 }
 
-int32_t soma_collect_training(soma_system *sys, uint32_t n, uint32_t round, uint32_t phase,
-                              float *features, float *r0, float *dr, uint32_t *picked,
-                              void *stream) {
+int32_t soma_collect_training(soma_system *sys, uint32_t species, uint32_t n, uint32_t round,
+                              uint32_t phase, float *features, float *r0, float *dr,
+                              uint32_t *picked, void *stream) {
   if (!sys || !r0) return fail(SOMA_E_INVAL, "NULL argument");
   if (phase > 1) return fail(SOMA_E_INVAL, "phase %u", phase);
+  if (species != SOMA_ALL_SPECIES &&
+      (species >= sys->cfg.n_species || sys->cfg.species[species].n_chains == 0))
+    return fail(SOMA_E_INVAL, "species %u has no chains", species);
   if (phase == 1 && !dr) return fail(SOMA_E_INVAL, "phase 1 needs dr");
   if (n == 0) return SOMA_OK;
   soma::CollectArgs a;
@@ -731,6 +734,9 @@ int32_t soma_collect_training(soma_system *sys, uint32_t n, uint32_t round, uint
   a.r0 = r0;
   a.dr = dr;
   a.picked = picked;
+  a.chain_lo = species == SOMA_ALL_SPECIES ? 0u : (uint32_t)sys->d.chain_off[species];
+  a.chain_count = species == SOMA_ALL_SPECIES ? (uint32_t)sys->d.n_chains
+                                              : sys->cfg.species[species].n_chains;
   hipLaunchKernelGGL(soma::collect_kernel, dim3((n + 255) / 256), dim3(256), 0,
                      reinterpret_cast<hipStream_t>(stream), a);
   LAUNCH_TRY();

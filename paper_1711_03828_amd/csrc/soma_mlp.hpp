@@ -295,8 +295,8 @@ __global__ __launch_bounds__(256) void features_kernel(const float *__restrict__
 }
 
 // Training samples drawn from the running melt.  Sample s of a round picks a
-// chain uniformly among all chains and a bead uniformly along it, from the
-// Philox block (s, purpose 5, round, replica).  Phase 0 records the bead's
+// chain uniformly among the chains of one species (or of all species) and a
+// bead uniformly along it, from the Philox block (s, purpose 5, round, replica).  Phase 0 records the bead's
 // features (optional) and position; phase 1, later in the run, the
 // displacement from that recorded position.
 struct CollectArgs {
@@ -305,6 +305,7 @@ struct CollectArgs {
   Grid grid;
   SpeciesTable st;
   uint32_t seed_lo, seed_hi, replica, round, n, phase;
+  uint32_t chain_lo, chain_count;  // chains drawn from [chain_lo, chain_lo + chain_count)
   float *features;   // [n][60] or null (phase 0)
   float *r0;         // [n][3]
   float *dr;         // [n][3] (phase 1)
@@ -315,7 +316,7 @@ __global__ __launch_bounds__(256) void collect_kernel(const CollectArgs a) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= a.n) return;
   const Rand4 q = philox(s, kPurposeCollect << 16, a.round, a.replica, a.seed_lo, a.seed_hi);
-  const uint32_t c = __umulhi(q.x, a.st.total_chains);
+  const uint32_t c = a.chain_lo + __umulhi(q.x, a.chain_count);
   uint32_t sp;
   const float *chain = chain_start(a.pos, a.st, c, &sp);
   const uint32_t i = __umulhi(q.y, a.st.n[sp]);

@@ -28,10 +28,11 @@ def _stream():
 
 
 def collect(melt, n_per_round: int, lag: int, rounds: int, move=C.SOMA_MOVE_LOCAL,
-            first_round: int = 0, frozen_field: bool = False):
+            first_round: int = 0, frozen_field: bool = False, species=C.SOMA_ALL_SPECIES):
     """(features [rounds*n, 60], displacements [rounds*n, 3]) on the device: each
     round records n random beads, runs `lag` SCMF cycles with `move` (sweeps
-    without field refresh if `frozen_field`), and records their displacements."""
+    without field refresh if `frozen_field`), and records their displacements.
+    `species` restricts the beads to one species (per-species networks)."""
     n = n_per_round
     feats = torch.empty((rounds * n, 60), dtype=torch.float32, device="cuda")
     disp = torch.empty((rounds * n, 3), dtype=torch.float32, device="cuda")
@@ -40,12 +41,14 @@ def collect(melt, n_per_round: int, lag: int, rounds: int, move=C.SOMA_MOVE_LOCA
     for k in range(rounds):
         f_ptr = feats.data_ptr() + k * n * 60 * 4
         d_ptr = disp.data_ptr() + k * n * 3 * 4
-        C.soma_collect_training(melt.handle, n, first_round + k, 0, f_ptr, r0.data_ptr(), 0, 0, s)
+        C.soma_collect_training(melt.handle, n, first_round + k, 0, f_ptr, r0.data_ptr(), 0, 0, s,
+                                species)
         if frozen_field:
             melt.sweep(lag, move)
         else:
             melt.cycle(lag, move)
-        C.soma_collect_training(melt.handle, n, first_round + k, 1, 0, r0.data_ptr(), d_ptr, 0, s)
+        C.soma_collect_training(melt.handle, n, first_round + k, 1, 0, r0.data_ptr(), d_ptr, 0, s,
+                                species)
     return feats, disp
 
 

@@ -131,7 +131,7 @@ _SIGS = {
     "soma_set_proposal": ([_P, _u32, _P, _P], _i32),
     "soma_mlp_forward": ([_P, _P, _u32, _P, _P], _i32),
     "soma_features": ([_P, _P, _P, _u32, _P, _P], _i32),
-    "soma_collect_training": ([_P, _u32, _u32, _u32, _P, _P, _P, _P, _P], _i32),
+    "soma_collect_training": ([_P, _u32, _u32, _u32, _u32, _P, _P, _P, _P, _P], _i32),
     "soma_train_workspace_bytes": ([_u32], ctypes.c_uint64),
     "soma_train_step": ([_P, _P, _u32, _P, _P, _P, _u32, ctypes.POINTER(soma_train_opts), _P,
                          _u64, _P, _P, _P], _i32),
@@ -327,10 +327,12 @@ def soma_features(h, chains_ptr: int, beads_ptr: int, n: int, out_ptr: int, stre
 
 
 def soma_collect_training(h, n: int, round_: int, phase: int, features_ptr: int, r0_ptr: int,
-                          dr_ptr: int, picked_ptr: int, stream: int) -> None:
+                          dr_ptr: int, picked_ptr: int, stream: int,
+                          species: int = SOMA_ALL_SPECIES) -> None:
     vp = lambda x: ctypes.c_void_p(x) if x else None
-    _check(_lib.soma_collect_training(h, n, round_, phase, vp(features_ptr), vp(r0_ptr),
-                                      vp(dr_ptr), vp(picked_ptr), ctypes.c_void_p(stream)))
+    _check(_lib.soma_collect_training(h, species, n, round_, phase, vp(features_ptr),
+                                      vp(r0_ptr), vp(dr_ptr), vp(picked_ptr),
+                                      ctypes.c_void_p(stream)))
 
 
 def soma_sq_workspace_bytes(h) -> int:

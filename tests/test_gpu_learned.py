@@ -143,6 +143,15 @@ def test_collect_training(orc):
     now = m.pos.cpu().numpy()[idx]
     np.testing.assert_array_equal(dr.cpu().numpy(), now - pos[idx])
     assert np.abs(dr.cpu().numpy()).max() > 0
+    # one species only: chains 200 + floor(w0 * 50 / 2^32)
+    C.soma_collect_training(m.handle, n, rnd, 0, 0, r0.data_ptr(), 0, picked.data_ptr(),
+                            _stream(), species=1)
+    torch.cuda.synchronize()
+    got = picked.cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(got[:, 0], 200 + ((blk[:, 0] * 50) >> 32))
+    np.testing.assert_array_equal(got[:, 1], (blk[:, 1] * 17) >> 32)
+    with pytest.raises(C.SomaError):
+        C.soma_collect_training(m.handle, n, rnd, 0, 0, r0.data_ptr(), 0, 0, _stream(), species=2)
 
 
 @pytest.mark.parametrize("p_learn", [1.0, 0.5])
