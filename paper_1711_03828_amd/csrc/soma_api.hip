@@ -64,7 +64,8 @@ int32_t derive(const soma_config *c, Derived *d) {
   if (c->nx == 0 || c->ny == 0 || c->nz == 0)
     return fail(SOMA_E_INVAL, "grid dimensions must be positive");
   const uint64_t n_cells = (uint64_t)c->nx * c->ny * c->nz;
-  if (n_cells >= (1ull << 31)) return fail(SOMA_E_UNSUPPORTED, "more than 2^31 - 1 cells");
+  // field planes are addressed with 32-bit byte offsets: 2 * 4 * n_cells < 2^32
+  if (n_cells >= (1ull << 29)) return fail(SOMA_E_UNSUPPORTED, "more than 2^29 - 1 cells");
   if (c->n_species == 0 || c->n_species > SOMA_MAX_SPECIES)
     return fail(SOMA_E_INVAL, "n_species must be in 1..%d", SOMA_MAX_SPECIES);
   if (c->count_width != 16 && c->count_width != 32)

@@ -36,7 +36,7 @@ struct BatchLaunch {
 template <bool COUNT64, bool VEC2, uint32_t KIND>
 __global__ __launch_bounds__(256) void batched_sweep_kernel(const BatchLaunch L) {
   __shared__ __bf16 s_act[KIND == 2 ? 4 : 1][KIND == 2 ? 64 * kActStride : 1];
-  __shared__ float s_z[KIND == 2 ? 4 : 1][KIND == 2 ? 64 * 8 : 1];
+  __shared__ __bf16 s_tmp[KIND == 2 ? 4 : 1][KIND == 2 ? 64 * kActStride : 1];
   uint32_t item, end, stride;
   if (L.mode == 0) {   // grid is a multiple of 8 blocks (host-checked)
     const uint32_t x = blockIdx.x & 7u;
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void batched_sweep_kernel(const BatchLaunch L)
       const MixArgs mx = L.segs[sg].mx;
       uint32_t cnt[3];
       mixed_wave<COUNT64, VEC2>(a, mx, m, s_act[KIND == 2 ? m.wib : 0],
-                                s_z[KIND == 2 ? m.wib : 0], cnt);
+                                s_tmp[KIND == 2 ? m.wib : 0], mx.net->shift, cnt);
       mixed_finish(a, mx, cnt);
     }
   }

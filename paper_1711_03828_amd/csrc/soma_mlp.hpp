@@ -65,54 +65,57 @@ __global__ __launch_bounds__(256) void net_prepare_kernel(const float *__restric
   }
 }
 
-__device__ __forceinline__ float silu(float a) { return a / (1.0f + __expf(-a)); }
+// SiLU a * sigmoid(a); the reciprocal is the hardware approximation (1 ulp),
+// ample for an activation that is rounded to bfloat16 next.
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float silu(float a) { return a * fast_rcp(1.0f + __expf(-a)); }
 
 __device__ __forceinline__ bf16x8 lds_b8(const __bf16 *p) {
   return *reinterpret_cast<const bf16x8 *>(p);
 }
 
-// One fully connected layer of 64 outputs with SiLU, for the wave's 64
-// samples: reads the inputs from `act`, overwrites `act` with the outputs.
+// One fully connected layer of 64 outputs with SiLU for the wave's 64
+// samples: inputs from LDS tile `in`, outputs to LDS tile `out`.  Output
+// units are produced 16 at a time (one MFMA row tile), so only 16
+// accumulators per lane are live.
 __device__ __forceinline__ void hidden_layer(const __bf16 *__restrict__ w,
-                                             const float *__restrict__ bias, __bf16 *act) {
+                                             const float *__restrict__ bias,
+                                             const __bf16 *in, __bf16 *out) {
   const int lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
-  f32x4 acc[4][4];
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+#pragma unroll 1
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 acc[4];
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
+    for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int kb = 0; kb < 2; ++kb) {
-    bf16x8 b[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) b[t] = lds_b8(act + (16 * t + col) * kActStride + 32 * kb + 8 * g);
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
+    for (int kb = 0; kb < 2; ++kb) {
       const bf16x8 av = *reinterpret_cast<const bf16x8 *>(w + (16 * mt + col) * 64 + 32 * kb + 8 * g);
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[t], acc[mt][t], 0, 0, 0);
+      for (int t = 0; t < 4; ++t) {
+        const bf16x8 bv = lds_b8(in + (16 * t + col) * kActStride + 32 * kb + 8 * g);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
+      }
     }
-  }
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
+    const int unit = 16 * mt + 4 * g;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const int unit = 16 * mt + 4 * g;
-      typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
       bf16x4 v;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) v[r] = (__bf16)silu(acc[mt][t][r] + bias[unit + r]);
-      *reinterpret_cast<bf16x4 *>(act + (16 * t + col) * kActStride + unit) = v;
+      for (int r = 0; r < 4; ++r) v[r] = (__bf16)silu(acc[t][r] + bias[unit + r]);
+      *reinterpret_cast<bf16x4 *>(out + (16 * t + col) * kActStride + unit) = v;
     }
+  }
 }
 
 // Network output z (6 per sample) for the 64 samples whose standardised
-// inputs are in `act` (row = lane); z of sample s lands in zout[8 s .. 8 s + 5].
+// inputs are in LDS tile `act` (row = lane); `tmp` is a second tile of the
+// same size.  z of sample s lands in zout[8 s .. 8 s + 5] (zout may alias
+// `act`: it is written after the last read of `act`).
 __device__ __forceinline__ void wave_forward(const NetDev *__restrict__ net, __bf16 *act,
-                                             float *zout) {
-  hidden_layer(net->w1, net->b1, act);
-  hidden_layer(net->w2, net->b2, act);
+                                             __bf16 *tmp, float *zout) {
+  hidden_layer(net->w1, net->b1, act, tmp);
+  hidden_layer(net->w2, net->b2, tmp, act);
   const int lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
   f32x4 acc[4];
 #pragma unroll
@@ -172,29 +175,88 @@ __device__ __forceinline__ float raw_feature(int k, const Neighbourhood &nb, con
   return d == 0 ? v.x : (d == 1 ? v.y : v.z);
 }
 
+// Three x-consecutive cells (periodic in x) of one grid row: one 12-byte load
+// of an in-range triple plus, in the first and last column, one more value
+// from the other end of the row.  Needs nx >= 3.
+typedef float f32x3u __attribute__((ext_vector_type(3), aligned(4)));
+
+__device__ __forceinline__ void row3(const float *__restrict__ plane, uint32_t base, uint32_t cx,
+                                     uint32_t nx, float &v0, float &v1, float &v2) {
+  const bool lo = cx == 0u, hi = cx + 1u == nx;
+  const uint32_t start = lo ? 0u : (hi ? nx - 3u : cx - 1u);
+  const f32x3u t = *reinterpret_cast<const f32x3u *>(plane + base + start);
+  float extra = 0.0f;
+  if (lo || hi) extra = plane[base + (lo ? nx - 1u : 0u)];
+  v0 = lo ? extra : (hi ? t.y : t.x);
+  v1 = lo ? t.x : (hi ? t.z : t.y);
+  v2 = lo ? t.y : (hi ? extra : t.z);
+}
+
+// The 60 raw features of a bead (see raw_feature), gathered row by row.
+__device__ __forceinline__ void gather_features(const Grid &g, const Neighbourhood &nb,
+                                                const float *__restrict__ own,
+                                                const float *__restrict__ oth, F3 bp, F3 bn,
+                                                float (&f)[kNF]) {
+  if (g.nx >= 3) {
+    const uint32_t cx = nb.xs[1];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      row3(own, nb.base[q], cx, (uint32_t)g.nx, f[3 * q], f[3 * q + 1], f[3 * q + 2]);
+      row3(oth, nb.base[q], cx, (uint32_t)g.nx, f[27 + 3 * q], f[28 + 3 * q], f[29 + 3 * q]);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 54; ++k) f[k] = raw_feature(k, nb, own, oth, bp, bn);
+  }
+  f[54] = bp.x; f[55] = bp.y; f[56] = bp.z;
+  f[57] = bn.x; f[58] = bn.y; f[59] = bn.z;
+}
+
+// Field value at cell index c of the plane starting `plane_off` floats into
+// omega: a 32-bit byte offset from the uniform base (fields < 4 GiB,
+// host-checked), so the load needs no 64-bit address arithmetic per lane.
+__device__ __forceinline__ float field_at(const float *__restrict__ omega, uint32_t plane_off,
+                                          uint32_t c) {
+  return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(omega) +
+                                          ((plane_off + c) << 2));
+}
+
+// Per-block LDS copy of the standardisation constants: shift[64], scale[64].
+__device__ __forceinline__ void load_standardisation(const NetDev *__restrict__ net,
+                                                     float *s_std) {
+  if (threadIdx.x < 64) {
+    s_std[threadIdx.x] = net->shift[threadIdx.x];
+    s_std[64 + threadIdx.x] = net->scale[threadIdx.x];
+  }
+}
+
 // Gathers, standardises and stores the 60 features of a bead at r into one
-// LDS row of bf16 (entries 60..63 zero), 8 at a time.  Returns the bead's own
-// field in its cell; `cell` receives that cell's index.
+// LDS row of bf16 (entries 60..63 zero), 8 at a time.  `s_std` holds the
+// standardisation constants (LDS).  Returns the bead's own field in its cell;
+// `cell` receives that cell's index.
 __device__ __forceinline__ float features_to_row(const Grid &g, const float *__restrict__ omega,
                                                  bool is_b, F3 r, F3 bp, F3 bn,
-                                                 const NetDev *__restrict__ net, __bf16 *row,
+                                                 const float *s_std, __bf16 *row,
                                                  uint32_t &cell) {
   const Neighbourhood nb = neighbourhood(g, r);
-  const float *own = omega + (is_b ? g.n_cells : 0u);
-  const float *oth = omega + (is_b ? 0u : g.n_cells);
+  const uint32_t own = is_b ? g.n_cells : 0u, oth = is_b ? 0u : g.n_cells;
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     bf16x8 v;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int k = 8 * c + j;
-      v[j] = k < kNF ? (__bf16)((raw_feature(k, nb, own, oth, bp, bn) - net->shift[k]) * net->scale[k])
-                     : (__bf16)0.0f;
+      float x = 0.0f;
+      if (k < 27) x = field_at(omega, own, nb.base[k / 3] + nb.xs[k % 3]);
+      else if (k < 54) x = field_at(omega, oth, nb.base[(k - 27) / 3] + nb.xs[(k - 27) % 3]);
+      else if (k < 57) x = (k == 54) ? bp.x : (k == 55 ? bp.y : bp.z);
+      else if (k < 60) x = (k == 57) ? bn.x : (k == 58 ? bn.y : bn.z);
+      v[j] = k < kNF ? (__bf16)((x - s_std[k]) * s_std[64 + k]) : (__bf16)0.0f;
     }
     *reinterpret_cast<bf16x8 *>(row + 8 * c) = v;
   }
   cell = nb.centre;
-  return own[nb.centre];
+  return field_at(omega, own, nb.centre);
 }
 
 // Gaussian head of one sample: mean, sigma and log sigma.
@@ -203,7 +265,7 @@ __device__ __forceinline__ void head(const float *z, const HeadArgs &h, float (&
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     mu[d] = h.m_max * tanhf(z[d] / h.m_max);
-    const float s = 1.0f / (1.0f + __expf(-z[3 + d]));
+    const float s = fast_rcp(1.0f + __expf(-z[3 + d]));
     lsig[d] = h.lo + (h.hi - h.lo) * s;
     sig[d] = __expf(lsig[d]);
   }
@@ -214,6 +276,7 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const NetDev *__restri
                                                           const float *__restrict__ feat,
                                                           uint32_t n, float *__restrict__ z) {
   __shared__ __bf16 s_act[4][64 * kActStride];
+  __shared__ __bf16 s_tmp[4][64 * kActStride];
   __shared__ float s_z[4][64 * 8];
   const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   const uint32_t s = (blockIdx.x * 4u + wv) * 64u + lane;
@@ -229,7 +292,7 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const NetDev *__restri
     }
     *reinterpret_cast<bf16x8 *>(row + 8 * c) = v;
   }
-  wave_forward(net, s_act[wv], s_z[wv]);
+  wave_forward(net, s_act[wv], s_tmp[wv], s_z[wv]);
   if (s < n)
 #pragma unroll
     for (int o = 0; o < kNO; ++o) z[(size_t)s * kNO + o] = s_z[wv][lane * 8 + o];
@@ -269,8 +332,10 @@ __device__ __forceinline__ void bead_features(const float *chain, const float *o
   const bool is_b = i >= st.n_a[sp];
   const float *own = omega + (is_b ? g.n_cells : 0u);
   const float *oth = omega + (is_b ? 0u : g.n_cells);
+  float f[kNF];
+  gather_features(g, nb, own, oth, bp, bn, f);
 #pragma unroll
-  for (int k = 0; k < kNF; ++k) row[k] = raw_feature(k, nb, own, oth, bp, bn);
+  for (int k = 0; k < kNF; ++k) row[k] = f[k];
 }
 
 // Raw features (FP32) of bead `beads[s]` of global chain `chains[s]` at the

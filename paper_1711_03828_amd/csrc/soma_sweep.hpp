@@ -447,11 +447,15 @@ struct MixArgs {
 // non-finite network output rejects it and raises error bit 2.  The network
 // needs the bond vectors, so the two sets are handled one after the other.
 // ---------------------------------------------------------------------------
-// One wave's chains; act/zb are the wave's LDS tiles.  Returns through cnt the
-// wave's accepted local moves, accepted learned moves and learned attempts.
+// One wave's chains; act/tmp are the wave's two LDS activation tiles (the
+// network output z reuses tmp), s_std the block's LDS copy of the
+// standardisation constants.  Returns through cnt the wave's accepted local
+// moves, accepted learned moves and learned attempts.
 template <bool COUNT64, bool VEC2>
 __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx, const LaneMap &m,
-                                           __bf16 *act, float *zb, uint32_t cnt[3]) {
+                                           __bf16 *act, __bf16 *tmp, const float *s_std,
+                                           uint32_t cnt[3]) {
+  float *zb = reinterpret_cast<float *>(tmp);
   __bf16 *row = act + m.lane * kActStride;
   const uint32_t N = a.n;
   const uint32_t i0 = 2u * m.k, i1 = i0 + 1u;
@@ -497,8 +501,8 @@ __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx
     bool net_bad = false;
     if (__ballot(learned) != 0ull) {
       w_old = features_to_row(a.grid, a.omega, is_b, r, has_l ? left - r : zero3,
-                              has_r ? right - r : zero3, mx.net, row, co);
-      wave_forward(mx.net, act, zb);
+                              has_r ? right - r : zero3, s_std, row, co);
+      wave_forward(mx.net, act, tmp, zb);
       float mu[3], sig[3], lsig[3];
       head(zb + m.lane * 8, mx.head, mu, sig, lsig);
       float xi0, xi1, xi2, xi3;
@@ -510,8 +514,8 @@ __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx
                      fmaf(a.step, uniform11(w.z), r.z)};
       rn = sel(learned, tl, tp);
       w_new = features_to_row(a.grid, a.omega, is_b, rn, has_l ? left - rn : zero3,
-                              has_r ? right - rn : zero3, mx.net, row, cn);
-      wave_forward(mx.net, act, zb);
+                              has_r ? right - rn : zero3, s_std, row, cn);
+      wave_forward(mx.net, act, tmp, zb);
       float mun[3], sign[3], lsign[3];
       head(zb + m.lane * 8, mx.head, mun, sign, lsign);
       float lq = 0.0f;
@@ -521,7 +525,8 @@ __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx
         const float td = d == 0 ? rn.x : (d == 1 ? rn.y : rn.z);
         const float ef = td - rd - mu[d];
         const float er = rd - td - mun[d];
-        lq += 0.5f * ef * ef / (sig[d] * sig[d]) + lsig[d] - 0.5f * er * er / (sign[d] * sign[d]) - lsign[d];
+        lq += 0.5f * ef * ef * fast_rcp(sig[d] * sig[d]) + lsig[d] -
+              0.5f * er * er * fast_rcp(sign[d] * sign[d]) - lsign[d];
         net_bad |= !(isfinite(mu[d]) && isfinite(sig[d]) && isfinite(mun[d]) && isfinite(sign[d]));
       }
       log_q = lq;   // log q(r|r') - log q(r'|r)
@@ -584,11 +589,11 @@ template <bool COUNT64, bool VEC2>
 __global__ __launch_bounds__(256) void mc_sweep_mixed_kernel(const SweepArgs a_in,
                                                              const MixArgs mx) {
   __shared__ __bf16 s_act[4][64 * kActStride];
-  __shared__ float s_z[4][64 * 8];
+  __shared__ __bf16 s_tmp[4][64 * kActStride];
   const SweepArgs a = resolve_sweep(a_in, 0u);
   const LaneMap m = lane_map(a);
   uint32_t cnt[3];
-  mixed_wave<COUNT64, VEC2>(a, mx, m, s_act[m.wib], s_z[m.wib], cnt);
+  mixed_wave<COUNT64, VEC2>(a, mx, m, s_act[m.wib], s_tmp[m.wib], mx.net->shift, cnt);
   mixed_finish(a, mx, cnt);
 }
 

@@ -31,7 +31,7 @@ struct TrainArgs {
 __device__ __forceinline__ bf16x8 lds8(const __bf16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
 
 __device__ __forceinline__ float dsilu(float a) {
-  const float s = 1.0f / (1.0f + __expf(-a));
+  const float s = fast_rcp(1.0f + __expf(-a));
   return s * (1.0f + a * (1.0f - s));
 }
 
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const TrainArgs a) {
       for (int d = 0; d < 3; ++d) {
         const float tgt = valid ? a.target[(size_t)s * 3 + d] : 0.0f;
         const float mu = a.head.m_max * tanhf(z[d] / a.head.m_max);
-        const float sg = 1.0f / (1.0f + __expf(-z[3 + d]));
+        const float sg = fast_rcp(1.0f + __expf(-z[3 + d]));
         const float ls = a.head.lo + (a.head.hi - a.head.lo) * sg;
         const float inv_var = __expf(-2.0f * ls);
         const float e = tgt - mu;
