@@ -163,100 +163,82 @@ __device__ __forceinline__ Neighbourhood neighbourhood(const Grid &g, F3 r) {
   return nb;
 }
 
-// Raw feature k (0..59) of a bead: fields of its own type at the 27 cells
-// around its cell ((dz, dy, dx) order, periodic), then the other type's, then
-// the bond vectors to the previous and next bead (zero where absent).
-__device__ __forceinline__ float raw_feature(int k, const Neighbourhood &nb, const float *own,
-                                             const float *oth, F3 bp, F3 bn) {
-  if (k < 27) return own[nb.base[k / 3] + nb.xs[k % 3]];
-  if (k < 54) return oth[nb.base[(k - 27) / 3] + nb.xs[(k - 27) % 3]];
-  const int d = (k - 54) % 3;
-  const F3 v = k < 57 ? bp : bn;
-  return d == 0 ? v.x : (d == 1 ? v.y : v.z);
+// Field value at cell index c of the plane starting `pl` floats into omega:
+// a 32-bit byte offset from the uniform base (fields < 4 GiB, host-checked),
+// so the load needs no 64-bit address arithmetic per lane.
+__device__ __forceinline__ float field_at(const float *__restrict__ omega, uint32_t pl,
+                                          uint32_t c) {
+  return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(omega) +
+                                          ((pl + c) << 2));
 }
 
-// Three x-consecutive cells (periodic in x) of one grid row: one 12-byte load
-// of an in-range triple plus, in the first and last column, one more value
-// from the other end of the row.  Needs nx >= 3.
+// Three x-consecutive cells (periodic in x) of one grid row of the plane at
+// `pl`: one 12-byte load of an in-range triple plus, in the first and last
+// column, one more value from the other end of the row.  Needs nx >= 3.
 typedef float f32x3u __attribute__((ext_vector_type(3), aligned(4)));
 
-__device__ __forceinline__ void row3(const float *__restrict__ plane, uint32_t base, uint32_t cx,
-                                     uint32_t nx, float &v0, float &v1, float &v2) {
+__device__ __forceinline__ void row3(const float *__restrict__ omega, uint32_t pl, uint32_t base,
+                                     uint32_t cx, uint32_t nx, float &v0, float &v1, float &v2) {
   const bool lo = cx == 0u, hi = cx + 1u == nx;
   const uint32_t start = lo ? 0u : (hi ? nx - 3u : cx - 1u);
-  const f32x3u t = *reinterpret_cast<const f32x3u *>(plane + base + start);
+  const f32x3u t = *reinterpret_cast<const f32x3u *>(reinterpret_cast<const char *>(omega) +
+                                                      ((pl + base + start) << 2));
   float extra = 0.0f;
-  if (lo || hi) extra = plane[base + (lo ? nx - 1u : 0u)];
+  if (lo || hi) extra = field_at(omega, pl, base + (lo ? nx - 1u : 0u));
   v0 = lo ? extra : (hi ? t.y : t.x);
   v1 = lo ? t.x : (hi ? t.z : t.y);
   v2 = lo ? t.y : (hi ? extra : t.z);
 }
 
-// The 60 raw features of a bead (see raw_feature), gathered row by row.
+// The 60 raw features of a bead: fields of its own type (plane `own`) at the
+// 27 cells around its cell ((dz, dy, dx) order, periodic), then the other
+// type's (plane `oth`), then the bond vectors to the previous and next bead
+// (zero where absent).  Gathered row by row.
 __device__ __forceinline__ void gather_features(const Grid &g, const Neighbourhood &nb,
-                                                const float *__restrict__ own,
-                                                const float *__restrict__ oth, F3 bp, F3 bn,
-                                                float (&f)[kNF]) {
+                                                const float *__restrict__ omega, uint32_t own,
+                                                uint32_t oth, F3 bp, F3 bn, float (&f)[kNF]) {
   if (g.nx >= 3) {
     const uint32_t cx = nb.xs[1];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-      row3(own, nb.base[q], cx, (uint32_t)g.nx, f[3 * q], f[3 * q + 1], f[3 * q + 2]);
-      row3(oth, nb.base[q], cx, (uint32_t)g.nx, f[27 + 3 * q], f[28 + 3 * q], f[29 + 3 * q]);
+      row3(omega, own, nb.base[q], cx, (uint32_t)g.nx, f[3 * q], f[3 * q + 1], f[3 * q + 2]);
+      row3(omega, oth, nb.base[q], cx, (uint32_t)g.nx, f[27 + 3 * q], f[28 + 3 * q],
+           f[29 + 3 * q]);
     }
   } else {
 #pragma unroll
-    for (int k = 0; k < 54; ++k) f[k] = raw_feature(k, nb, own, oth, bp, bn);
+    for (int k = 0; k < 27; ++k) {
+      f[k] = field_at(omega, own, nb.base[k / 3] + nb.xs[k % 3]);
+      f[27 + k] = field_at(omega, oth, nb.base[k / 3] + nb.xs[k % 3]);
+    }
   }
   f[54] = bp.x; f[55] = bp.y; f[56] = bp.z;
   f[57] = bn.x; f[58] = bn.y; f[59] = bn.z;
 }
 
-// Field value at cell index c of the plane starting `plane_off` floats into
-// omega: a 32-bit byte offset from the uniform base (fields < 4 GiB,
-// host-checked), so the load needs no 64-bit address arithmetic per lane.
-__device__ __forceinline__ float field_at(const float *__restrict__ omega, uint32_t plane_off,
-                                          uint32_t c) {
-  return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(omega) +
-                                          ((plane_off + c) << 2));
-}
-
-// Per-block LDS copy of the standardisation constants: shift[64], scale[64].
-__device__ __forceinline__ void load_standardisation(const NetDev *__restrict__ net,
-                                                     float *s_std) {
-  if (threadIdx.x < 64) {
-    s_std[threadIdx.x] = net->shift[threadIdx.x];
-    s_std[64 + threadIdx.x] = net->scale[threadIdx.x];
-  }
-}
-
 // Gathers, standardises and stores the 60 features of a bead at r into one
-// LDS row of bf16 (entries 60..63 zero), 8 at a time.  `s_std` holds the
-// standardisation constants (LDS).  Returns the bead's own field in its cell;
-// `cell` receives that cell's index.
+// LDS row of bf16 (entries 60..63 zero), 8 at a time.  `stdz` points at the
+// network's shift[64] followed by scale[64].  Returns the bead's own field in
+// its cell; `cell` receives that cell's index.
 __device__ __forceinline__ float features_to_row(const Grid &g, const float *__restrict__ omega,
                                                  bool is_b, F3 r, F3 bp, F3 bn,
-                                                 const float *s_std, __bf16 *row,
+                                                 const float *__restrict__ stdz, __bf16 *row,
                                                  uint32_t &cell) {
   const Neighbourhood nb = neighbourhood(g, r);
-  const uint32_t own = is_b ? g.n_cells : 0u, oth = is_b ? 0u : g.n_cells;
+  float f[kNF];
+  gather_features(g, nb, omega, is_b ? g.n_cells : 0u, is_b ? 0u : g.n_cells, bp, bn, f);
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     bf16x8 v;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int k = 8 * c + j;
-      float x = 0.0f;
-      if (k < 27) x = field_at(omega, own, nb.base[k / 3] + nb.xs[k % 3]);
-      else if (k < 54) x = field_at(omega, oth, nb.base[(k - 27) / 3] + nb.xs[(k - 27) % 3]);
-      else if (k < 57) x = (k == 54) ? bp.x : (k == 55 ? bp.y : bp.z);
-      else if (k < 60) x = (k == 57) ? bn.x : (k == 58 ? bn.y : bn.z);
-      v[j] = k < kNF ? (__bf16)((x - s_std[k]) * s_std[64 + k]) : (__bf16)0.0f;
+      v[j] = k < kNF ? (__bf16)((f[k < kNF ? k : 0] - stdz[k]) * stdz[64 + k]) : (__bf16)0.0f;
     }
     *reinterpret_cast<bf16x8 *>(row + 8 * c) = v;
   }
   cell = nb.centre;
-  return field_at(omega, own, nb.centre);
+  return f[13];   // own field at (dz, dy, dx) = (0, 0, 0)
 }
 
 // Gaussian head of one sample: mean, sigma and log sigma.
@@ -330,10 +312,8 @@ __device__ __forceinline__ void bead_features(const float *chain, const float *o
   const F3 bn = i + 1 < nn ? F3{chain[3 * i + 3], chain[3 * i + 4], chain[3 * i + 5]} - r : zero3;
   const Neighbourhood nb = neighbourhood(g, r);
   const bool is_b = i >= st.n_a[sp];
-  const float *own = omega + (is_b ? g.n_cells : 0u);
-  const float *oth = omega + (is_b ? 0u : g.n_cells);
   float f[kNF];
-  gather_features(g, nb, own, oth, bp, bn, f);
+  gather_features(g, nb, omega, is_b ? g.n_cells : 0u, is_b ? 0u : g.n_cells, bp, bn, f);
 #pragma unroll
   for (int k = 0; k < kNF; ++k) row[k] = f[k];
 }

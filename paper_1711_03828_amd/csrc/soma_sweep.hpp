@@ -120,19 +120,19 @@ __device__ __forceinline__ void store_pair(float *cp, const LaneMap &m, F3 r0, F
   }
 }
 
-// Move one bead's unit from cell `from` to cell `to` in the packed counts.
+// Move one bead's unit from cell `from` to cell `to` in the packed counts
+// (32-bit byte offsets from the uniform base: counts < 4 GiB, host-checked).
 template <bool COUNT64>
 __device__ __forceinline__ void move_count(void *counts, uint32_t from, uint32_t to, bool is_b) {
+  char *base = reinterpret_cast<char *>(counts);
   if (COUNT64) {
-    unsigned long long *c = reinterpret_cast<unsigned long long *>(counts);
     const unsigned long long inc = is_b ? (1ull << 32) : 1ull;
-    atomicAdd(c + from, (unsigned long long)(0ull - inc));
-    atomicAdd(c + to, inc);
+    atomicAdd(reinterpret_cast<unsigned long long *>(base + (from << 3)), 0ull - inc);
+    atomicAdd(reinterpret_cast<unsigned long long *>(base + (to << 3)), inc);
   } else {
-    unsigned int *c = reinterpret_cast<unsigned int *>(counts);
     const unsigned int inc = is_b ? (1u << 16) : 1u;
-    atomicAdd(c + from, 0u - inc);
-    atomicAdd(c + to, inc);
+    atomicAdd(reinterpret_cast<unsigned int *>(base + (from << 2)), 0u - inc);
+    atomicAdd(reinterpret_cast<unsigned int *>(base + (to << 2)), inc);
   }
 }
 
@@ -183,9 +183,8 @@ __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap
   const uint32_t c0 = cell_index(a.grid, x0, y0, z0);
   const uint32_t c1 = cell_index(a.grid, x1, y1, z1);
   const bool b0 = i0 >= a.n_a, b1 = i1 >= a.n_a;
-  const float *om0 = a.omega + (b0 ? a.grid.n_cells : 0u);
-  const float *om1 = a.omega + (b1 ? a.grid.n_cells : 0u);
-  const float wo0 = om0[c0], wo1 = om1[c1];
+  const uint32_t pl0 = b0 ? a.grid.n_cells : 0u, pl1 = b1 ? a.grid.n_cells : 0u;
+  const float wo0 = field_at(a.omega, pl0, c0), wo1 = field_at(a.omega, pl1, c1);
 
   const Rand4 w0 = philox(gchain, i0 | (kPurposeMoveA << 16), a.sweep, a.replica, a.seed_lo, a.seed_hi);
   const Rand4 w1 = philox(gchain, i1 | (kPurposeMoveA << 16), a.sweep, a.replica, a.seed_lo, a.seed_hi);
@@ -203,8 +202,8 @@ __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap
                                  shift_cell(y1, r1.y, t1.y, a.grid.ny),
                                  shift_cell(z1, r1.z, t1.z, a.grid.nz));
   float wn0 = wo0, wn1 = wo1;
-  if (n0 != c0) wn0 = om0[n0];
-  if (n1 != c1) wn1 = om1[n1];
+  if (n0 != c0) wn0 = field_at(a.omega, pl0, n0);
+  if (n1 != c1) wn1 = field_at(a.omega, pl1, n1);
 
   // relabel by set order: a moves first, b second
   const F3 ra0 = sel(odd_first, r1, r0), rb0 = sel(odd_first, r0, r1);
@@ -305,7 +304,7 @@ __global__ __launch_bounds__(256) void mc_sweep_local_kernel(const SweepArgs a_i
 
 // Central-difference gradient of one field plane at cell (cx,cy,cz); the
 // force of the grid field on a bead is -(1/N) grad omega.
-__device__ __forceinline__ F3 field_grad(const Grid &g, const float *om,
+__device__ __forceinline__ F3 field_grad(const Grid &g, const float *omega, uint32_t pl,
                                          uint32_t cx, uint32_t cy,
                                          uint32_t cz) {
   const uint32_t xp = cx + 1 == (uint32_t)g.nx ? 0 : cx + 1;
@@ -315,9 +314,9 @@ __device__ __forceinline__ F3 field_grad(const Grid &g, const float *om,
   const uint32_t zp = cz + 1 == (uint32_t)g.nz ? 0 : cz + 1;
   const uint32_t zm = cz == 0 ? g.nz - 1 : cz - 1;
   F3 r;
-  r.x = 0.5f * (om[cell_index(g, xp, cy, cz)] - om[cell_index(g, xm, cy, cz)]);
-  r.y = 0.5f * (om[cell_index(g, cx, yp, cz)] - om[cell_index(g, cx, ym, cz)]);
-  r.z = 0.5f * (om[cell_index(g, cx, cy, zp)] - om[cell_index(g, cx, cy, zm)]);
+  r.x = 0.5f * (field_at(omega, pl, cell_index(g, xp, cy, cz)) - field_at(omega, pl, cell_index(g, xm, cy, cz)));
+  r.y = 0.5f * (field_at(omega, pl, cell_index(g, cx, yp, cz)) - field_at(omega, pl, cell_index(g, cx, ym, cz)));
+  r.z = 0.5f * (field_at(omega, pl, cell_index(g, cx, cy, zp)) - field_at(omega, pl, cell_index(g, cx, cy, zm)));
   return r;
 }
 
@@ -361,7 +360,7 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
     const F3 r = sel(odd, r1, r0);
     const Rand4 w = odd ? wa1 : wa0;
     const float u = uniform01(odd ? wb1.x : wb0.x);
-    const float *om = a.omega + ((odd ? b1 : b0) ? a.grid.n_cells : 0u);
+    const uint32_t pl = (odd ? b1 : b0) ? a.grid.n_cells : 0u;
 
     bool acc = false;
     uint32_t co = 0, cn = 0;
@@ -375,7 +374,7 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
       float xi0, xi1, xi2, xi3;
       box_muller(w.x, w.y, xi0, xi1);
       box_muller(w.z, w.w, xi2, xi3);
-      const F3 g_old = field_grad(a.grid, om, ox, oy, oz);
+      const F3 g_old = field_grad(a.grid, a.omega, pl, ox, oy, oz);
       const F3 f_old = {-a.k0 * (wl * el.x + wr * er.x) - a.inv_nref * g_old.x,
                         -a.k0 * (wl * el.y + wr * er.y) - a.inv_nref * g_old.y,
                         -a.k0 * (wl * el.z + wr * er.z) - a.inv_nref * g_old.z};
@@ -387,7 +386,7 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
       cn = cell_index(a.grid, nx_, ny_, nz_);
       // force at the trial position with the same bonded neighbours; the
       // field gradient is constant inside a cell
-      const F3 g_new = cn == co ? g_old : field_grad(a.grid, om, nx_, ny_, nz_);
+      const F3 g_new = cn == co ? g_old : field_grad(a.grid, a.omega, pl, nx_, ny_, nz_);
       const F3 d = {rn.x - r.x, rn.y - r.y, rn.z - r.z};
       const F3 nl = {rn.x - left.x, rn.y - left.y, rn.z - left.z};
       const F3 nr = {rn.x - right.x, rn.y - right.y, rn.z - right.z};
@@ -401,8 +400,8 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
       const float qx = wl * (2.0f * el.x + d.x) + wr * (2.0f * er.x + d.x);
       const float qy = wl * (2.0f * el.y + d.y) + wr * (2.0f * er.y + d.y);
       const float qz = wl * (2.0f * el.z + d.z) + wr * (2.0f * er.z + d.z);
-      const float w_old = om[co];
-      const float w_new = cn == co ? w_old : om[cn];
+      const float w_old = field_at(a.omega, pl, co);
+      const float w_new = cn == co ? w_old : field_at(a.omega, pl, cn);
       const float d_e = a.half_k0 * (d.x * qx + d.y * qy + d.z * qz) + (w_new - w_old) * a.inv_nref;
       const float lr = log_q - d_e;
       acc = lr >= 0.0f || u < __expf(lr);
@@ -448,12 +447,12 @@ struct MixArgs {
 // needs the bond vectors, so the two sets are handled one after the other.
 // ---------------------------------------------------------------------------
 // One wave's chains; act/tmp are the wave's two LDS activation tiles (the
-// network output z reuses tmp), s_std the block's LDS copy of the
-// standardisation constants.  Returns through cnt the wave's accepted local
+// network output z reuses tmp), stdz the network's standardisation constants
+// (shift[64] then scale[64]).  Returns through cnt the wave's accepted local
 // moves, accepted learned moves and learned attempts.
 template <bool COUNT64, bool VEC2>
 __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx, const LaneMap &m,
-                                           __bf16 *act, __bf16 *tmp, const float *s_std,
+                                           __bf16 *act, __bf16 *tmp, const float *stdz,
                                            uint32_t cnt[3]) {
   float *zb = reinterpret_cast<float *>(tmp);
   __bf16 *row = act + m.lane * kActStride;
@@ -492,7 +491,7 @@ __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx
     const Rand4 wb = odd ? wb1 : wb0;
     const bool is_b = odd ? b1 : b0;
     const bool learned = moving && uniform01(wb.y) < mx.p_learn;
-    const float *om = a.omega + (is_b ? a.grid.n_cells : 0u);
+    const uint32_t pl = is_b ? a.grid.n_cells : 0u;
     const F3 zero3 = F3{0.f, 0.f, 0.f};
 
     F3 rn;
@@ -501,7 +500,7 @@ __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx
     bool net_bad = false;
     if (__ballot(learned) != 0ull) {
       w_old = features_to_row(a.grid, a.omega, is_b, r, has_l ? left - r : zero3,
-                              has_r ? right - r : zero3, s_std, row, co);
+                              has_r ? right - r : zero3, stdz, row, co);
       wave_forward(mx.net, act, tmp, zb);
       float mu[3], sig[3], lsig[3];
       head(zb + m.lane * 8, mx.head, mu, sig, lsig);
@@ -514,7 +513,7 @@ __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx
                      fmaf(a.step, uniform11(w.z), r.z)};
       rn = sel(learned, tl, tp);
       w_new = features_to_row(a.grid, a.omega, is_b, rn, has_l ? left - rn : zero3,
-                              has_r ? right - rn : zero3, s_std, row, cn);
+                              has_r ? right - rn : zero3, stdz, row, cn);
       wave_forward(mx.net, act, tmp, zb);
       float mun[3], sign[3], lsign[3];
       head(zb + m.lane * 8, mx.head, mun, sign, lsign);
@@ -536,8 +535,8 @@ __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx
               fmaf(a.step, uniform11(w.z), r.z)};
       co = cell_of(a.grid, r.x, r.y, r.z);
       cn = cell_of(a.grid, rn.x, rn.y, rn.z);
-      w_old = om[co];
-      w_new = cn == co ? w_old : om[cn];
+      w_old = field_at(a.omega, pl, co);
+      w_new = cn == co ? w_old : field_at(a.omega, pl, cn);
     }
     const F3 d = rn - r;
     const F3 q = wl * (2.0f * (r - left) + d) + wr * (2.0f * (r - right) + d);
