@@ -278,7 +278,7 @@ int32_t soma_init_positions(const soma_config *cfg, float *pos, void *stream);
  * Features of a bead: its own type's field at the 27 cells around its cell
  * ((dz,dy,dx) in -1..1, dz slowest), the other type's field at the same cells,
  * then the bond vectors r_{i-1} - r and r_{i+1} - r (zero where absent).
- * Network: SiLU, 60 -> 64 -> 64 -> 6, evaluated with BF16 inputs and weights
+ * Network: ReLU, 60 -> 64 -> 64 -> 6, evaluated with BF16 inputs and weights
  * and FP32 accumulation on the matrix cores. */
 
 /* Bytes of a prepared network (see soma_prepare_net). */

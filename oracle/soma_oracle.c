@@ -531,7 +531,7 @@ double orc_field_energy(const float *pos, uint32_t n_chains, uint32_t n,
 /* (cells in (dz, dy, dx) order, each -1..1, periodic), then the bond vectors */
 /* r_{i-1} - r and r_{i+1} - r (zero where the neighbour does not exist).     */
 /* Standardised per feature: (f - shift) * scale.                             */
-/* Network: h1 = silu(W1 x + b1), h2 = silu(W2 h1 + b2), z = W3 h2 + b3       */
+/* Network: h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), z = W3 h2 + b3       */
 /* (60 -> 64 -> 64 -> 6).  Head: mu_d = m tanh(z_d / m),                      */
 /* log sigma_d = lo + (hi - lo) sigmoid(z_{3+d}).                             */
 /* Proposal: r' = r + mu(r) + sigma(r) xi, xi ~ N(0,1)^3.                     */
@@ -571,11 +571,8 @@ float orc_bf16(float x) {
   return x;
 }
 
-static double orc_silu(double a) { return a / (1.0 + exp(-a)); }
-static double orc_dsilu(double a) {
-  double s = 1.0 / (1.0 + exp(-a));
-  return s * (1.0 + a * (1.0 - s));
-}
+static double orc_relu(double a) { return a > 0.0 ? a : 0.0; }
+static double orc_drelu(double a) { return a > 0.0 ? 1.0 : 0.0; }
 
 /* cache layout: x[60] a1[64] h1[64] a2[64] h2[64] */
 void orc_mlp_forward(const float *p, const double *f, int bf16, double *z,
@@ -590,14 +587,14 @@ void orc_mlp_forward(const float *p, const double *f, int bf16, double *z,
     double acc = 0.0;
     for (int k = 0; k < ORC_NF; ++k) acc += ORC_W(ORC_P_W1, m * ORC_NF + k) * x[k];
     a1[m] = acc + p[ORC_P_B1 + m];
-    h1[m] = orc_silu(a1[m]);
+    h1[m] = orc_relu(a1[m]);
     if (bf16) h1[m] = orc_bf16((float)h1[m]);
   }
   for (int m = 0; m < ORC_NH; ++m) {
     double acc = 0.0;
     for (int k = 0; k < ORC_NH; ++k) acc += ORC_W(ORC_P_W2, m * ORC_NH + k) * h1[k];
     a2[m] = acc + p[ORC_P_B2 + m];
-    h2[m] = orc_silu(a2[m]);
+    h2[m] = orc_relu(a2[m]);
     if (bf16) h2[m] = orc_bf16((float)h2[m]);
   }
   for (int o = 0; o < ORC_NO; ++o) {
@@ -632,7 +629,7 @@ void orc_mlp_backward(const float *p, const double *cache, const double *dz,
   for (int k = 0; k < ORC_NH; ++k) {
     double s = 0.0;
     for (int o = 0; o < ORC_NO; ++o) s += ORC_W(ORC_P_W3, o * ORC_NH + k) * dz[o];
-    d2[k] = s * orc_dsilu(a2[k]);
+    d2[k] = s * orc_drelu(a2[k]);
   }
   for (int m = 0; m < ORC_NH; ++m) {
     grad[ORC_P_B2 + m] += d2[m];
@@ -641,7 +638,7 @@ void orc_mlp_backward(const float *p, const double *cache, const double *dz,
   for (int k = 0; k < ORC_NH; ++k) {
     double s = 0.0;
     for (int m = 0; m < ORC_NH; ++m) s += ORC_W(ORC_P_W2, m * ORC_NH + k) * d2[m];
-    d1[k] = s * orc_dsilu(a1[k]);
+    d1[k] = s * orc_drelu(a1[k]);
   }
   for (int m = 0; m < ORC_NH; ++m) {
     grad[ORC_P_B1 + m] += d1[m];

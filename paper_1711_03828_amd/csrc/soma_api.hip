@@ -649,7 +649,7 @@ uint64_t soma_net_bytes(void) { return sizeof(soma::NetDev); }
 int32_t soma_prepare_net(const float *params, void *net, void *stream) {
   if (!params || !net) return fail(SOMA_E_INVAL, "NULL buffer");
   if (!aligned(net, 16)) return fail(SOMA_E_INVAL, "net buffer must be 16-byte aligned");
-  hipLaunchKernelGGL(soma::net_prepare_kernel, dim3(1), dim3(256), 0,
+  hipLaunchKernelGGL(soma::net_prepare_kernel, dim3(soma::kNetPrepareBlocks), dim3(256), 0,
                      reinterpret_cast<hipStream_t>(stream), params,
                      reinterpret_cast<soma::NetDev *>(net));
   LAUNCH_TRY();
@@ -864,7 +864,7 @@ int32_t soma_train_step(const float *features, const float *targets, uint32_t n,
   float *partials = reinterpret_cast<float *>(ws + align_up(sizeof(soma::NetDev)));
   float *lossp = reinterpret_cast<float *>(ws + align_up(sizeof(soma::NetDev)) +
                                            align_up((uint64_t)waves * soma::kPSize * 4ull));
-  hipLaunchKernelGGL(soma::net_prepare_kernel, dim3(1), dim3(256), 0, s, params, net);
+  hipLaunchKernelGGL(soma::net_prepare_kernel, dim3(soma::kNetPrepareBlocks), dim3(256), 0, s, params, net);
   LAUNCH_TRY();
   soma::TrainArgs ta;
   ta.net = net;
@@ -895,7 +895,9 @@ int32_t soma_train_step(const float *features, const float *targets, uint32_t n,
   aa.apply = o->apply ? 1 : 0;
   aa.grad_out = grad_out;
   aa.loss_out = loss_out;
-  hipLaunchKernelGGL(soma::mlp_adam_kernel, dim3((soma::kPSize + 255) / 256), dim3(256), 0, s, aa);
+  hipLaunchKernelGGL(soma::mlp_adam_kernel,
+                     dim3((soma::kPSize + soma::kAdamParamsPerBlock - 1) / soma::kAdamParamsPerBlock),
+                     dim3(256), 0, s, aa);
   LAUNCH_TRY();
   return SOMA_OK;
 }

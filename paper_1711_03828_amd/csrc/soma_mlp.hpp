@@ -1,7 +1,7 @@
 // soma_mlp.hpp -- the learned proposal's network on the gfx950 matrix cores.
 //
 // A learned move proposes r' = r + mu(r) + sigma(r) xi from a small network
-// (60 -> 64 -> 64 -> 6, SiLU) fed with the fields around the bead and its two
+// (60 -> 64 -> 64 -> 6, ReLU) fed with the fields around the bead and its two
 // bond vectors, and is accepted by Metropolis-Hastings with the exact ratio
 // of the Gaussian proposal densities, so the sampled distribution of the
 // method (Sec. 2.2) is unchanged; the move is an addition to the paper's local
@@ -43,38 +43,43 @@ struct HeadArgs {
   float m_max, lo, hi;         // mu = m tanh(z/m); log sigma = lo + (hi-lo) sigmoid(z)
 };
 
+// One thread per weight index i < 64*64 (launched with kNetPrepareBlocks
+// blocks of 256 threads).
+constexpr uint32_t kNetPrepareBlocks = 16;
+
 __global__ __launch_bounds__(256) void net_prepare_kernel(const float *__restrict__ p,
                                                           NetDev *__restrict__ net) {
-  for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= 64 * 64) return;
+  if (i < 64) {
     net->shift[i] = i < kNF ? p[kPShift + i] : 0.0f;
     net->scale[i] = i < kNF ? p[kPScale + i] : 0.0f;
     net->b1[i] = p[kPB1 + i];
     net->b2[i] = p[kPB2 + i];
     if (i < 16) net->b3[i] = i < kNO ? p[kPB3 + i] : 0.0f;
   }
-  for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) {
-    const int o = i >> 6, k = i & 63;
-    net->w1[i] = (__bf16)(k < kNF ? p[kPW1 + o * kNF + k] : 0.0f);
-    net->w2[i] = (__bf16)p[kPW2 + o * kNH + k];
-    net->w2t[i] = (__bf16)p[kPW2 + k * kNH + o];
-    if (o < 16) net->w3[i] = (__bf16)(o < kNO ? p[kPW3 + o * kNH + k] : 0.0f);
-  }
-  for (int i = threadIdx.x; i < 64 * 32; i += blockDim.x) {
-    const int h = i >> 5, k = i & 31;
-    net->w3t[i] = (__bf16)(k < kNO ? p[kPW3 + k * kNH + h] : 0.0f);
+  const int o = i >> 6, k = i & 63;
+  net->w1[i] = (__bf16)(k < kNF ? p[kPW1 + o * kNF + k] : 0.0f);
+  net->w2[i] = (__bf16)p[kPW2 + o * kNH + k];
+  net->w2t[i] = (__bf16)p[kPW2 + k * kNH + o];
+  if (o < 16) net->w3[i] = (__bf16)(o < kNO ? p[kPW3 + o * kNH + k] : 0.0f);
+  if (i < 64 * 32) {
+    const int h = i >> 5, kk = i & 31;
+    net->w3t[i] = (__bf16)(kk < kNO ? p[kPW3 + kk * kNH + h] : 0.0f);
   }
 }
 
-// SiLU a * sigmoid(a); the reciprocal is the hardware approximation (1 ulp),
-// ample for an activation that is rounded to bfloat16 next.
+// Hardware reciprocal (1 ulp): ample where the result feeds a bfloat16 tile
+// or a Metropolis-Hastings log ratio.
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ float silu(float a) { return a * fast_rcp(1.0f + __expf(-a)); }
+// Hidden activation: ReLU (one VALU operation per unit).
+__device__ __forceinline__ float relu(float a) { return fmaxf(a, 0.0f); }
 
 __device__ __forceinline__ bf16x8 lds_b8(const __bf16 *p) {
   return *reinterpret_cast<const bf16x8 *>(p);
 }
 
-// One fully connected layer of 64 outputs with SiLU for the wave's 64
+// One fully connected layer of 64 outputs with ReLU for the wave's 64
 // samples: inputs from LDS tile `in`, outputs to LDS tile `out`.  Output
 // units are produced 16 at a time (one MFMA row tile), so only 16
 // accumulators per lane are live.
@@ -102,7 +107,7 @@ __device__ __forceinline__ void hidden_layer(const __bf16 *__restrict__ w,
     for (int t = 0; t < 4; ++t) {
       bf16x4 v;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) v[r] = (__bf16)silu(acc[t][r] + bias[unit + r]);
+      for (int r = 0; r < 4; ++r) v[r] = (__bf16)relu(acc[t][r] + bias[unit + r]);
       *reinterpret_cast<bf16x4 *>(out + (16 * t + col) * kActStride + unit) = v;
     }
   }

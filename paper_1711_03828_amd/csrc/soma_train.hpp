@@ -30,10 +30,7 @@ struct TrainArgs {
 
 __device__ __forceinline__ bf16x8 lds8(const __bf16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
 
-__device__ __forceinline__ float dsilu(float a) {
-  const float s = fast_rcp(1.0f + __expf(-a));
-  return s * (1.0f + a * (1.0f - s));
-}
+__device__ __forceinline__ float drelu(float a) { return a > 0.0f ? 1.0f : 0.0f; }
 
 // out[mt][t] += W[16 mt + row][k] * act[sample][k] over K = 64 (two blocks):
 // rows of W (global, [64][64] bf16), act sample-major LDS [64][72].
@@ -120,7 +117,7 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const TrainArgs a) {
         for (int r = 0; r < 4; ++r) {
           const int u = 16 * mt + 4 * g + r, sm = 16 * t + col;
           const float pre = acc[mt][t][r] + net->b1[u];
-          const __bf16 h = (__bf16)silu(pre);
+          const __bf16 h = (__bf16)relu(pre);
           a1_f[sm * 64 + u] = pre;
           h1_s[sm * kActStride + u] = h;
           h1_t[u * kTStride + sm] = h;
@@ -136,7 +133,7 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const TrainArgs a) {
         for (int r = 0; r < 4; ++r) {
           const int u = 16 * mt + 4 * g + r, sm = 16 * t + col;
           const float pre = acc[mt][t][r] + net->b2[u];
-          const __bf16 h = (__bf16)silu(pre);
+          const __bf16 h = (__bf16)relu(pre);
           a2_f[sm * 64 + u] = pre;
           h2_s[sm * kActStride + u] = h;
           h2_t[u * kTStride + sm] = h;
@@ -180,7 +177,7 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const TrainArgs a) {
       for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
       gb3[o] += v;
     }
-    // delta2 = (W3^T dz) * silu'(a2)
+    // delta2 = (W3^T dz) * relu'(a2)
     zero_acc(acc);
     {
       // K = 32 (6 used): one block; B operand from dz_s rows
@@ -202,13 +199,13 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const TrainArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int u = 16 * mt + 4 * g + r, sm = 16 * t + col;
-          const float d = acc[mt][t][r] * dsilu(a2_f[sm * 64 + u]);
+          const float d = acc[mt][t][r] * drelu(a2_f[sm * 64 + u]);
           gb2[mt][r] += d;
           const __bf16 db = (__bf16)d;
           d2_s[sm * kActStride + u] = db;
           d2_t[u * kTStride + sm] = db;
         }
-    // delta1 = (W2^T delta2) * silu'(a1)
+    // delta1 = (W2^T delta2) * relu'(a1)
     zero_acc(acc);
     mm_units(net->w2t, 64, 4, 2, d2_s, acc);
 #pragma unroll
@@ -218,7 +215,7 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const TrainArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int u = 16 * mt + 4 * g + r, sm = 16 * t + col;
-          const float d = acc[mt][t][r] * dsilu(a1_f[sm * 64 + u]);
+          const float d = acc[mt][t][r] * drelu(a1_f[sm * 64 + u]);
           gb1[mt][r] += d;
           d1_t[u * kTStride + sm] = (__bf16)d;
         }
@@ -280,19 +277,38 @@ struct AdamArgs {
   float *loss_out;       // may be null
 };
 
-// Mean gradient over the batch (fixed-order sum of the partials) and the Adam
-// step on the FP32 master parameters (standardisation constants untouched).
+// Mean gradient over the batch and the Adam step on the FP32 master
+// parameters (standardisation constants untouched).  A block covers 64
+// parameters; its four waves sum the partials of waves q, q+4, q+8, ... (q the
+// wave in the block), eight loads in flight, and the four sums are combined
+// in a fixed order: the result does not depend on timing.
+constexpr uint32_t kAdamParamsPerBlock = 64;
+
 __global__ __launch_bounds__(256) void mlp_adam_kernel(const AdamArgs a) {
-  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p == 0 && a.loss_out) {
+  __shared__ float s_part[4][kAdamParamsPerBlock];
+  const uint32_t lane = threadIdx.x & 63u, q = threadIdx.x >> 6;
+  const uint32_t p = blockIdx.x * kAdamParamsPerBlock + lane;
+  float gsum = 0.0f;
+  if (p < (uint32_t)kPSize) {
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    uint32_t w = q;
+    for (; w + 28u < a.waves; w += 32u) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += a.partials[(size_t)(w + 4u * u) * kPSize + p];
+    }
+    for (; w < a.waves; w += 4u) acc[0] += a.partials[(size_t)w * kPSize + p];
+    gsum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  }
+  s_part[q][lane] = gsum;
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 64 && a.loss_out) {
     float l = 0.0f;
     for (uint32_t w = 0; w < a.waves; ++w) l += a.loss_partials[w];
     *a.loss_out = l / (float)a.n;
   }
-  if (p >= (uint32_t)kPSize) return;
-  float gsum = 0.0f;
-  for (uint32_t w = 0; w < a.waves; ++w) gsum += a.partials[(size_t)w * kPSize + p];
-  const float grad = gsum / (float)a.n;
+  if (q != 0 || p >= (uint32_t)kPSize) return;
+  const float grad = ((s_part[0][lane] + s_part[1][lane]) + (s_part[2][lane] + s_part[3][lane])) /
+                     (float)a.n;
   if (a.grad_out) a.grad_out[p] = grad;
   if (!a.apply || p < (uint32_t)kPW1 || p >= (uint32_t)(kPB3 + kNO)) return;
   const float m = a.beta1 * a.m[p] + (1.0f - a.beta1) * grad;
