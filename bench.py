@@ -118,7 +118,8 @@ def _re_vectors(melt, n):
     return (x[:, -1] - x[:, 0]).double()
 
 
-def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: int):
+def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: int,
+                equil_cycles: int):
     """Plain vs learned proposal on the 262,144-chain melt (96^3 cells, chiN 25).
 
     1. Training data from the plain sampler: 10 rounds of 2^20 random beads,
@@ -126,10 +127,11 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
        (10,485,760 samples), collected and trained on the device.
     2. Bead-moves/s of both samplers on the full melt (HIP events, graph-replayed
        SCMF cycles).
-    3. tau_int of the end-to-end vectors (Sokal window) on a 4096-chain melt of the
-       same density and chemistry (24^3 cells), from frames every `frame_cycles`
-       cycles (plain: plain_mult times as many), after equilibration with the
-       learned sampler; uncorrelated
+    3. The melt equilibrated with the learned sampler for `equil_cycles` cycles,
+       the network fine-tuned on plain trajectories from that state (4 x 2^20
+       samples), then tau_int (Sokal window) of the end-to-end vectors of every
+       16th chain from frames every `frame_cycles` cycles (plain: `plain_mult`
+       times as many cycles between frames), learned run first.  Uncorrelated
        samples/s = n_chains * cycles/s / (2 tau_int), cycles/s from step 2.
     """
     import torch
@@ -171,34 +173,47 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
     obs = melt.observables()
     out["learned"]["acceptance"] = obs.accepted[2] / max(1, obs.attempted[2])
     out["plain"]["acceptance"] = obs.accepted[0] / max(1, obs.attempted[0])
-    melt.close()
 
-    sub_w = synth.scaled(w, 4096, (24, 24, 24))
-    sub = Melt(make_config(sub_w, p_learn=p_learn))
-    sub.set_proposal(params)
-    sub.capture_cycle(frame_cycles, C.SOMA_MOVE_MIXED)
-    sub.run_cycle(max(1, 20000 // frame_cycles))       # equilibrate (learned sampler)
+    # equilibrate the full melt with the learned sampler, fine-tune on plain
+    # trajectories from that state, then the tau_int runs on the full melt
+    melt.capture_cycle(100, C.SOMA_MOVE_MIXED)
+    melt.run_cycle(max(1, equil_cycles // 100))
+    feats, disp = learned.collect(melt, 1 << 20, 128, 4, first_round=1000)
+    tune = learned.Trainer(params, lr=1e-3)
+    tl = tune.run(feats, disp, steps=2000, batch=8192, loss_every=500)
+    del feats, disp
+    melt.set_proposal(params)
+    out["training"]["fine_tune"] = {"samples": 4 << 20, "adam_steps": 2000,
+                                    "loss_first": tl[0], "loss_last": tl[-1],
+                                    "after_learned_cycles": equil_cycles}
+    stride = 16                              # end-to-end vectors of every 16th chain
     for name, kind, mult in (("learned", C.SOMA_MOVE_MIXED, 1),
                              ("plain", C.SOMA_MOVE_LOCAL, plain_mult)):
-        sub.capture_cycle(frame_cycles * mult, kind)
+        melt.capture_cycle(frame_cycles * mult, kind)
         n_frames = sub_frames
-        re = torch.empty((n_frames, sub_w.n_chains, 3), dtype=torch.float64, device="cuda")
+        o0 = melt.observables()
+        re = torch.empty((n_frames, w.n_chains // stride, 3), dtype=torch.float32,
+                         device="cuda")
         for f in range(n_frames):
-            sub.run_cycle(1)
-            re[f] = _re_vectors(sub, 32)
+            melt.run_cycle(1)
+            re[f] = _re_vectors(melt, 32)[::stride].float()
+        o1 = melt.observables()
         series = re.reshape(n_frames, -1).cpu().numpy()
         tau_frames, window = analysis.tau_int(series)
         step = frame_cycles * mult
         tau = tau_frames * step
-        re2 = float((re ** 2).sum(-1).mean()) / w.re_cells ** 2
+        re2 = float((re.double() ** 2).sum(-1).mean()) / w.re_cells ** 2
+        k = 2 if kind == C.SOMA_MOVE_MIXED else 0
         out[name].update({"tau_int_cycles": tau, "window_frames": window,
                           "frames": n_frames, "cycles_per_frame": step,
                           "re2_over_re02": re2,
+                          "acceptance_tau_run": (o1.accepted[k] - o0.accepted[k]) /
+                                                max(1, o1.attempted[k] - o0.attempted[k]),
                           "uncorrelated_samples_per_s":
                               w.n_chains * rates[name] / (2.0 * tau)})
         print(f"# {name}: tau_int {tau:.1f} cycles (window {window} frames), "
               f"<Re^2>/Re0^2 {re2:.4f}", file=sys.stderr, flush=True)
-    sub.close()
+    melt.close()
     out["gain_uncorrelated_samples_per_s"] = (out["learned"]["uncorrelated_samples_per_s"] /
                                               out["plain"]["uncorrelated_samples_per_s"])
     return out
@@ -249,6 +264,127 @@ def batched_leg(cycles: int):
             "acceptance": acc}
 
 
+def blend_leg(rate_cycles: int, tau_frames: int, frame_cycles: int, plain_mult: int,
+              equil_cycles: int, tau_scale: float):
+    """Ternary blend replicas (32 melts of A16B16 diblocks with A16 and B16
+    homopolymers, chiN 15..35): one network per species trained on the blend's
+    own plain trajectories, used inside graph-captured batched cycles.
+
+    Rates at full size (about 4.2e7 beads); tau_int of the diblocks' end-to-end
+    vectors and the S(q) peak shell of every replica on a copy scaled by
+    `tau_scale` in chains (same density and chemistry)."""
+    import numpy as np
+    import torch
+
+    from paper_1711_03828_amd import analysis, learned
+    from paper_1711_03828_amd import soma as C
+    from paper_1711_03828_amd.melt import Batch, Melt, make_config
+
+    def build(reps):
+        melts = [Melt(make_config(w, replica=i, p_learn=0.9)) for i, w in enumerate(reps)]
+        return melts, Batch(melts)
+
+    out = {}
+    # training data from the full-size blend: per species, 2^15 beads per replica and round
+    reps = synth.c5_replicas()
+    melts, batch = build(reps)
+    batch.cycle(20)
+    n_round, rounds, lag = 1 << 15, 4, 128
+    data = {sp: (torch.empty((len(melts) * rounds * n_round, 60), device="cuda"),
+                 torch.empty((len(melts) * rounds * n_round, 3), device="cuda")) for sp in range(3)}
+    r0 = torch.empty((len(melts), 3, n_round, 3), device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    batch.capture_cycle(lag, C.SOMA_MOVE_LOCAL)
+    for k in range(rounds):
+        for i, m in enumerate(melts):
+            for sp in range(3):
+                off = ((k * len(melts)) + i) * n_round
+                C.soma_collect_training(m.handle, n_round, k, 0, data[sp][0][off].data_ptr(),
+                                        r0[i, sp].data_ptr(), 0, 0, s, species=sp)
+        batch.run_cycle(1)
+        for i, m in enumerate(melts):
+            for sp in range(3):
+                off = ((k * len(melts)) + i) * n_round
+                C.soma_collect_training(m.handle, n_round, k, 1, 0, r0[i, sp].data_ptr(),
+                                        data[sp][1][off].data_ptr(), 0, s, species=sp)
+    nets = []
+    for sp in range(3):
+        params = learned.init_params(data[sp][0], seed=10 + sp)
+        losses = learned.train(params, data[sp][0], data[sp][1], steps=2000, batch=8192,
+                               loss_every=500)
+        nets.append(params)
+        out[f"species{sp}_loss"] = [losses[0], losses[-1]]
+    del data
+    for m in melts:
+        for sp in range(3):
+            m.set_proposal(nets[sp], species=sp)
+    n_beads = sum(w.n_beads for w in reps)
+    stream = torch.cuda.current_stream()
+    for name, kind in (("plain", C.SOMA_MOVE_LOCAL), ("learned", C.SOMA_MOVE_MIXED)):
+        batch.capture_cycle(10, kind)
+        batch.run_cycle(1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        batch.run_cycle(rate_cycles // 10)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / (rate_cycles // 10 * 10)
+        out[name] = {"ms_per_cycle": ms, "bead_moves_per_s": n_beads * 1e3 / ms}
+    out["workload"] = f"{len(reps)} blend replicas, {n_beads} beads"
+    batch.close()
+    for m in melts:
+        m.close()
+    # tau_int and S(q) peaks on the scaled copy
+    sreps = synth.c5_replicas(scale=tau_scale)
+    melts, batch = build(sreps)
+    for m in melts:
+        for sp in range(3):
+            m.set_proposal(nets[sp], species=sp)
+    batch.capture_cycle(frame_cycles, C.SOMA_MOVE_MIXED)
+    batch.run_cycle(max(1, equil_cycles // frame_cycles))
+    ws = [torch.empty(C.soma_sq_workspace_bytes(m.handle), dtype=torch.uint8, device="cuda")
+          for m in melts]
+    for name, kind, mult in (("learned", C.SOMA_MOVE_MIXED, 1), ("plain", C.SOMA_MOVE_LOCAL,
+                                                                  plain_mult)):
+        batch.capture_cycle(frame_cycles * mult, kind)
+        series = []
+        for f in range(tau_frames):
+            batch.run_cycle(1)
+            series.append(torch.cat([_re_vectors_species(m, w) for m, w in zip(melts, sreps)]))
+        x = torch.stack(series).reshape(tau_frames, -1).cpu().numpy()
+        tau, window = analysis.tau_int(x)
+        tau *= frame_cycles * mult
+        peaks = []
+        for m, w, wsb in zip(melts, sreps, ws):
+            sq = torch.empty(w.n_cells, dtype=torch.float64, device="cuda")
+            C.soma_structure_factor(m.handle, wsb.data_ptr(), wsb.numel(), sq.data_ptr(), s)
+            torch.cuda.synchronize()
+            _, mean, _, peak = C.soma_sq_shells(sq.cpu().numpy(), w.grid, 16)
+            peaks.append(int(peak))
+        out[name].update({"tau_int_cycles": tau, "window_frames": window,
+                          "uncorrelated_samples_per_s":
+                              sum(w.species[0].n_chains for w in reps) * 1e3 /
+                              out[name]["ms_per_cycle"] / (2.0 * tau),
+                          "sq_peak_shells": peaks})
+        print(f"# blend {name}: tau_int {tau:.1f} cycles, S(q) peaks {peaks[:8]}",
+              file=sys.stderr, flush=True)
+    out["gain_uncorrelated_samples_per_s"] = (out["learned"]["uncorrelated_samples_per_s"] /
+                                              out["plain"]["uncorrelated_samples_per_s"])
+    out["tau_workload"] = (f"the same 32 replicas with {tau_scale:g} of the chains "
+                           f"({sum(w.n_beads for w in sreps)} beads); diblock end-to-end vectors")
+    batch.close()
+    for m in melts:
+        m.close()
+    return out
+
+
+def _re_vectors_species(melt, w):
+    """End-to-end vectors of the first species' chains (the diblocks)."""
+    sp = w.species[0]
+    x = melt.pos[:sp.n_chains * sp.n].view(sp.n_chains, sp.n, 3)
+    return (x[:, -1] - x[:, 0]).double()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,8 +400,12 @@ def main():
     ap.add_argument("--tau-frames", type=int, default=400, help="frames per tau_int run")
     ap.add_argument("--frame-cycles", type=int, default=50,
                     help="cycles between frames of the learned run")
-    ap.add_argument("--plain-frame-mult", type=int, default=16,
+    ap.add_argument("--equil-cycles", type=int, default=20000,
+                    help="learned-sampler cycles before the tau_int runs")
+    ap.add_argument("--plain-frame-mult", type=int, default=8,
                     help="the plain run's frames are this many times further apart")
+    ap.add_argument("--blend", action="store_true",
+                    help="also run the ternary-blend batched learned-proposal measurement")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-replica batched measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -354,9 +494,13 @@ def main():
     melt.close()
     if not args.no_learned:
         result["learned_proposal"] = learned_leg(args.p_learn, args.tau_frames,
-                                                 args.frame_cycles, args.plain_frame_mult)
+                                                 args.frame_cycles, args.plain_frame_mult,
+                                                 args.equil_cycles)
     if not args.no_batched:
         result["batched"] = batched_leg(50)
+    if args.blend:
+        result["blend"] = blend_leg(50, args.tau_frames // 2, args.frame_cycles,
+                                    args.plain_frame_mult, args.equil_cycles // 2, 1.0 / 16)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(result), flush=True)

@@ -194,9 +194,22 @@ int32_t soma_check(soma_system *sys, uint32_t *flags, void *stream);
 int32_t soma_get_sweep(const soma_system *sys, uint64_t *sweep);
 int32_t soma_set_sweep(soma_system *sys, uint64_t sweep, void *stream);
 
+/* ---- SCMF cycles -----------------------------------------------------------
+ * soma_cycle runs n_cycles SCMF cycles: the MC sweep of move_kind and the
+ * field refresh of stage 1 (Sec. 2.2).  With soma_set_substeps(sys, k), k > 1,
+ * a cycle sweeps the chains in k interleaved subsets (chains j, j + k, ...)
+ * and refreshes the fields after each subset: every bead still makes one move
+ * per cycle, with the draws of an ordinary sweep, but fewer beads move between
+ * two field refreshes.  Large moves (the learned proposal) make the
+ * quasi-instantaneous field approximation coarser; sub-steps restore it at the
+ * cost of k field refreshes per cycle.  k = 1 (default) is the plain cycle.
+ * Asynchronous.  SOMA_E_INVAL for k outside 1..4096. */
+int32_t soma_set_substeps(soma_system *sys, uint32_t k);
+int32_t soma_cycle(soma_system *sys, uint32_t n_cycles, uint32_t move_kind, void *stream);
+
 /* ---- Captured SCMF cycles ----------------------------------------------
- * soma_capture_cycle records `cycles` SCMF cycles of the system (MC sweep of
- * move_kind, then the field refresh of stage 1, Sec. 2.2), followed by the
+ * soma_capture_cycle records `cycles` SCMF cycles of the system (as soma_cycle,
+ * with the system's sub-steps), followed by the
  * advance of the device sweep counter, into a HIP graph; soma_run_cycle
  * replays it n_launches times on `stream` (asynchronous).  A replay gives the
  * same bits as the same cycles called one by one.  The graph holds the launch
@@ -248,6 +261,10 @@ int32_t soma_batch_set_launch(soma_batch *b, uint32_t mode, uint32_t grid_blocks
 int32_t soma_batch_sweep(soma_batch *b, uint32_t n_sweeps, uint32_t move_kind, void *stream);
 /* Field refresh of every system (asynchronous). */
 int32_t soma_batch_update_fields(soma_batch *b, void *stream);
+/* Cycles of the whole batch (as soma_cycle), with k chain subsets per cycle
+ * (soma_batch_set_substeps copies the re-cut work list: blocking). */
+int32_t soma_batch_set_substeps(soma_batch *b, uint32_t k, void *stream);
+int32_t soma_batch_cycle(soma_batch *b, uint32_t n_cycles, uint32_t move_kind, void *stream);
 /* Captured cycles of the whole batch, as soma_capture_cycle / soma_run_cycle. */
 int32_t soma_batch_capture_cycle(soma_batch *b, uint32_t cycles, uint32_t move_kind);
 int32_t soma_batch_run_cycle(soma_batch *b, uint32_t n_launches, void *stream);

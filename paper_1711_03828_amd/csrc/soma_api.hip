@@ -246,6 +246,7 @@ struct soma_system {
   uint32_t sweep_blocks = 0;  // local-move grid: 0 = one tile per wave, else persistent blocks
   uint64_t mixed_moves = 0;   // bead moves made by mixed sweeps (local or learned)
   uint32_t net_mask = 0;      // species with an installed network (bit per species)
+  uint32_t substeps = 1;      // field refreshes per SCMF cycle (chain subsets)
   unsigned char *ws = nullptr;
   CycleGraph graph;
   ~soma_system() { graph.release(); }
@@ -312,6 +313,9 @@ void sweep_args(soma_system *sys, uint32_t sp, uint32_t kind, soma::SweepArgs &a
   a.replica = c->replica;
   a.set_order = c->set_order;
   a.sweep_ctr = sys->sweep_ctr();
+  a.sub_k = 1;
+  a.sub_j = 0;
+  a.n_sub = S.n_chains;
   mx.net = sys->net(sp);
   mx.head.m_max = c->mu_max;
   mx.head.lo = c->log_sigma_min;
@@ -327,8 +331,13 @@ bool species_vec2(const soma_system *sys, uint32_t sp) {
          aligned(sys->buf.pos + 3 * off, 8);
 }
 
-// One sweep of every species; `off` is added to the device sweep counter.
-int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s, uint32_t off) {
+// Chains sub_j, sub_j + sub_k, ... of a species of n chains.
+uint32_t subset_size(uint32_t n, uint32_t k, uint32_t j) { return n > j ? (n - j + k - 1) / k : 0u; }
+
+// One sweep of chain subset j of k of every species (k = 1: all chains); `off`
+// is added to the device sweep counter.
+int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s, uint32_t off,
+                     uint32_t k = 1, uint32_t j = 0) {
   const soma_config *c = &sys->cfg;
   for (uint32_t sp = 0; sp < c->n_species; ++sp) {
     const soma_species &S = c->species[sp];
@@ -337,8 +346,12 @@ int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s, uint32_t of
     soma::MixArgs mx;
     sweep_args(sys, sp, kind, a, mx);
     a.sweep = off;
+    a.sub_k = k;
+    a.sub_j = j;
+    a.n_sub = subset_size(S.n_chains, k, j);
+    if (a.n_sub == 0) continue;
     const uint64_t chains_per_block = 4ull * a.chains_per_wave;
-    uint64_t blocks = (S.n_chains + chains_per_block - 1) / chains_per_block;
+    uint64_t blocks = (a.n_sub + chains_per_block - 1) / chains_per_block;
     if (kind == SOMA_MOVE_LOCAL && sys->sweep_blocks && sys->sweep_blocks < blocks)
       blocks = sys->sweep_blocks;
     const bool v2 = species_vec2(sys, sp);
@@ -371,6 +384,18 @@ int32_t check_kind(soma_system *sys, uint32_t move_kind) {
     return fail(SOMA_E_INVAL, "smart-MC moves need smc_a > 0");
   if (move_kind != SOMA_MOVE_SMC && !(sys->cfg.local_a < 1.f))
     return fail(SOMA_E_UNSUPPORTED, "local moves need a half-width below one cell");
+  return SOMA_OK;
+}
+
+// One SCMF cycle with sweep offset `off`: for each of the system's k chain
+// subsets, its sweep and then the field refresh (k = 1: sweep, refresh).
+int32_t enqueue_cycle(soma_system *sys, uint32_t kind, hipStream_t s, uint32_t off) {
+  const uint32_t k = sys->substeps;
+  for (uint32_t j = 0; j < k; ++j) {
+    int32_t r = launch_sweep(sys, kind, s, off, k, j);
+    if (!r) r = launch_field(&sys->cfg, sys->d, sys->buf.counts, sys->buf.omega, sys->fpart(), s);
+    if (r) return r;
+  }
   return SOMA_OK;
 }
 
@@ -501,12 +526,33 @@ int32_t soma_capture_cycle(soma_system *sys, uint32_t cycles, uint32_t move_kind
   if (rc) return rc;
   return capture_graph(sys->graph, cycles, move_kind, [&](hipStream_t cs) -> int32_t {
     for (uint32_t i = 0; i < cycles; ++i) {
-      int32_t r = launch_sweep(sys, move_kind, cs, i);
-      if (!r) r = launch_field(&sys->cfg, sys->d, sys->buf.counts, sys->buf.omega, sys->fpart(), cs);
+      const int32_t r = enqueue_cycle(sys, move_kind, cs, i);
       if (r) return r;
     }
     return launch_counter(sys->sweep_ctr(), cycles, 0, 0, cs);
   });
+}
+
+int32_t soma_set_substeps(soma_system *sys, uint32_t k) {
+  if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
+  if (k == 0 || k > 4096) return fail(SOMA_E_INVAL, "substeps must be 1..4096");
+  sys->substeps = k;
+  return SOMA_OK;
+}
+
+int32_t soma_cycle(soma_system *sys, uint32_t n_cycles, uint32_t move_kind, void *stream) {
+  if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
+  int32_t rc = check_kind(sys, move_kind);
+  if (rc || n_cycles == 0) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (uint32_t i = 0; i < n_cycles; ++i) {
+    rc = enqueue_cycle(sys, move_kind, s, i);
+    if (rc) return rc;
+  }
+  rc = launch_counter(sys->sweep_ctr(), n_cycles, 0, 0, s);
+  if (rc) return rc;
+  sys->count_sweeps(move_kind, n_cycles);
+  return SOMA_OK;
 }
 
 int32_t soma_run_cycle(soma_system *sys, uint32_t n_launches, void *stream) {
@@ -921,6 +967,7 @@ struct soma_batch {
   uint32_t **d_ctrs = nullptr;
   uint32_t n_items = 0, c64 = 0, v2 = 1;
   uint32_t mode = 0, grid_blocks = 0;  // launch shape (results do not depend on it)
+  uint32_t substeps = 1;                // chain subsets per cycle (field refresh after each)
   CycleGraph graph;
   ~soma_batch() { graph.release(); }
 };
@@ -964,9 +1011,25 @@ int32_t batch_segments(soma_system *const *systems, uint32_t n, uint64_t *n_segs
   return SOMA_OK;
 }
 
-uint32_t items_of(const soma::SweepArgs &a) {
+// Items (blocks of four wave tiles) of one segment when its chains are split
+// into k subsets: enough for the largest subset.
+uint32_t items_of(const soma::SweepArgs &a, uint32_t k) {
   const uint32_t per = 4u * a.chains_per_wave;
-  return (a.n_chains + per - 1u) / per;
+  const uint32_t n = (a.n_chains + k - 1u) / k;
+  return (n + per - 1u) / per;
+}
+
+// Segment prefix of the work list for the batch's current subset count.
+int32_t batch_items(soma_batch *b) {
+  b->seg_first.assign(1, 0u);
+  uint64_t items = 0;
+  for (const soma::BatchSeg &seg : b->segs[0]) {
+    items += items_of(seg.a, b->substeps);
+    if (items >= (1ull << 31)) return fail(SOMA_E_UNSUPPORTED, "batch too large");
+    b->seg_first.push_back((uint32_t)items);
+  }
+  b->n_items = (uint32_t)items;
+  return SOMA_OK;
 }
 
 template <bool C64, bool V2>
@@ -979,8 +1042,11 @@ void launch_batch_t(uint32_t kind, dim3 grid, hipStream_t s, const soma::BatchLa
     hipLaunchKernelGGL((soma::batched_sweep_kernel<C64, V2, 0>), grid, dim3(256), 0, s, L);
 }
 
-int32_t launch_batch_sweep(soma_batch *b, uint32_t kind, hipStream_t s, uint32_t off) {
+int32_t launch_batch_sweep(soma_batch *b, uint32_t kind, hipStream_t s, uint32_t off,
+                           uint32_t j) {
   soma::BatchLaunch L;
+  L.sub_k = b->substeps;
+  L.sub_j = j;
   L.segs = b->d_segs[kind];
   L.seg_first = b->d_seg_first;
   L.n_segs = (uint32_t)b->seg_first.size() - 1u;
@@ -1081,21 +1147,17 @@ int32_t soma_batch_create(soma_system *const *systems, uint32_t n, void *workspa
     }
   std::stable_sort(refs.begin(), refs.end(),
                    [](const Ref &x, const Ref &y) { return x.beads > y.beads; });
-  uint64_t items = 0;
-  b->seg_first.push_back(0);
   for (const Ref &r : refs) {
     soma::BatchSeg seg[3];
     for (uint32_t k = 0; k < 3; ++k) sweep_args(systems[r.s], r.sp, k, seg[k].a, seg[k].mx);
     for (uint32_t k = 0; k < 3; ++k) b->segs[k].push_back(seg[k]);
     if (!species_vec2(systems[r.s], r.sp)) b->v2 = 0;
-    items += items_of(seg[0].a);
-    if (items >= (1ull << 31)) {
-      delete b;
-      return fail(SOMA_E_UNSUPPORTED, "batch too large");
-    }
-    b->seg_first.push_back((uint32_t)items);
   }
-  b->n_items = (uint32_t)items;
+  rc = batch_items(b);
+  if (rc) {
+    delete b;
+    return rc;
+  }
   b->fb_first.push_back(0);
   for (uint32_t i = 0; i < n; ++i) {
     soma_system *x = systems[i];
@@ -1145,10 +1207,11 @@ int32_t soma_batch_sweep(soma_batch *b, uint32_t n_sweeps, uint32_t move_kind, v
   int32_t rc = batch_check_kind(b, move_kind);
   if (rc || n_sweeps == 0) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  for (uint32_t i = 0; i < n_sweeps; ++i) {
-    rc = launch_batch_sweep(b, move_kind, s, i);
-    if (rc) return rc;
-  }
+  for (uint32_t i = 0; i < n_sweeps; ++i)
+    for (uint32_t j = 0; j < b->substeps; ++j) {   // fields fixed: subsets in turn = one sweep
+      rc = launch_batch_sweep(b, move_kind, s, i, j);
+      if (rc) return rc;
+    }
   rc = launch_batch_counter(b, n_sweeps, s);
   if (rc) return rc;
   batch_count(b, move_kind, n_sweeps);
@@ -1166,13 +1229,44 @@ int32_t soma_batch_capture_cycle(soma_batch *b, uint32_t cycles, uint32_t move_k
   const int32_t rc = batch_check_kind(b, move_kind);
   if (rc) return rc;
   return capture_graph(b->graph, cycles, move_kind, [&](hipStream_t cs) -> int32_t {
-    for (uint32_t i = 0; i < cycles; ++i) {
-      int32_t r = launch_batch_sweep(b, move_kind, cs, i);
-      if (!r) r = launch_batch_field(b, cs);
-      if (r) return r;
-    }
+    for (uint32_t i = 0; i < cycles; ++i)
+      for (uint32_t j = 0; j < b->substeps; ++j) {
+        int32_t r = launch_batch_sweep(b, move_kind, cs, i, j);
+        if (!r) r = launch_batch_field(b, cs);
+        if (r) return r;
+      }
     return launch_batch_counter(b, cycles, cs);
   });
+}
+
+int32_t soma_batch_set_substeps(soma_batch *b, uint32_t k, void *stream) {
+  if (!b) return fail(SOMA_E_INVAL, "batch is NULL");
+  if (k == 0 || k > 4096) return fail(SOMA_E_INVAL, "substeps must be 1..4096");
+  b->substeps = k;
+  int32_t rc = batch_items(b);
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemcpyAsync(b->d_seg_first, b->seg_first.data(), b->seg_first.size() * 4,
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));   // the host table must outlive the copy
+  return SOMA_OK;
+}
+
+int32_t soma_batch_cycle(soma_batch *b, uint32_t n_cycles, uint32_t move_kind, void *stream) {
+  if (!b) return fail(SOMA_E_INVAL, "batch is NULL");
+  int32_t rc = batch_check_kind(b, move_kind);
+  if (rc || n_cycles == 0) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (uint32_t i = 0; i < n_cycles; ++i)
+    for (uint32_t j = 0; j < b->substeps; ++j) {
+      rc = launch_batch_sweep(b, move_kind, s, i, j);
+      if (!rc) rc = launch_batch_field(b, s);
+      if (rc) return rc;
+    }
+  rc = launch_batch_counter(b, n_cycles, s);
+  if (rc) return rc;
+  batch_count(b, move_kind, n_cycles);
+  return SOMA_OK;
 }
 
 int32_t soma_batch_run_cycle(soma_batch *b, uint32_t n_launches, void *stream) {
@@ -1317,11 +1411,7 @@ int32_t soma_autotune(soma_system *sys, uint32_t cycles, uint32_t move_kind,
   std::snprintf(kind_s, sizeof kind_s, "sys/k%u/", move_kind);
   return tune(local_shapes, n_shapes, cycles, cache_path, kind_s + system_key(sys), s,
               [&](uint32_t, uint32_t grid) { sys->sweep_blocks = grid; },
-              [&]() -> int32_t {
-                int32_t r = soma_mc_sweep(sys, 1, move_kind, stream);
-                if (!r) r = soma_update_fields(sys, stream);
-                return r;
-              },
+              [&]() -> int32_t { return soma_cycle(sys, 1, move_kind, stream); },
               out);
 }
 
@@ -1342,11 +1432,7 @@ int32_t soma_batch_autotune(soma_batch *b, uint32_t cycles, uint32_t move_kind,
                 b->mode = mode;
                 b->grid_blocks = grid;
               },
-              [&]() -> int32_t {
-                int32_t r = soma_batch_sweep(b, 1, move_kind, stream);
-                if (!r) r = soma_batch_update_fields(b, stream);
-                return r;
-              },
+              [&]() -> int32_t { return soma_batch_cycle(b, 1, move_kind, stream); },
               out);
 }
 

@@ -31,6 +31,7 @@ struct BatchLaunch {
   uint32_t per_xcd;            // items per XCD range (mode 0)
   uint32_t mode;               // 0: XCD ranges; 1: items dealt round-robin
   uint32_t sweep_off;          // offset of this launch within a captured cycle
+  uint32_t sub_k, sub_j;       // chain subset of this launch (see SweepArgs)
 };
 
 template <bool COUNT64, bool VEC2, uint32_t KIND>
@@ -50,7 +51,10 @@ __global__ __launch_bounds__(256) void batched_sweep_kernel(const BatchLaunch L)
   }
   for (; item < end; item += stride) {   // block-uniform loop
     const uint32_t sg = range_of(L.seg_first, L.n_segs, item);
-    const SweepArgs a = resolve_sweep(L.segs[sg].a, L.sweep_off);
+    SweepArgs a = resolve_sweep(L.segs[sg].a, L.sweep_off);
+    a.sub_k = L.sub_k;
+    a.sub_j = L.sub_j;
+    a.n_sub = a.n_chains > L.sub_j ? (a.n_chains - L.sub_j + L.sub_k - 1u) / L.sub_k : 0u;
     const uint32_t tile = (item - L.seg_first[sg]) * 4u + (threadIdx.x >> 6);
     const LaneMap m = lane_map_tile(a, tile, true);
     if (KIND == 0) {

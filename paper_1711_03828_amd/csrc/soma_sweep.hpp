@@ -41,6 +41,9 @@ struct SweepArgs {
   uint32_t replica;
   uint32_t set_order;              // 0 random per chain and sweep, 1 even first
   const uint32_t *sweep_ctr;       // device sweep counter of the system
+  // chain subset of this launch: chains sub_j, sub_j + sub_k, ... (n_sub of them);
+  // sub_k = 1 moves every chain
+  uint32_t sub_k, sub_j, n_sub;
 };
 
 // Arguments with the Philox sweep word resolved: the system's device counter
@@ -76,8 +79,9 @@ __device__ __forceinline__ LaneMap lane_map_tile(const SweepArgs &a, uint32_t ti
   const uint32_t L = a.lanes_per_chain;
   const uint32_t slot = (uint32_t)m.lane / L;
   m.k = (uint32_t)m.lane - slot * L;
-  m.chain = tile * a.chains_per_wave + slot;
-  const bool active = valid && slot < a.chains_per_wave && m.chain < a.n_chains;
+  const uint32_t cl = tile * a.chains_per_wave + slot;   // index within the subset
+  m.chain = cl * a.sub_k + a.sub_j;
+  const bool active = valid && slot < a.chains_per_wave && cl < a.n_sub;
   m.has0 = active;  // 2k < N for every k < ceil(N/2)
   m.has1 = active && 2u * m.k + 1u < a.n;
   return m;
@@ -270,7 +274,7 @@ __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap
 template <bool COUNT64, bool VEC2>
 __global__ __launch_bounds__(256) void mc_sweep_local_kernel(const SweepArgs a_in) {
   const SweepArgs a = resolve_sweep(a_in, 0u);
-  const uint32_t n_tiles = (a.n_chains + a.chains_per_wave - 1u) / a.chains_per_wave;
+  const uint32_t n_tiles = (a.n_sub + a.chains_per_wave - 1u) / a.chains_per_wave;
   const uint32_t blocks = gridDim.x;
   // XCD split only when the grid is a multiple of 8 blocks
   const uint32_t parts = (blocks & 7u) == 0u ? 8u : 1u;

@@ -90,11 +90,13 @@ class Melt:
         C.soma_rebuild_histogram(self.handle, _stream(stream))
 
     def cycle(self, n=1, move_kind=C.SOMA_MOVE_LOCAL, stream=None):
-        """n SCMF cycles: one sweep, then the field refresh."""
-        s = _stream(stream)
-        for _ in range(n):
-            C.soma_mc_sweep(self.handle, 1, move_kind, s)
-            C.soma_update_fields(self.handle, s)
+        """n SCMF cycles: the sweep, then the field refresh (per chain subset when
+        sub-steps are set)."""
+        C.soma_cycle(self.handle, n, move_kind, _stream(stream))
+
+    def set_substeps(self, k: int):
+        """Field refreshes per cycle (k interleaved chain subsets)."""
+        C.soma_set_substeps(self.handle, k)
 
     def observables(self, stream=None, raise_on_flag=True) -> C.soma_obs:
         return C.soma_observables(self.handle, _stream(stream), raise_on_flag)
@@ -159,10 +161,10 @@ class Batch:
         C.soma_batch_update_fields(self.handle, _stream(stream))
 
     def cycle(self, n=1, move_kind=C.SOMA_MOVE_LOCAL, stream=None):
-        s = _stream(stream)
-        for _ in range(n):
-            C.soma_batch_sweep(self.handle, 1, move_kind, s)
-            C.soma_batch_update_fields(self.handle, s)
+        C.soma_batch_cycle(self.handle, n, move_kind, _stream(stream))
+
+    def set_substeps(self, k: int, stream=None):
+        C.soma_batch_set_substeps(self.handle, k, _stream(stream))
 
     def capture_cycle(self, cycles: int, move_kind=C.SOMA_MOVE_LOCAL):
         C.soma_batch_capture_cycle(self.handle, cycles, move_kind)

@@ -110,6 +110,10 @@ _SIGS = {
     "soma_check": ([_P, _pu32, _P], _i32),
     "soma_get_sweep": ([_P, _pu64], _i32),
     "soma_set_sweep": ([_P, _u64, _P], _i32),
+    "soma_set_substeps": ([_P, _u32], _i32),
+    "soma_cycle": ([_P, _u32, _u32, _P], _i32),
+    "soma_batch_set_substeps": ([_P, _u32, _P], _i32),
+    "soma_batch_cycle": ([_P, _u32, _u32, _P], _i32),
     "soma_capture_cycle": ([_P, _u32, _u32], _i32),
     "soma_run_cycle": ([_P, _u32, _P], _i32),
     "soma_autotune": ([_P, _u32, _u32, ctypes.c_char_p, _P, ctypes.POINTER(soma_tune)], _i32),
@@ -216,6 +220,22 @@ def soma_get_sweep(h) -> int:
 
 def soma_set_sweep(h, sweep: int, stream: int = 0) -> None:
     _check(_lib.soma_set_sweep(h, sweep, ctypes.c_void_p(stream)))
+
+
+def soma_set_substeps(h, k: int) -> None:
+    _check(_lib.soma_set_substeps(h, k))
+
+
+def soma_cycle(h, n_cycles: int, move_kind: int, stream: int) -> None:
+    _check(_lib.soma_cycle(h, n_cycles, move_kind, ctypes.c_void_p(stream)))
+
+
+def soma_batch_set_substeps(b, k: int, stream: int) -> None:
+    _check(_lib.soma_batch_set_substeps(b, k, ctypes.c_void_p(stream)))
+
+
+def soma_batch_cycle(b, n_cycles: int, move_kind: int, stream: int) -> None:
+    _check(_lib.soma_batch_cycle(b, n_cycles, move_kind, ctypes.c_void_p(stream)))
 
 
 def soma_capture_cycle(h, cycles: int, move_kind: int) -> None:
