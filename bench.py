@@ -119,14 +119,17 @@ def _re_vectors(melt, n):
 
 
 def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: int,
-                equil_cycles: int):
+                equil_cycles: int, substeps: int):
     """Plain vs learned proposal on the 262,144-chain melt (96^3 cells, chiN 25).
 
     1. Training data from the plain sampler: 10 rounds of 2^20 random beads,
        features at cycle t and displacement after 128 further plain cycles
        (10,485,760 samples), collected and trained on the device.
     2. Bead-moves/s of both samplers on the full melt (HIP events, graph-replayed
-       SCMF cycles).
+       SCMF cycles).  The learned sampler runs `substeps` chain subsets per cycle
+       with a field refresh after each: its moves are large, and the
+       quasi-instantaneous field approximation needs few beads moved between two
+       refreshes to give the plain sampler's observables (end-to-end distance).
     3. The melt equilibrated with the learned sampler for `equil_cycles` cycles,
        the network fine-tuned on plain trajectories from that state (4 x 2^20
        samples), then tau_int (Sokal window) of the end-to-end vectors of every
@@ -159,7 +162,9 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
                         "batch": 8192, "loss_first": losses[0], "loss_last": losses[-1],
                         "seconds_collect_and_train": t_train}}
     rates = {}
+    ksub = {"plain": 1, "learned": substeps}
     for name, kind in (("plain", C.SOMA_MOVE_LOCAL), ("learned", C.SOMA_MOVE_MIXED)):
+        melt.set_substeps(ksub[name])
         melt.capture_cycle(10, kind)
         melt.run_cycle(2)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -169,15 +174,18 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / 50
         rates[name] = 1e3 / ms
-        out[name] = {"ms_per_cycle": ms, "bead_moves_per_s": w.n_beads * 1e3 / ms}
+        out[name] = {"ms_per_cycle": ms, "bead_moves_per_s": w.n_beads * 1e3 / ms,
+                     "substeps": ksub[name]}
     obs = melt.observables()
     out["learned"]["acceptance"] = obs.accepted[2] / max(1, obs.attempted[2])
     out["plain"]["acceptance"] = obs.accepted[0] / max(1, obs.attempted[0])
 
     # equilibrate the full melt with the learned sampler, fine-tune on plain
     # trajectories from that state, then the tau_int runs on the full melt
+    melt.set_substeps(substeps)
     melt.capture_cycle(100, C.SOMA_MOVE_MIXED)
     melt.run_cycle(max(1, equil_cycles // 100))
+    melt.set_substeps(1)
     feats, disp = learned.collect(melt, 1 << 20, 128, 4, first_round=1000)
     tune = learned.Trainer(params, lr=1e-3)
     tl = tune.run(feats, disp, steps=2000, batch=8192, loss_every=500)
@@ -189,6 +197,7 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
     stride = 16                              # end-to-end vectors of every 16th chain
     for name, kind, mult in (("learned", C.SOMA_MOVE_MIXED, 1),
                              ("plain", C.SOMA_MOVE_LOCAL, plain_mult)):
+        melt.set_substeps(ksub[name])
         melt.capture_cycle(frame_cycles * mult, kind)
         n_frames = sub_frames
         o0 = melt.observables()
@@ -397,6 +406,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the plain-vs-learned proposal comparison")
     ap.add_argument("--p-learn", type=float, default=0.9)
+    ap.add_argument("--learned-substeps", type=int, default=8,
+                    help="chain subsets (field refreshes) per cycle for the learned sampler")
     ap.add_argument("--tau-frames", type=int, default=400, help="frames per tau_int run")
     ap.add_argument("--frame-cycles", type=int, default=50,
                     help="cycles between frames of the learned run")
@@ -495,7 +506,7 @@ def main():
     if not args.no_learned:
         result["learned_proposal"] = learned_leg(args.p_learn, args.tau_frames,
                                                  args.frame_cycles, args.plain_frame_mult,
-                                                 args.equil_cycles)
+                                                 args.equil_cycles, args.learned_substeps)
     if not args.no_batched:
         result["batched"] = batched_leg(50)
     if args.blend:
