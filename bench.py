@@ -394,6 +394,30 @@ def _re_vectors_species(melt, w):
     return (x[:, -1] - x[:, 0]).double()
 
 
+def copy_bandwidth():
+    """Device-to-device copy bandwidth (read + write bytes per second) of a 4 GiB
+    working set (HBM) and a 128 MiB one (resident in the 256 MB Infinity Cache),
+    the measured denominators beside the datasheet peak."""
+    import torch
+    out = {}
+    for name, nbytes, reps in (("hbm_4GiB", 4 << 30, 5), ("mall_128MiB", 128 << 20, 50)):
+        src = torch.ones(nbytes // 8, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = 2 * src.numel() * 4 / (ms * 1e-3) / 1e9
+        del src, dst
+    out["unit"] = "GB/s"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -503,6 +527,30 @@ def main():
         "acceptance": acc,
     }
     melt.close()
+    # the second move kind of this workload: smart-MC, with the kept gradient field
+    melt = Melt(make_config(w))
+    melt.keep_grad_field()
+    smc = {}
+    for _ in range(2):
+        melt.cycle(1, C.SOMA_MOVE_SMC)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record(stream)
+    melt.sweep(10, C.SOMA_MOVE_SMC)
+    e1.record(stream)
+    for _ in range(10):
+        melt.update_fields()
+    e2.record(stream)
+    torch.cuda.synchronize()
+    smc["sweep_ms"] = e0.elapsed_time(e1) / 10
+    smc["field_and_gradient_ms"] = e1.elapsed_time(e2) / 10
+    smc["bead_moves_per_s"] = w.n_beads * 1e3 / (smc["sweep_ms"] + smc["field_and_gradient_ms"])
+    obs = melt.observables()
+    smc["acceptance"] = obs.accepted[1] / max(1, obs.attempted[1])
+    result["smart_mc"] = smc
+    melt.close()
+    copy = copy_bandwidth()
+    result["roofline"]["copy_bandwidth"] = copy
+    result["roofline"]["frac_of_copy_hbm"] = achieved / copy["hbm_4GiB"]
     if not args.no_learned:
         result["learned_proposal"] = learned_leg(args.p_learn, args.tau_frames,
                                                  args.frame_cycles, args.plain_frame_mult,

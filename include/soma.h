@@ -167,6 +167,16 @@ int32_t soma_mc_sweep(soma_system *sys, uint32_t n_sweeps, uint32_t move_kind,
  * are left unchanged.  Asynchronous. */
 int32_t soma_update_fields(soma_system *sys, void *stream);
 
+/* Optional gradient field for smart-MC moves: `grad` (device, caller-owned,
+ * 16-byte aligned, >= 32 * n_cells bytes) receives, for each type t and cell
+ * c, the float4 (omega_t(c), and the central differences along x, y, z,
+ * 0.5 (omega_t(c + e) - omega_t(c - e)) over the periodic neighbours) at every
+ * field refresh, starting now.  Smart-MC sweeps then read the field and its
+ * gradient at a cell with one 16-byte gather instead of seven; results are
+ * bit-identical either way.  grad = NULL detaches it.  Attach before creating
+ * a batch that holds the system.  Asynchronous. */
+int32_t soma_set_grad_field(soma_system *sys, void *grad, uint64_t grad_bytes, void *stream);
+
 /* Launch shape of the local-move sweep: 0 (default) runs one wave per tile
  * of chains; blocks > 0 runs that many persistent 256-thread blocks, each wave
  * looping over tiles and prefetching the next tile's positions.  Results are

@@ -247,6 +247,7 @@ struct soma_system {
   uint64_t mixed_moves = 0;   // bead moves made by mixed sweeps (local or learned)
   uint32_t net_mask = 0;      // species with an installed network (bit per species)
   uint32_t substeps = 1;      // field refreshes per SCMF cycle (chain subsets)
+  float4 *grad = nullptr;     // optional gradient field (caller-owned), see soma_set_grad_field
   unsigned char *ws = nullptr;
   CycleGraph graph;
   ~soma_system() { graph.release(); }
@@ -316,6 +317,7 @@ void sweep_args(soma_system *sys, uint32_t sp, uint32_t kind, soma::SweepArgs &a
   a.sub_k = 1;
   a.sub_j = 0;
   a.n_sub = S.n_chains;
+  a.grad = sys->grad;
   mx.net = sys->net(sp);
   mx.head.m_max = c->mu_max;
   mx.head.lo = c->log_sigma_min;
@@ -387,13 +389,28 @@ int32_t check_kind(soma_system *sys, uint32_t move_kind) {
   return SOMA_OK;
 }
 
+int32_t launch_grad(soma_system *sys, hipStream_t s) {
+  const uint32_t n = 2u * (uint32_t)sys->d.n_cells;
+  hipLaunchKernelGGL(soma::grad_field_kernel, dim3((n + 255) / 256), dim3(256), 0, s,
+                     sys->buf.omega, sys->grad, sys->grid);
+  LAUNCH_TRY();
+  return SOMA_OK;
+}
+
+// Stage 1 of the cycle: fields from the counts, then the gradient field if kept.
+int32_t refresh_fields(soma_system *sys, hipStream_t s) {
+  int32_t r = launch_field(&sys->cfg, sys->d, sys->buf.counts, sys->buf.omega, sys->fpart(), s);
+  if (!r && sys->grad) r = launch_grad(sys, s);
+  return r;
+}
+
 // One SCMF cycle with sweep offset `off`: for each of the system's k chain
 // subsets, its sweep and then the field refresh (k = 1: sweep, refresh).
 int32_t enqueue_cycle(soma_system *sys, uint32_t kind, hipStream_t s, uint32_t off) {
   const uint32_t k = sys->substeps;
   for (uint32_t j = 0; j < k; ++j) {
     int32_t r = launch_sweep(sys, kind, s, off, k, j);
-    if (!r) r = launch_field(&sys->cfg, sys->d, sys->buf.counts, sys->buf.omega, sys->fpart(), s);
+    if (!r) r = refresh_fields(sys, s);
     if (r) return r;
   }
   return SOMA_OK;
@@ -580,8 +597,22 @@ int32_t soma_rebuild_histogram(soma_system *sys, void *stream) {
 
 int32_t soma_update_fields(soma_system *sys, void *stream) {
   if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
-  return launch_field(&sys->cfg, sys->d, sys->buf.counts, sys->buf.omega, sys->fpart(),
-                      reinterpret_cast<hipStream_t>(stream));
+  return refresh_fields(sys, reinterpret_cast<hipStream_t>(stream));
+}
+
+int32_t soma_set_grad_field(soma_system *sys, void *grad, uint64_t grad_bytes, void *stream) {
+  if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
+  if (!grad) {
+    sys->grad = nullptr;
+    return SOMA_OK;
+  }
+  const uint64_t need = 32ull * sys->d.n_cells;
+  if (grad_bytes < need)
+    return fail(SOMA_E_SIZE, "gradient field: %llu < %llu bytes", (unsigned long long)grad_bytes,
+                (unsigned long long)need);
+  if (!aligned(grad, 16)) return fail(SOMA_E_INVAL, "gradient field must be 16-byte aligned");
+  sys->grad = reinterpret_cast<float4 *>(grad);
+  return launch_grad(sys, reinterpret_cast<hipStream_t>(stream));
 }
 
 int32_t soma_observables(soma_system *sys, soma_obs *out, void *stream) {
@@ -1084,6 +1115,11 @@ int32_t launch_batch_field(soma_batch *b, hipStream_t s) {
     hipLaunchKernelGGL(soma::batched_field_kernel<false>, grid, dim3(256), 0, s, b->d_fargs,
                        b->d_fb_first, n_sys);
   LAUNCH_TRY();
+  for (soma_system *x : b->sys)   // gradient fields of the systems that keep one
+    if (x->grad) {
+      const int32_t r = launch_grad(x, s);
+      if (r) return r;
+    }
   return SOMA_OK;
 }
 

@@ -206,6 +206,33 @@ __global__ __launch_bounds__(256) void batched_field_kernel(const FieldArgs *fa,
   field_body<COUNT64>(fa[s], blockIdx.x - first[s], first[s + 1] - first[s]);
 }
 
+// Gradient field for smart-MC moves: for each type and cell, the field and its
+// central differences 0.5 (omega(c + e) - omega(c - e)) over the periodic
+// neighbours, in the arithmetic the sweep uses when it gathers them itself.
+__global__ __launch_bounds__(256) void grad_field_kernel(const float *__restrict__ omega,
+                                                         float4 *__restrict__ grad, Grid g) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2u * g.n_cells) return;
+  const uint32_t t = i >= g.n_cells ? 1u : 0u;
+  const uint32_t c = i - t * g.n_cells;
+  const uint32_t nxy = (uint32_t)g.nx * (uint32_t)g.ny;
+  const uint32_t cz = c / nxy, rem = c - cz * nxy;
+  const uint32_t cy = rem / (uint32_t)g.nx, cx = rem - cy * (uint32_t)g.nx;
+  const float *om = omega + t * g.n_cells;
+  const uint32_t xp = cx + 1 == (uint32_t)g.nx ? 0 : cx + 1;
+  const uint32_t xm = cx == 0 ? g.nx - 1 : cx - 1;
+  const uint32_t yp = cy + 1 == (uint32_t)g.ny ? 0 : cy + 1;
+  const uint32_t ym = cy == 0 ? g.ny - 1 : cy - 1;
+  const uint32_t zp = cz + 1 == (uint32_t)g.nz ? 0 : cz + 1;
+  const uint32_t zm = cz == 0 ? g.nz - 1 : cz - 1;
+  float4 v;
+  v.x = om[c];
+  v.y = 0.5f * (om[cell_index(g, xp, cy, cz)] - om[cell_index(g, xm, cy, cz)]);
+  v.z = 0.5f * (om[cell_index(g, cx, yp, cz)] - om[cell_index(g, cx, ym, cz)]);
+  v.w = 0.5f * (om[cell_index(g, cx, cy, zp)] - om[cell_index(g, cx, cy, zm)]);
+  grad[i] = v;
+}
+
 // Device sweep counters: add `by` to each (or set them to `value`).
 __global__ __launch_bounds__(64) void sweep_counter_kernel(uint32_t *const *ctrs, uint32_t n,
                                                            uint32_t by, uint32_t set,

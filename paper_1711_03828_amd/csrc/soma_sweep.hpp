@@ -44,6 +44,9 @@ struct SweepArgs {
   // chain subset of this launch: chains sub_j, sub_j + sub_k, ... (n_sub of them);
   // sub_k = 1 moves every chain
   uint32_t sub_k, sub_j, n_sub;
+  // optional [2][n_cells] (omega, d omega/dx, d omega/dy, d omega/dz) per type and
+  // cell, refreshed with the fields; null: smart-MC gathers the 6 neighbours
+  const float4 *grad;
 };
 
 // Arguments with the Philox sweep word resolved: the system's device counter
@@ -324,6 +327,19 @@ __device__ __forceinline__ F3 field_grad(const Grid &g, const float *omega, uint
   return r;
 }
 
+// Field value and central-difference gradient of plane `pl` at cell c = (cx,cy,cz):
+// one 16-byte gather from the gradient field when it is kept, else 7 gathers.
+__device__ __forceinline__ float field_and_grad(const SweepArgs &a, uint32_t pl, uint32_t c,
+                                                uint32_t cx, uint32_t cy, uint32_t cz, F3 &g) {
+  if (a.grad) {
+    const float4 v = a.grad[pl + c];
+    g = F3{v.y, v.z, v.w};
+    return v.x;
+  }
+  g = field_grad(a.grid, a.omega, pl, cx, cy, cz);
+  return field_at(a.omega, pl, c);
+}
+
 // ---------------------------------------------------------------------------
 // Smart-MC moves (Sec. 2.2, move (ii)): r' = r + A F(r) + sqrt(2A) xi with the
 // bonded force plus the grid-field force -(1/N) grad omega; accepted with
@@ -378,7 +394,8 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
       float xi0, xi1, xi2, xi3;
       box_muller(w.x, w.y, xi0, xi1);
       box_muller(w.z, w.w, xi2, xi3);
-      const F3 g_old = field_grad(a.grid, a.omega, pl, ox, oy, oz);
+      F3 g_old;
+      const float w_old = field_and_grad(a, pl, co, ox, oy, oz, g_old);
       const F3 f_old = {-a.k0 * (wl * el.x + wr * er.x) - a.inv_nref * g_old.x,
                         -a.k0 * (wl * el.y + wr * er.y) - a.inv_nref * g_old.y,
                         -a.k0 * (wl * el.z + wr * er.z) - a.inv_nref * g_old.z};
@@ -390,7 +407,9 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
       cn = cell_index(a.grid, nx_, ny_, nz_);
       // force at the trial position with the same bonded neighbours; the
       // field gradient is constant inside a cell
-      const F3 g_new = cn == co ? g_old : field_grad(a.grid, a.omega, pl, nx_, ny_, nz_);
+      F3 g_new = g_old;
+      float w_new = w_old;
+      if (cn != co) w_new = field_and_grad(a, pl, cn, nx_, ny_, nz_, g_new);
       const F3 d = {rn.x - r.x, rn.y - r.y, rn.z - r.z};
       const F3 nl = {rn.x - left.x, rn.y - left.y, rn.z - left.z};
       const F3 nr = {rn.x - right.x, rn.y - right.y, rn.z - right.z};
@@ -404,8 +423,6 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
       const float qx = wl * (2.0f * el.x + d.x) + wr * (2.0f * er.x + d.x);
       const float qy = wl * (2.0f * el.y + d.y) + wr * (2.0f * er.y + d.y);
       const float qz = wl * (2.0f * el.z + d.z) + wr * (2.0f * er.z + d.z);
-      const float w_old = field_at(a.omega, pl, co);
-      const float w_new = cn == co ? w_old : field_at(a.omega, pl, cn);
       const float d_e = a.half_k0 * (d.x * qx + d.y * qy + d.z * qz) + (w_new - w_old) * a.inv_nref;
       const float lr = log_q - d_e;
       acc = lr >= 0.0f || u < __expf(lr);

@@ -94,6 +94,18 @@ class Melt:
         sub-steps are set)."""
         C.soma_cycle(self.handle, n, move_kind, _stream(stream))
 
+    def keep_grad_field(self, on: bool = True, stream=None):
+        """Keep the (omega, grad omega) float4 field for smart-MC moves (allocates
+        32 B per cell), or drop it."""
+        if on:
+            self.grad = torch.empty((2, self.n_cells, 4), dtype=torch.float32,
+                                    device=self.pos.device)
+            C.soma_set_grad_field(self.handle, self.grad.data_ptr(), self.grad.numel() * 4,
+                                  _stream(stream))
+        else:
+            C.soma_set_grad_field(self.handle, 0, 0, _stream(stream))
+            self.grad = None
+
     def set_substeps(self, k: int):
         """Field refreshes per cycle (k interleaved chain subsets)."""
         C.soma_set_substeps(self.handle, k)

@@ -111,6 +111,7 @@ _SIGS = {
     "soma_get_sweep": ([_P, _pu64], _i32),
     "soma_set_sweep": ([_P, _u64, _P], _i32),
     "soma_set_substeps": ([_P, _u32], _i32),
+    "soma_set_grad_field": ([_P, _P, _u64, _P], _i32),
     "soma_cycle": ([_P, _u32, _u32, _P], _i32),
     "soma_batch_set_substeps": ([_P, _u32, _P], _i32),
     "soma_batch_cycle": ([_P, _u32, _u32, _P], _i32),
@@ -220,6 +221,11 @@ def soma_get_sweep(h) -> int:
 
 def soma_set_sweep(h, sweep: int, stream: int = 0) -> None:
     _check(_lib.soma_set_sweep(h, sweep, ctypes.c_void_p(stream)))
+
+
+def soma_set_grad_field(h, grad_ptr: int, grad_bytes: int, stream: int) -> None:
+    _check(_lib.soma_set_grad_field(h, ctypes.c_void_p(grad_ptr) if grad_ptr else None,
+                                    grad_bytes, ctypes.c_void_p(stream)))
 
 
 def soma_set_substeps(h, k: int) -> None:
