@@ -44,6 +44,8 @@ int main(void) {
          sizeof(soma_buffers), sizeof(soma_obs), offsetof(soma_config, seed));
   printf("%zu %zu %zu\n", offsetof(soma_obs, re2_sum), offsetof(soma_obs, error_flags),
          offsetof(soma_config, origin_mode));
+  printf("%zu %zu %zu %zu\n", sizeof(soma_train_opts), offsetof(soma_train_opts, apply),
+         sizeof(soma_tune), offsetof(soma_tune, from_cache));
   return 0;
 }''')
     exe = tmp_path / "layout"
@@ -54,7 +56,9 @@ int main(void) {
     exp = [ctypes.sizeof(C.soma_species), ctypes.sizeof(C.soma_config),
            ctypes.sizeof(C.soma_buffers), ctypes.sizeof(C.soma_obs),
            C.soma_config.seed.offset, C.soma_obs.re2_sum.offset, C.soma_obs.error_flags.offset,
-           C.soma_config.origin_mode.offset]
+           C.soma_config.origin_mode.offset, ctypes.sizeof(C.soma_train_opts),
+           C.soma_train_opts.apply.offset, ctypes.sizeof(C.soma_tune),
+           C.soma_tune.from_cache.offset]
     assert got == exp
 
 
