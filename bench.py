@@ -274,14 +274,15 @@ def batched_leg(cycles: int):
 
 
 def blend_leg(rate_cycles: int, tau_frames: int, frame_cycles: int, plain_mult: int,
-              equil_cycles: int, tau_scale: float):
+              equil_cycles: int, tau_scale: float, substeps: int):
     """Ternary blend replicas (32 melts of A16B16 diblocks with A16 and B16
     homopolymers, chiN 15..35): one network per species trained on the blend's
     own plain trajectories, used inside graph-captured batched cycles.
 
     Rates at full size (about 4.2e7 beads); tau_int of the diblocks' end-to-end
     vectors and the S(q) peak shell of every replica on a copy scaled by
-    `tau_scale` in chains (same density and chemistry)."""
+    `tau_scale` in chains (same density and chemistry), with the diblocks' <Re^2>.
+    The learned sampler runs `substeps` field refreshes per cycle."""
     import numpy as np
     import torch
 
@@ -329,7 +330,9 @@ def blend_leg(rate_cycles: int, tau_frames: int, frame_cycles: int, plain_mult: 
             m.set_proposal(nets[sp], species=sp)
     n_beads = sum(w.n_beads for w in reps)
     stream = torch.cuda.current_stream()
+    ksub = {"plain": 1, "learned": substeps}
     for name, kind in (("plain", C.SOMA_MOVE_LOCAL), ("learned", C.SOMA_MOVE_MIXED)):
+        batch.set_substeps(ksub[name])
         batch.capture_cycle(10, kind)
         batch.run_cycle(1)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -338,7 +341,8 @@ def blend_leg(rate_cycles: int, tau_frames: int, frame_cycles: int, plain_mult: 
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / (rate_cycles // 10 * 10)
-        out[name] = {"ms_per_cycle": ms, "bead_moves_per_s": n_beads * 1e3 / ms}
+        out[name] = {"ms_per_cycle": ms, "bead_moves_per_s": n_beads * 1e3 / ms,
+                     "substeps": ksub[name]}
     out["workload"] = f"{len(reps)} blend replicas, {n_beads} beads"
     batch.close()
     for m in melts:
@@ -349,19 +353,22 @@ def blend_leg(rate_cycles: int, tau_frames: int, frame_cycles: int, plain_mult: 
     for m in melts:
         for sp in range(3):
             m.set_proposal(nets[sp], species=sp)
+    batch.set_substeps(substeps)
     batch.capture_cycle(frame_cycles, C.SOMA_MOVE_MIXED)
     batch.run_cycle(max(1, equil_cycles // frame_cycles))
     ws = [torch.empty(C.soma_sq_workspace_bytes(m.handle), dtype=torch.uint8, device="cuda")
           for m in melts]
     for name, kind, mult in (("learned", C.SOMA_MOVE_MIXED, 1), ("plain", C.SOMA_MOVE_LOCAL,
                                                                   plain_mult)):
+        batch.set_substeps(ksub[name])
         batch.capture_cycle(frame_cycles * mult, kind)
         series = []
         for f in range(tau_frames):
             batch.run_cycle(1)
             series.append(torch.cat([_re_vectors_species(m, w) for m, w in zip(melts, sreps)]))
-        x = torch.stack(series).reshape(tau_frames, -1).cpu().numpy()
-        tau, window = analysis.tau_int(x)
+        xs = torch.stack(series)
+        re2 = float((xs ** 2).sum(-1).mean()) / 36.0
+        tau, window = analysis.tau_int(xs.reshape(tau_frames, -1).cpu().numpy())
         tau *= frame_cycles * mult
         peaks = []
         for m, w, wsb in zip(melts, sreps, ws):
@@ -371,6 +378,7 @@ def blend_leg(rate_cycles: int, tau_frames: int, frame_cycles: int, plain_mult: 
             _, mean, _, peak = C.soma_sq_shells(sq.cpu().numpy(), w.grid, 16)
             peaks.append(int(peak))
         out[name].update({"tau_int_cycles": tau, "window_frames": window,
+                          "diblock_re2_over_re02": re2,
                           "uncorrelated_samples_per_s":
                               sum(w.species[0].n_chains for w in reps) * 1e3 /
                               out[name]["ms_per_cycle"] / (2.0 * tau),
@@ -559,7 +567,8 @@ def main():
         result["batched"] = batched_leg(50)
     if args.blend:
         result["blend"] = blend_leg(50, args.tau_frames // 2, args.frame_cycles,
-                                    args.plain_frame_mult, args.equil_cycles // 2, 1.0 / 16)
+                                    args.plain_frame_mult, args.equil_cycles // 2, 1.0 / 16,
+                                    args.learned_substeps)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(result), flush=True)
