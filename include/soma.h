@@ -167,6 +167,13 @@ int32_t soma_mc_sweep(soma_system *sys, uint32_t n_sweeps, uint32_t move_kind,
  * are left unchanged.  Asynchronous. */
 int32_t soma_update_fields(soma_system *sys, void *stream);
 
+/* After the caller has written buf->omega directly (for example a frozen
+ * external field), rebuilds the copies the sweeps read besides it: the
+ * learned proposal's halo copy (kept when p_learn > 0) and the gradient field
+ * (if kept).  Field refreshes by the library keep them current by themselves.
+ * Asynchronous. */
+int32_t soma_sync_fields(soma_system *sys, void *stream);
+
 /* Optional gradient field for smart-MC moves: `grad` (device, caller-owned,
  * 16-byte aligned, >= 32 * n_cells bytes) receives, for each type t and cell
  * c, the float4 (omega_t(c), and the central differences along x, y, z,

@@ -54,7 +54,8 @@ struct Derived {
   uint64_t pos_bytes = 0, counts_bytes = 0, omega_bytes = 0;
   // workspace layout
   uint64_t off_err = 0, off_acc = 0, off_att = 0, off_net = 0, off_fpart = 0, off_totals = 0,
-           off_opart = 0;
+           off_opart = 0, off_halo = 0;
+  uint64_t halo_plane = 0;    // floats per plane of the halo copy (0: not kept)
   uint64_t ws_bytes = 0;
   uint32_t field_blocks = 1;  // blocks of the field update (and its FP64 partial sums)
 };
@@ -115,7 +116,13 @@ int32_t derive(const soma_config *c, Derived *d) {
   d->off_fpart = align_up(d->off_net + SOMA_MAX_SPECIES * align_up(sizeof(soma::NetDev)));
   d->off_totals = align_up(d->off_fpart + soma::kFieldBlocks * sizeof(soma::FieldPartial));
   d->off_opart = align_up(d->off_totals + sizeof(soma::Totals));
-  d->ws_bytes = align_up(d->off_opart + (d->obs_blocks ? d->obs_blocks : 1) * sizeof(soma::ObsPartial));
+  d->off_halo = align_up(d->off_opart + (d->obs_blocks ? d->obs_blocks : 1) * sizeof(soma::ObsPartial));
+  // the learned proposal reads its 27-cell neighbourhoods from a copy of the
+  // fields with one periodic halo cell at both ends of each x row
+  d->halo_plane = c->p_learn > 0.f ? (uint64_t)c->nz * c->ny * (c->nx + 2u) : 0u;
+  if (8ull * d->halo_plane >= (1ull << 32))
+    return fail(SOMA_E_UNSUPPORTED, "grid too large for the learned proposal's field copy");
+  d->ws_bytes = align_up(d->off_halo + 8ull * d->halo_plane);
   return SOMA_OK;
 }
 
@@ -165,7 +172,7 @@ int32_t launch_hist(const soma_config *c, const Derived &d, const float *pos, vo
 }
 
 soma::FieldArgs field_args(const soma_config *c, const Derived &d, void *counts, float *omega,
-                           soma::FieldPartial *partials) {
+                           soma::FieldPartial *partials, float *halo = nullptr) {
   soma::FieldArgs a;
   a.counts = counts;
   a.omega = omega;
@@ -178,12 +185,15 @@ soma::FieldArgs field_args(const soma_config *c, const Derived &d, void *counts,
   a.kappa_n_d = (double)c->kappa_n;
   a.partials = partials;
   a.clear = 0;
+  a.halo = d.halo_plane ? halo : nullptr;
+  a.nx = c->nx;
+  a.halo_plane = (uint32_t)d.halo_plane;
   return a;
 }
 
 int32_t launch_field(const soma_config *c, const Derived &d, void *counts, float *omega,
-                     soma::FieldPartial *partials, hipStream_t s) {
-  const soma::FieldArgs a = field_args(c, d, counts, omega, partials);
+                     soma::FieldPartial *partials, hipStream_t s, float *halo = nullptr) {
+  const soma::FieldArgs a = field_args(c, d, counts, omega, partials, halo);
   const uint32_t blocks = d.field_blocks;
   if (c->count_width == 32)
     hipLaunchKernelGGL(soma::field_update_kernel<true>, dim3(blocks), dim3(256), 0, s, a);
@@ -262,6 +272,7 @@ struct soma_system {
   soma::FieldPartial *fpart() { return reinterpret_cast<soma::FieldPartial *>(ws + d.off_fpart); }
   soma::Totals *totals() { return reinterpret_cast<soma::Totals *>(ws + d.off_totals); }
   soma::ObsPartial *opart() { return reinterpret_cast<soma::ObsPartial *>(ws + d.off_opart); }
+  float *halo() { return d.halo_plane ? reinterpret_cast<float *>(ws + d.off_halo) : nullptr; }
   unsigned long long *att() { return reinterpret_cast<unsigned long long *>(ws + d.off_att); }
   soma::NetDev *net(uint32_t sp) {
     return reinterpret_cast<soma::NetDev *>(ws + d.off_net + sp * align_up(sizeof(soma::NetDev)));
@@ -325,6 +336,8 @@ void sweep_args(soma_system *sys, uint32_t sp, uint32_t kind, soma::SweepArgs &a
   mx.p_learn = c->p_learn;
   mx.att_slots = sys->att();
   mx.err = sys->err();
+  mx.halo = sys->halo();
+  mx.halo_plane = (uint32_t)sys->d.halo_plane;
 }
 
 bool species_vec2(const soma_system *sys, uint32_t sp) {
@@ -399,7 +412,8 @@ int32_t launch_grad(soma_system *sys, hipStream_t s) {
 
 // Stage 1 of the cycle: fields from the counts, then the gradient field if kept.
 int32_t refresh_fields(soma_system *sys, hipStream_t s) {
-  int32_t r = launch_field(&sys->cfg, sys->d, sys->buf.counts, sys->buf.omega, sys->fpart(), s);
+  int32_t r = launch_field(&sys->cfg, sys->d, sys->buf.counts, sys->buf.omega, sys->fpart(), s,
+                           sys->halo());
   if (!r && sys->grad) r = launch_grad(sys, s);
   return r;
 }
@@ -511,7 +525,7 @@ int32_t soma_init_system(const soma_config *cfg, const soma_buffers *buf, uint32
   rc = launch_zero(sys->ws, d.ws_bytes, s);
   if (!rc && init_positions) rc = launch_init(cfg, d, buf->pos, s);
   if (!rc) rc = launch_hist(cfg, d, buf->pos, buf->counts, s);
-  if (!rc) rc = launch_field(cfg, d, buf->counts, buf->omega, sys->fpart(), s);
+  if (!rc) rc = launch_field(cfg, d, buf->counts, buf->omega, sys->fpart(), s, sys->halo());
   if (rc) {
     delete sys;
     return rc;
@@ -598,6 +612,20 @@ int32_t soma_rebuild_histogram(soma_system *sys, void *stream) {
 int32_t soma_update_fields(soma_system *sys, void *stream) {
   if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
   return refresh_fields(sys, reinterpret_cast<hipStream_t>(stream));
+}
+
+int32_t soma_sync_fields(soma_system *sys, void *stream) {
+  if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (sys->halo()) {
+    const soma::FieldArgs a = field_args(&sys->cfg, sys->d, sys->buf.counts, sys->buf.omega,
+                                         nullptr, sys->halo());
+    hipLaunchKernelGGL(soma::halo_from_fields_kernel, dim3((uint32_t)((sys->d.n_cells + 255) / 256)),
+                       dim3(256), 0, s, a);
+    LAUNCH_TRY();
+  }
+  if (sys->grad) return launch_grad(sys, s);
+  return SOMA_OK;
 }
 
 int32_t soma_set_grad_field(soma_system *sys, void *grad, uint64_t grad_bytes, void *stream) {
@@ -1197,7 +1225,8 @@ int32_t soma_batch_create(soma_system *const *systems, uint32_t n, void *workspa
   b->fb_first.push_back(0);
   for (uint32_t i = 0; i < n; ++i) {
     soma_system *x = systems[i];
-    b->fargs.push_back(field_args(&x->cfg, x->d, x->buf.counts, x->buf.omega, x->fpart()));
+    b->fargs.push_back(field_args(&x->cfg, x->d, x->buf.counts, x->buf.omega, x->fpart(),
+                                  x->halo()));
     b->fb_first.push_back(b->fb_first.back() + x->d.field_blocks);
     b->ctrs.push_back(x->sweep_ctr());
   }

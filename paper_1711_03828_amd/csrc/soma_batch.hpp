@@ -35,7 +35,7 @@ struct BatchLaunch {
 };
 
 template <bool COUNT64, bool VEC2, uint32_t KIND>
-__global__ __launch_bounds__(256) void batched_sweep_kernel(const BatchLaunch L) {
+__global__ __launch_bounds__(256, 2) void batched_sweep_kernel(const BatchLaunch L) {
   __shared__ __bf16 s_act[KIND == 2 ? 4 : 1][KIND == 2 ? 64 * kActStride : 1];
   __shared__ __bf16 s_tmp[KIND == 2 ? 4 : 1][KIND == 2 ? 64 * kActStride : 1];
   uint32_t item, end, stride;

@@ -64,7 +64,28 @@ struct FieldArgs {
   double inv_rho_d, chi_n_d, kappa_n_d;
   FieldPartial *partials;  // may be null
   int clear;
+  // optional copy of the fields with one periodic halo cell at each end of every
+  // x row: [2][nz*ny][nx + 2] (null: not kept)
+  float *halo;
+  uint32_t nx, halo_plane;
 };
+
+// Writes the two field values of the cell at column x of row r into the halo
+// copy (and into the halo cell that mirrors it when x is at either end).
+__device__ __forceinline__ void halo_put_rx(const FieldArgs &a, uint32_t r, uint32_t x, float va,
+                                            float vb) {
+  const uint32_t w = a.nx + 2u;
+  float *ha = a.halo + (size_t)r * w, *hb = ha + a.halo_plane;
+  ha[x + 1u] = va;
+  hb[x + 1u] = vb;
+  if (x == 0u) { ha[a.nx + 1u] = va; hb[a.nx + 1u] = vb; }
+  if (x + 1u == a.nx) { ha[0] = va; hb[0] = vb; }
+}
+
+__device__ __forceinline__ void halo_put(const FieldArgs &a, uint32_t c, float va, float vb) {
+  const uint32_t r = c / a.nx;
+  halo_put_rx(a, r, c - r * a.nx, va, vb);
+}
 
 __device__ __forceinline__ void field_cell(uint32_t na, uint32_t nb,
                                            const FieldArgs &a, float &oa,
@@ -126,6 +147,14 @@ __device__ __forceinline__ void field_body(const FieldArgs &a, uint32_t blk, uin
       if (stats) { sum_a += na[j]; sum_b += nb[j]; h += hnb_cell(na[j], nb[j], a); }
     }
     oa4[q] = make_float4(va[0], va[1], va[2], va[3]);
+    if (a.halo) {   // four consecutive cells: one division, then step along the row
+      uint32_t r = (4u * q) / a.nx, x = 4u * q - r * a.nx;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        halo_put_rx(a, r, x, va[j], vb[j]);
+        if (++x == a.nx) { x = 0; ++r; }
+      }
+    }
     if (b_aligned) {
       ob4[q] = make_float4(vb[0], vb[1], vb[2], vb[3]);
     } else {  // the B plane starts n_cells floats in: 16-byte stores only if n_cells % 4 == 0
@@ -160,6 +189,7 @@ __device__ __forceinline__ void field_body(const FieldArgs &a, uint32_t blk, uin
     field_cell(na, nb, a, va, vb);
     a.omega[c] = va;
     a.omega[a.n_cells + c] = vb;
+    if (a.halo) halo_put(a, c, va, vb);
     if (stats) { sum_a += na; sum_b += nb; h += hnb_cell(na, nb, a); }
   }
   if (!stats) return;
@@ -204,6 +234,14 @@ __global__ __launch_bounds__(256) void batched_field_kernel(const FieldArgs *fa,
                                                             const uint32_t *first, uint32_t n_sys) {
   const uint32_t s = range_of(first, n_sys, blockIdx.x);
   field_body<COUNT64>(fa[s], blockIdx.x - first[s], first[s + 1] - first[s]);
+}
+
+// Halo copy of the fields rebuilt from the field planes (after the caller has
+// written the fields directly).  One thread per cell.
+__global__ __launch_bounds__(256) void halo_from_fields_kernel(const FieldArgs a) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.n_cells) return;
+  halo_put(a, c, a.omega[c], a.omega[a.n_cells + c]);
 }
 
 // Gradient field for smart-MC moves: for each type and cell, the field and its

@@ -246,6 +246,45 @@ __device__ __forceinline__ float features_to_row(const Grid &g, const float *__r
   return f[13];   // own field at (dz, dy, dx) = (0, 0, 0)
 }
 
+// features_to_row from the halo copy of the fields ([2][nz*ny][nx + 2], plane
+// size `halo_plane`): each of the 18 rows of three cells is one 12-byte load.
+__device__ __forceinline__ float features_to_row_halo(const Grid &g, const float *__restrict__ halo,
+                                                      uint32_t halo_plane, bool is_b, F3 r,
+                                                      F3 bp, F3 bn, const float *__restrict__ stdz,
+                                                      __bf16 *row, uint32_t &cell) {
+  uint32_t cx, cy, cz;
+  cell3(g, r.x, r.y, r.z, cx, cy, cz);
+  const uint32_t w = (uint32_t)g.nx + 2u;
+  const uint32_t ys[3] = {cy == 0 ? g.ny - 1u : cy - 1u, cy, cy + 1 == (uint32_t)g.ny ? 0u : cy + 1u};
+  const uint32_t zs[3] = {cz == 0 ? g.nz - 1u : cz - 1u, cz, cz + 1 == (uint32_t)g.nz ? 0u : cz + 1u};
+  const uint32_t own = is_b ? halo_plane : 0u, oth = is_b ? 0u : halo_plane;
+  float f[kNF];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const uint32_t rowb = (zs[q / 3] * (uint32_t)g.ny + ys[q % 3]) * w + cx;
+    const f32x3u a = *reinterpret_cast<const f32x3u *>(reinterpret_cast<const char *>(halo) +
+                                                      ((own + rowb) << 2));
+    const f32x3u b = *reinterpret_cast<const f32x3u *>(reinterpret_cast<const char *>(halo) +
+                                                      ((oth + rowb) << 2));
+    f[3 * q] = a.x; f[3 * q + 1] = a.y; f[3 * q + 2] = a.z;
+    f[27 + 3 * q] = b.x; f[28 + 3 * q] = b.y; f[29 + 3 * q] = b.z;
+  }
+  f[54] = bp.x; f[55] = bp.y; f[56] = bp.z;
+  f[57] = bn.x; f[58] = bn.y; f[59] = bn.z;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    bf16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 8 * c + j;
+      v[j] = k < kNF ? (__bf16)((f[k < kNF ? k : 0] - stdz[k]) * stdz[64 + k]) : (__bf16)0.0f;
+    }
+    *reinterpret_cast<bf16x8 *>(row + 8 * c) = v;
+  }
+  cell = cell_index(g, cx, cy, cz);
+  return f[13];   // own field at (dz, dy, dx) = (0, 0, 0)
+}
+
 // Gaussian head of one sample: mean, sigma and log sigma.
 __device__ __forceinline__ void head(const float *z, const HeadArgs &h, float (&mu)[3],
                                      float (&sig)[3], float (&lsig)[3]) {

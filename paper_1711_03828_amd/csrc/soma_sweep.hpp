@@ -456,6 +456,8 @@ struct MixArgs {
   float p_learn;                   // probability of the learned move (state-independent)
   unsigned long long *att_slots;   // [kAccSlots] attempted learned moves
   uint32_t *err;                   // device error word (bit 2: non-finite network output)
+  const float *halo;               // fields with x halos [2][nz*ny][nx + 2] (p_learn > 0)
+  uint32_t halo_plane;
 };
 
 // ---------------------------------------------------------------------------
@@ -520,8 +522,9 @@ __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx
     float w_old, w_new, log_q = 0.0f;
     bool net_bad = false;
     if (__ballot(learned) != 0ull) {
-      w_old = features_to_row(a.grid, a.omega, is_b, r, has_l ? left - r : zero3,
-                              has_r ? right - r : zero3, stdz, row, co);
+      features_to_row_halo(a.grid, mx.halo, mx.halo_plane, is_b, r, has_l ? left - r : zero3,
+                           has_r ? right - r : zero3, stdz, row, co);
+      w_old = field_at(a.omega, pl, co);   // energies from the field itself
       wave_forward(mx.net, act, tmp, zb);
       float mu[3], sig[3], lsig[3];
       head(zb + m.lane * 8, mx.head, mu, sig, lsig);
@@ -533,8 +536,9 @@ __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx
       const F3 tp = {fmaf(a.step, uniform11(w.x), r.x), fmaf(a.step, uniform11(w.y), r.y),
                      fmaf(a.step, uniform11(w.z), r.z)};
       rn = sel(learned, tl, tp);
-      w_new = features_to_row(a.grid, a.omega, is_b, rn, has_l ? left - rn : zero3,
-                              has_r ? right - rn : zero3, stdz, row, cn);
+      features_to_row_halo(a.grid, mx.halo, mx.halo_plane, is_b, rn, has_l ? left - rn : zero3,
+                           has_r ? right - rn : zero3, stdz, row, cn);
+      w_new = cn == co ? w_old : field_at(a.omega, pl, cn);
       wave_forward(mx.net, act, tmp, zb);
       float mun[3], sign[3], lsign[3];
       head(zb + m.lane * 8, mx.head, mun, sign, lsign);

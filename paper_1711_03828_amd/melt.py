@@ -94,6 +94,10 @@ class Melt:
         sub-steps are set)."""
         C.soma_cycle(self.handle, n, move_kind, _stream(stream))
 
+    def sync_fields(self, stream=None):
+        """After writing self.omega directly: rebuild the copies the sweeps read."""
+        C.soma_sync_fields(self.handle, _stream(stream))
+
     def keep_grad_field(self, on: bool = True, stream=None):
         """Keep the (omega, grad omega) float4 field for smart-MC moves (allocates
         32 B per cell), or drop it."""

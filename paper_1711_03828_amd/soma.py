@@ -112,6 +112,7 @@ _SIGS = {
     "soma_set_sweep": ([_P, _u64, _P], _i32),
     "soma_set_substeps": ([_P, _u32], _i32),
     "soma_set_grad_field": ([_P, _P, _u64, _P], _i32),
+    "soma_sync_fields": ([_P, _P], _i32),
     "soma_cycle": ([_P, _u32, _u32, _P], _i32),
     "soma_batch_set_substeps": ([_P, _u32, _P], _i32),
     "soma_batch_cycle": ([_P, _u32, _u32, _P], _i32),
@@ -221,6 +222,10 @@ def soma_get_sweep(h) -> int:
 
 def soma_set_sweep(h, sweep: int, stream: int = 0) -> None:
     _check(_lib.soma_set_sweep(h, sweep, ctypes.c_void_p(stream)))
+
+
+def soma_sync_fields(h, stream: int) -> None:
+    _check(_lib.soma_sync_fields(h, ctypes.c_void_p(stream)))
 
 
 def soma_set_grad_field(h, grad_ptr: int, grad_bytes: int, stream: int) -> None:

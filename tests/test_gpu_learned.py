@@ -201,6 +201,7 @@ def test_three_bead_boltzmann_mixed_on_device(p_learn, trained):
                         seed=99, count_width=32, p_learn=p_learn)
     m = Melt(cfg, positions=torch.from_numpy(pos))
     m.omega.copy_(torch.from_numpy(omega))       # frozen field
+    m.sync_fields()
     m.sweep(150, C.SOMA_MOVE_LOCAL)              # equilibrate
     if trained:
         F, D = learned.collect(m, 65536, 10, 4, frozen_field=True)

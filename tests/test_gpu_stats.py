@@ -65,6 +65,7 @@ def test_three_bead_boltzmann_on_device(kind, step):
                         smc_a=step, seed=99, count_width=32)
     m = Melt(cfg, positions=torch.from_numpy(pos))
     m.omega.copy_(torch.from_numpy(omega))      # frozen field: no field updates
+    m.sync_fields()
     m.sweep(300, kind)
     torch.cuda.synchronize()
     p = m.pos.cpu().numpy().astype(np.float64)
