@@ -88,7 +88,7 @@ __device__ __forceinline__ void hidden_layer(const __bf16 *__restrict__ w,
                                              const __bf16 *in, __bf16 *out) {
   const int lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
   typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-#pragma unroll 1
+#pragma unroll 2
   for (int mt = 0; mt < 4; ++mt) {
     f32x4 acc[4];
 #pragma unroll
