@@ -288,7 +288,8 @@ int32_t soma_batch_run_cycle(soma_batch *b, uint32_t n_launches, void *stream);
 /* Autotuning of the batch's launch shape, as soma_autotune. */
 int32_t soma_batch_autotune(soma_batch *b, uint32_t cycles, uint32_t move_kind,
                             const char *cache_path, void *stream, soma_tune *out);
-/* Releases the batch (host memory; the graph). */
+/* Releases the batch (host memory; the graph), after its queued work has
+ * completed.  The systems stay valid. */
 void soma_batch_destroy(soma_batch *b);
 
 /* Stand-alone occupation histogram (Eq. (4)) of `pos` into `counts`
@@ -408,7 +409,8 @@ int32_t soma_train_step(const float *features, const float *targets, uint32_t n,
                         uint64_t workspace_bytes, float *grad_out, float *loss_out,
                         void *stream);
 
-/* Releases the handle (host memory and a captured graph). */
+/* Releases the handle (host memory and a captured graph).  Call it after the
+ * work queued through the handle has completed. */
 void soma_destroy(soma_system *sys);
 
 /* Message of the last failed call on this thread ("" if none). */
