@@ -129,13 +129,15 @@ __device__ __forceinline__ void store_pair(float *cp, const LaneMap &m, F3 r0, F
 
 // Move one bead's unit from cell `from` to cell `to` in the packed counts
 // (32-bit byte offsets from the uniform base: counts < 4 GiB, host-checked).
+// A count stays below 2^16 (u16 pairs) or 2^32 (u32 pairs), so adding -1 or +1
+// to one half never carries into the other.
 template <bool COUNT64>
 __device__ __forceinline__ void move_count(void *counts, uint32_t from, uint32_t to, bool is_b) {
   char *base = reinterpret_cast<char *>(counts);
-  if (COUNT64) {
-    const unsigned long long inc = is_b ? (1ull << 32) : 1ull;
-    atomicAdd(reinterpret_cast<unsigned long long *>(base + (from << 3)), 0ull - inc);
-    atomicAdd(reinterpret_cast<unsigned long long *>(base + (to << 3)), inc);
+  if (COUNT64) {   // a bead changes only its own type's 32-bit half of the word
+    const uint32_t half = is_b ? 4u : 0u;
+    atomicAdd(reinterpret_cast<unsigned int *>(base + (from << 3) + half), 0xFFFFFFFFu);
+    atomicAdd(reinterpret_cast<unsigned int *>(base + (to << 3) + half), 1u);
   } else {
     const unsigned int inc = is_b ? (1u << 16) : 1u;
     atomicAdd(reinterpret_cast<unsigned int *>(base + (from << 2)), 0u - inc);
