@@ -44,13 +44,19 @@ def field_bytes(w):
     return (cw + 8) * w.n_cells   # counts read, two fields written
 
 
+# Sources the sweep kernels and their launches are built from.
+SWEEP_SOURCES = ("include/soma.h", "paper_1711_03828_amd/csrc/soma_api.hip",
+                 "paper_1711_03828_amd/csrc/soma_device.hpp",
+                 "paper_1711_03828_amd/csrc/soma_mlp.hpp",
+                 "paper_1711_03828_amd/csrc/soma_sweep.hpp")
+
+
 def kernel_source_digest() -> str:
-    """SHA-1 of the HIP sources, to tell whether stored counters still apply."""
-    import glob
+    """SHA-1 of the sweep kernels' sources, to tell whether stored counters still apply."""
     import hashlib
     h = hashlib.sha1()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1711_03828_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 

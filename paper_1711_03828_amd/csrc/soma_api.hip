@@ -656,6 +656,9 @@ int32_t soma_observables(soma_system *sys, soma_obs *out, void *stream) {
     a.n_chains = S.n_chains;
     a.n = S.n;
     a.n_a = S.n_a;
+    a.seg = 1;
+    while (a.seg < S.n && a.seg < 64) a.seg <<= 1;
+    a.inv_n = 1.0 / (double)S.n;
     a.half_k0 = 0.5 * (double)S.k0;
     a.inv_nref = 1.0 / (double)c->n_ref;
     a.grid = sys->grid;

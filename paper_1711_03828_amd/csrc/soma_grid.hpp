@@ -26,7 +26,7 @@ __global__ __launch_bounds__(256) void density_hist_kernel(
   if (b >= n_beads) return;
   const float *r = pos + 3 * b;
   const uint32_t cell = cell_of(g, r[0], r[1], r[2]);
-  const uint32_t i = (uint32_t)(b % n);
+  const uint32_t i = n_beads <= 0xFFFFFFFFull ? (uint32_t)b % n : (uint32_t)(b % n);
   if (COUNT64) {
     const unsigned long long inc = 1ull << (i < n_a ? 0u : 32u);
     atomicAdd(reinterpret_cast<unsigned long long *>(counts) + cell, inc);

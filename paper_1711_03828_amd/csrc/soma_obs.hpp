@@ -24,6 +24,8 @@ struct ObsArgs {
   const float *pos;
   const float *omega;
   uint32_t n_chains, n, n_a;
+  uint32_t seg;      // lanes per chain: smallest power of two >= n, at most 64
+  double inv_n;      // 1 / n
   double half_k0;
   double inv_nref;
   Grid grid;
@@ -46,45 +48,59 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*s)[NV]) {
     for (int j = 0; j < NV; ++j) v[j] = ((s[0][j] + s[1][j]) + s[2][j]) + s[3][j];
 }
 
-// One thread per chain: Re^2 = |r_{N-1} - r_0|^2, Rg^2 = (1/N) sum |r_i - r_cm|^2,
-// sum of squared bond lengths, bond energy (k0/2) sum b^2 (Eqs. (1)-(2)) and
-// field energy sum_i omega_t(c_i) / N (Eq. (13)); partial sums per block.
+// Per-chain observables, Eqs. (1)-(2) and (13): Re^2 = |r_{N-1} - r_0|^2,
+// Rg^2 = (1/N) sum |r_i - r_cm|^2, sum of squared bond lengths, bond energy
+// (k0/2) sum b^2 and field energy sum_i omega_t(c_i) / N. A chain occupies a
+// segment of `seg` lanes (the smallest power of two >= N, at most 64) and bead
+// i sits on lane i mod seg, so a wave reads 64/seg whole chains with adjacent
+// lanes on adjacent beads. A block of four waves covers 256 consecutive chains
+// (wave w the 64 from 64 w, seg groups of 64/seg chains). Per-lane FP64 sums,
+// one fixed-order block reduction into a partial per block.
 __global__ __launch_bounds__(256) void chain_obs_kernel(const ObsArgs a) {
   __shared__ double s[4][5];
-  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  double v[5] = {0, 0, 0, 0, 0};
-  if (c < a.n_chains) {
-    const float *p = a.pos + (size_t)c * a.n * 3;
-    double cx = 0, cy = 0, cz = 0, b2 = 0, ef = 0;
-    bool bad = false;
-    for (uint32_t i = 0; i < a.n; ++i) {
-      const float x = p[3 * i], y = p[3 * i + 1], z = p[3 * i + 2];
-      bad |= !(coord_ok(x) && coord_ok(y) && coord_ok(z));
-      cx += x; cy += y; cz += z;
-      if (i > 0) {
-        const double dx = (double)x - p[3 * i - 3], dy = (double)y - p[3 * i - 2],
-                     dz = (double)z - p[3 * i - 1];
-        b2 += dx * dx + dy * dy + dz * dz;
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  const uint32_t seg = a.seg, sl = lane & (seg - 1u), per = 64u / seg;
+  const uint32_t first = blockIdx.x * 256u + wv * 64u + lane / seg;
+  double re2 = 0, rg = 0, b2 = 0, ef = 0;
+  bool bad = false;
+  for (uint32_t g = 0; g < seg; ++g) {
+    const uint32_t c = first + g * per;
+    const bool live = c < a.n_chains;
+    const float *p = a.pos + (size_t)(live ? c : 0u) * a.n * 3;
+    double sx = 0, sy = 0, sz = 0;
+    if (live) {
+      for (uint32_t i = sl; i < a.n; i += seg) {
+        const float x = p[3 * i], y = p[3 * i + 1], z = p[3 * i + 2];
+        bad |= !(coord_ok(x) && coord_ok(y) && coord_ok(z));
+        sx += x; sy += y; sz += z;
+        if (i > 0) {
+          const double dx = (double)x - p[3 * i - 3], dy = (double)y - p[3 * i - 2],
+                       dz = (double)z - p[3 * i - 1];
+          b2 += dx * dx + dy * dy + dz * dz;
+        }
+        if (i == a.n - 1) {
+          const double ex = (double)x - p[0], ey = (double)y - p[1], ez = (double)z - p[2];
+          re2 += ex * ex + ey * ey + ez * ez;
+        }
+        const uint32_t cell = cell_of(a.grid, x, y, z);
+        ef += (double)a.omega[(i < a.n_a ? 0u : a.grid.n_cells) + cell];
       }
-      const uint32_t cell = cell_of(a.grid, x, y, z);
-      ef += (double)a.omega[(i < a.n_a ? 0u : a.grid.n_cells) + cell];
     }
-    if (bad) atomicOr(a.err, SOMA_FLAG_POSITION_BIT);
-    const double inv_n = 1.0 / (double)a.n;
-    cx *= inv_n; cy *= inv_n; cz *= inv_n;
-    double rg = 0;
-    for (uint32_t i = 0; i < a.n; ++i) {
-      const double dx = p[3 * i] - cx, dy = p[3 * i + 1] - cy, dz = p[3 * i + 2] - cz;
-      rg += dx * dx + dy * dy + dz * dz;
+    for (uint32_t off = seg >> 1; off > 0; off >>= 1) {   // sums within the segment
+      sx += __shfl_xor(sx, off, 64);
+      sy += __shfl_xor(sy, off, 64);
+      sz += __shfl_xor(sz, off, 64);
     }
-    const float *q = p + 3 * (a.n - 1);
-    const double ex = (double)q[0] - p[0], ey = (double)q[1] - p[1], ez = (double)q[2] - p[2];
-    v[0] = ex * ex + ey * ey + ez * ez;
-    v[1] = rg * inv_n;
-    v[2] = b2;
-    v[3] = a.half_k0 * b2;
-    v[4] = ef * a.inv_nref;
+    if (live) {
+      const double cx = sx * a.inv_n, cy = sy * a.inv_n, cz = sz * a.inv_n;
+      for (uint32_t i = sl; i < a.n; i += seg) {
+        const double dx = p[3 * i] - cx, dy = p[3 * i + 1] - cy, dz = p[3 * i + 2] - cz;
+        rg += dx * dx + dy * dy + dz * dz;
+      }
+    }
   }
+  if (bad) atomicOr(a.err, SOMA_FLAG_POSITION_BIT);
+  double v[5] = {re2, rg * a.inv_n, b2, a.half_k0 * b2, ef * a.inv_nref};
   block_sum<5>(v, s);
   if (threadIdx.x == 0) {
     ObsPartial o;

@@ -365,6 +365,20 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
   const uint32_t first = set_order_bit(a, m, wa0.x);
   const bool b0 = i0 >= a.n_a, b1 = i1 >= a.n_a;
 
+  // A bead's position does not change before its own pass, so the old cells
+  // of both beads are known up front, and with the kept gradient field (one
+  // gather per cell) so are their field values and gradients.
+  uint32_t ox0, oy0, oz0, ox1, oy1, oz1;
+  cell3(a.grid, r0.x, r0.y, r0.z, ox0, oy0, oz0);
+  cell3(a.grid, r1.x, r1.y, r1.z, ox1, oy1, oz1);
+  const uint32_t co0 = cell_index(a.grid, ox0, oy0, oz0), co1 = cell_index(a.grid, ox1, oy1, oz1);
+  F3 g0 = {0.f, 0.f, 0.f}, g1 = {0.f, 0.f, 0.f};
+  float f0 = 0.f, f1 = 0.f;
+  if (a.grad) {
+    if (m.has0) f0 = field_and_grad(a, b0 ? a.grid.n_cells : 0u, co0, ox0, oy0, oz0, g0);
+    if (m.has1) f1 = field_and_grad(a, b1 ? a.grid.n_cells : 0u, co1, ox1, oy1, oz1, g1);
+  }
+
   uint32_t from0 = 0, to0 = 0, from1 = 0, to1 = 0;
   bool moved0 = false, moved1 = false;
   uint32_t n_acc = 0;
@@ -388,16 +402,15 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
     uint32_t co = 0, cn = 0;
     F3 rn = r;
     if (moving) {
-      uint32_t ox, oy, oz;
-      cell3(a.grid, r.x, r.y, r.z, ox, oy, oz);
-      co = cell_index(a.grid, ox, oy, oz);
+      co = odd ? co1 : co0;
       const F3 el = {r.x - left.x, r.y - left.y, r.z - left.z};
       const F3 er = {r.x - right.x, r.y - right.y, r.z - right.z};
       float xi0, xi1, xi2, xi3;
       box_muller(w.x, w.y, xi0, xi1);
       box_muller(w.z, w.w, xi2, xi3);
-      F3 g_old;
-      const float w_old = field_and_grad(a, pl, co, ox, oy, oz, g_old);
+      F3 g_old = sel(odd, g1, g0);
+      float w_old = odd ? f1 : f0;
+      if (!a.grad) w_old = field_and_grad(a, pl, co, odd ? ox1 : ox0, odd ? oy1 : oy0, odd ? oz1 : oz0, g_old);
       const F3 f_old = {-a.k0 * (wl * el.x + wr * er.x) - a.inv_nref * g_old.x,
                         -a.k0 * (wl * el.y + wr * er.y) - a.inv_nref * g_old.y,
                         -a.k0 * (wl * el.z + wr * er.z) - a.inv_nref * g_old.z};
