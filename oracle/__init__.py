@@ -67,6 +67,11 @@ def lib() -> ctypes.CDLL:
         L.orc_mc_sweep.argtypes = [P, u32, u32, u32, f32, u32, P, u32, u32, u32, u32,
                                    f32, u64, u32, u32, u32, u32, P, i32]
         L.orc_mc_sweep.restype = u64
+        L.orc_mc_sweep_molecule.argtypes = [P, u32, u32, u32, f32, u32, P, u32, u32, u32, f32,
+                                            u64, u32, u32, u32, P, P, ctypes.c_int]
+        L.orc_mc_sweep_molecule.restype = u64
+        L.orc_pick_bead.argtypes = [u32, u32]
+        L.orc_pick_bead.restype = u32
         L.orc_brick_cell_batch.argtypes = [u64, P, u32, u32, u32, P]
         L.orc_init_chains.argtypes = [P, u32, u32, f32, u32, u32, u32, u64, u32, u32,
                                       u32, u32]
@@ -164,6 +169,31 @@ def mc_sweep(pos: np.ndarray, sp: Species, omega: np.ndarray, grid, *, k0, n_ref
                              set_order, _ptr(flags) if flags is not None else None,
                              threads)
     return acc, flags
+
+
+def mc_sweep_molecule(pos: np.ndarray, sp: Species, omega: np.ndarray, grid, *, k0, n_ref,
+                      step, seed, sweep, replica=0, chain_base=0, want_flags=False,
+                      threads=1):
+    """In-place local-move sweep in the molecule-parallel order (N attempts per
+    chain on randomly picked beads).  Returns (n_accepted, accept flags or None,
+    picked beads or None), the last two per attempt [n_chains * N]."""
+    assert pos.dtype == np.float32 and pos.flags.c_contiguous
+    assert pos.size == sp.n_chains * sp.n * 3
+    nx, ny, nz = grid
+    omega = _c(omega, np.float32)
+    assert omega.size == 2 * nx * ny * nz
+    flags = np.zeros(sp.n_chains * sp.n, np.uint8) if want_flags else None
+    picked = np.zeros(sp.n_chains * sp.n, np.uint32) if want_flags else None
+    acc = lib().orc_mc_sweep_molecule(_ptr(pos), sp.n_chains, sp.n, sp.n_a,
+                                      float(np.float32(k0)), n_ref, _ptr(omega), nx, ny, nz,
+                                      float(np.float32(step)), seed, sweep, replica, chain_base,
+                                      _ptr(flags) if flags is not None else None,
+                                      _ptr(picked) if picked is not None else None, threads)
+    return acc, flags, picked
+
+
+def pick_bead(word: int, n: int) -> int:
+    return lib().orc_pick_bead(int(word), int(n))
 
 
 def brick_cell(k: np.ndarray, grid) -> np.ndarray:

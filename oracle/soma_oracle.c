@@ -278,13 +278,11 @@ static void orc_force(const float *r, const float *chain, uint32_t i,
 /* accept_flags (n_chains * N bytes, may be NULL) records 1 for an accepted    */
 /* move.  Returns the number of accepted moves.                                */
 /* ------------------------------------------------------------------------- */
-static int orc_move_local(float *chain, uint32_t c_id, uint32_t i, uint32_t n,
-                          uint32_t n_a, double k0, const float *omega,
-                          uint64_t n_cells, uint32_t nx, uint32_t ny,
-                          uint32_t nz, uint32_t n_ref, float a, uint64_t seed,
-                          uint32_t sweep, uint32_t replica) {
-  uint32_t w[4];
-  orc_draw(seed, c_id, i, ORC_PURPOSE_MOVE_A, sweep, replica, w);
+/* One local attempt on bead i from the four words w of its draw. */
+static int orc_local_attempt(float *chain, uint32_t i, uint32_t n, uint32_t n_a,
+                             double k0, const float *omega, uint64_t n_cells,
+                             uint32_t nx, uint32_t ny, uint32_t nz,
+                             uint32_t n_ref, float a, const uint32_t w[4]) {
   float *r = chain + 3 * i;
   float trial[3];
   for (int d = 0; d < 3; ++d) trial[d] = fmaf(a, orc_v11(w[d]), r[d]);
@@ -299,6 +297,17 @@ static int orc_move_local(float *chain, uint32_t c_id, uint32_t i, uint32_t n,
   int accept = (d_e <= 0.0) || (u < exp(-d_e));
   if (accept) memcpy(r, trial, sizeof trial);
   return accept;
+}
+
+static int orc_move_local(float *chain, uint32_t c_id, uint32_t i, uint32_t n,
+                          uint32_t n_a, double k0, const float *omega,
+                          uint64_t n_cells, uint32_t nx, uint32_t ny,
+                          uint32_t nz, uint32_t n_ref, float a, uint64_t seed,
+                          uint32_t sweep, uint32_t replica) {
+  uint32_t w[4];
+  orc_draw(seed, c_id, i, ORC_PURPOSE_MOVE_A, sweep, replica, w);
+  return orc_local_attempt(chain, i, n, n_a, k0, omega, n_cells, nx, ny, nz,
+                           n_ref, a, w);
 }
 
 static int orc_move_smc(float *chain, uint32_t c_id, uint32_t i, uint32_t n,
@@ -375,6 +384,58 @@ uint64_t orc_mc_sweep(float *pos, uint32_t n_chains, uint32_t n,
         accepted += (uint64_t)acc;
         if (accept_flags) accept_flags[(uint64_t)c * n + i] = (uint8_t)acc;
       }
+    }
+  }
+  return accepted;
+}
+
+/* ------------------------------------------------------------------------- */
+/* One MC sweep with local moves in the molecule-parallel order (Sec. 3.1.2,   */
+/* scheme 1, "parallelization over distinct molecules"): every chain makes N  */
+/* attempts one after another; attempt s picks its bead uniformly at random,  */
+/* independently of the configuration, so a bead is attempted once per sweep */
+/* on average and each attempt satisfies detailed balance.                    */
+/*                                                                             */
+/* Random numbers (this project's counter layout, Philox as above):           */
+/*   bead of attempt s: word s mod 4 of the purpose-7 block with bead field   */
+/*     floor(s/4), mapped to i = floor(word * N / 2^32);                      */
+/*   the attempt itself: the purpose-6 block with bead field s, words 0-2     */
+/*     the displacement, word 3 the acceptance, as for a LOCAL move.          */
+/* accept_flags and picked (n_chains * N entries each, may be NULL) record    */
+/* per attempt whether it was accepted and which bead it moved.              */
+/* ------------------------------------------------------------------------- */
+#define ORC_PURPOSE_MOLECULE 6u
+#define ORC_PURPOSE_PICK 7u
+
+uint32_t orc_pick_bead(uint32_t word, uint32_t n) {
+  return (uint32_t)(((uint64_t)word * (uint64_t)n) >> 32);
+}
+
+uint64_t orc_mc_sweep_molecule(float *pos, uint32_t n_chains, uint32_t n,
+                               uint32_t n_a, float k0, uint32_t n_ref,
+                               const float *omega, uint32_t nx, uint32_t ny,
+                               uint32_t nz, float step, uint64_t seed,
+                               uint32_t sweep, uint32_t replica,
+                               uint32_t chain_base, uint8_t *accept_flags,
+                               uint32_t *picked, int n_threads) {
+  uint64_t n_cells = (uint64_t)nx * ny * nz;
+  uint64_t accepted = 0;
+#pragma omp parallel for schedule(static) reduction(+ : accepted) num_threads(n_threads > 0 ? n_threads : 1)
+  for (int64_t c = 0; c < (int64_t)n_chains; ++c) {
+    float *chain = pos + (uint64_t)c * n * 3;
+    uint32_t c_id = chain_base + (uint32_t)c;
+    uint32_t sel[4] = {0, 0, 0, 0};
+    for (uint32_t s = 0; s < n; ++s) {
+      if (s % 4u == 0u)
+        orc_draw(seed, c_id, s / 4u, ORC_PURPOSE_PICK, sweep, replica, sel);
+      uint32_t i = orc_pick_bead(sel[s % 4u], n);
+      uint32_t w[4];
+      orc_draw(seed, c_id, s, ORC_PURPOSE_MOLECULE, sweep, replica, w);
+      int acc = orc_local_attempt(chain, i, n, n_a, (double)k0, omega, n_cells,
+                                  nx, ny, nz, n_ref, step, w);
+      accepted += (uint64_t)acc;
+      if (accept_flags) accept_flags[(uint64_t)c * n + s] = (uint8_t)acc;
+      if (picked) picked[(uint64_t)c * n + s] = i;
     }
   }
   return accepted;
