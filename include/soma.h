@@ -67,6 +67,12 @@ typedef enum soma_status {
 #define SOMA_MOVE_SMC 1u   /* force-biased (smart MC) proposal, Metropolis-Hastings */
 #define SOMA_MOVE_MIXED 2u /* learned proposal with probability p_learn, else local; MH */
 
+/* Iteration orders of local moves (Sec. 3.1.2). */
+#define SOMA_SCHEME_SET 0u      /* per chain, the even and the odd beads as two sets in random
+                                   order, each set moved at once (default) */
+#define SOMA_SCHEME_MOLECULE 1u /* one thread per chain making N attempts one after another,
+                                   each on a bead picked at random */
+
 /* Device error word bits (returned by soma_check / soma_observables). */
 #define SOMA_FLAG_POSITION 1u /* soma_observables found a position non-finite or |x| >= 2^22 */
 #define SOMA_FLAG_NETWORK 2u  /* a learned move met a non-finite network output (rejected) */
@@ -191,6 +197,27 @@ int32_t soma_set_grad_field(soma_system *sys, void *grad, uint64_t grad_bytes, v
  * A multiple of 8 keeps each XCD on one contiguous range of chains. */
 int32_t soma_set_sweep_blocks(soma_system *sys, uint32_t blocks);
 
+/* Iteration order of SOMA_MOVE_LOCAL sweeps (Sec. 3.1.2, schemes 2 and 1).
+ * SOMA_SCHEME_SET (default): every bead is attempted once per sweep, the two
+ * independent sets of a chain in a random order per chain and sweep.
+ * SOMA_SCHEME_MOLECULE: each chain makes N attempts in sequence, attempt s on
+ * bead floor(w N / 2^32), w = word s mod 4 of the chain's Philox block
+ * (chain, floor(s/4) | 7 << 16, sweep, replica); the attempt draws from the
+ * block (chain, s | 6 << 16, sweep, replica).  Both orders sample the same
+ * distribution along different trajectories.  With SOMA_SCHEME_MOLECULE,
+ * smart-MC and mixed sweeps and batched sweeps return SOMA_E_UNSUPPORTED,
+ * and soma_set_sweep_blocks has no effect.  Capture graphs again after a
+ * change.  Returns SOMA_E_INVAL for an unknown scheme. */
+int32_t soma_set_scheme(soma_system *sys, uint32_t scheme);
+
+/* Times `cycles` local-move SCMF cycles (after one warm-up cycle) with each
+ * order, SET first, and keeps the faster one (*chosen; ms, if not NULL,
+ * receives {SET, MOLECULE} milliseconds per cycle).  The system advances by
+ * 2 (1 + cycles) cycles, so the trajectory differs from an untimed run; the
+ * sampled distribution does not.  BLOCKING. */
+int32_t soma_choose_scheme(soma_system *sys, uint32_t cycles, void *stream, uint32_t *chosen,
+                           float *ms);
+
 /* Recounts buf->counts from buf->pos (cleared first).  Needed only after the
  * caller has changed positions outside the library.  Asynchronous. */
 int32_t soma_rebuild_histogram(soma_system *sys, void *stream);
@@ -231,7 +258,7 @@ int32_t soma_cycle(soma_system *sys, uint32_t n_cycles, uint32_t move_kind, void
  * replays it n_launches times on `stream` (asynchronous).  A replay gives the
  * same bits as the same cycles called one by one.  The graph holds the launch
  * shape and buffers of capture time: capture again after
- * soma_set_sweep_blocks.  The graph contains kernel nodes only. */
+ * soma_set_sweep_blocks or soma_set_scheme.  The graph contains kernel nodes only. */
 int32_t soma_capture_cycle(soma_system *sys, uint32_t cycles, uint32_t move_kind);
 int32_t soma_run_cycle(soma_system *sys, uint32_t n_launches, void *stream);
 

@@ -16,6 +16,7 @@
 #include "soma_grid.hpp"
 #include "soma_obs.hpp"
 #include "soma_sweep.hpp"
+#include "soma_molecule.hpp"
 #include "soma_train.hpp"
 #include "soma_batch.hpp"
 #include "soma_sq.hpp"
@@ -257,6 +258,7 @@ struct soma_system {
   uint64_t mixed_moves = 0;   // bead moves made by mixed sweeps (local or learned)
   uint32_t net_mask = 0;      // species with an installed network (bit per species)
   uint32_t substeps = 1;      // field refreshes per SCMF cycle (chain subsets)
+  uint32_t scheme = SOMA_SCHEME_SET;  // iteration order of local moves
   float4 *grad = nullptr;     // optional gradient field (caller-owned), see soma_set_grad_field
   unsigned char *ws = nullptr;
   CycleGraph graph;
@@ -365,12 +367,19 @@ int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s, uint32_t of
     a.sub_j = j;
     a.n_sub = subset_size(S.n_chains, k, j);
     if (a.n_sub == 0) continue;
+    const bool c64 = c->count_width == 32;
+    if (kind == SOMA_MOVE_LOCAL && sys->scheme == SOMA_SCHEME_MOLECULE) {
+      const dim3 grid((a.n_sub + 255u) / 256u);
+      if (c64) hipLaunchKernelGGL(soma::mc_sweep_molecule_kernel<true>, grid, dim3(256), 0, s, a);
+      else hipLaunchKernelGGL(soma::mc_sweep_molecule_kernel<false>, grid, dim3(256), 0, s, a);
+      LAUNCH_TRY();
+      continue;
+    }
     const uint64_t chains_per_block = 4ull * a.chains_per_wave;
     uint64_t blocks = (a.n_sub + chains_per_block - 1) / chains_per_block;
     if (kind == SOMA_MOVE_LOCAL && sys->sweep_blocks && sys->sweep_blocks < blocks)
       blocks = sys->sweep_blocks;
     const bool v2 = species_vec2(sys, sp);
-    const bool c64 = c->count_width == 32;
     const dim3 grid((uint32_t)blocks);
     if (c64) {
       if (v2) launch_sweep_t<true, true>(kind, grid, s, a, mx);
@@ -399,6 +408,8 @@ int32_t check_kind(soma_system *sys, uint32_t move_kind) {
     return fail(SOMA_E_INVAL, "smart-MC moves need smc_a > 0");
   if (move_kind != SOMA_MOVE_SMC && !(sys->cfg.local_a < 1.f))
     return fail(SOMA_E_UNSUPPORTED, "local moves need a half-width below one cell");
+  if (move_kind != SOMA_MOVE_LOCAL && sys->scheme != SOMA_SCHEME_SET)
+    return fail(SOMA_E_UNSUPPORTED, "the molecule-parallel order has local moves only");
   return SOMA_OK;
 }
 
@@ -594,6 +605,14 @@ int32_t soma_run_cycle(soma_system *sys, uint32_t n_launches, void *stream) {
     HIP_TRY(hipGraphLaunch(sys->graph.exec, s));
     sys->count_sweeps(sys->graph.kind, sys->graph.cycles);
   }
+  return SOMA_OK;
+}
+
+int32_t soma_set_scheme(soma_system *sys, uint32_t scheme) {
+  if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
+  if (scheme != SOMA_SCHEME_SET && scheme != SOMA_SCHEME_MOLECULE)
+    return fail(SOMA_E_INVAL, "scheme %u", scheme);
+  sys->scheme = scheme;
   return SOMA_OK;
 }
 
@@ -1166,6 +1185,8 @@ int32_t batch_check_kind(soma_batch *b, uint32_t kind) {
   for (soma_system *x : b->sys) {
     const int32_t rc = check_kind(x, kind);
     if (rc) return rc;
+    if (x->scheme != SOMA_SCHEME_SET)
+      return fail(SOMA_E_UNSUPPORTED, "batched sweeps use the SET order only");
   }
   return SOMA_OK;
 }
@@ -1472,15 +1493,46 @@ int32_t soma_autotune(soma_system *sys, uint32_t cycles, uint32_t move_kind,
   const int32_t rc = check_kind(sys, move_kind);
   if (rc) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  // only the local-move kernel has a second launch shape (persistent blocks)
+  // only the SET-order local-move kernel has a second launch shape (persistent blocks)
   static const Shape local_shapes[] = {{0, 0}, {0, 1024}, {0, 2048}, {0, 4096}};
-  const uint32_t n_shapes = move_kind == SOMA_MOVE_LOCAL ? 4u : 1u;
-  char kind_s[16];
-  std::snprintf(kind_s, sizeof kind_s, "sys/k%u/", move_kind);
+  const uint32_t n_shapes = move_kind == SOMA_MOVE_LOCAL && sys->scheme == SOMA_SCHEME_SET ? 4u : 1u;
+  char kind_s[24];
+  std::snprintf(kind_s, sizeof kind_s, "sys/k%u/s%u/", move_kind, sys->scheme);
   return tune(local_shapes, n_shapes, cycles, cache_path, kind_s + system_key(sys), s,
               [&](uint32_t, uint32_t grid) { sys->sweep_blocks = grid; },
               [&]() -> int32_t { return soma_cycle(sys, 1, move_kind, stream); },
               out);
+}
+
+int32_t soma_choose_scheme(soma_system *sys, uint32_t cycles, void *stream, uint32_t *chosen,
+                           float *ms) {
+  if (!sys || !chosen) return fail(SOMA_E_INVAL, "system or chosen is NULL");
+  if (cycles == 0) return fail(SOMA_E_INVAL, "cycles must be positive");
+  const uint32_t keep = sys->scheme;
+  sys->scheme = SOMA_SCHEME_SET;
+  int32_t rc = check_kind(sys, SOMA_MOVE_LOCAL);
+  if (rc) {
+    sys->scheme = keep;
+    return rc;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  float t[2] = {0.f, 0.f};
+  for (uint32_t k = 0; k < 2 && !rc; ++k) {
+    sys->scheme = k;
+    rc = time_cycles(s, cycles, [&]() -> int32_t { return soma_cycle(sys, 1, SOMA_MOVE_LOCAL, stream); },
+                     &t[k]);
+  }
+  if (rc) {
+    sys->scheme = keep;
+    return rc;
+  }
+  sys->scheme = t[1] < t[0] ? SOMA_SCHEME_MOLECULE : SOMA_SCHEME_SET;
+  *chosen = sys->scheme;
+  if (ms) {
+    ms[0] = t[0];
+    ms[1] = t[1];
+  }
+  return SOMA_OK;
 }
 
 int32_t soma_batch_autotune(soma_batch *b, uint32_t cycles, uint32_t move_kind,

@@ -135,6 +135,14 @@ class Melt:
     def autotune(self, cycles: int, move_kind=C.SOMA_MOVE_LOCAL, cache_path=None, stream=None):
         return C.soma_autotune(self.handle, cycles, move_kind, cache_path, _stream(stream))
 
+    def set_scheme(self, scheme: int):
+        """Iteration order of local moves: C.SOMA_SCHEME_SET or C.SOMA_SCHEME_MOLECULE."""
+        C.soma_set_scheme(self.handle, scheme)
+
+    def choose_scheme(self, cycles: int, stream=None):
+        """Times both orders and keeps the faster; returns (scheme, [ms SET, ms MOLECULE])."""
+        return C.soma_choose_scheme(self.handle, cycles, _stream(stream))
+
     def counts_planes(self) -> np.ndarray:
         """Unpack the packed counts to uint32 [2, n_cells] on the host."""
         c = self.counts.cpu().numpy()

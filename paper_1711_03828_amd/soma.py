@@ -24,6 +24,8 @@ SOMA_E_DEVICE_FLAG = -5
 SOMA_MOVE_LOCAL = 0
 SOMA_MOVE_SMC = 1
 SOMA_MOVE_MIXED = 2
+SOMA_SCHEME_SET = 0
+SOMA_SCHEME_MOLECULE = 1
 SOMA_FLAG_POSITION = 1
 SOMA_FLAG_NETWORK = 2
 SOMA_ALL_SPECIES = 0xFFFFFFFF
@@ -106,6 +108,9 @@ _SIGS = {
     "soma_update_fields": ([_P, _P], _i32),
     "soma_rebuild_histogram": ([_P, _P], _i32),
     "soma_set_sweep_blocks": ([_P, _u32], _i32),
+    "soma_set_scheme": ([_P, _u32], _i32),
+    "soma_choose_scheme": ([_P, _u32, _P, ctypes.POINTER(_u32), ctypes.POINTER(ctypes.c_float)],
+                           _i32),
     "soma_observables": ([_P, ctypes.POINTER(soma_obs), _P], _i32),
     "soma_check": ([_P, _pu32, _P], _i32),
     "soma_get_sweep": ([_P, _pu64], _i32),
@@ -192,6 +197,18 @@ def soma_update_fields(h, stream: int) -> None:
 
 def soma_set_sweep_blocks(h, blocks: int) -> None:
     _check(_lib.soma_set_sweep_blocks(h, blocks))
+
+
+def soma_set_scheme(h, scheme: int) -> None:
+    _check(_lib.soma_set_scheme(h, scheme))
+
+
+def soma_choose_scheme(h, cycles: int, stream):
+    """Returns (chosen scheme, [ms per cycle SET, MOLECULE])."""
+    chosen = _u32()
+    ms = (ctypes.c_float * 2)()
+    _check(_lib.soma_choose_scheme(h, cycles, stream, ctypes.byref(chosen), ms))
+    return chosen.value, [ms[0], ms[1]]
 
 
 def soma_rebuild_histogram(h, stream: int) -> None:

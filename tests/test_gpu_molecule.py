@@ -1,0 +1,218 @@
+"""GPU parity of the molecule-parallel order of local moves (Sec. 3.1.2,
+scheme 1: one thread per chain, N attempts in sequence on randomly picked
+beads) against the oracle's sweep in the same order.
+
+Bars, as for the SET order: one sweep from identical state and fields gives
+bit-identical positions for every chain without an accept-decision mismatch
+(FP32 energies on the device, FP64 in the oracle), mismatches at most 1e-6 of
+the attempts, rounded up; the kept histogram equals the recount of the final
+positions bit for bit; ideal chain and 3-bead statistics as the model fixes
+them; graph replays and chain subsets give the bits of eager cycles.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import Species, references
+from tests.gpu_helpers import constants, custom_config, device_config, flush, walks_for
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+RE = 6.0
+
+
+@pytest.fixture(scope="module")
+def C():
+    from paper_1711_03828_amd import soma
+    return soma
+
+
+def _melt(C, orc, w, seed):
+    from paper_1711_03828_amd.melt import Melt
+    k0, a, A, inv_rho = constants(w)
+    pos = walks_for(w, seed)
+    melt = Melt(device_config(w), positions=torch.from_numpy(pos))
+    melt.set_scheme(C.SOMA_SCHEME_MOLECULE)
+    sp = [Species(s.n_chains, s.n, s.n_a) for s in w.species]
+    omega = orc.field_f32(orc.density_hist(pos, sp, w.grid), inv_rho, np.float32(w.chi_n),
+                          np.float32(w.kappa_n))
+    return melt, pos.copy(), omega, sp, (k0, a)
+
+
+def _bad_chains(got, exp, n):
+    g = got.reshape(-1, n, 3)
+    e = exp.reshape(-1, n, 3)
+    return (g != e).reshape(g.shape[0], -1).any(axis=1)
+
+
+RAGGED = synth.Workload("ragged", (17, 23, 9),
+                        (synth.SpeciesSpec(301, 32, 16), synth.SpeciesSpec(77, 16, 16),
+                         synth.SpeciesSpec(45, 17, 4), synth.SpeciesSpec(13, 64, 13),
+                         synth.SpeciesSpec(3, 1, 1)),
+                        6.0, 32, 25.0, 50.0, 32)
+
+
+@pytest.mark.parametrize("wname", ["c1", "ragged"])
+def test_one_sweep_parity(C, orc, wname):
+    w = synth.scaled(synth.C1_SMALL, 16384, (48, 48, 48)) if wname == "c1" else RAGGED
+    flush("case molecule sweep", wname)
+    melt, pos, omega, sp, (k0, a) = _melt(C, orc, w, 61)
+    melt.sweep(1, C.SOMA_MOVE_LOCAL)
+    torch.cuda.synchronize()
+    got = melt.pos.cpu().numpy()
+    off = base = acc_total = bad = 0
+    for s in sp:
+        seg = pos[off:off + s.n_chains * s.n]
+        acc, _, _ = orc.mc_sweep_molecule(seg, s, omega, w.grid, k0=k0, n_ref=w.n_ref, step=a,
+                                          seed=w.seed, sweep=0, chain_base=base, threads=8)
+        acc_total += acc
+        bad += int(_bad_chains(got[off:off + s.n_chains * s.n], seg, s.n).sum())
+        off += s.n_chains * s.n
+        base += s.n_chains
+    moves = w.n_beads
+    allowed = math.ceil(1e-6 * moves)
+    flush("mismatched chains", bad, "allowed", allowed)
+    assert bad <= allowed
+    # kept histogram == recount of the final positions; == oracle histogram without mismatches
+    hist = melt.counts_planes()
+    n_a_beads = sum(s.n_chains * s.n_a for s in w.species)
+    assert (hist.sum(axis=1) == [n_a_beads, w.n_beads - n_a_beads]).all()
+    np.testing.assert_array_equal(hist, orc.density_hist(got, sp, w.grid))
+    if bad == 0:
+        np.testing.assert_array_equal(hist, orc.density_hist(pos, sp, w.grid))
+    obs = melt.observables()
+    assert obs.attempted[0] == moves
+    assert abs(int(obs.accepted[0]) - int(acc_total)) <= 64 * allowed
+    assert obs.counts_conserved == 1 and obs.error_flags == 0
+    melt.close()
+
+
+def test_cycles_parity_c1(C, orc):
+    w = synth.C1_SMALL
+    melt, pos, omega, sp, (k0, a) = _melt(C, orc, w, 62)
+    inv_rho = constants(w)[3]
+    for cyc in range(8):
+        melt.cycle(1)
+        orc.mc_sweep_molecule(pos, sp[0], omega, w.grid, k0=k0, n_ref=w.n_ref, step=a,
+                              seed=w.seed, sweep=cyc, threads=8)
+        omega = orc.field_f32(orc.density_hist(pos, sp, w.grid), inv_rho, np.float32(w.chi_n),
+                              np.float32(w.kappa_n))
+    torch.cuda.synchronize()
+    bad = _bad_chains(melt.pos.cpu().numpy(), pos, 32)
+    flush("chains differing after 8 cycles:", int(bad.sum()))
+    assert bad.sum() <= 8
+    if bad.sum() == 0:
+        np.testing.assert_array_equal(melt.omega.cpu().numpy(), omega)
+    melt.close()
+
+
+def test_graph_and_substeps_equal_eager(C, orc):
+    from paper_1711_03828_amd.melt import Melt
+    w = synth.C1_SMALL
+    pos = walks_for(w, 63)
+    runs = []
+    for mode in ("eager", "graph"):
+        m = Melt(device_config(w), positions=torch.from_numpy(pos))
+        m.set_scheme(C.SOMA_SCHEME_MOLECULE)
+        m.set_substeps(3)
+        if mode == "eager":
+            m.cycle(6)
+        else:
+            m.capture_cycle(2)
+            for _ in range(3):
+                m.run_cycle(1)
+                torch.cuda.synchronize()
+                m.observables()          # eager work between replays
+        torch.cuda.synchronize()
+        runs.append((m.pos.cpu().numpy(), m.counts_planes(), m.omega.cpu().numpy()))
+        m.close()
+    for x, y in zip(runs[0], runs[1]):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_unsupported_combinations_rejected(C):
+    from paper_1711_03828_amd.melt import Batch, Melt
+    w = synth.C1_SMALL
+    m = Melt(device_config(w))
+    with pytest.raises(RuntimeError):
+        C.soma_set_scheme(m.handle, 2)
+    m.set_scheme(C.SOMA_SCHEME_MOLECULE)
+    with pytest.raises(RuntimeError):
+        m.sweep(1, C.SOMA_MOVE_SMC)
+    b = Batch([m])
+    with pytest.raises(RuntimeError):
+        b.sweep(1, C.SOMA_MOVE_LOCAL)
+    m.set_scheme(C.SOMA_SCHEME_SET)
+    b.sweep(1, C.SOMA_MOVE_LOCAL)
+    b.close()
+    m.close()
+
+
+def test_choose_scheme(C):
+    from paper_1711_03828_amd.melt import Melt
+    w = synth.scaled(synth.C1_SMALL, 16384, (48, 48, 48))
+    m = Melt(device_config(w))
+    chosen, ms = m.choose_scheme(3)
+    flush("ms per cycle SET, MOLECULE:", ms, "chosen", chosen)
+    assert chosen in (C.SOMA_SCHEME_SET, C.SOMA_SCHEME_MOLECULE)
+    assert min(ms) > 0 and ms[chosen] == min(ms)
+    obs = m.observables()
+    assert obs.counts_conserved == 1 and obs.sweeps == 8
+    m.close()
+
+
+def test_ideal_chain_acceptance_and_moments(C):
+    from paper_1711_03828_amd.melt import Melt
+    n, n_chains = 32, 65536
+    w = synth.Workload("ideal", (48, 48, 48), (synth.SpeciesSpec(n_chains, n, 16),), RE, n,
+                       0.0, 0.0, 32)
+    k0 = float(constants(w)[0])
+    m = Melt(device_config(w, seed=21))
+    m.set_scheme(C.SOMA_SCHEME_MOLECULE)
+    m.omega.zero_()
+    m.sweep(20, C.SOMA_MOVE_LOCAL)
+    obs = m.observables()
+    rate = obs.accepted[0] / obs.attempted[0]
+    a = float(np.float32(0.1 * RE / math.sqrt(n - 1)))
+    exp = references.ideal_local_acceptance_chain(n, k0, a)
+    sigma = math.sqrt(exp * (1 - exp) / obs.attempted[0])
+    flush("acceptance", rate, "closed form", exp)
+    assert abs(rate - exp) < 6 * sigma + 1e-4
+    re2_exp = 3 * (n - 1) / k0
+    rg2_exp = (3 / k0) * (n * n - 1) / (6 * n)
+    for val, e, rel_sd in ((obs.re2_sum / n_chains, re2_exp, math.sqrt(2 / 3)),
+                           (obs.rg2_sum / n_chains, rg2_exp, 0.5)):
+        assert abs(val - e) < 5 * rel_sd * e / math.sqrt(n_chains), (val, e)
+    m.close()
+
+
+def test_three_bead_boltzmann_on_device(C):
+    from paper_1711_03828_amd.melt import Melt
+    L, n_chains = 4, 65536
+    grid = (L, L, L)
+    omega = synth.uniform_field(21, L ** 3, -2.0, 2.0)
+    pos = synth.gaussian_walks(24, n_chains, 3, grid, 1.0 / math.sqrt(3.0))
+    cfg = custom_config(grid, [Species(n_chains, 3, 2)], k0=3.0, n_ref=1, local_a=0.7, seed=98,
+                        count_width=32)
+    m = Melt(cfg, positions=torch.from_numpy(pos))
+    m.set_scheme(C.SOMA_SCHEME_MOLECULE)
+    m.omega.copy_(torch.from_numpy(omega))
+    m.sync_fields()
+    m.sweep(300, C.SOMA_MOVE_LOCAL)
+    torch.cuda.synchronize()
+    p = m.pos.cpu().numpy().astype(np.float64)
+    cells = np.floor(p).astype(np.int64) % L
+    lin = ((cells[:, 2] * L + cells[:, 1]) * L + cells[:, 0]).reshape(n_chains, 3)
+    dist = references.three_bead_cell_distribution(omega[0], omega[1], 3.0, L)
+    marg = [dist.sum(axis=(1, 2)), dist.sum(axis=(0, 2)), dist.sum(axis=(0, 1))]
+    for b in range(3):
+        pval, stat, dof = references.chi2_pvalue(np.bincount(lin[:, b], minlength=L ** 3), marg[b])
+        assert pval > 1e-4, (b, stat, dof)
+    obs = np.bincount(lin[:, 0] * L ** 3 + lin[:, 2], minlength=L ** 6)
+    pval, stat, dof = references.chi2_pvalue(obs, dist.sum(axis=1).ravel())
+    assert pval > 1e-4, (stat, dof)
+    m.close()
