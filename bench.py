@@ -279,6 +279,52 @@ def batched_leg(cycles: int):
             "acceptance": acc}
 
 
+def scheme_leg(cycles: int):
+    """The two iteration orders of local moves (Sec. 3.1.2) over system size, as in
+    the weak-scaling study of Sec. 4.2: homopolymer melts of N = 64 at
+    sqrt(Nbar) = 128 (8192 beads per Re0^3, Delta L = Re0/6, kappaN = 50) with
+    n = 2^7 .. 2^17 chains in a cube of side round(6 (n/128)^(1/3)) cells.  Each
+    order is autotuned (launch grid), then runs graph-replayed SCMF cycles (10
+    per graph) from the same initial state; bead moves per second per order
+    and size."""
+    import torch
+
+    from paper_1711_03828_amd import soma as C
+    from paper_1711_03828_amd.melt import Melt, make_config
+
+    stream = torch.cuda.current_stream()
+    rows = []
+    for e in range(7, 18, 2):
+        n = 1 << e
+        side = int(round(6 * (n / 128) ** (1 / 3)))
+        w = synth.Workload(f"homopolymer_N64_n{n}", (side, side, side),
+                           (synth.SpeciesSpec(n, 64, 64),), 6.0, 64, 0.0, 50.0, 16)
+        row = {"chains": n, "beads": w.n_beads, "grid": side}
+        for name, scheme in (("set", C.SOMA_SCHEME_SET), ("molecule", C.SOMA_SCHEME_MOLECULE)):
+            m = Melt(make_config(w))
+            m.set_scheme(scheme)
+            tune = m.autotune(3)
+            m.capture_cycle(10, C.SOMA_MOVE_LOCAL)
+            m.run_cycle(2)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            m.run_cycle(cycles // 10)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / (cycles // 10 * 10)
+            obs = m.observables()
+            row[name] = {"ms_per_cycle": ms, "bead_moves_per_s": w.n_beads * 1e3 / ms,
+                         "grid_blocks": tune.grid_blocks,
+                         "acceptance": obs.accepted[0] / max(1, obs.attempted[0])}
+            m.close()
+        row["set_over_molecule"] = row["set"]["bead_moves_per_s"] / row["molecule"]["bead_moves_per_s"]
+        print(f"# schemes n={n}: SET {row['set']['bead_moves_per_s']:.3e}, molecule "
+              f"{row['molecule']['bead_moves_per_s']:.3e} moves/s", file=sys.stderr, flush=True)
+        rows.append(row)
+    return {"workload": "homopolymer N=64, sqrt(Nbar)=128, n=2^7..2^17 chains",
+            "cycles": cycles // 10 * 10, "sizes": rows}
+
+
 def blend_leg(rate_cycles: int, tau_frames: int, frame_cycles: int, plain_mult: int,
               equil_cycles: int, tau_scale: float, substeps: int):
     """Ternary blend replicas (32 melts of A16B16 diblocks with A16 and B16
@@ -457,6 +503,8 @@ def main():
                     help="also run the ternary-blend batched learned-proposal measurement")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-replica batched measurement")
+    ap.add_argument("--no-schemes", action="store_true",
+                    help="skip the SET vs molecule-parallel comparison over system size")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -540,6 +588,21 @@ def main():
                          "achieved_GBs": field_bytes(w) / (field_ms * 1e-3) / 1e9},
         "acceptance": acc,
     }
+    if args.move == "local":
+        # the molecule-parallel order (Sec. 3.1.2, scheme 1) on the same melt
+        melt.set_scheme(C.SOMA_SCHEME_MOLECULE)
+        tune = melt.autotune(2)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        melt.cycle(10)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_mol = e0.elapsed_time(e1) / 10
+        result["molecule_order"] = {"ms_per_cycle": ms_mol,
+                                    "bead_moves_per_s": w.n_beads * 1e3 / ms_mol,
+                                    "grid_blocks": tune.grid_blocks}
+        melt.set_scheme(C.SOMA_SCHEME_SET)
+        C.soma_set_sweep_blocks(melt.handle, 0)
     melt.close()
     # the second move kind of this workload: smart-MC, with the kept gradient field
     melt = Melt(make_config(w))
@@ -571,6 +634,8 @@ def main():
                                                  args.equil_cycles, args.learned_substeps)
     if not args.no_batched:
         result["batched"] = batched_leg(50)
+    if not args.no_schemes:
+        result["schemes"] = scheme_leg(200)
     if args.blend:
         result["blend"] = blend_leg(50, args.tau_frames // 2, args.frame_cycles,
                                     args.plain_frame_mult, args.equil_cycles // 2, 1.0 / 16,

@@ -205,9 +205,10 @@ int32_t soma_set_sweep_blocks(soma_system *sys, uint32_t blocks);
  * (chain, floor(s/4) | 7 << 16, sweep, replica); the attempt draws from the
  * block (chain, s | 6 << 16, sweep, replica).  Both orders sample the same
  * distribution along different trajectories.  With SOMA_SCHEME_MOLECULE,
- * smart-MC and mixed sweeps and batched sweeps return SOMA_E_UNSUPPORTED,
- * and soma_set_sweep_blocks has no effect.  Capture graphs again after a
- * change.  Returns SOMA_E_INVAL for an unknown scheme. */
+ * smart-MC and mixed sweeps and batched sweeps return SOMA_E_UNSUPPORTED;
+ * soma_set_sweep_blocks then caps the grid of the molecule-order kernel
+ * (lanes loop over chains), which keeps fewer chains in flight.  Capture
+ * graphs again after a change.  Returns SOMA_E_INVAL for an unknown scheme. */
 int32_t soma_set_scheme(soma_system *sys, uint32_t scheme);
 
 /* Times `cycles` local-move SCMF cycles (after one warm-up cycle) with each

@@ -369,7 +369,9 @@ int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s, uint32_t of
     if (a.n_sub == 0) continue;
     const bool c64 = c->count_width == 32;
     if (kind == SOMA_MOVE_LOCAL && sys->scheme == SOMA_SCHEME_MOLECULE) {
-      const dim3 grid((a.n_sub + 255u) / 256u);
+      uint32_t blocks = (a.n_sub + 255u) / 256u;   // one lane per chain
+      if (sys->sweep_blocks && sys->sweep_blocks < blocks) blocks = sys->sweep_blocks;
+      const dim3 grid(blocks);
       if (c64) hipLaunchKernelGGL(soma::mc_sweep_molecule_kernel<true>, grid, dim3(256), 0, s, a);
       else hipLaunchKernelGGL(soma::mc_sweep_molecule_kernel<false>, grid, dim3(256), 0, s, a);
       LAUNCH_TRY();
@@ -1493,9 +1495,13 @@ int32_t soma_autotune(soma_system *sys, uint32_t cycles, uint32_t move_kind,
   const int32_t rc = check_kind(sys, move_kind);
   if (rc) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  // only the SET-order local-move kernel has a second launch shape (persistent blocks)
-  static const Shape local_shapes[] = {{0, 0}, {0, 1024}, {0, 2048}, {0, 4096}};
-  const uint32_t n_shapes = move_kind == SOMA_MOVE_LOCAL && sys->scheme == SOMA_SCHEME_SET ? 4u : 1u;
+  // only the local-move kernels have other launch shapes (persistent blocks); the
+  // molecule-order kernel also tries grids small enough to keep its chains in L2
+  static const Shape set_shapes[] = {{0, 0}, {0, 1024}, {0, 2048}, {0, 4096}};
+  static const Shape mol_shapes[] = {{0, 0}, {0, 256}, {0, 512}, {0, 1024}, {0, 2048}};
+  const bool mol = sys->scheme == SOMA_SCHEME_MOLECULE;
+  const Shape *local_shapes = mol ? mol_shapes : set_shapes;
+  const uint32_t n_shapes = move_kind == SOMA_MOVE_LOCAL ? (mol ? 5u : 4u) : 1u;
   char kind_s[24];
   std::snprintf(kind_s, sizeof kind_s, "sys/k%u/s%u/", move_kind, sys->scheme);
   return tune(local_shapes, n_shapes, cycles, cache_path, kind_s + system_key(sys), s,

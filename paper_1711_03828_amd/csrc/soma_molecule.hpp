@@ -17,13 +17,20 @@ constexpr uint32_t kPurposePick = 7u;      // block floor(s/4), word s mod 4: be
 // field energy change, Metropolis test), drawn from the purpose-6 block of
 // attempt s.  Each lane reads and writes its own chain in place, so a later
 // attempt sees every earlier one; the lanes of a wave touch 64 different
-// chains (384 B apart for N = 32), so these accesses are not coalesced.
+// chains (384 B apart for N = 32), so these accesses are not coalesced and
+// hit in L2 only while few chains are in flight.  The grid may therefore be
+// smaller than one lane per chain: lanes then loop over chains with the
+// grid's stride (chains running together on one XCD stay one contiguous,
+// spatially compact range).
 template <bool COUNT64>
 __global__ __launch_bounds__(256) void mc_sweep_molecule_kernel(const SweepArgs a_in) {
   const SweepArgs a = resolve_sweep(a_in, 0u);
-  const uint32_t cl = xcd_remap(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * 256u;
   uint32_t n_acc = 0;
-  if (cl < a.n_sub) {
+  for (uint64_t c64 = (uint64_t)xcd_remap(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
+       __ballot(c64 < a.n_sub) != 0ull; c64 += stride) {
+    if (c64 >= a.n_sub) continue;
+    const uint32_t cl = (uint32_t)c64;
     const uint32_t N = a.n;
     const uint32_t chain = cl * a.sub_k + a.sub_j;
     const uint32_t gchain = a.chain_base + chain;

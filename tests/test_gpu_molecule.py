@@ -134,6 +134,25 @@ def test_graph_and_substeps_equal_eager(C, orc):
         np.testing.assert_array_equal(x, y)
 
 
+def test_capped_grid_is_bit_identical(C):
+    from paper_1711_03828_amd.melt import Melt
+    w = RAGGED
+    pos = walks_for(w, 64)
+    runs = []
+    for blocks in (0, 1, 3, 8):
+        m = Melt(device_config(w), positions=torch.from_numpy(pos))
+        m.set_scheme(C.SOMA_SCHEME_MOLECULE)
+        C.soma_set_sweep_blocks(m.handle, blocks)
+        m.cycle(3)
+        torch.cuda.synchronize()
+        runs.append((m.pos.cpu().numpy(), m.counts_planes(), m.observables().accepted[0]))
+        m.close()
+    for r in runs[1:]:
+        np.testing.assert_array_equal(r[0], runs[0][0])
+        np.testing.assert_array_equal(r[1], runs[0][1])
+        assert r[2] == runs[0][2]
+
+
 def test_unsupported_combinations_rejected(C):
     from paper_1711_03828_amd.melt import Batch, Melt
     w = synth.C1_SMALL
