@@ -281,7 +281,7 @@ def batched_leg(cycles: int):
 
 def scheme_leg(cycles: int):
     """The two iteration orders of local moves (Sec. 3.1.2) over system size, as in
-    the weak-scaling study of Sec. 4.2: homopolymer melts of N = 64 at
+    the weak-scaling study of Sec. 5.2: homopolymer melts of N = 64 at
     sqrt(Nbar) = 128 (8192 beads per Re0^3, Delta L = Re0/6, kappaN = 50) with
     n = 2^7 .. 2^17 chains in a cube of side round(6 (n/128)^(1/3)) cells.  Each
     order is autotuned (launch grid), then runs graph-replayed SCMF cycles (10
