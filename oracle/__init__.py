@@ -60,9 +60,10 @@ def lib() -> ctypes.CDLL:
         L.orc_v11.argtypes = [u32]
         L.orc_v11.restype = f32
         L.orc_density_hist.argtypes = [P, u32, P, P, P, u32, u32, u32, P]
-        L.orc_field_f64.argtypes = [P, u64, f64, f64, f64, P]
-        L.orc_field_f32.argtypes = [P, u64, f32, f32, f32, P]
-        L.orc_h_nb.argtypes = [P, u64, f64, f64, f64, u32]
+        L.orc_field_f64.argtypes = [P, u64, f64, f64, f64, P, P, P]
+        L.orc_field_f32.argtypes = [P, u64, f32, f32, f32, P, P, P]
+        L.orc_h_nb.argtypes = [P, u64, f64, f64, f64, u32, P]
+        L.orc_set_forbidden.argtypes = [P]
         L.orc_h_nb.restype = f64
         L.orc_mc_sweep.argtypes = [P, u32, u32, u32, f32, u32, P, u32, u32, u32, u32,
                                    f32, u64, u32, u32, u32, u32, P, i32]
@@ -129,31 +130,59 @@ def density_hist(pos: np.ndarray, species: list[Species], grid) -> np.ndarray:
     return counts
 
 
-def field_f64(counts: np.ndarray, inv_rho: float, chi_n: float, kappa_n: float) -> np.ndarray:
+def _opt(a, dtype):
+    return None if a is None else _c(a, dtype)
+
+
+def field_f64(counts: np.ndarray, inv_rho: float, chi_n: float, kappa_n: float, ext=None,
+              forbid=None) -> np.ndarray:
+    """ext: optional float32 [2, n_cells] external field; forbid: optional packed
+    bit mask (uint32, bit c % 32 of word c // 32) of impenetrable cells."""
     counts = _c(counts, np.uint32)
     n_cells = counts.shape[-1]
+    ext, forbid = _opt(ext, np.float32), _opt(forbid, np.uint32)
     om = np.empty((2, n_cells), np.float64)
-    lib().orc_field_f64(_ptr(counts), n_cells, inv_rho, chi_n, kappa_n, _ptr(om))
+    lib().orc_field_f64(_ptr(counts), n_cells, inv_rho, chi_n, kappa_n,
+                        _ptr(ext) if ext is not None else None,
+                        _ptr(forbid) if forbid is not None else None, _ptr(om))
     return om
 
 
-def field_f32(counts: np.ndarray, inv_rho, chi_n, kappa_n) -> np.ndarray:
+def field_f32(counts: np.ndarray, inv_rho, chi_n, kappa_n, ext=None, forbid=None) -> np.ndarray:
     counts = _c(counts, np.uint32)
     n_cells = counts.shape[-1]
+    ext, forbid = _opt(ext, np.float32), _opt(forbid, np.uint32)
     om = np.empty((2, n_cells), np.float32)
     lib().orc_field_f32(_ptr(counts), n_cells, float(np.float32(inv_rho)),
-                        float(np.float32(chi_n)), float(np.float32(kappa_n)), _ptr(om))
+                        float(np.float32(chi_n)), float(np.float32(kappa_n)),
+                        _ptr(ext) if ext is not None else None,
+                        _ptr(forbid) if forbid is not None else None, _ptr(om))
     return om
 
 
-def h_nb(counts, inv_rho, chi_n, kappa_n, n_ref) -> float:
+def h_nb(counts, inv_rho, chi_n, kappa_n, n_ref, forbid=None) -> float:
     counts = _c(counts, np.uint32)
-    return lib().orc_h_nb(_ptr(counts), counts.shape[-1], inv_rho, chi_n, kappa_n, n_ref)
+    forbid = _opt(forbid, np.uint32)
+    return lib().orc_h_nb(_ptr(counts), counts.shape[-1], inv_rho, chi_n, kappa_n, n_ref,
+                          _ptr(forbid) if forbid is not None else None)
+
+
+class _walls:
+    """Sets the oracle's impenetrable-cell mask for the duration of one sweep."""
+
+    def __init__(self, forbid):
+        self.mask = _opt(forbid, np.uint32)
+
+    def __enter__(self):
+        lib().orc_set_forbidden(_ptr(self.mask) if self.mask is not None else None)
+
+    def __exit__(self, *exc):
+        lib().orc_set_forbidden(None)
 
 
 def mc_sweep(pos: np.ndarray, sp: Species, omega: np.ndarray, grid, *, k0, n_ref,
              move_kind=MOVE_LOCAL, step, seed, sweep, replica=0, chain_base=0,
-             set_order=0, want_flags=False, threads=1):
+             set_order=0, want_flags=False, threads=1, forbid=None):
     """In-place sweep of one species' chains (pos is that species' slice).
 
     Returns (n_accepted, flags or None)."""
@@ -163,17 +192,18 @@ def mc_sweep(pos: np.ndarray, sp: Species, omega: np.ndarray, grid, *, k0, n_ref
     omega = _c(omega, np.float32)
     assert omega.size == 2 * nx * ny * nz
     flags = np.zeros(sp.n_chains * sp.n, np.uint8) if want_flags else None
-    acc = lib().orc_mc_sweep(_ptr(pos), sp.n_chains, sp.n, sp.n_a, float(np.float32(k0)),
-                             n_ref, _ptr(omega), nx, ny, nz, move_kind,
-                             float(np.float32(step)), seed, sweep, replica, chain_base,
-                             set_order, _ptr(flags) if flags is not None else None,
-                             threads)
+    with _walls(forbid):
+        acc = lib().orc_mc_sweep(_ptr(pos), sp.n_chains, sp.n, sp.n_a, float(np.float32(k0)),
+                                 n_ref, _ptr(omega), nx, ny, nz, move_kind,
+                                 float(np.float32(step)), seed, sweep, replica, chain_base,
+                                 set_order, _ptr(flags) if flags is not None else None,
+                                 threads)
     return acc, flags
 
 
 def mc_sweep_molecule(pos: np.ndarray, sp: Species, omega: np.ndarray, grid, *, k0, n_ref,
                       step, seed, sweep, replica=0, chain_base=0, want_flags=False,
-                      threads=1):
+                      threads=1, forbid=None):
     """In-place local-move sweep in the molecule-parallel order (N attempts per
     chain on randomly picked beads).  Returns (n_accepted, accept flags or None,
     picked beads or None), the last two per attempt [n_chains * N]."""
@@ -184,11 +214,12 @@ def mc_sweep_molecule(pos: np.ndarray, sp: Species, omega: np.ndarray, grid, *, 
     assert omega.size == 2 * nx * ny * nz
     flags = np.zeros(sp.n_chains * sp.n, np.uint8) if want_flags else None
     picked = np.zeros(sp.n_chains * sp.n, np.uint32) if want_flags else None
-    acc = lib().orc_mc_sweep_molecule(_ptr(pos), sp.n_chains, sp.n, sp.n_a,
-                                      float(np.float32(k0)), n_ref, _ptr(omega), nx, ny, nz,
-                                      float(np.float32(step)), seed, sweep, replica, chain_base,
-                                      _ptr(flags) if flags is not None else None,
-                                      _ptr(picked) if picked is not None else None, threads)
+    with _walls(forbid):
+        acc = lib().orc_mc_sweep_molecule(_ptr(pos), sp.n_chains, sp.n, sp.n_a,
+                                          float(np.float32(k0)), n_ref, _ptr(omega), nx, ny, nz,
+                                          float(np.float32(step)), seed, sweep, replica, chain_base,
+                                          _ptr(flags) if flags is not None else None,
+                                          _ptr(picked) if picked is not None else None, threads)
     return acc, flags, picked
 
 
@@ -311,7 +342,7 @@ def features(pos, sp: Species, beads, omega, grid):
 
 def mc_sweep_mixed(pos, sp: Species, omega, grid, *, k0, n_ref, local_a, p_learn, params,
                    m_max, lo, hi, bf16_mode=True, seed, sweep, replica=0, chain_base=0,
-                   set_order=0, want_flags=False, threads=1):
+                   set_order=0, want_flags=False, threads=1, forbid=None):
     """In-place mixed (local / learned) sweep.  Returns (accepted, accepted_learned,
     bad_net, kind_flags, accept_flags)."""
     L = _lib_mlp()
@@ -322,12 +353,17 @@ def mc_sweep_mixed(pos, sp: Species, omega, grid, *, k0, n_ref, local_a, p_learn
     af = np.zeros(sp.n_chains * sp.n, np.uint8) if want_flags else None
     acc_l = ctypes.c_uint64()
     bad = ctypes.c_uint32()
-    acc = L.orc_mc_sweep_mixed(_ptr(pos), sp.n_chains, sp.n, sp.n_a, float(np.float32(k0)), n_ref,
-                               _ptr(omega), *grid, float(np.float32(local_a)),
-                               float(np.float32(p_learn)), _ptr(params), float(np.float32(m_max)),
-                               float(np.float32(lo)), float(np.float32(hi)), int(bf16_mode), seed,
-                               sweep, replica, chain_base, set_order,
-                               _ptr(kf) if kf is not None else None,
-                               _ptr(af) if af is not None else None,
-                               ctypes.byref(acc_l), ctypes.byref(bad), threads)
+    walls = _opt(forbid, np.uint32)
+    lib().orc_set_forbidden(_ptr(walls) if walls is not None else None)
+    try:
+        acc = L.orc_mc_sweep_mixed(_ptr(pos), sp.n_chains, sp.n, sp.n_a, float(np.float32(k0)), n_ref,
+                                   _ptr(omega), *grid, float(np.float32(local_a)),
+                                   float(np.float32(p_learn)), _ptr(params), float(np.float32(m_max)),
+                                   float(np.float32(lo)), float(np.float32(hi)), int(bf16_mode), seed,
+                                   sweep, replica, chain_base, set_order,
+                                   _ptr(kf) if kf is not None else None,
+                                   _ptr(af) if af is not None else None,
+                                   ctypes.byref(acc_l), ctypes.byref(bad), threads)
+    finally:
+        lib().orc_set_forbidden(None)
     return acc, acc_l.value, bad.value, kf, af

@@ -165,14 +165,29 @@ void orc_density_hist(const float *pos, uint32_t n_species,
 /* N the reference chain length (Sec. 2.1, the paragraph on N-invariance).     */
 /* inv_rho = 1/(rho0 dL^3) = n_cells / n_beads.                                */
 /* ------------------------------------------------------------------------- */
+/* External fields (Sec. 4): ext (may be NULL) holds per type and cell an
+ * energy in the units of omega, added to the interaction field; a cell whose
+ * bit is set in forbid (may be NULL) is impenetrable and gets the field 0
+ * (no bead enters it).  With forbidden cells the reference density counts
+ * the free cells only (inv_rho = n_free / n_beads, chosen by the caller). */
+static int orc_bit(const uint32_t *mask, uint64_t c) {
+  return mask && ((mask[c >> 5] >> (c & 31u)) & 1u);
+}
+
 void orc_field_f64(const uint32_t *counts, uint64_t n_cells, double inv_rho,
-                   double chi_n, double kappa_n, double *omega) {
+                   double chi_n, double kappa_n, const float *ext,
+                   const uint32_t *forbid, double *omega) {
   for (uint64_t c = 0; c < n_cells; ++c) {
     double phi_a = counts[c] * inv_rho;
     double phi_b = counts[n_cells + c] * inv_rho;
     double incompress = kappa_n * (phi_a + phi_b - 1.0);
     omega[c] = incompress + chi_n * phi_b;
     omega[n_cells + c] = incompress + chi_n * phi_a;
+    if (ext) {
+      omega[c] += (double)ext[c];
+      omega[n_cells + c] += (double)ext[n_cells + c];
+    }
+    if (orc_bit(forbid, c)) omega[c] = omega[n_cells + c] = 0.0;
   }
 }
 
@@ -181,14 +196,22 @@ void orc_field_f64(const uint32_t *counts, uint64_t n_cells, double inv_rho,
  * bit equality.  Compiled with -ffp-contract=off so the order is the one
  * written. */
 void orc_field_f32(const uint32_t *counts, uint64_t n_cells, float inv_rho,
-                   float chi_n, float kappa_n, float *omega) {
+                   float chi_n, float kappa_n, const float *ext,
+                   const uint32_t *forbid, float *omega) {
   for (uint64_t c = 0; c < n_cells; ++c) {
     float phi_a = (float)counts[c] * inv_rho;
     float phi_b = (float)counts[n_cells + c] * inv_rho;
     float s = (phi_a + phi_b) - 1.0f;
     float t = kappa_n * s;
-    omega[c] = fmaf(chi_n, phi_b, t);
-    omega[n_cells + c] = fmaf(chi_n, phi_a, t);
+    float wa = fmaf(chi_n, phi_b, t);
+    float wb = fmaf(chi_n, phi_a, t);
+    if (ext) {
+      wa = wa + ext[c];
+      wb = wb + ext[n_cells + c];
+    }
+    if (orc_bit(forbid, c)) wa = wb = 0.0f;
+    omega[c] = wa;
+    omega[n_cells + c] = wb;
   }
 }
 
@@ -197,9 +220,11 @@ void orc_field_f32(const uint32_t *counts, uint64_t n_cells, float inv_rho,
  * (the i != j sum of Eq. (8) read over unordered pairs, which is the reading
  * that reproduces the field of Eq. (12) as its derivative). */
 double orc_h_nb(const uint32_t *counts, uint64_t n_cells, double inv_rho,
-                double chi_n, double kappa_n, uint32_t n_ref) {
+                double chi_n, double kappa_n, uint32_t n_ref,
+                const uint32_t *forbid) {
   double sum = 0.0;
   for (uint64_t c = 0; c < n_cells; ++c) {
+    if (orc_bit(forbid, c)) continue;   /* impenetrable cells hold no beads */
     double phi_a = counts[c] * inv_rho;
     double phi_b = counts[n_cells + c] * inv_rho;
     double dev = phi_a + phi_b - 1.0;
@@ -278,6 +303,19 @@ static void orc_force(const float *r, const float *chain, uint32_t i,
 /* accept_flags (n_chains * N bytes, may be NULL) records 1 for an accepted    */
 /* move.  Returns the number of accepted moves.                                */
 /* ------------------------------------------------------------------------- */
+/* Impenetrable cells for the moves (Sec. 4, geometric confinement): a trial
+ * position in a set cell other than the bead's own cell is rejected (an
+ * infinite energy).  NULL: none.  Set by orc_set_forbidden before a sweep;
+ * read-only during it. */
+static const uint32_t *orc_forbidden = NULL;
+void orc_set_forbidden(const uint32_t *mask) { orc_forbidden = mask; }
+static int orc_blocked(const float *r, const float *trial, uint32_t nx, uint32_t ny,
+                       uint32_t nz) {
+  if (!orc_forbidden) return 0;
+  uint64_t to = orc_cell(trial, nx, ny, nz);
+  return to != orc_cell(r, nx, ny, nz) && orc_bit(orc_forbidden, to);
+}
+
 /* One local attempt on bead i from the four words w of its draw. */
 static int orc_local_attempt(float *chain, uint32_t i, uint32_t n, uint32_t n_a,
                              double k0, const float *omega, uint64_t n_cells,
@@ -286,6 +324,7 @@ static int orc_local_attempt(float *chain, uint32_t i, uint32_t n, uint32_t n_a,
   float *r = chain + 3 * i;
   float trial[3];
   for (int d = 0; d < 3; ++d) trial[d] = fmaf(a, orc_v11(w[d]), r[d]);
+  if (orc_blocked(r, trial, nx, ny, nz)) return 0;
   double d_bond = orc_bond_energy(trial, chain, i, n, k0) -
                   orc_bond_energy(r, chain, i, n, k0);
   const float *om = omega + (uint64_t)orc_type(i, n_a) * n_cells;
@@ -329,6 +368,7 @@ static int orc_move_smc(float *chain, uint32_t c_id, uint32_t i, uint32_t n,
   float trial[3];
   for (int d = 0; d < 3; ++d)
     trial[d] = (float)((double)r[d] + A * f_old[d] + sqrt(2.0 * A) * xi[d]);
+  if (orc_blocked(r, trial, nx, ny, nz)) return 0;
   orc_force(trial, chain, i, n, k0, om, nx, ny, nz, n_ref, f_new);
   double log_fwd = 0.0, log_rev = 0.0;
   for (int d = 0; d < 3; ++d) {
@@ -826,6 +866,7 @@ static int orc_move_learned(float *chain, uint32_t c_id, uint32_t i, uint32_t n,
   orc_head(zn, m_max, lo, hi, mun, sign, lsign);
   for (int d = 0; d < 6; ++d)
     if (!isfinite(z[d]) || !isfinite(zn[d])) { (*bad_net)++; return 0; }
+  if (orc_blocked(r, trial, nx, ny, nz)) return 0;
   double log_fwd = 0.0, log_rev = 0.0;
   for (int d = 0; d < 3; ++d) {
     double ef = (double)trial[d] - (double)r[d] - mu[d];

@@ -93,6 +93,46 @@ def gaussian_walks(seed: int, n_chains: int, n: int, grid, bond_sigma: float,
     return (origin + walk).astype(np.float32).reshape(-1, 3)
 
 
+def pack_mask(cells: np.ndarray) -> np.ndarray:
+    """Boolean per-cell array (cell order) -> packed uint32 words, bit c % 32 of
+    word c // 32 set for a True cell (the interface format of impenetrable cells)."""
+    cells = np.asarray(cells, bool).ravel()
+    n_words = (cells.size + 31) // 32
+    padded = np.zeros(n_words * 32, bool)
+    padded[:cells.size] = cells
+    bits = padded.reshape(n_words, 32).astype(np.uint64) << np.arange(32, dtype=np.uint64)
+    return bits.sum(axis=1).astype(np.uint32)
+
+
+def wall_cells(grid, z_planes) -> np.ndarray:
+    """Boolean [n_cells] (cell order (z*ny + y)*nx + x) marking whole z planes."""
+    nx, ny, nz = grid
+    m = np.zeros((nz, ny, nx), bool)
+    m[list(z_planes)] = True
+    return m.ravel()
+
+
+def film_walks(seed: int, n_chains: int, n: int, grid, bond_sigma: float, z_lo: float,
+               z_hi: float) -> np.ndarray:
+    """Random walks as gaussian_walks, with origins uniform in the slab
+    z_lo <= z < z_hi and every z coordinate folded back into the slab by
+    reflection at its faces (an initial state inside a film; float32)."""
+    g = rng(seed)
+    nx, ny, _ = grid
+    width = z_hi - z_lo
+    origin = g.random((n_chains, 1, 3)) * np.array([nx, ny, width]) + np.array([0, 0, z_lo])
+    bonds = g.standard_normal((n_chains, n - 1, 3)) * bond_sigma
+    walk = np.concatenate([np.zeros((n_chains, 1, 3)), np.cumsum(bonds, axis=1)], axis=1)
+    pos = origin + walk
+    t = np.mod(pos[..., 2] - z_lo, 2 * width)
+    pos[..., 2] = z_lo + np.where(t < width, t, 2 * width - t)
+    pos = pos.astype(np.float32)
+    # float32 rounding may land on the upper face: keep it inside
+    pos[..., 2] = np.minimum(pos[..., 2], np.nextafter(np.float32(z_hi), np.float32(0)))
+    pos[..., 2] = np.maximum(pos[..., 2], np.float32(z_lo))
+    return pos.reshape(-1, 3)
+
+
 def uniform_field(seed: int, n_cells: int, lo: float, hi: float) -> np.ndarray:
     """Random per-type fields, float32 [2, n_cells]."""
     return rng(seed).uniform(lo, hi, size=(2, n_cells)).astype(np.float32)
