@@ -190,6 +190,24 @@ int32_t soma_sync_fields(soma_system *sys, void *stream);
  * a batch that holds the system.  Asynchronous. */
 int32_t soma_set_grad_field(soma_system *sys, void *grad, uint64_t grad_bytes, void *stream);
 
+/* External fields (Sec. 4).  ext (device, caller-owned, FP32 [2][n_cells], or
+ * NULL): per type and cell an energy in the units of the fields, added to the
+ * interaction field at every refresh (a bead of type t in cell c then carries
+ * (omega_t(c) + ext_t(c)) / N) -- a linear attraction or repulsion, e.g. of one
+ * type by a substrate.  forbid (device, caller-owned, ceil(n_cells/32) words,
+ * or NULL): bit c % 32 of word c / 32 marks cell c impenetrable; every move
+ * whose trial position lies in an impenetrable cell other than the bead's own
+ * is rejected (geometric confinement, e.g. the walls of a film; trial steps
+ * below one cell cannot cross a wall plane).  Impenetrable cells get the field
+ * 0 and are left out of H_nb, and the reference density counts free cells
+ * only.  Positions must start outside impenetrable cells (not checked).  The
+ * fields are recomputed from the current counts before the call returns.
+ * Capture graphs again afterwards; attach before creating a batch that holds
+ * the system.  NULL, NULL detaches both.  BLOCKING.  SOMA_E_SIZE for short
+ * buffers, SOMA_E_INVAL if every cell is impenetrable. */
+int32_t soma_set_external(soma_system *sys, const float *ext, uint64_t ext_bytes,
+                          const uint32_t *forbid, uint64_t forbid_bytes, void *stream);
+
 /* Launch shape of the local-move sweep: 0 (default) runs one wave per tile
  * of chains; blocks > 0 runs that many persistent 256-thread blocks, each wave
  * looping over tiles and prefetching the next tile's positions.  Results are

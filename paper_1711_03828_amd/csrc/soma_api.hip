@@ -57,6 +57,11 @@ struct Derived {
   uint64_t off_err = 0, off_acc = 0, off_att = 0, off_net = 0, off_fpart = 0, off_totals = 0,
            off_opart = 0, off_halo = 0;
   uint64_t halo_plane = 0;    // floats per plane of the halo copy (0: not kept)
+  // external fields (soma_set_external): caller-owned device buffers, null if none;
+  // n_free = cells not impenetrable (the reference density counts these)
+  const float *ext = nullptr;
+  const uint32_t *forbid = nullptr;
+  uint64_t n_free = 0;
   uint64_t ws_bytes = 0;
   uint32_t field_blocks = 1;  // blocks of the field update (and its FP64 partial sums)
 };
@@ -84,6 +89,7 @@ int32_t derive(const soma_config *c, Derived *d) {
       !std::isfinite(c->smc_a) || c->local_a < 0.f || c->smc_a < 0.f)
     return fail(SOMA_E_INVAL, "chi_n, kappa_n, local_a, smc_a must be finite (steps >= 0)");
   d->n_cells = n_cells;
+  d->n_free = n_cells;
   {
     const uint64_t fb = (n_cells + 4095) / 4096;
     d->field_blocks = (uint32_t)(fb < soma::kFieldBlocks ? fb : soma::kFieldBlocks);
@@ -137,7 +143,9 @@ soma::Grid make_grid(const soma_config *c, uint64_t n_cells) {
   return g;
 }
 
-float inv_rho_f(const Derived &d) { return (float)((double)d.n_cells / (double)d.n_beads); }
+// 1 / rho_bar: free cells per bead (all cells without impenetrable ones)
+double inv_rho_d(const Derived &d) { return (double)d.n_free / (double)d.n_beads; }
+float inv_rho_f(const Derived &d) { return (float)inv_rho_d(d); }
 
 int32_t launch_zero(void *p, uint64_t bytes, hipStream_t s) {
   const uint64_t words = bytes / 4;
@@ -181,7 +189,7 @@ soma::FieldArgs field_args(const soma_config *c, const Derived &d, void *counts,
   a.inv_rho = inv_rho_f(d);
   a.chi_n = c->chi_n;
   a.kappa_n = c->kappa_n;
-  a.inv_rho_d = (double)d.n_cells / (double)d.n_beads;
+  a.inv_rho_d = inv_rho_d(d);
   a.chi_n_d = (double)c->chi_n;
   a.kappa_n_d = (double)c->kappa_n;
   a.partials = partials;
@@ -189,6 +197,8 @@ soma::FieldArgs field_args(const soma_config *c, const Derived &d, void *counts,
   a.halo = d.halo_plane ? halo : nullptr;
   a.nx = c->nx;
   a.halo_plane = (uint32_t)d.halo_plane;
+  a.ext = d.ext;
+  a.forbid = d.forbid;
   return a;
 }
 
@@ -331,6 +341,7 @@ void sweep_args(soma_system *sys, uint32_t sp, uint32_t kind, soma::SweepArgs &a
   a.sub_j = 0;
   a.n_sub = S.n_chains;
   a.grad = sys->grad;
+  a.forbid = sys->d.forbid;
   mx.net = sys->net(sp);
   mx.head.m_max = c->mu_max;
   mx.head.lo = c->log_sigma_min;
@@ -664,6 +675,44 @@ int32_t soma_set_grad_field(soma_system *sys, void *grad, uint64_t grad_bytes, v
   return launch_grad(sys, reinterpret_cast<hipStream_t>(stream));
 }
 
+int32_t soma_set_external(soma_system *sys, const float *ext, uint64_t ext_bytes,
+                          const uint32_t *forbid, uint64_t forbid_bytes, void *stream) {
+  if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
+  const uint64_t n_cells = sys->d.n_cells;
+  if (ext && ext_bytes < 8ull * n_cells)
+    return fail(SOMA_E_SIZE, "external field: %llu < %llu bytes", (unsigned long long)ext_bytes,
+                (unsigned long long)(8ull * n_cells));
+  if (ext && !aligned(ext, 4)) return fail(SOMA_E_INVAL, "external field must be 4-byte aligned");
+  const uint64_t words = (n_cells + 31) / 32;
+  uint64_t n_free = n_cells;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (forbid) {
+    if (forbid_bytes < 4ull * words)
+      return fail(SOMA_E_SIZE, "impenetrable-cell mask: %llu < %llu bytes",
+                  (unsigned long long)forbid_bytes, (unsigned long long)(4ull * words));
+    if (!aligned(forbid, 4)) return fail(SOMA_E_INVAL, "mask must be 4-byte aligned");
+    std::vector<uint32_t> h(words);
+    HIP_TRY(hipMemcpyAsync(h.data(), forbid, 4ull * words, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    uint64_t blocked = 0;
+    for (uint64_t w = 0; w < words; ++w) {
+      uint32_t v = h[w];
+      if (w == words - 1 && (n_cells & 31u)) v &= (1u << (n_cells & 31u)) - 1u;  // bits past the grid
+      blocked += (uint64_t)__builtin_popcount(v);
+    }
+    if (blocked >= n_cells) return fail(SOMA_E_INVAL, "every cell is impenetrable");
+    n_free = n_cells - blocked;
+  }
+  sys->d.ext = ext;
+  sys->d.forbid = forbid;
+  sys->d.n_free = n_free;
+  sys->graph.release();   // captured launches hold the old arguments
+  const int32_t rc = refresh_fields(sys, s);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(s));
+  return SOMA_OK;
+}
+
 int32_t soma_observables(soma_system *sys, soma_obs *out, void *stream) {
   if (!sys || !out) return fail(SOMA_E_INVAL, "system or out is NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -710,7 +759,7 @@ int32_t soma_observables(soma_system *sys, soma_obs *out, void *stream) {
   out->b2_sum = t.b2;
   out->e_bond = t.e_bond;
   out->e_field = t.e_field;
-  out->h_nb = t.h_nb / ((double)sys->d.n_cells / (double)sys->d.n_beads * (double)c->n_ref);
+  out->h_nb = t.h_nb / (inv_rho_d(sys->d) * (double)c->n_ref);
   out->error_flags = t.err;
   out->counts_conserved =
       (t.sum_a == sys->d.n_a_total && t.sum_b == sys->d.n_beads - sys->d.n_a_total) ? 1u : 0u;

@@ -68,7 +68,26 @@ struct FieldArgs {
   // x row: [2][nz*ny][nx + 2] (null: not kept)
   float *halo;
   uint32_t nx, halo_plane;
+  // external fields (null: none): ext [2][n_cells] added to the fields;
+  // forbid one bit per cell (bit c % 32 of word c / 32): impenetrable cells get
+  // the field 0 and are left out of H_nb
+  const float *ext;
+  const uint32_t *forbid;
 };
+
+__device__ __forceinline__ bool cell_forbidden(const uint32_t *m, uint32_t c) {
+  return m != nullptr && ((m[c >> 5] >> (c & 31u)) & 1u) != 0u;
+}
+
+// External terms of cell c on top of its interaction fields.
+__device__ __forceinline__ void field_extras(const FieldArgs &a, uint32_t c, bool off, float &va,
+                                             float &vb) {
+  if (a.ext) {
+    va = va + a.ext[c];
+    vb = vb + a.ext[a.n_cells + c];
+  }
+  if (off) va = vb = 0.0f;
+}
 
 // Writes the two field values of the cell at column x of row r into the halo
 // copy (and into the halo cell that mirrors it when x is at either end).
@@ -140,11 +159,19 @@ __device__ __forceinline__ void field_body(const FieldArgs &a, uint32_t blk, uin
   for (uint32_t q = tid; q < n4; q += stride) {
     uint32_t na[4], nb[4];
     load4<COUNT64>(a.counts, q, na, nb);
+    // the four cells 4q..4q+3 share one mask word
+    const uint32_t fb = a.forbid ? (a.forbid[q >> 3] >> ((4u * q) & 31u)) & 0xFu : 0u;
     float va[4], vb[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       field_cell(na[j], nb[j], a, va[j], vb[j]);
-      if (stats) { sum_a += na[j]; sum_b += nb[j]; h += hnb_cell(na[j], nb[j], a); }
+      const bool off = ((fb >> j) & 1u) != 0u;
+      if (a.ext || a.forbid) field_extras(a, 4u * q + j, off, va[j], vb[j]);
+      if (stats) {
+        sum_a += na[j];
+        sum_b += nb[j];
+        if (!off) h += hnb_cell(na[j], nb[j], a);
+      }
     }
     oa4[q] = make_float4(va[0], va[1], va[2], va[3]);
     if (a.halo) {   // four consecutive cells: one division, then step along the row
@@ -187,10 +214,16 @@ __device__ __forceinline__ void field_body(const FieldArgs &a, uint32_t blk, uin
     }
     float va, vb;
     field_cell(na, nb, a, va, vb);
+    const bool off = cell_forbidden(a.forbid, c);
+    if (a.ext || a.forbid) field_extras(a, c, off, va, vb);
     a.omega[c] = va;
     a.omega[a.n_cells + c] = vb;
     if (a.halo) halo_put(a, c, va, vb);
-    if (stats) { sum_a += na; sum_b += nb; h += hnb_cell(na, nb, a); }
+    if (stats) {
+      sum_a += na;
+      sum_b += nb;
+      if (!off) h += hnb_cell(na, nb, a);
+    }
   }
   if (!stats) return;
   // block reduction: wave shuffles, then four waves through LDS

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void mc_sweep_molecule_kernel(const SweepArgs 
       const float wl = has_l ? 1.0f : 0.0f, wr = has_r ? 1.0f : 0.0f;
       const F3 qv = wl * (2.0f * (r - left) + d) + wr * (2.0f * (r - right) + d);
       const float d_e = a.half_k0 * (d.x * qv.x + d.y * qv.y + d.z * qv.z) + (wn - wo) * a.inv_nref;
-      const bool acc = d_e <= 0.0f || uniform01(w.w) < __expf(-d_e);
+      const bool acc = move_allowed(a, co, cn) && (d_e <= 0.0f || uniform01(w.w) < __expf(-d_e));
       if (acc) {
         p[0] = t.x;
         p[1] = t.y;

@@ -47,7 +47,15 @@ struct SweepArgs {
   // optional [2][n_cells] (omega, d omega/dx, d omega/dy, d omega/dz) per type and
   // cell, refreshed with the fields; null: smart-MC gathers the 6 neighbours
   const float4 *grad;
+  // optional impenetrable cells, one bit per cell (null: none): a trial position
+  // in such a cell, other than the bead's own, is rejected
+  const uint32_t *forbid;
 };
+
+// A move from cell `from` to cell `to` that the impenetrable cells allow.
+__device__ __forceinline__ bool move_allowed(const SweepArgs &a, uint32_t from, uint32_t to) {
+  return a.forbid == nullptr || to == from || ((a.forbid[to >> 5] >> (to & 31u)) & 1u) == 0u;
+}
 
 // Arguments with the Philox sweep word resolved: the system's device counter
 // plus the launch's offset, so that a launch recorded once (a captured graph)
@@ -213,12 +221,14 @@ __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap
   float wn0 = wo0, wn1 = wo1;
   if (n0 != c0) wn0 = field_at(a.omega, pl0, n0);
   if (n1 != c1) wn1 = field_at(a.omega, pl1, n1);
+  const bool ok0 = move_allowed(a, c0, n0), ok1 = move_allowed(a, c1, n1);
 
   // relabel by set order: a moves first, b second
   const F3 ra0 = sel(odd_first, r1, r0), rb0 = sel(odd_first, r0, r1);
   const F3 ta = sel(odd_first, t1, t0), tb = sel(odd_first, t0, t1);
   const Rand4 wa = odd_first ? w1 : w0, wb = odd_first ? w0 : w1;
   const bool has_a = odd_first ? m.has1 : m.has0, has_b = odd_first ? m.has0 : m.has1;
+  const bool ok_a = odd_first ? ok1 : ok0, ok_b = odd_first ? ok0 : ok1;
   const float dfa = ((odd_first ? wn1 : wn0) - (odd_first ? wo1 : wo0)) * a.inv_nref;
   const float dfb = ((odd_first ? wn0 : wn1) - (odd_first ? wo0 : wo1)) * a.inv_nref;
   // bonded neighbours of a: own b and b of the adjacent lane (lane k-1 if a is
@@ -238,7 +248,7 @@ __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap
     const F3 d = ta - ra;
     const F3 q = wown_a * (2.0f * (ra - rb0) + d) + wadj_a * (2.0f * (ra - nb) + d);
     const float d_e = a.half_k0 * (d.x * q.x + d.y * q.y + d.z * q.z) + dfa;
-    acc_a = has_a && (d_e <= 0.0f || uniform01(wa.w) < __expf(-d_e));
+    acc_a = has_a && ok_a && (d_e <= 0.0f || uniform01(wa.w) < __expf(-d_e));
     ra = acc_a ? ta : ra;
   }
   // pass 2: set of b, against the updated a beads
@@ -249,7 +259,7 @@ __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap
     const F3 d = tb - rb;
     const F3 q = wown_b * (2.0f * (rb - ra) + d) + wadj_b * (2.0f * (rb - nb) + d);
     const float d_e = a.half_k0 * (d.x * q.x + d.y * q.y + d.z * q.z) + dfb;
-    acc_b = has_b && (d_e <= 0.0f || uniform01(wb.w) < __expf(-d_e));
+    acc_b = has_b && ok_b && (d_e <= 0.0f || uniform01(wb.w) < __expf(-d_e));
     rb = acc_b ? tb : rb;
   }
   store_pair<VEC2>(cp, m, sel(odd_first, rb, ra), sel(odd_first, ra, rb));
@@ -425,6 +435,7 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
       F3 g_new = g_old;
       float w_new = w_old;
       if (cn != co) w_new = field_and_grad(a, pl, cn, nx_, ny_, nz_, g_new);
+      const bool ok = move_allowed(a, co, cn);
       const F3 d = {rn.x - r.x, rn.y - r.y, rn.z - r.z};
       const F3 nl = {rn.x - left.x, rn.y - left.y, rn.z - left.z};
       const F3 nr = {rn.x - right.x, rn.y - right.y, rn.z - right.z};
@@ -440,7 +451,7 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
       const float qz = wl * (2.0f * el.z + d.z) + wr * (2.0f * er.z + d.z);
       const float d_e = a.half_k0 * (d.x * qx + d.y * qy + d.z * qz) + (w_new - w_old) * a.inv_nref;
       const float lr = log_q - d_e;
-      acc = lr >= 0.0f || u < __expf(lr);
+      acc = ok && (lr >= 0.0f || u < __expf(lr));
     }
     if (odd) { r1 = acc ? rn : r1; moved1 = acc && cn != co; from1 = co; to1 = cn; }
     else     { r0 = acc ? rn : r0; moved0 = acc && cn != co; from0 = co; to0 = cn; }
@@ -588,6 +599,7 @@ __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx
     } else {
       acc = moving && (d_e <= 0.0f || uniform01(w.w) < __expf(-d_e));
     }
+    acc = acc && move_allowed(a, co, cn);
     net_bad_any |= net_bad;
     if (odd) { r1 = acc ? rn : r1; moved1 = acc && cn != co; from1 = co; to1 = cn; }
     else     { r0 = acc ? rn : r0; moved0 = acc && cn != co; from0 = co; to0 = cn; }

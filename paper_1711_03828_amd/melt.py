@@ -135,6 +135,16 @@ class Melt:
     def autotune(self, cycles: int, move_kind=C.SOMA_MOVE_LOCAL, cache_path=None, stream=None):
         return C.soma_autotune(self.handle, cycles, move_kind, cache_path, _stream(stream))
 
+    def set_external(self, ext=None, forbid=None, stream=None):
+        """External fields: ext a device float32 tensor [2, n_cells] (or None),
+        forbid a device int32/uint32 tensor of packed impenetrable-cell bits (or
+        None).  The melt keeps references to both."""
+        self.ext, self.forbid = ext, forbid
+        C.soma_set_external(self.handle, ext.data_ptr() if ext is not None else None,
+                            ext.numel() * 4 if ext is not None else 0,
+                            forbid.data_ptr() if forbid is not None else None,
+                            forbid.numel() * 4 if forbid is not None else 0, _stream(stream))
+
     def set_scheme(self, scheme: int):
         """Iteration order of local moves: C.SOMA_SCHEME_SET or C.SOMA_SCHEME_MOLECULE."""
         C.soma_set_scheme(self.handle, scheme)
