@@ -436,6 +436,13 @@ int32_t soma_sq_shells(const double *sq, uint32_t nx, uint32_t ny, uint32_t nz,
                        uint32_t n_shells, double *q_mid, double *s_avg, uint64_t *count,
                        uint32_t *peak);
 
+/* The in-plane structure factor of a film (Sec. 5.6: S(q_par)), shell-averaged
+ * over |q_par|: the first nx * ny entries of soma_structure_factor's output
+ * (the m_z = 0 plane, i.e. the transform of the composition summed over z),
+ * shell width 2 pi / min(nx, ny); otherwise as soma_sq_shells. */
+int32_t soma_sq_plane_shells(const double *sq, uint32_t nx, uint32_t ny, uint32_t n_shells,
+                             double *q_mid, double *s_avg, uint64_t *count, uint32_t *peak);
+
 /* Device workspace bytes of soma_train_step for up to max_waves partials. */
 uint64_t soma_train_workspace_bytes(uint32_t max_waves);
 

@@ -38,9 +38,9 @@ def lattice_q(grid) -> np.ndarray:
     return (2.0 * np.pi * np.sqrt(q2)).reshape(-1)
 
 
-def sq_shells(sq: np.ndarray, grid, n_shells: int):
+def sq_shells(sq: np.ndarray, grid, n_shells: int, l_min=None):
     """(q_mid, mean, count, peak) of the shell average."""
-    dq = 2.0 * np.pi / min(int(v) for v in grid)
+    dq = 2.0 * np.pi / (min(int(v) for v in grid) if l_min is None else l_min)
     k = np.floor(lattice_q(grid) / dq + 0.5).astype(np.int64)
     keep = k < n_shells
     cnt = np.bincount(k[keep], minlength=n_shells)[:n_shells]
@@ -49,6 +49,15 @@ def sq_shells(sq: np.ndarray, grid, n_shells: int):
     cand = [j for j in range(1, n_shells) if cnt[j] > 0]
     peak = max(cand, key=lambda j: (mean[j], -j)) if cand else 0
     return dq * np.arange(n_shells), mean, cnt, peak
+
+
+def sq_plane_shells(sq: np.ndarray, grid, n_shells: int):
+    """In-plane structure factor of a film (Sec. 5.6, S(q_par)): the m_z = 0 plane
+    of the 3-D S(q) (the transform of the composition summed over z), averaged
+    over shells of |q_par| of width 2 pi / min(nx, ny).  (q_mid, mean, count, peak)."""
+    nx, ny = int(grid[0]), int(grid[1])
+    return sq_shells(np.asarray(sq).ravel()[:nx * ny], (nx, ny, 1), n_shells,
+                     l_min=min(nx, ny))
 
 
 def autocorrelation(x: np.ndarray) -> np.ndarray:

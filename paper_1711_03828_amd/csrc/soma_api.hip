@@ -974,13 +974,19 @@ int32_t soma_structure_factor(soma_system *sys, void *workspace, uint64_t worksp
   return SOMA_OK;
 }
 
-int32_t soma_sq_shells(const double *sq, uint32_t nx, uint32_t ny, uint32_t nz,
-                       uint32_t n_shells, double *q_mid, double *s_avg, uint64_t *count,
-                       uint32_t *peak) {
+}  // extern "C"
+
+namespace {
+
+// Shell average over the lattice vectors of an nx x ny x nz grid (nz = 1: the
+// m_z = 0 plane of a 3-D S(q), i.e. the in-plane structure factor), shell
+// width 2 pi / lmin.
+int32_t soma_sq_shells_impl(const double *sq, uint32_t nx, uint32_t ny, uint32_t nz,
+                            uint32_t lmin, uint32_t n_shells, double *q_mid, double *s_avg,
+                            uint64_t *count, uint32_t *peak) {
   if (!sq || !s_avg || !count || n_shells == 0) return fail(SOMA_E_INVAL, "NULL argument");
   if (nx == 0 || ny == 0 || nz == 0) return fail(SOMA_E_INVAL, "empty grid");
   const double two_pi = 6.283185307179586476925286766559;
-  const uint32_t lmin = std::min(nx, std::min(ny, nz));
   const double dq = two_pi / (double)lmin;
   for (uint32_t k = 0; k < n_shells; ++k) {
     s_avg[k] = 0.0;
@@ -1011,6 +1017,23 @@ int32_t soma_sq_shells(const double *sq, uint32_t nx, uint32_t ny, uint32_t nz,
   if (peak) *peak = best;
   return SOMA_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+int32_t soma_sq_plane_shells(const double *sq, uint32_t nx, uint32_t ny, uint32_t n_shells,
+                             double *q_mid, double *s_avg, uint64_t *count, uint32_t *peak) {
+  return soma_sq_shells_impl(sq, nx, ny, 1, std::min(nx, ny), n_shells, q_mid, s_avg, count, peak);
+}
+
+int32_t soma_sq_shells(const double *sq, uint32_t nx, uint32_t ny, uint32_t nz,
+                       uint32_t n_shells, double *q_mid, double *s_avg, uint64_t *count,
+                       uint32_t *peak) {
+  return soma_sq_shells_impl(sq, nx, ny, nz, std::min(nx, std::min(ny, nz)), n_shells, q_mid,
+                             s_avg, count, peak);
+}
+
 
 uint64_t soma_train_workspace_bytes(uint32_t max_waves) {
   if (max_waves == 0) max_waves = 1;

@@ -150,6 +150,7 @@ _SIGS = {
     "soma_sq_workspace_bytes": ([_P], ctypes.c_uint64),
     "soma_structure_factor": ([_P, _P, _u64, _P, _P], _i32),
     "soma_sq_shells": ([_P, _u32, _u32, _u32, _u32, _P, _P, _P, _pu32], _i32),
+    "soma_sq_plane_shells": ([_P, _u32, _u32, _u32, _P, _P, _P, _pu32], _i32),
     "soma_destroy": ([_P], None),
     "soma_last_error": ([], ctypes.c_char_p),
 }
@@ -409,6 +410,21 @@ def soma_sq_shells(sq_host, grid, n_shells: int):
     nx, ny, nz = (int(v) for v in grid)
     _check(_lib.soma_sq_shells(sq_host.ctypes.data, nx, ny, nz, n_shells, q.ctypes.data,
                                s.ctypes.data, c.ctypes.data, ctypes.byref(peak)))
+    return q, s, c, peak.value
+
+
+def soma_sq_plane_shells(sq_host, grid, n_shells: int):
+    """In-plane (m_z = 0) shell average of a host float64 S(q) array of a film:
+    (q_mid, s_avg, count, peak)."""
+    import numpy as np
+    nx, ny, _ = (int(v) for v in grid)
+    plane = np.ascontiguousarray(np.asarray(sq_host, dtype=np.float64).ravel()[:nx * ny])
+    q = np.zeros(n_shells)
+    s = np.zeros(n_shells)
+    c = np.zeros(n_shells, np.uint64)
+    peak = ctypes.c_uint32()
+    _check(_lib.soma_sq_plane_shells(plane.ctypes.data, nx, ny, n_shells, q.ctypes.data,
+                                     s.ctypes.data, c.ctypes.data, ctypes.byref(peak)))
     return q, s, c, peak.value
 
 

@@ -118,3 +118,45 @@ def test_package_tau_int_matches_oracle():
         x[t] = 0.9 * x[t - 1] + rng.standard_normal(8)
     np.testing.assert_allclose(P.autocorrelation(x), A.autocorrelation(x), atol=1e-12)
     assert P.tau_int(x) == pytest.approx(A.tau_int(x), rel=1e-12)
+
+
+def test_plane_structure_factor_of_a_film():
+    """A z-invariant stripe pattern n_A - n_B ~ cos(2 pi 3 x / nx) in a film:
+    the in-plane S(q_par) is the 2-D transform of the z-summed composition
+    (numpy fft2, a separate route from the 3-D transform) and peaks in the
+    shell of |q_par| = 2 pi 3 / nx."""
+    grid = (24, 18, 5)
+    nx, ny, nz = grid
+    x = np.arange(nx)
+    wave = np.round(4 + 3 * np.cos(2 * np.pi * 3 * x / nx)).astype(np.uint32)
+    a = np.broadcast_to(wave[None, None, :], (nz, ny, nx)).ravel()
+    b = np.broadcast_to((8 - wave)[None, None, :], (nz, ny, nx)).ravel()
+    counts = np.stack([a, b]).astype(np.uint32)
+    nb = int(counts.sum())
+    s3 = A.structure_factor(counts, grid, 32, nb)
+    psi2 = (a.astype(np.float64) - b).reshape(nz, ny, nx).sum(axis=0)
+    s2 = 32 ** 2 / (4 * nb) * np.abs(np.fft.fft2(psi2)) ** 2
+    np.testing.assert_allclose(s3[:nx * ny], s2.ravel(), rtol=1e-9, atol=1e-9)
+    q, mean, cnt, peak = A.sq_plane_shells(s3, grid, 20)
+    assert cnt.sum() == nx * ny and cnt[0] == 1
+    dq = 2 * np.pi / min(nx, ny)
+    assert peak == int(np.floor(2 * np.pi * 3 / nx / dq + 0.5))
+
+
+def test_library_plane_shells_match_oracle():
+    import os
+    lib = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_1711_03828_amd", "libsoma_hip.so")
+    if not os.path.exists(lib):
+        pytest.skip("library not built")
+    from paper_1711_03828_amd import soma as C
+    rng = np.random.default_rng(6)
+    for grid in [(8, 8, 3), (9, 7, 5), (30, 24, 4)]:
+        n = grid[0] * grid[1] * grid[2]
+        sq = rng.random(n) * 10
+        q1, m1, c1, p1 = C.soma_sq_plane_shells(sq, grid, 30)
+        q2, m2, c2, p2 = A.sq_plane_shells(sq, grid, 30)
+        np.testing.assert_array_equal(c1, c2)
+        np.testing.assert_allclose(m1, m2, rtol=1e-12)
+        np.testing.assert_allclose(q1, q2, rtol=1e-15)
+        assert p1 == p2
