@@ -325,6 +325,73 @@ def scheme_leg(cycles: int):
             "cycles": cycles // 10 * 10, "sizes": rows}
 
 
+def film_leg(kind: str, lateral_re: float, cycles: int):
+    """The thin-film workloads of Sec. 5.6 on one GPU: diblocks of N = 100 at
+    sqrt(Nbar) = 85.7 (Delta L = Re0/6, kappaN = 50), lamella-forming (f = 0.5,
+    chiN = 17, film thickness 1.2 Re0) or cylinder-forming (f = 0.75, chiN = 28,
+    0.75 Re0), lateral size lateral_re x lateral_re Re0 (periodic), between two
+    impenetrable, non-preferential walls (one plane of cells each).  Disordered
+    start (Gaussian walks folded into the film) quenched to chiN; graph-replayed
+    SCMF cycles; the in-plane structure factor S(q_par) at the end and the
+    domain spacing 2 pi / q* it implies."""
+    import numpy as np
+    import torch
+
+    from paper_1711_03828_amd import soma as C
+    from paper_1711_03828_amd.melt import Melt, make_config
+
+    f, chi_n, lz_re = (0.5, 17.0, 1.2) if kind == "lam" else (0.75, 28.0, 0.75)
+    n, re = 100, 6.0
+    side = int(round(lateral_re * re))
+    inner = int(round(lz_re * re))
+    nz = inner + 2
+    n_chains = int(round(85.7 * n / re ** 3 * side * side * inner / n))
+    w = synth.Workload(f"film_{kind}_{lateral_re:g}Re0_N100", (side, side, nz),
+                       (synth.SpeciesSpec(n_chains, n, int(round(f * n))),), re, n, chi_n, 50.0, 16)
+    t0 = time.perf_counter()
+    m = Melt(make_config(w))
+    z = m.pos.view(-1, 3)[:, 2]            # fold every z into the film interior [1, nz - 1)
+    t = torch.remainder(z - 1.0, 2.0 * inner)
+    z.copy_(1.0 + torch.where(t < inner, t, 2.0 * inner - t))
+    z.clamp_(1.0, float(np.nextafter(np.float32(nz - 1), np.float32(0))))
+    m.rebuild_histogram()
+    forbid = torch.from_numpy(synth.pack_mask(synth.wall_cells(w.grid, [0, nz - 1]))
+                              .view(np.int32)).cuda()
+    m.set_external(None, forbid)
+    tune = m.autotune(2)
+    m.capture_cycle(10)
+    m.run_cycle(1)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    m.run_cycle(cycles // 10)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / (cycles // 10 * 10)
+    obs = m.observables()
+    ws = torch.empty(C.soma_sq_workspace_bytes(m.handle), dtype=torch.uint8, device="cuda")
+    sq = torch.empty(w.n_cells, dtype=torch.float64, device="cuda")
+    C.soma_structure_factor(m.handle, ws.data_ptr(), ws.numel(), sq.data_ptr(),
+                            stream.cuda_stream)
+    q, mean, cnt, peak = C.soma_sq_plane_shells(sq.cpu().numpy(), w.grid, side // 2)
+    z = m.pos.view(-1, 3)[:, 2]
+    zc = torch.remainder(torch.floor(z), nz)
+    in_walls = int(((zc == 0) | (zc == nz - 1)).sum().item())
+    m.close()
+    print(f"# film {kind}: {w.n_beads} beads, {ms:.3f} ms per cycle, S(q_par) peak shell {peak}",
+          file=sys.stderr, flush=True)
+    return {"workload": w.name, "n_beads": w.n_beads, "n_chains": n_chains,
+            "grid": list(w.grid), "f": f, "chi_n": chi_n, "cycles": cycles // 10 * 10,
+            "ms_per_cycle": ms, "bead_moves_per_s": w.n_beads * 1e3 / ms,
+            "grid_blocks": tune.grid_blocks, "setup_s": t_setup,
+            "acceptance": obs.accepted[0] / max(1, obs.attempted[0]),
+            "beads_in_walls": in_walls, "counts_conserved": obs.counts_conserved,
+            "sq_peak_shell": peak, "q_star": float(q[peak]),
+            "spacing_over_re0": float(2 * math.pi / q[peak] / re) if peak else None}
+
+
 def blend_leg(rate_cycles: int, tau_frames: int, frame_cycles: int, plain_mult: int,
               equil_cycles: int, tau_scale: float, substeps: int):
     """Ternary blend replicas (32 melts of A16B16 diblocks with A16 and B16
@@ -505,6 +572,12 @@ def main():
                     help="skip the 64-replica batched measurement")
     ap.add_argument("--no-schemes", action="store_true",
                     help="skip the SET vs molecule-parallel comparison over system size")
+    ap.add_argument("--film", choices=["lam", "hex"], default="lam",
+                    help="thin-film workload: lamella- or cylinder-forming diblocks")
+    ap.add_argument("--film-lateral", type=float, default=200.0,
+                    help="lateral film size in Re0 (the paper's films: 200)")
+    ap.add_argument("--film-cycles", type=int, default=2500,
+                    help="SCMF cycles of the film run after the quench (0: skip the film)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -636,6 +709,8 @@ def main():
         result["batched"] = batched_leg(50)
     if not args.no_schemes:
         result["schemes"] = scheme_leg(200)
+    if args.film_cycles > 0:
+        result["film"] = film_leg(args.film, args.film_lateral, args.film_cycles)
     if args.blend:
         result["blend"] = blend_leg(50, args.tau_frames // 2, args.frame_cycles,
                                     args.plain_frame_mult, args.equil_cycles // 2, 1.0 / 16,

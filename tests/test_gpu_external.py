@@ -203,3 +203,38 @@ def test_batched_cycles_equal_single_with_walls(C, orc):
     for (p0, o0), (p1, o1) in zip(runs[0], runs[1]):
         np.testing.assert_array_equal(p0, p1)
         np.testing.assert_array_equal(o0, o1)
+
+
+def test_small_film_cycles_and_in_plane_structure_factor(C, orc):
+    """A lamella-forming film (N = 32 here, 8 x 8 Re0, thickness 1.2 Re0 between
+    two wall planes), 200 SCMF cycles: no bead enters a wall, the kept
+    histogram equals the recount of the positions, the fields equal the
+    oracle's fields of those counts, and the in-plane S(q_par) from the device
+    equals the oracle's transform of the same counts (its shell average too)."""
+    from oracle import analysis as A
+    w = _film((48, 48, 9), (synth.SpeciesSpec(4000, 32, 16),), 16, "small_film")
+    m, pos, sp, walls, mask, ext, inv_rho = _setup(C, w, 90, ext_scale=0.0)
+    m.set_external(None, torch.from_numpy(mask.view(np.int32)).cuda())
+    m.cycle(200)
+    torch.cuda.synchronize()
+    got = m.pos.cpu().numpy()
+    z = np.floor(got[:, 2].astype(np.float64)).astype(np.int64) % w.grid[2]
+    assert ((z >= 1) & (z <= w.grid[2] - 2)).all()
+    counts = orc.density_hist(got, sp, w.grid)
+    np.testing.assert_array_equal(m.counts_planes(), counts)
+    omega = orc.field_f32(counts, inv_rho, np.float32(w.chi_n), np.float32(w.kappa_n), None, mask)
+    np.testing.assert_array_equal(m.omega.cpu().numpy(), omega)
+    ws = torch.empty(C.soma_sq_workspace_bytes(m.handle), dtype=torch.uint8, device="cuda")
+    sq = torch.empty(w.n_cells, dtype=torch.float64, device="cuda")
+    C.soma_structure_factor(m.handle, ws.data_ptr(), ws.numel(), sq.data_ptr(),
+                            torch.cuda.current_stream().cuda_stream)
+    sq = sq.cpu().numpy()
+    ref = A.structure_factor(counts, w.grid, w.n_ref, w.n_beads)
+    np.testing.assert_allclose(sq[:48 * 48], ref[:48 * 48], rtol=1e-9, atol=1e-9 * ref.max())
+    q1, m1, c1, p1 = C.soma_sq_plane_shells(sq, w.grid, 24)
+    q2, m2, c2, p2 = A.sq_plane_shells(ref, w.grid, 24)
+    np.testing.assert_array_equal(c1, c2)
+    np.testing.assert_allclose(m1, m2, rtol=1e-8)
+    assert p1 == p2
+    flush("small film: S(q_par) peak shell", p1)
+    m.close()
