@@ -71,6 +71,13 @@ def lib() -> ctypes.CDLL:
         L.orc_mc_sweep_molecule.argtypes = [P, u32, u32, u32, f32, u32, P, u32, u32, u32, f32,
                                             u64, u32, u32, u32, P, P, ctypes.c_int]
         L.orc_mc_sweep_molecule.restype = u64
+        L.orc_mc_sweep_arch.argtypes = [P, u32, P, u32, f32, u32, P, u32, u32, u32, f32, u64,
+                                        u32, u32, u32, u32, P, ctypes.c_int]
+        L.orc_mc_sweep_arch.restype = u64
+        L.orc_arch_sets.argtypes = [P, u32, P]
+        L.orc_arch_sets.restype = ctypes.c_int
+        L.orc_density_hist_arch.argtypes = [P, u32, P, u32, u32, u32, u32, P]
+        L.orc_density_hist_arch.restype = ctypes.c_int
         L.orc_pick_bead.argtypes = [u32, u32]
         L.orc_pick_bead.restype = u32
         L.orc_brick_cell_batch.argtypes = [u64, P, u32, u32, u32, P]
@@ -221,6 +228,50 @@ def mc_sweep_molecule(pos: np.ndarray, sp: Species, omega: np.ndarray, grid, *, 
                                           _ptr(flags) if flags is not None else None,
                                           _ptr(picked) if picked is not None else None, threads)
     return acc, flags, picked
+
+
+def arch_sets(words: np.ndarray):
+    """(number of independent sets, set of every monomer) of an architecture, or
+    (-1, None) if the words are malformed."""
+    words = _c(words, np.uint32)
+    n = int(words[0]) if words.size else 0
+    out = np.zeros(max(n, 1), np.uint32)
+    k = lib().orc_arch_sets(_ptr(words), words.size, _ptr(out))
+    return (k, out[:n]) if k > 0 else (-1, None)
+
+
+def mc_sweep_arch(pos: np.ndarray, n_chains: int, words: np.ndarray, omega: np.ndarray, grid, *,
+                  k0, n_ref, step, seed, sweep, replica=0, chain_base=0, set_order=0,
+                  want_flags=False, threads=1, forbid=None):
+    """In-place local-move sweep (SET order) of chains of one architecture.
+    Returns (n_accepted, flags or None)."""
+    words = _c(words, np.uint32)
+    n = int(words[0])
+    assert pos.dtype == np.float32 and pos.flags.c_contiguous and pos.size == n_chains * n * 3
+    nx, ny, nz = grid
+    omega = _c(omega, np.float32)
+    assert omega.size == 2 * nx * ny * nz
+    flags = np.zeros(n_chains * n, np.uint8) if want_flags else None
+    with _walls(forbid):
+        acc = lib().orc_mc_sweep_arch(_ptr(pos), n_chains, _ptr(words), words.size,
+                                      float(np.float32(k0)), n_ref, _ptr(omega), nx, ny, nz,
+                                      float(np.float32(step)), seed, sweep, replica, chain_base,
+                                      set_order, _ptr(flags) if flags is not None else None,
+                                      threads)
+    if acc == 2 ** 64 - 1:
+        raise ValueError("malformed architecture")
+    return acc, flags
+
+
+def density_hist_arch(pos: np.ndarray, n_chains: int, words: np.ndarray, grid) -> np.ndarray:
+    words = _c(words, np.uint32)
+    pos = _c(pos, np.float32)
+    nx, ny, nz = grid
+    out = np.empty((2, nx * ny * nz), np.uint32)
+    if lib().orc_density_hist_arch(_ptr(pos), n_chains, _ptr(words), words.size, nx, ny, nz,
+                                   _ptr(out)):
+        raise ValueError("malformed architecture")
+    return out
 
 
 def pick_bead(word: int, n: int) -> int:

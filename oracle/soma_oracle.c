@@ -933,3 +933,178 @@ uint64_t orc_mc_sweep_mixed(float *pos, uint32_t n_chains, uint32_t n, uint32_t 
   if (bad_net) *bad_net = bad;
   return acc_total;
 }
+
+/* ------------------------------------------------------------------------- */
+/* General molecular architectures (Sec. 3.2.1): one array of 32-bit words per */
+/* molecule type.  Word 0 holds N; word 1+i describes monomer i: its type in  */
+/* the top byte and, in the low 24 bits, the index (from the start of the      */
+/* array) of its bond list, 0 for a monomer without bonds.  A bond word holds */
+/* the signed offset partner - i in its low 27 bits, the bond type in bits    */
+/* 27-30 (0: harmonic, the only kind) and, in bit 31, the flag that ends the  */
+/* monomer's list.  Two types (A = 0, B = 1).                                  */
+/*                                                                             */
+/* Independent sets (Sec. 3.1.2, scheme 2): greedy colouring in index order,  */
+/* monomer i gets the smallest set number not used by a bonded monomer of     */
+/* lower index (a linear chain gives the even and the odd monomers).  Order   */
+/* of the sets per chain and sweep: with two sets, set 1 first iff bit 0 of    */
+/* word 0 of monomer 0's move draw is set (as for linear chains); with more,  */
+/* a Fisher-Yates shuffle, step t = k-1 .. 1 swapping t with                   */
+/* floor(w (t+1) / 2^32), w = word (k-1-t) mod 4 of the Philox block          */
+/* (chain, floor((k-1-t)/4) | 8 << 16, sweep, replica); set_order = 1 keeps   */
+/* the numerical order.  A move is the LOCAL move with the bond energy summed */
+/* over the monomer's bond list.                                              */
+/* ------------------------------------------------------------------------- */
+#define ORC_MAX_N 128
+#define ORC_MAX_BONDS 2048
+#define ORC_PURPOSE_SET_ORDER 8u
+
+typedef struct {
+  uint32_t n, n_sets, n_bonds;
+  uint8_t type[ORC_MAX_N];
+  uint32_t color[ORC_MAX_N];
+  uint32_t nb_start[ORC_MAX_N + 1];
+  uint32_t nb[ORC_MAX_BONDS];
+} orc_arch;
+
+/* Decodes and checks an architecture; returns 0, or -1 if it is malformed
+ * (a partner out of range or equal to the monomer, a non-harmonic bond, a
+ * bond listed on one side only, a list running off the array, a type > 1). */
+static int orc_arch_decode(const uint32_t *w, uint32_t n_words, orc_arch *a) {
+  if (n_words < 1) return -1;
+  uint32_t n = w[0];
+  if (n == 0 || n > ORC_MAX_N || n_words < 1 + n) return -1;
+  a->n = n;
+  uint32_t nb = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    uint32_t m = w[1 + i];
+    a->type[i] = (uint8_t)(m >> 24);
+    if (a->type[i] > 1) return -1;
+    a->nb_start[i] = nb;
+    uint32_t k = m & 0xFFFFFFu;
+    if (k == 0) continue;
+    for (;; ++k) {
+      if (k >= n_words || nb >= ORC_MAX_BONDS) return -1;
+      uint32_t b = w[k];
+      int32_t off = (int32_t)(b << 5) >> 5;          /* sign-extend 27 bits */
+      if (((b >> 27) & 0xFu) != 0u) return -1;
+      int64_t p = (int64_t)i + off;
+      if (off == 0 || p < 0 || p >= (int64_t)n) return -1;
+      a->nb[nb++] = (uint32_t)p;
+      if (b >> 31) break;
+    }
+  }
+  a->nb_start[n] = nb;
+  a->n_bonds = nb;
+  /* every bond must be listed at both ends */
+  for (uint32_t i = 0; i < n; ++i)
+    for (uint32_t q = a->nb_start[i]; q < a->nb_start[i + 1]; ++q) {
+      uint32_t j = a->nb[q], found = 0;
+      for (uint32_t r = a->nb_start[j]; r < a->nb_start[j + 1]; ++r) found |= a->nb[r] == i;
+      if (!found) return -1;
+    }
+  uint32_t k_max = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    uint64_t used = 0;
+    for (uint32_t q = a->nb_start[i]; q < a->nb_start[i + 1]; ++q)
+      if (a->nb[q] < i) used |= 1ull << a->color[a->nb[q]];
+    uint32_t c = 0;
+    while (used & (1ull << c)) ++c;
+    a->color[i] = c;
+    if (c + 1 > k_max) k_max = c + 1;
+  }
+  a->n_sets = k_max;
+  return 0;
+}
+
+/* Set numbers of the monomers (set_of[N]); returns the number of sets or -1. */
+int orc_arch_sets(const uint32_t *w, uint32_t n_words, uint32_t *set_of) {
+  static orc_arch a;
+  if (orc_arch_decode(w, n_words, &a)) return -1;
+  for (uint32_t i = 0; i < a.n; ++i) set_of[i] = a.color[i];
+  return (int)a.n_sets;
+}
+
+/* Bond energy of monomer i at position r with its bonded partners, Eqs. (1)-(2). */
+static double orc_arch_bond_energy(const float *r, const float *chain, const orc_arch *a,
+                                   uint32_t i, double k0) {
+  double e = 0.0;
+  for (uint32_t q = a->nb_start[i]; q < a->nb_start[i + 1]; ++q) {
+    const float *rj = chain + 3 * a->nb[q];
+    for (int d = 0; d < 3; ++d) {
+      double dx = (double)r[d] - (double)rj[d];
+      e += 0.5 * k0 * dx * dx;
+    }
+  }
+  return e;
+}
+
+uint64_t orc_mc_sweep_arch(float *pos, uint32_t n_chains, const uint32_t *w,
+                           uint32_t n_words, float k0, uint32_t n_ref, const float *omega,
+                           uint32_t nx, uint32_t ny, uint32_t nz, float step, uint64_t seed,
+                           uint32_t sweep, uint32_t replica, uint32_t chain_base,
+                           uint32_t set_order, uint8_t *accept_flags, int n_threads) {
+  static orc_arch a;
+  if (orc_arch_decode(w, n_words, &a)) return UINT64_MAX;
+  const uint32_t n = a.n, k = a.n_sets;
+  uint64_t n_cells = (uint64_t)nx * ny * nz;
+  uint64_t accepted = 0;
+#pragma omp parallel for schedule(static) reduction(+ : accepted) num_threads(n_threads > 0 ? n_threads : 1)
+  for (int64_t c = 0; c < (int64_t)n_chains; ++c) {
+    float *chain = pos + (uint64_t)c * n * 3;
+    uint32_t c_id = chain_base + (uint32_t)c;
+    uint32_t order[ORC_MAX_N];
+    for (uint32_t s = 0; s < k; ++s) order[s] = s;
+    if (set_order == 0 && k == 2) {
+      uint32_t d[4];
+      orc_draw(seed, c_id, 0, ORC_PURPOSE_MOVE_A, sweep, replica, d);
+      if (d[0] & 1u) { order[0] = 1; order[1] = 0; }
+    } else if (set_order == 0 && k > 2) {
+      uint32_t d[4];
+      for (uint32_t t = k - 1, step_i = 0; t >= 1; --t, ++step_i) {
+        if (step_i % 4u == 0u)
+          orc_draw(seed, c_id, step_i / 4u, ORC_PURPOSE_SET_ORDER, sweep, replica, d);
+        uint32_t j = orc_pick_bead(d[step_i % 4u], t + 1);
+        uint32_t tmp = order[t]; order[t] = order[j]; order[j] = tmp;
+      }
+    }
+    for (uint32_t s = 0; s < k; ++s)
+      for (uint32_t i = 0; i < n; ++i) {
+        if (a.color[i] != order[s]) continue;
+        uint32_t wd[4];
+        orc_draw(seed, c_id, i, ORC_PURPOSE_MOVE_A, sweep, replica, wd);
+        float *r = chain + 3 * i;
+        float trial[3];
+        for (int d = 0; d < 3; ++d) trial[d] = fmaf(step, orc_v11(wd[d]), r[d]);
+        int acc = 0;
+        if (!orc_blocked(r, trial, nx, ny, nz)) {
+          double d_bond = orc_arch_bond_energy(trial, chain, &a, i, (double)k0) -
+                          orc_arch_bond_energy(r, chain, &a, i, (double)k0);
+          const float *om = omega + (uint64_t)a.type[i] * n_cells;
+          double d_field = ((double)om[orc_cell(trial, nx, ny, nz)] -
+                            (double)om[orc_cell(r, nx, ny, nz)]) / (double)n_ref;
+          double d_e = d_bond + d_field;
+          acc = (d_e <= 0.0) || ((double)orc_u01(wd[3]) < exp(-d_e));
+          if (acc) memcpy(r, trial, sizeof trial);
+        }
+        accepted += (uint64_t)acc;
+        if (accept_flags) accept_flags[(uint64_t)c * n + i] = (uint8_t)acc;
+      }
+  }
+  return accepted;
+}
+
+/* Histogram of chains of one architecture (types from the architecture). */
+int orc_density_hist_arch(const float *pos, uint32_t n_chains, const uint32_t *w,
+                          uint32_t n_words, uint32_t nx, uint32_t ny, uint32_t nz,
+                          uint32_t *counts) {
+  static orc_arch a;
+  if (orc_arch_decode(w, n_words, &a)) return -1;
+  uint64_t n_cells = (uint64_t)nx * ny * nz;
+  memset(counts, 0, 2 * n_cells * sizeof(uint32_t));
+  for (uint64_t c = 0; c < n_chains; ++c)
+    for (uint32_t i = 0; i < a.n; ++i) {
+      uint64_t cell = orc_cell(pos + 3 * (c * a.n + i), nx, ny, nz);
+      counts[(uint64_t)a.type[i] * n_cells + cell] += 1u;
+    }
+  return 0;
+}

@@ -133,6 +133,78 @@ def film_walks(seed: int, n_chains: int, n: int, grid, bond_sigma: float, z_lo: 
     return pos.reshape(-1, 3)
 
 
+def encode_architecture(n: int, types, bonds) -> np.ndarray:
+    """Molecular architecture in the 32-bit array format (interface format):
+    word 0 = N; word 1+i = type_i << 24 | index of monomer i's bond list (0: no
+    bonds); a bond word = (partner - i) in the low 27 bits (two's complement),
+    bond type 0 in bits 27-30, bit 31 set on the last bond of a list.  Each
+    bond (i, j) is listed at both ends, partners in ascending order."""
+    nbrs = [[] for _ in range(n)]
+    for i, j in bonds:
+        nbrs[i].append(j)
+        nbrs[j].append(i)
+    words = [n] + [0] * n
+    for i in range(n):
+        lst = sorted(nbrs[i])
+        start = len(words) if lst else 0
+        words[1 + i] = (int(types[i]) << 24) | start
+        for q, j in enumerate(lst):
+            words.append(((j - i) & 0x7FFFFFF) | ((1 << 31) if q == len(lst) - 1 else 0))
+    return np.asarray(words, np.uint32)
+
+
+def linear_architecture(n: int, n_a: int) -> np.ndarray:
+    return encode_architecture(n, [0 if i < n_a else 1 for i in range(n)],
+                               [(i, i + 1) for i in range(n - 1)])
+
+
+def star_bonds(arms: int, arm_len: int):
+    """Star of `arms` arms of `arm_len` monomers around a core (monomer 0),
+    numbered arm by arm outward: (n, bonds)."""
+    bonds = []
+    for a in range(arms):
+        first = 1 + a * arm_len
+        bonds.append((0, first))
+        bonds += [(first + k, first + k + 1) for k in range(arm_len - 1)]
+    return 1 + arms * arm_len, bonds
+
+
+def ring_bonds(n: int):
+    return n, [(i, (i + 1) % n) for i in range(n)]
+
+
+def tree_walks(seed: int, n_chains: int, n: int, bonds, grid, bond_sigma: float) -> np.ndarray:
+    """Ideal conformations of a tree molecule: monomer 0 uniform in the box, every
+    other monomer its lower-numbered bonded partner plus an N(0, bond_sigma^2)
+    vector per component (every monomer must have one; float32)."""
+    parent = [-1] * n
+    for i, j in bonds:
+        lo, hi = min(i, j), max(i, j)
+        if parent[hi] < 0:
+            parent[hi] = lo
+    assert all(p >= 0 for p in parent[1:])
+    g = rng(seed)
+    pos = np.zeros((n_chains, n, 3))
+    pos[:, 0] = g.random((n_chains, 3)) * np.asarray(grid, np.float64)
+    steps = g.standard_normal((n_chains, n, 3)) * bond_sigma
+    for i in range(1, n):
+        pos[:, i] = pos[:, parent[i]] + steps[:, i]
+    return pos.astype(np.float32).reshape(-1, 3)
+
+
+def ring_walks(seed: int, n_chains: int, n: int, grid, bond_sigma: float) -> np.ndarray:
+    """Ideal ring conformations: a Gaussian walk of n steps with its end-to-end
+    vector spread back over the steps (the walk conditioned to close); float32."""
+    g = rng(seed)
+    steps = g.standard_normal((n_chains, n, 3)) * bond_sigma
+    walk = np.cumsum(steps, axis=1)
+    frac = (np.arange(1, n + 1) / n)[None, :, None]
+    bridge = walk - frac * walk[:, -1:, :]
+    origin = g.random((n_chains, 1, 3)) * np.asarray(grid, np.float64)
+    pos = origin + np.concatenate([np.zeros((n_chains, 1, 3)), bridge[:, :-1]], axis=1)
+    return pos.astype(np.float32).reshape(-1, 3)
+
+
 def uniform_field(seed: int, n_cells: int, lo: float, hi: float) -> np.ndarray:
     """Random per-type fields, float32 [2, n_cells]."""
     return rng(seed).uniform(lo, hi, size=(2, n_cells)).astype(np.float32)
