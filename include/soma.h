@@ -208,6 +208,33 @@ int32_t soma_set_grad_field(soma_system *sys, void *grad, uint64_t grad_bytes, v
 int32_t soma_set_external(soma_system *sys, const float *ext, uint64_t ext_bytes,
                           const uint32_t *forbid, uint64_t forbid_bytes, void *stream);
 
+/* General molecular architecture of one species (Sec. 3.2.1), in place of the
+ * linear chain A_{n_a} B_{N - n_a}.  words (host memory, n_words entries):
+ * word 0 = N (must equal the species' n); word 1 + i = monomer i's type
+ * (0 = A, 1 = B) in the top byte and, in the low 24 bits, the index in the
+ * array of its bond list (0: no bonds); a bond word holds partner - i as a
+ * signed 27-bit integer in its low bits, the bond type in bits 27-30 (0,
+ * harmonic with the species' k0, is the only kind) and, in bit 31, the flag
+ * that ends the list.  Every bond must be listed at both ends; N <= 128,
+ * <= 2048 list entries, <= 16 independent sets.  The sets are found greedily
+ * in index order (monomer i joins the lowest set holding none of its bonded
+ * partners of lower index; a linear chain gives the even and the odd
+ * monomers) and swept as in SOMA_SCHEME_SET: with two sets, set 1 first iff
+ * bit 0 of word 0 of monomer 0's move draw is set; with more, a Fisher-Yates
+ * shuffle (step t = k-1 .. 1 swaps t with floor(w (t+1) / 2^32), w = word
+ * (k-1-t) mod 4 of the block (chain, floor((k-1-t)/4) | 8 << 16, sweep,
+ * replica)); set_order = 1: numerical order.  A linear chain given this way
+ * moves bit for bit as without it.  Positions are kept: they must be
+ * conformations of the architecture (the library's Gaussian-walk init
+ * follows index order).  The histogram and the fields are rebuilt.  Species
+ * with an architecture take SOMA_MOVE_LOCAL in the SET order only; they are
+ * not batched and give no training data (SOMA_E_UNSUPPORTED).  The bond
+ * observables sum over the bonds; Re^2 stays |r_{N-1} - r_0|^2.  words = NULL
+ * restores the linear chain.  Capture graphs again afterwards.  BLOCKING;
+ * SOMA_E_INVAL for a malformed array. */
+int32_t soma_set_architecture(soma_system *sys, uint32_t species, const uint32_t *words,
+                              uint32_t n_words, void *stream);
+
 /* Launch shape of the local-move sweep: 0 (default) runs one wave per tile
  * of chains; blocks > 0 runs that many persistent 256-thread blocks, each wave
  * looping over tiles and prefetching the next tile's positions.  Results are

@@ -17,6 +17,7 @@
 #include "soma_obs.hpp"
 #include "soma_sweep.hpp"
 #include "soma_molecule.hpp"
+#include "soma_arch.hpp"
 #include "soma_train.hpp"
 #include "soma_batch.hpp"
 #include "soma_sq.hpp"
@@ -55,13 +56,15 @@ struct Derived {
   uint64_t pos_bytes = 0, counts_bytes = 0, omega_bytes = 0;
   // workspace layout
   uint64_t off_err = 0, off_acc = 0, off_att = 0, off_net = 0, off_fpart = 0, off_totals = 0,
-           off_opart = 0, off_halo = 0;
+           off_opart = 0, off_halo = 0, off_arch = 0;
   uint64_t halo_plane = 0;    // floats per plane of the halo copy (0: not kept)
   // external fields (soma_set_external): caller-owned device buffers, null if none;
   // n_free = cells not impenetrable (the reference density counts these)
   const float *ext = nullptr;
   const uint32_t *forbid = nullptr;
   uint64_t n_free = 0;
+  // general architectures (soma_set_architecture): device tables per species, null: linear
+  const soma::ArchDev *arch[SOMA_MAX_SPECIES] = {};
   uint64_t ws_bytes = 0;
   uint32_t field_blocks = 1;  // blocks of the field update (and its FP64 partial sums)
 };
@@ -123,7 +126,8 @@ int32_t derive(const soma_config *c, Derived *d) {
   d->off_fpart = align_up(d->off_net + SOMA_MAX_SPECIES * align_up(sizeof(soma::NetDev)));
   d->off_totals = align_up(d->off_fpart + soma::kFieldBlocks * sizeof(soma::FieldPartial));
   d->off_opart = align_up(d->off_totals + sizeof(soma::Totals));
-  d->off_halo = align_up(d->off_opart + (d->obs_blocks ? d->obs_blocks : 1) * sizeof(soma::ObsPartial));
+  d->off_arch = align_up(d->off_opart + (d->obs_blocks ? d->obs_blocks : 1) * sizeof(soma::ObsPartial));
+  d->off_halo = align_up(d->off_arch + SOMA_MAX_SPECIES * align_up(sizeof(soma::ArchDev)));
   // the learned proposal reads its 27-cell neighbourhoods from a copy of the
   // fields with one periodic halo cell at both ends of each x row
   d->halo_plane = c->p_learn > 0.f ? (uint64_t)c->nz * c->ny * (c->nx + 2u) : 0u;
@@ -171,10 +175,10 @@ int32_t launch_hist(const soma_config *c, const Derived &d, const float *pos, vo
     const float *p = pos + 3 * d.bead_off[sp];
     if (c->count_width == 32)
       hipLaunchKernelGGL(soma::density_hist_kernel<true>, dim3((uint32_t)blocks), dim3(256), 0, s,
-                         p, nb, S.n, S.n_a, g, counts);
+                         p, nb, S.n, S.n_a, g, counts, d.arch[sp]);
     else
       hipLaunchKernelGGL(soma::density_hist_kernel<false>, dim3((uint32_t)blocks), dim3(256), 0,
-                         s, p, nb, S.n, S.n_a, g, counts);
+                         s, p, nb, S.n, S.n_a, g, counts, d.arch[sp]);
     LAUNCH_TRY();
   }
   return SOMA_OK;
@@ -267,6 +271,8 @@ struct soma_system {
   uint32_t sweep_blocks = 0;  // local-move grid: 0 = one tile per wave, else persistent blocks
   uint64_t mixed_moves = 0;   // bead moves made by mixed sweeps (local or learned)
   uint32_t net_mask = 0;      // species with an installed network (bit per species)
+  uint32_t arch_mask = 0;     // species with a general architecture (bit per species)
+  uint32_t arch_type0[SOMA_MAX_SPECIES] = {};  // A monomers per molecule of those species
   uint32_t substeps = 1;      // field refreshes per SCMF cycle (chain subsets)
   uint32_t scheme = SOMA_SCHEME_SET;  // iteration order of local moves
   float4 *grad = nullptr;     // optional gradient field (caller-owned), see soma_set_grad_field
@@ -286,6 +292,10 @@ struct soma_system {
   soma::ObsPartial *opart() { return reinterpret_cast<soma::ObsPartial *>(ws + d.off_opart); }
   float *halo() { return d.halo_plane ? reinterpret_cast<float *>(ws + d.off_halo) : nullptr; }
   unsigned long long *att() { return reinterpret_cast<unsigned long long *>(ws + d.off_att); }
+  soma::ArchDev *arch(uint32_t sp) {
+    return reinterpret_cast<soma::ArchDev *>(ws + d.off_arch + sp * align_up(sizeof(soma::ArchDev)));
+  }
+  const soma::ArchDev *arch_or_null(uint32_t sp) { return (arch_mask >> sp & 1u) ? arch(sp) : nullptr; }
   soma::NetDev *net(uint32_t sp) {
     return reinterpret_cast<soma::NetDev *>(ws + d.off_net + sp * align_up(sizeof(soma::NetDev)));
   }
@@ -379,6 +389,13 @@ int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s, uint32_t of
     a.n_sub = subset_size(S.n_chains, k, j);
     if (a.n_sub == 0) continue;
     const bool c64 = c->count_width == 32;
+    if (sys->d.arch[sp]) {   // general architecture: one wave per molecule (local moves, SET)
+      const dim3 grid((a.n_sub + 3u) / 4u);
+      if (c64) hipLaunchKernelGGL(soma::mc_sweep_arch_kernel<true>, grid, dim3(256), 0, s, a, sys->d.arch[sp]);
+      else hipLaunchKernelGGL(soma::mc_sweep_arch_kernel<false>, grid, dim3(256), 0, s, a, sys->d.arch[sp]);
+      LAUNCH_TRY();
+      continue;
+    }
     if (kind == SOMA_MOVE_LOCAL && sys->scheme == SOMA_SCHEME_MOLECULE) {
       uint32_t blocks = (a.n_sub + 255u) / 256u;   // one lane per chain
       if (sys->sweep_blocks && sys->sweep_blocks < blocks) blocks = sys->sweep_blocks;
@@ -423,6 +440,8 @@ int32_t check_kind(soma_system *sys, uint32_t move_kind) {
     return fail(SOMA_E_UNSUPPORTED, "local moves need a half-width below one cell");
   if (move_kind != SOMA_MOVE_LOCAL && sys->scheme != SOMA_SCHEME_SET)
     return fail(SOMA_E_UNSUPPORTED, "the molecule-parallel order has local moves only");
+  if (sys->arch_mask && (move_kind != SOMA_MOVE_LOCAL || sys->scheme != SOMA_SCHEME_SET))
+    return fail(SOMA_E_UNSUPPORTED, "general architectures have local moves in the SET order only");
   return SOMA_OK;
 }
 
@@ -713,6 +732,115 @@ int32_t soma_set_external(soma_system *sys, const float *ext, uint64_t ext_bytes
   return SOMA_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Decodes a 32-bit architecture array (Sec. 3.2.1) into the device table:
+// types, bond lists and the greedy independent sets (monomer i joins the
+// lowest set not holding a bonded monomer of lower index).  Returns 0 or a
+// message naming the first defect.
+const char *decode_architecture(const uint32_t *w, uint32_t n_words, uint32_t n_expected,
+                                soma::ArchDev &t) {
+  std::memset(&t, 0, sizeof t);
+  if (n_words < 1) return "empty array";
+  const uint32_t n = w[0];
+  if (n != n_expected) return "N differs from the species' chain length";
+  if (n == 0 || n > soma::kArchMaxN || n_words < 1 + n) return "N out of range or array too short";
+  t.n = n;
+  std::vector<std::vector<uint32_t>> nbrs(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    const uint32_t m = w[1 + i];
+    const uint32_t type = m >> 24;
+    if (type > 1) return "monomer type above 1";
+    t.type[i] = (uint8_t)type;
+    if (type == 0) ++t.n_type0;
+    uint32_t k = m & 0xFFFFFFu;
+    if (k == 0) continue;   // no bonds
+    while (true) {
+      if (k >= n_words) return "bond list runs off the array";
+      const uint32_t b = w[k++];
+      const int32_t off = (int32_t)(b << 5) >> 5;
+      if ((b >> 27) & 0xFu) return "bond type other than harmonic";
+      const int64_t j = (int64_t)i + off;
+      if (off == 0 || j < 0 || j >= (int64_t)n) return "bond partner out of range";
+      nbrs[i].push_back((uint32_t)j);
+      if (b >> 31) break;
+    }
+  }
+  uint32_t n_nb = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    for (uint32_t j : nbrs[i])
+      if (std::find(nbrs[j].begin(), nbrs[j].end(), i) == nbrs[j].end())
+        return "bond listed at one end only";
+    t.nb_start[i] = (uint16_t)n_nb;
+    for (uint32_t j : nbrs[i]) {
+      if (n_nb >= soma::kArchMaxBonds) return "too many bonds";
+      t.nb[n_nb++] = (uint8_t)j;
+    }
+  }
+  t.nb_start[n] = (uint16_t)n_nb;
+  std::vector<uint32_t> set(n, 0);
+  uint32_t k = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    uint32_t used = 0;
+    for (uint32_t j : nbrs[i])
+      if (j < i) used |= 1u << set[j];
+    uint32_t c = 0;
+    while (used >> c & 1u) ++c;
+    if (c >= soma::kArchMaxSets) return "more than 16 independent sets";
+    set[i] = c;
+    k = std::max(k, c + 1);
+  }
+  t.n_sets = k;
+  uint32_t pos = 0;
+  for (uint32_t c = 0; c < k; ++c) {
+    t.set_start[c] = (uint16_t)pos;
+    for (uint32_t i = 0; i < n; ++i)
+      if (set[i] == c) t.member[pos++] = (uint8_t)i;
+  }
+  t.set_start[k] = (uint16_t)pos;
+  return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t soma_set_architecture(soma_system *sys, uint32_t species, const uint32_t *words,
+                              uint32_t n_words, void *stream) {
+  if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
+  if (species >= sys->cfg.n_species) return fail(SOMA_E_INVAL, "species %u", species);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const soma_species &S = sys->cfg.species[species];
+  if (words) {
+    soma::ArchDev t;
+    const char *err = decode_architecture(words, n_words, S.n, t);
+    if (err) return fail(SOMA_E_INVAL, "architecture of species %u: %s", species, err);
+    HIP_TRY(hipMemcpyAsync(sys->arch(species), &t, sizeof t, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    sys->arch_mask |= 1u << species;
+    sys->arch_type0[species] = t.n_type0;
+    sys->d.arch[species] = sys->arch(species);
+  } else {
+    sys->arch_mask &= ~(1u << species);
+    sys->d.arch[species] = nullptr;
+  }
+  // expected A count for the conservation check
+  uint64_t n_a = 0;
+  for (uint32_t sp = 0; sp < sys->cfg.n_species; ++sp) {
+    const soma_species &X = sys->cfg.species[sp];
+    n_a += (uint64_t)X.n_chains * ((sys->arch_mask >> sp & 1u) ? sys->arch_type0[sp] : X.n_a);
+  }
+  sys->d.n_a_total = n_a;
+  sys->graph.release();
+  int32_t rc = launch_hist(&sys->cfg, sys->d, sys->buf.pos, sys->buf.counts, s);
+  if (!rc) rc = refresh_fields(sys, s);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(s));
+  return SOMA_OK;
+}
+
 int32_t soma_observables(soma_system *sys, soma_obs *out, void *stream) {
   if (!sys || !out) return fail(SOMA_E_INVAL, "system or out is NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -733,6 +861,7 @@ int32_t soma_observables(soma_system *sys, soma_obs *out, void *stream) {
     a.inv_nref = 1.0 / (double)c->n_ref;
     a.grid = sys->grid;
     a.partials = sys->opart() + sys->d.obs_block_off[sp];
+    a.arch = sys->d.arch[sp];
     a.err = sys->err();
     hipLaunchKernelGGL(soma::chain_obs_kernel, dim3((S.n_chains + 255) / 256), dim3(256), 0, s, a);
     LAUNCH_TRY();
@@ -897,6 +1026,7 @@ int32_t soma_collect_training(soma_system *sys, uint32_t species, uint32_t n, ui
       (species >= sys->cfg.n_species || sys->cfg.species[species].n_chains == 0))
     return fail(SOMA_E_INVAL, "species %u has no chains", species);
   if (phase == 1 && !dr) return fail(SOMA_E_INVAL, "phase 1 needs dr");
+  if (sys->arch_mask) return fail(SOMA_E_UNSUPPORTED, "training data of linear chains only");
   if (n == 0) return SOMA_OK;
   soma::CollectArgs a;
   a.pos = sys->buf.pos;
@@ -1261,6 +1391,7 @@ int32_t batch_check_kind(soma_batch *b, uint32_t kind) {
     if (rc) return rc;
     if (x->scheme != SOMA_SCHEME_SET)
       return fail(SOMA_E_UNSUPPORTED, "batched sweeps use the SET order only");
+    if (x->arch_mask) return fail(SOMA_E_UNSUPPORTED, "batched sweeps take linear chains only");
   }
   return SOMA_OK;
 }

@@ -1,0 +1,105 @@
+// soma_arch.hpp -- general molecular architectures: device tables and the SET
+// sweep over arbitrary bond graphs.
+#pragma once
+
+#include "soma_sweep.hpp"
+
+namespace soma {
+
+constexpr uint32_t kPurposeSetOrder = 8u; // Philox purpose of the shuffled set order
+
+// Sec. 3.1.2, scheme 2, for any architecture: one wave per molecule, the
+// molecule's positions staged in LDS; the independent sets one after another
+// in the molecule's order for this sweep (two sets: set 1 first iff bit 0 of
+// word 0 of monomer 0's move draw, as for linear chains; more: a Fisher-Yates
+// shuffle from the purpose-8 blocks; set_order = 1: numerical order), the
+// members of a set on the lanes at once.  A move is the LOCAL move of the
+// linear kernel, the bond term summed over the monomer's bond list in list
+// order, so a linear chain given as an architecture moves bit for bit as in
+// mc_sweep_local_kernel.
+template <bool COUNT64>
+__global__ __launch_bounds__(256) void mc_sweep_arch_kernel(const SweepArgs a_in,
+                                                            const ArchDev *__restrict__ A) {
+  __shared__ float s_pos[4][3 * kArchMaxN];
+  __shared__ uint8_t s_order[4][kArchMaxSets];
+  const SweepArgs a = resolve_sweep(a_in, 0u);
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  const uint32_t cl = xcd_remap(blockIdx.x, gridDim.x) * 4u + wv;
+  uint32_t n_acc = 0;
+  if (cl < a.n_sub) {
+    const uint32_t N = A->n, k = A->n_sets;
+    const uint32_t chain = cl * a.sub_k + a.sub_j;
+    const uint32_t gchain = a.chain_base + chain;
+    float *cp = a.pos + (size_t)chain * N * 3u;
+    float *sp = s_pos[wv];
+    for (uint32_t q = lane; q < 3u * N; q += 64u) sp[q] = cp[q];
+    if (lane == 0) {
+      for (uint32_t s = 0; s < k; ++s) s_order[wv][s] = (uint8_t)s;
+      if (a.set_order == 0 && k == 2) {
+        const Rand4 d = philox(gchain, 0u, a.sweep, a.replica, a.seed_lo, a.seed_hi);
+        if (d.x & 1u) { s_order[wv][0] = 1; s_order[wv][1] = 0; }
+      } else if (a.set_order == 0 && k > 2) {
+        Rand4 d = {0u, 0u, 0u, 0u};
+        for (uint32_t t = k - 1, st = 0; t >= 1; --t, ++st) {
+          if ((st & 3u) == 0u)
+            d = philox(gchain, (st >> 2) | (kPurposeSetOrder << 16), a.sweep, a.replica, a.seed_lo,
+                       a.seed_hi);
+          const uint32_t q = st & 3u;
+          const uint32_t word = q == 0u ? d.x : (q == 1u ? d.y : (q == 2u ? d.z : d.w));
+          const uint32_t j = __umulhi(word, t + 1u);
+          const uint8_t tmp = s_order[wv][t];
+          s_order[wv][t] = s_order[wv][j];
+          s_order[wv][j] = tmp;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (uint32_t s = 0; s < k; ++s) {
+      const uint32_t set = s_order[wv][s];
+      const uint32_t m0 = A->set_start[set], m1 = A->set_start[set + 1];
+      for (uint32_t base = m0; base < m1; base += 64u) {
+        const uint32_t idx = base + lane;
+        bool acc = false;
+        if (idx < m1) {
+          const uint32_t i = A->member[idx];
+          const F3 r = {sp[3 * i], sp[3 * i + 1], sp[3 * i + 2]};
+          const Rand4 w = philox(gchain, i | (kPurposeMoveA << 16), a.sweep, a.replica, a.seed_lo,
+                                 a.seed_hi);
+          const F3 t = {fmaf(a.step, uniform11(w.x), r.x), fmaf(a.step, uniform11(w.y), r.y),
+                        fmaf(a.step, uniform11(w.z), r.z)};
+          const F3 d = t - r;
+          F3 qv = {0.f, 0.f, 0.f};
+          for (uint32_t b = A->nb_start[i]; b < A->nb_start[i + 1]; ++b) {
+            const uint32_t j = A->nb[b];
+            const F3 rj = {sp[3 * j], sp[3 * j + 1], sp[3 * j + 2]};
+            qv = qv + (2.0f * (r - rj) + d);
+          }
+          uint32_t x, y, z;
+          cell3(a.grid, r.x, r.y, r.z, x, y, z);
+          const uint32_t co = cell_index(a.grid, x, y, z);
+          const uint32_t cn = cell_index(a.grid, shift_cell(x, r.x, t.x, a.grid.nx),
+                                         shift_cell(y, r.y, t.y, a.grid.ny),
+                                         shift_cell(z, r.z, t.z, a.grid.nz));
+          const bool is_b = A->type[i] != 0;
+          const uint32_t pl = is_b ? a.grid.n_cells : 0u;
+          const float wo = field_at(a.omega, pl, co);
+          const float wn = cn == co ? wo : field_at(a.omega, pl, cn);
+          const float d_e = a.half_k0 * (d.x * qv.x + d.y * qv.y + d.z * qv.z) + (wn - wo) * a.inv_nref;
+          acc = move_allowed(a, co, cn) && (d_e <= 0.0f || uniform01(w.w) < __expf(-d_e));
+          if (acc) {
+            sp[3 * i] = t.x;
+            sp[3 * i + 1] = t.y;
+            sp[3 * i + 2] = t.z;
+            if (cn != co) move_count<COUNT64>(a.counts, co, cn, is_b);
+          }
+        }
+        n_acc += (uint32_t)__popcll(__ballot(acc));
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+    for (uint32_t q = lane; q < 3u * N; q += 64u) cp[q] = sp[q];
+  }
+  finish_block(a, n_acc);
+}
+
+}  // namespace soma

@@ -131,4 +131,28 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t n) {
   return (b & 7u) * (n8 >> 3) + (b >> 3);
 }
 
+// ---------------------------------------------------------------------------
+// General molecular architectures (decoded on the host).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kArchMaxN = 128;       // monomers per molecule
+constexpr uint32_t kArchMaxBonds = 2048;  // bond-list entries (each bond twice)
+constexpr uint32_t kArchMaxSets = 16;
+
+// One molecule type, decoded from the 32-bit architecture array (Sec. 3.2.1)
+// on the host: types, the bond lists (partners in the array's order) and the
+// independent sets (members of set s: member[set_start[s] .. set_start[s+1])).
+struct ArchDev {
+  uint32_t n, n_sets, n_type0, pad;
+  uint8_t type[kArchMaxN];
+  uint8_t member[kArchMaxN];
+  uint16_t set_start[kArchMaxSets + 1];
+  uint16_t nb_start[kArchMaxN + 1];
+  uint8_t nb[kArchMaxBonds];
+};
+
+// Type of monomer i: from the architecture, else the linear rule i < n_a -> A.
+__device__ __forceinline__ bool bead_is_b(const ArchDev *arch, uint32_t i, uint32_t n_a) {
+  return arch ? arch->type[i] != 0 : i >= n_a;
+}
+
 }  // namespace soma

@@ -21,17 +21,18 @@ struct FieldPartial {
 template <bool COUNT64>
 __global__ __launch_bounds__(256) void density_hist_kernel(
     const float *pos, uint64_t n_beads, uint32_t n, uint32_t n_a, Grid g,
-    void *counts) {
+    void *counts, const ArchDev *arch) {
   const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n_beads) return;
   const float *r = pos + 3 * b;
   const uint32_t cell = cell_of(g, r[0], r[1], r[2]);
   const uint32_t i = n_beads <= 0xFFFFFFFFull ? (uint32_t)b % n : (uint32_t)(b % n);
+  const bool is_b = bead_is_b(arch, i, n_a);
   if (COUNT64) {
-    const unsigned long long inc = 1ull << (i < n_a ? 0u : 32u);
+    const unsigned long long inc = 1ull << (is_b ? 32u : 0u);
     atomicAdd(reinterpret_cast<unsigned long long *>(counts) + cell, inc);
   } else {
-    const unsigned int inc = 1u << (i < n_a ? 0u : 16u);
+    const unsigned int inc = 1u << (is_b ? 16u : 0u);
     atomicAdd(reinterpret_cast<unsigned int *>(counts) + cell, inc);
   }
 }

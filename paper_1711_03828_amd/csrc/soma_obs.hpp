@@ -31,6 +31,7 @@ struct ObsArgs {
   Grid grid;
   ObsPartial *partials;
   uint32_t *err;
+  const ArchDev *arch;   // general architecture (types, bonds), or null: linear chain
 };
 
 template <int NV>
@@ -50,7 +51,8 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*s)[NV]) {
 
 // Per-chain observables, Eqs. (1)-(2) and (13): Re^2 = |r_{N-1} - r_0|^2,
 // Rg^2 = (1/N) sum |r_i - r_cm|^2, sum of squared bond lengths, bond energy
-// (k0/2) sum b^2 and field energy sum_i omega_t(c_i) / N. A chain occupies a
+// (k0/2) sum b^2 (over the bond list for a general architecture) and field
+// energy sum_i omega_t(c_i) / N. A chain occupies a
 // segment of `seg` lanes (the smallest power of two >= N, at most 64) and bead
 // i sits on lane i mod seg, so a wave reads 64/seg whole chains with adjacent
 // lanes on adjacent beads. A block of four waves covers 256 consecutive chains
@@ -73,7 +75,15 @@ __global__ __launch_bounds__(256) void chain_obs_kernel(const ObsArgs a) {
         const float x = p[3 * i], y = p[3 * i + 1], z = p[3 * i + 2];
         bad |= !(coord_ok(x) && coord_ok(y) && coord_ok(z));
         sx += x; sy += y; sz += z;
-        if (i > 0) {
+        if (a.arch) {   // each bond once, from its lower-numbered end
+          for (uint32_t q = a.arch->nb_start[i]; q < a.arch->nb_start[i + 1]; ++q) {
+            const uint32_t j = a.arch->nb[q];
+            if (j < i) continue;
+            const double dx = (double)x - p[3 * j], dy = (double)y - p[3 * j + 1],
+                         dz = (double)z - p[3 * j + 2];
+            b2 += dx * dx + dy * dy + dz * dz;
+          }
+        } else if (i > 0) {
           const double dx = (double)x - p[3 * i - 3], dy = (double)y - p[3 * i - 2],
                        dz = (double)z - p[3 * i - 1];
           b2 += dx * dx + dy * dy + dz * dz;
@@ -83,7 +93,7 @@ __global__ __launch_bounds__(256) void chain_obs_kernel(const ObsArgs a) {
           re2 += ex * ex + ey * ey + ez * ez;
         }
         const uint32_t cell = cell_of(a.grid, x, y, z);
-        ef += (double)a.omega[(i < a.n_a ? 0u : a.grid.n_cells) + cell];
+        ef += (double)a.omega[(bead_is_b(a.arch, i, a.n_a) ? a.grid.n_cells : 0u) + cell];
       }
     }
     for (uint32_t off = seg >> 1; off > 0; off >>= 1) {   // sums within the segment

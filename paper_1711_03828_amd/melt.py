@@ -145,6 +145,11 @@ class Melt:
                             forbid.data_ptr() if forbid is not None else None,
                             forbid.numel() * 4 if forbid is not None else 0, _stream(stream))
 
+    def set_architecture(self, words, species: int = 0, stream=None):
+        """General molecular architecture of a species (numpy uint32 array in the
+        32-bit format), or None for a linear chain."""
+        C.soma_set_architecture(self.handle, species, words, _stream(stream))
+
     def set_scheme(self, scheme: int):
         """Iteration order of local moves: C.SOMA_SCHEME_SET or C.SOMA_SCHEME_MOLECULE."""
         C.soma_set_scheme(self.handle, scheme)

@@ -109,6 +109,7 @@ _SIGS = {
     "soma_rebuild_histogram": ([_P, _P], _i32),
     "soma_set_sweep_blocks": ([_P, _u32], _i32),
     "soma_set_scheme": ([_P, _u32], _i32),
+    "soma_set_architecture": ([_P, _u32, _P, _u32, _P], _i32),
     "soma_set_external": ([_P, _P, _u64, _P, _u64, _P], _i32),
     "soma_choose_scheme": ([_P, _u32, _P, ctypes.POINTER(_u32), ctypes.POINTER(ctypes.c_float)],
                            _i32),
@@ -203,6 +204,16 @@ def soma_set_sweep_blocks(h, blocks: int) -> None:
 
 def soma_set_external(h, ext_ptr, ext_bytes: int, forbid_ptr, forbid_bytes: int, stream) -> None:
     _check(_lib.soma_set_external(h, ext_ptr, ext_bytes, forbid_ptr, forbid_bytes, stream))
+
+
+def soma_set_architecture(h, species: int, words, stream) -> None:
+    """words: numpy uint32 architecture array (host), or None for a linear chain."""
+    import numpy as np
+    if words is None:
+        _check(_lib.soma_set_architecture(h, species, None, 0, stream))
+        return
+    w = np.ascontiguousarray(words, dtype=np.uint32)
+    _check(_lib.soma_set_architecture(h, species, w.ctypes.data, w.size, stream))
 
 
 def soma_set_scheme(h, scheme: int) -> None:
