@@ -325,6 +325,61 @@ def scheme_leg(cycles: int):
             "cycles": cycles // 10 * 10, "sizes": rows}
 
 
+def arch_leg(cycles: int):
+    """General molecular architectures (Sec. 3.2.1): the 262,144-chain A16B16 melt
+    swept by the linear kernel and, given as an architecture, by the
+    general-architecture kernel (same bits, the cost of generality), and a melt
+    of 6-arm stars (31 monomers, arms of 5, A core half) at the same density.
+    Graph-replayed SCMF cycles."""
+    import numpy as np
+    import torch
+
+    from paper_1711_03828_amd import soma as C
+    from paper_1711_03828_amd.melt import Melt, make_config
+
+    stream = torch.cuda.current_stream()
+
+    def timed(m):
+        m.capture_cycle(10)
+        m.run_cycle(1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        m.run_cycle(cycles // 10)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / (cycles // 10 * 10)
+
+    out = {}
+    w = synth.C4_MEDIUM
+    for name, arch in (("linear_kernel", False), ("architecture_kernel", True)):
+        m = Melt(make_config(w))
+        if arch:
+            m.set_architecture(synth.linear_architecture(32, 16))
+        ms = timed(m)
+        out[name] = {"workload": w.name, "ms_per_cycle": ms, "bead_moves_per_s": w.n_beads * 1e3 / ms}
+        m.close()
+    n, bonds = synth.star_bonds(6, 5)
+    types = [0] + [0 if (i - 1) % 5 < 2 else 1 for i in range(1, n)]
+    n_chains = w.n_beads // n
+    ws = synth.Workload("star6x5_melt_grid96", w.grid, (synth.SpeciesSpec(n_chains, n, 0),),
+                        6.0, 32, w.chi_n, w.kappa_n, 16)
+    k0 = 3.0 * 31 / 36.0
+    pos = torch.from_numpy(synth.tree_walks(7, n_chains, n, bonds, w.grid, 1 / math.sqrt(k0)))
+    m = Melt(make_config(ws), positions=pos)
+    m.set_architecture(synth.encode_architecture(n, types, bonds))
+    ms = timed(m)
+    obs = m.observables()
+    out["star_melt"] = {"workload": ws.name, "molecules": n_chains, "n_beads": ws.n_beads,
+                        "ms_per_cycle": ms, "bead_moves_per_s": ws.n_beads * 1e3 / ms,
+                        "acceptance": obs.accepted[0] / max(1, obs.attempted[0]),
+                        "counts_conserved": obs.counts_conserved}
+    m.close()
+    print(f"# architectures: linear {out['linear_kernel']['ms_per_cycle']:.3f} ms, as architecture "
+          f"{out['architecture_kernel']['ms_per_cycle']:.3f} ms, stars {ms:.3f} ms per cycle",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def film_leg(kind: str, lateral_re: float, cycles: int):
     """The thin-film workloads of Sec. 5.6 on one GPU: diblocks of N = 100 at
     sqrt(Nbar) = 85.7 (Delta L = Re0/6, kappaN = 50), lamella-forming (f = 0.5,
@@ -572,6 +627,8 @@ def main():
                     help="skip the 64-replica batched measurement")
     ap.add_argument("--no-schemes", action="store_true",
                     help="skip the SET vs molecule-parallel comparison over system size")
+    ap.add_argument("--no-arch", action="store_true",
+                    help="skip the general-architecture measurement")
     ap.add_argument("--film", choices=["lam", "hex"], default="lam",
                     help="thin-film workload: lamella- or cylinder-forming diblocks")
     ap.add_argument("--film-lateral", type=float, default=200.0,
@@ -709,6 +766,8 @@ def main():
         result["batched"] = batched_leg(50)
     if not args.no_schemes:
         result["schemes"] = scheme_leg(200)
+    if not args.no_arch:
+        result["architectures"] = arch_leg(200)
     if args.film_cycles > 0:
         result["film"] = film_leg(args.film, args.film_lateral, args.film_cycles)
     if args.blend:

@@ -273,6 +273,7 @@ struct soma_system {
   uint32_t net_mask = 0;      // species with an installed network (bit per species)
   uint32_t arch_mask = 0;     // species with a general architecture (bit per species)
   uint32_t arch_type0[SOMA_MAX_SPECIES] = {};  // A monomers per molecule of those species
+  uint32_t arch_per_wave[SOMA_MAX_SPECIES] = {};  // molecules per wave of their sweep
   uint32_t substeps = 1;      // field refreshes per SCMF cycle (chain subsets)
   uint32_t scheme = SOMA_SCHEME_SET;  // iteration order of local moves
   float4 *grad = nullptr;     // optional gradient field (caller-owned), see soma_set_grad_field
@@ -389,8 +390,9 @@ int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s, uint32_t of
     a.n_sub = subset_size(S.n_chains, k, j);
     if (a.n_sub == 0) continue;
     const bool c64 = c->count_width == 32;
-    if (sys->d.arch[sp]) {   // general architecture: one wave per molecule (local moves, SET)
-      const dim3 grid((a.n_sub + 3u) / 4u);
+    if (sys->d.arch[sp]) {   // general architecture: per_wave molecules per wave (local moves, SET)
+      const uint32_t per_block = 4u * sys->arch_per_wave[sp];
+      const dim3 grid((a.n_sub + per_block - 1u) / per_block);
       if (c64) hipLaunchKernelGGL(soma::mc_sweep_arch_kernel<true>, grid, dim3(256), 0, s, a, sys->d.arch[sp]);
       else hipLaunchKernelGGL(soma::mc_sweep_arch_kernel<false>, grid, dim3(256), 0, s, a, sys->d.arch[sp]);
       LAUNCH_TRY();
@@ -800,6 +802,9 @@ const char *decode_architecture(const uint32_t *w, uint32_t n_words, uint32_t n_
       if (set[i] == c) t.member[pos++] = (uint8_t)i;
   }
   t.set_start[k] = (uint16_t)pos;
+  uint32_t largest = 1;
+  for (uint32_t c = 0; c < k; ++c) largest = std::max<uint32_t>(largest, t.set_start[c + 1] - t.set_start[c]);
+  t.per_wave = std::max(1u, std::min(64u / largest, soma::kArchMaxN / n));
   return nullptr;
 }
 
@@ -821,6 +826,7 @@ int32_t soma_set_architecture(soma_system *sys, uint32_t species, const uint32_t
     HIP_TRY(hipStreamSynchronize(s));
     sys->arch_mask |= 1u << species;
     sys->arch_type0[species] = t.n_type0;
+    sys->arch_per_wave[species] = t.per_wave;
     sys->d.arch[species] = sys->arch(species);
   } else {
     sys->arch_mask &= ~(1u << species);

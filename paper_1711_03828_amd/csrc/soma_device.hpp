@@ -142,7 +142,8 @@ constexpr uint32_t kArchMaxSets = 16;
 // on the host: types, the bond lists (partners in the array's order) and the
 // independent sets (members of set s: member[set_start[s] .. set_start[s+1])).
 struct ArchDev {
-  uint32_t n, n_sets, n_type0, pad;
+  uint32_t n, n_sets, n_type0;
+  uint32_t per_wave;   // molecules per wave: min(64 / largest set, 128 / n), at least 1
   uint8_t type[kArchMaxN];
   uint8_t member[kArchMaxN];
   uint16_t set_start[kArchMaxSets + 1];

@@ -37,8 +37,8 @@ def _cfg(grid, species, k0, **kw):
                          kappa_n=40.0, local_a=0.3, count_width=16, seed=123, **kw)
 
 
-@pytest.mark.parametrize("set_order", [0, 1])
-def test_linear_architecture_equals_linear_kernel(C, set_order):
+@pytest.mark.parametrize("set_order,substeps", [(0, 1), (1, 1), (0, 3)])
+def test_linear_architecture_equals_linear_kernel(C, set_order, substeps):
     from paper_1711_03828_amd.melt import Melt
     grid = (20, 18, 10)
     species = [(300, 32, 16), (70, 17, 5), (40, 1, 1)]
@@ -53,6 +53,7 @@ def test_linear_architecture_equals_linear_kernel(C, set_order):
         if use_arch:
             for sp, (_, n, n_a) in enumerate(species):
                 m.set_architecture(synth.linear_architecture(n, n_a), sp)
+        m.set_substeps(substeps)
         m.cycle(4)
         torch.cuda.synchronize()
         obs = m.observables()
