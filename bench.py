@@ -718,6 +718,19 @@ def main():
                          "achieved_GBs": field_bytes(w) / (field_ms * 1e-3) / 1e9},
         "acceptance": acc,
     }
+    # histogram atomic rate: a sweep issues two count atomics per bead that changes
+    # cell; counted for one more sweep by comparing the cells before and after it
+    grid_t = torch.tensor(w.grid, dtype=torch.float64, device=melt.pos.device)
+
+    def cells():
+        return torch.remainder(torch.floor(melt.pos.view(-1, 3).double()), grid_t)
+
+    before = cells()
+    melt.sweep(1, move)
+    changed = int((cells() != before).any(dim=1).sum().item())
+    del before
+    result["atomics"] = {"per_sweep": 2 * changed, "per_s": 2 * changed / (sweep_ms * 1e-3),
+                         "beads_changing_cell": changed / w.n_beads}
     if args.move == "local":
         # the molecule-parallel order (Sec. 3.1.2, scheme 1) on the same melt
         melt.set_scheme(C.SOMA_SCHEME_MOLECULE)
