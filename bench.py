@@ -45,7 +45,7 @@ def field_bytes(w):
 
 
 # Sources the sweep kernels and their launches are built from.
-SWEEP_SOURCES = ("include/soma.h", "paper_1711_03828_amd/csrc/soma_api.hip",
+SWEEP_SOURCES = ("paper_1711_03828_amd/csrc/soma_api.hip",
                  "paper_1711_03828_amd/csrc/soma_device.hpp",
                  "paper_1711_03828_amd/csrc/soma_mlp.hpp",
                  "paper_1711_03828_amd/csrc/soma_sweep.hpp")

@@ -58,7 +58,7 @@ typedef enum soma_status {
   SOMA_E_INVAL = -1,        /* invalid argument or configuration */
   SOMA_E_HIP = -2,          /* a HIP runtime call or kernel launch failed */
   SOMA_E_SIZE = -3,         /* a caller buffer is smaller than required */
-  SOMA_E_UNSUPPORTED = -4,  /* valid request this build does not support */
+  SOMA_E_UNSUPPORTED = -4,  /* valid request the library does not support */
   SOMA_E_DEVICE_FLAG = -5   /* a kernel raised the device error word */
 } soma_status;
 
