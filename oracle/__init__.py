@@ -60,9 +60,9 @@ def lib() -> ctypes.CDLL:
         L.orc_v11.argtypes = [u32]
         L.orc_v11.restype = f32
         L.orc_density_hist.argtypes = [P, u32, P, P, P, u32, u32, u32, P]
-        L.orc_field_f64.argtypes = [P, u64, f64, f64, f64, P, P, P]
-        L.orc_field_f32.argtypes = [P, u64, f32, f32, f32, P, P, P]
-        L.orc_h_nb.argtypes = [P, u64, f64, f64, f64, u32, P]
+        L.orc_field_f64.argtypes = [P, u64, f64, f64, f64, u32, P, P, P]
+        L.orc_field_f32.argtypes = [P, u64, f32, f32, f32, u32, P, P, P]
+        L.orc_h_nb.argtypes = [P, u64, f64, f64, f64, u32, u32, P]
         L.orc_set_forbidden.argtypes = [P]
         L.orc_h_nb.restype = f64
         L.orc_mc_sweep.argtypes = [P, u32, u32, u32, f32, u32, P, u32, u32, u32, u32,
@@ -142,35 +142,37 @@ def _opt(a, dtype):
 
 
 def field_f64(counts: np.ndarray, inv_rho: float, chi_n: float, kappa_n: float, ext=None,
-              forbid=None) -> np.ndarray:
+              forbid=None, form=1) -> np.ndarray:
     """ext: optional float32 [2, n_cells] external field; forbid: optional packed
     bit mask (uint32, bit c % 32 of word c // 32) of impenetrable cells."""
     counts = _c(counts, np.uint32)
     n_cells = counts.shape[-1]
     ext, forbid = _opt(ext, np.float32), _opt(forbid, np.uint32)
     om = np.empty((2, n_cells), np.float64)
-    lib().orc_field_f64(_ptr(counts), n_cells, inv_rho, chi_n, kappa_n,
+    lib().orc_field_f64(_ptr(counts), n_cells, inv_rho, chi_n, kappa_n, form,
                         _ptr(ext) if ext is not None else None,
                         _ptr(forbid) if forbid is not None else None, _ptr(om))
     return om
 
 
-def field_f32(counts: np.ndarray, inv_rho, chi_n, kappa_n, ext=None, forbid=None) -> np.ndarray:
+def field_f32(counts: np.ndarray, inv_rho, chi_n, kappa_n, ext=None, forbid=None,
+              form=1) -> np.ndarray:
     counts = _c(counts, np.uint32)
     n_cells = counts.shape[-1]
     ext, forbid = _opt(ext, np.float32), _opt(forbid, np.uint32)
     om = np.empty((2, n_cells), np.float32)
     lib().orc_field_f32(_ptr(counts), n_cells, float(np.float32(inv_rho)),
-                        float(np.float32(chi_n)), float(np.float32(kappa_n)),
+                        float(np.float32(chi_n)), float(np.float32(kappa_n)), form,
                         _ptr(ext) if ext is not None else None,
                         _ptr(forbid) if forbid is not None else None, _ptr(om))
     return om
 
 
-def h_nb(counts, inv_rho, chi_n, kappa_n, n_ref, forbid=None) -> float:
+def h_nb(counts, inv_rho, chi_n, kappa_n, n_ref, forbid=None, form=1) -> float:
+    """form 1: the K^1 interaction term, 0: K^0 (Eq. (6))."""
     counts = _c(counts, np.uint32)
     forbid = _opt(forbid, np.uint32)
-    return lib().orc_h_nb(_ptr(counts), counts.shape[-1], inv_rho, chi_n, kappa_n, n_ref,
+    return lib().orc_h_nb(_ptr(counts), counts.shape[-1], inv_rho, chi_n, kappa_n, n_ref, form,
                           _ptr(forbid) if forbid is not None else None)
 
 

@@ -174,15 +174,24 @@ static int orc_bit(const uint32_t *mask, uint64_t c) {
   return mask && ((mask[c >> 5] >> (c & 31u)) & 1u);
 }
 
+/* form selects the interaction term of Eq. (6): 1 = K^1 (chiN phi_A phi_B, the
+ * default), 0 = K^0 (-chiN/4 (phi_A - phi_B)^2), both read over unordered
+ * pairs; the K^0 field is kappaN (phi_A+phi_B-1) -+ chiN/2 (phi_A - phi_B)
+ * (Eq. (12), its first form). */
 void orc_field_f64(const uint32_t *counts, uint64_t n_cells, double inv_rho,
-                   double chi_n, double kappa_n, const float *ext,
+                   double chi_n, double kappa_n, uint32_t form, const float *ext,
                    const uint32_t *forbid, double *omega) {
   for (uint64_t c = 0; c < n_cells; ++c) {
     double phi_a = counts[c] * inv_rho;
     double phi_b = counts[n_cells + c] * inv_rho;
     double incompress = kappa_n * (phi_a + phi_b - 1.0);
-    omega[c] = incompress + chi_n * phi_b;
-    omega[n_cells + c] = incompress + chi_n * phi_a;
+    if (form == 0) {
+      omega[c] = incompress - 0.5 * chi_n * (phi_a - phi_b);
+      omega[n_cells + c] = incompress - 0.5 * chi_n * (phi_b - phi_a);
+    } else {
+      omega[c] = incompress + chi_n * phi_b;
+      omega[n_cells + c] = incompress + chi_n * phi_a;
+    }
     if (ext) {
       omega[c] += (double)ext[c];
       omega[n_cells + c] += (double)ext[n_cells + c];
@@ -195,16 +204,25 @@ void orc_field_f64(const uint32_t *counts, uint64_t n_cells, double inv_rho,
  * one by one, the chi term fused), used to hold the device result to
  * bit equality.  Compiled with -ffp-contract=off so the order is the one
  * written. */
+/* K^0 in FP32: d = phi_A - phi_B, omega_A = fma(-chiN/2, d, t),
+ * omega_B = fma(chiN/2, d, t) (chiN/2 is exact). */
 void orc_field_f32(const uint32_t *counts, uint64_t n_cells, float inv_rho,
-                   float chi_n, float kappa_n, const float *ext,
+                   float chi_n, float kappa_n, uint32_t form, const float *ext,
                    const uint32_t *forbid, float *omega) {
   for (uint64_t c = 0; c < n_cells; ++c) {
     float phi_a = (float)counts[c] * inv_rho;
     float phi_b = (float)counts[n_cells + c] * inv_rho;
     float s = (phi_a + phi_b) - 1.0f;
     float t = kappa_n * s;
-    float wa = fmaf(chi_n, phi_b, t);
-    float wb = fmaf(chi_n, phi_a, t);
+    float wa, wb;
+    if (form == 0) {
+      float d = phi_a - phi_b;
+      wa = fmaf(-0.5f * chi_n, d, t);
+      wb = fmaf(0.5f * chi_n, d, t);
+    } else {
+      wa = fmaf(chi_n, phi_b, t);
+      wb = fmaf(chi_n, phi_a, t);
+    }
     if (ext) {
       wa = wa + ext[c];
       wb = wb + ext[n_cells + c];
@@ -220,7 +238,7 @@ void orc_field_f32(const uint32_t *counts, uint64_t n_cells, float inv_rho,
  * (the i != j sum of Eq. (8) read over unordered pairs, which is the reading
  * that reproduces the field of Eq. (12) as its derivative). */
 double orc_h_nb(const uint32_t *counts, uint64_t n_cells, double inv_rho,
-                double chi_n, double kappa_n, uint32_t n_ref,
+                double chi_n, double kappa_n, uint32_t n_ref, uint32_t form,
                 const uint32_t *forbid) {
   double sum = 0.0;
   for (uint64_t c = 0; c < n_cells; ++c) {
@@ -228,7 +246,9 @@ double orc_h_nb(const uint32_t *counts, uint64_t n_cells, double inv_rho,
     double phi_a = counts[c] * inv_rho;
     double phi_b = counts[n_cells + c] * inv_rho;
     double dev = phi_a + phi_b - 1.0;
-    sum += 0.5 * kappa_n * dev * dev + chi_n * phi_a * phi_b;
+    double inter = form == 0 ? -0.25 * chi_n * (phi_a - phi_b) * (phi_a - phi_b)
+                             : chi_n * phi_a * phi_b;
+    sum += 0.5 * kappa_n * dev * dev + inter;
   }
   return sum / (inv_rho * (double)n_ref);
 }

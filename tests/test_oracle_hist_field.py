@@ -114,3 +114,35 @@ def test_field_fp32_close_to_fp64(orc):
     a = orc.field_f64(counts, 27.0 / 128.0, 20.0, 50.0)
     b = orc.field_f32(counts, 27.0 / 128.0, 20.0, 50.0)
     np.testing.assert_allclose(b, a, rtol=0, atol=5e-5 * np.abs(a).max())
+
+
+def test_k0_field_closed_values(orc):
+    """The K^0 interaction (Eq. (6), first form): an empty cell -kappaN, a pure A
+    cell at the reference density -chiN/2 for A and +chiN/2 for B, a balanced
+    cell 0 for both; FP64 and the FP32 order."""
+    counts = np.array([[0, 10, 0, 5], [0, 0, 10, 5]], np.uint32)
+    inv_rho, chi, kap = 0.1, 24.0, 50.0
+    exp = np.array([[-kap, -chi / 2, chi / 2, 0.0], [-kap, chi / 2, -chi / 2, 0.0]])
+    np.testing.assert_allclose(orc.field_f64(counts, inv_rho, chi, kap, form=0), exp, atol=1e-12)
+    np.testing.assert_allclose(orc.field_f32(counts, np.float32(inv_rho), chi, kap, form=0), exp,
+                               atol=1e-5)
+
+
+def test_k0_field_is_derivative_of_grid_hamiltonian(orc):
+    g = np.random.default_rng(17)
+    n_cells = 50
+    counts = g.integers(1, 12, size=(2, n_cells)).astype(np.uint32)
+    inv_rho, chi, kappa, n_ref = 0.21, 17.0, 45.0, 32
+    om = orc.field_f64(counts, inv_rho, chi, kappa, form=0)
+    for t in range(2):
+        for c in g.choice(n_cells, 10, replace=False):
+            up = counts.copy(); up[t, c] += 1
+            dn = counts.copy(); dn[t, c] -= 1
+            d = (orc.h_nb(up, inv_rho, chi, kappa, n_ref, form=0)
+                 - orc.h_nb(dn, inv_rho, chi, kappa, n_ref, form=0)) / 2.0
+            assert n_ref * d == pytest.approx(om[t, c], rel=1e-9, abs=1e-9)
+    # the two forms differ by -chiN/4 (phi_A + phi_B)^2 per cell (a total-density term)
+    h1 = orc.h_nb(counts, inv_rho, chi, kappa, n_ref, form=1)
+    h0 = orc.h_nb(counts, inv_rho, chi, kappa, n_ref, form=0)
+    tot = (counts.sum(axis=0) * inv_rho) ** 2
+    assert h0 - h1 == pytest.approx(-chi / 4 * tot.sum() / (inv_rho * n_ref), rel=1e-9)
