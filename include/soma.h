@@ -190,6 +190,17 @@ int32_t soma_sync_fields(soma_system *sys, void *stream);
  * a batch that holds the system.  Asynchronous. */
 int32_t soma_set_grad_field(soma_system *sys, void *grad, uint64_t grad_bytes, void *stream);
 
+/* Interaction term of the grid Hamiltonian, Eq. (6) read over unordered pairs
+ * of types: form 1 (default) chiN phi_A phi_B, with the fields of Eq. (12)'s
+ * second form, omega_A = kappaN (phi_A + phi_B - 1) + chiN phi_B; form 0
+ * -chiN/4 (phi_A - phi_B)^2, with omega_A = kappaN (phi_A + phi_B - 1)
+ * - chiN/2 (phi_A - phi_B) and omega_B = ... + chiN/2 (phi_A - phi_B) (FP32:
+ * fma(-+chiN/2, phi_A - phi_B, kappaN s)).  H_nb follows.  The fields are
+ * recomputed from the current counts (asynchronous).  Set before creating a
+ * batch that holds the system; capture graphs again afterwards.
+ * SOMA_E_INVAL for another form. */
+int32_t soma_set_hamiltonian(soma_system *sys, uint32_t form, void *stream);
+
 /* External fields (Sec. 4).  ext (device, caller-owned, FP32 [2][n_cells], or
  * NULL): per type and cell an energy in the units of the fields, added to the
  * interaction field at every refresh (a bead of type t in cell c then carries

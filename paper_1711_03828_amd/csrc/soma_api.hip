@@ -65,6 +65,7 @@ struct Derived {
   uint64_t n_free = 0;
   // general architectures (soma_set_architecture): device tables per species, null: linear
   const soma::ArchDev *arch[SOMA_MAX_SPECIES] = {};
+  uint32_t form = 1;   // interaction term of the Hamiltonian (soma_set_hamiltonian)
   uint64_t ws_bytes = 0;
   uint32_t field_blocks = 1;  // blocks of the field update (and its FP64 partial sums)
 };
@@ -203,6 +204,7 @@ soma::FieldArgs field_args(const soma_config *c, const Derived &d, void *counts,
   a.halo_plane = (uint32_t)d.halo_plane;
   a.ext = d.ext;
   a.forbid = d.forbid;
+  a.form = d.form;
   return a;
 }
 
@@ -694,6 +696,14 @@ int32_t soma_set_grad_field(soma_system *sys, void *grad, uint64_t grad_bytes, v
   if (!aligned(grad, 16)) return fail(SOMA_E_INVAL, "gradient field must be 16-byte aligned");
   sys->grad = reinterpret_cast<float4 *>(grad);
   return launch_grad(sys, reinterpret_cast<hipStream_t>(stream));
+}
+
+int32_t soma_set_hamiltonian(soma_system *sys, uint32_t form, void *stream) {
+  if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
+  if (form > 1) return fail(SOMA_E_INVAL, "Hamiltonian form %u", form);
+  sys->d.form = form;
+  sys->graph.release();   // captured launches hold the old arguments
+  return refresh_fields(sys, reinterpret_cast<hipStream_t>(stream));
 }
 
 int32_t soma_set_external(soma_system *sys, const float *ext, uint64_t ext_bytes,

@@ -74,6 +74,9 @@ struct FieldArgs {
   // the field 0 and are left out of H_nb
   const float *ext;
   const uint32_t *forbid;
+  // interaction term of the grid Hamiltonian: 1 = chiN phi_A phi_B (default),
+  // 0 = -chiN/4 (phi_A - phi_B)^2
+  uint32_t form;
 };
 
 __device__ __forceinline__ bool cell_forbidden(const uint32_t *m, uint32_t c) {
@@ -114,15 +117,22 @@ __device__ __forceinline__ void field_cell(uint32_t na, uint32_t nb,
   const float phi_b = (float)nb * a.inv_rho;
   const float s = (phi_a + phi_b) - 1.0f;
   const float t = a.kappa_n * s;
-  oa = fmaf(a.chi_n, phi_b, t);
-  ob = fmaf(a.chi_n, phi_a, t);
+  if (a.form == 0) {   // Eq. (12), first form: t -+ chiN/2 (phi_A - phi_B)
+    const float d = phi_a - phi_b;
+    oa = fmaf(-0.5f * a.chi_n, d, t);
+    ob = fmaf(0.5f * a.chi_n, d, t);
+  } else {
+    oa = fmaf(a.chi_n, phi_b, t);
+    ob = fmaf(a.chi_n, phi_a, t);
+  }
 }
 
 __device__ __forceinline__ double hnb_cell(uint32_t na, uint32_t nb,
                                            const FieldArgs &a) {
   const double pa = (double)na * a.inv_rho_d, pb = (double)nb * a.inv_rho_d;
   const double dev = pa + pb - 1.0;
-  return 0.5 * a.kappa_n_d * dev * dev + a.chi_n_d * pa * pb;
+  const double inter = a.form == 0 ? -0.25 * a.chi_n_d * (pa - pb) * (pa - pb) : a.chi_n_d * pa * pb;
+  return 0.5 * a.kappa_n_d * dev * dev + inter;
 }
 
 template <bool COUNT64>

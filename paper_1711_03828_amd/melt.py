@@ -150,6 +150,10 @@ class Melt:
         32-bit format), or None for a linear chain."""
         C.soma_set_architecture(self.handle, species, words, _stream(stream))
 
+    def set_hamiltonian(self, form: int, stream=None):
+        """Interaction term: 1 = chiN phi_A phi_B (default), 0 = -chiN/4 (phi_A - phi_B)^2."""
+        C.soma_set_hamiltonian(self.handle, form, _stream(stream))
+
     def set_scheme(self, scheme: int):
         """Iteration order of local moves: C.SOMA_SCHEME_SET or C.SOMA_SCHEME_MOLECULE."""
         C.soma_set_scheme(self.handle, scheme)

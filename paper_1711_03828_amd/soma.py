@@ -109,6 +109,7 @@ _SIGS = {
     "soma_rebuild_histogram": ([_P, _P], _i32),
     "soma_set_sweep_blocks": ([_P, _u32], _i32),
     "soma_set_scheme": ([_P, _u32], _i32),
+    "soma_set_hamiltonian": ([_P, _u32, _P], _i32),
     "soma_set_architecture": ([_P, _u32, _P, _u32, _P], _i32),
     "soma_set_external": ([_P, _P, _u64, _P, _u64, _P], _i32),
     "soma_choose_scheme": ([_P, _u32, _P, ctypes.POINTER(_u32), ctypes.POINTER(ctypes.c_float)],
@@ -214,6 +215,10 @@ def soma_set_architecture(h, species: int, words, stream) -> None:
         return
     w = np.ascontiguousarray(words, dtype=np.uint32)
     _check(_lib.soma_set_architecture(h, species, w.ctypes.data, w.size, stream))
+
+
+def soma_set_hamiltonian(h, form: int, stream) -> None:
+    _check(_lib.soma_set_hamiltonian(h, form, stream))
 
 
 def soma_set_scheme(h, scheme: int) -> None:

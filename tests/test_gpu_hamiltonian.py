@@ -1,0 +1,69 @@
+"""GPU parity of the K^0 interaction term (Eq. (6), first form; fields of Eq.
+(12), first form) against the oracle: fields bit-exact in the FP32 order for
+both count widths and a ragged grid, H_nb within 1e-9 relative, and eight SCMF
+cycles of local moves chain-for-chain identical (a decision mismatch spreads
+through the fields; at most 8 chains may differ); switching back restores the
+K^1 fields."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import Species
+from tests.gpu_helpers import constants, device_config, flush, walks_for
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+@pytest.mark.parametrize("grid,width", [((24, 24, 24), 16), ((17, 23, 9), 32)])
+def test_k0_fields_and_h_nb(orc, grid, width):
+    from paper_1711_03828_amd.melt import Melt
+    w = synth.Workload("k0", grid, (synth.SpeciesSpec(900, 32, 16), synth.SpeciesSpec(41, 17, 5)),
+                       6.0, 32, 30.0, 50.0, width)
+    pos = walks_for(w, 91)
+    m = Melt(device_config(w), positions=torch.from_numpy(pos))
+    m.set_hamiltonian(0)
+    sp = [Species(s.n_chains, s.n, s.n_a) for s in w.species]
+    counts = orc.density_hist(pos, sp, w.grid)
+    inv_rho = constants(w)[3]
+    exp = orc.field_f32(counts, inv_rho, np.float32(w.chi_n), np.float32(w.kappa_n), form=0)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(m.omega.cpu().numpy(), exp)
+    obs = m.observables()
+    h = orc.h_nb(counts, w.n_cells / w.n_beads, w.chi_n, w.kappa_n, w.n_ref, form=0)
+    assert obs.h_nb == pytest.approx(h, rel=1e-9)
+    m.set_hamiltonian(1)
+    exp1 = orc.field_f32(counts, inv_rho, np.float32(w.chi_n), np.float32(w.kappa_n))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(m.omega.cpu().numpy(), exp1)
+    with pytest.raises(RuntimeError):
+        m.set_hamiltonian(2)
+    m.close()
+
+
+def test_k0_cycles_parity(orc):
+    from paper_1711_03828_amd.melt import Melt
+    w = synth.C1_SMALL
+    k0, a, A, inv_rho = constants(w)
+    pos = walks_for(w, 92)
+    m = Melt(device_config(w), positions=torch.from_numpy(pos))
+    m.set_hamiltonian(0)
+    sp = [Species(1024, 32, 16)]
+    ref = pos.copy()
+    omega = orc.field_f32(orc.density_hist(ref, sp, w.grid), inv_rho, np.float32(w.chi_n),
+                          np.float32(w.kappa_n), form=0)
+    for cyc in range(8):
+        m.cycle(1)
+        orc.mc_sweep(ref, sp[0], omega, w.grid, k0=k0, n_ref=w.n_ref, step=a, seed=w.seed,
+                     sweep=cyc, threads=8)
+        omega = orc.field_f32(orc.density_hist(ref, sp, w.grid), inv_rho, np.float32(w.chi_n),
+                              np.float32(w.kappa_n), form=0)
+    torch.cuda.synchronize()
+    got = m.pos.cpu().numpy().reshape(1024, -1)
+    bad = (got != ref.reshape(1024, -1)).any(axis=1)
+    flush("K0: chains differing after 8 cycles:", int(bad.sum()))
+    assert bad.sum() <= 8
+    if bad.sum() == 0:
+        np.testing.assert_array_equal(m.omega.cpu().numpy(), omega)
+    m.close()
