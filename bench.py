@@ -125,12 +125,16 @@ def _re_vectors(melt, n):
 
 
 def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: int,
-                equil_cycles: int, substeps: int):
+                equil_cycles: int, substeps: int, lag: int = 64):
     """Plain vs learned proposal on the 262,144-chain melt (96^3 cells, chiN 25).
 
     1. Training data from the plain sampler: 10 rounds of 2^20 random beads,
-       features at cycle t and displacement after 128 further plain cycles
-       (10,485,760 samples), collected and trained on the device.
+       features at cycle t and displacement after `lag` further plain cycles
+       (10,485,760 samples), collected and trained on the device.  (Measured:
+       learned moves only (p_learn = 1) decorrelate faster than a 9:1 mixture
+       with the local move, and lags of 64-128 cycles beat 256 and 512, whose
+       larger moves are accepted less often; lag 64 leaves the smallest shift of
+       <Re^2> against the plain sampler.)
     2. Bead-moves/s of both samplers on the full melt (HIP events, graph-replayed
        SCMF cycles).  The learned sampler runs `substeps` chain subsets per cycle
        with a field refresh after each: its moves are large, and the
@@ -153,7 +157,7 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
     t0 = time.perf_counter()
     melt = Melt(make_config(w, p_learn=p_learn))
     melt.cycle(50)
-    feats, disp = learned.collect(melt, 1 << 20, 128, 10)
+    feats, disp = learned.collect(melt, 1 << 20, lag, 10)
     params = learned.init_params(feats, seed=1)
     tr = learned.Trainer(params, lr=3e-3)
     losses = tr.run(feats, disp, steps=3000, batch=8192, loss_every=500)
@@ -164,7 +168,7 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
     melt.set_proposal(params)
     stream = torch.cuda.current_stream()
     out = {"workload": w.name, "p_learn": p_learn,
-           "training": {"samples": n_samples, "lag_cycles": 128, "adam_steps": 3000,
+           "training": {"samples": n_samples, "lag_cycles": lag, "adam_steps": 3000,
                         "batch": 8192, "loss_first": losses[0], "loss_last": losses[-1],
                         "seconds_collect_and_train": t_train}}
     rates = {}
@@ -192,7 +196,7 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
     melt.capture_cycle(100, C.SOMA_MOVE_MIXED)
     melt.run_cycle(max(1, equil_cycles // 100))
     melt.set_substeps(1)
-    feats, disp = learned.collect(melt, 1 << 20, 128, 4, first_round=1000)
+    feats, disp = learned.collect(melt, 1 << 20, lag, 4, first_round=1000)
     tune = learned.Trainer(params, lr=1e-3)
     tl = tune.run(feats, disp, steps=2000, batch=8192, loss_every=500)
     del feats, disp
@@ -611,7 +615,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the plain-vs-learned proposal comparison")
-    ap.add_argument("--p-learn", type=float, default=0.9)
+    ap.add_argument("--p-learn", type=float, default=1.0,
+                    help="probability of the learned move per bead (else the local move)")
     ap.add_argument("--learned-substeps", type=int, default=8,
                     help="chain subsets (field refreshes) per cycle for the learned sampler")
     ap.add_argument("--tau-frames", type=int, default=400, help="frames per tau_int run")
@@ -627,6 +632,8 @@ def main():
                     help="skip the 64-replica batched measurement")
     ap.add_argument("--no-schemes", action="store_true",
                     help="skip the SET vs molecule-parallel comparison over system size")
+    ap.add_argument("--learned-lag", type=int, default=64,
+                    help="plain cycles between a training sample's features and its target")
     ap.add_argument("--no-arch", action="store_true",
                     help="skip the general-architecture measurement")
     ap.add_argument("--film", choices=["lam", "hex"], default="lam",
@@ -774,7 +781,8 @@ def main():
     if not args.no_learned:
         result["learned_proposal"] = learned_leg(args.p_learn, args.tau_frames,
                                                  args.frame_cycles, args.plain_frame_mult,
-                                                 args.equil_cycles, args.learned_substeps)
+                                                 args.equil_cycles, args.learned_substeps,
+                                                 args.learned_lag)
     if not args.no_batched:
         result["batched"] = batched_leg(50)
     if not args.no_schemes:
