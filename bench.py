@@ -640,6 +640,8 @@ def main():
                     help="thin-film workload: lamella- or cylinder-forming diblocks")
     ap.add_argument("--film-lateral", type=float, default=200.0,
                     help="lateral film size in Re0 (the paper's films: 200)")
+    ap.add_argument("--no-second-film", action="store_true",
+                    help="skip the cylinder-forming film after the lamella-forming one")
     ap.add_argument("--film-cycles", type=int, default=2500,
                     help="SCMF cycles of the film run after the quench (0: skip the film)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -791,6 +793,8 @@ def main():
         result["architectures"] = arch_leg(200)
     if args.film_cycles > 0:
         result["film"] = film_leg(args.film, args.film_lateral, args.film_cycles)
+        if args.film == "lam" and not args.no_second_film:   # the paper's second film system
+            result["film_hex"] = film_leg("hex", args.film_lateral, args.film_cycles)
     if args.blend:
         result["blend"] = blend_leg(50, args.tau_frames // 2, args.frame_cycles,
                                     args.plain_frame_mult, args.equil_cycles // 2, 1.0 / 16,
