@@ -738,8 +738,19 @@ def main():
     melt.sweep(1, move)
     changed = int((cells() != before).any(dim=1).sum().item())
     del before
+    # against a from-scratch recount: one atomic per bead (before aggregation)
+    melt.rebuild_histogram()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(3):
+        melt.rebuild_histogram()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    recount_ms = e0.elapsed_time(e1) / 3
     result["atomics"] = {"per_sweep": 2 * changed, "per_s": 2 * changed / (sweep_ms * 1e-3),
-                         "beads_changing_cell": changed / w.n_beads}
+                         "beads_changing_cell": changed / w.n_beads,
+                         "recount_ms": recount_ms,
+                         "recount_atomics_per_s": w.n_beads / (recount_ms * 1e-3)}
     if args.move == "local":
         # the molecule-parallel order (Sec. 3.1.2, scheme 1) on the same melt
         melt.set_scheme(C.SOMA_SCHEME_MOLECULE)

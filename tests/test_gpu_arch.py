@@ -80,28 +80,41 @@ def _arch(kind):
     return n, bonds, synth.encode_architecture(n, types, bonds)
 
 
-@pytest.mark.parametrize("kind", ["star", "comb", "ring"])
+@pytest.mark.parametrize("kind", ["star", "comb", "ring", "star_walls"])
 def test_architecture_sweep_matches_oracle(C, orc, kind):
     from paper_1711_03828_amd.melt import Melt
+    walls = kind.endswith("_walls")
+    kind = kind.replace("_walls", "")
     n, bonds, words = _arch(kind)
     n_chains = 4000
     grid = (30, 30, 30)
     k0 = np.float32(2.0)
     pos = (synth.ring_walks(61, n_chains, n, grid, 1 / math.sqrt(float(k0))) if kind == "ring"
            else synth.tree_walks(61, n_chains, n, bonds, grid, 1 / math.sqrt(float(k0))))
+    mask = None
+    if walls:   # a wall plane at z = 0; start every monomer outside it
+        z = pos[:, 2].astype(np.float64)
+        pos[:, 2] = np.where(np.floor(z) % 30 == 0, z + 1.0, z).astype(np.float32)
+        mask = synth.pack_mask(synth.wall_cells(grid, [0]))
     m = Melt(_cfg(grid, [(n_chains, n, 0)], k0), positions=torch.from_numpy(pos))
+    if walls:
+        m.set_external(None, torch.from_numpy(mask.view(np.int32)).cuda())
     m.set_architecture(words)
     counts = orc.density_hist_arch(pos, n_chains, words, grid)
     np.testing.assert_array_equal(m.counts_planes(), counts)
-    inv_rho = np.float32(grid[0] * grid[1] * grid[2] / (n_chains * n))
-    omega = orc.field_f32(counts, inv_rho, np.float32(20.0), np.float32(40.0))
+    n_free = grid[0] * grid[1] * (grid[2] - 1) if walls else grid[0] * grid[1] * grid[2]
+    inv_rho = np.float32(n_free / (n_chains * n))
+    omega = orc.field_f32(counts, inv_rho, np.float32(20.0), np.float32(40.0), None, mask)
     np.testing.assert_array_equal(m.omega.cpu().numpy(), omega)
     m.sweep(1, C.SOMA_MOVE_LOCAL)
     torch.cuda.synchronize()
     got = m.pos.cpu().numpy()
     ref = pos.copy()
     acc, _ = orc.mc_sweep_arch(ref, n_chains, words, omega, grid, k0=k0, n_ref=32,
-                               step=np.float32(0.3), seed=123, sweep=0, threads=8)
+                               step=np.float32(0.3), seed=123, sweep=0, threads=8, forbid=mask)
+    if walls:
+        zc = np.floor(got[:, 2].astype(np.float64)).astype(np.int64) % 30
+        assert (zc != 0).all()
     bad = (got.reshape(n_chains, -1) != ref.reshape(n_chains, -1)).any(axis=1)
     allowed = math.ceil(1e-6 * n_chains * n)
     flush(kind, "mismatched molecules", int(bad.sum()), "allowed", allowed)
