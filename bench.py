@@ -223,7 +223,13 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
         tau = tau_frames * step
         re2 = float((re.double() ** 2).sum(-1).mean()) / w.re_cells ** 2
         k = 2 if kind == C.SOMA_MOVE_MIXED else 0
-        out[name].update({"tau_int_cycles": tau, "window_frames": window,
+        # statistical error of tau_int from the pooled series (Sokal: var(tau)/tau^2 =
+        # 2 (2M + 1) / n for one series of n frames and window M; m pooled, nearly
+        # independent series divide it by m); the window's truncation bias is not in it
+        m_series = series.shape[1]
+        tau_err = tau * math.sqrt(2.0 * (2 * window + 1) / (n_frames * m_series))
+        out[name].update({"tau_int_cycles": tau, "tau_int_err_cycles": tau_err,
+                          "window_frames": window,
                           "frames": n_frames, "cycles_per_frame": step,
                           "re2_over_re02": re2,
                           "acceptance_tau_run": (o1.accepted[k] - o0.accepted[k]) /
@@ -235,6 +241,9 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
     melt.close()
     out["gain_uncorrelated_samples_per_s"] = (out["learned"]["uncorrelated_samples_per_s"] /
                                               out["plain"]["uncorrelated_samples_per_s"])
+    rel = math.hypot(out["learned"]["tau_int_err_cycles"] / out["learned"]["tau_int_cycles"],
+                     out["plain"]["tau_int_err_cycles"] / out["plain"]["tau_int_cycles"])
+    out["gain_err"] = out["gain_uncorrelated_samples_per_s"] * rel
     return out
 
 
