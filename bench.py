@@ -626,7 +626,7 @@ def main():
                     help="skip the plain-vs-learned proposal comparison")
     ap.add_argument("--p-learn", type=float, default=1.0,
                     help="probability of the learned move per bead (else the local move)")
-    ap.add_argument("--learned-substeps", type=int, default=4,
+    ap.add_argument("--learned-substeps", type=int, default=2,
                     help="chain subsets (field refreshes) per cycle for the learned sampler")
     ap.add_argument("--tau-frames", type=int, default=400, help="frames per tau_int run")
     ap.add_argument("--frame-cycles", type=int, default=50,
