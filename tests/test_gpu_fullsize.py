@@ -112,3 +112,33 @@ def test_fullsize_learned_sweep_sampled(orc):
     torch.cuda.synchronize()
     assert torch.equal(recount, melt.counts)
     melt.close()
+
+
+def test_fullsize_batch_equals_single():
+    """The 64-replica ensemble at full size (1.9e8 beads), in the launch shape
+    the autotuner picks: two batched SCMF cycles give the bits of the same
+    cycles run melt by melt (whose parity with the oracle the other tests pin)."""
+    from paper_1711_03828_amd import soma as C
+    from paper_1711_03828_amd.melt import Batch, Melt, make_config
+    reps = synth.c3_replicas()
+    runs = []
+    for batched in (True, False):
+        melts = [Melt(make_config(w, replica=i)) for i, w in enumerate(reps)]
+        if batched:
+            b = Batch(melts)
+            tune = b.autotune(1, C.SOMA_MOVE_LOCAL)
+            flush("tuned", tune.mode, tune.grid_blocks)
+            # the tuning ran cycles: bring the unbatched run to the same sweep index
+            b.cycle(2, C.SOMA_MOVE_LOCAL)
+            b.close()
+            n_tuned = tune.cycles_run
+        else:
+            for m in melts:
+                m.cycle(n_tuned + 2)
+        torch.cuda.synchronize()
+        runs.append([(m.pos.cpu().numpy(), m.omega.cpu().numpy()) for m in melts])
+        for m in melts:
+            m.close()
+    for (p0, o0), (p1, o1) in zip(runs[0], runs[1]):
+        np.testing.assert_array_equal(p0, p1)
+        np.testing.assert_array_equal(o0, o1)
