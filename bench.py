@@ -461,7 +461,8 @@ def film_leg(kind: str, lateral_re: float, cycles: int):
 
 
 def blend_leg(rate_cycles: int, tau_frames: int, frame_cycles: int, plain_mult: int,
-              equil_cycles: int, tau_scale: float, substeps: int):
+              equil_cycles: int, tau_scale: float, substeps: int, p_learn: float = 1.0,
+              lag: int = 64):
     """Ternary blend replicas (32 melts of A16B16 diblocks with A16 and B16
     homopolymers, chiN 15..35): one network per species trained on the blend's
     own plain trajectories, used inside graph-captured batched cycles.
@@ -478,7 +479,7 @@ def blend_leg(rate_cycles: int, tau_frames: int, frame_cycles: int, plain_mult: 
     from paper_1711_03828_amd.melt import Batch, Melt, make_config
 
     def build(reps):
-        melts = [Melt(make_config(w, replica=i, p_learn=0.9)) for i, w in enumerate(reps)]
+        melts = [Melt(make_config(w, replica=i, p_learn=p_learn)) for i, w in enumerate(reps)]
         return melts, Batch(melts)
 
     out = {}
@@ -486,7 +487,7 @@ def blend_leg(rate_cycles: int, tau_frames: int, frame_cycles: int, plain_mult: 
     reps = synth.c5_replicas()
     melts, batch = build(reps)
     batch.cycle(20)
-    n_round, rounds, lag = 1 << 15, 4, 128
+    n_round, rounds = 1 << 15, 4
     data = {sp: (torch.empty((len(melts) * rounds * n_round, 60), device="cuda"),
                  torch.empty((len(melts) * rounds * n_round, 3), device="cuda")) for sp in range(3)}
     r0 = torch.empty((len(melts), 3, n_round, 3), device="cuda")
@@ -818,7 +819,7 @@ def main():
     if args.blend:
         result["blend"] = blend_leg(50, args.tau_frames // 2, args.frame_cycles,
                                     args.plain_frame_mult, args.equil_cycles // 2, 1.0 / 16,
-                                    args.learned_substeps)
+                                    args.learned_substeps, args.p_learn, args.learned_lag)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(result), flush=True)
