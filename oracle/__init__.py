@@ -76,7 +76,11 @@ def lib() -> ctypes.CDLL:
         L.orc_mc_sweep_arch.restype = u64
         L.orc_arch_sets.argtypes = [P, u32, P]
         L.orc_arch_sets.restype = ctypes.c_int
-        L.orc_density_hist_arch.argtypes = [P, u32, P, u32, u32, u32, u32, P]
+        L.orc_density_hist_arch.argtypes = [P, u32, P, u32, u32, u32, u32, u32, P]
+        L.orc_field_multi_f64.argtypes = [P, u64, u32, f64, P, f64, u32, P]
+        L.orc_field_multi_f32.argtypes = [P, u64, u32, f32, P, f32, u32, P]
+        L.orc_h_nb_multi.argtypes = [P, u64, u32, f64, P, f64, u32, u32]
+        L.orc_h_nb_multi.restype = f64
         L.orc_density_hist_arch.restype = ctypes.c_int
         L.orc_pick_bead.argtypes = [u32, u32]
         L.orc_pick_bead.restype = u32
@@ -176,6 +180,42 @@ def h_nb(counts, inv_rho, chi_n, kappa_n, n_ref, forbid=None, form=1) -> float:
                           _ptr(forbid) if forbid is not None else None)
 
 
+def _chi_matrix(chi, n_t, dtype):
+    chi = np.ascontiguousarray(np.asarray(chi, dtype=dtype).reshape(n_t, n_t))
+    if not np.array_equal(chi, chi.T):
+        raise ValueError("chi matrix must be symmetric")
+    return chi
+
+
+def field_multi_f64(counts, inv_rho, chi, kappa_n, form=1) -> np.ndarray:
+    """Fields of n_t types (counts [n_t, n_cells], chi [n_t, n_t] of chi_ij N)."""
+    counts = _c(counts, np.uint32)
+    n_t, n_cells = counts.shape
+    chi = _chi_matrix(chi, n_t, np.float64)
+    om = np.empty((n_t, n_cells), np.float64)
+    lib().orc_field_multi_f64(_ptr(counts), n_cells, n_t, inv_rho, _ptr(chi), kappa_n, form,
+                              _ptr(om))
+    return om
+
+
+def field_multi_f32(counts, inv_rho, chi, kappa_n, form=1) -> np.ndarray:
+    counts = _c(counts, np.uint32)
+    n_t, n_cells = counts.shape
+    chi = _chi_matrix(chi, n_t, np.float32)
+    om = np.empty((n_t, n_cells), np.float32)
+    lib().orc_field_multi_f32(_ptr(counts), n_cells, n_t, float(np.float32(inv_rho)), _ptr(chi),
+                              float(np.float32(kappa_n)), form, _ptr(om))
+    return om
+
+
+def h_nb_multi(counts, inv_rho, chi, kappa_n, n_ref, form=1) -> float:
+    counts = _c(counts, np.uint32)
+    n_t, n_cells = counts.shape
+    chi = _chi_matrix(chi, n_t, np.float64)
+    return lib().orc_h_nb_multi(_ptr(counts), n_cells, n_t, inv_rho, _ptr(chi), kappa_n, n_ref,
+                                form)
+
+
 class _walls:
     """Sets the oracle's impenetrable-cell mask for the duration of one sweep."""
 
@@ -252,7 +292,10 @@ def mc_sweep_arch(pos: np.ndarray, n_chains: int, words: np.ndarray, omega: np.n
     assert pos.dtype == np.float32 and pos.flags.c_contiguous and pos.size == n_chains * n * 3
     nx, ny, nz = grid
     omega = _c(omega, np.float32)
-    assert omega.size == 2 * nx * ny * nz
+    n_cells = nx * ny * nz
+    types = words[1:1 + n] >> 24
+    assert omega.size % n_cells == 0 and omega.size // n_cells > int(types.max()), \
+        "omega needs a plane for every type of the architecture"
     flags = np.zeros(n_chains * n, np.uint8) if want_flags else None
     with _walls(forbid):
         acc = lib().orc_mc_sweep_arch(_ptr(pos), n_chains, _ptr(words), words.size,
@@ -265,13 +308,15 @@ def mc_sweep_arch(pos: np.ndarray, n_chains: int, words: np.ndarray, omega: np.n
     return acc, flags
 
 
-def density_hist_arch(pos: np.ndarray, n_chains: int, words: np.ndarray, grid) -> np.ndarray:
+def density_hist_arch(pos: np.ndarray, n_chains: int, words: np.ndarray, grid,
+                      n_types: int = 2) -> np.ndarray:
+    """Counts [n_types, n_cells] of chains of one architecture."""
     words = _c(words, np.uint32)
     pos = _c(pos, np.float32)
     nx, ny, nz = grid
-    out = np.empty((2, nx * ny * nz), np.uint32)
+    out = np.empty((n_types, nx * ny * nz), np.uint32)
     if lib().orc_density_hist_arch(_ptr(pos), n_chains, _ptr(words), words.size, nx, ny, nz,
-                                   _ptr(out)):
+                                   n_types, _ptr(out)):
         raise ValueError("malformed architecture")
     return out
 

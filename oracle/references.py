@@ -73,14 +73,17 @@ def _bond_cell_kernel(k0: float, L: int, npts: int = 64, images: int = 3):
 
 
 def three_bead_cell_distribution(omega_a: np.ndarray, omega_b: np.ndarray, k0: float,
-                                 L: int, n_ref: int = 1, types=(0, 0, 1)):
+                                 L: int, n_ref: int = 1, types=(0, 0, 1), omega_c=None):
     """Exact P(c1, c2, c3) for a 3-bead linear chain in an L^3 periodic box with a
     frozen field, as an array [L^3, L^3, L^3] over linear cell indices
-    (z*L + y)*L + x.  omega_* are per-chain fields (bead energy omega/n_ref)."""
+    (z*L + y)*L + x.  omega_* are the fields of types 0, 1 (and 2) (bead energy
+    omega/n_ref)."""
     I = _bond_cell_kernel(k0, L)
     idx = np.arange(L ** 3)
     cx, cy, cz = idx % L, (idx // L) % L, idx // (L * L)
     om = [np.asarray(omega_a, float), np.asarray(omega_b, float)]
+    if omega_c is not None:
+        om.append(np.asarray(omega_c, float))
     # positional weight, separable over x, y, z
     wpos = (I[cx[:, None, None], cx[None, :, None], cx[None, None, :]]
             * I[cy[:, None, None], cy[None, :, None], cy[None, None, :]]

@@ -170,6 +170,7 @@ void orc_density_hist(const float *pos, uint32_t n_species,
  * bit is set in forbid (may be NULL) is impenetrable and gets the field 0
  * (no bead enters it).  With forbidden cells the reference density counts
  * the free cells only (inv_rho = n_free / n_beads, chosen by the caller). */
+#define ORC_MAX_TYPES 8
 static int orc_bit(const uint32_t *mask, uint64_t c) {
   return mask && ((mask[c >> 5] >> (c & 31u)) & 1u);
 }
@@ -249,6 +250,85 @@ double orc_h_nb(const uint32_t *counts, uint64_t n_cells, double inv_rho,
     double inter = form == 0 ? -0.25 * chi_n * (phi_a - phi_b) * (phi_a - phi_b)
                              : chi_n * phi_a * phi_b;
     sum += 0.5 * kappa_n * dev * dev + inter;
+  }
+  return sum / (inv_rho * (double)n_ref);
+}
+
+/* ------------------------------------------------------------------------- */
+/* n_t bead types (Sec. 2.1).  counts: n_t planes of n_cells (type i in plane  */
+/* i); chi: the symmetric n_t x n_t matrix of chi_ij N (diagonal unused).      */
+/* Fields, Eq. (12):                                                           */
+/*   K^1: omega_i = kappaN (sum_k phi_k - 1) + sum_{k != i} chi_ik N phi_k      */
+/*   K^0: omega_i = kappaN (sum_k phi_k - 1)                                   */
+/*                  - sum_{k != i} (chi_ik N / 2) (phi_i - phi_k)               */
+/* For n_t = 2 these are the two-type fields above.                            */
+/* ------------------------------------------------------------------------- */
+void orc_field_multi_f64(const uint32_t *counts, uint64_t n_cells, uint32_t n_t,
+                         double inv_rho, const double *chi, double kappa_n, uint32_t form,
+                         double *omega) {
+  for (uint64_t c = 0; c < n_cells; ++c) {
+    double phi[ORC_MAX_TYPES], total = 0.0;
+    for (uint32_t i = 0; i < n_t; ++i) {
+      phi[i] = counts[(uint64_t)i * n_cells + c] * inv_rho;
+      total += phi[i];
+    }
+    for (uint32_t i = 0; i < n_t; ++i) {
+      double w = kappa_n * (total - 1.0);
+      for (uint32_t k = 0; k < n_t; ++k) {
+        if (k == i) continue;
+        if (form == 0) w -= 0.5 * chi[i * n_t + k] * (phi[i] - phi[k]);
+        else w += chi[i * n_t + k] * phi[k];
+      }
+      omega[(uint64_t)i * n_cells + c] = w;
+    }
+  }
+}
+
+/* The same in FP32, operation by operation:
+ *   s = (((phi_0 + phi_1) + phi_2) + ...) - 1,  t = kappaN * s,
+ *   then for k = 0, 1, ... (k != i): t = fma(chi_ik, phi_k, t) (K^1) or
+ *   t = fma(-chi_ik / 2, phi_i - phi_k, t) (K^0); omega_i = t.
+ * With two types this is the two-type FP32 order above. */
+void orc_field_multi_f32(const uint32_t *counts, uint64_t n_cells, uint32_t n_t,
+                         float inv_rho, const float *chi, float kappa_n, uint32_t form,
+                         float *omega) {
+  for (uint64_t c = 0; c < n_cells; ++c) {
+    float phi[ORC_MAX_TYPES];
+    for (uint32_t i = 0; i < n_t; ++i) phi[i] = (float)counts[(uint64_t)i * n_cells + c] * inv_rho;
+    float s = phi[0];
+    for (uint32_t i = 1; i < n_t; ++i) s = s + phi[i];
+    s = s - 1.0f;
+    for (uint32_t i = 0; i < n_t; ++i) {
+      float t = kappa_n * s;
+      for (uint32_t k = 0; k < n_t; ++k) {
+        if (k == i) continue;
+        if (form == 0) t = fmaf(-0.5f * chi[i * n_t + k], phi[i] - phi[k], t);
+        else t = fmaf(chi[i * n_t + k], phi[k], t);
+      }
+      omega[(uint64_t)i * n_cells + c] = t;
+    }
+  }
+}
+
+/* H_nb / kT for n_t types, Eqs. (5), (6), (8), the i != j sums over
+ * unordered pairs i < j:
+ *   (rho0 dL^3 / N) sum_c [ kappaN/2 (sum phi - 1)^2 + sum_{i<j} K_ij ],
+ *   K_ij = chi_ij N phi_i phi_j (K^1) or -(chi_ij N / 4)(phi_i - phi_j)^2 (K^0). */
+double orc_h_nb_multi(const uint32_t *counts, uint64_t n_cells, uint32_t n_t, double inv_rho,
+                      const double *chi, double kappa_n, uint32_t n_ref, uint32_t form) {
+  double sum = 0.0;
+  for (uint64_t c = 0; c < n_cells; ++c) {
+    double phi[ORC_MAX_TYPES], total = 0.0, inter = 0.0;
+    for (uint32_t i = 0; i < n_t; ++i) {
+      phi[i] = counts[(uint64_t)i * n_cells + c] * inv_rho;
+      total += phi[i];
+    }
+    for (uint32_t i = 0; i < n_t; ++i)
+      for (uint32_t j = i + 1; j < n_t; ++j) {
+        double x = chi[i * n_t + j];
+        inter += form == 0 ? -0.25 * x * (phi[i] - phi[j]) * (phi[i] - phi[j]) : x * phi[i] * phi[j];
+      }
+    sum += 0.5 * kappa_n * (total - 1.0) * (total - 1.0) + inter;
   }
   return sum / (inv_rho * (double)n_ref);
 }
@@ -988,7 +1068,8 @@ typedef struct {
 
 /* Decodes and checks an architecture; returns 0, or -1 if it is malformed
  * (a partner out of range or equal to the monomer, a non-harmonic bond, a
- * bond listed on one side only, a list running off the array, a type > 1). */
+ * bond listed on one side only, a list running off the array, a type code of
+ * ORC_MAX_TYPES or more). */
 static int orc_arch_decode(const uint32_t *w, uint32_t n_words, orc_arch *a) {
   if (n_words < 1) return -1;
   uint32_t n = w[0];
@@ -998,7 +1079,7 @@ static int orc_arch_decode(const uint32_t *w, uint32_t n_words, orc_arch *a) {
   for (uint32_t i = 0; i < n; ++i) {
     uint32_t m = w[1 + i];
     a->type[i] = (uint8_t)(m >> 24);
-    if (a->type[i] > 1) return -1;
+    if ((m >> 24) >= ORC_MAX_TYPES) return -1;
     a->nb_start[i] = nb;
     uint32_t k = m & 0xFFFFFFu;
     if (k == 0) continue;
@@ -1113,14 +1194,17 @@ uint64_t orc_mc_sweep_arch(float *pos, uint32_t n_chains, const uint32_t *w,
   return accepted;
 }
 
-/* Histogram of chains of one architecture (types from the architecture). */
+/* Histogram of chains of one architecture (types from the architecture) into
+ * n_t planes; -1 if the architecture is malformed or uses a type >= n_t. */
 int orc_density_hist_arch(const float *pos, uint32_t n_chains, const uint32_t *w,
                           uint32_t n_words, uint32_t nx, uint32_t ny, uint32_t nz,
-                          uint32_t *counts) {
+                          uint32_t n_t, uint32_t *counts) {
   static orc_arch a;
   if (orc_arch_decode(w, n_words, &a)) return -1;
+  for (uint32_t i = 0; i < a.n; ++i)
+    if (a.type[i] >= n_t) return -1;
   uint64_t n_cells = (uint64_t)nx * ny * nz;
-  memset(counts, 0, 2 * n_cells * sizeof(uint32_t));
+  memset(counts, 0, (uint64_t)n_t * n_cells * sizeof(uint32_t));
   for (uint64_t c = 0; c < n_chains; ++c)
     for (uint32_t i = 0; i < a.n; ++i) {
       uint64_t cell = orc_cell(pos + 3 * (c * a.n + i), nx, ny, nz);

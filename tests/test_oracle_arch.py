@@ -37,9 +37,9 @@ def test_malformed_architectures_rejected(orc):
     w = good.copy()
     w[int(w[1] & 0xFFFFFF)] |= 1 << 27
     assert orc.arch_sets(w)[0] == -1
-    # type 2
+    # type code 8 (at most 8 types)
     w = good.copy()
-    w[2] = (2 << 24) | (w[2] & 0xFFFFFF)
+    w[2] = (8 << 24) | (w[2] & 0xFFFFFF)
     assert orc.arch_sets(w)[0] == -1
     # list running off the array
     assert orc.arch_sets(good[:-1])[0] == -1
