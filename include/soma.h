@@ -222,7 +222,8 @@ int32_t soma_set_external(soma_system *sys, const float *ext, uint64_t ext_bytes
 /* General molecular architecture of one species (Sec. 3.2.1), in place of the
  * linear chain A_{n_a} B_{N - n_a}.  words (host memory, n_words entries):
  * word 0 = N (must equal the species' n); word 1 + i = monomer i's type
- * (0 = A, 1 = B) in the top byte and, in the low 24 bits, the index in the
+ * code (0 = A, 1 = B; up to n_types - 1 after soma_set_types) in the top
+ * byte and, in the low 24 bits, the index in the
  * array of its bond list (0: no bonds); a bond word holds partner - i as a
  * signed 27-bit integer in its low bits, the bond type in bits 27-30 (0,
  * harmonic with the species' k0, is the only kind) and, in bit 31, the flag
@@ -245,6 +246,39 @@ int32_t soma_set_external(soma_system *sys, const float *ext, uint64_t ext_bytes
  * SOMA_E_INVAL for a malformed array. */
 int32_t soma_set_architecture(soma_system *sys, uint32_t species, const uint32_t *words,
                               uint32_t n_words, void *stream);
+
+/* n_t bead types (Sec. 2.1) with a symmetric matrix chi_ij N, the fields of
+ * Eq. (12) in the form chosen by soma_set_hamiltonian:
+ *   K^1: omega_i = kappaN (sum_k phi_k - 1) + sum_{k != i} chi_ik N phi_k,
+ *   K^0: omega_i = kappaN (sum_k phi_k - 1) - sum_{k != i} chi_ik N/2 (phi_i - phi_k),
+ * in FP32 as s = (((phi_0 + phi_1) + phi_2) + ...) - 1, t = kappaN s, then
+ * t = fma(chi_ik, phi_k, t) or fma(-chi_ik/2, phi_i - phi_k, t) for k = 0, 1,
+ * ... (k != i); H_nb sums chi_ij N phi_i phi_j (or -chi_ij N/4 (phi_i -
+ * phi_j)^2) over pairs i < j.  n_types in 2..8; chi_n (host) holds
+ * n_types x n_types floats, row-major, symmetric (the diagonal is ignored);
+ * with n_types = 2 it replaces the config's chi_n.  counts and omega (device,
+ * caller-owned, 16-byte aligned) replace the buffers given at init: counts
+ * holds ceil(n_types/2) planes of n_cells packed words of the config's count
+ * width, plane p carrying types 2p (low half) and 2p + 1 (high half); omega
+ * holds n_types planes of n_cells floats, plane t the field of type t.  Types
+ * come from architectures (soma_set_architecture; call this first for codes
+ * above 1); linear species keep types 0 and 1.  With more than two types:
+ * SOMA_MOVE_LOCAL only, no external fields or walls, no gradient field, no
+ * training data, no batching (SOMA_E_UNSUPPORTED); soma_obs's count_a is the
+ * type-0 total and count_b that of all other types; the structure factor is
+ * that of phi_0 - phi_1.  The histogram is rebuilt from the positions and the
+ * fields recomputed; capture graphs again afterwards, and call before
+ * creating a batch that holds the system.  BLOCKING.  SOMA_E_INVAL for a
+ * non-symmetric or non-finite matrix or an architecture with a type code
+ * >= n_types, SOMA_E_SIZE for short buffers, SOMA_E_UNSUPPORTED if the planes
+ * exceed 32-bit byte offsets. */
+int32_t soma_set_types(soma_system *sys, uint32_t n_types, const float *chi_n, void *counts,
+                       uint64_t counts_bytes, float *omega, uint64_t omega_bytes, void *stream);
+
+/* Total count of each bead type in the kept histogram (out[0 .. n_types-1],
+ * host; n_out >= the number of types).  BLOCKING.  SOMA_E_SIZE if n_out is
+ * too small. */
+int32_t soma_type_counts(soma_system *sys, uint64_t *out, uint32_t n_out, void *stream);
 
 /* Launch shape of the local-move sweep: 0 (default) runs one wave per tile
  * of chains; blocks > 0 runs that many persistent 256-thread blocks, each wave

@@ -56,7 +56,7 @@ struct Derived {
   uint64_t pos_bytes = 0, counts_bytes = 0, omega_bytes = 0;
   // workspace layout
   uint64_t off_err = 0, off_acc = 0, off_att = 0, off_net = 0, off_fpart = 0, off_totals = 0,
-           off_opart = 0, off_halo = 0, off_arch = 0;
+           off_opart = 0, off_halo = 0, off_arch = 0, off_tcount = 0;
   uint64_t halo_plane = 0;    // floats per plane of the halo copy (0: not kept)
   // external fields (soma_set_external): caller-owned device buffers, null if none;
   // n_free = cells not impenetrable (the reference density counts these)
@@ -66,6 +66,10 @@ struct Derived {
   // general architectures (soma_set_architecture): device tables per species, null: linear
   const soma::ArchDev *arch[SOMA_MAX_SPECIES] = {};
   uint32_t form = 1;   // interaction term of the Hamiltonian (soma_set_hamiltonian)
+  // bead types (soma_set_types): 2 uses chi_n of the config; more use chi_m,
+  // chi_ij N at [i * kMaxTypes + j]
+  uint32_t n_types = 2;
+  float chi_m[soma::kMaxTypes * soma::kMaxTypes] = {};
   uint64_t ws_bytes = 0;
   uint32_t field_blocks = 1;  // blocks of the field update (and its FP64 partial sums)
 };
@@ -128,7 +132,8 @@ int32_t derive(const soma_config *c, Derived *d) {
   d->off_totals = align_up(d->off_fpart + soma::kFieldBlocks * sizeof(soma::FieldPartial));
   d->off_opart = align_up(d->off_totals + sizeof(soma::Totals));
   d->off_arch = align_up(d->off_opart + (d->obs_blocks ? d->obs_blocks : 1) * sizeof(soma::ObsPartial));
-  d->off_halo = align_up(d->off_arch + SOMA_MAX_SPECIES * align_up(sizeof(soma::ArchDev)));
+  d->off_tcount = align_up(d->off_arch + SOMA_MAX_SPECIES * align_up(sizeof(soma::ArchDev)));
+  d->off_halo = align_up(d->off_tcount + 8ull * soma::kFieldBlocks * soma::kMaxTypes);
   // the learned proposal reads its 27-cell neighbourhoods from a copy of the
   // fields with one periodic halo cell at both ends of each x row
   d->halo_plane = c->p_learn > 0.f ? (uint64_t)c->nz * c->ny * (c->nx + 2u) : 0u;
@@ -210,8 +215,29 @@ soma::FieldArgs field_args(const soma_config *c, const Derived &d, void *counts,
 
 int32_t launch_field(const soma_config *c, const Derived &d, void *counts, float *omega,
                      soma::FieldPartial *partials, hipStream_t s, float *halo = nullptr) {
-  const soma::FieldArgs a = field_args(c, d, counts, omega, partials, halo);
   const uint32_t blocks = d.field_blocks;
+  if (d.n_types > 2) {   // no halo copy, external fields or walls with more than two types
+    soma::MultiFieldArgs m;
+    m.counts = counts;
+    m.omega = omega;
+    m.n_cells = (uint32_t)d.n_cells;
+    m.n_t = d.n_types;
+    m.form = d.form;
+    m.clear = 0;
+    m.inv_rho = inv_rho_f(d);
+    m.kappa_n = c->kappa_n;
+    m.inv_rho_d = inv_rho_d(d);
+    m.kappa_n_d = (double)c->kappa_n;
+    std::memcpy(m.chi, d.chi_m, sizeof m.chi);
+    m.partials = partials;
+    if (c->count_width == 32)
+      hipLaunchKernelGGL(soma::field_multi_kernel<true>, dim3(blocks), dim3(256), 0, s, m);
+    else
+      hipLaunchKernelGGL(soma::field_multi_kernel<false>, dim3(blocks), dim3(256), 0, s, m);
+    LAUNCH_TRY();
+    return SOMA_OK;
+  }
+  const soma::FieldArgs a = field_args(c, d, counts, omega, partials, halo);
   if (c->count_width == 32)
     hipLaunchKernelGGL(soma::field_update_kernel<true>, dim3(blocks), dim3(256), 0, s, a);
   else
@@ -276,6 +302,7 @@ struct soma_system {
   uint32_t arch_mask = 0;     // species with a general architecture (bit per species)
   uint32_t arch_type0[SOMA_MAX_SPECIES] = {};  // A monomers per molecule of those species
   uint32_t arch_per_wave[SOMA_MAX_SPECIES] = {};  // molecules per wave of their sweep
+  uint32_t arch_max_type[SOMA_MAX_SPECIES] = {};  // largest type code of their monomers
   uint32_t substeps = 1;      // field refreshes per SCMF cycle (chain subsets)
   uint32_t scheme = SOMA_SCHEME_SET;  // iteration order of local moves
   float4 *grad = nullptr;     // optional gradient field (caller-owned), see soma_set_grad_field
@@ -446,6 +473,8 @@ int32_t check_kind(soma_system *sys, uint32_t move_kind) {
     return fail(SOMA_E_UNSUPPORTED, "the molecule-parallel order has local moves only");
   if (sys->arch_mask && (move_kind != SOMA_MOVE_LOCAL || sys->scheme != SOMA_SCHEME_SET))
     return fail(SOMA_E_UNSUPPORTED, "general architectures have local moves in the SET order only");
+  if (sys->d.n_types > 2 && move_kind != SOMA_MOVE_LOCAL)
+    return fail(SOMA_E_UNSUPPORTED, "more than two bead types: local moves only");
   return SOMA_OK;
 }
 
@@ -685,6 +714,8 @@ int32_t soma_sync_fields(soma_system *sys, void *stream) {
 
 int32_t soma_set_grad_field(soma_system *sys, void *grad, uint64_t grad_bytes, void *stream) {
   if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
+  if (grad && sys->d.n_types > 2)
+    return fail(SOMA_E_UNSUPPORTED, "gradient field with two bead types only");
   if (!grad) {
     sys->grad = nullptr;
     return SOMA_OK;
@@ -709,6 +740,8 @@ int32_t soma_set_hamiltonian(soma_system *sys, uint32_t form, void *stream) {
 int32_t soma_set_external(soma_system *sys, const float *ext, uint64_t ext_bytes,
                           const uint32_t *forbid, uint64_t forbid_bytes, void *stream) {
   if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
+  if (sys->d.n_types > 2 && (ext || forbid))
+    return fail(SOMA_E_UNSUPPORTED, "external fields with two bead types only");
   const uint64_t n_cells = sys->d.n_cells;
   if (ext && ext_bytes < 8ull * n_cells)
     return fail(SOMA_E_SIZE, "external field: %llu < %llu bytes", (unsigned long long)ext_bytes,
@@ -753,7 +786,7 @@ namespace {
 // lowest set not holding a bonded monomer of lower index).  Returns 0 or a
 // message naming the first defect.
 const char *decode_architecture(const uint32_t *w, uint32_t n_words, uint32_t n_expected,
-                                soma::ArchDev &t) {
+                                uint32_t n_types, soma::ArchDev &t) {
   std::memset(&t, 0, sizeof t);
   if (n_words < 1) return "empty array";
   const uint32_t n = w[0];
@@ -764,7 +797,7 @@ const char *decode_architecture(const uint32_t *w, uint32_t n_words, uint32_t n_
   for (uint32_t i = 0; i < n; ++i) {
     const uint32_t m = w[1 + i];
     const uint32_t type = m >> 24;
-    if (type > 1) return "monomer type above 1";
+    if (type >= n_types) return "monomer type code not below the number of types";
     t.type[i] = (uint8_t)type;
     if (type == 0) ++t.n_type0;
     uint32_t k = m & 0xFFFFFFu;
@@ -830,13 +863,14 @@ int32_t soma_set_architecture(soma_system *sys, uint32_t species, const uint32_t
   const soma_species &S = sys->cfg.species[species];
   if (words) {
     soma::ArchDev t;
-    const char *err = decode_architecture(words, n_words, S.n, t);
+    const char *err = decode_architecture(words, n_words, S.n, sys->d.n_types, t);
     if (err) return fail(SOMA_E_INVAL, "architecture of species %u: %s", species, err);
     HIP_TRY(hipMemcpyAsync(sys->arch(species), &t, sizeof t, hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
     sys->arch_mask |= 1u << species;
     sys->arch_type0[species] = t.n_type0;
     sys->arch_per_wave[species] = t.per_wave;
+    sys->arch_max_type[species] = *std::max_element(t.type, t.type + t.n);
     sys->d.arch[species] = sys->arch(species);
   } else {
     sys->arch_mask &= ~(1u << species);
@@ -854,6 +888,82 @@ int32_t soma_set_architecture(soma_system *sys, uint32_t species, const uint32_t
   if (!rc) rc = refresh_fields(sys, s);
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(s));
+  return SOMA_OK;
+}
+
+int32_t soma_set_types(soma_system *sys, uint32_t n_types, const float *chi_n, void *counts,
+                       uint64_t counts_bytes, float *omega, uint64_t omega_bytes, void *stream) {
+  if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
+  if (n_types < 2 || n_types > soma::kMaxTypes)
+    return fail(SOMA_E_INVAL, "n_types must be in 2..%u", soma::kMaxTypes);
+  if (!chi_n || !counts || !omega) return fail(SOMA_E_INVAL, "chi_n, counts and omega are required");
+  for (uint32_t i = 0; i < n_types; ++i)
+    for (uint32_t j = 0; j < n_types; ++j) {
+      const float x = chi_n[i * n_types + j], y = chi_n[j * n_types + i];
+      if (!std::isfinite(x)) return fail(SOMA_E_INVAL, "chi_n[%u][%u] is not finite", i, j);
+      if (x != y) return fail(SOMA_E_INVAL, "chi_n is not symmetric at (%u, %u)", i, j);
+    }
+  const uint64_t n_cells = sys->d.n_cells, word = sys->cfg.count_width == 32 ? 8u : 4u;
+  const uint64_t planes = (n_types + 1) / 2;
+  // count and field planes are addressed with 32-bit byte offsets
+  if (planes * n_cells * word >= (1ull << 32) || 4ull * n_types * n_cells >= (1ull << 32))
+    return fail(SOMA_E_UNSUPPORTED, "%u types on %llu cells exceed 32-bit plane offsets", n_types,
+                (unsigned long long)n_cells);
+  if (counts_bytes < planes * n_cells * word)
+    return fail(SOMA_E_SIZE, "counts: %llu < %llu bytes", (unsigned long long)counts_bytes,
+                (unsigned long long)(planes * n_cells * word));
+  if (omega_bytes < 4ull * n_types * n_cells)
+    return fail(SOMA_E_SIZE, "omega: %llu < %llu bytes", (unsigned long long)omega_bytes,
+                (unsigned long long)(4ull * n_types * n_cells));
+  if (!aligned(counts, 16) || !aligned(omega, 16))
+    return fail(SOMA_E_INVAL, "counts and omega must be 16-byte aligned");
+  if (n_types > 2 && (sys->d.ext || sys->d.forbid))
+    return fail(SOMA_E_UNSUPPORTED, "external fields with two bead types only");
+  if (n_types > 2 && sys->grad)
+    return fail(SOMA_E_UNSUPPORTED, "gradient field with two bead types only");
+  for (uint32_t sp = 0; sp < sys->cfg.n_species; ++sp)
+    if ((sys->arch_mask >> sp & 1u) && sys->arch_max_type[sp] >= n_types)
+      return fail(SOMA_E_INVAL, "species %u has monomers of type %u", sp, sys->arch_max_type[sp]);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  sys->d.n_types = n_types;
+  std::memset(sys->d.chi_m, 0, sizeof sys->d.chi_m);
+  for (uint32_t i = 0; i < n_types; ++i)
+    for (uint32_t j = 0; j < n_types; ++j)
+      sys->d.chi_m[i * soma::kMaxTypes + j] = i == j ? 0.f : chi_n[i * n_types + j];
+  if (n_types == 2) sys->cfg.chi_n = chi_n[1];
+  sys->buf.counts = counts;
+  sys->buf.counts_bytes = counts_bytes;
+  sys->buf.omega = omega;
+  sys->buf.omega_bytes = omega_bytes;
+  sys->d.counts_bytes = planes * n_cells * word;
+  sys->d.omega_bytes = 4ull * n_types * n_cells;
+  sys->graph.release();   // captured launches hold the old buffers
+  int32_t rc = launch_hist(&sys->cfg, sys->d, sys->buf.pos, sys->buf.counts, s);
+  if (!rc) rc = refresh_fields(sys, s);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(s));
+  return SOMA_OK;
+}
+
+int32_t soma_type_counts(soma_system *sys, uint64_t *out, uint32_t n_out, void *stream) {
+  if (!sys || !out) return fail(SOMA_E_INVAL, "system or out is NULL");
+  if (n_out < sys->d.n_types) return fail(SOMA_E_SIZE, "out holds %u < %u types", n_out, sys->d.n_types);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const uint32_t blocks = sys->d.field_blocks;
+  unsigned long long *part = reinterpret_cast<unsigned long long *>(sys->ws + sys->d.off_tcount);
+  if (sys->cfg.count_width == 32)
+    hipLaunchKernelGGL(soma::type_count_kernel<true>, dim3(blocks), dim3(256), 0, s,
+                       sys->buf.counts, (uint32_t)sys->d.n_cells, sys->d.n_types, part);
+  else
+    hipLaunchKernelGGL(soma::type_count_kernel<false>, dim3(blocks), dim3(256), 0, s,
+                       sys->buf.counts, (uint32_t)sys->d.n_cells, sys->d.n_types, part);
+  LAUNCH_TRY();
+  std::vector<unsigned long long> h((size_t)blocks * soma::kMaxTypes);
+  HIP_TRY(hipMemcpyAsync(h.data(), part, 8ull * h.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (uint32_t t = 0; t < n_out; ++t) out[t] = 0;
+  for (uint32_t b = 0; b < blocks; ++b)
+    for (uint32_t t = 0; t < sys->d.n_types; ++t) out[t] += h[(size_t)b * soma::kMaxTypes + t];
   return SOMA_OK;
 }
 
@@ -1043,6 +1153,7 @@ int32_t soma_collect_training(soma_system *sys, uint32_t species, uint32_t n, ui
     return fail(SOMA_E_INVAL, "species %u has no chains", species);
   if (phase == 1 && !dr) return fail(SOMA_E_INVAL, "phase 1 needs dr");
   if (sys->arch_mask) return fail(SOMA_E_UNSUPPORTED, "training data of linear chains only");
+  if (sys->d.n_types > 2) return fail(SOMA_E_UNSUPPORTED, "training data with two bead types only");
   if (n == 0) return SOMA_OK;
   soma::CollectArgs a;
   a.pos = sys->buf.pos;
@@ -1408,6 +1519,7 @@ int32_t batch_check_kind(soma_batch *b, uint32_t kind) {
     if (x->scheme != SOMA_SCHEME_SET)
       return fail(SOMA_E_UNSUPPORTED, "batched sweeps use the SET order only");
     if (x->arch_mask) return fail(SOMA_E_UNSUPPORTED, "batched sweeps take linear chains only");
+    if (x->d.n_types > 2) return fail(SOMA_E_UNSUPPORTED, "batched sweeps take two bead types");
   }
   return SOMA_OK;
 }

@@ -17,7 +17,8 @@ constexpr uint32_t kPurposeSetOrder = 8u; // Philox purpose of the shuffled set 
 // members of a set on the molecule's lanes at once.  A move is the LOCAL move
 // of the linear kernel, the bond term summed over the monomer's bond list in
 // list order, so a linear chain given as an architecture moves bit for bit as
-// in mc_sweep_local_kernel.
+// in mc_sweep_local_kernel.  A monomer of type t sees field plane t and
+// counts in half t & 1 of count plane t >> 1 (any number of types).
 template <bool COUNT64>
 __global__ __launch_bounds__(256) void mc_sweep_arch_kernel(const SweepArgs a_in,
                                                             const ArchDev *__restrict__ A) {
@@ -91,8 +92,8 @@ __global__ __launch_bounds__(256) void mc_sweep_arch_kernel(const SweepArgs a_in
           const uint32_t cn = cell_index(a.grid, shift_cell(x, r.x, t.x, a.grid.nx),
                                          shift_cell(y, r.y, t.y, a.grid.ny),
                                          shift_cell(z, r.z, t.z, a.grid.nz));
-          const bool is_b = A->type[i] != 0;
-          const uint32_t pl = is_b ? a.grid.n_cells : 0u;
+          const uint32_t ty = A->type[i];
+          const uint32_t pl = ty * a.grid.n_cells;          // field plane of the type
           const float wo = field_at(a.omega, pl, co);
           const float wn = cn == co ? wo : field_at(a.omega, pl, cn);
           const float d_e = a.half_k0 * (d.x * qv.x + d.y * qv.y + d.z * qv.z) + (wn - wo) * a.inv_nref;
@@ -101,7 +102,10 @@ __global__ __launch_bounds__(256) void mc_sweep_arch_kernel(const SweepArgs a_in
             sp[3 * i] = t.x;
             sp[3 * i + 1] = t.y;
             sp[3 * i + 2] = t.z;
-            if (cn != co) move_count<COUNT64>(a.counts, co, cn, is_b);
+            if (cn != co) {   // count plane ty >> 1, half ty & 1
+              const uint32_t pw = (ty >> 1) * a.grid.n_cells;
+              move_count<COUNT64>(a.counts, co + pw, cn + pw, (ty & 1u) != 0u);
+            }
           }
         }
         n_acc += (uint32_t)__popcll(__ballot(acc));

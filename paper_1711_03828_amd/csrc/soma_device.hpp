@@ -151,9 +151,11 @@ struct ArchDev {
   uint8_t nb[kArchMaxBonds];
 };
 
-// Type of monomer i: from the architecture, else the linear rule i < n_a -> A.
-__device__ __forceinline__ bool bead_is_b(const ArchDev *arch, uint32_t i, uint32_t n_a) {
-  return arch ? arch->type[i] != 0 : i >= n_a;
+// Type code of monomer i (0 .. n_t - 1): from the architecture, else 0 (A) for
+// i < n_a and 1 (B).  Counts of type t live in the half t & 1 of the words of
+// count plane t >> 1; its field is plane t.
+__device__ __forceinline__ uint32_t bead_type(const ArchDev *arch, uint32_t i, uint32_t n_a) {
+  return arch ? (uint32_t)arch->type[i] : (i >= n_a ? 1u : 0u);
 }
 
 }  // namespace soma

@@ -27,13 +27,14 @@ __global__ __launch_bounds__(256) void density_hist_kernel(
   const float *r = pos + 3 * b;
   const uint32_t cell = cell_of(g, r[0], r[1], r[2]);
   const uint32_t i = n_beads <= 0xFFFFFFFFull ? (uint32_t)b % n : (uint32_t)(b % n);
-  const bool is_b = bead_is_b(arch, i, n_a);
+  const uint32_t t = bead_type(arch, i, n_a);
+  const size_t w = (size_t)(t >> 1) * g.n_cells + cell;   // count plane of the type
   if (COUNT64) {
-    const unsigned long long inc = 1ull << (is_b ? 32u : 0u);
-    atomicAdd(reinterpret_cast<unsigned long long *>(counts) + cell, inc);
+    const unsigned long long inc = 1ull << ((t & 1u) ? 32u : 0u);
+    atomicAdd(reinterpret_cast<unsigned long long *>(counts) + w, inc);
   } else {
-    const unsigned int inc = 1u << (is_b ? 16u : 0u);
-    atomicAdd(reinterpret_cast<unsigned int *>(counts) + cell, inc);
+    const unsigned int inc = 1u << ((t & 1u) ? 16u : 0u);
+    atomicAdd(reinterpret_cast<unsigned int *>(counts) + w, inc);
   }
 }
 
@@ -259,6 +260,167 @@ __device__ __forceinline__ void field_body(const FieldArgs &a, uint32_t blk, uin
 template <bool COUNT64>
 __global__ __launch_bounds__(256) void field_update_kernel(const FieldArgs a) {
   field_body<COUNT64>(a, blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// n_t bead types (Sec. 2.1) with a symmetric matrix of chi_ij N, Eq. (12):
+//   K^1: omega_i = kappaN (sum_k phi_k - 1) + sum_{k != i} chi_ik N phi_k
+//   K^0: omega_i = kappaN (sum_k phi_k - 1) - sum_{k != i} chi_ik N/2 (phi_i - phi_k)
+// FP32 order: s = (((phi_0 + phi_1) + phi_2) + ...) - 1, t = kappaN * s, then
+// t = fma(chi_ik, phi_k, t) (K^1) or fma(-chi_ik/2, phi_i - phi_k, t) (K^0)
+// for k = 0, 1, ... (k != i); with two types this is field_cell's order.
+// Counts: plane p holds types 2p (low half) and 2p + 1 (high half) of every
+// cell.  One thread per cell in a grid-stride loop; the FP64 partials are
+// sum_a = the type-0 count, sum_b = the other types, and H_nb (Eqs. (5), (6),
+// (8), pairs i < j).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kMaxTypes = 8u;
+
+struct MultiFieldArgs {
+  void *counts;
+  float *omega;
+  uint32_t n_cells, n_t, form, clear;
+  float inv_rho, kappa_n;
+  double inv_rho_d, kappa_n_d;
+  float chi[kMaxTypes * kMaxTypes];   // chi_ik N at [i * kMaxTypes + k]
+  FieldPartial *partials;              // may be null
+};
+
+template <bool COUNT64>
+__device__ __forceinline__ void load_types(const MultiFieldArgs &a, uint32_t c, uint32_t (&n)[kMaxTypes]) {
+  const uint32_t n_pl = (a.n_t + 1u) >> 1;
+#pragma unroll
+  for (uint32_t p = 0; p < kMaxTypes / 2; ++p) {
+    n[2 * p] = n[2 * p + 1] = 0u;
+    if (p < n_pl) {
+      const size_t w = (size_t)p * a.n_cells + c;
+      if (COUNT64) {
+        unsigned long long *q = reinterpret_cast<unsigned long long *>(a.counts) + w;
+        const unsigned long long v = *q;
+        n[2 * p] = (uint32_t)v;
+        n[2 * p + 1] = (uint32_t)(v >> 32);
+        if (a.clear) *q = 0ull;
+      } else {
+        uint32_t *q = reinterpret_cast<uint32_t *>(a.counts) + w;
+        const uint32_t v = *q;
+        n[2 * p] = v & 0xFFFFu;
+        n[2 * p + 1] = v >> 16;
+        if (a.clear) *q = 0u;
+      }
+    }
+  }
+}
+
+template <bool COUNT64>
+__global__ __launch_bounds__(256) void field_multi_kernel(const MultiFieldArgs a) {
+  __shared__ unsigned long long s_a[4], s_b[4];
+  __shared__ double s_h[4];
+  const uint32_t n_t = a.n_t;
+  const bool stats = a.partials != nullptr;
+  unsigned long long sum_a = 0, sum_b = 0;
+  double h = 0.0;
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < a.n_cells;
+       c += gridDim.x * blockDim.x) {
+    uint32_t n[kMaxTypes];
+    load_types<COUNT64>(a, c, n);
+    float phi[kMaxTypes];
+#pragma unroll
+    for (uint32_t i = 0; i < kMaxTypes; ++i) phi[i] = (float)n[i] * a.inv_rho;
+    float s = phi[0];
+#pragma unroll
+    for (uint32_t i = 1; i < kMaxTypes; ++i)
+      if (i < n_t) s = s + phi[i];
+    s = s - 1.0f;
+    const float t0 = a.kappa_n * s;
+#pragma unroll
+    for (uint32_t i = 0; i < kMaxTypes; ++i) {
+      if (i < n_t) {
+        float t = t0;
+#pragma unroll
+        for (uint32_t k = 0; k < kMaxTypes; ++k) {
+          if (k < n_t && k != i) {
+            const float x = a.chi[i * kMaxTypes + k];
+            t = a.form == 0 ? fmaf(-0.5f * x, phi[i] - phi[k], t) : fmaf(x, phi[k], t);
+          }
+        }
+        a.omega[(size_t)i * a.n_cells + c] = t;
+      }
+    }
+    if (stats) {
+      double pd[kMaxTypes], tot = 0.0, inter = 0.0;
+#pragma unroll
+      for (uint32_t i = 0; i < kMaxTypes; ++i) {
+        pd[i] = i < n_t ? (double)n[i] * a.inv_rho_d : 0.0;
+        tot += pd[i];
+        if (i == 0) sum_a += n[i];
+        else if (i < n_t) sum_b += n[i];
+      }
+#pragma unroll
+      for (uint32_t i = 0; i < kMaxTypes; ++i)
+#pragma unroll
+        for (uint32_t j = i + 1; j < kMaxTypes; ++j)
+          if (j < n_t) {
+            const double x = (double)a.chi[i * kMaxTypes + j], d = pd[i] - pd[j];
+            inter += a.form == 0 ? -0.25 * x * d * d : x * pd[i] * pd[j];
+          }
+      const double dev = tot - 1.0;
+      h += 0.5 * a.kappa_n_d * dev * dev + inter;
+    }
+  }
+  if (!stats) return;
+  for (int off = 32; off > 0; off >>= 1) {
+    sum_a += __shfl_down(sum_a, off, 64);
+    sum_b += __shfl_down(sum_b, off, 64);
+    h += __shfl_down(h, off, 64);
+  }
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  if (lane == 0) { s_a[wv] = sum_a; s_b[wv] = sum_b; s_h[wv] = h; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    FieldPartial p;
+    p.sum_a = s_a[0] + s_a[1] + s_a[2] + s_a[3];
+    p.sum_b = s_b[0] + s_b[1] + s_b[2] + s_b[3];
+    p.h_nb = ((s_h[0] + s_h[1]) + s_h[2]) + s_h[3];
+    p.pad = 0.0;
+    a.partials[blockIdx.x] = p;
+  }
+}
+
+// Per-type totals of the counts: block b writes out[b * kMaxTypes + t].
+template <bool COUNT64>
+__global__ __launch_bounds__(256) void type_count_kernel(const void *counts, uint32_t n_cells,
+                                                         uint32_t n_t, unsigned long long *out) {
+  __shared__ unsigned long long s[4][kMaxTypes];
+  unsigned long long v[kMaxTypes] = {};
+  const uint32_t n_pl = (n_t + 1u) >> 1;
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n_cells; c += gridDim.x * blockDim.x) {
+#pragma unroll
+    for (uint32_t p = 0; p < kMaxTypes / 2; ++p)
+      if (p < n_pl) {
+        const size_t w = (size_t)p * n_cells + c;
+        if (COUNT64) {
+          const unsigned long long x = reinterpret_cast<const unsigned long long *>(counts)[w];
+          v[2 * p] += (uint32_t)x;
+          v[2 * p + 1] += (uint32_t)(x >> 32);
+        } else {
+          const uint32_t x = reinterpret_cast<const uint32_t *>(counts)[w];
+          v[2 * p] += x & 0xFFFFu;
+          v[2 * p + 1] += x >> 16;
+        }
+      }
+  }
+#pragma unroll
+  for (uint32_t t = 0; t < kMaxTypes; ++t)
+    for (int off = 32; off > 0; off >>= 1) v[t] += __shfl_down(v[t], off, 64);
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (uint32_t t = 0; t < kMaxTypes; ++t) s[wv][t] = v[t];
+  __syncthreads();
+  if (threadIdx.x < kMaxTypes) {
+    const uint32_t t = threadIdx.x;
+    out[(size_t)blockIdx.x * kMaxTypes + t] = s[0][t] + s[1][t] + s[2][t] + s[3][t];
+  }
 }
 
 // Blocks of the grid-field update for a number of systems are given out in

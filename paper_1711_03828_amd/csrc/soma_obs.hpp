@@ -93,7 +93,7 @@ __global__ __launch_bounds__(256) void chain_obs_kernel(const ObsArgs a) {
           re2 += ex * ex + ey * ey + ez * ez;
         }
         const uint32_t cell = cell_of(a.grid, x, y, z);
-        ef += (double)a.omega[(bead_is_b(a.arch, i, a.n_a) ? a.grid.n_cells : 0u) + cell];
+        ef += (double)a.omega[(size_t)bead_type(a.arch, i, a.n_a) * a.grid.n_cells + cell];
       }
     }
     for (uint32_t off = seg >> 1; off > 0; off >>= 1) {   // sums within the segment

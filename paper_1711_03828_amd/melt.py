@@ -68,6 +68,7 @@ class Melt:
         cdt = torch.int32 if cfg.count_width == 16 else torch.int64
         self.counts = torch.empty(self.n_cells, dtype=cdt, device=device)
         self.omega = torch.empty((2, self.n_cells), dtype=torch.float32, device=device)
+        self.n_types = 2
         self.workspace = torch.empty(ws_b, dtype=torch.uint8, device=device)
         self.buf = C.soma_buffers(self.pos.data_ptr(), pos_b, self.counts.data_ptr(), cnt_b,
                                   self.omega.data_ptr(), om_b, self.workspace.data_ptr(), ws_b)
@@ -154,6 +155,25 @@ class Melt:
         """Interaction term: 1 = chiN phi_A phi_B (default), 0 = -chiN/4 (phi_A - phi_B)^2."""
         C.soma_set_hamiltonian(self.handle, form, _stream(stream))
 
+    def set_types(self, chi_n, stream=None):
+        """n_t bead types with the symmetric matrix chi_n (n_t x n_t, chi_ij N):
+        count and field buffers with a plane per type pair and per type
+        replace the two-type ones; the histogram and fields are rebuilt."""
+        chi = np.asarray(chi_n, dtype=np.float32)
+        n_t = chi.shape[0]
+        planes = (n_t + 1) // 2
+        cdt = self.counts.dtype
+        counts = torch.zeros(planes * self.n_cells, dtype=cdt, device=self.pos.device)
+        omega = torch.empty((n_t, self.n_cells), dtype=torch.float32, device=self.pos.device)
+        C.soma_set_types(self.handle, n_t, chi, counts.data_ptr(),
+                         counts.numel() * counts.element_size(), omega.data_ptr(),
+                         omega.numel() * 4, _stream(stream))
+        self.counts, self.omega, self.n_types = counts, omega, n_t
+
+    def type_counts(self, stream=None):
+        """Total count of every bead type in the kept histogram."""
+        return C.soma_type_counts(self.handle, self.n_types, _stream(stream))
+
     def set_scheme(self, scheme: int):
         """Iteration order of local moves: C.SOMA_SCHEME_SET or C.SOMA_SCHEME_MOLECULE."""
         C.soma_set_scheme(self.handle, scheme)
@@ -163,13 +183,18 @@ class Melt:
         return C.soma_choose_scheme(self.handle, cycles, _stream(stream))
 
     def counts_planes(self) -> np.ndarray:
-        """Unpack the packed counts to uint32 [2, n_cells] on the host."""
-        c = self.counts.cpu().numpy()
+        """Unpack the packed counts to uint32 [n_types, n_cells] on the host."""
+        n_t = self.n_types
+        c = self.counts.cpu().numpy().reshape(-1, self.n_cells)
         if self.cfg.count_width == 16:
             u = c.view(np.uint32)
-            return np.stack([u & 0xFFFF, u >> 16]).astype(np.uint32)
-        u = c.view(np.uint64)
-        return np.stack([u & 0xFFFFFFFF, u >> 32]).astype(np.uint32)
+            lo, hi = u & 0xFFFF, u >> 16
+        else:
+            u = c.view(np.uint64)
+            lo, hi = u & 0xFFFFFFFF, u >> 32
+        out = np.empty((2 * u.shape[0], self.n_cells), np.uint32)
+        out[0::2], out[1::2] = lo, hi
+        return out[:n_t]
 
     def close(self):
         if self.handle:

@@ -110,6 +110,8 @@ _SIGS = {
     "soma_set_sweep_blocks": ([_P, _u32], _i32),
     "soma_set_scheme": ([_P, _u32], _i32),
     "soma_set_hamiltonian": ([_P, _u32, _P], _i32),
+    "soma_set_types": ([_P, _u32, _P, _P, _u64, _P, _u64, _P], _i32),
+    "soma_type_counts": ([_P, _pu64, _u32, _P], _i32),
     "soma_set_architecture": ([_P, _u32, _P, _u32, _P], _i32),
     "soma_set_external": ([_P, _P, _u64, _P, _u64, _P], _i32),
     "soma_choose_scheme": ([_P, _u32, _P, ctypes.POINTER(_u32), ctypes.POINTER(ctypes.c_float)],
@@ -219,6 +221,21 @@ def soma_set_architecture(h, species: int, words, stream) -> None:
 
 def soma_set_hamiltonian(h, form: int, stream) -> None:
     _check(_lib.soma_set_hamiltonian(h, form, stream))
+
+
+def soma_set_types(h, n_types: int, chi_n, counts_ptr: int, counts_bytes: int, omega_ptr: int,
+                   omega_bytes: int, stream) -> None:
+    """chi_n: host n_types x n_types matrix of chi_ij N (symmetric)."""
+    import numpy as np
+    chi = np.ascontiguousarray(chi_n, dtype=np.float32).reshape(n_types, n_types)
+    _check(_lib.soma_set_types(h, n_types, chi.ctypes.data, counts_ptr, counts_bytes, omega_ptr,
+                               omega_bytes, stream))
+
+
+def soma_type_counts(h, n_types: int, stream):
+    out = (ctypes.c_uint64 * n_types)()
+    _check(_lib.soma_type_counts(h, out, n_types, stream))
+    return [int(x) for x in out]
 
 
 def soma_set_scheme(h, scheme: int) -> None:
