@@ -341,8 +341,9 @@ def scheme_leg(cycles: int):
 def arch_leg(cycles: int):
     """General molecular architectures (Sec. 3.2.1): the 262,144-chain A16B16 melt
     swept by the linear kernel and, given as an architecture, by the
-    general-architecture kernel (same bits, the cost of generality), and a melt
-    of 6-arm stars (31 monomers, arms of 5, A core half) at the same density.
+    general-architecture kernel (same bits, the cost of generality), a melt
+    of 6-arm stars (31 monomers, arms of 5, A core half) and a melt of ABC
+    triblocks (three bead types, Sec. 2.1) at the same density.
     Graph-replayed SCMF cycles."""
     import numpy as np
     import torch
@@ -387,8 +388,38 @@ def arch_leg(cycles: int):
                         "acceptance": obs.accepted[0] / max(1, obs.attempted[0]),
                         "counts_conserved": obs.counts_conserved}
     m.close()
+    # ABC triblock terpolymer A11 B10 C11: three types, fields from a chi_ij N matrix
+    n = 32
+    types = [0] * 11 + [1] * 10 + [2] * 11
+    bonds = [(i, i + 1) for i in range(n - 1)]
+    chi = [[0.0, w.chi_n, 2.0 * w.chi_n], [w.chi_n, 0.0, w.chi_n], [2.0 * w.chi_n, w.chi_n, 0.0]]
+    wt = synth.Workload("abc_triblock_A11B10C11_grid96", w.grid,
+                        (synth.SpeciesSpec(w.n_beads // n, n, 0),), 6.0, 32, w.chi_n, w.kappa_n, 16)
+    m = Melt(make_config(wt))
+    m.set_types(chi)
+    m.set_architecture(synth.encode_architecture(n, types, bonds))
+    ms_t = timed(m)
+    reps = 50
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        m.update_fields()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    field_ms = e0.elapsed_time(e1) / reps
+    obs = m.observables()
+    per_type = m.type_counts()
+    field_bytes = wt.n_cells * (2 * 4 + 3 * 4)   # two packed u32 count planes read, three fields written
+    out["abc_triblock_melt"] = {
+        "workload": wt.name, "n_types": 3, "chi_n_matrix": chi, "n_beads": wt.n_beads,
+        "ms_per_cycle": ms_t, "bead_moves_per_s": wt.n_beads * 1e3 / ms_t,
+        "field_refresh_ms": field_ms, "field_refresh_GBs": field_bytes / field_ms / 1e6,
+        "acceptance": obs.accepted[0] / max(1, obs.attempted[0]),
+        "type_counts": per_type, "counts_conserved": obs.counts_conserved}
+    m.close()
     print(f"# architectures: linear {out['linear_kernel']['ms_per_cycle']:.3f} ms, as architecture "
-          f"{out['architecture_kernel']['ms_per_cycle']:.3f} ms, stars {ms:.3f} ms per cycle",
+          f"{out['architecture_kernel']['ms_per_cycle']:.3f} ms, stars {ms:.3f} ms, ABC triblock "
+          f"{ms_t:.3f} ms per cycle (3-type field {field_ms * 1e3:.1f} us)",
           file=sys.stderr, flush=True)
     return out
 
