@@ -30,6 +30,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 MOVE_LOCAL = 0
 MOVE_SMC = 1
+MOVE_GIBBS = 3
 
 
 def build(force: bool = False) -> str:

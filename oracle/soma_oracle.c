@@ -34,6 +34,7 @@
 
 #define ORC_MOVE_LOCAL 0u
 #define ORC_MOVE_SMC 1u
+#define ORC_MOVE_GIBBS 3u
 
 #define ORC_PURPOSE_MOVE_A 0u
 #define ORC_PURPOSE_MOVE_B 1u
@@ -489,6 +490,58 @@ static int orc_move_smc(float *chain, uint32_t c_id, uint32_t i, uint32_t n,
   return accept;
 }
 
+/* Bond-Gibbs move: the trial position is drawn from the distribution of the
+ * bead given its bonded neighbours under the bond energy alone, Eqs. (1)-(2):
+ * a Gaussian around the mean of the neighbours with variance 1/(n_b k0) per
+ * component (n_b = 1 or 2 neighbours); a bead without bonds makes a symmetric
+ * Gaussian step of variance 1/(2 k0).  Accepted by the Metropolis-Hastings
+ * ratio exp(-dE) q(r|r') / q(r'|r), evaluated here term by term (the bond and
+ * proposal terms cancel in exact arithmetic, leaving the field term).  Draws:
+ * block A (purpose 0) for four normals (three used), block B (purpose 1), word
+ * 0, for acceptance -- the smart-MC layout. */
+static int orc_move_gibbs(float *chain, uint32_t c_id, uint32_t i, uint32_t n,
+                          uint32_t n_a, double k0, const float *omega,
+                          uint64_t n_cells, uint32_t nx, uint32_t ny,
+                          uint32_t nz, uint32_t n_ref, uint64_t seed,
+                          uint32_t sweep, uint32_t replica) {
+  uint32_t wa[4], wb[4];
+  orc_draw(seed, c_id, i, ORC_PURPOSE_MOVE_A, sweep, replica, wa);
+  orc_draw(seed, c_id, i, ORC_PURPOSE_MOVE_B, sweep, replica, wb);
+  double xi[4];
+  orc_box_muller(wa[0], wa[1], &xi[0], &xi[1]);
+  orc_box_muller(wa[2], wa[3], &xi[2], &xi[3]);
+  float *r = chain + 3 * i;
+  int n_b = (i > 0) + (i + 1 < n);
+  double mu[3], var;
+  for (int d = 0; d < 3; ++d) {
+    double s = 0.0;
+    if (i > 0) s += (double)chain[3 * (i - 1) + d];
+    if (i + 1 < n) s += (double)chain[3 * (i + 1) + d];
+    mu[d] = n_b > 0 ? s / n_b : (double)r[d];
+  }
+  var = 1.0 / ((n_b > 0 ? n_b : 2) * k0);
+  float trial[3];
+  for (int d = 0; d < 3; ++d) trial[d] = (float)(mu[d] + sqrt(var) * xi[d]);
+  if (orc_blocked(r, trial, nx, ny, nz)) return 0;
+  /* log q(x | y): the Gaussian around mu (n_b > 0, independent of y) or around y */
+  double log_fwd = 0.0, log_rev = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    double cf = n_b > 0 ? mu[d] : (double)r[d];
+    double cr = n_b > 0 ? mu[d] : (double)trial[d];
+    log_fwd -= ((double)trial[d] - cf) * ((double)trial[d] - cf) / (2.0 * var);
+    log_rev -= ((double)r[d] - cr) * ((double)r[d] - cr) / (2.0 * var);
+  }
+  const float *om = omega + (uint64_t)orc_type(i, n_a) * n_cells;
+  double d_bond = orc_bond_energy(trial, chain, i, n, k0) - orc_bond_energy(r, chain, i, n, k0);
+  double d_field = ((double)om[orc_cell(trial, nx, ny, nz)] -
+                    (double)om[orc_cell(r, nx, ny, nz)]) / (double)n_ref;
+  double log_ratio = -(d_bond + d_field) + log_rev - log_fwd;
+  double u = (double)orc_u01(wb[0]);
+  int accept = (log_ratio >= 0.0) || (u < exp(log_ratio));
+  if (accept) memcpy(r, trial, sizeof trial);
+  return accept;
+}
+
 uint64_t orc_mc_sweep(float *pos, uint32_t n_chains, uint32_t n,
                       uint32_t n_a, float k0, uint32_t n_ref,
                       const float *omega, uint32_t nx, uint32_t ny,
@@ -517,6 +570,9 @@ uint64_t orc_mc_sweep(float *pos, uint32_t n_chains, uint32_t n,
           acc = orc_move_smc(chain, c_id, i, n, n_a, (double)k0, omega,
                              n_cells, nx, ny, nz, n_ref, step, seed, sweep,
                              replica);
+        else if (move_kind == ORC_MOVE_GIBBS)
+          acc = orc_move_gibbs(chain, c_id, i, n, n_a, (double)k0, omega, n_cells, nx, ny, nz,
+                               n_ref, seed, sweep, replica);
         else
           acc = orc_move_local(chain, c_id, i, n, n_a, (double)k0, omega,
                                n_cells, nx, ny, nz, n_ref, step, seed, sweep,
