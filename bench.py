@@ -146,6 +146,10 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
        16th chain from frames every `frame_cycles` cycles (plain: `plain_mult`
        times as many cycles between frames), learned run first.  Uncorrelated
        samples/s = n_chains * cycles/s / (2 tau_int), cycles/s from step 2.
+    4. As context, the analytic bond-Gibbs proposal (each bead drawn from its
+       law given its bonded neighbours, accepted on the field term alone) with
+       the learned sampler's sub-steps, measured the same way after the learned
+       run.
     """
     import torch
 
@@ -172,8 +176,10 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
                         "batch": 8192, "loss_first": losses[0], "loss_last": losses[-1],
                         "seconds_collect_and_train": t_train}}
     rates = {}
-    ksub = {"plain": 1, "learned": substeps}
-    for name, kind in (("plain", C.SOMA_MOVE_LOCAL), ("learned", C.SOMA_MOVE_MIXED)):
+    ksub = {"plain": 1, "learned": substeps, "gibbs": substeps}
+    kidx = {C.SOMA_MOVE_LOCAL: 0, C.SOMA_MOVE_MIXED: 2, C.SOMA_MOVE_GIBBS: 3}
+    for name, kind in (("plain", C.SOMA_MOVE_LOCAL), ("learned", C.SOMA_MOVE_MIXED),
+                       ("gibbs", C.SOMA_MOVE_GIBBS)):
         melt.set_substeps(ksub[name])
         melt.capture_cycle(10, kind)
         melt.run_cycle(2)
@@ -189,6 +195,7 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
     obs = melt.observables()
     out["learned"]["acceptance"] = obs.accepted[2] / max(1, obs.attempted[2])
     out["plain"]["acceptance"] = obs.accepted[0] / max(1, obs.attempted[0])
+    out["gibbs"]["acceptance"] = obs.accepted[3] / max(1, obs.attempted[3])
 
     # equilibrate the full melt with the learned sampler, fine-tune on plain
     # trajectories from that state, then the tau_int runs on the full melt
@@ -205,7 +212,7 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
                                     "loss_first": tl[0], "loss_last": tl[-1],
                                     "after_learned_cycles": equil_cycles}
     stride = 16                              # end-to-end vectors of every 16th chain
-    for name, kind, mult in (("learned", C.SOMA_MOVE_MIXED, 1),
+    for name, kind, mult in (("learned", C.SOMA_MOVE_MIXED, 1), ("gibbs", C.SOMA_MOVE_GIBBS, 1),
                              ("plain", C.SOMA_MOVE_LOCAL, plain_mult)):
         melt.set_substeps(ksub[name])
         melt.capture_cycle(frame_cycles * mult, kind)
@@ -222,7 +229,7 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
         step = frame_cycles * mult
         tau = tau_frames * step
         re2 = float((re.double() ** 2).sum(-1).mean()) / w.re_cells ** 2
-        k = 2 if kind == C.SOMA_MOVE_MIXED else 0
+        k = kidx[kind]
         # statistical error of tau_int from the pooled series (Sokal: var(tau)/tau^2 =
         # 2 (2M + 1) / n for one series of n frames and window M; m pooled, nearly
         # independent series divide it by m); the window's truncation bias is not in it
@@ -244,6 +251,10 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
     rel = math.hypot(out["learned"]["tau_int_err_cycles"] / out["learned"]["tau_int_cycles"],
                      out["plain"]["tau_int_err_cycles"] / out["plain"]["tau_int_cycles"])
     out["gain_err"] = out["gain_uncorrelated_samples_per_s"] * rel
+    out["gibbs_gain_over_plain"] = (out["gibbs"]["uncorrelated_samples_per_s"] /
+                                    out["plain"]["uncorrelated_samples_per_s"])
+    out["learned_over_gibbs"] = (out["learned"]["uncorrelated_samples_per_s"] /
+                                 out["gibbs"]["uncorrelated_samples_per_s"])
     return out
 
 

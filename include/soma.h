@@ -66,6 +66,16 @@ typedef enum soma_status {
 #define SOMA_MOVE_LOCAL 0u /* uniform trial displacement in [-a,a]^3, Metropolis */
 #define SOMA_MOVE_SMC 1u   /* force-biased (smart MC) proposal, Metropolis-Hastings */
 #define SOMA_MOVE_MIXED 2u /* learned proposal with probability p_learn, else local; MH */
+/* bond-Gibbs proposal: a bead's trial position drawn from its law given its
+ * bonded neighbours under the bond energy alone (Eqs. (1)-(2)): Gaussian
+ * around the mean of the neighbours, variance 1/(n_b k0) per component
+ * (n_b = 1 or 2; a bead without bonds steps by N(0, 1/(2 k0))), computed as
+ * fma(s, xi, mu) in FP32 with s = 1/sqrt(2 k0) or 1/sqrt(k0) rounded from
+ * FP64, xi by Box-Muller from the smart-MC draws.  The bond energy and the
+ * proposal densities cancel in the Metropolis-Hastings ratio of Sec. 2.2, so
+ * a move is accepted with min(1, exp(-(omega(c') - omega(c))/N)).  Linear
+ * chains, SET order; not in batched sweeps. */
+#define SOMA_MOVE_GIBBS 3u
 
 /* Iteration orders of local moves (Sec. 3.1.2). */
 #define SOMA_SCHEME_SET 0u      /* per chain, the even and the odd beads as two sets in random
@@ -121,8 +131,8 @@ typedef struct soma_obs {
   uint64_t n_beads, n_chains;
   uint64_t count_a;       /* sum of A counts of the last field update */
   uint64_t count_b;       /* sum of B counts of the last field update */
-  uint64_t accepted[3];   /* accepted moves since init: local, smart-MC, learned */
-  uint64_t attempted[3];  /* attempted moves since init: local, smart-MC, learned */
+  uint64_t accepted[4];   /* accepted moves since init: local, smart-MC, learned, bond-Gibbs */
+  uint64_t attempted[4];  /* attempted moves since init: local, smart-MC, learned, bond-Gibbs */
   double re2_sum;         /* sum over chains of |r_{N-1} - r_0|^2 */
   double rg2_sum;         /* sum over chains of (1/N) sum_i |r_i - r_cm|^2 */
   double b2_sum;          /* sum over bonds of |r_{i+1} - r_i|^2 */
@@ -161,7 +171,7 @@ int32_t soma_init_system(const soma_config *cfg, const soma_buffers *buf,
  * fixed: each sweep attempts one move of every bead, the even and the odd
  * beads of a chain forming the two independent sets of Sec. 3.1.2, moved set
  * after set in a random order per chain and sweep.  move_kind is
- * SOMA_MOVE_LOCAL, SOMA_MOVE_SMC or SOMA_MOVE_MIXED.  The histogram in buf->counts is updated
+ * SOMA_MOVE_LOCAL, SOMA_MOVE_SMC, SOMA_MOVE_MIXED or SOMA_MOVE_GIBBS.  The histogram in buf->counts is updated
  * in the same pass (a bead that changes cell is moved from its old to its new
  * cell), so after the call it equals the histogram of the final positions,
  * bit for bit.  Asynchronous. */

@@ -126,7 +126,7 @@ int32_t derive(const soma_config *c, Derived *d) {
   d->omega_bytes = 8ull * n_cells;
   d->off_err = 0;
   d->off_acc = align_up(d->off_err + 16);
-  d->off_att = align_up(d->off_acc + 3ull * soma::kAccSlots * 8ull);
+  d->off_att = align_up(d->off_acc + 4ull * soma::kAccSlots * 8ull);
   d->off_net = align_up(d->off_att + soma::kAccSlots * 8ull);
   d->off_fpart = align_up(d->off_net + SOMA_MAX_SPECIES * align_up(sizeof(soma::NetDev)));
   d->off_totals = align_up(d->off_fpart + soma::kFieldBlocks * sizeof(soma::FieldPartial));
@@ -295,7 +295,7 @@ struct soma_system {
   Derived d;
   soma::Grid grid;
   uint64_t sweep = 0;
-  uint64_t attempted[2] = {0, 0};
+  uint64_t attempted[4] = {0, 0, 0, 0};   // by move kind (the learned slot unused)
   uint32_t sweep_blocks = 0;  // local-move grid: 0 = one tile per wave, else persistent blocks
   uint64_t mixed_moves = 0;   // bead moves made by mixed sweeps (local or learned)
   uint32_t net_mask = 0;      // species with an installed network (bit per species)
@@ -345,6 +345,8 @@ void launch_sweep_t(uint32_t kind, dim3 grid, hipStream_t s, const soma::SweepAr
     hipLaunchKernelGGL((soma::mc_sweep_mixed_kernel<C64, V2>), grid, dim3(256), 0, s, a, mx);
   else if (kind == SOMA_MOVE_SMC)
     hipLaunchKernelGGL((soma::mc_sweep_smc_kernel<C64, V2>), grid, dim3(256), 0, s, a);
+  else if (kind == SOMA_MOVE_GIBBS)
+    hipLaunchKernelGGL((soma::mc_sweep_gibbs_kernel<C64, V2>), grid, dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL((soma::mc_sweep_local_kernel<C64, V2>), grid, dim3(256), 0, s, a);
 }
@@ -357,7 +359,10 @@ void sweep_args(soma_system *sys, uint32_t sp, uint32_t kind, soma::SweepArgs &a
   a.pos = sys->buf.pos + 3 * sys->d.bead_off[sp];
   a.omega = sys->buf.omega;
   a.counts = sys->buf.counts;
-  a.acc_slots = sys->acc() + (kind == SOMA_MOVE_SMC ? soma::kAccSlots : 0u);
+  // accepted-move counters: local (and the local part of mixed sweeps), smart MC,
+  // learned, bond-Gibbs
+  a.acc_slots = sys->acc() + (kind == SOMA_MOVE_SMC ? soma::kAccSlots
+                              : kind == SOMA_MOVE_GIBBS ? 3u * soma::kAccSlots : 0u);
   a.grid = sys->grid;
   a.n_chains = S.n_chains;
   a.n = S.n;
@@ -382,6 +387,8 @@ void sweep_args(soma_system *sys, uint32_t sp, uint32_t kind, soma::SweepArgs &a
   a.n_sub = S.n_chains;
   a.grad = sys->grad;
   a.forbid = sys->d.forbid;
+  a.gibbs_s2 = (float)(1.0 / std::sqrt(2.0 * (double)S.k0));
+  a.gibbs_s1 = (float)(1.0 / std::sqrt((double)S.k0));
   mx.net = sys->net(sp);
   mx.head.m_max = c->mu_max;
   mx.head.lo = c->log_sigma_min;
@@ -461,13 +468,14 @@ int32_t launch_counter(uint32_t *ctr, uint32_t by, uint32_t set, uint32_t value,
 }
 
 int32_t check_kind(soma_system *sys, uint32_t move_kind) {
-  if (move_kind != SOMA_MOVE_LOCAL && move_kind != SOMA_MOVE_SMC && move_kind != SOMA_MOVE_MIXED)
+  if (move_kind != SOMA_MOVE_LOCAL && move_kind != SOMA_MOVE_SMC && move_kind != SOMA_MOVE_MIXED &&
+      move_kind != SOMA_MOVE_GIBBS)
     return fail(SOMA_E_UNSUPPORTED, "move kind %u", move_kind);
   if (move_kind == SOMA_MOVE_MIXED && sys->cfg.p_learn > 0.f && !sys->nets_ready())
     return fail(SOMA_E_INVAL, "mixed moves need a network for every species (soma_set_proposal)");
   if (move_kind == SOMA_MOVE_SMC && !(sys->cfg.smc_a > 0.f))
     return fail(SOMA_E_INVAL, "smart-MC moves need smc_a > 0");
-  if (move_kind != SOMA_MOVE_SMC && !(sys->cfg.local_a < 1.f))
+  if ((move_kind == SOMA_MOVE_LOCAL || move_kind == SOMA_MOVE_MIXED) && !(sys->cfg.local_a < 1.f))
     return fail(SOMA_E_UNSUPPORTED, "local moves need a half-width below one cell");
   if (move_kind != SOMA_MOVE_LOCAL && sys->scheme != SOMA_SCHEME_SET)
     return fail(SOMA_E_UNSUPPORTED, "the molecule-parallel order has local moves only");
@@ -1005,10 +1013,11 @@ int32_t soma_observables(soma_system *sys, soma_obs *out, void *stream) {
   out->n_chains = sys->d.n_chains;
   out->count_a = t.sum_a;
   out->count_b = t.sum_b;
-  for (int k = 0; k < 3; ++k) out->accepted[k] = t.accepted[k];
+  for (int k = 0; k < 4; ++k) out->accepted[k] = t.accepted[k];
   out->attempted[0] = sys->attempted[0] + (sys->mixed_moves - t.attempted_learned);
   out->attempted[1] = sys->attempted[1];
   out->attempted[2] = t.attempted_learned;
+  out->attempted[3] = sys->attempted[3];
   out->re2_sum = t.re2;
   out->rg2_sum = t.rg2;
   out->b2_sum = t.b2;
@@ -1520,6 +1529,7 @@ int32_t batch_check_kind(soma_batch *b, uint32_t kind) {
       return fail(SOMA_E_UNSUPPORTED, "batched sweeps use the SET order only");
     if (x->arch_mask) return fail(SOMA_E_UNSUPPORTED, "batched sweeps take linear chains only");
     if (x->d.n_types > 2) return fail(SOMA_E_UNSUPPORTED, "batched sweeps take two bead types");
+    if (kind == SOMA_MOVE_GIBBS) return fail(SOMA_E_UNSUPPORTED, "batched sweeps: no bond-Gibbs moves");
   }
   return SOMA_OK;
 }

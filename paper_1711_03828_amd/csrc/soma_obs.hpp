@@ -13,7 +13,7 @@ struct ObsPartial {
 };
 
 struct Totals {
-  unsigned long long accepted[3];
+  unsigned long long accepted[4];   // local, smart MC, learned, bond-Gibbs
   unsigned long long attempted_learned;
   unsigned long long sum_a, sum_b;
   double re2, rg2, b2, e_bond, e_field, h_nb;
@@ -120,16 +120,16 @@ __global__ __launch_bounds__(256) void chain_obs_kernel(const ObsArgs a) {
 }
 
 // Single block: fixed-order reduction of all partials into one Totals record.
-// acc_slots holds kAccSlots counters for each of local, smart-MC and learned
-// moves; att_slots the attempted learned moves.
+// acc_slots holds kAccSlots counters for each of local, smart-MC, learned and
+// bond-Gibbs moves; att_slots the attempted learned moves.
 __global__ __launch_bounds__(256) void reduce_totals_kernel(
     const ObsPartial *op, uint32_t n_op, const FieldPartial *fp, uint32_t n_fp,
     const unsigned long long *acc_slots, const unsigned long long *att_slots,
     const uint32_t *err, Totals *out) {
   __shared__ double s[4][6];
-  __shared__ unsigned long long su[4][6];
+  __shared__ unsigned long long su[4][7];
   double v[6] = {0, 0, 0, 0, 0, 0};
-  unsigned long long u[6] = {0, 0, 0, 0, 0, 0};
+  unsigned long long u[7] = {0, 0, 0, 0, 0, 0, 0};
   for (uint32_t i = threadIdx.x; i < n_op; i += blockDim.x) {
     v[0] += op[i].re2; v[1] += op[i].rg2; v[2] += op[i].b2;
     v[3] += op[i].e_bond; v[4] += op[i].e_field;
@@ -142,20 +142,22 @@ __global__ __launch_bounds__(256) void reduce_totals_kernel(
     u[1] += acc_slots[kAccSlots + i];
     u[2] += acc_slots[2 * kAccSlots + i];
     u[5] += att_slots[i];
+    u[6] += acc_slots[3 * kAccSlots + i];
   }
   block_sum<6>(v, s);
   for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-    for (int j = 0; j < 6; ++j) u[j] += __shfl_down(u[j], off, 64);
+    for (int j = 0; j < 7; ++j) u[j] += __shfl_down(u[j], off, 64);
   const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
   if (lane == 0)
 #pragma unroll
-    for (int j = 0; j < 6; ++j) su[wv][j] = u[j];
+    for (int j = 0; j < 7; ++j) su[wv][j] = u[j];
   __syncthreads();
   if (threadIdx.x == 0) {
     Totals t;
 #pragma unroll
     for (int j = 0; j < 3; ++j) t.accepted[j] = su[0][j] + su[1][j] + su[2][j] + su[3][j];
+    t.accepted[3] = su[0][6] + su[1][6] + su[2][6] + su[3][6];
     t.sum_a = su[0][3] + su[1][3] + su[2][3] + su[3][3];
     t.sum_b = su[0][4] + su[1][4] + su[2][4] + su[3][4];
     t.attempted_learned = su[0][5] + su[1][5] + su[2][5] + su[3][5];

@@ -50,6 +50,10 @@ struct SweepArgs {
   // optional impenetrable cells, one bit per cell (null: none): a trial position
   // in such a cell, other than the bead's own, is rejected
   const uint32_t *forbid;
+  // bond-Gibbs moves: standard deviation of the trial around the mean of two
+  // bonded neighbours, 1/sqrt(2 k0) (also the step of a bead without bonds),
+  // and around one, 1/sqrt(k0)
+  float gibbs_s2, gibbs_s1;
 };
 
 // A move from cell `from` to cell `to` that the impenetrable cells allow.
@@ -358,8 +362,16 @@ __device__ __forceinline__ float field_and_grad(const SweepArgs &a, uint32_t pl,
 // min(1, exp(-dE) q(r|r')/q(r'|r)), q the Gaussian proposal density.  The
 // trial position of the second set depends on the first set's outcome through
 // the bonded force, so the sets are handled one after the other.
+//
+// GIBBS: bond-Gibbs moves instead.  The trial is drawn from the bead's law
+// given its bonded neighbours under the bond energy (Eqs. (1)-(2)):
+// r' = fma(s, xi, mu), mu = 0.5 (r_l + r_r) and s = 1/sqrt(2 k0) between two
+// neighbours, mu = the neighbour and s = 1/sqrt(k0) at a chain end, mu = r and
+// s = 1/sqrt(2 k0) without bonds.  The bond energy and the proposal densities
+// then cancel in the Metropolis-Hastings ratio, which leaves
+// exp(-(omega(c') - omega(c))/N).  Same draws as smart MC.
 // ---------------------------------------------------------------------------
-template <bool COUNT64, bool VEC2>
+template <bool COUNT64, bool VEC2, bool GIBBS = false>
 __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &m) {
   const uint32_t N = a.n;
   const uint32_t i0 = 2u * m.k, i1 = i0 + 1u;
@@ -384,7 +396,10 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
   const uint32_t co0 = cell_index(a.grid, ox0, oy0, oz0), co1 = cell_index(a.grid, ox1, oy1, oz1);
   F3 g0 = {0.f, 0.f, 0.f}, g1 = {0.f, 0.f, 0.f};
   float f0 = 0.f, f1 = 0.f;
-  if (a.grad) {
+  if (GIBBS) {   // only the field values at the old cells
+    if (m.has0) f0 = field_at(a.omega, b0 ? a.grid.n_cells : 0u, co0);
+    if (m.has1) f1 = field_at(a.omega, b1 ? a.grid.n_cells : 0u, co1);
+  } else if (a.grad) {
     if (m.has0) f0 = field_and_grad(a, b0 ? a.grid.n_cells : 0u, co0, ox0, oy0, oz0, g0);
     if (m.has1) f1 = field_and_grad(a, b1 ? a.grid.n_cells : 0u, co1, ox1, oy1, oz1, g1);
   }
@@ -411,7 +426,28 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
     bool acc = false;
     uint32_t co = 0, cn = 0;
     F3 rn = r;
-    if (moving) {
+    if (GIBBS && moving) {
+      co = odd ? co1 : co0;
+      float xi0, xi1, xi2, xi3;
+      box_muller(w.x, w.y, xi0, xi1);
+      box_muller(w.z, w.w, xi2, xi3);
+      F3 mu = r;
+      float sg = a.gibbs_s2;
+      if (wl > 0.0f && wr > 0.0f) {
+        mu = {0.5f * (left.x + right.x), 0.5f * (left.y + right.y), 0.5f * (left.z + right.z)};
+      } else if (wl > 0.0f || wr > 0.0f) {
+        mu = wl > 0.0f ? left : right;
+        sg = a.gibbs_s1;
+      }
+      rn = {fmaf(sg, xi0, mu.x), fmaf(sg, xi1, mu.y), fmaf(sg, xi2, mu.z)};
+      uint32_t nx_, ny_, nz_;
+      cell3(a.grid, rn.x, rn.y, rn.z, nx_, ny_, nz_);
+      cn = cell_index(a.grid, nx_, ny_, nz_);
+      const float w_old = odd ? f1 : f0;
+      const float w_new = cn == co ? w_old : field_at(a.omega, pl, cn);
+      const float d_e = (w_new - w_old) * a.inv_nref;
+      acc = move_allowed(a, co, cn) && (d_e <= 0.0f || u < __expf(-d_e));
+    } else if (moving) {
       co = odd ? co1 : co0;
       const F3 el = {r.x - left.x, r.y - left.y, r.z - left.z};
       const F3 er = {r.x - right.x, r.y - right.y, r.z - right.z};
@@ -469,6 +505,13 @@ __global__ __launch_bounds__(256) void mc_sweep_smc_kernel(const SweepArgs a_in)
   const SweepArgs a = resolve_sweep(a_in, 0u);
   const LaneMap m = lane_map(a);
   finish_block(a, smc_wave<COUNT64, VEC2>(a, m));
+}
+
+template <bool COUNT64, bool VEC2>
+__global__ __launch_bounds__(256) void mc_sweep_gibbs_kernel(const SweepArgs a_in) {
+  const SweepArgs a = resolve_sweep(a_in, 0u);
+  const LaneMap m = lane_map(a);
+  finish_block(a, smc_wave<COUNT64, VEC2, true>(a, m));
 }
 
 }  // namespace soma

@@ -24,6 +24,7 @@ SOMA_E_DEVICE_FLAG = -5
 SOMA_MOVE_LOCAL = 0
 SOMA_MOVE_SMC = 1
 SOMA_MOVE_MIXED = 2
+SOMA_MOVE_GIBBS = 3
 SOMA_SCHEME_SET = 0
 SOMA_SCHEME_MOLECULE = 1
 SOMA_FLAG_POSITION = 1
@@ -62,8 +63,8 @@ class soma_buffers(ctypes.Structure):
 class soma_obs(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_uint64), ("n_beads", ctypes.c_uint64),
                 ("n_chains", ctypes.c_uint64), ("count_a", ctypes.c_uint64),
-                ("count_b", ctypes.c_uint64), ("accepted", ctypes.c_uint64 * 3),
-                ("attempted", ctypes.c_uint64 * 3), ("re2_sum", ctypes.c_double),
+                ("count_b", ctypes.c_uint64), ("accepted", ctypes.c_uint64 * 4),
+                ("attempted", ctypes.c_uint64 * 4), ("re2_sum", ctypes.c_double),
                 ("rg2_sum", ctypes.c_double), ("b2_sum", ctypes.c_double),
                 ("e_bond", ctypes.c_double), ("e_field", ctypes.c_double),
                 ("h_nb", ctypes.c_double), ("error_flags", ctypes.c_uint32),

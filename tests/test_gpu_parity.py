@@ -8,7 +8,8 @@ Bars (written here, applied element by element on identical seeded inputs):
     chain without an accept-decision mismatch; mismatches (FP32 vs FP64
     energies at the Metropolis threshold) at most 1e-6 of the attempted moves,
     rounded up;
-  * smart-MC moves: positions within 1e-5 Re0 per coordinate, same mismatch bar;
+  * smart-MC and bond-Gibbs moves: positions within 1e-5 Re0 per coordinate, same
+    mismatch bar;
   * initial walks: origins bit-exact, every bead within 1e-5 Re0;
   * observables: FP64 sums within 1e-9 relative.
 """
@@ -133,7 +134,7 @@ def _chain_mismatch(got, exp, n, tol):
     return np.abs(g - e).reshape(g.shape[0], -1).max(axis=1) > tol
 
 
-@pytest.mark.parametrize("kind", ["local", "smc"])
+@pytest.mark.parametrize("kind", ["local", "smc", "gibbs"])
 @pytest.mark.parametrize("wname", ["c1", "ragged"])
 def test_one_sweep_parity(C, orc, kind, wname):
     if wname == "c1":
@@ -145,7 +146,7 @@ def test_one_sweep_parity(C, orc, kind, wname):
                            6.0, 32, 25.0, 50.0, 32)
     flush("case", wname, kind)
     melt, pos, omega, sp, (k0, a, A) = _both_sides(C, orc, w, 42)
-    move = C.SOMA_MOVE_LOCAL if kind == "local" else C.SOMA_MOVE_SMC
+    move = {"local": C.SOMA_MOVE_LOCAL, "smc": C.SOMA_MOVE_SMC, "gibbs": C.SOMA_MOVE_GIBBS}[kind]
     melt.sweep(1, move)
     torch.cuda.synchronize()
     got = melt.pos.cpu().numpy()
@@ -156,7 +157,7 @@ def test_one_sweep_parity(C, orc, kind, wname):
     for s in sp:
         seg = pos[off:off + s.n_chains * s.n]
         acc, _ = orc.mc_sweep(seg, s, omega, w.grid, k0=k0, n_ref=w.n_ref,
-                              move_kind=0 if kind == "local" else 1,
+                              move_kind={"local": 0, "smc": 1, "gibbs": 3}[kind],
                               step=a if kind == "local" else A, seed=w.seed, sweep=0,
                               chain_base=chain_base, threads=8)
         acc_total += acc
@@ -187,7 +188,7 @@ def test_one_sweep_parity(C, orc, kind, wname):
         assert cells_differ == 0
     assert int((hist_gpu != hist_ref).sum()) <= 2 * cells_differ
     obs = melt.observables()
-    kidx = 0 if kind == "local" else 1
+    kidx = {"local": 0, "smc": 1, "gibbs": 3}[kind]
     assert obs.attempted[kidx] == moves
     assert abs(int(obs.accepted[kidx]) - int(acc_total)) <= allowed
     assert obs.counts_conserved == 1  # conservation of the init histogram

@@ -1,11 +1,12 @@
 """Statistical parity of the device sampler with what the model fixes.
 
 * ideal chain (chiN = kappaN = 0): Metropolis acceptance of local moves equals
-  the closed form; <b^2>, <Re^2>, <Rg^2> keep their Gaussian-chain values under
-  local and smart-MC moves (the walk starts in equilibrium);
+  the closed form, bond-Gibbs moves are all accepted; <b^2>, <Re^2>, <Rg^2>
+  keep their Gaussian-chain values under local, smart-MC and bond-Gibbs moves
+  (the walk starts in equilibrium);
 * 3-bead chain in a frozen random field: per-bead cell marginals and the joint
   of the two end beads match the exact Boltzmann distribution (chi-square,
-  fixed p-threshold 1e-4), for local and smart-MC moves;
+  fixed p-threshold 1e-4), for local, smart-MC and bond-Gibbs moves;
 * the 1024-chain melt after 100 SCMF cycles: <Re^2> and the acceptance rate of
   the device and of an independent oracle run agree within 4 sigma.
 """
@@ -31,7 +32,7 @@ def test_ideal_chain_acceptance_and_moments():
     w = synth.Workload("ideal", (48, 48, 48), (synth.SpeciesSpec(n_chains, n, 16),), RE, n,
                        0.0, 0.0, 32)
     k0 = float(constants(w)[0])
-    for kind in (C.SOMA_MOVE_LOCAL, C.SOMA_MOVE_SMC):
+    for kind in (C.SOMA_MOVE_LOCAL, C.SOMA_MOVE_SMC, C.SOMA_MOVE_GIBBS):
         m = Melt(device_config(w, seed=11 + kind))
         m.omega.zero_()                       # chiN = kappaN = 0: zero field
         m.sweep(20, kind)
@@ -43,6 +44,8 @@ def test_ideal_chain_acceptance_and_moments():
             sigma = math.sqrt(exp * (1 - exp) / obs.attempted[kind])
             flush("acceptance", rate, "closed form", exp)
             assert abs(rate - exp) < 6 * sigma + 1e-4   # moves within a sweep are correlated
+        if kind == C.SOMA_MOVE_GIBBS:   # the exact conditional law of the bonds: all accepted
+            assert obs.accepted[kind] == obs.attempted[kind] == 20 * n * n_chains
         re2_exp = 3 * (n - 1) / k0
         rg2_exp = (3 / k0) * (n * n - 1) / (6 * n)
         b2_exp = 3 / k0 * (n - 1)
@@ -54,7 +57,7 @@ def test_ideal_chain_acceptance_and_moments():
         m.close()
 
 
-@pytest.mark.parametrize("kind,step", [(0, 0.7), (1, 0.12)])
+@pytest.mark.parametrize("kind,step", [(0, 0.7), (1, 0.12), (3, 0.0)])
 def test_three_bead_boltzmann_on_device(kind, step):
     from paper_1711_03828_amd.melt import Melt
     L, n_chains = 4, 65536
