@@ -148,7 +148,7 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
        samples/s = n_chains * cycles/s / (2 tau_int), cycles/s from step 2.
     4. As context, the analytic bond-Gibbs proposal (each bead drawn from its
        law given its bonded neighbours, accepted on the field term alone) with
-       the learned sampler's sub-steps, measured the same way after the learned
+       the learned sampler's sub-steps, measured the same way after the plain
        run.
     """
     import torch
@@ -212,8 +212,11 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
                                     "loss_first": tl[0], "loss_last": tl[-1],
                                     "after_learned_cycles": equil_cycles}
     stride = 16                              # end-to-end vectors of every 16th chain
-    for name, kind, mult in (("learned", C.SOMA_MOVE_MIXED, 1), ("gibbs", C.SOMA_MOVE_GIBBS, 1),
-                             ("plain", C.SOMA_MOVE_LOCAL, plain_mult)):
+    # the bond-Gibbs run last: its stationary state differs most from the plain
+    # sampler's, and a run that starts away from its own state pays a transient
+    for name, kind, mult in (("learned", C.SOMA_MOVE_MIXED, 1),
+                             ("plain", C.SOMA_MOVE_LOCAL, plain_mult),
+                             ("gibbs", C.SOMA_MOVE_GIBBS, 1)):
         melt.set_substeps(ksub[name])
         melt.capture_cycle(frame_cycles * mult, kind)
         n_frames = sub_frames
