@@ -4,8 +4,9 @@ oracle.
 Bars: the kept histogram planes equal the oracle's recount bit for bit; the
 fields equal the oracle's FP32 order bit for bit (both interaction forms, 16-
 and 32-bit counts); H_nb within 1e-12; a sweep of an ABC triblock (three
-types, next to a linear AB diblock species) and of a four-type miktoarm star
-matches the oracle's sweep bit for bit per molecule, with at most 1e-6 of the
+types, next to a linear AB diblock species), of a four-type miktoarm star and
+of a chain cycling through all eight types (four count planes, an odd number
+of cells) matches the oracle's sweep bit for bit per molecule, with at most 1e-6 of the
 moves in molecules with an accept-decision mismatch (rounded up); per-type
 totals and the conservation flag hold; two types set this way equal the
 two-type path bit for bit; unsupported combinations are refused.
@@ -42,6 +43,14 @@ def _system(kind):
         bonds = [(i, i + 1) for i in range(n - 1)]
         return [(900, n, 0), (500, 32, 16)], synth.encode_architecture(n, types, bonds), \
             bonds, types, CHI3
+    if kind == "octa":   # eight types (four count planes), a linear 24-mer cycling through them
+        n = 24
+        types = [i % 8 for i in range(n)]
+        bonds = [(i, i + 1) for i in range(n - 1)]
+        chi = np.random.default_rng(8).uniform(0.0, 40.0, (8, 8)).astype(np.float32)
+        chi = np.triu(chi, 1) + np.triu(chi, 1).T
+        return [(1500, n, 0)], synth.encode_architecture(n, types, bonds), bonds, types, \
+            chi.tolist()
     n, bonds = synth.star_bonds(4, 6)   # core + four arms of six, arm k of type k
     types = [0] + [k for k in range(4) for _ in range(6)]
     return [(1200, n, 0)], synth.encode_architecture(n, types, bonds), bonds, types, CHI4
@@ -82,12 +91,12 @@ def _oracle_sweep(orc, pos, species, words, omega, grid, k0, sweep):
 
 
 @pytest.mark.parametrize("kind,width,form", [("abc", 16, 1), ("abc", 32, 0), ("mikto4", 16, 0),
-                                             ("mikto4", 32, 1)])
+                                             ("mikto4", 32, 1), ("octa", 32, 1), ("octa", 16, 0)])
 def test_types_sweep_and_fields_match_oracle(C, orc, kind, width, form):
     from paper_1711_03828_amd.melt import Melt
     species, words, bonds, types, chi = _system(kind)
     n_t = len(chi)
-    grid = (26, 22, 18)
+    grid = (23, 19, 13) if kind == "octa" else (26, 22, 18)   # octa: n_cells odd
     k0 = np.float32(2.0)
     pos = _positions(species, bonds, grid, k0)
     cfg = custom_config(grid, [Species(*s) for s in species], k0=k0, n_ref=32, chi_n=20.0,
