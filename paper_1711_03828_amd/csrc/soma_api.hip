@@ -230,10 +230,23 @@ int32_t launch_field(const soma_config *c, const Derived &d, void *counts, float
     m.kappa_n_d = (double)c->kappa_n;
     std::memcpy(m.chi, d.chi_m, sizeof m.chi);
     m.partials = partials;
-    if (c->count_width == 32)
-      hipLaunchKernelGGL(soma::field_multi_kernel<true>, dim3(blocks), dim3(256), 0, s, m);
-    else
-      hipLaunchKernelGGL(soma::field_multi_kernel<false>, dim3(blocks), dim3(256), 0, s, m);
+    const bool c64 = c->count_width == 32;
+    switch (d.n_types) {
+#define SOMA_MULTI_CASE(NT)                                                                       \
+  case NT:                                                                                        \
+    if (c64) hipLaunchKernelGGL((soma::field_multi_kernel<true, NT>), dim3(blocks), dim3(256), 0, s, m); \
+    else hipLaunchKernelGGL((soma::field_multi_kernel<false, NT>), dim3(blocks), dim3(256), 0, s, m);    \
+    break;
+      SOMA_MULTI_CASE(3)
+      SOMA_MULTI_CASE(4)
+      SOMA_MULTI_CASE(5)
+      SOMA_MULTI_CASE(6)
+      SOMA_MULTI_CASE(7)
+      SOMA_MULTI_CASE(8)
+#undef SOMA_MULTI_CASE
+      default:
+        return fail(SOMA_E_INVAL, "%u bead types", d.n_types);
+    }
     LAUNCH_TRY();
     return SOMA_OK;
   }

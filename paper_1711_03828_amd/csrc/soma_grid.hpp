@@ -311,60 +311,114 @@ __device__ __forceinline__ void load_types(const MultiFieldArgs &a, uint32_t c, 
   }
 }
 
-template <bool COUNT64>
+// Fields of one cell of NT types from its counts (the order stated above), and
+// its contribution to the count sums and H_nb.
+template <uint32_t NT>
+__device__ __forceinline__ void multi_cell(const MultiFieldArgs &a, const uint32_t (&n)[NT],
+                                           float (&w)[NT], bool stats,
+                                           unsigned long long &sum_a, unsigned long long &sum_b,
+                                           double &h) {
+  float phi[NT];
+#pragma unroll
+  for (uint32_t i = 0; i < NT; ++i) phi[i] = (float)n[i] * a.inv_rho;
+  float s = phi[0];
+#pragma unroll
+  for (uint32_t i = 1; i < NT; ++i) s = s + phi[i];
+  s = s - 1.0f;
+  const float t0 = a.kappa_n * s;
+#pragma unroll
+  for (uint32_t i = 0; i < NT; ++i) {
+    float t = t0;
+#pragma unroll
+    for (uint32_t k = 0; k < NT; ++k) {
+      if (k == i) continue;
+      const float x = a.chi[i * kMaxTypes + k];
+      t = a.form == 0 ? fmaf(-0.5f * x, phi[i] - phi[k], t) : fmaf(x, phi[k], t);
+    }
+    w[i] = t;
+  }
+  if (!stats) return;
+  double pd[NT], tot = 0.0, inter = 0.0;
+#pragma unroll
+  for (uint32_t i = 0; i < NT; ++i) {
+    pd[i] = (double)n[i] * a.inv_rho_d;
+    tot += pd[i];
+    if (i == 0) sum_a += n[i];
+    else sum_b += n[i];
+  }
+#pragma unroll
+  for (uint32_t i = 0; i < NT; ++i)
+#pragma unroll
+    for (uint32_t j = i + 1; j < NT; ++j) {
+      const double x = (double)a.chi[i * kMaxTypes + j], d = pd[i] - pd[j];
+      inter += a.form == 0 ? -0.25 * x * d * d : x * pd[i] * pd[j];
+    }
+  const double dev = tot - 1.0;
+  h += 0.5 * a.kappa_n_d * dev * dev + inter;
+}
+
+// One kernel per number of types NT (3..8; a.n_t == NT).  With n_cells % 4 == 0
+// every plane starts on a 16-byte boundary: for NT <= 4 a thread then takes
+// four consecutive cells per step (16-byte loads and stores per plane); more
+// types, or other grids, one cell per step (fewer registers).
+template <bool COUNT64, uint32_t NT>
 __global__ __launch_bounds__(256) void field_multi_kernel(const MultiFieldArgs a) {
+  constexpr uint32_t NP = (NT + 1u) / 2u;   // count planes
   __shared__ unsigned long long s_a[4], s_b[4];
   __shared__ double s_h[4];
-  const uint32_t n_t = a.n_t;
   const bool stats = a.partials != nullptr;
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
   unsigned long long sum_a = 0, sum_b = 0;
   double h = 0.0;
-  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < a.n_cells;
-       c += gridDim.x * blockDim.x) {
-    uint32_t n[kMaxTypes];
-    load_types<COUNT64>(a, c, n);
-    float phi[kMaxTypes];
+  if (NT <= 4u && (a.n_cells & 3u) == 0u) {
+    const uint32_t n4 = a.n_cells >> 2;
+    for (uint32_t q = tid; q < n4; q += stride) {
+      uint32_t n[4][NT];
 #pragma unroll
-    for (uint32_t i = 0; i < kMaxTypes; ++i) phi[i] = (float)n[i] * a.inv_rho;
-    float s = phi[0];
+      for (uint32_t p = 0; p < NP; ++p) {
+        uint32_t lo[4], hi[4];
+        if (COUNT64) {
+          ulonglong2 *c = reinterpret_cast<ulonglong2 *>(reinterpret_cast<unsigned long long *>(a.counts) +
+                                                         (size_t)p * a.n_cells) + 2 * (size_t)q;
+          const ulonglong2 v0 = c[0], v1 = c[1];
+          const unsigned long long wv[4] = {v0.x, v0.y, v1.x, v1.y};
 #pragma unroll
-    for (uint32_t i = 1; i < kMaxTypes; ++i)
-      if (i < n_t) s = s + phi[i];
-    s = s - 1.0f;
-    const float t0 = a.kappa_n * s;
+          for (int j = 0; j < 4; ++j) { lo[j] = (uint32_t)wv[j]; hi[j] = (uint32_t)(wv[j] >> 32); }
+          if (a.clear) { c[0] = make_ulonglong2(0ull, 0ull); c[1] = make_ulonglong2(0ull, 0ull); }
+        } else {
+          uint4 *c = reinterpret_cast<uint4 *>(reinterpret_cast<uint32_t *>(a.counts) +
+                                               (size_t)p * a.n_cells) + q;
+          const uint4 v = *c;
+          const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-    for (uint32_t i = 0; i < kMaxTypes; ++i) {
-      if (i < n_t) {
-        float t = t0;
-#pragma unroll
-        for (uint32_t k = 0; k < kMaxTypes; ++k) {
-          if (k < n_t && k != i) {
-            const float x = a.chi[i * kMaxTypes + k];
-            t = a.form == 0 ? fmaf(-0.5f * x, phi[i] - phi[k], t) : fmaf(x, phi[k], t);
-          }
+          for (int j = 0; j < 4; ++j) { lo[j] = wv[j] & 0xFFFFu; hi[j] = wv[j] >> 16; }
+          if (a.clear) *c = make_uint4(0u, 0u, 0u, 0u);
         }
-        a.omega[(size_t)i * a.n_cells + c] = t;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          n[j][2 * p] = lo[j];
+          if (2 * p + 1 < NT) n[j][2 * p + 1] = hi[j];
+        }
       }
+      float w[4][NT];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) multi_cell<NT>(a, n[j], w[j], stats, sum_a, sum_b, h);
+#pragma unroll
+      for (uint32_t i = 0; i < NT; ++i)
+        reinterpret_cast<float4 *>(a.omega + (size_t)i * a.n_cells)[q] =
+            make_float4(w[0][i], w[1][i], w[2][i], w[3][i]);
     }
-    if (stats) {
-      double pd[kMaxTypes], tot = 0.0, inter = 0.0;
+  } else {
+    for (uint32_t c = tid; c < a.n_cells; c += stride) {
+      uint32_t nn[kMaxTypes];
+      load_types<COUNT64>(a, c, nn);
+      uint32_t n[NT];
 #pragma unroll
-      for (uint32_t i = 0; i < kMaxTypes; ++i) {
-        pd[i] = i < n_t ? (double)n[i] * a.inv_rho_d : 0.0;
-        tot += pd[i];
-        if (i == 0) sum_a += n[i];
-        else if (i < n_t) sum_b += n[i];
-      }
+      for (uint32_t i = 0; i < NT; ++i) n[i] = nn[i];
+      float w[NT];
+      multi_cell<NT>(a, n, w, stats, sum_a, sum_b, h);
 #pragma unroll
-      for (uint32_t i = 0; i < kMaxTypes; ++i)
-#pragma unroll
-        for (uint32_t j = i + 1; j < kMaxTypes; ++j)
-          if (j < n_t) {
-            const double x = (double)a.chi[i * kMaxTypes + j], d = pd[i] - pd[j];
-            inter += a.form == 0 ? -0.25 * x * d * d : x * pd[i] * pd[j];
-          }
-      const double dev = tot - 1.0;
-      h += 0.5 * a.kappa_n_d * dev * dev + inter;
+      for (uint32_t i = 0; i < NT; ++i) a.omega[(size_t)i * a.n_cells + c] = w[i];
     }
   }
   if (!stats) return;
