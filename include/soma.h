@@ -218,8 +218,11 @@ int32_t soma_set_hamiltonian(soma_system *sys, uint32_t form, void *stream);
  * type by a substrate.  forbid (device, caller-owned, ceil(n_cells/32) words,
  * or NULL): bit c % 32 of word c / 32 marks cell c impenetrable; every move
  * whose trial position lies in an impenetrable cell other than the bead's own
- * is rejected (geometric confinement, e.g. the walls of a film; trial steps
- * below one cell cannot cross a wall plane).  Impenetrable cells get the field
+ * is rejected (geometric confinement, e.g. the walls of a film), and so is
+ * every trial more than one cell away along any axis (floor(x') - floor(x)
+ * outside {-1, 0, 1} on the unwrapped coordinates), so that no smart-MC,
+ * bond-Gibbs or learned step jumps over a wall plane; the condition is
+ * symmetric in (x, x'), so detailed balance holds.  Impenetrable cells get the field
  * 0 and are left out of H_nb, and the reference density counts free cells
  * only.  Positions must start outside impenetrable cells (not checked).  The
  * fields are recomputed from the current counts before the call returns.

@@ -414,6 +414,16 @@ def mlp_forward(params: np.ndarray, features: np.ndarray, bf16_mode=False):
     return z
 
 
+def nll(z, dr, *, m_max, lo, hi):
+    """(NLL of one displacement dr [3] under the head of z [6], dL/dz [6])."""
+    L = _lib_mlp()
+    z = _c(z, np.float64).reshape(NO)
+    dr = _c(dr, np.float64).reshape(3)
+    dz = np.empty(NO)
+    loss = L.orc_nll(_ptr(z), _ptr(dr), m_max, lo, hi, _ptr(dz))
+    return loss, dz
+
+
 def nll_batch(params, features, targets, *, m_max, lo, hi, bf16_mode=False):
     """(mean NLL, gradient [P], z [n, 6])."""
     L = _lib_mlp()

@@ -406,13 +406,19 @@ static void orc_force(const float *r, const float *chain, uint32_t i,
 /* ------------------------------------------------------------------------- */
 /* Impenetrable cells for the moves (Sec. 4, geometric confinement): a trial
  * position in a set cell other than the bead's own cell is rejected (an
- * infinite energy).  NULL: none.  Set by orc_set_forbidden before a sweep;
- * read-only during it. */
+ * infinite energy).  With impenetrable cells set, a trial more than one cell
+ * away from the bead along any axis is rejected as well, so that no move can
+ * jump over a wall of impenetrable cells: floor(x') - floor(x) must lie in
+ * {-1, 0, 1} per axis on the unwrapped coordinates.  The condition is
+ * symmetric in (x, x'), so detailed balance holds for the restricted move.
+ * NULL: none.  Set by orc_set_forbidden before a sweep; read-only during it. */
 static const uint32_t *orc_forbidden = NULL;
 void orc_set_forbidden(const uint32_t *mask) { orc_forbidden = mask; }
 static int orc_blocked(const float *r, const float *trial, uint32_t nx, uint32_t ny,
                        uint32_t nz) {
   if (!orc_forbidden) return 0;
+  for (int d = 0; d < 3; ++d)
+    if (fabs(floor((double)trial[d]) - floor((double)r[d])) > 1.0) return 1;
   uint64_t to = orc_cell(trial, nx, ny, nz);
   return to != orc_cell(r, nx, ny, nz) && orc_bit(orc_forbidden, to);
 }

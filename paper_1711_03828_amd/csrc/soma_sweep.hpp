@@ -61,6 +61,17 @@ __device__ __forceinline__ bool move_allowed(const SweepArgs &a, uint32_t from, 
   return a.forbid == nullptr || to == from || ((a.forbid[to >> 5] >> (to & 31u)) & 1u) == 0u;
 }
 
+// With impenetrable cells set, a trial more than one cell away from the bead
+// along any axis is rejected as well (floor(x') - floor(x) outside {-1, 0, 1}
+// on the unwrapped coordinates), so that no move can jump over a wall.  The
+// condition is symmetric in (r, r'): detailed balance holds for the
+// restricted move.  Local moves (half-width below one cell) always pass.
+__device__ __forceinline__ bool step_allowed(const SweepArgs &a, F3 r, F3 rn) {
+  return a.forbid == nullptr ||
+         (fabsf(floorf(rn.x) - floorf(r.x)) <= 1.0f && fabsf(floorf(rn.y) - floorf(r.y)) <= 1.0f &&
+          fabsf(floorf(rn.z) - floorf(r.z)) <= 1.0f);
+}
+
 // Arguments with the Philox sweep word resolved: the system's device counter
 // plus the launch's offset, so that a launch recorded once (a captured graph)
 // still draws fresh numbers on every replay.
@@ -446,7 +457,7 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
       const float w_old = odd ? f1 : f0;
       const float w_new = cn == co ? w_old : field_at(a.omega, pl, cn);
       const float d_e = (w_new - w_old) * a.inv_nref;
-      acc = move_allowed(a, co, cn) && (d_e <= 0.0f || u < __expf(-d_e));
+      acc = move_allowed(a, co, cn) && step_allowed(a, r, rn) && (d_e <= 0.0f || u < __expf(-d_e));
     } else if (moving) {
       co = odd ? co1 : co0;
       const F3 el = {r.x - left.x, r.y - left.y, r.z - left.z};
@@ -471,7 +482,7 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
       F3 g_new = g_old;
       float w_new = w_old;
       if (cn != co) w_new = field_and_grad(a, pl, cn, nx_, ny_, nz_, g_new);
-      const bool ok = move_allowed(a, co, cn);
+      const bool ok = move_allowed(a, co, cn) && step_allowed(a, r, rn);
       const F3 d = {rn.x - r.x, rn.y - r.y, rn.z - r.z};
       const F3 nl = {rn.x - left.x, rn.y - left.y, rn.z - left.z};
       const F3 nr = {rn.x - right.x, rn.y - right.y, rn.z - right.z};
@@ -642,7 +653,7 @@ __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx
     } else {
       acc = moving && (d_e <= 0.0f || uniform01(w.w) < __expf(-d_e));
     }
-    acc = acc && move_allowed(a, co, cn);
+    acc = acc && move_allowed(a, co, cn) && step_allowed(a, r, rn);
     net_bad_any |= net_bad;
     if (odd) { r1 = acc ? rn : r1; moved1 = acc && cn != co; from1 = co; to1 = cn; }
     else     { r0 = acc ? rn : r0; moved0 = acc && cn != co; from0 = co; to0 = cn; }

@@ -9,7 +9,10 @@ added to the interaction field, and impenetrable cells.
 * moves: with impenetrable planes, no bead starting outside them ever enters
   them (local, smart-MC and molecule-order moves), and the 3-bead chain in a
   frozen random field samples the exact Boltzmann distribution restricted to
-  the free cells (the unrestricted distribution is rejected).
+  the free cells (the unrestricted distribution is rejected);
+* no smart-MC, bond-Gibbs or learned step jumps over a wall of one cell plane
+  (with walls set, trials more than one cell away along an axis are rejected),
+  while the same moves without walls do make such steps.
 """
 import math
 
@@ -17,7 +20,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import MOVE_LOCAL, MOVE_SMC, Species, references
+from oracle import MOVE_GIBBS, MOVE_LOCAL, MOVE_SMC, Species, references
 
 
 def test_field_closed_values_with_external_term(orc):
@@ -132,3 +135,54 @@ def test_three_bead_boltzmann_with_walls(orc, order, step):
     obs1 = np.bincount(lin[:, 1], minlength=L ** 3)
     pval, _, _ = references.chi2_pvalue(obs1[~walls], m_free[~walls])
     assert pval < 1e-6
+
+
+def _big_step_params():
+    """Network weights whose proposal width is about 1.6 cells (log sigma near
+    0.46 with the head used below): far enough to jump a one-plane wall."""
+    params = synth.mlp_params(9, out_gain=0.1)
+    b3 = synth.MLP_LAYOUT["b3"]
+    params[b3 + 3:b3 + 6] = 3.0
+    return params
+
+
+WIDE_HEAD = dict(m_max=1.0, lo=math.log(0.02), hi=math.log(2.0))
+
+
+def _sweep_kind(orc, kind, pos, sp, omega, grid, sweep, mask):
+    if kind == "mixed":
+        orc.mc_sweep_mixed(pos, sp, omega, grid, k0=0.5, n_ref=16, local_a=0.5, p_learn=1.0,
+                           params=_big_step_params(), **WIDE_HEAD, seed=4, sweep=sweep,
+                           forbid=mask, threads=4)
+    else:
+        orc.mc_sweep(pos, sp, omega, grid, k0=0.5, n_ref=16,
+                     move_kind=MOVE_SMC if kind == "smc" else MOVE_GIBBS, step=0.5, seed=4,
+                     sweep=sweep, forbid=mask, threads=4)
+
+
+@pytest.mark.parametrize("kind", ["smc", "gibbs", "mixed"])
+def test_no_move_jumps_a_wall(orc, kind):
+    """Smart-MC (A = 0.5), bond-Gibbs (k0 = 0.5: width 1 cell) and learned moves
+    (width about 1.6 cells) next to a wall of a single cell plane (z = 0, nz = 6,
+    periodic): with the walls set, no trial more than one cell away along an axis
+    is taken, so every unwrapped z stays inside the free slab [1, 6).  Without
+    the walls the same moves do make such steps (the test has power)."""
+    grid = (10, 10, 6)
+    n, n_chains = 8, 300
+    walls = synth.wall_cells(grid, [0])
+    mask = synth.pack_mask(walls)
+    omega = synth.uniform_field(6, 10 * 10 * 6, -1, 1)
+    sp = Species(n_chains, n, 4)
+    pos = synth.film_walks(8, n_chains, n, grid, 0.5, 1.0, 6.0)
+    assert ((pos[:, 2] >= 1.0) & (pos[:, 2] < 6.0)).all()
+    for sweep in range(20):
+        _sweep_kind(orc, kind, pos, sp, omega, grid, sweep, mask)
+        z = pos[:, 2].astype(np.float64)
+        assert ((z >= 1.0) & (z < 6.0)).all(), sweep
+    free = pos.copy()
+    jumps = 0
+    for sweep in range(5):
+        before = np.floor(free.astype(np.float64))
+        _sweep_kind(orc, kind, free, sp, omega, grid, sweep, None)
+        jumps += int((np.abs(np.floor(free.astype(np.float64)) - before) > 1).any(axis=1).sum())
+    assert jumps > 0

@@ -6,7 +6,11 @@
 * fields: closed values for an empty cell, a pure cell and a balanced cell,
   and omega = N * dH_nb/dn, i.e. the field is the derivative of the grid
   Hamiltonian of Eqs. (5), (6), (8) (a central difference, exact for a
-  quadratic), which ties two independently written oracle functions together.
+  quadratic), which ties two independently written oracle functions together;
+* field energy of the beads (Eq. (13) divided by N): a hand-worked case (cells
+  worked out by hand, including wrapped coordinates; the other field plane and
+  another type boundary give other values), constant fields (n_A alpha +
+  n_B beta)/N, and agreement with the histogram times the field.
 """
 import numpy as np
 import pytest
@@ -146,3 +150,57 @@ def test_k0_field_is_derivative_of_grid_hamiltonian(orc):
     h0 = orc.h_nb(counts, inv_rho, chi, kappa, n_ref, form=0)
     tot = (counts.sum(axis=0) * inv_rho) ** 2
     assert h0 - h1 == pytest.approx(-chi / 4 * tot.sum() / (inv_rho * n_ref), rel=1e-9)
+
+
+# ----------------------------------------------------------------------------
+# Field energy of the beads in their cells (the right-hand side of Eq. (13)
+# divided by N): closed values.
+# ----------------------------------------------------------------------------
+def test_field_energy_hand_worked(orc):
+    """Six beads in hand-computed cells of a 4 x 3 x 2 grid (x fastest), fields
+    omega_A(c) = c + 1/2 and omega_B(c) = 100 + 2c, species A2B1 (types A A B),
+    reference N = 4.  Cells, worked by hand (floor, then periodic wrap):
+      chain 0: ( 0.5,  0.5,  0.5) -> (0,0,0) = 0,  A:   0.5
+               ( 1.5,  2.5,  0.5) -> (1,2,0) = 9,  A:   9.5
+               (-0.5,  0.5,  1.5) -> (3,0,1) = 15, B: 130
+      chain 1: (4.25,  3.5,  2.5) -> (0,0,0) = 0,  A:   0.5
+               (3.75, -0.25,-0.75) -> (3,2,1) = 23, A:  23.5
+               ( 2.0,  1.0,  1.0) -> (2,1,1) = 18, B: 136
+    sum 300, energy 300 / 4 = 75."""
+    grid = (4, 3, 2)
+    c = np.arange(24, dtype=np.float32)
+    omega = np.stack([c + 0.5, 100 + 2 * c]).astype(np.float32)
+    pos = np.array([[0.5, 0.5, 0.5], [1.5, 2.5, 0.5], [-0.5, 0.5, 1.5],
+                    [4.25, 3.5, 2.5], [3.75, -0.25, -0.75], [2.0, 1.0, 1.0]], np.float32)
+    assert orc.field_energy(pos, Species(2, 3, 2), omega, grid, 4) == 75.0
+    # the other plane for every bead: A beads read 100 + 2c, B beads c + 1/2,
+    # (100 + 118 + 15.5 + 100 + 146 + 18.5) / 4
+    swapped = omega[::-1].copy()
+    assert orc.field_energy(pos, Species(2, 3, 2), swapped, grid, 4) == pytest.approx(498.0 / 4)
+    # all beads of type A (n_a = 3): the third beads read omega_A (15.5 and 18.5)
+    assert orc.field_energy(pos, Species(2, 3, 3), omega, grid, 4) == pytest.approx(
+        (0.5 + 9.5 + 15.5 + 0.5 + 23.5 + 18.5) / 4)
+
+
+def test_field_energy_constant_fields(orc):
+    """Constant fields omega_A = alpha, omega_B = beta: the energy is
+    (n_A alpha + n_B beta) / N whatever the positions."""
+    grid = (7, 5, 6)
+    n_cells = 7 * 5 * 6
+    sp = Species(37, 32, 11)
+    pos = synth.gaussian_walks(12, 37, 32, grid, 1.1)
+    omega = np.stack([np.full(n_cells, 1.25), np.full(n_cells, -3.5)]).astype(np.float32)
+    e = orc.field_energy(pos, sp, omega, grid, 32)
+    assert e == pytest.approx(37 * (11 * 1.25 + 21 * -3.5) / 32, rel=1e-14)
+
+
+def test_field_energy_equals_counts_times_field(orc):
+    """The sum over beads equals sum_c sum_t n_t(c) omega_t(c) / N with the
+    (independently pinned) histogram of the same positions."""
+    grid = (9, 8, 7)
+    sp = Species(50, 17, 6)
+    pos = synth.gaussian_walks(13, 50, 17, grid, 1.3)
+    omega = synth.uniform_field(14, 9 * 8 * 7, -3.0, 3.0)
+    counts = orc.density_hist(pos, [sp], grid).astype(np.float64)
+    exp = float((counts * omega.astype(np.float64)).sum()) / 17
+    assert orc.field_energy(pos, sp, omega, grid, 17) == pytest.approx(exp, rel=1e-12)

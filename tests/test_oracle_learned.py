@@ -2,6 +2,10 @@
 
 * back-propagation equals central finite differences of the FP64 loss
   (relative error < 1e-6 on every parameter group);
+* the loss itself: closed values at the head's mean (sum of log sigma, plus 1/2
+  one sigma away), equality with scipy's normal log-density, the mean over
+  targets drawn from the head's Gaussian (sum log sigma + 3/2), and dL/dz
+  against finite differences of the loss;
 * bfloat16 rounding equals the library converter (torch, round to nearest even);
 * BF16-emulating forward stays close to FP64 (rounding only);
 * features: hand-checked own/other field blocks, cell order and bond vectors;
@@ -138,3 +142,71 @@ def test_mixed_move_is_exact_with_random_weights(orc, p_learn):
     obs = np.bincount(lin[:, 0] * 64 + lin[:, 2], minlength=4096)
     pval, stat, dof = references.chi2_pvalue(obs, p.sum(axis=1).ravel())
     assert pval > 1e-4, (stat, dof)
+
+
+# ----------------------------------------------------------------------------
+# The loss itself (Gaussian negative log-likelihood without its constant), pinned
+# by closed values and by the normal density of scipy, independently of the
+# finite-difference check above (which ties only the gradient to the loss).
+# ----------------------------------------------------------------------------
+def test_nll_closed_value_at_the_mean(orc):
+    lo, hi = HEAD["lo"], HEAD["hi"]
+    # z = 0: mu = 0, sigmoid = 1/2, log sigma = (lo + hi)/2 on every axis; dr = mu
+    loss, dz = orc.nll(np.zeros(6), np.zeros(3), **HEAD)
+    assert loss == pytest.approx(3 * 0.5 * (lo + hi), rel=1e-14)
+    # dL/dmu = 0 at the mean; dL/dlog sigma = 1, times d log sigma/dz = (hi - lo)/4
+    np.testing.assert_allclose(dz[:3], 0.0, atol=1e-15)
+    np.testing.assert_allclose(dz[3:], (hi - lo) * 0.25, rtol=1e-14)
+    # any z, dr = mu(z): the loss is the sum of log sigma
+    z = np.array([0.3, -1.7, 0.05, 2.0, -0.4, 0.9])
+    mu = np.tanh(z[:3])                                   # m_max = 1
+    lsig = lo + (hi - lo) / (1 + np.exp(-z[3:]))
+    loss, dz = orc.nll(z, mu, **HEAD)
+    assert loss == pytest.approx(lsig.sum(), rel=1e-13)
+    np.testing.assert_allclose(dz[:3], 0.0, atol=1e-15)
+    # one sigma away on the first axis: + 1/2
+    dr = mu.copy()
+    dr[0] += np.exp(lsig[0])
+    loss1, _ = orc.nll(z, dr, **HEAD)
+    assert loss1 == pytest.approx(lsig.sum() + 0.5, rel=1e-13)
+
+
+def test_nll_equals_normal_log_density(orc):
+    from scipy.stats import norm
+    g = np.random.default_rng(17)
+    for _ in range(50):
+        z = g.standard_normal(6) * 2.0
+        dr = g.standard_normal(3) * 0.7
+        mu = HEAD["m_max"] * np.tanh(z[:3] / HEAD["m_max"])
+        sig = np.exp(HEAD["lo"] + (HEAD["hi"] - HEAD["lo"]) / (1 + np.exp(-z[3:])))
+        exp = -norm.logpdf(dr, loc=mu, scale=sig).sum() - 1.5 * math.log(2 * math.pi)
+        loss, _ = orc.nll(z, dr, **HEAD)
+        assert loss == pytest.approx(exp, rel=1e-12, abs=1e-12)
+
+
+def test_nll_mean_over_gaussian_targets(orc):
+    """Targets drawn from the head's own Gaussian: E[loss] = sum log sigma + 3/2
+    (each axis contributes log sigma + E[xi^2]/2)."""
+    g = np.random.default_rng(23)
+    z = np.array([0.4, -0.2, 1.1, -0.5, 0.7, 0.0])
+    mu = np.tanh(z[:3])
+    lsig = HEAD["lo"] + (HEAD["hi"] - HEAD["lo"]) / (1 + np.exp(-z[3:]))
+    n = 20000
+    dr = mu + np.exp(lsig) * g.standard_normal((n, 3))
+    losses = np.array([orc.nll(z, d, **HEAD)[0] for d in dr])
+    se = losses.std() / math.sqrt(n)
+    assert abs(losses.mean() - (lsig.sum() + 1.5)) < 4 * se
+
+
+def test_nll_gradient_in_z_matches_finite_differences(orc):
+    g = np.random.default_rng(29)
+    for _ in range(20):
+        z = g.standard_normal(6)
+        dr = g.standard_normal(3) * 0.5
+        _, dz = orc.nll(z, dr, **HEAD)
+        for k in range(6):
+            h = 1e-6
+            zp = z.copy(); zp[k] += h
+            zm = z.copy(); zm[k] -= h
+            fd = (orc.nll(zp, dr, **HEAD)[0] - orc.nll(zm, dr, **HEAD)[0]) / (2 * h)
+            assert fd == pytest.approx(dz[k], rel=1e-6, abs=1e-8)
