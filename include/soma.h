@@ -367,7 +367,8 @@ int32_t soma_capture_cycle(soma_system *sys, uint32_t cycles, uint32_t move_kind
 int32_t soma_run_cycle(soma_system *sys, uint32_t n_launches, void *stream);
 
 /* ---- Autotuning ----------------------------------------------------------
- * Times candidate launch shapes over real SCMF cycles and keeps the fastest.
+ * Times candidate launch shapes over real SCMF cycles and keeps the fastest,
+ * as the run-time tuner of Sec. 3.2.2 does for every critical parallel loop.
  * Launch shapes never change results, so the trajectory is bit-identical to
  * running the same number of cycles untuned: each candidate runs 1 + cycles
  * SCMF cycles of move_kind (out->cycles_run in total; the sweep index and the
@@ -390,7 +391,7 @@ int32_t soma_autotune(soma_system *sys, uint32_t cycles, uint32_t move_kind,
  * Several systems (replicas of different sizes, chain lengths, interaction
  * parameters; each created by soma_init_system with its own buffers) swept by
  * one kernel launch per sweep and refreshed by one launch per field update,
- * so that small systems together fill the GPU (Sec. 4).  Chain tiles of all
+ * so that small systems together fill the GPU (Secs. 5.1-5.2).  Chain tiles of all
  * systems form one work list, largest system first, cut into one contiguous
  * range per XCD.  Every bead draws the Philox numbers of its own system, so a
  * batched sweep equals the unbatched sweeps of the systems bit for bit.

@@ -1,7 +1,7 @@
 // soma_batch.hpp -- one sweep launch over many melts (replicas of different
 // size, chain length and interaction strength).
 //
-// Small melts alone cannot fill 256 compute units (Sec. 4: small systems
+// Small melts alone cannot fill 256 compute units (Secs. 5.1-5.2: small systems
 // leave the GPU idle), so the chain tiles of all melts of a batch form one
 // work list.  An item is one block's worth of chains (four wave tiles) of one
 // (melt, species) segment; segments are listed largest first and the list is

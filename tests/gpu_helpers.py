@@ -74,3 +74,47 @@ def unpack_counts(c: np.ndarray, width: int) -> np.ndarray:
         return np.stack([u & 0xFFFF, u >> 16]).astype(np.uint32)
     u = c.view(np.uint64)
     return np.stack([u & 0xFFFFFFFF, u >> 32]).astype(np.uint32)
+
+
+def stepwise_cycles(melt, orc, sp, grid, n_cycles, oracle_sweep, field_of, *, n_per_chain,
+                    tol=0.0):
+    """SCMF cycles checked one by one from the device's own state.
+
+    Before each cycle the device's positions, histogram and fields are read;
+    the histogram must equal the oracle's count of those positions and the
+    fields the oracle's fields of that histogram (bit for bit).  The device
+    then runs one cycle and the oracle one sweep from the same positions and
+    fields (``oracle_sweep(pos, omega, cycle)``, in place).  Per cycle the
+    chains whose positions differ by more than ``tol`` must number at most
+    ceil(1e-6 x moves), and the histogram the device kept must equal the
+    oracle's count of the device's new positions.  Every cycle is compared in
+    full, whether or not an earlier one had a mismatch.  Returns the number of
+    mismatched chains per cycle."""
+    import torch
+    n_beads = sum(s.n_chains * s.n for s in sp)
+    allowed = math.ceil(1e-6 * n_beads)
+    per_cycle = []
+    for cyc in range(n_cycles):
+        torch.cuda.synchronize()
+        pos = melt.pos.cpu().numpy()
+        omega = melt.omega.cpu().numpy()
+        counts = orc.density_hist(pos, sp, grid)
+        np.testing.assert_array_equal(melt.counts_planes(), counts)
+        np.testing.assert_array_equal(omega, field_of(counts))
+        melt.cycle(1)
+        ref = pos.copy()
+        oracle_sweep(ref, omega, cyc)
+        torch.cuda.synchronize()
+        got = melt.pos.cpu().numpy()
+        bad = int((np.abs(got.astype(np.float64) - ref.astype(np.float64)).reshape(-1, n_per_chain * 3)
+                   .max(axis=1) > tol).sum())
+        per_cycle.append(bad)
+        assert bad <= allowed, (cyc, bad, allowed)
+        np.testing.assert_array_equal(melt.counts_planes(), orc.density_hist(got, sp, grid))
+        if bad == 0 and tol == 0.0:
+            np.testing.assert_array_equal(melt.counts_planes(), orc.density_hist(ref, sp, grid))
+    torch.cuda.synchronize()
+    pos = melt.pos.cpu().numpy()
+    np.testing.assert_array_equal(melt.omega.cpu().numpy(), field_of(orc.density_hist(pos, sp, grid)))
+    flush("mismatched chains per cycle:", per_cycle, "allowed per cycle:", allowed)
+    return per_cycle

@@ -16,7 +16,8 @@ import pytest
 
 import synth
 from oracle import Species, references
-from tests.gpu_helpers import constants, custom_config, device_config, flush, walks_for
+from tests.gpu_helpers import (constants, custom_config, device_config, flush, stepwise_cycles,
+                               walks_for)
 
 torch = pytest.importorskip("torch")
 pytestmark = [pytest.mark.gpu,
@@ -92,21 +93,21 @@ def test_one_sweep_parity(C, orc, wname):
 
 
 def test_cycles_parity_c1(C, orc):
+    """Eight SCMF cycles in the molecule-parallel order, each compared in full
+    from the device's own state (histogram and fields bit-exact, positions
+    bit-identical per chain up to ceil(1e-6 x moves) threshold mismatches)."""
     w = synth.C1_SMALL
     melt, pos, omega, sp, (k0, a) = _melt(C, orc, w, 62)
     inv_rho = constants(w)[3]
-    for cyc in range(8):
-        melt.cycle(1)
-        orc.mc_sweep_molecule(pos, sp[0], omega, w.grid, k0=k0, n_ref=w.n_ref, step=a,
+
+    def sweep(p, om, cyc):
+        orc.mc_sweep_molecule(p, sp[0], om, w.grid, k0=k0, n_ref=w.n_ref, step=a,
                               seed=w.seed, sweep=cyc, threads=8)
-        omega = orc.field_f32(orc.density_hist(pos, sp, w.grid), inv_rho, np.float32(w.chi_n),
-                              np.float32(w.kappa_n))
-    torch.cuda.synchronize()
-    bad = _bad_chains(melt.pos.cpu().numpy(), pos, 32)
-    flush("chains differing after 8 cycles:", int(bad.sum()))
-    assert bad.sum() <= 8
-    if bad.sum() == 0:
-        np.testing.assert_array_equal(melt.omega.cpu().numpy(), omega)
+
+    def field_of(counts):
+        return orc.field_f32(counts, inv_rho, np.float32(w.chi_n), np.float32(w.kappa_n))
+
+    stepwise_cycles(melt, orc, sp, w.grid, 8, sweep, field_of, n_per_chain=32)
     melt.close()
 
 
