@@ -297,3 +297,71 @@ def c5_replicas(n_rep: int = 32, master: int = MASTER_SEED, scale: float = 1.0):
         out.append(Workload(f"c5_r{r}", (side, side, side), sp, 6.0, 32, chi, 50.0, 16,
                             seed=splitmix64(master + 1000 + r)))
     return out
+
+
+# ----------------------------------------------------------------------------
+# Statistical parity of observables: protocols run by both sides with their
+# own seeds (the two samples are independent), compared at equal cycles.
+# ----------------------------------------------------------------------------
+# A melt at the bead density of the 256k-chain study (256/27 per cell):
+# 256 A16B16 chains on 12 x 9 x 8 cells, chiN 25, kappaN 50.
+C4_DENSITY_SUB = Workload("diblock_256_N32_grid12x9x8", (12, 9, 8),
+                          (SpeciesSpec(256, 32, 16),), 6.0, 32, 25.0, 50.0, 16, sweeps=100)
+
+
+@dataclass(frozen=True)
+class ObsProtocol:
+    """Init from the seed (Philox init, stratified origins), `cycles` SCMF
+    cycles of `move`; samples of Re^2 and Rg^2 after cycles first, first +
+    every, ..., cycles; acceptance over cycles first+1 .. cycles; S(q) shells
+    after the last cycle."""
+    name: str
+    workload: Workload
+    move: str            # "local", "smc", "gibbs" or "learned" (p_learn = 1)
+    cycles: int
+    first: int
+    every: int
+    n_shells: int = 8
+
+
+OBS_PROTOCOLS = (
+    ObsProtocol("c1_local", C1_SMALL, "local", 300, 100, 10),
+    ObsProtocol("c1_smc", C1_SMALL, "smc", 300, 100, 10),
+    ObsProtocol("c1_gibbs", C1_SMALL, "gibbs", 300, 100, 10),
+    ObsProtocol("c4dens_local", C4_DENSITY_SUB, "local", 100, 40, 5),
+    ObsProtocol("c4dens_learned", C4_DENSITY_SUB, "learned", 100, 40, 5),
+)
+OBS_SEEDS_ORACLE = tuple(1001 + i for i in range(12))
+OBS_SEEDS_DEVICE = tuple(2001 + i for i in range(12))
+
+
+def designed_net_params(seed: int = 1, c: float = 0.1, sigma_bias: float = 0.36,
+                        noise: float = 0.01) -> np.ndarray:
+    """Network weights (interface layout) for a proposal that drifts a bead by
+    about c (b_prev + b_next) -- towards its bonded neighbours: ReLU pairs carry
+    the six bond features through both hidden layers; every other weight is
+    small noise, so the fields still enter.  The log-sigma outputs get the bias
+    sigma_bias (0.36: a width of about 0.2 cells with log-sigma bounds
+    log 0.02 .. 0)."""
+    L = MLP_LAYOUT
+    g = rng(seed)
+    p = np.zeros(L["size"], np.float32)
+    p[L["scale"]:L["scale"] + 60] = 1.0
+    w1 = g.standard_normal((64, 60)) * noise
+    for j in range(6):
+        w1[j, 54 + j] = 1.0
+        w1[6 + j, 54 + j] = -1.0
+    w2 = g.standard_normal((64, 64)) * noise
+    for u in range(12):
+        w2[u, u] = 1.0
+    w3 = g.standard_normal((6, 64)) * noise
+    for d in range(3):
+        w3[d, d] += c
+        w3[d, 6 + d] -= c
+        w3[d, 3 + d] += c
+        w3[d, 9 + d] -= c
+    p[L["w1"]:L["w1"] + 3840] = w1.ravel()
+    p[L["w2"]:L["w2"] + 4096] = w2.ravel()
+    p[L["w3"]:L["w3"] + 384] = w3.ravel()
+    p[L["b3"] + 3:L["b3"] + 6] = sigma_bias
+    return p
