@@ -385,7 +385,15 @@ def _lib_mlp():
     L.orc_features_batch.argtypes = [P, u32, u32, u32, P, P, u32, u32, u32, P]
     L.orc_mc_sweep_mixed.argtypes = [P, u32, u32, u32, f32, u32, P, u32, u32, u32, f32, f32,
                                      P, f32, f32, f32, i32, u64, u32, u32, u32, u32, P, P, P,
-                                     P, i32]
+                                     P, P, P, i32]
+    L.orc_bf16_boundary.argtypes = [f64, P]
+    L.orc_bf16_boundary.restype = f64
+    L.orc_set_envelope.argtypes = [f64]
+    L.orc_set_acc_f32.argtypes = [i32]
+    L.orc_nll_batch_envelope.argtypes = [P, u64, P, P, f64, f64, f64, P, P, P, P]
+    L.orc_nll_batch_envelope.restype = f64
+    L.orc_mlp_forward_envelope.argtypes = [P, u64, P, P, P]
+    L.orc_mlp_forward_envelope.restype = u64
     L.orc_mc_sweep_mixed.restype = u64
     L._mlp_ready = True
     return L
@@ -437,6 +445,71 @@ def nll_batch(params, features, targets, *, m_max, lo, hi, bf16_mode=False):
     return loss, grad, z
 
 
+def bf16_boundary(v: float):
+    """(distance of v from the nearest BF16 rounding boundary, the BF16 value
+    on the other side of it)."""
+    other = ctypes.c_double()
+    d = _lib_mlp().orc_bf16_boundary(float(v), ctypes.byref(other))
+    return d, other.value
+
+
+class fp32_sums:
+    """Context manager: the BF16 forward sums in FP32 in index order (another
+    order of FP32 additions a device may take) instead of FP64."""
+
+    def __enter__(self):
+        _lib_mlp().orc_set_acc_f32(1)
+
+    def __exit__(self, *exc):
+        _lib_mlp().orc_set_acc_f32(0)
+
+
+class envelope_scale:
+    """Context manager scaling the rounding windows of the envelope."""
+
+    def __init__(self, scale):
+        self.scale = float(scale)
+
+    def __enter__(self):
+        _lib_mlp().orc_set_envelope(self.scale)
+
+    def __exit__(self, *exc):
+        _lib_mlp().orc_set_envelope(1.0)
+
+
+def mlp_forward_envelope(params, features):
+    """(z [n, 6] with the device's rounding points, bound [n, 6], ambiguous
+    roundings): the device's outputs satisfy |z_dev - z| <= bound where every
+    FP32 sum of the device lies within the error bound of its terms."""
+    L = _lib_mlp()
+    params = _c(params, np.float32)
+    f = _c(features, np.float64).reshape(-1, NF)
+    z = np.empty((f.shape[0], NO))
+    bound = np.empty((f.shape[0], NO))
+    na = L.orc_mlp_forward_envelope(_ptr(params), f.shape[0], _ptr(f), _ptr(z), _ptr(bound))
+    return z, bound, int(na)
+
+
+def nll_batch_envelope(params, features, targets, *, m_max, lo, hi):
+    """Training gradient with the device's rounding points and its envelope:
+    (mean loss, gradient [P], bound [P], ambiguous roundings, samples with
+    one).  The device's gradient g satisfies |g - gradient| <= bound where
+    every sum of the device lies within the FP32 error bound of its terms."""
+    L = _lib_mlp()
+    params = _c(params, np.float32)
+    f = _c(features, np.float64).reshape(-1, NF)
+    t = _c(targets, np.float64).reshape(-1, 3)
+    size = param_layout()["size"]
+    grad = np.zeros(size)
+    bound = np.zeros(size)
+    n_amb = ctypes.c_uint64()
+    n_flag = ctypes.c_uint64()
+    loss = L.orc_nll_batch_envelope(_ptr(params), f.shape[0], _ptr(f), _ptr(t), m_max, lo, hi,
+                                    _ptr(grad), _ptr(bound), ctypes.byref(n_amb),
+                                    ctypes.byref(n_flag))
+    return loss, grad, bound, n_amb.value, n_flag.value
+
+
 def features(pos, sp: Species, beads, omega, grid):
     """Features of bead beads[c] of chain c, [n_chains, 60]."""
     L = _lib_mlp()
@@ -451,9 +524,14 @@ def features(pos, sp: Species, beads, omega, grid):
 
 def mc_sweep_mixed(pos, sp: Species, omega, grid, *, k0, n_ref, local_a, p_learn, params,
                    m_max, lo, hi, bf16_mode=True, seed, sweep, replica=0, chain_base=0,
-                   set_order=0, want_flags=False, threads=1, forbid=None):
+                   set_order=0, want_flags=False, threads=1, forbid=None, ambiguous=None,
+                   pos_env=None):
     """In-place mixed (local / learned) sweep.  Returns (accepted, accepted_learned,
-    bad_net, kind_flags, accept_flags)."""
+    bad_net, kind_flags, accept_flags).  With `ambiguous` (a uint8 array of
+    n_chains * n, BF16 mode only) each move's entry is set to 1 where rounding
+    alone may let the device decide it otherwise, and `pos_env` (float32, same
+    size, optional) to how far the device's new position of an accepted move
+    may lie from the oracle's through rounding (see ``nll_batch_envelope``)."""
     L = _lib_mlp()
     assert pos.dtype == np.float32 and pos.flags.c_contiguous
     params = _c(params, np.float32)
@@ -462,6 +540,14 @@ def mc_sweep_mixed(pos, sp: Species, omega, grid, *, k0, n_ref, local_a, p_learn
     af = np.zeros(sp.n_chains * sp.n, np.uint8) if want_flags else None
     acc_l = ctypes.c_uint64()
     bad = ctypes.c_uint32()
+    if ambiguous is not None:
+        assert ambiguous.dtype == np.uint8 and ambiguous.size == sp.n_chains * sp.n
+        assert ambiguous.flags.c_contiguous
+        if pos_env is None:
+            pos_env = np.zeros(sp.n_chains * sp.n, np.float32)
+        assert pos_env.dtype == np.float32 and pos_env.size == ambiguous.size
+        assert pos_env.flags.c_contiguous
+        pos_env[:] = 0.0
     walls = _opt(forbid, np.uint32)
     lib().orc_set_forbidden(_ptr(walls) if walls is not None else None)
     try:
@@ -472,6 +558,8 @@ def mc_sweep_mixed(pos, sp: Species, omega, grid, *, k0, n_ref, local_a, p_learn
                                    sweep, replica, chain_base, set_order,
                                    _ptr(kf) if kf is not None else None,
                                    _ptr(af) if af is not None else None,
+                                   _ptr(ambiguous) if ambiguous is not None else None,
+                                   _ptr(pos_env) if ambiguous is not None else None,
                                    ctypes.byref(acc_l), ctypes.byref(bad), threads)
     finally:
         lib().orc_set_forbidden(None)

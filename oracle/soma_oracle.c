@@ -837,6 +837,15 @@ float orc_bf16(float x) {
 static double orc_relu(double a) { return a > 0.0 ? a : 0.0; }
 static double orc_drelu(double a) { return a > 0.0 ? 1.0 : 0.0; }
 
+/* Test hook: with orc_acc_f32 set, the BF16 forward sums its terms in FP32
+ * in index order instead of FP64 -- another order of FP32 additions that a
+ * device may take, for testing the rounding envelope below.  Off by default. */
+static int orc_acc_f32 = 0;
+void orc_set_acc_f32(int on) { orc_acc_f32 = on; }
+static double orc_acc(double acc, double t, int bf16) {
+  return (bf16 && orc_acc_f32) ? (double)((float)acc + (float)t) : acc + t;
+}
+
 /* cache layout: x[60] a1[64] h1[64] a2[64] h2[64] */
 void orc_mlp_forward(const float *p, const double *f, int bf16, double *z,
                      double *cache) {
@@ -848,22 +857,22 @@ void orc_mlp_forward(const float *p, const double *f, int bf16, double *z,
 #define ORC_W(off, idx) (bf16 ? (double)orc_bf16(p[(off) + (idx)]) : (double)p[(off) + (idx)])
   for (int m = 0; m < ORC_NH; ++m) {
     double acc = 0.0;
-    for (int k = 0; k < ORC_NF; ++k) acc += ORC_W(ORC_P_W1, m * ORC_NF + k) * x[k];
-    a1[m] = acc + p[ORC_P_B1 + m];
+    for (int k = 0; k < ORC_NF; ++k) acc = orc_acc(acc, ORC_W(ORC_P_W1, m * ORC_NF + k) * x[k], bf16);
+    a1[m] = orc_acc(acc, p[ORC_P_B1 + m], bf16);
     h1[m] = orc_relu(a1[m]);
     if (bf16) h1[m] = orc_bf16((float)h1[m]);
   }
   for (int m = 0; m < ORC_NH; ++m) {
     double acc = 0.0;
-    for (int k = 0; k < ORC_NH; ++k) acc += ORC_W(ORC_P_W2, m * ORC_NH + k) * h1[k];
-    a2[m] = acc + p[ORC_P_B2 + m];
+    for (int k = 0; k < ORC_NH; ++k) acc = orc_acc(acc, ORC_W(ORC_P_W2, m * ORC_NH + k) * h1[k], bf16);
+    a2[m] = orc_acc(acc, p[ORC_P_B2 + m], bf16);
     h2[m] = orc_relu(a2[m]);
     if (bf16) h2[m] = orc_bf16((float)h2[m]);
   }
   for (int o = 0; o < ORC_NO; ++o) {
     double acc = 0.0;
-    for (int k = 0; k < ORC_NH; ++k) acc += ORC_W(ORC_P_W3, o * ORC_NH + k) * h2[k];
-    z[o] = acc + p[ORC_P_B3 + o];
+    for (int k = 0; k < ORC_NH; ++k) acc = orc_acc(acc, ORC_W(ORC_P_W3, o * ORC_NH + k) * h2[k], bf16);
+    z[o] = orc_acc(acc, p[ORC_P_B3 + o], bf16);
   }
 #undef ORC_W
   if (cache) {
@@ -959,6 +968,339 @@ double orc_nll_batch(const float *p, uint64_t n, const double *features,
   return total / (double)n;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Rounding envelope of the BF16 network -- a test instrument for the parity */
+/* of the device's learned proposal and training; the sampler above does    */
+/* not use it.  The device evaluates the network with BF16 operands whose    */
+/* products it sums in FP32 on the matrix cores, in an order of the          */
+/* hardware's, and rounds the hidden activations (and, in training, the      */
+/* back-propagated errors) to BF16.  Where the exact value of such a sum     */
+/* lies closer to a BF16 rounding boundary (or, under the ReLU, to zero)     */
+/* than an FP32 sum of its terms can err, the device may round it the other  */
+/* way.  The functions below take one sample through the network with the    */
+/* device's rounding points, list every such ambiguous rounding, and can     */
+/* re-evaluate the sample with one of them taken the other way, so that a    */
+/* test can bound the device's result by the oracle's plus the effect of     */
+/* each ambiguous rounding (to first order: one at a time).                  */
+/*                                                                           */
+/* Error of an FP32 sum of K exact products plus a bias, each addition       */
+/* rounded faithfully: at most (K + 2) 2^-23 S, S the sum of the magnitudes  */
+/* of the terms.  The matrix-core tiles sum K = 64 (hidden layers, output,   */
+/* error of the first layer) or K = 32 (error of the second layer) terms.    */
+/* orc_env_scale multiplies every such window (1: the bound as stated).      */
+/* ------------------------------------------------------------------------- */
+static double orc_env_scale = 1.0;
+void orc_set_envelope(double scale) { orc_env_scale = scale; }
+
+static double orc_env_window(int k, double s) { return orc_env_scale * (k + 2) * 0x1p-23 * s; }
+
+static float orc_bf16_bits(uint32_t u) {
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+
+/* The two BF16 values next to q (a BF16 value) in the directions of -inf and +inf. */
+static void orc_bf16_neighbours(float q, double *dn, double *up) {
+  uint32_t u;
+  memcpy(&u, &q, 4);
+  if ((u & 0x7FFFFFFFu) == 0u) {           /* +-0 */
+    *up = (double)orc_bf16_bits(0x00010000u);
+    *dn = -*up;
+  } else if (u & 0x80000000u) {            /* negative: magnitude up = toward -inf */
+    *dn = (double)orc_bf16_bits(u + 0x10000u);
+    *up = (double)orc_bf16_bits(u - 0x10000u);
+  } else {
+    *up = (double)orc_bf16_bits(u + 0x10000u);
+    *dn = (double)orc_bf16_bits(u - 0x10000u);
+  }
+}
+
+/* Distance of v from the nearest point where BF16 round-to-nearest changes
+ * its result (a midpoint between two neighbouring BF16 values), and the BF16
+ * value on the other side of that point. */
+double orc_bf16_boundary(double v, double *other) {
+  float q = orc_bf16((float)v);
+  double dn, up;
+  orc_bf16_neighbours(q, &dn, &up);
+  double m_up = 0.5 * ((double)q + up), m_dn = 0.5 * ((double)q + dn);
+  double d_up = fabs(v - m_up), d_dn = fabs(v - m_dn);
+  if (other) *other = d_up < d_dn ? up : dn;
+  return d_up < d_dn ? d_up : d_dn;
+}
+
+/* Stages of the rounding points of one sample. */
+enum { ORC_ST_NONE = 0, ORC_ST_X = 1, ORC_ST_H1 = 2, ORC_ST_H2 = 3, ORC_ST_R1 = 4,
+       ORC_ST_R2 = 5, ORC_ST_DZ = 6, ORC_ST_D2 = 7, ORC_ST_D1 = 8 };
+/* X: a standardised input; H1, H2: a hidden activation's BF16 rounding;
+ * R1, R2: a hidden unit's ReLU (pre-activation within the window of zero);
+ * DZ, D2, D1: the BF16 rounding of a back-propagated error. */
+
+#define ORC_AMB_MAX 1024
+typedef struct {
+  int stage[ORC_AMB_MAX], unit[ORC_AMB_MAX];
+  int n;
+} orc_amb_list;
+
+static void orc_amb_add(orc_amb_list *l, int stage, int unit) {
+  if (l && l->n < ORC_AMB_MAX) {
+    l->stage[l->n] = stage;
+    l->unit[l->n] = unit;
+    l->n++;
+  }
+}
+
+/* One sample as the device evaluates it.  x0: the standardised inputs [60]
+ * in FP32 (before their BF16 rounding), xwin: the window of each input
+ * (0: known exactly).  Override (ov_stage, ov_unit) takes that rounding the
+ * other way.  Writes z [6] and its windows zwin [6]; with `amb`, lists the
+ * ambiguous roundings.  With `tgt` (a training target, 3) and `grad`, also
+ * the training pass: adds the unnormalised loss gradient into grad[8576] and
+ * the bound of the FP32 (unrounded) bias terms into bias_err[8576] and the
+ * magnitudes of the gradient terms into gabs[8576] (both may be NULL). */
+static void orc_dev_sample(const float *p, const double *x0, const double *xwin,
+                           int ov_stage, int ov_unit, double *z, double *zwin,
+                           orc_amb_list *amb, const double *tgt, double m_max, double lo,
+                           double hi, double *grad, double *bias_err, double *gabs) {
+  double x[ORC_NF], a1[ORC_NH], h1[ORC_NH], a2[ORC_NH], h2[ORC_NH];
+  int r1[ORC_NH], r2[ORC_NH];
+#define ORC_WB(off, idx) ((double)orc_bf16(p[(off) + (idx)]))
+  for (int k = 0; k < ORC_NF; ++k) {
+    double other;
+    double dist = orc_bf16_boundary(x0[k], &other);
+    x[k] = (double)orc_bf16((float)x0[k]);
+    if (ov_stage == ORC_ST_X && ov_unit == k) x[k] = other;
+    else if (xwin && xwin[k] > 0.0 && dist <= xwin[k]) orc_amb_add(amb, ORC_ST_X, k);
+  }
+  /* hidden layers: pre-activation a, its window, ReLU, BF16 rounding */
+  for (int layer = 0; layer < 2; ++layer) {
+    const double *in = layer == 0 ? x : h1;
+    double *a = layer == 0 ? a1 : a2, *h = layer == 0 ? h1 : h2;
+    int *rl = layer == 0 ? r1 : r2;
+    int n_in = layer == 0 ? ORC_NF : ORC_NH;
+    int w_off = layer == 0 ? ORC_P_W1 : ORC_P_W2, b_off = layer == 0 ? ORC_P_B1 : ORC_P_B2;
+    int st_h = layer == 0 ? ORC_ST_H1 : ORC_ST_H2, st_r = layer == 0 ? ORC_ST_R1 : ORC_ST_R2;
+    for (int m = 0; m < ORC_NH; ++m) {
+      double acc = 0.0, s = fabs((double)p[b_off + m]);
+      for (int k = 0; k < n_in; ++k) {
+        double t = ORC_WB(w_off, m * n_in + k) * in[k];
+        acc += t;
+        s += fabs(t);
+      }
+      a[m] = acc + p[b_off + m];
+      double win = orc_env_window(64, s);
+      rl[m] = a[m] > 0.0;
+      if (fabs(a[m]) <= win) {
+        if (ov_stage == st_r && ov_unit == m) {
+          rl[m] = !rl[m];
+          h[m] = rl[m] ? (double)orc_bf16((float)win) : 0.0;
+          continue;
+        }
+        orc_amb_add(amb, st_r, m);
+        h[m] = rl[m] ? (double)orc_bf16((float)a[m]) : 0.0;
+        continue;
+      }
+      if (!rl[m]) { h[m] = 0.0; continue; }
+      double other;
+      double dist = orc_bf16_boundary(a[m], &other);
+      h[m] = (double)orc_bf16((float)a[m]);
+      if (ov_stage == st_h && ov_unit == m) h[m] = other;
+      else if (dist <= win) orc_amb_add(amb, st_h, m);
+    }
+  }
+  for (int o = 0; o < ORC_NO; ++o) {
+    double acc = 0.0, s = fabs((double)p[ORC_P_B3 + o]);
+    for (int k = 0; k < ORC_NH; ++k) {
+      double t = ORC_WB(ORC_P_W3, o * ORC_NH + k) * h2[k];
+      acc += t;
+      s += fabs(t);
+    }
+    z[o] = acc + p[ORC_P_B3 + o];
+    if (zwin) zwin[o] = orc_env_window(64, s);
+  }
+  if (!grad) return;
+
+  /* training: dL/dz in FP32 from z, rounded to BF16 for the tiles */
+  double dz[ORC_NO], dzb[ORC_NO], dzw[ORC_NO];
+  double zwl[ORC_NO];
+  for (int o = 0; o < ORC_NO; ++o) {
+    double acc_s = fabs((double)p[ORC_P_B3 + o]);
+    for (int k = 0; k < ORC_NH; ++k) acc_s += fabs(ORC_WB(ORC_P_W3, o * ORC_NH + k) * h2[k]);
+    zwl[o] = orc_env_window(64, acc_s);
+  }
+  /* |term| of every gradient entry, for the bound of the FP32 sums over samples */
+#define ORC_GABS(idx, v) do { if (gabs) gabs[idx] += fabs(v); } while (0)
+  orc_nll(z, tgt, m_max, lo, hi, dz);
+  for (int d = 0; d < 3; ++d) {
+    /* window of the device's FP32 dz: z within its window (four corners), and
+     * 2^-18 of the magnitudes for the FP32 head (transcendentals, cancellation) */
+    double zc[ORC_NO], dzc[ORC_NO], dev_mu = 0.0, dev_s = 0.0;
+    for (int corner = 0; corner < 4; ++corner) {
+      memcpy(zc, z, sizeof zc);
+      zc[d] += (corner & 1) ? zwl[d] : -zwl[d];
+      zc[3 + d] += (corner & 2) ? zwl[3 + d] : -zwl[3 + d];
+      orc_nll(zc, tgt, m_max, lo, hi, dzc);
+      if (fabs(dzc[d] - dz[d]) > dev_mu) dev_mu = fabs(dzc[d] - dz[d]);
+      if (fabs(dzc[3 + d] - dz[3 + d]) > dev_s) dev_s = fabs(dzc[3 + d] - dz[3 + d]);
+    }
+    double mu = m_max * tanh(z[d] / m_max);
+    double sg = 1.0 / (1.0 + exp(-z[3 + d]));
+    double inv_var = exp(-2.0 * (lo + (hi - lo) * sg));
+    double e = tgt[d] - mu;
+    double mag_mu = (fabs(tgt[d]) + fabs(mu)) * inv_var * 2.0;
+    double mag_s = (1.0 + e * e * inv_var) * (hi - lo) * sg * (1.0 - sg) * 2.0;
+    dzw[d] = dev_mu + orc_env_scale * 0x1p-18 * mag_mu;
+    dzw[3 + d] = dev_s + orc_env_scale * 0x1p-18 * mag_s;
+  }
+  for (int o = 0; o < ORC_NO; ++o) {
+    double other;
+    double dist = orc_bf16_boundary(dz[o], &other);
+    dzb[o] = (double)orc_bf16((float)dz[o]);
+    if (ov_stage == ORC_ST_DZ && ov_unit == o) dzb[o] = other;
+    else if (dist <= dzw[o]) orc_amb_add(amb, ORC_ST_DZ, o);
+    grad[ORC_P_B3 + o] += dz[o];
+    ORC_GABS(ORC_P_B3 + o, dz[o]);
+    if (bias_err) bias_err[ORC_P_B3 + o] += dzw[o];
+    for (int k = 0; k < ORC_NH; ++k) {
+      grad[ORC_P_W3 + o * ORC_NH + k] += dzb[o] * h2[k];
+      ORC_GABS(ORC_P_W3 + o * ORC_NH + k, dzb[o] * h2[k]);
+    }
+  }
+  /* error of the second hidden layer: K = 32 tile (6 used) */
+  double d2b[ORC_NH];
+  for (int k = 0; k < ORC_NH; ++k) {
+    double acc = 0.0, s = 0.0;
+    for (int o = 0; o < ORC_NO; ++o) {
+      double t = ORC_WB(ORC_P_W3, o * ORC_NH + k) * dzb[o];
+      acc += t;
+      s += fabs(t);
+    }
+    double d = r2[k] ? acc : 0.0;
+    double win = orc_env_window(32, s);
+    grad[ORC_P_B2 + k] += d;
+    ORC_GABS(ORC_P_B2 + k, d);
+    if (bias_err && r2[k]) bias_err[ORC_P_B2 + k] += win;
+    double other;
+    double dist = orc_bf16_boundary(d, &other);
+    d2b[k] = (double)orc_bf16((float)d);
+    if (ov_stage == ORC_ST_D2 && ov_unit == k) d2b[k] = other;
+    else if (r2[k] && dist <= win) orc_amb_add(amb, ORC_ST_D2, k);
+    for (int j = 0; j < ORC_NH; ++j) {
+      grad[ORC_P_W2 + k * ORC_NH + j] += d2b[k] * h1[j];
+      ORC_GABS(ORC_P_W2 + k * ORC_NH + j, d2b[k] * h1[j]);
+    }
+  }
+  /* error of the first hidden layer: K = 64 */
+  for (int k = 0; k < ORC_NH; ++k) {
+    double acc = 0.0, s = 0.0;
+    for (int m = 0; m < ORC_NH; ++m) {
+      double t = ORC_WB(ORC_P_W2, m * ORC_NH + k) * d2b[m];
+      acc += t;
+      s += fabs(t);
+    }
+    double d = r1[k] ? acc : 0.0;
+    double win = orc_env_window(64, s);
+    grad[ORC_P_B1 + k] += d;
+    ORC_GABS(ORC_P_B1 + k, d);
+    if (bias_err && r1[k]) bias_err[ORC_P_B1 + k] += win;
+    double other;
+    double dist = orc_bf16_boundary(d, &other);
+    double d1b = (double)orc_bf16((float)d);
+    if (ov_stage == ORC_ST_D1 && ov_unit == k) d1b = other;
+    else if (r1[k] && dist <= win) orc_amb_add(amb, ORC_ST_D1, k);
+    for (int j = 0; j < ORC_NF; ++j) {
+      grad[ORC_P_W1 + k * ORC_NF + j] += d1b * x[j];
+      ORC_GABS(ORC_P_W1 + k * ORC_NF + j, d1b * x[j]);
+    }
+  }
+#undef ORC_GABS
+#undef ORC_WB
+}
+
+/* Network outputs as the device computes them, with their envelope: z [n][6]
+ * (the BF16 forward with FP64 sums) and bound [n][6], the window of each
+ * output's own FP32 sum plus, for every ambiguous rounding of the sample, the
+ * change of the output when it is taken the other way.  Returns the number of
+ * ambiguous roundings. */
+uint64_t orc_mlp_forward_envelope(const float *p, uint64_t n, const double *features, double *z,
+                                  double *bound) {
+  orc_amb_list *amb = malloc(sizeof(orc_amb_list));
+  uint64_t na = 0;
+  for (uint64_t s = 0; s < n; ++s) {
+    double x0[ORC_NF], zw[ORC_NO], za[ORC_NO], zaw[ORC_NO];
+    double *zs = z + s * ORC_NO, *bs = bound + s * ORC_NO;
+    for (int k = 0; k < ORC_NF; ++k)
+      x0[k] = (double)(((float)features[s * ORC_NF + k] - p[ORC_P_SHIFT + k]) * p[ORC_P_SCALE + k]);
+    amb->n = 0;
+    orc_dev_sample(p, x0, NULL, ORC_ST_NONE, 0, zs, zw, amb, NULL, 0, 0, 0, NULL, NULL, NULL);
+    for (int o = 0; o < ORC_NO; ++o) bs[o] = zw[o];
+    for (int a = 0; a < amb->n; ++a) {
+      orc_dev_sample(p, x0, NULL, amb->stage[a], amb->unit[a], za, zaw, NULL, NULL, 0, 0, 0, NULL,
+                     NULL, NULL);
+      for (int o = 0; o < ORC_NO; ++o) bs[o] += fabs(za[o] - zs[o]);
+    }
+    na += (uint64_t)amb->n;
+  }
+  free(amb);
+  return na;
+}
+
+/* Training gradient as the device computes it, with its envelope.  Returns
+ * the mean loss.  grad [8576]: the mean gradient with the device's rounding
+ * points (BF16 inputs, weights, activations and back-propagated errors; FP64
+ * sums).  bound [8576]: per parameter, the sum over samples of the change of
+ * that sample's term when one ambiguous rounding is taken the other way (one
+ * at a time), plus the windows of the FP32 bias terms, plus
+ * (64 + n) 2^-23 times the sum of the magnitudes of the terms (the FP32 sums
+ * over samples), divided by n.  n_amb: ambiguous roundings found; n_flagged:
+ * samples with at least one. */
+double orc_nll_batch_envelope(const float *p, uint64_t n, const double *features,
+                              const double *targets, double m_max, double lo, double hi,
+                              double *grad, double *bound, uint64_t *n_amb,
+                              uint64_t *n_flagged) {
+  double *g_main = calloc(ORC_P_SIZE, sizeof(double));
+  double *g_alt = calloc(ORC_P_SIZE, sizeof(double));
+  double *gabs = calloc(ORC_P_SIZE, sizeof(double));
+  orc_amb_list *amb = malloc(sizeof(orc_amb_list));
+  memset(grad, 0, ORC_P_SIZE * sizeof(double));
+  memset(bound, 0, ORC_P_SIZE * sizeof(double));
+  double total = 0.0, z[ORC_NO], zw[ORC_NO], dz[ORC_NO];
+  uint64_t na = 0, nf = 0;
+  for (uint64_t s = 0; s < n; ++s) {
+    const double *f = features + s * ORC_NF;
+    const double *t = targets + 3 * s;
+    double x0[ORC_NF];
+    for (int k = 0; k < ORC_NF; ++k)
+      x0[k] = (double)(((float)f[k] - p[ORC_P_SHIFT + k]) * p[ORC_P_SCALE + k]);
+    memset(g_main, 0, ORC_P_SIZE * sizeof(double));
+    amb->n = 0;
+    orc_dev_sample(p, x0, NULL, ORC_ST_NONE, 0, z, zw, amb, t, m_max, lo, hi, g_main, bound,
+                   gabs);
+    total += orc_nll(z, t, m_max, lo, hi, dz);
+    for (int j = 0; j < ORC_P_SIZE; ++j) grad[j] += g_main[j];
+    na += (uint64_t)amb->n;
+    nf += amb->n > 0;
+    for (int a = 0; a < amb->n; ++a) {
+      memset(g_alt, 0, ORC_P_SIZE * sizeof(double));
+      orc_dev_sample(p, x0, NULL, amb->stage[a], amb->unit[a], z, zw, NULL, t, m_max, lo, hi,
+                     g_alt, NULL, NULL);
+      for (int j = 0; j < ORC_P_SIZE; ++j) bound[j] += fabs(g_alt[j] - g_main[j]);
+    }
+  }
+  const double gamma = orc_env_scale * (64.0 + (double)n) * 0x1p-23;
+  for (int j = 0; j < ORC_P_SIZE; ++j) {
+    grad[j] /= (double)n;
+    bound[j] = (bound[j] + gamma * gabs[j]) / (double)n + 0x1p-22 * fabs(grad[j]);
+  }
+  free(g_main);
+  free(g_alt);
+  free(gabs);
+  free(amb);
+  if (n_amb) *n_amb = na;
+  if (n_flagged) *n_flagged = nf;
+  return total / (double)n;
+}
+
 void orc_features(const float *chain, uint32_t i, uint32_t n, uint32_t n_a,
                   const float *omega, uint32_t nx, uint32_t ny, uint32_t nz,
                   const float *r, double *f) {
@@ -997,6 +1339,194 @@ void orc_features_batch(const float *pos, uint32_t n_chains, uint32_t n, uint32_
   }
 }
 
+/* Log of the Metropolis-Hastings ratio of a learned move r -> trial, from the
+ * network outputs z at r and zn at trial (as in orc_move_learned); with
+ * `mag`, also the sum of the magnitudes of its terms. */
+static double orc_learned_log_ratio(const float *chain, uint32_t i, uint32_t n, uint32_t n_a,
+                                    double k0, const float *omega, uint64_t n_cells,
+                                    uint32_t nx, uint32_t ny, uint32_t nz, uint32_t n_ref,
+                                    const float *r, const float *trial, const double *z,
+                                    const double *zn, double m_max, double lo, double hi,
+                                    double *mag) {
+  double mu[3], sig[3], lsig[3], mun[3], sign[3], lsign[3];
+  orc_head(z, m_max, lo, hi, mu, sig, lsig);
+  orc_head(zn, m_max, lo, hi, mun, sign, lsign);
+  double log_fwd = 0.0, log_rev = 0.0, m = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    double ef = (double)trial[d] - (double)r[d] - mu[d];
+    double er = (double)r[d] - (double)trial[d] - mun[d];
+    log_fwd -= ef * ef / (2.0 * sig[d] * sig[d]) + lsig[d];
+    log_rev -= er * er / (2.0 * sign[d] * sign[d]) + lsign[d];
+    m += ef * ef / (2.0 * sig[d] * sig[d]) + fabs(lsig[d]) + er * er / (2.0 * sign[d] * sign[d]) +
+         fabs(lsign[d]);
+  }
+  double e_new = orc_bond_energy(trial, chain, i, n, k0), e_old = orc_bond_energy(r, chain, i, n, k0);
+  const float *om = omega + (uint64_t)orc_type(i, n_a) * n_cells;
+  double w_new = om[orc_cell(trial, nx, ny, nz)], w_old = om[orc_cell(r, nx, ny, nz)];
+  if (mag) *mag = m + e_new + e_old + (fabs(w_new) + fabs(w_old)) / (double)n_ref;
+  return -((e_new - e_old) + (w_new - w_old) / (double)n_ref) + log_rev - log_fwd;
+}
+
+/* Standardised FP32 inputs of the network for raw features f. */
+static void orc_std_inputs(const float *p, const double *f, double *x0) {
+  for (int k = 0; k < ORC_NF; ++k)
+    x0[k] = (double)(((float)f[k] - p[ORC_P_SHIFT + k]) * p[ORC_P_SCALE + k]);
+}
+
+/* Trial position of a learned move from z and the normals xi, as the oracle
+ * forms it, and the bound dr[3] of the device's FP32 trial: the window of z
+ * carried through the head plus 2^-20 of |mu| + |sigma xi| (FP32 head and
+ * normals) plus 2^-23 of |r| + |trial| (the additions). */
+static void orc_learned_trial(const float *r, const double *z, const double *zw,
+                              const double *xi, double m_max, double lo, double hi,
+                              float *trial, double *dr) {
+  double mu[3], sig[3], lsig[3];
+  orc_head(z, m_max, lo, hi, mu, sig, lsig);
+  for (int d = 0; d < 3; ++d) {
+    trial[d] = (float)((double)r[d] + mu[d] + sig[d] * xi[d]);
+    if (!dr) continue;
+    double th = tanh(z[d] / m_max);
+    double sg = 1.0 / (1.0 + exp(-z[3 + d]));
+    double dmu = (1.0 - th * th) * zw[d];
+    double dsig = sig[d] * (hi - lo) * sg * (1.0 - sg) * zw[3 + d];
+    dr[d] = dmu + fabs(xi[d]) * dsig + 0x1p-20 * (fabs(mu[d]) + fabs(sig[d] * xi[d])) +
+            0x1p-23 * (fabs((double)r[d]) + fabs((double)trial[d]));
+    dr[d] *= orc_env_scale;
+  }
+}
+
+/* Whether the device's outcome of a learned move may differ from the
+ * oracle's through rounding alone: the trial (within its bound) may lie in
+ * another cell, or the log ratio (with the effect of every ambiguous rounding
+ * of both network passes, the windows of z, the trial's bound and nb_env, the
+ * amount by which the bonded neighbours may already sit elsewhere) may fall
+ * on the other side of log u.  *pos_env: how far the device's trial may lie
+ * from the oracle's (the trial's bound plus the largest shift of an
+ * ambiguous rounding of the pass at r).  The move is the one
+ * orc_move_learned makes from the chain's current state. */
+static int orc_learned_ambiguous(const float *chain, uint32_t i, uint32_t n, uint32_t n_a,
+                                 double k0, const float *omega, uint64_t n_cells,
+                                 uint32_t nx, uint32_t ny, uint32_t nz, uint32_t n_ref,
+                                 const float *p, double m_max, double lo, double hi,
+                                 const double *xi, double log_u, double nb_env,
+                                 double *pos_env) {
+  const float *r = chain + 3 * i;
+  orc_amb_list *amb1 = malloc(sizeof(orc_amb_list)), *amb2 = malloc(sizeof(orc_amb_list));
+  double f[ORC_NF], x0[ORC_NF], z[ORC_NO], zw[ORC_NO], dr[3];
+  double fn[ORC_NF], xn[ORC_NF], xnw[ORC_NF], zn[ORC_NO], znw[ORC_NO];
+  int flag = 0;
+  double shift = 0.0;
+  *pos_env = 0.0;
+  amb1->n = amb2->n = 0;
+  orc_features(chain, i, n, n_a, omega, nx, ny, nz, r, f);
+  orc_std_inputs(p, f, x0);
+  orc_dev_sample(p, x0, NULL, ORC_ST_NONE, 0, z, zw, amb1, NULL, 0, 0, 0, NULL, NULL, NULL);
+  float trial[3];
+  orc_learned_trial(r, z, zw, xi, m_max, lo, hi, trial, dr);
+  /* the trial's cell within its bound, and the bound against the tolerance */
+  for (int d = 0; d < 3; ++d) {
+    double t = (double)trial[d];
+    double frac = t - floor(t);
+    if (frac <= dr[d] || 1.0 - frac <= dr[d]) flag = 1;
+    if (dr[d] > *pos_env) *pos_env = dr[d];
+  }
+  orc_features(chain, i, n, n_a, omega, nx, ny, nz, trial, fn);
+  orc_std_inputs(p, fn, xn);
+  for (int k = 0; k < ORC_NF; ++k)
+    xnw[k] = k >= 54 ? fabs((double)p[ORC_P_SCALE + k]) * dr[(k - 54) % 3] + 0x1p-23 * fabs(xn[k])
+                     : 0.0;
+  orc_dev_sample(p, xn, xnw, ORC_ST_NONE, 0, zn, znw, amb2, NULL, 0, 0, 0, NULL, NULL, NULL);
+  double mag;
+  const double lr = orc_learned_log_ratio(chain, i, n, n_a, k0, omega, n_cells, nx, ny, nz, n_ref,
+                                          r, trial, z, zn, m_max, lo, hi, &mag);
+  /* FP32 evaluation of the ratio and of exp; neighbours elsewhere by up to
+   * nb_env change the bond terms by k0 |trial - r| nb_env and the network's
+   * inputs (bounded generously by nb_env itself) */
+  double step = 0.0;
+  for (int d = 0; d < 3; ++d) step += fabs((double)trial[d] - (double)r[d]);
+  double eps = orc_env_scale * (0x1p-18 * mag + 0x1p-20) + (k0 * step + 1.0) * nb_env;
+  /* windows of z at r (through the trial) and at the trial */
+  for (int j = 0; j < ORC_NO && !flag; ++j) {
+    double zp[ORC_NO];
+    float tp[3];
+    memcpy(zp, z, sizeof zp);
+    zp[j] += zw[j];
+    orc_learned_trial(r, zp, zw, xi, m_max, lo, hi, tp, NULL);
+    eps += fabs(orc_learned_log_ratio(chain, i, n, n_a, k0, omega, n_cells, nx, ny, nz, n_ref, r,
+                                      tp, zp, zn, m_max, lo, hi, NULL) - lr);
+    memcpy(zp, zn, sizeof zp);
+    zp[j] += znw[j];
+    eps += fabs(orc_learned_log_ratio(chain, i, n, n_a, k0, omega, n_cells, nx, ny, nz, n_ref, r,
+                                      trial, z, zp, m_max, lo, hi, NULL) - lr);
+  }
+  /* the trial's bound, axis by axis */
+  for (int d = 0; d < 3 && !flag; ++d) {
+    float tp[3] = {trial[0], trial[1], trial[2]};
+    tp[d] = (float)((double)trial[d] + dr[d]);
+    eps += fabs(orc_learned_log_ratio(chain, i, n, n_a, k0, omega, n_cells, nx, ny, nz, n_ref, r,
+                                      tp, z, zn, m_max, lo, hi, NULL) - lr);
+  }
+  /* every ambiguous rounding of the pass at r (moving the trial) ... */
+  double rad = 0.0;
+  for (int a = 0; a < amb1->n && !flag; ++a) {
+    double za[ORC_NO], zaw[ORC_NO], fa[ORC_NF], xa[ORC_NF], zna[ORC_NO], znaw[ORC_NO];
+    float ta[3];
+    orc_dev_sample(p, x0, NULL, amb1->stage[a], amb1->unit[a], za, zaw, NULL, NULL, 0, 0, 0,
+                   NULL, NULL, NULL);
+    orc_learned_trial(r, za, zw, xi, m_max, lo, hi, ta, NULL);
+    if (orc_cell(ta, nx, ny, nz) != orc_cell(trial, nx, ny, nz)) { flag = 1; break; }
+    for (int d = 0; d < 3; ++d) shift = fmax(shift, fabs((double)ta[d] - (double)trial[d]));
+    orc_features(chain, i, n, n_a, omega, nx, ny, nz, ta, fa);
+    orc_std_inputs(p, fa, xa);
+    orc_dev_sample(p, xa, NULL, ORC_ST_NONE, 0, zna, znaw, NULL, NULL, 0, 0, 0, NULL, NULL, NULL);
+    rad += fabs(orc_learned_log_ratio(chain, i, n, n_a, k0, omega, n_cells, nx, ny, nz, n_ref, r,
+                                      ta, za, zna, m_max, lo, hi, NULL) - lr);
+  }
+  /* ... and of the pass at the trial */
+  for (int a = 0; a < amb2->n && !flag; ++a) {
+    double zna[ORC_NO], znaw[ORC_NO];
+    orc_dev_sample(p, xn, xnw, amb2->stage[a], amb2->unit[a], zna, znaw, NULL, NULL, 0, 0, 0,
+                   NULL, NULL, NULL);
+    rad += fabs(orc_learned_log_ratio(chain, i, n, n_a, k0, omega, n_cells, nx, ny, nz, n_ref, r,
+                                      trial, z, zna, m_max, lo, hi, NULL) - lr);
+  }
+  if (!flag && fabs(lr - log_u) <= rad + eps) flag = 1;
+  *pos_env += shift;
+  free(amb1);
+  free(amb2);
+  return flag;
+}
+
+/* Whether the device's decision on a local move may differ from the oracle's
+ * through rounding alone: -dE within the FP32 error of its delta-form
+ * evaluation (2^-18 of the magnitudes of its terms) and of exp, plus the
+ * change of the bond term when the bonded neighbours sit elsewhere by up to
+ * nb_env, from log u. */
+static int orc_local_ambiguous(const float *chain, uint32_t i, uint32_t n, uint32_t n_a,
+                               double k0, const float *omega, uint64_t n_cells, uint32_t nx,
+                               uint32_t ny, uint32_t nz, uint32_t n_ref, float a,
+                               const uint32_t w[4], double nb_env) {
+  const float *r = chain + 3 * i;
+  float trial[3];
+  double mag = 0.0;
+  for (int d = 0; d < 3; ++d) trial[d] = fmaf(a, orc_v11(w[d]), r[d]);
+  for (int d = 0; d < 3; ++d) {
+    double dd = fabs((double)trial[d] - (double)r[d]);
+    if (i > 0) mag += dd * (2.0 * fabs((double)r[d] - (double)chain[3 * (i - 1) + d]) + dd);
+    if (i + 1 < n) mag += dd * (2.0 * fabs((double)r[d] - (double)chain[3 * (i + 1) + d]) + dd);
+  }
+  mag *= 0.5 * k0;
+  double d_bond = orc_bond_energy(trial, chain, i, n, k0) - orc_bond_energy(r, chain, i, n, k0);
+  const float *om = omega + (uint64_t)orc_type(i, n_a) * n_cells;
+  double w_new = om[orc_cell(trial, nx, ny, nz)], w_old = om[orc_cell(r, nx, ny, nz)];
+  double d_e = d_bond + (w_new - w_old) / (double)n_ref;
+  mag += (fabs(w_new) + fabs(w_old)) / (double)n_ref;
+  double step = 0.0;
+  for (int d = 0; d < 3; ++d) step += fabs((double)trial[d] - (double)r[d]);
+  double eps = orc_env_scale * (0x1p-18 * mag + 0x1p-20) + k0 * step * nb_env;
+  return fabs(-d_e - log((double)orc_u01(w[3]))) <= eps;
+}
+
 /* Mixed sweep: each bead makes the learned move with probability p_learn
  * (uniform from word 1 of its purpose-1 draw, independent of the state) and
  * the local move otherwise.  A learned move draws xi by Box-Muller from the
@@ -1007,7 +1537,8 @@ static int orc_move_learned(float *chain, uint32_t c_id, uint32_t i, uint32_t n,
                             uint64_t n_cells, uint32_t nx, uint32_t ny, uint32_t nz,
                             uint32_t n_ref, const float *params, double m_max,
                             double lo, double hi, int bf16, uint64_t seed,
-                            uint32_t sweep, uint32_t replica, uint32_t *bad_net) {
+                            uint32_t sweep, uint32_t replica, uint32_t *bad_net,
+                            uint8_t *ambiguous, double nb_env, double *pos_env) {
   uint32_t wa[4], wb[4];
   orc_draw(seed, c_id, i, ORC_PURPOSE_MOVE_A, sweep, replica, wa);
   orc_draw(seed, c_id, i, ORC_PURPOSE_MOVE_B, sweep, replica, wb);
@@ -1043,6 +1574,10 @@ static int orc_move_learned(float *chain, uint32_t c_id, uint32_t i, uint32_t n,
   double log_ratio = -(d_bond + d_field) + log_rev - log_fwd;
   double u = (double)orc_u01(wb[0]);
   int accept = (log_ratio >= 0.0) || (u < exp(log_ratio));
+  if (ambiguous && bf16)
+    *ambiguous = (uint8_t)orc_learned_ambiguous(chain, i, n, n_a, k0, omega, n_cells, nx, ny, nz,
+                                                n_ref, params, m_max, lo, hi, xi, log(u),
+                                                nb_env, pos_env);
   if (accept) memcpy(r, trial, sizeof trial);
   return accept;
 }
@@ -1053,8 +1588,8 @@ uint64_t orc_mc_sweep_mixed(float *pos, uint32_t n_chains, uint32_t n, uint32_t 
                             const float *params, float m_max, float lo, float hi, int bf16,
                             uint64_t seed, uint32_t sweep, uint32_t replica,
                             uint32_t chain_base, uint32_t set_order, uint8_t *kind_flags,
-                            uint8_t *accept_flags, uint64_t *accepted_learned,
-                            uint32_t *bad_net, int n_threads) {
+                            uint8_t *accept_flags, uint8_t *amb_flags, float *pos_env,
+                            uint64_t *accepted_learned, uint32_t *bad_net, int n_threads) {
   uint64_t n_cells = (uint64_t)nx * ny * nz;
   uint64_t acc_total = 0, acc_l = 0;
   uint32_t bad = 0;
@@ -1076,13 +1611,30 @@ uint64_t orc_mc_sweep_mixed(float *pos, uint32_t n_chains, uint32_t n, uint32_t 
         int learned = (double)orc_u01(wb[1]) < (double)p_learn;
         int acc;
         uint32_t b = 0;
-        if (learned)
+        uint8_t amb = 0;
+        double env = 0.0, nb_env = 0.0;
+        if (amb_flags) {   /* how far the bonded neighbours may sit elsewhere */
+          if (i > 0) nb_env += pos_env[(uint64_t)c * n + i - 1];
+          if (i + 1 < n) nb_env += pos_env[(uint64_t)c * n + i + 1];
+        }
+        if (learned) {
           acc = orc_move_learned(chain, c_id, i, n, n_a, (double)k0, omega, n_cells, nx, ny,
                                  nz, n_ref, params, m_max, lo, hi, bf16, seed, sweep,
-                                 replica, &b);
-        else
+                                 replica, &b, amb_flags ? &amb : NULL, nb_env, &env);
+        } else {
+          if (amb_flags) {
+            uint32_t w[4];
+            orc_draw(seed, c_id, i, ORC_PURPOSE_MOVE_A, sweep, replica, w);
+            amb = (uint8_t)orc_local_ambiguous(chain, i, n, n_a, (double)k0, omega, n_cells,
+                                               nx, ny, nz, n_ref, local_a, w, nb_env);
+          }
           acc = orc_move_local(chain, c_id, i, n, n_a, (double)k0, omega, n_cells, nx, ny,
                                nz, n_ref, local_a, seed, sweep, replica);
+        }
+        if (amb_flags) {
+          amb_flags[(uint64_t)c * n + i] = amb;
+          pos_env[(uint64_t)c * n + i] = acc ? (float)env : 0.0f;
+        }
         bad += b;
         acc_total += (uint64_t)acc;
         if (learned) acc_l += (uint64_t)acc;

@@ -118,3 +118,61 @@ def stepwise_cycles(melt, orc, sp, grid, n_cycles, oracle_sweep, field_of, *, n_
     np.testing.assert_array_equal(melt.omega.cpu().numpy(), field_of(orc.density_hist(pos, sp, grid)))
     flush("mismatched chains per cycle:", per_cycle, "allowed per cycle:", allowed)
     return per_cycle
+
+
+def proposal_test_params(orc, pos, sp, omega, grid, *, seed, mu_gain=0.2, out_gain=0.3,
+                         n_std=2048, sigma_bias=0.0):
+    """A random network for the parity tests of the learned move that moves
+    beads: inputs standardised with the mean and standard deviation of the
+    oracle's features of up to n_std chains (beads 0, 7, N/2, N-1), the rows of
+    the mean damped by mu_gain (a random drift makes the reverse move unlikely
+    and nearly every move rejected), sigma's bias set to sigma_bias."""
+    n_ch = min(sp.n_chains, n_std)
+    sub = Species_like(sp, n_ch)
+    beads = sorted({0, min(7, sp.n - 1), sp.n // 2, sp.n - 1})
+    feats = np.concatenate([orc.features(pos[:n_ch * sp.n], sub, np.full(n_ch, b, np.uint32),
+                                         omega, grid) for b in beads])
+    shift = feats.mean(axis=0)
+    sd = feats.std(axis=0)
+    scale = np.where(sd > 1e-6, 1.0 / np.maximum(sd, 1e-6), 1.0)
+    params = synth.mlp_params(seed, out_gain=out_gain, shift=shift.astype(np.float32),
+                              scale=scale.astype(np.float32))
+    L = synth.MLP_LAYOUT
+    params[L["w3"]:L["w3"] + 192] *= np.float32(mu_gain)
+    params[L["b3"]:L["b3"] + 3] = 0.0
+    params[L["b3"] + 3:L["b3"] + 6] = sigma_bias
+    return params
+
+
+def Species_like(sp, n_chains):
+    from oracle import Species
+    return Species(n_chains, sp.n, sp.n_a)
+
+
+def explain_mismatches(got, init, ref, accepted, amb, pos_env, n_per_chain, *, tol=6e-5):
+    """Per-move comparison of a mixed sweep with the oracle's (one sweep from
+    positions `init`; `ref`, `accepted`, `amb`, `pos_env` from the oracle).
+
+    The device accepted a move iff the bead moved.  A move is a mismatch if
+    the decisions differ, or, both accepting, if the new positions differ by
+    more than tol + the move's rounding envelope (plus a quarter of its bonded
+    neighbours'), or, both rejecting, if the bead is not where it started.  A
+    mismatched chain is explained if the oracle flags one of its moves as
+    decidable otherwise by rounding.  Returns (mismatched chains, unexplained
+    chains, flagged chains, decision mismatches)."""
+    nc = got.shape[0] // n_per_chain
+    g = got.astype(np.float64).reshape(nc, n_per_chain, 3)
+    r = ref.astype(np.float64).reshape(nc, n_per_chain, 3)
+    i0 = init.astype(np.float64).reshape(nc, n_per_chain, 3)
+    acc_o = accepted.reshape(nc, n_per_chain).astype(bool)
+    moved = np.abs(g - i0).max(axis=2) > 0
+    env = pos_env.reshape(nc, n_per_chain).astype(np.float64)
+    nb = np.zeros_like(env)
+    nb[:, 1:] += env[:, :-1]
+    nb[:, :-1] += env[:, 1:]
+    tol_b = tol + env + 0.25 * nb
+    dec = moved != acc_o
+    pos_bad = np.abs(g - r).max(axis=2) > tol_b
+    bad = (dec | pos_bad).any(axis=1)
+    flagged = amb.reshape(nc, n_per_chain).astype(bool).any(axis=1)
+    return int(bad.sum()), int((bad & ~flagged).sum()), int(flagged.sum()), int(dec.sum())

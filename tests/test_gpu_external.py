@@ -16,7 +16,8 @@ import pytest
 
 import synth
 from oracle import Species, references
-from tests.gpu_helpers import constants, custom_config, device_config, flush
+from tests.gpu_helpers import (constants, custom_config, device_config, explain_mismatches, flush,
+                               proposal_test_params)
 
 torch = pytest.importorskip("torch")
 pytestmark = [pytest.mark.gpu,
@@ -120,28 +121,35 @@ def test_one_sweep_parity_with_walls(C, orc, order):
 
 
 def test_mixed_sweep_parity_with_walls(C, orc):
+    """One mixed sweep in a film with wall planes, learned moves of sigma ~ 0.6
+    cells (walls matter), compared move by move with the oracle as in the
+    learned parity test; no bead ends in a wall plane."""
     w = _film((24, 24, 8), (synth.SpeciesSpec(2048, 32, 16),), 16)
     m, pos, sp, walls, mask, ext, inv_rho = _setup(C, w, 73, p_learn=0.5)
     k0, a, A, _ = constants(w)
-    params = synth.mlp_params(14, out_gain=0.1)
-    params[synth.MLP_LAYOUT["b3"] + 3:synth.MLP_LAYOUT["b3"] + 6] = 0.5   # sigma ~ 0.6: walls matter
-    m.set_proposal(torch.from_numpy(params).cuda())
     omega = m.omega.cpu().numpy()
+    params = proposal_test_params(orc, pos, sp[0], omega, w.grid, seed=14, sigma_bias=0.5)
+    m.set_proposal(torch.from_numpy(params).cuda())
     m.sweep(1, C.SOMA_MOVE_MIXED)
     obs = m.observables()
     ref = pos.copy()
-    acc, acc_l, bad, kinds, _ = orc.mc_sweep_mixed(ref, sp[0], omega, w.grid, k0=k0, n_ref=w.n_ref,
-                                                   local_a=a, p_learn=0.5, params=params, **HEAD,
-                                                   bf16_mode=True, seed=w.seed, sweep=0,
-                                                   want_flags=True, threads=8, forbid=mask)
+    amb = np.zeros(pos.shape[0], np.uint8)
+    env = np.zeros(pos.shape[0], np.float32)
+    acc, acc_l, bad, kinds, acc_flags = orc.mc_sweep_mixed(
+        ref, sp[0], omega, w.grid, k0=k0, n_ref=w.n_ref, local_a=a, p_learn=0.5, params=params,
+        **HEAD, bf16_mode=True, seed=w.seed, sweep=0, want_flags=True, threads=8, forbid=mask,
+        ambiguous=amb, pos_env=env)
     got = m.pos.cpu().numpy()
-    diff = np.abs(got.astype(np.float64) - ref).reshape(2048, -1).max(axis=1)
-    frac_ok = (diff <= 1e-5 * 6.0).mean()
-    flush("mixed with walls: chains within tolerance", frac_ok, "accepted learned",
-          obs.accepted[2], acc_l)
+    n_bad, unexplained, flagged, dec = explain_mismatches(got, pos, ref, acc_flags, amb, env, 32)
+    allowed = math.ceil(1e-6 * pos.shape[0])
+    flush("mixed with walls: accepted", acc / pos.shape[0], "mismatched", n_bad, "unexplained",
+          unexplained, "allowed", allowed, "flagged", flagged, "accepted learned", obs.accepted[2],
+          acc_l)
     assert obs.attempted[2] == int(kinds.sum())
-    assert frac_ok >= 0.99
-    assert abs(int(obs.accepted[2]) - acc_l) <= 0.01 * max(1, acc_l) + 5
+    assert acc > 0.3 * pos.shape[0]
+    assert unexplained <= allowed
+    assert flagged <= 0.08 * sp[0].n_chains
+    assert abs(int(obs.accepted[2]) - acc_l) <= int(amb[kinds == 1].sum())
     z = np.floor(got[:, 2].astype(np.float64)).astype(np.int64) % w.grid[2]
     assert ((z >= 1) & (z <= w.grid[2] - 2)).all()
     m.close()

@@ -4,11 +4,14 @@ Bars:
   * features: bit-exact against the oracle (FP32 field values and bond vectors);
   * network outputs z: the oracle's BF16-emulating forward (inputs, weights and
     hidden activations rounded to bfloat16 at the same points) with FP64
-    accumulation, against BF16 MFMA with FP32 accumulation: |dz| <= 2e-3 (1+|z|)
-    for 99.9% of samples (a hidden activation on a bfloat16 rounding boundary
-    may round the other way) and <= 3e-2 (1+|z|) for all;
-  * one mixed sweep (learned with probability p): positions within 1e-5 Re0
-    for at least 99% of chains, the rest explained by rounding flips;
+    accumulation, against BF16 MFMA with FP32 accumulation: every output
+    within the oracle's rounding envelope (the FP32 error bound of its own sum
+    plus the effect of every hidden rounding that such sums may take the other
+    way);
+  * one mixed sweep (learned with probability p): move by move, decisions equal
+    and accepted positions within 1e-5 Re0 plus the move's rounding envelope;
+    every chain that breaks this holds a move the oracle flags as decidable
+    otherwise by rounding (unexplained chains at most ceil(1e-6 x moves));
   * exactness: 3-bead chain in a frozen random field keeps the Boltzmann
     distribution under learned and mixed moves (chi-square, p > 1e-4).
 """
@@ -19,7 +22,8 @@ import pytest
 
 import synth
 from oracle import Species, references
-from tests.gpu_helpers import constants, custom_config, device_config, flush
+from tests.gpu_helpers import (constants, custom_config, device_config, explain_mismatches, flush,
+                               proposal_test_params)
 
 torch = pytest.importorskip("torch")
 pytestmark = [pytest.mark.gpu,
@@ -50,11 +54,13 @@ def test_forward_matches_bf16_oracle(orc, n):
     C.soma_mlp_forward(net.data_ptr(), f.data_ptr(), n, z.data_ptr(), _stream())
     torch.cuda.synchronize()
     got = z.cpu().numpy().astype(np.float64)
-    exp = orc.mlp_forward(params, feats.astype(np.float64), bf16_mode=True)
-    err = np.abs(got - exp) / (1 + np.abs(exp))
-    flush("n", n, "max rel err", err.max(), "99.9%", np.quantile(err.max(axis=1), 0.999))
-    assert np.quantile(err.max(axis=1), 0.999) <= 2e-3
-    assert err.max() <= 3e-2
+    exp, bound, n_amb = orc.mlp_forward_envelope(params, feats.astype(np.float64))
+    np.testing.assert_array_equal(exp, orc.mlp_forward(params, feats.astype(np.float64),
+                                                       bf16_mode=True))
+    excess = np.abs(got - exp) - bound
+    flush("n", n, "ambiguous roundings", n_amb, "max |dz|", np.abs(got - exp).max(),
+          "max |dz| / bound", (np.abs(got - exp) / bound).max(), "max excess", excess.max())
+    assert excess.max() <= 0.0
 
 
 def test_features_bit_exact(orc):
@@ -156,33 +162,47 @@ def test_collect_training(orc):
 
 @pytest.mark.parametrize("p_learn", [1.0, 0.5])
 def test_mixed_sweep_parity(orc, p_learn):
+    """One mixed sweep on the device against the oracle's BF16-emulating sweep
+    from the same positions and fields, move by move: the device accepted a
+    move iff the bead moved; decisions must agree, and accepted positions agree
+    within 1e-5 Re0 plus the move's rounding envelope (how far BF16 roundings
+    that FP32 sums may take either way can shift the trial).  Every chain that
+    breaks this must hold a move the oracle flags as decidable otherwise by
+    rounding; unexplained chains at most ceil(1e-6 x moves).  The network moves
+    beads (standardised inputs, damped mean), so most moves are accepted."""
     from paper_1711_03828_amd import soma as C
     from paper_1711_03828_amd.melt import Melt
     w = synth.scaled(synth.C4_MEDIUM, 2048, (24, 24, 24))
     k0, a, A, inv_rho = constants(w)
-    params = synth.mlp_params(12, out_gain=0.1)
     pos = synth.gaussian_walks(13, 2048, 32, w.grid, 1 / math.sqrt(float(k0)))
     sp = Species(2048, 32, 16)
     m = Melt(device_config(w, p_learn=p_learn), positions=torch.from_numpy(pos))
-    m.set_proposal(torch.from_numpy(params).cuda())
     omega = m.omega.cpu().numpy()   # equals the oracle's field bit for bit (test_gpu_parity)
     np.testing.assert_array_equal(omega, orc.field_f32(orc.density_hist(pos, [sp], w.grid), inv_rho,
                                                        np.float32(w.chi_n), np.float32(w.kappa_n)))
+    params = proposal_test_params(orc, pos, sp, omega, w.grid, seed=12)
+    m.set_proposal(torch.from_numpy(params).cuda())
     m.sweep(1, C.SOMA_MOVE_MIXED)
     obs = m.observables()
     ref = pos.copy()
-    acc, acc_l, bad, kinds, _ = orc.mc_sweep_mixed(ref, sp, omega, w.grid, k0=k0, n_ref=w.n_ref,
-                                                   local_a=a, p_learn=p_learn, params=params,
-                                                   **HEAD, bf16_mode=True, seed=w.seed, sweep=0,
-                                                   want_flags=True, threads=8)
+    amb = np.zeros(2048 * 32, np.uint8)
+    env = np.zeros(2048 * 32, np.float32)
+    acc, acc_l, bad, kinds, acc_flags = orc.mc_sweep_mixed(
+        ref, sp, omega, w.grid, k0=k0, n_ref=w.n_ref, local_a=a, p_learn=p_learn, params=params,
+        **HEAD, bf16_mode=True, seed=w.seed, sweep=0, want_flags=True, threads=8, ambiguous=amb,
+        pos_env=env)
     got = m.pos.cpu().numpy()
-    diff = np.abs(got.astype(np.float64) - ref).reshape(2048, -1).max(axis=1)
-    frac_ok = (diff <= 1e-5 * 6.0).mean()
-    flush("p_learn", p_learn, "chains within tolerance", frac_ok, "learned attempts",
-          obs.attempted[2], int(kinds.sum()), "accepted learned", obs.accepted[2], acc_l)
+    n_bad, unexplained, flagged, dec = explain_mismatches(got, pos, ref, acc_flags, amb, env, 32)
+    allowed = math.ceil(1e-6 * pos.shape[0])
+    flush("p_learn", p_learn, "accepted", acc / pos.shape[0], "mismatched chains", n_bad,
+          "unexplained", unexplained, "allowed", allowed, "flagged chains", flagged,
+          "decision mismatches", dec, "learned attempts", obs.attempted[2], int(kinds.sum()),
+          "accepted learned", obs.accepted[2], acc_l)
     assert obs.attempted[2] == int(kinds.sum())        # same mixture draws
-    assert frac_ok >= 0.99
-    assert abs(int(obs.accepted[2]) - acc_l) <= 0.01 * max(1, acc_l) + 5
+    assert acc > 0.3 * pos.shape[0]
+    assert unexplained <= allowed
+    assert flagged <= 0.08 * 2048
+    assert abs(int(obs.accepted[2]) - acc_l) <= int(amb[kinds == 1].sum())
     assert obs.counts_conserved == 1 and obs.error_flags == 0
     m.close()
 
