@@ -83,6 +83,12 @@ typedef enum soma_status {
 #define SOMA_SCHEME_MOLECULE 1u /* one thread per chain making N attempts one after another,
                                    each on a bead picked at random */
 
+/* How the SET sweeps keep the occupation histogram (Eq. (4), Sec. 3.1.1)
+ * current; see soma_set_histogram. */
+#define SOMA_HIST_DIRECT 0u /* one memory-side atomic per +-1 count update (default) */
+#define SOMA_HIST_BINNED 1u /* updates binned by brick of 16x16x8 cells, then applied
+                               brick by brick in LDS */
+
 /* Device error word bits (returned by soma_check / soma_observables). */
 #define SOMA_FLAG_POSITION 1u /* soma_observables found a position non-finite or |x| >= 2^22 */
 #define SOMA_FLAG_NETWORK 2u  /* a learned move met a non-finite network output (rejected) */
@@ -299,6 +305,23 @@ int32_t soma_type_counts(soma_system *sys, uint64_t *out, uint32_t n_out, void *
  * identical for every value (they depend only on seed, sweep and chain).
  * A multiple of 8 keeps each XCD on one contiguous range of chains. */
 int32_t soma_set_sweep_blocks(soma_system *sys, uint32_t blocks);
+
+/* Count updates of the SET-order sweeps (local, smart-MC, bond-Gibbs and
+ * mixed moves of linear chains; the histogram of Eq. (4), Sec. 3.1.1).
+ * SOMA_HIST_DIRECT: a bead that changes cell adds -1 and +1 to the packed
+ * counts with two device atomics.  SOMA_HIST_BINNED: the grid is cut into
+ * bricks of 16 x 16 x 8 cells (x fastest; partial bricks at the faces); each
+ * wave groups its updates by brick, reserves room in the brick's bin in the
+ * workspace with one atomic per (wave, brick) and stores them there; after
+ * the sweep one workgroup per brick adds its bin to the counts in LDS (a bin
+ * that is full takes further updates as direct atomics).  soma_mc_sweep,
+ * soma_cycle and captured cycles run that step themselves, so the counts are
+ * current whenever a call returns its stream to the caller.  Both modes give
+ * the same counts bit for bit (integer additions in any order); molecule-order,
+ * architecture and batched sweeps always use direct atomics.  Capture graphs
+ * again after a change.  SOMA_E_INVAL for an unknown mode, SOMA_E_UNSUPPORTED
+ * for SOMA_HIST_BINNED on a grid of 2^21 bricks or more. */
+int32_t soma_set_histogram(soma_system *sys, uint32_t mode);
 
 /* Iteration order of SOMA_MOVE_LOCAL sweeps (Sec. 3.1.2, schemes 2 and 1).
  * SOMA_SCHEME_SET (default): every bead is attempted once per sweep, the two

@@ -72,6 +72,10 @@ struct Derived {
   float chi_m[soma::kMaxTypes * soma::kMaxTypes] = {};
   uint64_t ws_bytes = 0;
   uint32_t field_blocks = 1;  // blocks of the field update (and its FP64 partial sums)
+  // per-brick bins of count updates (soma_set_histogram): bricks of 16 x 16 x 8 cells
+  uint32_t nbx = 0, nby = 0, nbz = 0, bin_cap = 0;
+  uint64_t n_bricks = 0, off_bin_count = 0, off_bins = 0;
+  bool bins_ok = false;
 };
 
 int32_t derive(const soma_config *c, Derived *d) {
@@ -140,6 +144,23 @@ int32_t derive(const soma_config *c, Derived *d) {
   if (8ull * d->halo_plane >= (1ull << 32))
     return fail(SOMA_E_UNSUPPORTED, "grid too large for the learned proposal's field copy");
   d->ws_bytes = align_up(d->off_halo + 8ull * d->halo_plane);
+  // bins: room for the updates of about half the beads of a brick per sweep
+  // (entries beyond it go to the counts as direct atomics)
+  d->nbx = (c->nx + 15u) / 16u;
+  d->nby = (c->ny + 15u) / 16u;
+  d->nbz = (c->nz + 7u) / 8u;
+  d->n_bricks = (uint64_t)d->nbx * d->nby * d->nbz;
+  d->bins_ok = d->n_bricks < (1ull << 21);
+  if (d->bins_ok) {
+    const double per_brick = (double)d->n_beads * soma::kBrickCells / (double)n_cells;
+    uint64_t cap = (uint64_t)std::ceil(0.55 * per_brick) + 256u;
+    cap = (cap + 63u) / 64u * 64u;
+    if (cap > (1ull << 26)) cap = 1ull << 26;
+    d->bin_cap = (uint32_t)cap;
+    d->off_bin_count = d->ws_bytes;
+    d->off_bins = align_up(d->off_bin_count + 4ull * d->n_bricks);
+    d->ws_bytes = align_up(d->off_bins + 4ull * d->n_bricks * cap);
+  }
   return SOMA_OK;
 }
 
@@ -318,6 +339,7 @@ struct soma_system {
   uint32_t arch_max_type[SOMA_MAX_SPECIES] = {};  // largest type code of their monomers
   uint32_t substeps = 1;      // field refreshes per SCMF cycle (chain subsets)
   uint32_t scheme = SOMA_SCHEME_SET;  // iteration order of local moves
+  uint32_t hist_mode = soma::kHistDirect;  // count updates of the SET sweeps (soma_set_histogram)
   float4 *grad = nullptr;     // optional gradient field (caller-owned), see soma_set_grad_field
   unsigned char *ws = nullptr;
   CycleGraph graph;
@@ -339,6 +361,16 @@ struct soma_system {
     return reinterpret_cast<soma::ArchDev *>(ws + d.off_arch + sp * align_up(sizeof(soma::ArchDev)));
   }
   const soma::ArchDev *arch_or_null(uint32_t sp) { return (arch_mask >> sp & 1u) ? arch(sp) : nullptr; }
+  soma::BinArgs bins() {
+    soma::BinArgs b;
+    b.bin_count = reinterpret_cast<uint32_t *>(ws + d.off_bin_count);
+    b.bins = reinterpret_cast<uint32_t *>(ws + d.off_bins);
+    b.cap = d.bin_cap;
+    b.nbx = d.nbx;
+    b.nby = d.nby;
+    b.nbz = d.nbz;
+    return b;
+  }
   soma::NetDev *net(uint32_t sp) {
     return reinterpret_cast<soma::NetDev *>(ws + d.off_net + sp * align_up(sizeof(soma::NetDev)));
   }
@@ -351,17 +383,42 @@ struct soma_system {
 
 namespace {
 
-template <bool C64, bool V2>
+template <bool C64, bool V2, bool B>
 void launch_sweep_t(uint32_t kind, dim3 grid, hipStream_t s, const soma::SweepArgs &a,
                     const soma::MixArgs &mx) {
   if (kind == SOMA_MOVE_MIXED)
-    hipLaunchKernelGGL((soma::mc_sweep_mixed_kernel<C64, V2>), grid, dim3(256), 0, s, a, mx);
+    hipLaunchKernelGGL((soma::mc_sweep_mixed_kernel<C64, V2, B>), grid, dim3(256), 0, s, a, mx);
   else if (kind == SOMA_MOVE_SMC)
-    hipLaunchKernelGGL((soma::mc_sweep_smc_kernel<C64, V2>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((soma::mc_sweep_smc_kernel<C64, V2, B>), grid, dim3(256), 0, s, a);
   else if (kind == SOMA_MOVE_GIBBS)
-    hipLaunchKernelGGL((soma::mc_sweep_gibbs_kernel<C64, V2>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((soma::mc_sweep_gibbs_kernel<C64, V2, B>), grid, dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((soma::mc_sweep_local_kernel<C64, V2>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((soma::mc_sweep_local_kernel<C64, V2, B>), grid, dim3(256), 0, s, a);
+}
+
+template <bool C64, bool V2>
+void launch_sweep_b(bool binned, uint32_t kind, dim3 grid, hipStream_t s,
+                    const soma::SweepArgs &a, const soma::MixArgs &mx) {
+  if (binned) launch_sweep_t<C64, V2, true>(kind, grid, s, a, mx);
+  else launch_sweep_t<C64, V2, false>(kind, grid, s, a, mx);
+}
+
+// Adds the binned count updates of the sweeps before it to the counts (one
+// workgroup per brick; the SET sweep kernels bin updates of types 0 and 1
+// only, which live in count plane 0).
+int32_t launch_bin_apply(soma_system *sys, hipStream_t s) {
+  const soma::BinArgs b = sys->bins();
+  const bool c64 = sys->cfg.count_width == 32;
+  const uint32_t planes = 1u;
+  const size_t lds = (size_t)planes * soma::kBrickCells * (c64 ? 8u : 4u);
+  if (c64)
+    hipLaunchKernelGGL(soma::bin_apply_kernel<true>, dim3((uint32_t)sys->d.n_bricks), dim3(256),
+                       lds, s, b, sys->grid, sys->buf.counts, planes);
+  else
+    hipLaunchKernelGGL(soma::bin_apply_kernel<false>, dim3((uint32_t)sys->d.n_bricks), dim3(256),
+                       lds, s, b, sys->grid, sys->buf.counts, planes);
+  LAUNCH_TRY();
+  return SOMA_OK;
 }
 
 // Arguments of species sp's sweep of kind `kind` (sweep offset 0).
@@ -402,6 +459,7 @@ void sweep_args(soma_system *sys, uint32_t sp, uint32_t kind, soma::SweepArgs &a
   a.forbid = sys->d.forbid;
   a.gibbs_s2 = (float)(1.0 / std::sqrt(2.0 * (double)S.k0));
   a.gibbs_s1 = (float)(1.0 / std::sqrt((double)S.k0));
+  a.bin = sys->d.bins_ok ? sys->bins() : soma::BinArgs{};
   mx.net = sys->net(sp);
   mx.head.m_max = c->mu_max;
   mx.head.lo = c->log_sigma_min;
@@ -427,6 +485,8 @@ uint32_t subset_size(uint32_t n, uint32_t k, uint32_t j) { return n > j ? (n - j
 int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s, uint32_t off,
                      uint32_t k = 1, uint32_t j = 0) {
   const soma_config *c = &sys->cfg;
+  const bool binned = sys->hist_mode == soma::kHistBinned;
+  bool any_binned = false;
   for (uint32_t sp = 0; sp < c->n_species; ++sp) {
     const soma_species &S = c->species[sp];
     if (!S.n_chains) continue;
@@ -463,14 +523,16 @@ int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s, uint32_t of
     const bool v2 = species_vec2(sys, sp);
     const dim3 grid((uint32_t)blocks);
     if (c64) {
-      if (v2) launch_sweep_t<true, true>(kind, grid, s, a, mx);
-      else launch_sweep_t<true, false>(kind, grid, s, a, mx);
+      if (v2) launch_sweep_b<true, true>(binned, kind, grid, s, a, mx);
+      else launch_sweep_b<true, false>(binned, kind, grid, s, a, mx);
     } else {
-      if (v2) launch_sweep_t<false, true>(kind, grid, s, a, mx);
-      else launch_sweep_t<false, false>(kind, grid, s, a, mx);
+      if (v2) launch_sweep_b<false, true>(binned, kind, grid, s, a, mx);
+      else launch_sweep_b<false, false>(binned, kind, grid, s, a, mx);
     }
     LAUNCH_TRY();
+    any_binned |= binned;
   }
+  if (any_binned) return launch_bin_apply(sys, s);
   return SOMA_OK;
 }
 
@@ -699,6 +761,16 @@ int32_t soma_set_scheme(soma_system *sys, uint32_t scheme) {
   if (scheme != SOMA_SCHEME_SET && scheme != SOMA_SCHEME_MOLECULE)
     return fail(SOMA_E_INVAL, "scheme %u", scheme);
   sys->scheme = scheme;
+  return SOMA_OK;
+}
+
+int32_t soma_set_histogram(soma_system *sys, uint32_t mode) {
+  if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
+  if (mode != SOMA_HIST_DIRECT && mode != SOMA_HIST_BINNED)
+    return fail(SOMA_E_INVAL, "histogram mode %u", mode);
+  if (mode == SOMA_HIST_BINNED && !sys->d.bins_ok)
+    return fail(SOMA_E_UNSUPPORTED, "binned count updates need fewer than 2^21 bricks of 16x16x8 cells");
+  sys->hist_mode = mode == SOMA_HIST_BINNED ? soma::kHistBinned : soma::kHistDirect;
   return SOMA_OK;
 }
 

@@ -61,13 +61,13 @@ __global__ __launch_bounds__(256, 2) void batched_sweep_kernel(const BatchLaunch
       float *cp = a.pos + (size_t)(m.has0 ? m.chain : 0u) * a.n * 3u + 6u * m.k;
       F3 r0, r1;
       load_pair<VEC2>(cp, m, r0, r1);
-      finish_block(a, local_tile<COUNT64, VEC2>(a, m, cp, r0, r1));
+      finish_block(a, local_tile<COUNT64, VEC2, false>(a, m, cp, r0, r1));
     } else if (KIND == 1) {
-      finish_block(a, smc_wave<COUNT64, VEC2>(a, m));
+      finish_block(a, smc_wave<COUNT64, VEC2, false>(a, m));
     } else {
       const MixArgs mx = L.segs[sg].mx;
       uint32_t cnt[3];
-      mixed_wave<COUNT64, VEC2>(a, mx, m, s_act[KIND == 2 ? m.wib : 0],
+      mixed_wave<COUNT64, VEC2, false>(a, mx, m, s_act[KIND == 2 ? m.wib : 0],
                                 s_tmp[KIND == 2 ? m.wib : 0], mx.net->shift, cnt);
       mixed_finish(a, mx, cnt);
     }

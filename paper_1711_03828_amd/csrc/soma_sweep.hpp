@@ -18,6 +18,7 @@
 // bit-identical to counting the final positions from scratch.
 #pragma once
 
+#include "soma_bins.hpp"
 #include "soma_device.hpp"
 #include "soma_mlp.hpp"
 
@@ -54,6 +55,9 @@ struct SweepArgs {
   // bonded neighbours, 1/sqrt(2 k0) (also the step of a bead without bonds),
   // and around one, 1/sqrt(k0)
   float gibbs_s2, gibbs_s1;
+  // per-brick bins of count updates (kernels instantiated with BINNED); the
+  // counts are current only after bin_apply_kernel has run
+  BinArgs bin;
 };
 
 // A move from cell `from` to cell `to` that the impenetrable cells allow.
@@ -202,7 +206,7 @@ __device__ __forceinline__ uint32_t set_order_bit(const SweepArgs &a, const Lane
 // a trial position is then at most one cell away along each axis.
 // ---------------------------------------------------------------------------
 // One wave's tile of local moves: positions r0/r1 already loaded for lane map m.
-template <bool COUNT64, bool VEC2>
+template <bool COUNT64, bool VEC2, bool BINNED>
 __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap &m, float *cp,
                                                F3 r0, F3 r1) {
   const uint32_t N = a.n;
@@ -227,12 +231,14 @@ __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap
                  fmaf(a.step, uniform11(w0.z), r0.z)};
   const F3 t1 = {fmaf(a.step, uniform11(w1.x), r1.x), fmaf(a.step, uniform11(w1.y), r1.y),
                  fmaf(a.step, uniform11(w1.z), r1.z)};
-  const uint32_t n0 = cell_index(a.grid, shift_cell(x0, r0.x, t0.x, a.grid.nx),
-                                 shift_cell(y0, r0.y, t0.y, a.grid.ny),
-                                 shift_cell(z0, r0.z, t0.z, a.grid.nz));
-  const uint32_t n1 = cell_index(a.grid, shift_cell(x1, r1.x, t1.x, a.grid.nx),
-                                 shift_cell(y1, r1.y, t1.y, a.grid.ny),
-                                 shift_cell(z1, r1.z, t1.z, a.grid.nz));
+  const uint32_t sx0 = shift_cell(x0, r0.x, t0.x, a.grid.nx),
+                 sy0 = shift_cell(y0, r0.y, t0.y, a.grid.ny),
+                 sz0 = shift_cell(z0, r0.z, t0.z, a.grid.nz);
+  const uint32_t sx1 = shift_cell(x1, r1.x, t1.x, a.grid.nx),
+                 sy1 = shift_cell(y1, r1.y, t1.y, a.grid.ny),
+                 sz1 = shift_cell(z1, r1.z, t1.z, a.grid.nz);
+  const uint32_t n0 = cell_index(a.grid, sx0, sy0, sz0);
+  const uint32_t n1 = cell_index(a.grid, sx1, sy1, sz1);
   float wn0 = wo0, wn1 = wo1;
   if (n0 != c0) wn0 = field_at(a.omega, pl0, n0);
   if (n1 != c1) wn1 = field_at(a.omega, pl1, n1);
@@ -279,8 +285,15 @@ __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap
   }
   store_pair<VEC2>(cp, m, sel(odd_first, rb, ra), sel(odd_first, ra, rb));
   const bool acc0 = odd_first ? acc_b : acc_a, acc1 = odd_first ? acc_a : acc_b;
-  if (acc0 && n0 != c0) move_count<COUNT64>(a.counts, c0, n0, b0);
-  if (acc1 && n1 != c1) move_count<COUNT64>(a.counts, c1, n1, b1);
+  if (BINNED) {
+    bin_moves<COUNT64>(a.bin, a.grid, a.counts, brick_key(a.bin, x0, y0, z0),
+                       brick_key(a.bin, sx0, sy0, sz0), b0 ? 1u : 0u, acc0 && n0 != c0,
+                       brick_key(a.bin, x1, y1, z1), brick_key(a.bin, sx1, sy1, sz1),
+                       b1 ? 1u : 0u, acc1 && n1 != c1);
+  } else {
+    if (acc0 && n0 != c0) move_count<COUNT64>(a.counts, c0, n0, b0);
+    if (acc1 && n1 != c1) move_count<COUNT64>(a.counts, c1, n1, b1);
+  }
   return (uint32_t)(__popcll(__ballot(acc_a)) + __popcll(__ballot(acc_b)));
 }
 
@@ -301,7 +314,7 @@ __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap
 // With fewer waves than tiles each wave loops, loading the next tile's
 // positions while it works on the current one.
 // ---------------------------------------------------------------------------
-template <bool COUNT64, bool VEC2>
+template <bool COUNT64, bool VEC2, bool BINNED>
 __global__ __launch_bounds__(256) void mc_sweep_local_kernel(const SweepArgs a_in) {
   const SweepArgs a = resolve_sweep(a_in, 0u);
   const uint32_t n_tiles = (a.n_sub + a.chains_per_wave - 1u) / a.chains_per_wave;
@@ -326,7 +339,7 @@ __global__ __launch_bounds__(256) void mc_sweep_local_kernel(const SweepArgs a_i
     float *cpn = a.pos + (size_t)(mn.has0 ? mn.chain : 0u) * a.n * 3u + 6u * mn.k;
     F3 s0, s1;
     load_pair<VEC2>(cpn, mn, s0, s1);    // next tile, in flight during this one
-    n_acc += local_tile<COUNT64, VEC2>(a, m, cp, r0, r1);
+    n_acc += local_tile<COUNT64, VEC2, BINNED>(a, m, cp, r0, r1);
     m = mn;
     cp = cpn;
     r0 = s0;
@@ -382,7 +395,7 @@ __device__ __forceinline__ float field_and_grad(const SweepArgs &a, uint32_t pl,
 // then cancel in the Metropolis-Hastings ratio, which leaves
 // exp(-(omega(c') - omega(c))/N).  Same draws as smart MC.
 // ---------------------------------------------------------------------------
-template <bool COUNT64, bool VEC2, bool GIBBS = false>
+template <bool COUNT64, bool VEC2, bool BINNED, bool GIBBS = false>
 __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &m) {
   const uint32_t N = a.n;
   const uint32_t i0 = 2u * m.k, i1 = i0 + 1u;
@@ -435,7 +448,7 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
     const uint32_t pl = (odd ? b1 : b0) ? a.grid.n_cells : 0u;
 
     bool acc = false;
-    uint32_t co = 0, cn = 0;
+    uint32_t co = 0, cn = 0, ko = 0, kn = 0;
     F3 rn = r;
     if (GIBBS && moving) {
       co = odd ? co1 : co0;
@@ -454,6 +467,10 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
       uint32_t nx_, ny_, nz_;
       cell3(a.grid, rn.x, rn.y, rn.z, nx_, ny_, nz_);
       cn = cell_index(a.grid, nx_, ny_, nz_);
+      if (BINNED) {
+        ko = brick_key(a.bin, odd ? ox1 : ox0, odd ? oy1 : oy0, odd ? oz1 : oz0);
+        kn = brick_key(a.bin, nx_, ny_, nz_);
+      }
       const float w_old = odd ? f1 : f0;
       const float w_new = cn == co ? w_old : field_at(a.omega, pl, cn);
       const float d_e = (w_new - w_old) * a.inv_nref;
@@ -477,6 +494,10 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
       uint32_t nx_, ny_, nz_;
       cell3(a.grid, rn.x, rn.y, rn.z, nx_, ny_, nz_);
       cn = cell_index(a.grid, nx_, ny_, nz_);
+      if (BINNED) {
+        ko = brick_key(a.bin, odd ? ox1 : ox0, odd ? oy1 : oy0, odd ? oz1 : oz0);
+        kn = brick_key(a.bin, nx_, ny_, nz_);
+      }
       // force at the trial position with the same bonded neighbours; the
       // field gradient is constant inside a cell
       F3 g_new = g_old;
@@ -500,29 +521,35 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
       const float lr = log_q - d_e;
       acc = ok && (lr >= 0.0f || u < __expf(lr));
     }
+    if (BINNED) { co = ko; cn = kn; }   // cells as brick keys from here on
     if (odd) { r1 = acc ? rn : r1; moved1 = acc && cn != co; from1 = co; to1 = cn; }
     else     { r0 = acc ? rn : r0; moved0 = acc && cn != co; from0 = co; to0 = cn; }
     n_acc += (uint32_t)__popcll(__ballot(acc));
   }
 
   store_pair<VEC2>(cp, m, r0, r1);
-  if (moved0) move_count<COUNT64>(a.counts, from0, to0, b0);
-  if (moved1) move_count<COUNT64>(a.counts, from1, to1, b1);
+  if (BINNED) {
+    bin_moves<COUNT64>(a.bin, a.grid, a.counts, from0, to0, b0 ? 1u : 0u, moved0, from1, to1,
+                       b1 ? 1u : 0u, moved1);
+  } else {
+    if (moved0) move_count<COUNT64>(a.counts, from0, to0, b0);
+    if (moved1) move_count<COUNT64>(a.counts, from1, to1, b1);
+  }
   return n_acc;
 }
 
-template <bool COUNT64, bool VEC2>
+template <bool COUNT64, bool VEC2, bool BINNED>
 __global__ __launch_bounds__(256) void mc_sweep_smc_kernel(const SweepArgs a_in) {
   const SweepArgs a = resolve_sweep(a_in, 0u);
   const LaneMap m = lane_map(a);
-  finish_block(a, smc_wave<COUNT64, VEC2>(a, m));
+  finish_block(a, smc_wave<COUNT64, VEC2, BINNED>(a, m));
 }
 
-template <bool COUNT64, bool VEC2>
+template <bool COUNT64, bool VEC2, bool BINNED>
 __global__ __launch_bounds__(256) void mc_sweep_gibbs_kernel(const SweepArgs a_in) {
   const SweepArgs a = resolve_sweep(a_in, 0u);
   const LaneMap m = lane_map(a);
-  finish_block(a, smc_wave<COUNT64, VEC2, true>(a, m));
+  finish_block(a, smc_wave<COUNT64, VEC2, BINNED, true>(a, m));
 }
 
 }  // namespace soma
@@ -553,7 +580,7 @@ struct MixArgs {
 // network output z reuses tmp), stdz the network's standardisation constants
 // (shift[64] then scale[64]).  Returns through cnt the wave's accepted local
 // moves, accepted learned moves and learned attempts.
-template <bool COUNT64, bool VEC2>
+template <bool COUNT64, bool VEC2, bool BINNED>
 __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx, const LaneMap &m,
                                            __bf16 *act, __bf16 *tmp, const float *stdz,
                                            uint32_t cnt[3]) {
@@ -662,8 +689,15 @@ __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx
     n_att_l += (uint32_t)__popcll(__ballot(learned));
   }
   store_pair<VEC2>(cp, m, r0, r1);
-  if (moved0) move_count<COUNT64>(a.counts, from0, to0, b0);
-  if (moved1) move_count<COUNT64>(a.counts, from1, to1, b1);
+  if (BINNED) {
+    bin_moves<COUNT64>(a.bin, a.grid, a.counts, cell_brick_key(a.bin, a.grid, from0),
+                       cell_brick_key(a.bin, a.grid, to0), b0 ? 1u : 0u, moved0,
+                       cell_brick_key(a.bin, a.grid, from1), cell_brick_key(a.bin, a.grid, to1),
+                       b1 ? 1u : 0u, moved1);
+  } else {
+    if (moved0) move_count<COUNT64>(a.counts, from0, to0, b0);
+    if (moved1) move_count<COUNT64>(a.counts, from1, to1, b1);
+  }
   if (__ballot(net_bad_any) != 0ull && m.lane == 0) atomicOr(mx.err, 2u);
   cnt[0] = n_acc - n_acc_l;
   cnt[1] = n_acc_l;
@@ -690,7 +724,7 @@ __device__ __forceinline__ void mixed_finish(const SweepArgs &a, const MixArgs &
   __syncthreads();
 }
 
-template <bool COUNT64, bool VEC2>
+template <bool COUNT64, bool VEC2, bool BINNED>
 __global__ __launch_bounds__(256) void mc_sweep_mixed_kernel(const SweepArgs a_in,
                                                              const MixArgs mx) {
   __shared__ __bf16 s_act[4][64 * kActStride];
@@ -698,7 +732,7 @@ __global__ __launch_bounds__(256) void mc_sweep_mixed_kernel(const SweepArgs a_i
   const SweepArgs a = resolve_sweep(a_in, 0u);
   const LaneMap m = lane_map(a);
   uint32_t cnt[3];
-  mixed_wave<COUNT64, VEC2>(a, mx, m, s_act[m.wib], s_tmp[m.wib], mx.net->shift, cnt);
+  mixed_wave<COUNT64, VEC2, BINNED>(a, mx, m, s_act[m.wib], s_tmp[m.wib], mx.net->shift, cnt);
   mixed_finish(a, mx, cnt);
 }
 

@@ -178,6 +178,10 @@ class Melt:
         """Iteration order of local moves: C.SOMA_SCHEME_SET or C.SOMA_SCHEME_MOLECULE."""
         C.soma_set_scheme(self.handle, scheme)
 
+    def set_histogram(self, mode: int):
+        """Count updates of SET sweeps: C.SOMA_HIST_DIRECT or C.SOMA_HIST_BINNED."""
+        C.soma_set_histogram(self.handle, mode)
+
     def choose_scheme(self, cycles: int, stream=None):
         """Times both orders and keeps the faster; returns (scheme, [ms SET, ms MOLECULE])."""
         return C.soma_choose_scheme(self.handle, cycles, _stream(stream))

@@ -27,6 +27,8 @@ SOMA_MOVE_MIXED = 2
 SOMA_MOVE_GIBBS = 3
 SOMA_SCHEME_SET = 0
 SOMA_SCHEME_MOLECULE = 1
+SOMA_HIST_DIRECT = 0
+SOMA_HIST_BINNED = 1
 SOMA_FLAG_POSITION = 1
 SOMA_FLAG_NETWORK = 2
 SOMA_ALL_SPECIES = 0xFFFFFFFF
@@ -109,6 +111,7 @@ _SIGS = {
     "soma_update_fields": ([_P, _P], _i32),
     "soma_rebuild_histogram": ([_P, _P], _i32),
     "soma_set_sweep_blocks": ([_P, _u32], _i32),
+    "soma_set_histogram": ([_P, _u32], _i32),
     "soma_set_scheme": ([_P, _u32], _i32),
     "soma_set_hamiltonian": ([_P, _u32, _P], _i32),
     "soma_set_types": ([_P, _u32, _P, _P, _u64, _P, _u64, _P], _i32),
@@ -204,6 +207,10 @@ def soma_update_fields(h, stream: int) -> None:
 
 def soma_set_sweep_blocks(h, blocks: int) -> None:
     _check(_lib.soma_set_sweep_blocks(h, blocks))
+
+
+def soma_set_histogram(h, mode: int) -> None:
+    _check(_lib.soma_set_histogram(h, mode))
 
 
 def soma_set_external(h, ext_ptr, ext_bytes: int, forbid_ptr, forbid_bytes: int, stream) -> None:
