@@ -27,6 +27,11 @@ import synth  # noqa: E402
 
 METRIC = "bead MC moves/s and uncorrelated samples/s, plain vs learned proposal, 1 GPU"
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0      # dense BF16 matrix cores (no sparsity)
+# the learned proposal's network 60 -> 64 -> 64 -> 6: 2 flop per weight
+FLOP_FORWARD = 2 * (60 * 64 + 64 * 64 + 64 * 6)                      # 16,640
+# training per sample: forward, errors back through layers 3 and 2, weight gradients
+FLOP_TRAIN_SAMPLE = FLOP_FORWARD + 2 * (6 * 64 + 64 * 64) + FLOP_FORWARD   # 42,240
 
 
 def algorithmic_bytes(w):
@@ -75,48 +80,101 @@ def measured_traffic(w, move: str):
     return rec["traffic_bytes"]
 
 
-def cpu_baseline(w, seconds: float):
-    """The oracle as it stands, OpenMP over chains on the host cores, on a
-    slab of the same melt (same density, chemistry and moves)."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_cycles(w, grid, n_chains, seconds, threads, *, learned=None, max_cycles=None):
+    """SCMF cycles of the oracle (sweep + histogram + fields) on n_chains chains
+    of w's species on `grid`, for about `seconds` (or max_cycles).  learned:
+    (params, p_learn) for mixed sweeps with the oracle's FP64 network.
+    Returns (bead moves per second, cycles, beads)."""
     import numpy as np
 
     import oracle
     from oracle import Species
 
+    s0 = w.species[0]
+    k0 = np.float32(3.0 * (w.n_ref - 1) / w.re_cells ** 2)
+    a = np.float32(w.a_frac * w.re_cells / math.sqrt(w.n_ref - 1))
+    n_beads = n_chains * s0.n
+    n_cells = grid[0] * grid[1] * grid[2]
+    inv_rho = np.float32(n_cells / n_beads)
+    sp = Species(n_chains, s0.n, s0.n_a)
+    pos = oracle.init_chains(sp, grid, bond_sigma=np.float32(1 / math.sqrt(float(k0))),
+                             seed=w.seed, origin_mode=1)
+
+    def fields():
+        return oracle.field_f32(oracle.density_hist(pos, [sp], grid), inv_rho,
+                                np.float32(w.chi_n), np.float32(w.kappa_n))
+    omega = fields()
+    cycles = 0
+    t0 = time.perf_counter()
+    while True:
+        if learned is None:
+            oracle.mc_sweep(pos, sp, omega, grid, k0=k0, n_ref=w.n_ref, step=a, seed=w.seed,
+                            sweep=cycles, threads=threads)
+        else:
+            params, p_learn = learned
+            oracle.mc_sweep_mixed(pos, sp, omega, grid, k0=k0, n_ref=w.n_ref, local_a=a,
+                                  p_learn=p_learn, params=params, m_max=1.0,
+                                  lo=math.log(0.02), hi=math.log(1.0), bf16_mode=False,
+                                  seed=w.seed, sweep=cycles, threads=threads)
+        omega = fields()
+        cycles += 1
+        dt = time.perf_counter() - t0
+        if (max_cycles is not None and cycles >= max_cycles) or \
+                (max_cycles is None and dt > seconds):
+            break
+    return n_beads * cycles / dt, cycles, n_beads
+
+
+def cpu_baseline(w, seconds: float):
+    """The oracle as it stands, OpenMP over chains on the host cores (the
+    paper's own CPU scheme), on bounded samples:
+      * a slab of the benchmark melt (same density, chemistry and moves),
+        all host threads: the reported value;
+      * the 1024-chain melt in full (100 cycles), one thread;
+      * a slab of the 262,144-chain learned-proposal melt with local moves and
+        with learned moves (the oracle's FP64 network, a random network of the
+        same shape), all host threads.
+    Cycles = sweep + histogram + fields, timed per call, excluding set-up."""
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     threads = max(1, min(threads, os.cpu_count() or 1))
     nx, ny, nz = w.grid
     slab_z = max(1, min(nz, 12))
-    frac = slab_z / nz
-    s0 = w.species[0]
-    n_chains = max(1, int(round(s0.n_chains * frac)))
-    sample = synth.Workload(w.name + "_slab", (nx, ny, slab_z),
-                            (synth.SpeciesSpec(n_chains, s0.n, s0.n_a),), w.re_cells, w.n_ref,
-                            w.chi_n, w.kappa_n, w.count_width, w.a_frac, w.smc_frac)
-    k0 = np.float32(3.0 * (w.n_ref - 1) / w.re_cells ** 2)
-    a = np.float32(w.a_frac * w.re_cells / math.sqrt(w.n_ref - 1))
-    inv_rho = np.float32(sample.n_cells / sample.n_beads)
-    sp = Species(n_chains, s0.n, s0.n_a)
-    pos = oracle.init_chains(sp, sample.grid, bond_sigma=np.float32(1 / math.sqrt(float(k0))),
-                             seed=w.seed, origin_mode=1)
-    omega = oracle.field_f32(oracle.density_hist(pos, [sp], sample.grid), inv_rho,
-                             np.float32(w.chi_n), np.float32(w.kappa_n))
-    sweeps = 0
-    t0 = time.perf_counter()
-    while True:
-        oracle.mc_sweep(pos, sp, omega, sample.grid, k0=k0, n_ref=w.n_ref, step=a, seed=w.seed,
-                        sweep=sweeps, threads=threads)
-        omega = oracle.field_f32(oracle.density_hist(pos, [sp], sample.grid), inv_rho,
-                                 np.float32(w.chi_n), np.float32(w.kappa_n))
-        sweeps += 1
-        if time.perf_counter() - t0 > seconds:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": sample.n_beads * sweeps / dt, "unit": "bead-moves/s", "cores": threads,
-            "kind": "oracle",
-            "sample": (f"{sweeps} SCMF cycles (local moves + histogram + fields) of a "
-                       f"{nx}x{ny}x{slab_z}-cell slab of the same melt: {n_chains} chains, "
-                       f"{sample.n_beads} beads, same density/chiN/kappaN")}
+    n_chains = max(1, int(round(w.species[0].n_chains * slab_z / nz)))
+    value, cycles, n_beads = _oracle_cycles(w, (nx, ny, slab_z), n_chains, seconds, threads)
+    out = {"value": value, "unit": "bead-moves/s", "cores": threads, "kind": "oracle",
+           "sample": (f"{cycles} SCMF cycles (local moves + histogram + fields) of a "
+                      f"{nx}x{ny}x{slab_z}-cell slab of the same melt: {n_chains} chains, "
+                      f"{n_beads} beads, same density/chiN/kappaN"),
+           "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
+    c1 = synth.C1_SMALL
+    v1, cyc1, nb1 = _oracle_cycles(c1, c1.grid, c1.species[0].n_chains, 0.0, 1, max_cycles=100)
+    out["single_thread_c1"] = {"value": v1, "unit": "bead-moves/s", "cores": 1,
+                               "sample": f"{c1.name} in full: {cyc1} cycles, {nb1} beads"}
+    c4 = synth.C4_MEDIUM
+    z4 = 6
+    n4 = int(round(c4.species[0].n_chains * z4 / c4.grid[2]))
+    vp, cp, nb4 = _oracle_cycles(c4, (c4.grid[0], c4.grid[1], z4), n4, seconds / 5, threads)
+    params = synth.mlp_params(1, out_gain=0.3)
+    vl, cl, _ = _oracle_cycles(c4, (c4.grid[0], c4.grid[1], z4), n4, seconds / 2, threads,
+                               learned=(params, 1.0), max_cycles=None)
+    out["c4_slab"] = {"sample": f"{c4.grid[0]}x{c4.grid[1]}x{z4}-cell slab of {c4.name}: "
+                                f"{n4} chains, {nb4} beads", "cores": threads,
+                      "plain_bead_moves_per_s": vp, "plain_cycles": cp,
+                      "learned_bead_moves_per_s": vl, "learned_cycles": cl,
+                      "learned_network": "60-64-64-6 MLP in FP64 (the oracle's), random "
+                                         "weights, every move learned (p_learn = 1)"}
+    return out
 
 
 def _re_vectors(melt, n):
@@ -124,8 +182,9 @@ def _re_vectors(melt, n):
     return (x[:, -1] - x[:, 0]).double()
 
 
-def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: int,
-                equil_cycles: int, substeps: int, lag: int = 64):
+def learned_leg(p_learn: float, equil_cycles: int, substeps: int, lag: int = 64,
+                n_rep: int = 8, side: int = 32, tau_scale: float = 1.0,
+                train_steps: int = 3000):
     """Plain vs learned proposal on the 262,144-chain melt (96^3 cells, chiN 25).
 
     1. Training data from the plain sampler: 10 rounds of 2^20 random beads,
@@ -140,20 +199,21 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
        with a field refresh after each: its moves are large, and the
        quasi-instantaneous field approximation needs few beads moved between two
        refreshes to give the plain sampler's observables (end-to-end distance).
-    3. The melt equilibrated with the learned sampler for `equil_cycles` cycles,
-       the network fine-tuned on plain trajectories from that state (4 x 2^20
-       samples), then tau_int (Sokal window) of the end-to-end vectors of every
-       16th chain from frames every `frame_cycles` cycles (plain: `plain_mult`
-       times as many cycles between frames), learned run first.  Uncorrelated
-       samples/s = n_chains * cycles/s / (2 tau_int), cycles/s from step 2.
-    4. As context, the analytic bond-Gibbs proposal (each bead drawn from its
-       law given its bonded neighbours, accepted on the field term alone) with
-       the learned sampler's sub-steps, measured the same way after the plain
-       run.
+    3. The melt equilibrated with the learned sampler for `equil_cycles` cycles
+       and the network fine-tuned on plain trajectories from that state
+       (4 x 2^20 samples).
+    4. tau_int and <Re^2> of the plain, learned and (as context) bond-Gibbs
+       samplers from n_rep independent replicas of a side^3-cell melt at the
+       same density and chiN (replica_statistics): discarded transients of
+       about 3 tau_int, measured runs of about 50 tau_int, seed-to-seed
+       standard errors.  Uncorrelated samples/s = n_chains * cycles/s /
+       (2 tau_int), cycles/s of the full melt from step 2.  The bond-Gibbs
+       proposal draws each bead from its law given its bonded neighbours and
+       is accepted on the field term alone.
     """
     import torch
 
-    from paper_1711_03828_amd import analysis, learned
+    from paper_1711_03828_amd import learned
     from paper_1711_03828_amd import soma as C
     from paper_1711_03828_amd.melt import Melt, make_config
 
@@ -164,20 +224,37 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
     feats, disp = learned.collect(melt, 1 << 20, lag, 10)
     params = learned.init_params(feats, seed=1)
     tr = learned.Trainer(params, lr=3e-3)
-    losses = tr.run(feats, disp, steps=3000, batch=8192, loss_every=500)
+    losses = tr.run(feats, disp, steps=train_steps, batch=8192, loss_every=500)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     n_samples = int(feats.shape[0])
-    del feats, disp
-    melt.set_proposal(params)
     stream = torch.cuda.current_stream()
+    # matrix-core roofline of a training step (batch 8192, lr 0 on a copy of
+    # the network): forward, back-propagation to the first hidden layer and
+    # the weight gradients, 42,240 flop per sample
+    probe = learned.Trainer(params.clone(), lr=0.0)
+    probe.run(feats, disp, steps=5, batch=8192, loss_every=5)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    probe.run(feats, disp, steps=50, batch=8192, loss_every=50)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1) / 50
+    del probe, feats, disp
+    melt.set_proposal(params)
     out = {"workload": w.name, "p_learn": p_learn,
-           "training": {"samples": n_samples, "lag_cycles": lag, "adam_steps": 3000,
+           "training": {"samples": n_samples, "lag_cycles": lag, "adam_steps": train_steps,
                         "batch": 8192, "loss_first": losses[0], "loss_last": losses[-1],
                         "seconds_collect_and_train": t_train}}
+    flop_train = 8192 * FLOP_TRAIN_SAMPLE
+    out["roofline_train_step"] = {
+        "bound": "mfma", "achieved": flop_train / (train_ms * 1e-3) / 1e12,
+        "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+        "frac": flop_train / (train_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, "traffic": None,
+        "kernel": "mlp_grad_kernel + mlp_adam_kernel", "ms_per_step": train_ms,
+        "flop_per_step": flop_train, "flop_per_sample": FLOP_TRAIN_SAMPLE}
     rates = {}
     ksub = {"plain": 1, "learned": substeps, "gibbs": substeps}
-    kidx = {C.SOMA_MOVE_LOCAL: 0, C.SOMA_MOVE_MIXED: 2, C.SOMA_MOVE_GIBBS: 3}
     for name, kind in (("plain", C.SOMA_MOVE_LOCAL), ("learned", C.SOMA_MOVE_MIXED),
                        ("gibbs", C.SOMA_MOVE_GIBBS)):
         melt.set_substeps(ksub[name])
@@ -192,13 +269,31 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
         rates[name] = 1e3 / ms
         out[name] = {"ms_per_cycle": ms, "bead_moves_per_s": w.n_beads * 1e3 / ms,
                      "substeps": ksub[name]}
+    # matrix-core roofline of the mixed sweep: every learned move evaluates the
+    # network at r and at r' (2 x 16,640 flop); sweeps with the fields frozen,
+    # HIP events on the launch stream
+    melt.set_substeps(1)
+    melt.sweep(2, C.SOMA_MOVE_MIXED)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    melt.sweep(10, C.SOMA_MOVE_MIXED)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    mixed_ms = e0.elapsed_time(e1) / 10
+    flop_sweep = w.n_beads * p_learn * 2 * FLOP_FORWARD
+    out["roofline_mixed_sweep"] = {
+        "bound": "mfma", "achieved": flop_sweep / (mixed_ms * 1e-3) / 1e12,
+        "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+        "frac": flop_sweep / (mixed_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, "traffic": None,
+        "kernel": "mc_sweep_mixed_kernel", "kernel_ms": mixed_ms, "flop_per_launch": flop_sweep,
+        "flop_per_learned_move": 2 * FLOP_FORWARD}
     obs = melt.observables()
     out["learned"]["acceptance"] = obs.accepted[2] / max(1, obs.attempted[2])
     out["plain"]["acceptance"] = obs.accepted[0] / max(1, obs.attempted[0])
     out["gibbs"]["acceptance"] = obs.accepted[3] / max(1, obs.attempted[3])
 
-    # equilibrate the full melt with the learned sampler, fine-tune on plain
-    # trajectories from that state, then the tau_int runs on the full melt
+    # equilibrate the full melt with the learned sampler, then fine-tune on
+    # plain trajectories from that state
     melt.set_substeps(substeps)
     melt.capture_cycle(100, C.SOMA_MOVE_MIXED)
     melt.run_cycle(max(1, equil_cycles // 100))
@@ -211,53 +306,143 @@ def learned_leg(p_learn: float, sub_frames: int, frame_cycles: int, plain_mult: 
     out["training"]["fine_tune"] = {"samples": 4 << 20, "adam_steps": 2000,
                                     "loss_first": tl[0], "loss_last": tl[-1],
                                     "after_learned_cycles": equil_cycles}
-    stride = 16                              # end-to-end vectors of every 16th chain
-    # the bond-Gibbs run last: its stationary state differs most from the plain
-    # sampler's, and a run that starts away from its own state pays a transient
-    for name, kind, mult in (("learned", C.SOMA_MOVE_MIXED, 1),
-                             ("plain", C.SOMA_MOVE_LOCAL, plain_mult),
-                             ("gibbs", C.SOMA_MOVE_GIBBS, 1)):
-        melt.set_substeps(ksub[name])
-        melt.capture_cycle(frame_cycles * mult, kind)
-        n_frames = sub_frames
-        o0 = melt.observables()
-        re = torch.empty((n_frames, w.n_chains // stride, 3), dtype=torch.float32,
-                         device="cuda")
-        for f in range(n_frames):
-            melt.run_cycle(1)
-            re[f] = _re_vectors(melt, 32)[::stride].float()
-        o1 = melt.observables()
-        series = re.reshape(n_frames, -1).cpu().numpy()
-        tau_frames, window = analysis.tau_int(series)
-        step = frame_cycles * mult
-        tau = tau_frames * step
-        re2 = float((re.double() ** 2).sum(-1).mean()) / w.re_cells ** 2
-        k = kidx[kind]
-        # statistical error of tau_int from the pooled series (Sokal: var(tau)/tau^2 =
-        # 2 (2M + 1) / n for one series of n frames and window M; m pooled, nearly
-        # independent series divide it by m); the window's truncation bias is not in it
-        m_series = series.shape[1]
-        tau_err = tau * math.sqrt(2.0 * (2 * window + 1) / (n_frames * m_series))
-        out[name].update({"tau_int_cycles": tau, "tau_int_err_cycles": tau_err,
-                          "window_frames": window,
-                          "frames": n_frames, "cycles_per_frame": step,
-                          "re2_over_re02": re2,
-                          "acceptance_tau_run": (o1.accepted[k] - o0.accepted[k]) /
-                                                max(1, o1.attempted[k] - o0.attempted[k]),
-                          "uncorrelated_samples_per_s":
-                              w.n_chains * rates[name] / (2.0 * tau)})
-        print(f"# {name}: tau_int {tau:.1f} cycles (window {window} frames), "
-              f"<Re^2>/Re0^2 {re2:.4f}", file=sys.stderr, flush=True)
     melt.close()
-    out["gain_uncorrelated_samples_per_s"] = (out["learned"]["uncorrelated_samples_per_s"] /
-                                              out["plain"]["uncorrelated_samples_per_s"])
-    rel = math.hypot(out["learned"]["tau_int_err_cycles"] / out["learned"]["tau_int_cycles"],
-                     out["plain"]["tau_int_err_cycles"] / out["plain"]["tau_int_cycles"])
-    out["gain_err"] = out["gain_uncorrelated_samples_per_s"] * rel
-    out["gibbs_gain_over_plain"] = (out["gibbs"]["uncorrelated_samples_per_s"] /
-                                    out["plain"]["uncorrelated_samples_per_s"])
-    out["learned_over_gibbs"] = (out["learned"]["uncorrelated_samples_per_s"] /
-                                 out["gibbs"]["uncorrelated_samples_per_s"])
+    if tau_scale > 0:
+        out["statistics"] = replica_statistics(params, substeps, p_learn, rates, n_rep, side,
+                                               tau_scale)
+    return out
+
+
+def _c4_subsystem(side: int):
+    """The learned-proposal melt's chemistry and density (262,144 A16B16 chains
+    on 96^3 cells: 9.48 beads per cell, chiN 25, kappaN 50) in a box of side^3
+    cells."""
+    w = synth.C4_MEDIUM
+    n = int(round(w.species[0].n_chains * side ** 3 / w.n_cells))
+    return synth.Workload(f"diblock_{n}_N32_grid{side}", (side, side, side),
+                          (synth.SpeciesSpec(n, 32, 16),), w.re_cells, w.n_ref, w.chi_n,
+                          w.kappa_n, w.count_width)
+
+
+# Per sampler: (move kind, chain subsets per cycle, cycles per frame, frames
+# discarded, frames measured).  Run lengths aim at >= 3 tau_int discarded and
+# >= 50 tau_int measured for tau_int of about 9,000 (plain), 500 (learned)
+# and 400 (bond-Gibbs) cycles; the JSON states the ratio actually reached.
+def _replica_plan(C, substeps: int, scale: float):
+    def n(x):
+        return max(20, int(round(x * scale)))
+    return {"plain": (C.SOMA_MOVE_LOCAL, 1, 200, n(150), n(2300)),
+            "learned": (C.SOMA_MOVE_MIXED, substeps, 10, n(160), n(2600)),
+            "gibbs": (C.SOMA_MOVE_GIBBS, substeps, 10, n(130), n(2100))}
+
+
+def replica_statistics(params, substeps: int, p_learn: float, rates: dict, n_rep: int,
+                       side: int, scale: float):
+    """tau_int and <Re^2> of each sampler from independent replicas.
+
+    n_rep replicas (independent Philox streams: replica index r) of the
+    learned-proposal melt's chemistry at its density in a side^3-cell box, all
+    in one batched launch.  A common start (bond-Gibbs cycles from the Gaussian
+    walks), then per sampler a discarded transient and a measured run; frames
+    of all chains' end-to-end vectors every few cycles.  Per replica: tau_int
+    (Sokal window over its chains' pooled autocorrelation) and <Re^2>; means
+    and standard errors over the replicas (seed-to-seed spread).  Uncorrelated
+    samples/s use the full melt's cycle rate (`rates`, cycles/s) and the
+    replicas' tau_int; the learned/plain gain carries the propagated seed
+    errors, and the shift of <Re^2> between samplers is given in units of its
+    standard error."""
+    import numpy as np
+    import torch
+
+    from paper_1711_03828_amd import analysis
+    from paper_1711_03828_amd import soma as C
+    from paper_1711_03828_amd.melt import Batch, Melt, make_config
+
+    w = _c4_subsystem(side)
+    nch = w.species[0].n_chains
+    n_obs = (nch + 1) // 2          # end-to-end vectors of every second chain
+    melts = [Melt(make_config(w, replica=r, p_learn=p_learn)) for r in range(n_rep)]
+    for m in melts:
+        m.set_proposal(params)
+    batch = Batch(melts)
+    t0 = time.perf_counter()
+    equil = max(100, int(round(8000 * scale)) // 100 * 100)
+    batch.set_substeps(substeps)
+    batch.capture_cycle(100, C.SOMA_MOVE_GIBBS)
+    batch.run_cycle(equil // 100)
+    out = {"workload": (f"{n_rep} replicas (independent Philox streams) of {w.name}: "
+                        f"{nch} A16B16 chains on {side}^3 cells, the density and chiN of the "
+                        f"262,144-chain melt; one batched launch; end-to-end vectors of "
+                        f"every second chain"),
+           "common_start_gibbs_cycles": equil}
+    kidx = {C.SOMA_MOVE_LOCAL: 0, C.SOMA_MOVE_MIXED: 2, C.SOMA_MOVE_GIBBS: 3}
+    for name, (kind, ksub, fc, discard, frames) in _replica_plan(C, substeps, scale).items():
+        batch.set_substeps(ksub)
+        batch.capture_cycle(fc, kind)
+        batch.run_cycle(discard)
+        o0 = [m.observables() for m in melts]
+        re = torch.empty((frames, n_rep, n_obs, 3), dtype=torch.float32, device="cuda")
+        for f in range(frames):
+            batch.run_cycle(1)
+            for r, m in enumerate(melts):
+                x = m.pos.view(nch, 32, 3)[::2]
+                re[f, r] = x[:, -1] - x[:, 0]
+        o1 = [m.observables() for m in melts]
+        k = kidx[kind]
+        acc = (sum(b.accepted[k] - a.accepted[k] for a, b in zip(o0, o1)) /
+               max(1, sum(b.attempted[k] - a.attempted[k] for a, b in zip(o0, o1))))
+        re_np = re.cpu().numpy().astype(np.float64)
+        del re
+        taus, re2s = [], []
+        for r in range(n_rep):
+            series = re_np[:, r].reshape(frames, -1)
+            t_frames, _ = analysis.tau_int(series)
+            taus.append(t_frames * fc)
+            re2s.append(float((re_np[:, r] ** 2).sum(-1).mean()) / w.re_cells ** 2)
+        taus, re2s = np.array(taus), np.array(re2s)
+        tau = float(taus.mean())
+        tau_err = float(taus.std(ddof=1) / math.sqrt(n_rep))
+        out[name] = {"tau_int_cycles": tau, "tau_int_err_cycles": tau_err,
+                     "tau_int_replicas": [round(float(t), 2) for t in taus],
+                     "re2_over_re02": float(re2s.mean()),
+                     "re2_err": float(re2s.std(ddof=1) / math.sqrt(n_rep)),
+                     "re2_replicas": [round(float(v), 5) for v in re2s],
+                     "discarded_cycles": discard * fc, "measured_cycles": frames * fc,
+                     "discarded_over_tau": discard * fc / tau,
+                     "measured_over_tau": frames * fc / tau,
+                     "cycles_per_frame": fc, "substeps": ksub, "acceptance": acc,
+                     "uncorrelated_samples_per_s":
+                         synth.C4_MEDIUM.n_chains * rates[name] / (2.0 * tau)}
+        print(f"# replicas {name}: tau_int {tau:.1f} +- {tau_err:.1f} cycles, <Re^2>/Re0^2 "
+              f"{re2s.mean():.4f} +- {out[name]['re2_err']:.4f}, run {frames * fc / tau:.1f} tau",
+              file=sys.stderr, flush=True)
+    batch.close()
+    for m in melts:
+        m.close()
+
+    def ratio(a, b):
+        g = out[a]["uncorrelated_samples_per_s"] / out[b]["uncorrelated_samples_per_s"]
+        rel = math.hypot(out[a]["tau_int_err_cycles"] / out[a]["tau_int_cycles"],
+                         out[b]["tau_int_err_cycles"] / out[b]["tau_int_cycles"])
+        shift = ((out[a]["re2_over_re02"] - out[b]["re2_over_re02"]) /
+                 math.hypot(out[a]["re2_err"], out[b]["re2_err"]))
+        return g, g * rel, shift
+
+    g, ge, sh = ratio("learned", "plain")
+    out["gain_learned_over_plain"] = g
+    out["gain_err"] = ge
+    out["re2_shift_learned_vs_plain_sigma"] = sh
+    # the gain counts as one at equal observable accuracy only if <Re^2> agrees
+    # within three standard errors
+    out["gain_at_equal_accuracy"] = g if abs(sh) < 3.0 else None
+    g2, ge2, sh2 = ratio("gibbs", "plain")
+    out["gain_gibbs_over_plain"] = g2
+    out["gain_gibbs_err"] = ge2
+    out["re2_shift_gibbs_vs_plain_sigma"] = sh2
+    g3, ge3, sh3 = ratio("learned", "gibbs")
+    out["learned_over_gibbs"] = g3
+    out["learned_over_gibbs_err"] = ge3
+    out["seconds"] = time.perf_counter() - t0
     return out
 
 
@@ -674,15 +859,25 @@ def main():
                     help="probability of the learned move per bead (else the local move)")
     ap.add_argument("--learned-substeps", type=int, default=2,
                     help="chain subsets (field refreshes) per cycle for the learned sampler")
-    ap.add_argument("--tau-frames", type=int, default=400, help="frames per tau_int run")
+    ap.add_argument("--replicas", type=int, default=8,
+                    help="independent replicas for tau_int and <Re^2> of each sampler")
+    ap.add_argument("--replica-side", type=int, default=32,
+                    help="cells per side of a replica (the learned-proposal melt's density)")
+    ap.add_argument("--tau-scale", type=float, default=1.0,
+                    help="scales the replica runs' lengths (1: about 50 tau_int measured; "
+                         "0: no replica runs)")
+    ap.add_argument("--train-steps", type=int, default=3000,
+                    help="Adam steps of the first training of the learned proposal")
+    ap.add_argument("--tau-frames", type=int, default=400,
+                    help="frames per tau_int run of the blend leg")
     ap.add_argument("--frame-cycles", type=int, default=50,
-                    help="cycles between frames of the learned run")
+                    help="cycles between frames of the blend leg's learned run")
     ap.add_argument("--equil-cycles", type=int, default=20000,
                     help="learned-sampler cycles before the tau_int runs")
     ap.add_argument("--plain-frame-mult", type=int, default=8,
-                    help="the plain run's frames are this many times further apart")
-    ap.add_argument("--blend", action="store_true",
-                    help="also run the ternary-blend batched learned-proposal measurement")
+                    help="the blend leg's plain frames are this many times further apart")
+    ap.add_argument("--no-blend", action="store_true",
+                    help="skip the ternary-blend batched learned-proposal measurement")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-replica batched measurement")
     ap.add_argument("--no-schemes", action="store_true",
@@ -842,15 +1037,30 @@ def main():
     obs = melt.observables()
     smc["acceptance"] = obs.accepted[1] / max(1, obs.attempted[1])
     result["smart_mc"] = smc
+    # local and smart-MC moves 50/50: cycles of the two kinds alternating (the
+    # composition of two kernels that each leave the distribution invariant)
+    for _ in range(2):
+        melt.cycle(1, C.SOMA_MOVE_LOCAL)
+        melt.cycle(1, C.SOMA_MOVE_SMC)
+    e0.record(stream)
+    for _ in range(10):
+        melt.cycle(1, C.SOMA_MOVE_LOCAL)
+        melt.cycle(1, C.SOMA_MOVE_SMC)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    mix_ms = e0.elapsed_time(e1) / 20
+    result["local_smc_mixture"] = {"ms_per_cycle": mix_ms,
+                                   "bead_moves_per_s": w.n_beads * 1e3 / mix_ms,
+                                   "cycles": 20, "order": "local and smart-MC cycles alternating"}
     melt.close()
     copy = copy_bandwidth()
     result["roofline"]["copy_bandwidth"] = copy
     result["roofline"]["frac_of_copy_hbm"] = achieved / copy["hbm_4GiB"]
     if not args.no_learned:
-        result["learned_proposal"] = learned_leg(args.p_learn, args.tau_frames,
-                                                 args.frame_cycles, args.plain_frame_mult,
-                                                 args.equil_cycles, args.learned_substeps,
-                                                 args.learned_lag)
+        result["learned_proposal"] = learned_leg(args.p_learn, args.equil_cycles,
+                                                 args.learned_substeps, args.learned_lag,
+                                                 args.replicas, args.replica_side,
+                                                 args.tau_scale, args.train_steps)
     if not args.no_batched:
         result["batched"] = batched_leg(50)
     if not args.no_schemes:
@@ -861,7 +1071,7 @@ def main():
         result["film"] = film_leg(args.film, args.film_lateral, args.film_cycles)
         if args.film == "lam" and not args.no_second_film:   # the paper's second film system
             result["film_hex"] = film_leg("hex", args.film_lateral, args.film_cycles)
-    if args.blend:
+    if not args.no_blend:
         result["blend"] = blend_leg(50, args.tau_frames // 2, args.frame_cycles,
                                     args.plain_frame_mult, args.equil_cycles // 2, 1.0 / 16,
                                     args.learned_substeps, args.p_learn, args.learned_lag)

@@ -74,7 +74,7 @@ typedef enum soma_status {
  * FP64, xi by Box-Muller from the smart-MC draws.  The bond energy and the
  * proposal densities cancel in the Metropolis-Hastings ratio of Sec. 2.2, so
  * a move is accepted with min(1, exp(-(omega(c') - omega(c))/N)).  Linear
- * chains, SET order; not in batched sweeps. */
+ * chains, SET order (single melts and batches). */
 #define SOMA_MOVE_GIBBS 3u
 
 /* Iteration orders of local moves (Sec. 3.1.2). */
@@ -306,6 +306,12 @@ int32_t soma_type_counts(soma_system *sys, uint64_t *out, uint32_t n_out, void *
  * A multiple of 8 keeps each XCD on one contiguous range of chains. */
 int32_t soma_set_sweep_blocks(soma_system *sys, uint32_t blocks);
 
+/* Threads per block (64, 128, ..., 512; default 256) of the local, smart-MC
+ * and bond-Gibbs sweeps in the SET order: each wave of 64 lanes holds the
+ * same chains whatever the block size, so results are identical for every
+ * value.  SOMA_E_INVAL for other values.  Capture graphs again after a change. */
+int32_t soma_set_sweep_threads(soma_system *sys, uint32_t threads);
+
 /* Count updates of the SET-order sweeps (local, smart-MC, bond-Gibbs and
  * mixed moves of linear chains; the histogram of Eq. (4), Sec. 3.1.1).
  * SOMA_HIST_DIRECT: a bead that changes cell adds -1 and +1 to the packed
@@ -406,7 +412,17 @@ typedef struct soma_tune {
   uint32_t candidates;    /* shapes timed */
   uint32_t cycles_run;    /* SCMF cycles run while tuning */
   uint32_t from_cache;
+  uint32_t hist_mode;     /* single systems: SOMA_HIST_DIRECT or SOMA_HIST_BINNED */
+  uint32_t block_threads; /* single systems: threads per block of the sweep */
 } soma_tune;
+/* Single systems, SET order: the search space is the histogram mode
+ * (SOMA_HIST_DIRECT, and SOMA_HIST_BINNED where the grid allows it) x the
+ * block size of the local, smart-MC and bond-Gibbs sweeps (128, 256, 512
+ * threads; the mixed sweep always runs 256) x, for local moves, the grid (one
+ * block per tile group, or 2048 persistent blocks): up to 12 candidates.
+ * Molecule order: the grid caps {none, 256, 512, 1024, 2048}.  Batches: the
+ * item order (XCD ranges or round-robin) x the grid {one block per item, 2048,
+ * 8192}. */
 int32_t soma_autotune(soma_system *sys, uint32_t cycles, uint32_t move_kind,
                       const char *cache_path, void *stream, soma_tune *out);
 

@@ -152,14 +152,16 @@ int32_t derive(const soma_config *c, Derived *d) {
   d->n_bricks = (uint64_t)d->nbx * d->nby * d->nbz;
   d->bins_ok = d->n_bricks < (1ull << 21);
   if (d->bins_ok) {
+    // per sub-bin: twice its share of about half a brick's beads, plus slack
+    // (a recount fills about half a brick's beads, a smart-MC sweep about 0.45)
     const double per_brick = (double)d->n_beads * soma::kBrickCells / (double)n_cells;
-    uint64_t cap = (uint64_t)std::ceil(0.55 * per_brick) + 256u;
-    cap = (cap + 63u) / 64u * 64u;
-    if (cap > (1ull << 26)) cap = 1ull << 26;
+    uint64_t cap = (uint64_t)std::ceil(1.1 * per_brick / soma::kSubBins) + 64u;
+    cap = (cap + 15u) / 16u * 16u;
+    if (cap > (1ull << 22)) cap = 1ull << 22;
     d->bin_cap = (uint32_t)cap;
     d->off_bin_count = d->ws_bytes;
-    d->off_bins = align_up(d->off_bin_count + 4ull * d->n_bricks);
-    d->ws_bytes = align_up(d->off_bins + 4ull * d->n_bricks * cap);
+    d->off_bins = align_up(d->off_bin_count + 4ull * d->n_bricks * soma::kSubBins);
+    d->ws_bytes = align_up(d->off_bins + 4ull * d->n_bricks * soma::kSubBins * cap);
   }
   return SOMA_OK;
 }
@@ -189,11 +191,41 @@ int32_t launch_zero(void *p, uint64_t bytes, hipStream_t s) {
   return SOMA_OK;
 }
 
+// From-scratch histogram.  With bins (`bins` not null: the system's workspace
+// holds them), each species' beads go through the per-brick bins and one
+// apply pass per brick; otherwise one device atomic per bead.
 int32_t launch_hist(const soma_config *c, const Derived &d, const float *pos, void *counts,
-                    hipStream_t s) {
+                    hipStream_t s, const soma::BinArgs *bins = nullptr) {
   int32_t rc = launch_zero(counts, d.counts_bytes, s);
   if (rc) return rc;
   const soma::Grid g = make_grid(c, d.n_cells);
+  if (bins) {
+    for (uint32_t sp = 0; sp < c->n_species; ++sp) {
+      const soma_species &S = c->species[sp];
+      const uint64_t nb = (uint64_t)S.n_chains * S.n;
+      if (!nb) continue;
+      const uint64_t blocks = ((nb + 1) / 2 + 255) / 256;
+      const float *p = pos + 3 * d.bead_off[sp];
+      const uint32_t v2 = (reinterpret_cast<uintptr_t>(p) % 8u) == 0u ? 1u : 0u;
+      if (c->count_width == 32)
+        hipLaunchKernelGGL(soma::density_hist_binned_kernel<true>, dim3((uint32_t)blocks),
+                           dim3(256), 0, s, p, nb, S.n, S.n_a, g, counts, d.arch[sp], *bins, v2);
+      else
+        hipLaunchKernelGGL(soma::density_hist_binned_kernel<false>, dim3((uint32_t)blocks),
+                           dim3(256), 0, s, p, nb, S.n, S.n_a, g, counts, d.arch[sp], *bins, v2);
+      LAUNCH_TRY();
+    }
+    const uint32_t planes = (d.n_types + 1u) / 2u;
+    const size_t lds = (size_t)planes * soma::kBrickCells * (c->count_width == 32 ? 8u : 4u);
+    if (c->count_width == 32)
+      hipLaunchKernelGGL(soma::bin_apply_kernel<true>, dim3((uint32_t)d.n_bricks), dim3(256), lds,
+                         s, *bins, g, counts, planes);
+    else
+      hipLaunchKernelGGL(soma::bin_apply_kernel<false>, dim3((uint32_t)d.n_bricks), dim3(256),
+                         lds, s, *bins, g, counts, planes);
+    LAUNCH_TRY();
+    return SOMA_OK;
+  }
   for (uint32_t sp = 0; sp < c->n_species; ++sp) {
     const soma_species &S = c->species[sp];
     const uint64_t nb = (uint64_t)S.n_chains * S.n;
@@ -340,6 +372,7 @@ struct soma_system {
   uint32_t substeps = 1;      // field refreshes per SCMF cycle (chain subsets)
   uint32_t scheme = SOMA_SCHEME_SET;  // iteration order of local moves
   uint32_t hist_mode = soma::kHistDirect;  // count updates of the SET sweeps (soma_set_histogram)
+  uint32_t sweep_threads = 256;  // block size of the local, smart-MC and bond-Gibbs sweeps
   float4 *grad = nullptr;     // optional gradient field (caller-owned), see soma_set_grad_field
   unsigned char *ws = nullptr;
   CycleGraph graph;
@@ -383,24 +416,34 @@ struct soma_system {
 
 namespace {
 
+// The system's recount goes through the bins whenever its grid has them.
+int32_t launch_hist_sys(soma_system *sys, hipStream_t s) {
+  soma::BinArgs b;
+  if (sys->d.bins_ok) b = sys->bins();
+  return launch_hist(&sys->cfg, sys->d, sys->buf.pos, sys->buf.counts, s,
+                     sys->d.bins_ok ? &b : nullptr);
+}
+
+// The mixed kernel's LDS tiles are laid out for four waves: it always runs
+// 256-thread blocks; the others take `threads` (64..512).
 template <bool C64, bool V2, bool B>
-void launch_sweep_t(uint32_t kind, dim3 grid, hipStream_t s, const soma::SweepArgs &a,
-                    const soma::MixArgs &mx) {
+void launch_sweep_t(uint32_t kind, dim3 grid, dim3 threads, hipStream_t s,
+                    const soma::SweepArgs &a, const soma::MixArgs &mx) {
   if (kind == SOMA_MOVE_MIXED)
     hipLaunchKernelGGL((soma::mc_sweep_mixed_kernel<C64, V2, B>), grid, dim3(256), 0, s, a, mx);
   else if (kind == SOMA_MOVE_SMC)
-    hipLaunchKernelGGL((soma::mc_sweep_smc_kernel<C64, V2, B>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((soma::mc_sweep_smc_kernel<C64, V2, B>), grid, threads, 0, s, a);
   else if (kind == SOMA_MOVE_GIBBS)
-    hipLaunchKernelGGL((soma::mc_sweep_gibbs_kernel<C64, V2, B>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((soma::mc_sweep_gibbs_kernel<C64, V2, B>), grid, threads, 0, s, a);
   else
-    hipLaunchKernelGGL((soma::mc_sweep_local_kernel<C64, V2, B>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((soma::mc_sweep_local_kernel<C64, V2, B>), grid, threads, 0, s, a);
 }
 
 template <bool C64, bool V2>
-void launch_sweep_b(bool binned, uint32_t kind, dim3 grid, hipStream_t s,
+void launch_sweep_b(bool binned, uint32_t kind, dim3 grid, dim3 threads, hipStream_t s,
                     const soma::SweepArgs &a, const soma::MixArgs &mx) {
-  if (binned) launch_sweep_t<C64, V2, true>(kind, grid, s, a, mx);
-  else launch_sweep_t<C64, V2, false>(kind, grid, s, a, mx);
+  if (binned) launch_sweep_t<C64, V2, true>(kind, grid, threads, s, a, mx);
+  else launch_sweep_t<C64, V2, false>(kind, grid, threads, s, a, mx);
 }
 
 // Adds the binned count updates of the sweeps before it to the counts (one
@@ -516,18 +559,19 @@ int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s, uint32_t of
       LAUNCH_TRY();
       continue;
     }
-    const uint64_t chains_per_block = 4ull * a.chains_per_wave;
+    const uint32_t threads = kind == SOMA_MOVE_MIXED ? 256u : sys->sweep_threads;
+    const uint64_t chains_per_block = (uint64_t)(threads / 64u) * a.chains_per_wave;
     uint64_t blocks = (a.n_sub + chains_per_block - 1) / chains_per_block;
     if (kind == SOMA_MOVE_LOCAL && sys->sweep_blocks && sys->sweep_blocks < blocks)
       blocks = sys->sweep_blocks;
     const bool v2 = species_vec2(sys, sp);
-    const dim3 grid((uint32_t)blocks);
+    const dim3 grid((uint32_t)blocks), block(threads);
     if (c64) {
-      if (v2) launch_sweep_b<true, true>(binned, kind, grid, s, a, mx);
-      else launch_sweep_b<true, false>(binned, kind, grid, s, a, mx);
+      if (v2) launch_sweep_b<true, true>(binned, kind, grid, block, s, a, mx);
+      else launch_sweep_b<true, false>(binned, kind, grid, block, s, a, mx);
     } else {
-      if (v2) launch_sweep_b<false, true>(binned, kind, grid, s, a, mx);
-      else launch_sweep_b<false, false>(binned, kind, grid, s, a, mx);
+      if (v2) launch_sweep_b<false, true>(binned, kind, grid, block, s, a, mx);
+      else launch_sweep_b<false, false>(binned, kind, grid, block, s, a, mx);
     }
     LAUNCH_TRY();
     any_binned |= binned;
@@ -683,7 +727,7 @@ int32_t soma_init_system(const soma_config *cfg, const soma_buffers *buf, uint32
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   rc = launch_zero(sys->ws, d.ws_bytes, s);
   if (!rc && init_positions) rc = launch_init(cfg, d, buf->pos, s);
-  if (!rc) rc = launch_hist(cfg, d, buf->pos, buf->counts, s);
+  if (!rc) rc = launch_hist_sys(sys, s);
   if (!rc) rc = launch_field(cfg, d, buf->counts, buf->omega, sys->fpart(), s, sys->halo());
   if (rc) {
     delete sys;
@@ -780,10 +824,17 @@ int32_t soma_set_sweep_blocks(soma_system *sys, uint32_t blocks) {
   return SOMA_OK;
 }
 
+int32_t soma_set_sweep_threads(soma_system *sys, uint32_t threads) {
+  if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
+  if (threads < 64 || threads > 512 || threads % 64)
+    return fail(SOMA_E_INVAL, "sweep threads must be 64, 128, ..., 512");
+  sys->sweep_threads = threads;
+  return SOMA_OK;
+}
+
 int32_t soma_rebuild_histogram(soma_system *sys, void *stream) {
   if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
-  return launch_hist(&sys->cfg, sys->d, sys->buf.pos, sys->buf.counts,
-                     reinterpret_cast<hipStream_t>(stream));
+  return launch_hist_sys(sys, reinterpret_cast<hipStream_t>(stream));
 }
 
 int32_t soma_update_fields(soma_system *sys, void *stream) {
@@ -977,7 +1028,7 @@ int32_t soma_set_architecture(soma_system *sys, uint32_t species, const uint32_t
   }
   sys->d.n_a_total = n_a;
   sys->graph.release();
-  int32_t rc = launch_hist(&sys->cfg, sys->d, sys->buf.pos, sys->buf.counts, s);
+  int32_t rc = launch_hist_sys(sys, s);
   if (!rc) rc = refresh_fields(sys, s);
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(s));
@@ -1031,7 +1082,7 @@ int32_t soma_set_types(soma_system *sys, uint32_t n_types, const float *chi_n, v
   sys->d.counts_bytes = planes * n_cells * word;
   sys->d.omega_bytes = 4ull * n_types * n_cells;
   sys->graph.release();   // captured launches hold the old buffers
-  int32_t rc = launch_hist(&sys->cfg, sys->d, sys->buf.pos, sys->buf.counts, s);
+  int32_t rc = launch_hist_sys(sys, s);
   if (!rc) rc = refresh_fields(sys, s);
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(s));
@@ -1454,6 +1505,7 @@ int32_t soma_train_step(const float *features, const float *targets, uint32_t n,
   return SOMA_OK;
 }
 
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
@@ -1462,12 +1514,12 @@ int32_t soma_train_step(const float *features, const float *targets, uint32_t n,
 struct soma_batch {
   std::vector<soma_system *> sys;
   // host copies of the device tables (kept for the batch's lifetime)
-  std::vector<soma::BatchSeg> segs[3];
+  std::vector<soma::BatchSeg> segs[4];   // by move kind (local, smart MC, mixed, bond-Gibbs)
   std::vector<uint32_t> seg_first;
   std::vector<soma::FieldArgs> fargs;
   std::vector<uint32_t> fb_first;
   std::vector<uint32_t *> ctrs;
-  soma::BatchSeg *d_segs[3] = {nullptr, nullptr, nullptr};
+  soma::BatchSeg *d_segs[4] = {nullptr, nullptr, nullptr, nullptr};
   uint32_t *d_seg_first = nullptr, *d_fb_first = nullptr;
   soma::FieldArgs *d_fargs = nullptr;
   uint32_t **d_ctrs = nullptr;
@@ -1481,13 +1533,13 @@ struct soma_batch {
 namespace {
 
 struct BatchLayout {
-  uint64_t segs[3], seg_first, fargs, fb_first, ctrs, total;
+  uint64_t segs[4], seg_first, fargs, fb_first, ctrs, total;
 };
 
 BatchLayout batch_layout(uint64_t n_segs, uint64_t n_sys) {
   BatchLayout L;
   uint64_t o = 0;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 4; ++k) {
     L.segs[k] = o;
     o = align_up(o + n_segs * sizeof(soma::BatchSeg));
   }
@@ -1542,6 +1594,8 @@ template <bool C64, bool V2>
 void launch_batch_t(uint32_t kind, dim3 grid, hipStream_t s, const soma::BatchLaunch &L) {
   if (kind == SOMA_MOVE_MIXED)
     hipLaunchKernelGGL((soma::batched_sweep_kernel<C64, V2, 2>), grid, dim3(256), 0, s, L);
+  else if (kind == SOMA_MOVE_GIBBS)
+    hipLaunchKernelGGL((soma::batched_sweep_kernel<C64, V2, 3>), grid, dim3(256), 0, s, L);
   else if (kind == SOMA_MOVE_SMC)
     hipLaunchKernelGGL((soma::batched_sweep_kernel<C64, V2, 1>), grid, dim3(256), 0, s, L);
   else
@@ -1614,7 +1668,6 @@ int32_t batch_check_kind(soma_batch *b, uint32_t kind) {
       return fail(SOMA_E_UNSUPPORTED, "batched sweeps use the SET order only");
     if (x->arch_mask) return fail(SOMA_E_UNSUPPORTED, "batched sweeps take linear chains only");
     if (x->d.n_types > 2) return fail(SOMA_E_UNSUPPORTED, "batched sweeps take two bead types");
-    if (kind == SOMA_MOVE_GIBBS) return fail(SOMA_E_UNSUPPORTED, "batched sweeps: no bond-Gibbs moves");
   }
   return SOMA_OK;
 }
@@ -1664,9 +1717,9 @@ int32_t soma_batch_create(soma_system *const *systems, uint32_t n, void *workspa
   std::stable_sort(refs.begin(), refs.end(),
                    [](const Ref &x, const Ref &y) { return x.beads > y.beads; });
   for (const Ref &r : refs) {
-    soma::BatchSeg seg[3];
-    for (uint32_t k = 0; k < 3; ++k) sweep_args(systems[r.s], r.sp, k, seg[k].a, seg[k].mx);
-    for (uint32_t k = 0; k < 3; ++k) b->segs[k].push_back(seg[k]);
+    soma::BatchSeg seg[4];
+    for (uint32_t k = 0; k < 4; ++k) sweep_args(systems[r.s], r.sp, k, seg[k].a, seg[k].mx);
+    for (uint32_t k = 0; k < 4; ++k) b->segs[k].push_back(seg[k]);
     if (!species_vec2(systems[r.s], r.sp)) b->v2 = 0;
   }
   rc = batch_items(b);
@@ -1683,7 +1736,7 @@ int32_t soma_batch_create(soma_system *const *systems, uint32_t n, void *workspa
     b->ctrs.push_back(x->sweep_ctr());
   }
   unsigned char *ws = reinterpret_cast<unsigned char *>(workspace);
-  for (int k = 0; k < 3; ++k) b->d_segs[k] = reinterpret_cast<soma::BatchSeg *>(ws + lay.segs[k]);
+  for (int k = 0; k < 4; ++k) b->d_segs[k] = reinterpret_cast<soma::BatchSeg *>(ws + lay.segs[k]);
   b->d_seg_first = reinterpret_cast<uint32_t *>(ws + lay.seg_first);
   b->d_fargs = reinterpret_cast<soma::FieldArgs *>(ws + lay.fargs);
   b->d_fb_first = reinterpret_cast<uint32_t *>(ws + lay.fb_first);
@@ -1693,7 +1746,7 @@ int32_t soma_batch_create(soma_system *const *systems, uint32_t n, void *workspa
     HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
     return SOMA_OK;
   };
-  for (int k = 0; k < 3 && !rc; ++k)
+  for (int k = 0; k < 4 && !rc; ++k)
     rc = put(b->d_segs[k], b->segs[k].data(), b->segs[k].size() * sizeof(soma::BatchSeg));
   if (!rc) rc = put(b->d_seg_first, b->seg_first.data(), b->seg_first.size() * 4);
   if (!rc) rc = put(b->d_fargs, b->fargs.data(), b->fargs.size() * sizeof(soma::FieldArgs));
@@ -1826,7 +1879,7 @@ bool cache_lookup(const char *path, const std::string &key, uint32_t *mode, uint
     if (!tab) continue;
     *tab = '\0';
     unsigned m = 0, g = 0;
-    if (key == line && std::sscanf(tab + 1, "%u %u", &m, &g) == 2 && m <= 1) {
+    if (key == line && std::sscanf(tab + 1, "%u %u", &m, &g) == 2 && m < 64) {
       *mode = m;
       *grid = g;
       found = true;  // the last matching line wins
@@ -1921,19 +1974,43 @@ int32_t soma_autotune(soma_system *sys, uint32_t cycles, uint32_t move_kind,
   const int32_t rc = check_kind(sys, move_kind);
   if (rc) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  // only the local-move kernels have other launch shapes (persistent blocks); the
-  // molecule-order kernel also tries grids small enough to keep its chains in L2
-  static const Shape set_shapes[] = {{0, 0}, {0, 1024}, {0, 2048}, {0, 4096}};
-  static const Shape mol_shapes[] = {{0, 0}, {0, 256}, {0, 512}, {0, 1024}, {0, 2048}};
+  // SET order: mode = histogram mode (bit 0) | block size / 64 - 1 (bits 1..3);
+  // the grid (persistent blocks) for local moves only.  Molecule order: grid
+  // caps small enough to keep its chains in L2.
+  std::vector<Shape> shapes;
   const bool mol = sys->scheme == SOMA_SCHEME_MOLECULE;
-  const Shape *local_shapes = mol ? mol_shapes : set_shapes;
-  const uint32_t n_shapes = move_kind == SOMA_MOVE_LOCAL ? (mol ? 5u : 4u) : 1u;
+  if (mol) {
+    for (uint32_t g : {0u, 256u, 512u, 1024u, 2048u}) shapes.push_back({0u, g});
+  } else {
+    const uint32_t n_hist = sys->d.bins_ok ? 2u : 1u;
+    const bool fixed_block = move_kind == SOMA_MOVE_MIXED;
+    for (uint32_t h = 0; h < n_hist; ++h)
+      for (uint32_t t : {256u, 128u, 512u}) {
+        if (fixed_block && t != 256u) continue;
+        for (uint32_t g : {0u, 2048u}) {
+          if (g && move_kind != SOMA_MOVE_LOCAL) continue;
+          shapes.push_back({h | ((t / 64u - 1u) << 1), g});
+        }
+      }
+  }
   char kind_s[24];
   std::snprintf(kind_s, sizeof kind_s, "sys/k%u/s%u/", move_kind, sys->scheme);
-  return tune(local_shapes, n_shapes, cycles, cache_path, kind_s + system_key(sys), s,
-              [&](uint32_t, uint32_t grid) { sys->sweep_blocks = grid; },
-              [&]() -> int32_t { return soma_cycle(sys, 1, move_kind, stream); },
-              out);
+  auto apply = [&](uint32_t mode, uint32_t grid) {
+    sys->sweep_blocks = grid;
+    if (!mol) {
+      sys->hist_mode = (mode & 1u) ? soma::kHistBinned : soma::kHistDirect;
+      sys->sweep_threads = 64u * (((mode >> 1) & 7u) + 1u);
+    }
+  };
+  const int32_t r = tune(shapes.data(), (uint32_t)shapes.size(), cycles, cache_path,
+                         kind_s + system_key(sys), s, apply,
+                         [&]() -> int32_t { return soma_cycle(sys, 1, move_kind, stream); }, out);
+  if (!r) {
+    out->mode = 0;   // the item order exists for batches only
+    out->hist_mode = sys->hist_mode == soma::kHistBinned ? SOMA_HIST_BINNED : SOMA_HIST_DIRECT;
+    out->block_threads = mol ? 256u : sys->sweep_threads;
+  }
+  return r;
 }
 
 int32_t soma_choose_scheme(soma_system *sys, uint32_t cycles, void *stream, uint32_t *chosen,
@@ -1974,12 +2051,12 @@ int32_t soma_batch_autotune(soma_batch *b, uint32_t cycles, uint32_t move_kind,
   const int32_t rc = batch_check_kind(b, move_kind);
   if (rc) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  static const Shape shapes[] = {{0, 0}, {1, 0}, {0, 2048}, {0, 8192}};
+  static const Shape shapes[] = {{0, 0}, {1, 0}, {0, 2048}, {1, 2048}, {0, 8192}, {1, 8192}};
   char kind_s[16];
   std::snprintf(kind_s, sizeof kind_s, "batch/k%u", move_kind);
   std::string key = kind_s;
   for (soma_system *x : b->sys) key += "/" + system_key(x);
-  return tune(shapes, 4u, cycles, cache_path, key, s,
+  return tune(shapes, 6u, cycles, cache_path, key, s,
               [&](uint32_t mode, uint32_t grid) {
                 b->mode = mode;
                 b->grid_blocks = grid;

@@ -64,6 +64,8 @@ __global__ __launch_bounds__(256, 2) void batched_sweep_kernel(const BatchLaunch
       finish_block(a, local_tile<COUNT64, VEC2, false>(a, m, cp, r0, r1));
     } else if (KIND == 1) {
       finish_block(a, smc_wave<COUNT64, VEC2, false>(a, m));
+    } else if (KIND == 3) {
+      finish_block(a, smc_wave<COUNT64, VEC2, false, true>(a, m));
     } else {
       const MixArgs mx = L.segs[sg].mx;
       uint32_t cnt[3];

@@ -29,12 +29,23 @@ constexpr uint32_t kHistBinned = 1u;         // per-brick bins, applied by bin_a
 constexpr uint32_t kUpdPresent = 0x8000u;
 constexpr uint32_t kUpdMinus = 0x4000u;
 
+// Every brick has kSubBins sub-bins; a wave appends to sub-bin (wave index
+// mod kSubBins), so that the waves working on one region of the grid at the
+// same time (they share its bricks) spread their reservations over
+// different counters instead of queueing on one.
+constexpr uint32_t kSubShift = 4u, kSubBins = 1u << kSubShift;
+
 struct BinArgs {
-  uint32_t *bins;        // [n_bricks][cap] entries
-  uint32_t *bin_count;   // [n_bricks] entries written (may exceed cap: the rest went direct)
-  uint32_t cap;          // entries per bin
+  uint32_t *bins;        // [n_bricks][kSubBins][cap] entries
+  uint32_t *bin_count;   // [n_bricks][kSubBins] entries written (beyond cap: went direct)
+  uint32_t cap;          // entries per sub-bin
   uint32_t nbx, nby, nbz;
 };
+
+// Sub-bin of the calling wave.
+__device__ __forceinline__ uint32_t wave_sub_bin() {
+  return ((blockIdx.x * (blockDim.x >> 6)) + (threadIdx.x >> 6)) & (kSubBins - 1u);
+}
 
 // Brick key of cell (x, y, z): brick index << 11 | cell inside the brick.
 __device__ __forceinline__ uint32_t brick_key(const BinArgs &b, uint32_t x, uint32_t y,
@@ -100,85 +111,90 @@ __device__ __forceinline__ void apply_entry_direct(const BinArgs &b, const Grid 
   }
 }
 
+// One group of bin_append: the brick of the first lane with a pending slot.
+// Marks the lane's slots in that brick with the group index j and their rank
+// (go_s = j | rank << 3), clears them from `want`, and has the first lane
+// reserve the group's room (*gb, read only after all groups are issued).
+__device__ __forceinline__ void bin_group(uint32_t *bin_count, uint32_t sub, uint32_t j, uint32_t k0,
+                                          uint32_t k1, uint32_t k2, uint32_t k3, uint32_t &want,
+                                          uint32_t &go0, uint32_t &go1, uint32_t &go2,
+                                          uint32_t &go3, uint32_t &gk, uint32_t &gb,
+                                          uint32_t &gl) {
+  const uint64_t any = __ballot(want != 0u);
+  if (any == 0ull) return;
+  const uint32_t lane = __lane_id();
+  const uint64_t below = (1ull << lane) - 1ull;
+  const uint32_t leader = (uint32_t)__ffsll((long long)any) - 1u;
+  const uint32_t first = (want & 1u) ? k0 : (want & 2u) ? k1 : (want & 4u) ? k2 : k3;
+  const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)first, (int)leader);
+  const bool m0 = (want & 1u) && k0 == k, m1 = (want & 2u) && k1 == k;
+  const bool m2 = (want & 4u) && k2 == k, m3 = (want & 8u) && k3 == k;
+  const uint64_t b0 = __ballot(m0), b1 = __ballot(m1), b2 = __ballot(m2), b3 = __ballot(m3);
+  const uint32_t c0 = (uint32_t)__popcll(b0), c1 = (uint32_t)__popcll(b1);
+  const uint32_t c2 = (uint32_t)__popcll(b2), c3 = (uint32_t)__popcll(b3);
+  if (m0) go0 = j | ((uint32_t)__popcll(b0 & below) << 3);
+  if (m1) go1 = j | ((c0 + (uint32_t)__popcll(b1 & below)) << 3);
+  if (m2) go2 = j | ((c0 + c1 + (uint32_t)__popcll(b2 & below)) << 3);
+  if (m3) go3 = j | ((c0 + c1 + c2 + (uint32_t)__popcll(b3 & below)) << 3);
+  want &= ~((m0 ? 1u : 0u) | (m1 ? 2u : 0u) | (m2 ? 4u : 0u) | (m3 ? 8u : 0u));
+  if (lane == leader) gb = atomicAdd(bin_count + ((k << kSubShift) | sub), c0 + c1 + c2 + c3);
+  gk = k;
+  gl = leader;
+}
+
+// Stores entry v of a slot marked go (group j = go & 7 of `only`, or of any
+// of the four groups if only > 3) at its reserved place, or applies it
+// directly if the bin is full.
+template <bool COUNT64>
+__device__ __forceinline__ void bin_put(const BinArgs &b, const Grid &g, void *counts,
+                                        uint32_t sub, uint32_t go, uint32_t v, uint32_t gk0, uint32_t gk1,
+                                        uint32_t gk2, uint32_t gk3, uint32_t base0, uint32_t base1,
+                                        uint32_t base2, uint32_t base3) {
+  const uint32_t j = go & 7u;
+  if (j > 3u) return;
+  const uint32_t bk = j == 0u ? gk0 : j == 1u ? gk1 : j == 2u ? gk2 : gk3;
+  const uint32_t pos = (j == 0u ? base0 : j == 1u ? base1 : j == 2u ? base2 : base3) + (go >> 3);
+  if (pos < b.cap) b.bins[(size_t)((bk << kSubShift) | sub) * b.cap + pos] = v;
+  else apply_entry_direct<COUNT64>(b, g, counts, bk, v);
+}
+
 // Appends the entries of a wave to their bricks' bins.  Each lane offers up
-// to four entries (slot s: brick key[s], value val[s], wanted if bit s of
-// `want`).  All lanes of the wave must call this together.  Entries are
-// grouped by brick; the first four groups reserve their room with atomics
-// issued back to back (one wait for all), further groups one at a time.
+// to four entries (slot s: brick ks, value vs, wanted if bit s of `want`).
+// All lanes of the wave must call this together.  Entries are grouped by
+// brick; the first four groups reserve their room with atomics issued back
+// to back (one wait for all), further groups one at a time.
 template <bool COUNT64>
 __device__ __forceinline__ void bin_append(const BinArgs &b, const Grid &g, void *counts,
-                                           const uint32_t key[4], const uint32_t val[4],
+                                           uint32_t k0, uint32_t k1, uint32_t k2, uint32_t k3,
+                                           uint32_t v0, uint32_t v1, uint32_t v2, uint32_t v3,
                                            uint32_t want) {
-  const uint32_t lane = __lane_id();
-  const uint64_t lanes_below = (1ull << lane) - 1ull;
-  uint32_t grp[4] = {4u, 4u, 4u, 4u};   // group of each slot (4: later groups)
-  uint32_t off[4] = {0u, 0u, 0u, 0u};   // rank inside the group
-  uint32_t gkey[4] = {0u, 0u, 0u, 0u};  // brick of each group (wave-uniform)
-  uint32_t gbase[4] = {0u, 0u, 0u, 0u}; // returned bin count (leader lane only)
-  uint32_t glead[4] = {0u, 0u, 0u, 0u};
-  uint32_t n_groups = 0;
-#pragma unroll
-  for (uint32_t j = 0; j < 4; ++j) {
-    const uint64_t any = __ballot(want != 0u);
-    if (any == 0ull) break;
-    const uint32_t leader = (uint32_t)__ffsll((long long)any) - 1u;
-    const uint32_t first = (want & 1u) ? key[0] : (want & 2u) ? key[1] : (want & 4u) ? key[2] : key[3];
-    const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)first, (int)leader);
-    uint32_t tot = 0;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const bool mt = ((want >> s) & 1u) && key[s] == k;
-      const uint64_t bm = __ballot(mt);
-      if (mt) { grp[s] = j; off[s] = tot + (uint32_t)__popcll(bm & lanes_below); }
-      tot += (uint32_t)__popcll(bm);
-      want &= mt ? ~(1u << s) : ~0u;
-    }
-    if (lane == leader) gbase[j] = atomicAdd(b.bin_count + k, tot);
-    gkey[j] = k;
-    glead[j] = leader;
-    n_groups = j + 1u;
-  }
-  uint32_t base[4];
-#pragma unroll
-  for (uint32_t j = 0; j < 4; ++j)
-    base[j] = j < n_groups ? (uint32_t)__builtin_amdgcn_readlane((int)gbase[j], (int)glead[j]) : 0u;
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    if (grp[s] < 4u) {
-      const uint32_t j = grp[s];
-      const uint32_t bk = j == 0 ? gkey[0] : j == 1 ? gkey[1] : j == 2 ? gkey[2] : gkey[3];
-      const uint32_t pos = (j == 0 ? base[0] : j == 1 ? base[1] : j == 2 ? base[2] : base[3]) + off[s];
-      if (pos < b.cap) b.bins[(size_t)bk * b.cap + pos] = val[s];
-      else apply_entry_direct<COUNT64>(b, g, counts, bk, val[s]);
-    }
-  }
-  // rare: more than four bricks in one wave
-  while (true) {
-    const uint64_t any = __ballot(want != 0u);
-    if (any == 0ull) break;
-    const uint32_t leader = (uint32_t)__ffsll((long long)any) - 1u;
-    const uint32_t first = (want & 1u) ? key[0] : (want & 2u) ? key[1] : (want & 4u) ? key[2] : key[3];
-    const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)first, (int)leader);
-    uint32_t tot = 0, my_off[4] = {0u, 0u, 0u, 0u}, mine = 0u;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const bool mt = ((want >> s) & 1u) && key[s] == k;
-      const uint64_t bm = __ballot(mt);
-      if (mt) { my_off[s] = tot + (uint32_t)__popcll(bm & lanes_below); mine |= 1u << s; }
-      tot += (uint32_t)__popcll(bm);
-    }
-    want &= ~mine;
-    uint32_t bs = 0;
-    if (lane == leader) bs = atomicAdd(b.bin_count + k, tot);
-    bs = (uint32_t)__builtin_amdgcn_readlane((int)bs, (int)leader);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      if ((mine >> s) & 1u) {
-        const uint32_t pos = bs + my_off[s];
-        if (pos < b.cap) b.bins[(size_t)k * b.cap + pos] = val[s];
-        else apply_entry_direct<COUNT64>(b, g, counts, k, val[s]);
-      }
-    }
+  const uint32_t sub = wave_sub_bin();
+  uint32_t go0 = 7u, go1 = 7u, go2 = 7u, go3 = 7u;
+  uint32_t gk0 = 0u, gk1 = 0u, gk2 = 0u, gk3 = 0u;
+  uint32_t gb0 = 0u, gb1 = 0u, gb2 = 0u, gb3 = 0u;
+  uint32_t gl0 = 0u, gl1 = 0u, gl2 = 0u, gl3 = 0u;
+  bin_group(b.bin_count, sub, 0u, k0, k1, k2, k3, want, go0, go1, go2, go3, gk0, gb0, gl0);
+  bin_group(b.bin_count, sub, 1u, k0, k1, k2, k3, want, go0, go1, go2, go3, gk1, gb1, gl1);
+  bin_group(b.bin_count, sub, 2u, k0, k1, k2, k3, want, go0, go1, go2, go3, gk2, gb2, gl2);
+  bin_group(b.bin_count, sub, 3u, k0, k1, k2, k3, want, go0, go1, go2, go3, gk3, gb3, gl3);
+  const uint32_t base0 = (uint32_t)__builtin_amdgcn_readlane((int)gb0, (int)gl0);
+  const uint32_t base1 = (uint32_t)__builtin_amdgcn_readlane((int)gb1, (int)gl1);
+  const uint32_t base2 = (uint32_t)__builtin_amdgcn_readlane((int)gb2, (int)gl2);
+  const uint32_t base3 = (uint32_t)__builtin_amdgcn_readlane((int)gb3, (int)gl3);
+  bin_put<COUNT64>(b, g, counts, sub, go0, v0, gk0, gk1, gk2, gk3, base0, base1, base2, base3);
+  bin_put<COUNT64>(b, g, counts, sub, go1, v1, gk0, gk1, gk2, gk3, base0, base1, base2, base3);
+  bin_put<COUNT64>(b, g, counts, sub, go2, v2, gk0, gk1, gk2, gk3, base0, base1, base2, base3);
+  bin_put<COUNT64>(b, g, counts, sub, go3, v3, gk0, gk1, gk2, gk3, base0, base1, base2, base3);
+  // rare: more than four bricks in one wave, one group at a time
+  while (__ballot(want != 0u) != 0ull) {
+    uint32_t gk = 0u, gb = 0u, gl = 0u;
+    go0 = go1 = go2 = go3 = 7u;
+    bin_group(b.bin_count, sub, 0u, k0, k1, k2, k3, want, go0, go1, go2, go3, gk, gb, gl);
+    const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)gb, (int)gl);
+    bin_put<COUNT64>(b, g, counts, sub, go0, v0, gk, gk, gk, gk, base, base, base, base);
+    bin_put<COUNT64>(b, g, counts, sub, go1, v1, gk, gk, gk, gk, base, base, base, base);
+    bin_put<COUNT64>(b, g, counts, sub, go2, v2, gk, gk, gk, gk, base, base, base, base);
+    bin_put<COUNT64>(b, g, counts, sub, go3, v3, gk, gk, gk, gk, base, base, base, base);
   }
 }
 
@@ -189,21 +205,55 @@ template <bool COUNT64>
 __device__ __forceinline__ void bin_moves(const BinArgs &b, const Grid &g, void *counts,
                                           uint32_t from0, uint32_t to0, uint32_t t0, bool moved0,
                                           uint32_t from1, uint32_t to1, uint32_t t1, bool moved1) {
-  uint32_t key[4], val[4], want = 0u;
-  const uint32_t from[2] = {from0, from1}, to[2] = {to0, to1}, ty[2] = {t0, t1};
-  const bool mv[2] = {moved0, moved1};
-#pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    const uint32_t hm = kUpdPresent | kUpdMinus | (ty[e] << 11) | (from[e] & 2047u);
-    const uint32_t hp = kUpdPresent | (ty[e] << 11) | (to[e] & 2047u);
-    const bool same = (from[e] >> 11) == (to[e] >> 11);
-    key[2 * e] = from[e] >> 11;
-    val[2 * e] = same ? (hm | (hp << 16)) : hm;
-    key[2 * e + 1] = to[e] >> 11;
-    val[2 * e + 1] = hp << 16;
-    if (mv[e]) want |= (same ? 1u : 3u) << (2 * e);
+  const uint32_t hm0 = kUpdPresent | kUpdMinus | (t0 << 11) | (from0 & 2047u);
+  const uint32_t hp0 = kUpdPresent | (t0 << 11) | (to0 & 2047u);
+  const uint32_t hm1 = kUpdPresent | kUpdMinus | (t1 << 11) | (from1 & 2047u);
+  const uint32_t hp1 = kUpdPresent | (t1 << 11) | (to1 & 2047u);
+  const bool same0 = (from0 >> 11) == (to0 >> 11), same1 = (from1 >> 11) == (to1 >> 11);
+  const uint32_t want = (moved0 ? (same0 ? 1u : 3u) : 0u) | (moved1 ? (same1 ? 4u : 12u) : 0u);
+  bin_append<COUNT64>(b, g, counts, from0 >> 11, to0 >> 11, from1 >> 11, to1 >> 11,
+                      same0 ? (hm0 | (hp0 << 16)) : hm0, hp0 << 16,
+                      same1 ? (hm1 | (hp1 << 16)) : hm1, hp1 << 16, want);
+}
+
+// From-scratch histogram of one species through the bins (counts cleared
+// before): lane q of the grid takes beads 2q and 2q+1 of the species (one
+// entry when both lie in one brick), so that a wave of 128 consecutive beads
+// reserves room once per brick it touches.  Positions are read as three
+// 8-byte pairs when `vec2` (8-byte aligned species start).
+template <bool COUNT64>
+__global__ __launch_bounds__(256) void density_hist_binned_kernel(
+    const float *pos, uint64_t n_beads, uint32_t n, uint32_t n_a, Grid g, void *counts,
+    const ArchDev *arch, BinArgs b, uint32_t vec2) {
+  const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t i0 = 2 * q, i1 = 2 * q + 1;
+  const bool has0 = i0 < n_beads, has1 = i1 < n_beads;
+  float r[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (has1 && vec2) {
+    const float2 *p2 = reinterpret_cast<const float2 *>(pos + 3 * i0);
+    const float2 a = p2[0], c = p2[1], d = p2[2];
+    r[0] = a.x; r[1] = a.y; r[2] = c.x; r[3] = c.y; r[4] = d.x; r[5] = d.y;
+  } else {
+    if (has0) { r[0] = pos[3 * i0]; r[1] = pos[3 * i0 + 1]; r[2] = pos[3 * i0 + 2]; }
+    if (has1) { r[3] = pos[3 * i1]; r[4] = pos[3 * i1 + 1]; r[5] = pos[3 * i1 + 2]; }
   }
-  bin_append<COUNT64>(b, g, counts, key, val, want);
+  uint32_t x0, y0, z0, x1, y1, z1;
+  cell3(g, r[0], r[1], r[2], x0, y0, z0);
+  cell3(g, r[3], r[4], r[5], x1, y1, z1);
+  const uint32_t k0 = brick_key(b, x0, y0, z0), k1 = brick_key(b, x1, y1, z1);
+  const uint32_t j0 = n_beads <= 0xFFFFFFFFull ? (uint32_t)i0 % n : (uint32_t)(i0 % n);
+  const uint32_t j1 = j0 + 1u == n ? 0u : j0 + 1u;
+  const uint32_t t0 = bead_type(arch, j0, n_a), t1 = bead_type(arch, j1, n_a);
+  const uint32_t h0 = kUpdPresent | (t0 << 11) | (k0 & 2047u);
+  const uint32_t h1 = kUpdPresent | (t1 << 11) | (k1 & 2047u);
+  const bool same = (k0 >> 11) == (k1 >> 11);
+  uint32_t want = 0u;
+  if (has0) want |= 1u;
+  if (has1) want |= same ? 0u : 2u;
+  const uint32_t v0 = (has1 && same) ? (h0 | (h1 << 16)) : h0;
+  const uint32_t v1 = h1 << 16;
+  // a lane without bead 2q has only bead 2q+1 absent too (n_beads is the end)
+  bin_append<COUNT64>(b, g, counts, k0 >> 11, k1 >> 11, 0u, 0u, v0, v1, 0u, 0u, want);
 }
 
 // Applies the bins to the counts: one workgroup per brick.  The brick's count
@@ -236,8 +286,9 @@ __global__ __launch_bounds__(256) void bin_apply_kernel(BinArgs b, Grid g, void 
     else s_cnt[i] = lo;
   }
   __syncthreads();
-  const uint32_t n = min(b.bin_count[brick], b.cap);
-  const uint32_t *bin = b.bins + (size_t)brick * b.cap;
+  for (uint32_t sb = 0; sb < kSubBins; ++sb) {
+  const uint32_t n = min(b.bin_count[(brick << kSubShift) | sb], b.cap);
+  const uint32_t *bin = b.bins + (size_t)((brick << kSubShift) | sb) * b.cap;
   for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
     const uint32_t e = bin[j];
 #pragma unroll
@@ -256,6 +307,7 @@ __global__ __launch_bounds__(256) void bin_apply_kernel(BinArgs b, Grid g, void 
       }
     }
   }
+  }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < planes * kBrickCells; i += blockDim.x) {
     const uint32_t p = i / kBrickCells, l = i % kBrickCells;
@@ -268,7 +320,7 @@ __global__ __launch_bounds__(256) void bin_apply_kernel(BinArgs b, Grid g, void 
         reinterpret_cast<uint32_t *>(counts)[w] = s_cnt[i];
     }
   }
-  if (threadIdx.x == 0) b.bin_count[brick] = 0u;
+  if (threadIdx.x < kSubBins) b.bin_count[(brick << kSubShift) | threadIdx.x] = 0u;
 }
 
 }  // namespace soma

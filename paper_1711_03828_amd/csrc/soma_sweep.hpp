@@ -118,7 +118,7 @@ __device__ __forceinline__ LaneMap lane_map_tile(const SweepArgs &a, uint32_t ti
 }
 
 __device__ __forceinline__ LaneMap lane_map(const SweepArgs &a) {
-  const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x) * 4u + (threadIdx.x >> 6);
+  const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
   return lane_map_tile(a, tile, true);
 }
 
@@ -172,13 +172,15 @@ __device__ __forceinline__ void move_count(void *counts, uint32_t from, uint32_t
   }
 }
 
-// Accepted-move count of the block into one of kAccSlots counters.
+// Accepted-move count of the block (up to 16 waves) into one of kAccSlots
+// counters (integer sums: the totals do not depend on the block size).
 __device__ __forceinline__ void finish_block(const SweepArgs &a, uint32_t n_acc) {
-  __shared__ uint32_t s_acc[4];
+  __shared__ uint32_t s_acc[16];
   if ((threadIdx.x & 63u) == 0u) s_acc[threadIdx.x >> 6] = n_acc;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t tot = s_acc[0] + s_acc[1] + s_acc[2] + s_acc[3];
+    uint32_t tot = 0;
+    for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) tot += s_acc[w];
     if (tot) atomicAdd(a.acc_slots + (blockIdx.x & (kAccSlots - 1u)), (unsigned long long)tot);
   }
   __syncthreads();
@@ -315,15 +317,16 @@ __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap
 // positions while it works on the current one.
 // ---------------------------------------------------------------------------
 template <bool COUNT64, bool VEC2, bool BINNED>
-__global__ __launch_bounds__(256) void mc_sweep_local_kernel(const SweepArgs a_in) {
+__global__ __launch_bounds__(512) void mc_sweep_local_kernel(const SweepArgs a_in) {
   const SweepArgs a = resolve_sweep(a_in, 0u);
   const uint32_t n_tiles = (a.n_sub + a.chains_per_wave - 1u) / a.chains_per_wave;
   const uint32_t blocks = gridDim.x;
   // XCD split only when the grid is a multiple of 8 blocks
   const uint32_t parts = (blocks & 7u) == 0u ? 8u : 1u;
   const uint32_t part = blockIdx.x % parts;
-  const uint32_t waves_per_part = (blocks / parts) * 4u;
-  const uint32_t wave_in_part = (blockIdx.x / parts) * 4u + (threadIdx.x >> 6);
+  const uint32_t wpb = blockDim.x >> 6;   // waves per block
+  const uint32_t waves_per_part = (blocks / parts) * wpb;
+  const uint32_t wave_in_part = (blockIdx.x / parts) * wpb + (threadIdx.x >> 6);
   const uint32_t t_begin = (uint32_t)(((uint64_t)n_tiles * part) / parts);
   const uint32_t t_end = (uint32_t)(((uint64_t)n_tiles * (part + 1u)) / parts);
 
@@ -539,14 +542,14 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
 }
 
 template <bool COUNT64, bool VEC2, bool BINNED>
-__global__ __launch_bounds__(256) void mc_sweep_smc_kernel(const SweepArgs a_in) {
+__global__ __launch_bounds__(512) void mc_sweep_smc_kernel(const SweepArgs a_in) {
   const SweepArgs a = resolve_sweep(a_in, 0u);
   const LaneMap m = lane_map(a);
   finish_block(a, smc_wave<COUNT64, VEC2, BINNED>(a, m));
 }
 
 template <bool COUNT64, bool VEC2, bool BINNED>
-__global__ __launch_bounds__(256) void mc_sweep_gibbs_kernel(const SweepArgs a_in) {
+__global__ __launch_bounds__(512) void mc_sweep_gibbs_kernel(const SweepArgs a_in) {
   const SweepArgs a = resolve_sweep(a_in, 0u);
   const LaneMap m = lane_map(a);
   finish_block(a, smc_wave<COUNT64, VEC2, BINNED, true>(a, m));

@@ -83,7 +83,8 @@ class soma_train_opts(ctypes.Structure):
 class soma_tune(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_uint32), ("grid_blocks", ctypes.c_uint32),
                 ("ms_per_cycle", ctypes.c_float), ("candidates", ctypes.c_uint32),
-                ("cycles_run", ctypes.c_uint32), ("from_cache", ctypes.c_uint32)]
+                ("cycles_run", ctypes.c_uint32), ("from_cache", ctypes.c_uint32),
+                ("hist_mode", ctypes.c_uint32), ("block_threads", ctypes.c_uint32)]
 
 
 class SomaError(RuntimeError):
@@ -112,6 +113,7 @@ _SIGS = {
     "soma_rebuild_histogram": ([_P, _P], _i32),
     "soma_set_sweep_blocks": ([_P, _u32], _i32),
     "soma_set_histogram": ([_P, _u32], _i32),
+    "soma_set_sweep_threads": ([_P, _u32], _i32),
     "soma_set_scheme": ([_P, _u32], _i32),
     "soma_set_hamiltonian": ([_P, _u32, _P], _i32),
     "soma_set_types": ([_P, _u32, _P, _P, _u64, _P, _u64, _P], _i32),
@@ -211,6 +213,10 @@ def soma_set_sweep_blocks(h, blocks: int) -> None:
 
 def soma_set_histogram(h, mode: int) -> None:
     _check(_lib.soma_set_histogram(h, mode))
+
+
+def soma_set_sweep_threads(h, threads: int) -> None:
+    _check(_lib.soma_set_sweep_threads(h, threads))
 
 
 def soma_set_external(h, ext_ptr, ext_bytes: int, forbid_ptr, forbid_bytes: int, stream) -> None:

@@ -89,11 +89,12 @@ def test_batched_local_sweep_matches_oracle(orc):
     batch.close()
 
 
-@pytest.mark.parametrize("kind", ["local", "smc", "mixed"])
+@pytest.mark.parametrize("kind", ["local", "smc", "mixed", "gibbs"])
 def test_batched_cycles_equal_single(kind):
     from paper_1711_03828_amd import soma as C
     from paper_1711_03828_amd.melt import Batch
-    move = {"local": C.SOMA_MOVE_LOCAL, "smc": C.SOMA_MOVE_SMC, "mixed": C.SOMA_MOVE_MIXED}[kind]
+    move = {"local": C.SOMA_MOVE_LOCAL, "smc": C.SOMA_MOVE_SMC, "mixed": C.SOMA_MOVE_MIXED,
+            "gibbs": C.SOMA_MOVE_GIBBS}[kind]
     reps = _replicas()
     p_learn = 0.5 if kind == "mixed" else 0.0
     ma, mb = _melts(reps, p_learn), _melts(reps, p_learn)
@@ -151,20 +152,23 @@ def test_autotune_keeps_results(tmp_path):
     a, b = Melt(device_config(w)), Melt(device_config(w))
     t = a.autotune(2, C.SOMA_MOVE_LOCAL, cache)
     flush("single tune", t.mode, t.grid_blocks, t.ms_per_cycle, t.candidates, t.cycles_run)
-    assert t.candidates == 4 and t.cycles_run == 12 and t.from_cache == 0
+    # histogram mode {direct, binned} x block size {256, 128, 512} x grid {0, 2048}
+    assert t.candidates == 12 and t.cycles_run == 36 and t.from_cache == 0
     b.cycle(t.cycles_run)
     a.cycle(5)
     b.cycle(5)
     _assert_same([a], [b], "tuned single")
     t2 = a.autotune(2, C.SOMA_MOVE_LOCAL, cache)
     assert t2.from_cache == 1 and t2.cycles_run == 0
-    assert (t2.mode, t2.grid_blocks) == (t.mode, t.grid_blocks)
+    assert (t2.mode, t2.grid_blocks, t2.hist_mode, t2.block_threads) == \
+        (t.mode, t.grid_blocks, t.hist_mode, t.block_threads)
     reps = _replicas()
     ma, mb = _melts(reps), _melts(reps)
     batch = Batch(ma)
     tb = batch.autotune(2, C.SOMA_MOVE_LOCAL, cache)
     flush("batch tune", tb.mode, tb.grid_blocks, tb.ms_per_cycle, tb.candidates, tb.cycles_run)
-    assert tb.candidates == 4 and tb.cycles_run == 12
+    # item order {XCD ranges, round-robin} x grid {one block per item, 2048, 8192}
+    assert tb.candidates == 6 and tb.cycles_run == 18
     for m in mb:
         m.cycle(tb.cycles_run)
     batch.cycle(3)
