@@ -587,6 +587,24 @@ int32_t soma_train_step(const float *features, const float *targets, uint32_t n,
                         uint64_t workspace_bytes, float *grad_out, float *loss_out,
                         void *stream);
 
+/* soma_train_step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same step, arguments and results, without a workspace argument.  Its
+ * scratch (the prepared network and up to SOMA_NOALLOC_TRAIN_WAVES partial
+ * gradients, about 4.4 MB) is a fixed device array of the library, one per
+ * GPU, held until the process ends; the call allocates nothing.  The number
+ * of partial gradients is that of soma_train_step (opts->max_waves, or one
+ * per 64 samples if 0); SOMA_E_SIZE if it exceeds SOMA_NOALLOC_TRAIN_WAVES
+ * (larger batches: set opts->max_waves <= SOMA_NOALLOC_TRAIN_WAVES).  Every
+ * scratch byte a step reads is written by the same step first.  All calls on
+ * one GPU share the array: calls that overlap on one GPU (concurrent streams
+ * or threads) race and must be serialised by the caller.  Asynchronous. */
+#define SOMA_NOALLOC_TRAIN_WAVES 128u
+int32_t soma_train_step_noalloc(const float *features, const float *targets, uint32_t n,
+                                float *params, float *adam_m, float *adam_v, uint32_t step,
+                                const soma_train_opts *opts, float *grad_out, float *loss_out,
+                                void *stream);
+
 /* Releases the handle (host memory and a captured graph).  Call it after the
  * work queued through the handle has completed. */
 void soma_destroy(soma_system *sys);

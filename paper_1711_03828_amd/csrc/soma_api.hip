@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1443,7 +1444,14 @@ uint64_t soma_train_workspace_bytes(uint32_t max_waves) {
          align_up((uint64_t)max_waves * 4ull);
 }
 
-int32_t soma_train_step(const float *features, const float *targets, uint32_t n, float *params,
+}  // extern "C"
+
+namespace {
+
+// The training step on a scratch buffer `workspace` of workspace_bytes bytes
+// (the prepared network, per-wave partial gradients and loss partials; every
+// byte the step reads is written by the step first).
+int32_t train_step_impl(const float *features, const float *targets, uint32_t n, float *params,
                         float *adam_m, float *adam_v, uint32_t step, const soma_train_opts *o,
                         void *workspace, uint64_t workspace_bytes, float *grad_out,
                         float *loss_out, void *stream) {
@@ -1505,6 +1513,72 @@ int32_t soma_train_step(const float *features, const float *targets, uint32_t n,
   return SOMA_OK;
 }
 
+// Scratch of soma_train_step_noalloc: the prepared network, up to
+// kNoAllocWaves partial gradients and their loss partials, in a device array
+// of the library (one copy per GPU, held until the process ends).
+constexpr uint64_t align256(uint64_t x) { return (x + 255u) / 256u * 256u; }
+constexpr uint32_t kNoAllocWaves = SOMA_NOALLOC_TRAIN_WAVES;
+constexpr uint64_t kNoAllocBytes = align256(sizeof(soma::NetDev)) +
+                                   align256((uint64_t)kNoAllocWaves * soma::kPSize * 4u) +
+                                   align256((uint64_t)kNoAllocWaves * 4u);
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device.  Host code uses only this address, never the array's name.
+int32_t scratch_address(void **out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SOMA_E_UNSUPPORTED, "device %d", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(SOMA_E_HIP, "hipGetSymbolAddress returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SOMA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t soma_train_step(const float *features, const float *targets, uint32_t n, float *params,
+                        float *adam_m, float *adam_v, uint32_t step, const soma_train_opts *o,
+                        void *workspace, uint64_t workspace_bytes, float *grad_out,
+                        float *loss_out, void *stream) {
+  return train_step_impl(features, targets, n, params, adam_m, adam_v, step, o, workspace,
+                         workspace_bytes, grad_out, loss_out, stream);
+}
+
+int32_t soma_train_step_noalloc(const float *features, const float *targets, uint32_t n,
+                                float *params, float *adam_m, float *adam_v, uint32_t step,
+                                const soma_train_opts *o, float *grad_out, float *loss_out,
+                                void *stream) {
+  if (!o) return fail(SOMA_E_INVAL, "NULL argument");
+  if (n == 0) return fail(SOMA_E_INVAL, "empty batch");
+  const uint32_t chunks = (n + 63u) / 64u;
+  const uint32_t waves = o->max_waves ? (chunks < o->max_waves ? chunks : o->max_waves) : chunks;
+  if (waves > kNoAllocWaves)
+    return fail(SOMA_E_SIZE, "the batch needs %u partial gradients, more than the %u of the "
+                             "fixed scratch; set opts->max_waves <= %u", waves, kNoAllocWaves,
+                kNoAllocWaves);
+  void *ws = nullptr;
+  const int32_t rc = scratch_address(&ws);
+  if (rc) return rc;
+  return train_step_impl(features, targets, n, params, adam_m, adam_v, step, o, ws,
+                         kNoAllocBytes, grad_out, loss_out, stream);
+}
 
 }  // extern "C"
 

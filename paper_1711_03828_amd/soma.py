@@ -29,6 +29,7 @@ SOMA_SCHEME_SET = 0
 SOMA_SCHEME_MOLECULE = 1
 SOMA_HIST_DIRECT = 0
 SOMA_HIST_BINNED = 1
+SOMA_NOALLOC_TRAIN_WAVES = 128
 SOMA_FLAG_POSITION = 1
 SOMA_FLAG_NETWORK = 2
 SOMA_ALL_SPECIES = 0xFFFFFFFF
@@ -157,6 +158,8 @@ _SIGS = {
     "soma_train_workspace_bytes": ([_u32], ctypes.c_uint64),
     "soma_train_step": ([_P, _P, _u32, _P, _P, _P, _u32, ctypes.POINTER(soma_train_opts), _P,
                          _u64, _P, _P, _P], _i32),
+    "soma_train_step_noalloc": ([_P, _P, _u32, _P, _P, _P, _u32, ctypes.POINTER(soma_train_opts),
+                                 _P, _P, _P], _i32),
     "soma_sq_workspace_bytes": ([_P], ctypes.c_uint64),
     "soma_structure_factor": ([_P, _P, _u64, _P, _P], _i32),
     "soma_sq_shells": ([_P, _u32, _u32, _u32, _u32, _P, _P, _P, _pu32], _i32),
@@ -485,6 +488,14 @@ def soma_train_step(features_ptr, targets_ptr, n, params_ptr, m_ptr, v_ptr, step
     _check(_lib.soma_train_step(vp(features_ptr), vp(targets_ptr), n, vp(params_ptr), vp(m_ptr),
                                 vp(v_ptr), step, ctypes.byref(opts), vp(ws_ptr), ws_bytes,
                                 vp(grad_ptr), vp(loss_ptr), ctypes.c_void_p(stream)))
+
+
+def soma_train_step_noalloc(features_ptr, targets_ptr, n, params_ptr, m_ptr, v_ptr, step,
+                            opts: soma_train_opts, grad_ptr, loss_ptr, stream) -> None:
+    vp = lambda x: ctypes.c_void_p(x) if x else None
+    _check(_lib.soma_train_step_noalloc(vp(features_ptr), vp(targets_ptr), n, vp(params_ptr),
+                                        vp(m_ptr), vp(v_ptr), step, ctypes.byref(opts),
+                                        vp(grad_ptr), vp(loss_ptr), ctypes.c_void_p(stream)))
 
 
 def soma_destroy(h) -> None:
