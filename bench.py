@@ -324,16 +324,19 @@ def _c4_subsystem(side: int):
                           w.kappa_n, w.count_width)
 
 
-# Per sampler: (move kind, chain subsets per cycle, cycles per frame, frames
-# discarded, frames measured).  Run lengths aim at >= 3 tau_int discarded and
-# >= 50 tau_int measured for tau_int of about 9,000 (plain), 500 (learned)
-# and 400 (bond-Gibbs) cycles; the JSON states the ratio actually reached.
+# Per sampler, in the order run: (move kind, chain subsets per cycle, cycles
+# per frame, frames discarded, frames measured).  Run lengths aim at >= 3
+# tau_int discarded and >= 50 tau_int measured for tau_int of about 800
+# (learned), 10,000 (plain) and 400 (bond-Gibbs) cycles; the JSON states the
+# ratio actually reached.  The learned sampler runs first, from the common
+# start it made; the plain run follows from the learned one's end state, the
+# bond-Gibbs run from the plain one's.
 def _replica_plan(C, substeps: int, scale: float):
     def n(x):
         return max(20, int(round(x * scale)))
-    return {"plain": (C.SOMA_MOVE_LOCAL, 1, 200, n(150), n(2300)),
-            "learned": (C.SOMA_MOVE_MIXED, substeps, 10, n(160), n(2600)),
-            "gibbs": (C.SOMA_MOVE_GIBBS, substeps, 10, n(130), n(2100))}
+    return {"learned": (C.SOMA_MOVE_MIXED, substeps, 20, n(150), n(2000)),
+            "plain": (C.SOMA_MOVE_LOCAL, 1, 250, n(160), n(2000)),
+            "gibbs": (C.SOMA_MOVE_GIBBS, substeps, 10, n(200), n(2000))}
 
 
 def replica_statistics(params, substeps: int, p_learn: float, rates: dict, n_rep: int,
@@ -342,9 +345,11 @@ def replica_statistics(params, substeps: int, p_learn: float, rates: dict, n_rep
 
     n_rep replicas (independent Philox streams: replica index r) of the
     learned-proposal melt's chemistry at its density in a side^3-cell box, all
-    in one batched launch.  A common start (bond-Gibbs cycles from the Gaussian
-    walks), then per sampler a discarded transient and a measured run; frames
-    of all chains' end-to-end vectors every few cycles.  Per replica: tau_int
+    in one batched launch.  A common start (learned-sampler cycles from the
+    Gaussian walks: its stationary <Re^2> is near the plain sampler's, while
+    the bond-Gibbs sampler's lies about 8% lower), then per sampler a
+    discarded transient and a measured run; frames of every second chain's
+    end-to-end vector every few cycles.  Per replica: tau_int
     (Sokal window over its chains' pooled autocorrelation) and <Re^2>; means
     and standard errors over the replicas (seed-to-seed spread).  Uncorrelated
     samples/s use the full melt's cycle rate (`rates`, cycles/s) and the
@@ -366,15 +371,15 @@ def replica_statistics(params, substeps: int, p_learn: float, rates: dict, n_rep
         m.set_proposal(params)
     batch = Batch(melts)
     t0 = time.perf_counter()
-    equil = max(100, int(round(8000 * scale)) // 100 * 100)
+    equil = max(100, int(round(20000 * scale)) // 100 * 100)
     batch.set_substeps(substeps)
-    batch.capture_cycle(100, C.SOMA_MOVE_GIBBS)
+    batch.capture_cycle(100, C.SOMA_MOVE_MIXED)
     batch.run_cycle(equil // 100)
     out = {"workload": (f"{n_rep} replicas (independent Philox streams) of {w.name}: "
                         f"{nch} A16B16 chains on {side}^3 cells, the density and chiN of the "
                         f"262,144-chain melt; one batched launch; end-to-end vectors of "
                         f"every second chain"),
-           "common_start_gibbs_cycles": equil}
+           "common_start_learned_cycles": equil}
     kidx = {C.SOMA_MOVE_LOCAL: 0, C.SOMA_MOVE_MIXED: 2, C.SOMA_MOVE_GIBBS: 3}
     for name, (kind, ksub, fc, discard, frames) in _replica_plan(C, substeps, scale).items():
         batch.set_substeps(ksub)
@@ -924,7 +929,13 @@ def main():
     for _ in range(args.warmup):
         melt.sweep(1, move)
         melt.update_fields()
+    # launch shape: histogram mode x block size x grid, timed on real cycles
+    # (results do not depend on it)
+    tune_main = melt.autotune(3, move)
     torch.cuda.synchronize()
+    print(f"# tuned: histogram {'binned' if tune_main.hist_mode else 'direct'}, "
+          f"{tune_main.block_threads} threads, grid {tune_main.grid_blocks}, "
+          f"{tune_main.candidates} candidates", file=sys.stderr, flush=True)
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
            torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
@@ -968,9 +979,15 @@ def main():
                    "grid": list(w.grid), "chi_n": w.chi_n, "kappa_n": w.kappa_n,
                    "move": args.move, "count_width": w.count_width,
                    "step": "1 MC sweep (fused histogram) + field update"},
+        "launch": {"hist_mode": "binned" if tune_main.hist_mode else "direct",
+                   "block_threads": tune_main.block_threads, "grid_blocks": tune_main.grid_blocks,
+                   "candidates": tune_main.candidates},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w, args.move),
-                     "kernel": f"mc_sweep_{args.move}_kernel", "kernel_ms": sweep_ms,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(w, args.move) if not tune_main.hist_mode else None,
+                     "kernel": (f"mc_sweep_{args.move}_kernel" +
+                                (" + bin_apply_kernel" if tune_main.hist_mode else "")),
+                     "kernel_ms": sweep_ms,
                      "algorithmic_bytes": nbytes,
                      "bytes_per_bead": per_bead, "bytes_per_cell": per_cell},
         "field_update": {"ms": field_ms,
@@ -999,8 +1016,11 @@ def main():
     recount_ms = e0.elapsed_time(e1) / 3
     result["atomics"] = {"per_sweep": 2 * changed, "per_s": 2 * changed / (sweep_ms * 1e-3),
                          "beads_changing_cell": changed / w.n_beads,
+                         "hist_mode": "binned" if tune_main.hist_mode else "direct",
                          "recount_ms": recount_ms,
-                         "recount_atomics_per_s": w.n_beads / (recount_ms * 1e-3)}
+                         "recount_beads_per_s": w.n_beads / (recount_ms * 1e-3),
+                         "recount": "binned: a reservation atomic per (wave, brick), the "
+                                    "updates added brick by brick in LDS"}
     if args.move == "local":
         # the molecule-parallel order (Sec. 3.1.2, scheme 1) on the same melt
         melt.set_scheme(C.SOMA_SCHEME_MOLECULE)
@@ -1023,6 +1043,9 @@ def main():
     smc = {}
     for _ in range(2):
         melt.cycle(1, C.SOMA_MOVE_SMC)
+    tune_smc = melt.autotune(2, C.SOMA_MOVE_SMC)
+    smc["launch"] = {"hist_mode": "binned" if tune_smc.hist_mode else "direct",
+                     "block_threads": tune_smc.block_threads}
     e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
     e0.record(stream)
     melt.sweep(10, C.SOMA_MOVE_SMC)

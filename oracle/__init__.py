@@ -377,6 +377,7 @@ def _lib_mlp():
     L.orc_bf16.argtypes = [f32]
     L.orc_bf16.restype = f32
     L.orc_mlp_forward.argtypes = [P, P, i32, P, P]
+    L.orc_fold_params.argtypes = [P, P]
     L.orc_mlp_backward.argtypes = [P, P, P, i32, P]
     L.orc_nll.argtypes = [P, P, f64, f64, f64, P]
     L.orc_nll.restype = f64
@@ -407,6 +408,15 @@ def param_layout():
 
 def bf16(x: float) -> float:
     return _lib_mlp().orc_bf16(float(x))
+
+
+def fold_params(params: np.ndarray) -> np.ndarray:
+    """The network with its input standardisation folded into the first layer
+    (the form the learned move evaluates; see orc_fold_params)."""
+    p = _c(params, np.float32)
+    q = np.empty_like(p)
+    _lib_mlp().orc_fold_params(_ptr(p), _ptr(q))
+    return q
 
 
 def mlp_forward(params: np.ndarray, features: np.ndarray, bf16_mode=False):

@@ -846,6 +846,31 @@ static double orc_acc(double acc, double t, int bf16) {
   return (bf16 && orc_acc_f32) ? (double)((float)acc + (float)t) : acc + t;
 }
 
+/* The network as the learned move evaluates it: the input standardisation
+ * folded into the first layer.  W1'[m][k] = W1[m][k] scale[k] (one FP32
+ * product), b1'[m] = b1[m] - sum_k W1'[m][k] shift[k] in FP32 with k
+ * ascending (each product rounded before it is subtracted), shift 0 and
+ * scale 1; the other parameters unchanged.  In exact arithmetic the same
+ * function, W1' f + b1' = W1 ((f - shift) scale) + b1; in BF16 mode the
+ * raw features and W1' are what gets rounded. */
+void orc_fold_params(const float *p, float *q) {
+  memcpy(q, p, ORC_P_SIZE * sizeof(float));
+  for (int m = 0; m < ORC_NH; ++m) {
+    float b = p[ORC_P_B1 + m];
+    for (int k = 0; k < ORC_NF; ++k) {
+      const float w = p[ORC_P_W1 + m * ORC_NF + k] * p[ORC_P_SCALE + k];
+      const float t = w * p[ORC_P_SHIFT + k];
+      q[ORC_P_W1 + m * ORC_NF + k] = w;
+      b = b - t;
+    }
+    q[ORC_P_B1 + m] = b;
+  }
+  for (int k = 0; k < ORC_NF; ++k) {
+    q[ORC_P_SHIFT + k] = 0.0f;
+    q[ORC_P_SCALE + k] = 1.0f;
+  }
+}
+
 /* cache layout: x[60] a1[64] h1[64] a2[64] h2[64] */
 void orc_mlp_forward(const float *p, const double *f, int bf16, double *z,
                      double *cache) {
@@ -1222,8 +1247,10 @@ static void orc_dev_sample(const float *p, const double *x0, const double *xwin,
  * output's own FP32 sum plus, for every ambiguous rounding of the sample, the
  * change of the output when it is taken the other way.  Returns the number of
  * ambiguous roundings. */
-uint64_t orc_mlp_forward_envelope(const float *p, uint64_t n, const double *features, double *z,
-                                  double *bound) {
+uint64_t orc_mlp_forward_envelope(const float *p_in, uint64_t n, const double *features,
+                                  double *z, double *bound) {
+  float p[ORC_P_SIZE];   /* the learned move's network: standardisation folded */
+  orc_fold_params(p_in, p);
   orc_amb_list *amb = malloc(sizeof(orc_amb_list));
   uint64_t na = 0;
   for (uint64_t s = 0; s < n; ++s) {
@@ -1593,6 +1620,14 @@ uint64_t orc_mc_sweep_mixed(float *pos, uint32_t n_chains, uint32_t n, uint32_t 
   uint64_t n_cells = (uint64_t)nx * ny * nz;
   uint64_t acc_total = 0, acc_l = 0;
   uint32_t bad = 0;
+  /* BF16 mode evaluates the network as the learned move does (standardisation
+   * folded into the first layer); FP64 mode is the definition itself */
+  float folded[ORC_P_SIZE];
+  const float *net = params;
+  if (bf16) {
+    orc_fold_params(params, folded);
+    net = folded;
+  }
 #pragma omp parallel for schedule(static) reduction(+ : acc_total, acc_l, bad) num_threads(n_threads > 0 ? n_threads : 1)
   for (int64_t c = 0; c < (int64_t)n_chains; ++c) {
     float *chain = pos + (uint64_t)c * n * 3;
@@ -1619,7 +1654,7 @@ uint64_t orc_mc_sweep_mixed(float *pos, uint32_t n_chains, uint32_t n, uint32_t 
         }
         if (learned) {
           acc = orc_move_learned(chain, c_id, i, n, n_a, (double)k0, omega, n_cells, nx, ny,
-                                 nz, n_ref, params, m_max, lo, hi, bf16, seed, sweep,
+                                 nz, n_ref, net, m_max, lo, hi, bf16, seed, sweep,
                                  replica, &b, amb_flags ? &amb : NULL, nb_env, &env);
         } else {
           if (amb_flags) {

@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256, 2) void batched_sweep_kernel(const BatchLaunch
       const MixArgs mx = L.segs[sg].mx;
       uint32_t cnt[3];
       mixed_wave<COUNT64, VEC2, false>(a, mx, m, s_act[KIND == 2 ? m.wib : 0],
-                                s_tmp[KIND == 2 ? m.wib : 0], mx.net->shift, cnt);
+                                       s_tmp[KIND == 2 ? m.wib : 0], cnt);
       mixed_finish(a, mx, cnt);
     }
   }

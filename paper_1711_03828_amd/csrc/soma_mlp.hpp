@@ -28,7 +28,11 @@ constexpr int kActStride = 72;  // bf16 per LDS row: 64 units + 8 padding
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// Device copy of the network, ready for the MFMA tiles.
+// Device copy of the network, ready for the MFMA tiles.  The learned move
+// evaluates the first layer with the input standardisation folded in (w1f,
+// b1f: W1'[o][k] = W1[o][k] scale[k], b1'[o] = b1[o] - sum_k W1'[o][k] shift[k]
+// in FP32, k ascending), so raw features go straight to BF16; training uses
+// the standardised form (shift, scale, w1, b1).
 struct NetDev {
   float shift[64], scale[64];  // entries 60..63: shift 0, scale 0 (feature 0)
   float b1[64], b2[64], b3[16];
@@ -37,6 +41,8 @@ struct NetDev {
   __bf16 w3[16 * 64];          // rows >= 6 zero
   __bf16 w2t[64 * 64];         // W2 transposed: [in][out]
   __bf16 w3t[64 * 32];         // [hidden][k]: W3[k][hidden] for k < 6, else 0
+  float b1f[64];               // folded first-layer bias
+  __bf16 w1f[64 * 64];         // folded first-layer weights [out][in], in >= 60 zero
 };
 
 struct HeadArgs {
@@ -57,9 +63,17 @@ __global__ __launch_bounds__(256) void net_prepare_kernel(const float *__restric
     net->b1[i] = p[kPB1 + i];
     net->b2[i] = p[kPB2 + i];
     if (i < 16) net->b3[i] = i < kNO ? p[kPB3 + i] : 0.0f;
+    float b = p[kPB1 + i];   // folded bias of unit i (built without FP contraction)
+    for (int k = 0; k < kNF; ++k) {
+      const float w = p[kPW1 + i * kNF + k] * p[kPScale + k];
+      const float t = w * p[kPShift + k];
+      b = b - t;
+    }
+    net->b1f[i] = b;
   }
   const int o = i >> 6, k = i & 63;
   net->w1[i] = (__bf16)(k < kNF ? p[kPW1 + o * kNF + k] : 0.0f);
+  net->w1f[i] = (__bf16)(k < kNF ? p[kPW1 + o * kNF + k] * p[kPScale + k] : 0.0f);
   net->w2[i] = (__bf16)p[kPW2 + o * kNH + k];
   net->w2t[i] = (__bf16)p[kPW2 + k * kNH + o];
   if (o < 16) net->w3[i] = (__bf16)(o < kNO ? p[kPW3 + o * kNH + k] : 0.0f);
@@ -82,17 +96,22 @@ __device__ __forceinline__ bf16x8 lds_b8(const __bf16 *p) {
 // One fully connected layer of 64 outputs with ReLU for the wave's 64
 // samples: inputs from LDS tile `in`, outputs to LDS tile `out`.  Output
 // units are produced 16 at a time (one MFMA row tile), so only 16
-// accumulators per lane are live.
+// accumulators per lane are live.  The accumulators start at the bias; the
+// outputs are rounded to BF16 and then clipped at zero on the BF16 bit
+// patterns (a negative BF16 is a negative 16-bit integer), which gives the
+// same values as rounding the clipped FP32 sum.
 __device__ __forceinline__ void hidden_layer(const __bf16 *__restrict__ w,
                                              const float *__restrict__ bias,
                                              const __bf16 *in, __bf16 *out) {
   const int lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
   typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  typedef short i16x4 __attribute__((ext_vector_type(4)));
 #pragma unroll 2
   for (int mt = 0; mt < 4; ++mt) {
+    const f32x4 b = *reinterpret_cast<const f32x4 *>(bias + 16 * mt + 4 * g);
     f32x4 acc[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 4; ++t) acc[t] = b;
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) {
       const bf16x8 av = *reinterpret_cast<const bf16x8 *>(w + (16 * mt + col) * 64 + 32 * kb + 8 * g);
@@ -105,10 +124,9 @@ __device__ __forceinline__ void hidden_layer(const __bf16 *__restrict__ w,
     const int unit = 16 * mt + 4 * g;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      bf16x4 v;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) v[r] = (__bf16)relu(acc[t][r] + bias[unit + r]);
-      *reinterpret_cast<bf16x4 *>(out + (16 * t + col) * kActStride + unit) = v;
+      const bf16x4 v = __builtin_convertvector(acc[t], bf16x4);
+      const i16x4 h = __builtin_elementwise_max(__builtin_bit_cast(i16x4, v), (i16x4)0);
+      *reinterpret_cast<i16x4 *>(out + (16 * t + col) * kActStride + unit) = h;
     }
   }
 }
@@ -119,7 +137,7 @@ __device__ __forceinline__ void hidden_layer(const __bf16 *__restrict__ w,
 // `act`: it is written after the last read of `act`).
 __device__ __forceinline__ void wave_forward(const NetDev *__restrict__ net, __bf16 *act,
                                              __bf16 *tmp, float *zout) {
-  hidden_layer(net->w1, net->b1, act, tmp);
+  hidden_layer(net->w1f, net->b1f, act, tmp);
   hidden_layer(net->w2, net->b2, tmp, act);
   const int lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
   f32x4 acc[4];
@@ -221,27 +239,30 @@ __device__ __forceinline__ void gather_features(const Grid &g, const Neighbourho
   f[57] = bn.x; f[58] = bn.y; f[59] = bn.z;
 }
 
-// Gathers, standardises and stores the 60 features of a bead at r into one
-// LDS row of bf16 (entries 60..63 zero), 8 at a time.  `stdz` points at the
-// network's shift[64] followed by scale[64].  Returns the bead's own field in
-// its cell; `cell` receives that cell's index.
-__device__ __forceinline__ float features_to_row(const Grid &g, const float *__restrict__ omega,
-                                                 bool is_b, F3 r, F3 bp, F3 bn,
-                                                 const float *__restrict__ stdz, __bf16 *row,
-                                                 uint32_t &cell) {
-  const Neighbourhood nb = neighbourhood(g, r);
-  float f[kNF];
-  gather_features(g, nb, omega, is_b ? g.n_cells : 0u, is_b ? 0u : g.n_cells, bp, bn, f);
+// The 60 raw features of a row as BF16 (entries 60..63 zero), 8 at a time:
+// the learned move's first layer holds the standardisation.
+__device__ __forceinline__ void store_row(const float (&f)[kNF], __bf16 *row) {
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     bf16x8 v;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int k = 8 * c + j;
-      v[j] = k < kNF ? (__bf16)((f[k < kNF ? k : 0] - stdz[k]) * stdz[64 + k]) : (__bf16)0.0f;
+      v[j] = k < kNF ? (__bf16)f[k < kNF ? k : 0] : (__bf16)0.0f;
     }
     *reinterpret_cast<bf16x8 *>(row + 8 * c) = v;
   }
+}
+
+// Gathers the 60 features of a bead at r into one LDS row of bf16.  Returns
+// the bead's own field in its cell; `cell` receives that cell's index.
+__device__ __forceinline__ float features_to_row(const Grid &g, const float *__restrict__ omega,
+                                                 bool is_b, F3 r, F3 bp, F3 bn, __bf16 *row,
+                                                 uint32_t &cell) {
+  const Neighbourhood nb = neighbourhood(g, r);
+  float f[kNF];
+  gather_features(g, nb, omega, is_b ? g.n_cells : 0u, is_b ? 0u : g.n_cells, bp, bn, f);
+  store_row(f, row);
   cell = nb.centre;
   return f[13];   // own field at (dz, dy, dx) = (0, 0, 0)
 }
@@ -250,8 +271,7 @@ __device__ __forceinline__ float features_to_row(const Grid &g, const float *__r
 // size `halo_plane`): each of the 18 rows of three cells is one 12-byte load.
 __device__ __forceinline__ float features_to_row_halo(const Grid &g, const float *__restrict__ halo,
                                                       uint32_t halo_plane, bool is_b, F3 r,
-                                                      F3 bp, F3 bn, const float *__restrict__ stdz,
-                                                      __bf16 *row, uint32_t &cell) {
+                                                      F3 bp, F3 bn, __bf16 *row, uint32_t &cell) {
   uint32_t cx, cy, cz;
   cell3(g, r.x, r.y, r.z, cx, cy, cz);
   const uint32_t w = (uint32_t)g.nx + 2u;
@@ -271,16 +291,7 @@ __device__ __forceinline__ float features_to_row_halo(const Grid &g, const float
   }
   f[54] = bp.x; f[55] = bp.y; f[56] = bp.z;
   f[57] = bn.x; f[58] = bn.y; f[59] = bn.z;
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    bf16x8 v;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int k = 8 * c + j;
-      v[j] = k < kNF ? (__bf16)((f[k < kNF ? k : 0] - stdz[k]) * stdz[64 + k]) : (__bf16)0.0f;
-    }
-    *reinterpret_cast<bf16x8 *>(row + 8 * c) = v;
-  }
+  store_row(f, row);
   cell = cell_index(g, cx, cy, cz);
   return f[13];   // own field at (dz, dy, dx) = (0, 0, 0)
 }
@@ -297,7 +308,9 @@ __device__ __forceinline__ void head(const float *z, const HeadArgs &h, float (&
   }
 }
 
-// Stand-alone forward pass: raw features [n][60] -> z [n][6]; one wave per 64 samples.
+// Stand-alone forward pass as the learned move evaluates the network (first
+// layer with the standardisation folded in): raw features [n][60] -> z [n][6];
+// one wave per 64 samples.
 __global__ __launch_bounds__(256) void mlp_forward_kernel(const NetDev *__restrict__ net,
                                                           const float *__restrict__ feat,
                                                           uint32_t n, float *__restrict__ z) {
@@ -314,7 +327,7 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const NetDev *__restri
     for (int j = 0; j < 8; ++j) {
       const int k = 8 * c + j;
       const float x = (k < kNF && s < n) ? feat[(size_t)s * kNF + (k < kNF ? k : 0)] : 0.0f;
-      v[j] = k < kNF ? (__bf16)((x - net->shift[k]) * net->scale[k]) : (__bf16)0.0f;
+      v[j] = (__bf16)x;
     }
     *reinterpret_cast<bf16x8 *>(row + 8 * c) = v;
   }

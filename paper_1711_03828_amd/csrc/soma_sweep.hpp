@@ -580,13 +580,11 @@ struct MixArgs {
 // needs the bond vectors, so the two sets are handled one after the other.
 // ---------------------------------------------------------------------------
 // One wave's chains; act/tmp are the wave's two LDS activation tiles (the
-// network output z reuses tmp), stdz the network's standardisation constants
-// (shift[64] then scale[64]).  Returns through cnt the wave's accepted local
+// network output z reuses tmp).  Returns through cnt the wave's accepted local
 // moves, accepted learned moves and learned attempts.
 template <bool COUNT64, bool VEC2, bool BINNED>
 __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx, const LaneMap &m,
-                                           __bf16 *act, __bf16 *tmp, const float *stdz,
-                                           uint32_t cnt[3]) {
+                                           __bf16 *act, __bf16 *tmp, uint32_t cnt[3]) {
   float *zb = reinterpret_cast<float *>(tmp);
   __bf16 *row = act + m.lane * kActStride;
   const uint32_t N = a.n;
@@ -633,7 +631,7 @@ __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx
     bool net_bad = false;
     if (__ballot(learned) != 0ull) {
       features_to_row_halo(a.grid, mx.halo, mx.halo_plane, is_b, r, has_l ? left - r : zero3,
-                           has_r ? right - r : zero3, stdz, row, co);
+                           has_r ? right - r : zero3, row, co);
       w_old = field_at(a.omega, pl, co);   // energies from the field itself
       wave_forward(mx.net, act, tmp, zb);
       float mu[3], sig[3], lsig[3];
@@ -647,7 +645,7 @@ __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx
                      fmaf(a.step, uniform11(w.z), r.z)};
       rn = sel(learned, tl, tp);
       features_to_row_halo(a.grid, mx.halo, mx.halo_plane, is_b, rn, has_l ? left - rn : zero3,
-                           has_r ? right - rn : zero3, stdz, row, cn);
+                           has_r ? right - rn : zero3, row, cn);
       w_new = cn == co ? w_old : field_at(a.omega, pl, cn);
       wave_forward(mx.net, act, tmp, zb);
       float mun[3], sign[3], lsign[3];
@@ -735,7 +733,7 @@ __global__ __launch_bounds__(256) void mc_sweep_mixed_kernel(const SweepArgs a_i
   const SweepArgs a = resolve_sweep(a_in, 0u);
   const LaneMap m = lane_map(a);
   uint32_t cnt[3];
-  mixed_wave<COUNT64, VEC2, BINNED>(a, mx, m, s_act[m.wib], s_tmp[m.wib], mx.net->shift, cnt);
+  mixed_wave<COUNT64, VEC2, BINNED>(a, mx, m, s_act[m.wib], s_tmp[m.wib], cnt);
   mixed_finish(a, mx, cnt);
 }
 

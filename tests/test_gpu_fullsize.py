@@ -30,21 +30,29 @@ def big():
     return w, pos
 
 
-def test_fullsize_histogram_fields_and_sampled_sweep(orc, big):
+@pytest.fixture(scope="module")
+def big_fields(orc, big):
+    """The oracle's histogram and fields of the full-size initial positions."""
+    w, pos = big
+    inv_rho = constants(w)[3]
+    flush("oracle histogram + fields")
+    counts = orc.density_hist(pos, [Species(w.n_chains, 32, 16)], w.grid)
+    omega = orc.field_f32(counts, inv_rho, np.float32(w.chi_n), np.float32(w.kappa_n))
+    return counts, omega
+
+
+def test_fullsize_histogram_fields_and_sampled_sweep(orc, big, big_fields):
     from paper_1711_03828_amd import soma as C
     from paper_1711_03828_amd.melt import Melt
     w, pos = big
     k0, a, A, inv_rho = constants(w)
     sp = Species(w.n_chains, 32, 16)
-    flush("oracle histogram + fields")
-    counts = orc.density_hist(pos, [sp], w.grid)
-    omega = orc.field_f32(counts, inv_rho, np.float32(w.chi_n), np.float32(w.kappa_n))
+    counts, omega = big_fields
     flush("device init")
     melt = Melt(device_config(w), positions=torch.from_numpy(pos))
     torch.cuda.synchronize()
     np.testing.assert_array_equal(melt.counts_planes(), counts)
     np.testing.assert_array_equal(melt.omega.cpu().numpy(), omega)
-    del counts
 
     flush("device sweep")
     melt.sweep(1, C.SOMA_MOVE_LOCAL)
@@ -64,6 +72,44 @@ def test_fullsize_histogram_fields_and_sampled_sweep(orc, big):
     # a from-scratch recount of the device positions
     obs = melt.observables()
     assert obs.counts_conserved == 1
+    recount = torch.zeros_like(melt.counts)
+    C.soma_density_hist(melt.cfg, melt.pos.data_ptr(), recount.data_ptr(),
+                        torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(recount, melt.counts)
+    melt.close()
+
+
+def test_fullsize_smc_sweep_sampled(orc, big, big_fields):
+    """One smart-MC sweep of the whole 134M-bead melt on the device (field
+    gradient from the neighbour gathers); the oracle sweeps 4096 chains spread
+    over the whole range one by one from the same positions and fields.
+    Positions within 1e-5 Re0 per coordinate; chains beyond it at most
+    ceil(1e-6 x moves)."""
+    from paper_1711_03828_amd import soma as C
+    from paper_1711_03828_amd.melt import Melt
+    w, pos = big
+    k0, a, A, inv_rho = constants(w)
+    _, omega = big_fields
+    melt = Melt(device_config(w), positions=torch.from_numpy(pos))
+    flush("device smart-MC sweep")
+    melt.sweep(1, C.SOMA_MOVE_SMC)
+    torch.cuda.synchronize()
+    got = melt.pos.cpu().numpy().reshape(w.n_chains, 32, 3)
+    sample = np.unique(np.linspace(0, w.n_chains - 1, 4096).astype(np.int64))
+    tol = 1e-5 * w.re_cells
+    bad = 0
+    for c in sample:
+        ref = pos.reshape(w.n_chains, 32, 3)[c].copy()
+        orc.mc_sweep(ref.reshape(-1, 3), Species(1, 32, 16), omega, w.grid, k0=k0,
+                     n_ref=w.n_ref, move_kind=orc.MOVE_SMC, step=A, seed=w.seed, sweep=0,
+                     chain_base=int(c))
+        bad += int(np.abs(ref.astype(np.float64) - got[c].astype(np.float64)).max() > tol)
+    allowed = math.ceil(1e-6 * w.n_beads)
+    flush("smart-MC sampled chains", sample.size, "beyond 1e-5 Re0", bad, "allowed", allowed)
+    assert bad <= allowed
+    obs = melt.observables()
+    assert obs.counts_conserved == 1 and obs.error_flags == 0
     recount = torch.zeros_like(melt.counts)
     C.soma_density_hist(melt.cfg, melt.pos.data_ptr(), recount.data_ptr(),
                         torch.cuda.current_stream().cuda_stream)

@@ -55,8 +55,10 @@ def test_forward_matches_bf16_oracle(orc, n):
     torch.cuda.synchronize()
     got = z.cpu().numpy().astype(np.float64)
     exp, bound, n_amb = orc.mlp_forward_envelope(params, feats.astype(np.float64))
-    np.testing.assert_array_equal(exp, orc.mlp_forward(params, feats.astype(np.float64),
-                                                       bf16_mode=True))
+    # the device evaluates the network with the standardisation folded into the
+    # first layer; the envelope's centre is the oracle's BF16 forward of that form
+    np.testing.assert_array_equal(exp, orc.mlp_forward(orc.fold_params(params),
+                                                       feats.astype(np.float64), bf16_mode=True))
     excess = np.abs(got - exp) - bound
     flush("n", n, "ambiguous roundings", n_amb, "max |dz|", np.abs(got - exp).max(),
           "max |dz| / bound", (np.abs(got - exp) / bound).max(), "max excess", excess.max())

@@ -210,3 +210,35 @@ def test_nll_gradient_in_z_matches_finite_differences(orc):
             zm = z.copy(); zm[k] -= h
             fd = (orc.nll(zp, dr, **HEAD)[0] - orc.nll(zm, dr, **HEAD)[0]) / (2 * h)
             assert fd == pytest.approx(dz[k], rel=1e-6, abs=1e-8)
+
+
+def test_fold_params_is_the_same_network(orc):
+    """The folded form of the learned move's network (standardisation inside the
+    first layer): identity for shift 0 and scale 1 (bit for bit), a hand-worked
+    unit, and in FP64 the same outputs as the standardised network up to the
+    FP32 rounding of W1' and b1' (a planted wrong sign of the shift term is
+    caught by the same comparison)."""
+    L = synth.MLP_LAYOUT
+    p0 = synth.mlp_params(5, shift=np.zeros(60, np.float32), scale=np.ones(60, np.float32))
+    np.testing.assert_array_equal(orc.fold_params(p0), p0)
+    # hand case: unit 0 sees only feature 0 with weight 2, shift 5, scale 3
+    p = np.zeros(8576, np.float32)
+    p[L["scale"]:L["scale"] + 60] = 1.0
+    p[L["w1"]] = 2.0
+    p[L["scale"]] = 3.0
+    p[L["shift"]] = 5.0
+    p[L["b1"]] = 0.25
+    q = orc.fold_params(p)
+    assert q[L["w1"]] == 6.0 and q[L["b1"]] == np.float32(0.25 - 30.0)
+    assert np.all(q[L["shift"]:L["shift"] + 60] == 0.0) and np.all(q[L["scale"]:L["scale"] + 60] == 1.0)
+    # random networks with real standardisation constants
+    g = np.random.default_rng(12)
+    f = g.standard_normal((200, 60)) * 8.0 + 20.0
+    p = synth.mlp_params(9, weight_gain=1.1, out_gain=0.5, shift=(20 + g.standard_normal(60)).astype(np.float32),
+                         scale=(0.1 + 0.2 * g.random(60)).astype(np.float32))
+    z = orc.mlp_forward(p, f, bf16_mode=False)
+    zf = orc.mlp_forward(orc.fold_params(p), f, bf16_mode=False)
+    assert np.abs(zf - z).max() < 1e-4 * (1.0 + np.abs(z).max())
+    bad = orc.fold_params(p)
+    bad[L["b1"]:L["b1"] + 64] = p[L["b1"]:L["b1"] + 64] + (p[L["b1"]:L["b1"] + 64] - bad[L["b1"]:L["b1"] + 64])
+    assert np.abs(orc.mlp_forward(bad, f, bf16_mode=False) - z).max() > 1e-2
