@@ -326,21 +326,21 @@ def _c4_subsystem(side: int):
 
 # Per sampler, in the order run: (move kind, chain subsets per cycle, cycles
 # per frame, frames discarded, frames measured).  Run lengths aim at >= 3
-# tau_int discarded and >= 50 tau_int measured for tau_int of about 800
-# (learned), 10,000 (plain) and 400 (bond-Gibbs) cycles; the JSON states the
-# ratio actually reached.  The learned sampler runs first, from the common
-# start it made; the plain run follows from the learned one's end state, the
-# bond-Gibbs run from the plain one's.
+# tau_int discarded and >= 50 tau_int measured for the tau_int these replicas
+# show (about 600 cycles learned with 2 refreshes, 16,700 plain, 400
+# bond-Gibbs); the JSON states the ratio actually reached.  The learned
+# sampler runs first, from the common start it made; the plain run follows
+# from the learned one's end state, the bond-Gibbs run from the plain one's.
 def _replica_plan(C, substeps: int, scale: float):
     def n(x):
         return max(20, int(round(x * scale)))
-    return {"learned": (C.SOMA_MOVE_MIXED, substeps, 20, n(150), n(2000)),
-            "plain": (C.SOMA_MOVE_LOCAL, 1, 250, n(160), n(2000)),
-            "gibbs": (C.SOMA_MOVE_GIBBS, substeps, 10, n(200), n(2000))}
+    return {"learned": (C.SOMA_MOVE_MIXED, substeps, 20, n(100), n(1600)),
+            "plain": (C.SOMA_MOVE_LOCAL, 1, 400, n(130), n(2100)),
+            "gibbs": (C.SOMA_MOVE_GIBBS, substeps, 10, n(150), n(2100))}
 
 
 def replica_statistics(params, substeps: int, p_learn: float, rates: dict, n_rep: int,
-                       side: int, scale: float):
+                       side: int, scale: float, plan=None):
     """tau_int and <Re^2> of each sampler from independent replicas.
 
     n_rep replicas (independent Philox streams: replica index r) of the
@@ -381,7 +381,8 @@ def replica_statistics(params, substeps: int, p_learn: float, rates: dict, n_rep
                         f"every second chain"),
            "common_start_learned_cycles": equil}
     kidx = {C.SOMA_MOVE_LOCAL: 0, C.SOMA_MOVE_MIXED: 2, C.SOMA_MOVE_GIBBS: 3}
-    for name, (kind, ksub, fc, discard, frames) in _replica_plan(C, substeps, scale).items():
+    plan = plan or _replica_plan(C, substeps, scale)
+    for name, (kind, ksub, fc, discard, frames) in plan.items():
         batch.set_substeps(ksub)
         batch.capture_cycle(fc, kind)
         batch.run_cycle(discard)
@@ -433,6 +434,8 @@ def replica_statistics(params, substeps: int, p_learn: float, rates: dict, n_rep
                  math.hypot(out[a]["re2_err"], out[b]["re2_err"]))
         return g, g * rel, shift
 
+    if not all(k in out for k in ("learned", "plain", "gibbs")):
+        return out
     g, ge, sh = ratio("learned", "plain")
     out["gain_learned_over_plain"] = g
     out["gain_err"] = ge
@@ -1014,7 +1017,26 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     recount_ms = e0.elapsed_time(e1) / 3
+    # the device's scattered-update rates over an array the size of this melt's
+    # counts, with as many updates as the sweep's direct histogram issues
+    probe = torch.zeros(melt.counts.numel() * melt.counts.element_size() // 4,
+                        dtype=torch.int32, device="cuda")
+    probe_rates = {}
+    for mode, name in ((0, "atomic_random"), (1, "atomic_local"), (2, "store_random")):
+        C.soma_probe_atomics(probe.data_ptr(), probe.numel(), 2 * changed, mode, 1,
+                             stream.cuda_stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for rep in range(3):
+            C.soma_probe_atomics(probe.data_ptr(), probe.numel(), 2 * changed, mode, 2 + rep,
+                                 stream.cuda_stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        probe_rates[name] = {"per_s": 2 * changed / (ms * 1e-3), "ms": ms}
+    del probe
     result["atomics"] = {"per_sweep": 2 * changed, "per_s": 2 * changed / (sweep_ms * 1e-3),
+                         "probe": probe_rates,
                          "beads_changing_cell": changed / w.n_beads,
                          "hist_mode": "binned" if tune_main.hist_mode else "direct",
                          "recount_ms": recount_ms,

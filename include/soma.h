@@ -351,6 +351,18 @@ int32_t soma_set_scheme(soma_system *sys, uint32_t scheme);
 int32_t soma_choose_scheme(soma_system *sys, uint32_t cycles, void *stream, uint32_t *chosen,
                            float *ms);
 
+/* Measurement only (the roofline of the histogram updates): n_updates
+ * scattered 32-bit updates of the device array words[n_words] on `stream`,
+ * one thread each, addresses from an integer hash of the thread index and
+ * `seed`.  mode 0: atomicAdd(+1) at a uniformly random word; mode 1:
+ * atomicAdd(+1) at a random word of a 4096-word window that moves with the
+ * thread index (the locality of a sweep's count updates); mode 2: a plain
+ * store at a uniformly random word.  Time it with events on `stream`.
+ * SOMA_E_INVAL for an empty or misaligned array or an unknown mode.
+ * Asynchronous. */
+int32_t soma_probe_atomics(uint32_t *words, uint64_t n_words, uint64_t n_updates,
+                           uint32_t mode, uint32_t seed, void *stream);
+
 /* Recounts buf->counts from buf->pos (cleared first).  Needed only after the
  * caller has changed positions outside the library.  Asynchronous. */
 int32_t soma_rebuild_histogram(soma_system *sys, void *stream);

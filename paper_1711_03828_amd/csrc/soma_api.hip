@@ -819,6 +819,20 @@ int32_t soma_set_histogram(soma_system *sys, uint32_t mode) {
   return SOMA_OK;
 }
 
+int32_t soma_probe_atomics(uint32_t *words, uint64_t n_words, uint64_t n_updates,
+                           uint32_t mode, uint32_t seed, void *stream) {
+  if (!words || n_words == 0) return fail(SOMA_E_INVAL, "empty word array");
+  if (mode > 2) return fail(SOMA_E_INVAL, "probe mode %u", mode);
+  if (n_updates == 0) return SOMA_OK;
+  if (!aligned(words, 4)) return fail(SOMA_E_INVAL, "words must be 4-byte aligned");
+  const uint64_t blocks = (n_updates + 255) / 256;
+  if (blocks >= (1ull << 31)) return fail(SOMA_E_UNSUPPORTED, "too many updates");
+  hipLaunchKernelGGL(soma::probe_atomics_kernel, dim3((uint32_t)blocks), dim3(256), 0,
+                     reinterpret_cast<hipStream_t>(stream), words, n_words, n_updates, mode, seed);
+  LAUNCH_TRY();
+  return SOMA_OK;
+}
+
 int32_t soma_set_sweep_blocks(soma_system *sys, uint32_t blocks) {
   if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
   sys->sweep_blocks = blocks;

@@ -38,6 +38,30 @@ __global__ __launch_bounds__(256) void density_hist_kernel(
   }
 }
 
+// Throughput probe of scattered 32-bit updates (measurement only): thread i
+// updates word addr(i) of `words`.  mode 0: atomicAdd at a uniformly random
+// word; mode 1: atomicAdd at a word chosen within a window of 4096 words that
+// moves with the thread index (the locality of a sweep's count updates,
+// whose waves work on compact regions); mode 2: a plain store at a uniformly
+// random word.  Addresses from a 32-bit integer hash of (i, seed).
+__global__ __launch_bounds__(256) void probe_atomics_kernel(uint32_t *words, uint64_t n_words,
+                                                            uint64_t n_updates, uint32_t mode,
+                                                            uint32_t seed) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_updates) return;
+  uint32_t h = (uint32_t)i * 0x9E3779B1u ^ seed;
+  h ^= h >> 15; h *= 0x85EBCA77u; h ^= h >> 13; h *= 0xC2B2AE3Du; h ^= h >> 16;
+  uint64_t addr;
+  if (mode == 1) {
+    const uint64_t base = (i * 7u) % n_words;           // moves slowly with i
+    addr = (base + (h & 4095u)) % n_words;
+  } else {
+    addr = (((uint64_t)h << 32) | (h * 0x27D4EB2Fu)) % n_words;
+  }
+  if (mode == 2) words[addr] = (uint32_t)i;
+  else atomicAdd(words + addr, 1u);
+}
+
 // Fill a buffer of n_words 32-bit words with zeros (a kernel, not a memset
 // node, so that it can live inside a captured graph).
 __global__ __launch_bounds__(256) void zero_kernel(uint32_t *p, uint64_t n_words) {

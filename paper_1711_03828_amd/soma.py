@@ -115,6 +115,7 @@ _SIGS = {
     "soma_set_sweep_blocks": ([_P, _u32], _i32),
     "soma_set_histogram": ([_P, _u32], _i32),
     "soma_set_sweep_threads": ([_P, _u32], _i32),
+    "soma_probe_atomics": ([_P, _u64, _u64, _u32, _u32, _P], _i32),
     "soma_set_scheme": ([_P, _u32], _i32),
     "soma_set_hamiltonian": ([_P, _u32, _P], _i32),
     "soma_set_types": ([_P, _u32, _P, _P, _u64, _P, _u64, _P], _i32),
@@ -220,6 +221,12 @@ def soma_set_histogram(h, mode: int) -> None:
 
 def soma_set_sweep_threads(h, threads: int) -> None:
     _check(_lib.soma_set_sweep_threads(h, threads))
+
+
+def soma_probe_atomics(words_ptr: int, n_words: int, n_updates: int, mode: int, seed: int,
+                       stream) -> None:
+    _check(_lib.soma_probe_atomics(ctypes.c_void_p(words_ptr), n_words, n_updates, mode, seed,
+                                   ctypes.c_void_p(stream)))
 
 
 def soma_set_external(h, ext_ptr, ext_bytes: int, forbid_ptr, forbid_bytes: int, stream) -> None:

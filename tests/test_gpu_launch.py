@@ -91,3 +91,17 @@ def test_autotune_search_space_keeps_results(tmp_path, kind_name, n_expected):
     assert t2.from_cache == 1 and t2.hist_mode == t.hist_mode and t2.block_threads == t.block_threads
     tuned.close()
     plain.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_probe_atomics_adds_every_update(mode):
+    """The throughput probe's atomic modes add exactly one per update."""
+    from paper_1711_03828_amd import soma as C
+    words = torch.zeros(100003, dtype=torch.int32, device="cuda")
+    C.soma_probe_atomics(words.data_ptr(), words.numel(), 1234567, mode, 9,
+                         torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert int(words.sum().item()) == 1234567
+    with pytest.raises(C.SomaError):
+        C.soma_probe_atomics(words.data_ptr(), words.numel(), 10, 3, 9,
+                             torch.cuda.current_stream().cuda_stream)
