@@ -19,6 +19,7 @@ import math
 import os
 import sys
 import time
+import types
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -51,6 +52,7 @@ def field_bytes(w):
 
 # Sources the sweep kernels and their launches are built from.
 SWEEP_SOURCES = ("paper_1711_03828_amd/csrc/soma_api.hip",
+                 "paper_1711_03828_amd/csrc/soma_bins.hpp",
                  "paper_1711_03828_amd/csrc/soma_device.hpp",
                  "paper_1711_03828_amd/csrc/soma_mlp.hpp",
                  "paper_1711_03828_amd/csrc/soma_sweep.hpp")
@@ -66,18 +68,22 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(w, move: str):
-    """HBM bytes per sweep launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+def measured_traffic(w, move: str, launch: dict):
+    """HBM bytes per sweep (the sweep kernel, plus the bin-apply kernel when the
+    count updates are binned) from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summary (scaled by the copy-kernel calibration), or None if the kernel
-    sources changed since it was taken or no summary covers this workload."""
+    sources changed since it was taken or no record covers this workload and
+    launch shape (histogram mode, block size, grid)."""
     path = os.path.join(ROOT, "profiles", f"mc_sweep_{move}_diblock_4M_N32_traffic.json")
     if w.name != "diblock_4M_N32_grid384x384x192" or not os.path.exists(path):
         return None
     with open(path) as fh:
-        rec = json.load(fh)
-    if rec.get("kernel_source_sha1") != kernel_source_digest():
-        return None
-    return rec["traffic_bytes"]
+        recs = json.load(fh).get("records", [])
+    digest = kernel_source_digest()
+    for rec in recs:
+        if rec["kernel_source_sha1"] == digest and rec["launch"] == launch:
+            return rec["traffic_bytes"]
+    return None
 
 
 def _cpu_model() -> str:
@@ -184,7 +190,7 @@ def _re_vectors(melt, n):
 
 def learned_leg(p_learn: float, equil_cycles: int, substeps: int, lag: int = 64,
                 n_rep: int = 8, side: int = 32, tau_scale: float = 1.0,
-                train_steps: int = 3000):
+                train_steps: int = 3000, self_term: int = 1):
     """Plain vs learned proposal on the 262,144-chain melt (96^3 cells, chiN 25).
 
     1. Training data from the plain sampler: 10 rounds of 2^20 random beads,
@@ -210,6 +216,11 @@ def learned_leg(p_learn: float, equil_cycles: int, substeps: int, lag: int = 64,
        (2 tau_int), cycles/s of the full melt from step 2.  The bond-Gibbs
        proposal draws each bead from its law given its bonded neighbours and
        is accepted on the field term alone.
+    With self_term = 1 every sampler (steps 2-4) charges a cell-changing move
+    the bead's own share of the grid Hamiltonian's change (soma_set_self_term):
+    the samplers' <Re^2> then agree within a few standard errors, where without
+    it moves that change cell more often (the learned and bond-Gibbs ones) end
+    up more or less stretched than the plain sampler's chains.
     """
     import torch
 
@@ -242,7 +253,8 @@ def learned_leg(p_learn: float, equil_cycles: int, substeps: int, lag: int = 64,
     train_ms = e0.elapsed_time(e1) / 50
     del probe, feats, disp
     melt.set_proposal(params)
-    out = {"workload": w.name, "p_learn": p_learn,
+    C.soma_set_self_term(melt.handle, self_term)
+    out = {"workload": w.name, "p_learn": p_learn, "self_term": self_term,
            "training": {"samples": n_samples, "lag_cycles": lag, "adam_steps": train_steps,
                         "batch": 8192, "loss_first": losses[0], "loss_last": losses[-1],
                         "seconds_collect_and_train": t_train}}
@@ -298,6 +310,7 @@ def learned_leg(p_learn: float, equil_cycles: int, substeps: int, lag: int = 64,
     melt.capture_cycle(100, C.SOMA_MOVE_MIXED)
     melt.run_cycle(max(1, equil_cycles // 100))
     melt.set_substeps(1)
+    C.soma_set_self_term(melt.handle, 0)    # training targets: the paper's plain sampler
     feats, disp = learned.collect(melt, 1 << 20, lag, 4, first_round=1000)
     tune = learned.Trainer(params, lr=1e-3)
     tl = tune.run(feats, disp, steps=2000, batch=8192, loss_every=500)
@@ -309,7 +322,7 @@ def learned_leg(p_learn: float, equil_cycles: int, substeps: int, lag: int = 64,
     melt.close()
     if tau_scale > 0:
         out["statistics"] = replica_statistics(params, substeps, p_learn, rates, n_rep, side,
-                                               tau_scale)
+                                               tau_scale, self_term=self_term)
     return out
 
 
@@ -327,20 +340,20 @@ def _c4_subsystem(side: int):
 # Per sampler, in the order run: (move kind, chain subsets per cycle, cycles
 # per frame, frames discarded, frames measured).  Run lengths aim at >= 3
 # tau_int discarded and >= 50 tau_int measured for the tau_int these replicas
-# show (about 600 cycles learned with 2 refreshes, 16,700 plain, 400
-# bond-Gibbs); the JSON states the ratio actually reached.  The learned
+# show with the self term (about 560 cycles learned with 8 refreshes, 21,000
+# plain, 400 bond-Gibbs); the JSON states the ratio actually reached.  The learned
 # sampler runs first, from the common start it made; the plain run follows
 # from the learned one's end state, the bond-Gibbs run from the plain one's.
 def _replica_plan(C, substeps: int, scale: float):
     def n(x):
         return max(20, int(round(x * scale)))
     return {"learned": (C.SOMA_MOVE_MIXED, substeps, 20, n(100), n(1600)),
-            "plain": (C.SOMA_MOVE_LOCAL, 1, 400, n(130), n(2100)),
+            "plain": (C.SOMA_MOVE_LOCAL, 1, 400, n(160), n(2650)),
             "gibbs": (C.SOMA_MOVE_GIBBS, substeps, 10, n(150), n(2100))}
 
 
 def replica_statistics(params, substeps: int, p_learn: float, rates: dict, n_rep: int,
-                       side: int, scale: float, plan=None):
+                       side: int, scale: float, plan=None, self_term: int = 0):
     """tau_int and <Re^2> of each sampler from independent replicas.
 
     n_rep replicas (independent Philox streams: replica index r) of the
@@ -369,6 +382,7 @@ def replica_statistics(params, substeps: int, p_learn: float, rates: dict, n_rep
     melts = [Melt(make_config(w, replica=r, p_learn=p_learn)) for r in range(n_rep)]
     for m in melts:
         m.set_proposal(params)
+        C.soma_set_self_term(m.handle, self_term)
     batch = Batch(melts)
     t0 = time.perf_counter()
     equil = max(100, int(round(20000 * scale)) // 100 * 100)
@@ -379,7 +393,7 @@ def replica_statistics(params, substeps: int, p_learn: float, rates: dict, n_rep
                         f"{nch} A16B16 chains on {side}^3 cells, the density and chiN of the "
                         f"262,144-chain melt; one batched launch; end-to-end vectors of "
                         f"every second chain"),
-           "common_start_learned_cycles": equil}
+           "common_start_learned_cycles": equil, "self_term": self_term}
     kidx = {C.SOMA_MOVE_LOCAL: 0, C.SOMA_MOVE_MIXED: 2, C.SOMA_MOVE_GIBBS: 3}
     plan = plan or _replica_plan(C, substeps, scale)
     for name, (kind, ksub, fc, discard, frames) in plan.items():
@@ -865,8 +879,14 @@ def main():
                     help="skip the plain-vs-learned proposal comparison")
     ap.add_argument("--p-learn", type=float, default=1.0,
                     help="probability of the learned move per bead (else the local move)")
-    ap.add_argument("--learned-substeps", type=int, default=2,
-                    help="chain subsets (field refreshes) per cycle for the learned sampler")
+    ap.add_argument("--learned-substeps", type=int, default=8,
+                    help="chain subsets (field refreshes) per cycle for the learned and "
+                         "bond-Gibbs samplers of the 262,144-chain melt")
+    ap.add_argument("--blend-substeps", type=int, default=2,
+                    help="chain subsets per cycle for the blend leg's learned sampler")
+    ap.add_argument("--no-self-term", action="store_true",
+                    help="the learned-proposal leg's samplers without the single-bead self "
+                         "term of cell-changing moves (the paper's SCMF)")
     ap.add_argument("--replicas", type=int, default=8,
                     help="independent replicas for tau_int and <Re^2> of each sampler")
     ap.add_argument("--replica-side", type=int, default=32,
@@ -902,6 +922,10 @@ def main():
                     help="skip the cylinder-forming film after the lamella-forming one")
     ap.add_argument("--film-cycles", type=int, default=2500,
                     help="SCMF cycles of the film run after the quench (0: skip the film)")
+    ap.add_argument("--launch", default="auto",
+                    help="launch shape of the main leg's sweeps: 'auto' (autotuned) or "
+                         "HIST,THREADS,GRID, e.g. binned,128,0 (HIST: direct or binned; "
+                         "GRID 0: one block per tile group)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -909,6 +933,11 @@ def main():
         print("bench.py measures one GPU only: the SCMF path here runs on a single "
               "device (--gpus 1).", file=sys.stderr)
         sys.exit(2)
+    if args.launch != "auto":
+        parts = args.launch.split(",")
+        if (len(parts) != 3 or parts[0] not in ("direct", "binned")
+                or not all(p.isdigit() for p in parts[1:])):
+            ap.error("--launch: 'auto' or HIST,THREADS,GRID (HIST direct or binned)")
 
     import torch
 
@@ -933,8 +962,17 @@ def main():
         melt.sweep(1, move)
         melt.update_fields()
     # launch shape: histogram mode x block size x grid, timed on real cycles
-    # (results do not depend on it)
-    tune_main = melt.autotune(3, move)
+    # (results do not depend on it), or the one named by --launch
+    if args.launch == "auto":
+        tune_main = melt.autotune(3, move)
+    else:
+        hist, threads, blocks = args.launch.split(",")
+        tune_main = types.SimpleNamespace(
+            hist_mode=C.SOMA_HIST_BINNED if hist == "binned" else C.SOMA_HIST_DIRECT,
+            block_threads=int(threads), grid_blocks=int(blocks), candidates=0)
+        melt.set_histogram(tune_main.hist_mode)
+        C.soma_set_sweep_threads(melt.handle, tune_main.block_threads)
+        C.soma_set_sweep_blocks(melt.handle, tune_main.grid_blocks)
     torch.cuda.synchronize()
     print(f"# tuned: histogram {'binned' if tune_main.hist_mode else 'direct'}, "
           f"{tune_main.block_threads} threads, grid {tune_main.grid_blocks}, "
@@ -963,6 +1001,8 @@ def main():
 
     ms_per_step = wall * 1e3 / args.steps
     value = w.n_beads * args.steps / wall
+    launch = {"hist_mode": "binned" if tune_main.hist_mode else "direct",
+              "block_threads": tune_main.block_threads, "grid_blocks": tune_main.grid_blocks}
     nbytes, per_bead, per_cell = algorithmic_bytes(w)
     achieved = nbytes / (sweep_ms * 1e-3) / 1e9
     result = {
@@ -982,12 +1022,10 @@ def main():
                    "grid": list(w.grid), "chi_n": w.chi_n, "kappa_n": w.kappa_n,
                    "move": args.move, "count_width": w.count_width,
                    "step": "1 MC sweep (fused histogram) + field update"},
-        "launch": {"hist_mode": "binned" if tune_main.hist_mode else "direct",
-                   "block_threads": tune_main.block_threads, "grid_blocks": tune_main.grid_blocks,
-                   "candidates": tune_main.candidates},
+        "launch": dict(launch, candidates=tune_main.candidates),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(w, args.move) if not tune_main.hist_mode else None,
+                     "traffic": measured_traffic(w, args.move, launch),
                      "kernel": (f"mc_sweep_{args.move}_kernel" +
                                 (" + bin_apply_kernel" if tune_main.hist_mode else "")),
                      "kernel_ms": sweep_ms,
@@ -1105,7 +1143,8 @@ def main():
         result["learned_proposal"] = learned_leg(args.p_learn, args.equil_cycles,
                                                  args.learned_substeps, args.learned_lag,
                                                  args.replicas, args.replica_side,
-                                                 args.tau_scale, args.train_steps)
+                                                 args.tau_scale, args.train_steps,
+                                                 0 if args.no_self_term else 1)
     if not args.no_batched:
         result["batched"] = batched_leg(50)
     if not args.no_schemes:
@@ -1119,7 +1158,7 @@ def main():
     if not args.no_blend:
         result["blend"] = blend_leg(50, args.tau_frames // 2, args.frame_cycles,
                                     args.plain_frame_mult, args.equil_cycles // 2, 1.0 / 16,
-                                    args.learned_substeps, args.p_learn, args.learned_lag)
+                                    args.blend_substeps, args.p_learn, args.learned_lag)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(result), flush=True)

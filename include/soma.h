@@ -351,6 +351,21 @@ int32_t soma_set_scheme(soma_system *sys, uint32_t scheme);
 int32_t soma_choose_scheme(soma_system *sys, uint32_t cycles, void *stream, uint32_t *chosen,
                            float *ms);
 
+/* Single-bead energy of cell-changing moves.  The quasi-instantaneous field
+ * of Sec. 2.2 charges a move of a bead of type t from cell c to c'
+ * (omega_t(c') - omega_t(c))/N, with the bead itself still counted in c.
+ * The grid Hamiltonian (Eqs. (5), (6), (8)) is quadratic in the counts, and
+ * the exact change adds the second difference kappaN/(N rho) (K^1 form;
+ * (kappaN - chiN/2)/(N rho) for K^0).  on = 1 adds it to every move that
+ * changes cell (local, smart-MC, bond-Gibbs and learned moves of linear
+ * chains of two types, SET order, single melts and batches created after the
+ * call); on = 0 (default) is the paper's SCMF.  With the fields frozen the
+ * term is not the energy difference of any fixed distribution: it is meant
+ * for SCMF cycles, where it removes the bias that moves changing cell more
+ * often (larger moves) would otherwise carry.  SOMA_E_UNSUPPORTED for other
+ * systems.  Capture graphs again after a change. */
+int32_t soma_set_self_term(soma_system *sys, uint32_t on);
+
 /* Measurement only (the roofline of the histogram updates): n_updates
  * scattered 32-bit updates of the device array words[n_words] on `stream`,
  * one thread each, addresses from an integer hash of the thread index and

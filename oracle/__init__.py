@@ -65,6 +65,7 @@ def lib() -> ctypes.CDLL:
         L.orc_field_f32.argtypes = [P, u64, f32, f32, f32, u32, P, P, P]
         L.orc_h_nb.argtypes = [P, u64, f64, f64, f64, u32, u32, P]
         L.orc_set_forbidden.argtypes = [P]
+        L.orc_set_self_term.argtypes = [ctypes.c_double]
         L.orc_h_nb.restype = f64
         L.orc_mc_sweep.argtypes = [P, u32, u32, u32, f32, u32, P, u32, u32, u32, u32,
                                    f32, u64, u32, u32, u32, u32, P, i32]
@@ -230,10 +231,32 @@ class _walls:
         lib().orc_set_forbidden(None)
 
 
+class _self_term:
+    """Sets the energy of cell-changing moves (orc_set_self_term) for one call."""
+
+    def __init__(self, s):
+        self.s = float(s)
+
+    def __enter__(self):
+        lib().orc_set_self_term(self.s)
+
+    def __exit__(self, *exc):
+        lib().orc_set_self_term(0.0)
+
+
+def self_energy(kappa_n, chi_n, inv_rho, n_ref, form=1) -> np.float32:
+    """Second difference of the grid Hamiltonian per bead, kT (FP32 as the
+    device rounds it): kappaN/(N rho) for the K^1 form, (kappaN - chiN/2)/(N rho)
+    for K^0."""
+    k = float(kappa_n) - (0.5 * float(chi_n) if form == 0 else 0.0)
+    return np.float32(k * float(inv_rho) / float(n_ref))
+
+
 def mc_sweep(pos: np.ndarray, sp: Species, omega: np.ndarray, grid, *, k0, n_ref,
              move_kind=MOVE_LOCAL, step, seed, sweep, replica=0, chain_base=0,
-             set_order=0, want_flags=False, threads=1, forbid=None):
+             set_order=0, want_flags=False, threads=1, forbid=None, self_term=0.0):
     """In-place sweep of one species' chains (pos is that species' slice).
+    self_term: energy added to every move that changes cell (0: none).
 
     Returns (n_accepted, flags or None)."""
     assert pos.dtype == np.float32 and pos.flags.c_contiguous
@@ -242,7 +265,7 @@ def mc_sweep(pos: np.ndarray, sp: Species, omega: np.ndarray, grid, *, k0, n_ref
     omega = _c(omega, np.float32)
     assert omega.size == 2 * nx * ny * nz
     flags = np.zeros(sp.n_chains * sp.n, np.uint8) if want_flags else None
-    with _walls(forbid):
+    with _walls(forbid), _self_term(self_term):
         acc = lib().orc_mc_sweep(_ptr(pos), sp.n_chains, sp.n, sp.n_a, float(np.float32(k0)),
                                  n_ref, _ptr(omega), nx, ny, nz, move_kind,
                                  float(np.float32(step)), seed, sweep, replica, chain_base,
@@ -535,7 +558,7 @@ def features(pos, sp: Species, beads, omega, grid):
 def mc_sweep_mixed(pos, sp: Species, omega, grid, *, k0, n_ref, local_a, p_learn, params,
                    m_max, lo, hi, bf16_mode=True, seed, sweep, replica=0, chain_base=0,
                    set_order=0, want_flags=False, threads=1, forbid=None, ambiguous=None,
-                   pos_env=None):
+                   pos_env=None, self_term=0.0):
     """In-place mixed (local / learned) sweep.  Returns (accepted, accepted_learned,
     bad_net, kind_flags, accept_flags).  With `ambiguous` (a uint8 array of
     n_chains * n, BF16 mode only) each move's entry is set to 1 where rounding
@@ -560,6 +583,7 @@ def mc_sweep_mixed(pos, sp: Species, omega, grid, *, k0, n_ref, local_a, p_learn
         pos_env[:] = 0.0
     walls = _opt(forbid, np.uint32)
     lib().orc_set_forbidden(_ptr(walls) if walls is not None else None)
+    lib().orc_set_self_term(float(self_term))
     try:
         acc = L.orc_mc_sweep_mixed(_ptr(pos), sp.n_chains, sp.n, sp.n_a, float(np.float32(k0)), n_ref,
                                    _ptr(omega), *grid, float(np.float32(local_a)),
@@ -573,4 +597,5 @@ def mc_sweep_mixed(pos, sp: Species, omega, grid, *, k0, n_ref, local_a, p_learn
                                    ctypes.byref(acc_l), ctypes.byref(bad), threads)
     finally:
         lib().orc_set_forbidden(None)
+        lib().orc_set_self_term(0.0)
     return acc, acc_l.value, bad.value, kf, af

@@ -423,6 +423,18 @@ static int orc_blocked(const float *r, const float *trial, uint32_t nx, uint32_t
   return to != orc_cell(r, nx, ny, nz) && orc_bit(orc_forbidden, to);
 }
 
+/* Energy added to every move that changes cell (0: the quasi-instantaneous
+ * field alone).  Moving one bead of type t from cell c to c' changes the grid
+ * Hamiltonian of Eqs. (5), (6), (8) (quadratic in the counts) by
+ * (omega_t(c') - omega_t(c))/N plus its second difference in n_t, which the
+ * caller passes here (kappaN/(N rho) for the K^1 form). */
+static double orc_self = 0.0;
+void orc_set_self_term(double s) { orc_self = s; }
+static double orc_self_extra(const float *r, const float *trial, uint32_t nx, uint32_t ny,
+                             uint32_t nz) {
+  return orc_cell(r, nx, ny, nz) != orc_cell(trial, nx, ny, nz) ? orc_self : 0.0;
+}
+
 /* One local attempt on bead i from the four words w of its draw. */
 static int orc_local_attempt(float *chain, uint32_t i, uint32_t n, uint32_t n_a,
                              double k0, const float *omega, uint64_t n_cells,
@@ -437,7 +449,7 @@ static int orc_local_attempt(float *chain, uint32_t i, uint32_t n, uint32_t n_a,
   const float *om = omega + (uint64_t)orc_type(i, n_a) * n_cells;
   double d_field = ((double)om[orc_cell(trial, nx, ny, nz)] -
                     (double)om[orc_cell(r, nx, ny, nz)]) /
-                   (double)n_ref;
+                   (double)n_ref + orc_self_extra(r, trial, nx, ny, nz);
   double d_e = d_bond + d_field;
   double u = (double)orc_u01(w[3]);
   int accept = (d_e <= 0.0) || (u < exp(-d_e));
@@ -488,7 +500,7 @@ static int orc_move_smc(float *chain, uint32_t c_id, uint32_t i, uint32_t n,
                   orc_bond_energy(r, chain, i, n, k0);
   double d_field = ((double)om[orc_cell(trial, nx, ny, nz)] -
                     (double)om[orc_cell(r, nx, ny, nz)]) /
-                   (double)n_ref;
+                   (double)n_ref + orc_self_extra(r, trial, nx, ny, nz);
   double log_ratio = -(d_bond + d_field) + log_rev - log_fwd;
   double u = (double)orc_u01(wb[0]);
   int accept = (log_ratio >= 0.0) || (u < exp(log_ratio));
@@ -540,7 +552,8 @@ static int orc_move_gibbs(float *chain, uint32_t c_id, uint32_t i, uint32_t n,
   const float *om = omega + (uint64_t)orc_type(i, n_a) * n_cells;
   double d_bond = orc_bond_energy(trial, chain, i, n, k0) - orc_bond_energy(r, chain, i, n, k0);
   double d_field = ((double)om[orc_cell(trial, nx, ny, nz)] -
-                    (double)om[orc_cell(r, nx, ny, nz)]) / (double)n_ref;
+                    (double)om[orc_cell(r, nx, ny, nz)]) / (double)n_ref +
+                   orc_self_extra(r, trial, nx, ny, nz);
   double log_ratio = -(d_bond + d_field) + log_rev - log_fwd;
   double u = (double)orc_u01(wb[0]);
   int accept = (log_ratio >= 0.0) || (u < exp(log_ratio));
@@ -1391,7 +1404,8 @@ static double orc_learned_log_ratio(const float *chain, uint32_t i, uint32_t n, 
   const float *om = omega + (uint64_t)orc_type(i, n_a) * n_cells;
   double w_new = om[orc_cell(trial, nx, ny, nz)], w_old = om[orc_cell(r, nx, ny, nz)];
   if (mag) *mag = m + e_new + e_old + (fabs(w_new) + fabs(w_old)) / (double)n_ref;
-  return -((e_new - e_old) + (w_new - w_old) / (double)n_ref) + log_rev - log_fwd;
+  return -((e_new - e_old) + (w_new - w_old) / (double)n_ref +
+           orc_self_extra(r, trial, nx, ny, nz)) + log_rev - log_fwd;
 }
 
 /* Standardised FP32 inputs of the network for raw features f. */
@@ -1546,7 +1560,7 @@ static int orc_local_ambiguous(const float *chain, uint32_t i, uint32_t n, uint3
   double d_bond = orc_bond_energy(trial, chain, i, n, k0) - orc_bond_energy(r, chain, i, n, k0);
   const float *om = omega + (uint64_t)orc_type(i, n_a) * n_cells;
   double w_new = om[orc_cell(trial, nx, ny, nz)], w_old = om[orc_cell(r, nx, ny, nz)];
-  double d_e = d_bond + (w_new - w_old) / (double)n_ref;
+  double d_e = d_bond + (w_new - w_old) / (double)n_ref + orc_self_extra(r, trial, nx, ny, nz);
   mag += (fabs(w_new) + fabs(w_old)) / (double)n_ref;
   double step = 0.0;
   for (int d = 0; d < 3; ++d) step += fabs((double)trial[d] - (double)r[d]);
@@ -1597,7 +1611,8 @@ static int orc_move_learned(float *chain, uint32_t c_id, uint32_t i, uint32_t n,
   double d_bond = orc_bond_energy(trial, chain, i, n, k0) - orc_bond_energy(r, chain, i, n, k0);
   const float *om = omega + (uint64_t)orc_type(i, n_a) * n_cells;
   double d_field = ((double)om[orc_cell(trial, nx, ny, nz)] -
-                    (double)om[orc_cell(r, nx, ny, nz)]) / (double)n_ref;
+                    (double)om[orc_cell(r, nx, ny, nz)]) / (double)n_ref +
+                   orc_self_extra(r, trial, nx, ny, nz);
   double log_ratio = -(d_bond + d_field) + log_rev - log_fwd;
   double u = (double)orc_u01(wb[0]);
   int accept = (log_ratio >= 0.0) || (u < exp(log_ratio));

@@ -374,6 +374,7 @@ struct soma_system {
   uint32_t scheme = SOMA_SCHEME_SET;  // iteration order of local moves
   uint32_t hist_mode = soma::kHistDirect;  // count updates of the SET sweeps (soma_set_histogram)
   uint32_t sweep_threads = 256;  // block size of the local, smart-MC and bond-Gibbs sweeps
+  uint32_t self_term = 0;        // add the bead's own share to cell-changing moves (soma_set_self_term)
   float4 *grad = nullptr;     // optional gradient field (caller-owned), see soma_set_grad_field
   unsigned char *ws = nullptr;
   CycleGraph graph;
@@ -465,6 +466,17 @@ int32_t launch_bin_apply(soma_system *sys, hipStream_t s) {
   return SOMA_OK;
 }
 
+// The second difference of the grid Hamiltonian per bead and cell, in kT:
+// moving one bead from cell c to c' changes H_nb by (omega(c') - omega(c))/N
+// plus this (the bead no longer counts in c and now counts in c').  K^1 form:
+// kappaN / (N rho); K^0 form: (kappaN - chiN/2) / (N rho).
+float self_energy(const soma_system *sys) {
+  const double inv_rho = inv_rho_d(sys->d);
+  const double k = sys->d.form == 0 ? (double)sys->cfg.kappa_n - 0.5 * (double)sys->cfg.chi_n
+                                    : (double)sys->cfg.kappa_n;
+  return (float)(k * inv_rho / (double)sys->cfg.n_ref);
+}
+
 // Arguments of species sp's sweep of kind `kind` (sweep offset 0).
 void sweep_args(soma_system *sys, uint32_t sp, uint32_t kind, soma::SweepArgs &a,
                 soma::MixArgs &mx) {
@@ -504,6 +516,7 @@ void sweep_args(soma_system *sys, uint32_t sp, uint32_t kind, soma::SweepArgs &a
   a.gibbs_s2 = (float)(1.0 / std::sqrt(2.0 * (double)S.k0));
   a.gibbs_s1 = (float)(1.0 / std::sqrt((double)S.k0));
   a.bin = sys->d.bins_ok ? sys->bins() : soma::BinArgs{};
+  a.self_term = sys->self_term ? self_energy(sys) : 0.0f;
   mx.net = sys->net(sp);
   mx.head.m_max = c->mu_max;
   mx.head.lo = c->log_sigma_min;
@@ -603,6 +616,8 @@ int32_t check_kind(soma_system *sys, uint32_t move_kind) {
     return fail(SOMA_E_UNSUPPORTED, "general architectures have local moves in the SET order only");
   if (sys->d.n_types > 2 && move_kind != SOMA_MOVE_LOCAL)
     return fail(SOMA_E_UNSUPPORTED, "more than two bead types: local moves only");
+  if (sys->self_term && (sys->scheme != SOMA_SCHEME_SET || sys->arch_mask || sys->d.n_types > 2))
+    return fail(SOMA_E_UNSUPPORTED, "the self term: linear chains of two types, SET order");
   return SOMA_OK;
 }
 
@@ -816,6 +831,15 @@ int32_t soma_set_histogram(soma_system *sys, uint32_t mode) {
   if (mode == SOMA_HIST_BINNED && !sys->d.bins_ok)
     return fail(SOMA_E_UNSUPPORTED, "binned count updates need fewer than 2^21 bricks of 16x16x8 cells");
   sys->hist_mode = mode == SOMA_HIST_BINNED ? soma::kHistBinned : soma::kHistDirect;
+  return SOMA_OK;
+}
+
+int32_t soma_set_self_term(soma_system *sys, uint32_t on) {
+  if (!sys) return fail(SOMA_E_INVAL, "system is NULL");
+  if (on > 1) return fail(SOMA_E_INVAL, "self term: 0 or 1");
+  if (on && (sys->d.n_types > 2 || sys->arch_mask || sys->scheme != SOMA_SCHEME_SET))
+    return fail(SOMA_E_UNSUPPORTED, "the self term: linear chains of two types, SET order");
+  sys->self_term = on;
   return SOMA_OK;
 }
 

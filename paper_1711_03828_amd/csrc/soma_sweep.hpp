@@ -58,6 +58,9 @@ struct SweepArgs {
   // per-brick bins of count updates (kernels instantiated with BINNED); the
   // counts are current only after bin_apply_kernel has run
   BinArgs bin;
+  // energy added to every move that changes cell (0: the quasi-instantaneous
+  // field alone); see soma_set_self_term
+  float self_term;
 };
 
 // A move from cell `from` to cell `to` that the impenetrable cells allow.
@@ -252,8 +255,10 @@ __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap
   const Rand4 wa = odd_first ? w1 : w0, wb = odd_first ? w0 : w1;
   const bool has_a = odd_first ? m.has1 : m.has0, has_b = odd_first ? m.has0 : m.has1;
   const bool ok_a = odd_first ? ok1 : ok0, ok_b = odd_first ? ok0 : ok1;
-  const float dfa = ((odd_first ? wn1 : wn0) - (odd_first ? wo1 : wo0)) * a.inv_nref;
-  const float dfb = ((odd_first ? wn0 : wn1) - (odd_first ? wo0 : wo1)) * a.inv_nref;
+  const float sa = (odd_first ? n1 != c1 : n0 != c0) ? a.self_term : 0.0f;
+  const float sb = (odd_first ? n0 != c0 : n1 != c1) ? a.self_term : 0.0f;
+  const float dfa = ((odd_first ? wn1 : wn0) - (odd_first ? wo1 : wo0)) * a.inv_nref + sa;
+  const float dfb = ((odd_first ? wn0 : wn1) - (odd_first ? wo0 : wo1)) * a.inv_nref + sb;
   // bonded neighbours of a: own b and b of the adjacent lane (lane k-1 if a is
   // even, lane k+1 if a is odd); of b: own a and a of the other adjacent lane
   const int up = m.lane < 63 ? m.lane + 1 : m.lane, dn = m.lane > 0 ? m.lane - 1 : m.lane;
@@ -476,7 +481,7 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
       }
       const float w_old = odd ? f1 : f0;
       const float w_new = cn == co ? w_old : field_at(a.omega, pl, cn);
-      const float d_e = (w_new - w_old) * a.inv_nref;
+      const float d_e = (w_new - w_old) * a.inv_nref + (cn != co ? a.self_term : 0.0f);
       acc = move_allowed(a, co, cn) && step_allowed(a, r, rn) && (d_e <= 0.0f || u < __expf(-d_e));
     } else if (moving) {
       co = odd ? co1 : co0;
@@ -520,7 +525,8 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
       const float qx = wl * (2.0f * el.x + d.x) + wr * (2.0f * er.x + d.x);
       const float qy = wl * (2.0f * el.y + d.y) + wr * (2.0f * er.y + d.y);
       const float qz = wl * (2.0f * el.z + d.z) + wr * (2.0f * er.z + d.z);
-      const float d_e = a.half_k0 * (d.x * qx + d.y * qy + d.z * qz) + (w_new - w_old) * a.inv_nref;
+      const float d_e = a.half_k0 * (d.x * qx + d.y * qy + d.z * qz) + (w_new - w_old) * a.inv_nref +
+                        (cn != co ? a.self_term : 0.0f);
       const float lr = log_q - d_e;
       acc = ok && (lr >= 0.0f || u < __expf(lr));
     }
@@ -673,7 +679,8 @@ __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx
     }
     const F3 d = rn - r;
     const F3 q = wl * (2.0f * (r - left) + d) + wr * (2.0f * (r - right) + d);
-    const float d_e = a.half_k0 * (d.x * q.x + d.y * q.y + d.z * q.z) + (w_new - w_old) * a.inv_nref;
+    const float d_e = a.half_k0 * (d.x * q.x + d.y * q.y + d.z * q.z) + (w_new - w_old) * a.inv_nref +
+                      (cn != co ? a.self_term : 0.0f);
     bool acc;
     if (learned) {
       const float lr = log_q - d_e;

@@ -116,6 +116,7 @@ _SIGS = {
     "soma_set_histogram": ([_P, _u32], _i32),
     "soma_set_sweep_threads": ([_P, _u32], _i32),
     "soma_probe_atomics": ([_P, _u64, _u64, _u32, _u32, _P], _i32),
+    "soma_set_self_term": ([_P, _u32], _i32),
     "soma_set_scheme": ([_P, _u32], _i32),
     "soma_set_hamiltonian": ([_P, _u32, _P], _i32),
     "soma_set_types": ([_P, _u32, _P, _P, _u64, _P, _u64, _P], _i32),
@@ -221,6 +222,10 @@ def soma_set_histogram(h, mode: int) -> None:
 
 def soma_set_sweep_threads(h, threads: int) -> None:
     _check(_lib.soma_set_sweep_threads(h, threads))
+
+
+def soma_set_self_term(h, on: int) -> None:
+    _check(_lib.soma_set_self_term(h, on))
 
 
 def soma_probe_atomics(words_ptr: int, n_words: int, n_updates: int, mode: int, seed: int,

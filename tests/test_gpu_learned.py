@@ -162,8 +162,8 @@ def test_collect_training(orc):
         C.soma_collect_training(m.handle, n, rnd, 0, 0, r0.data_ptr(), 0, 0, _stream(), species=2)
 
 
-@pytest.mark.parametrize("p_learn", [1.0, 0.5])
-def test_mixed_sweep_parity(orc, p_learn):
+@pytest.mark.parametrize("p_learn,self_term", [(1.0, False), (0.5, False), (1.0, True)])
+def test_mixed_sweep_parity(orc, p_learn, self_term):
     """One mixed sweep on the device against the oracle's BF16-emulating sweep
     from the same positions and fields, move by move: the device accepted a
     move iff the bead moved; decisions must agree, and accepted positions agree
@@ -184,6 +184,11 @@ def test_mixed_sweep_parity(orc, p_learn):
                                                        np.float32(w.chi_n), np.float32(w.kappa_n)))
     params = proposal_test_params(orc, pos, sp, omega, w.grid, seed=12)
     m.set_proposal(torch.from_numpy(params).cuda())
+    s_term = 0.0
+    if self_term:   # the bead's own share of a cell-changing move on both sides
+        C.soma_set_self_term(m.handle, 1)
+        s_term = orc.self_energy(np.float32(w.kappa_n), np.float32(w.chi_n),
+                                 w.n_cells / w.n_beads, w.n_ref)
     m.sweep(1, C.SOMA_MOVE_MIXED)
     obs = m.observables()
     ref = pos.copy()
@@ -192,7 +197,7 @@ def test_mixed_sweep_parity(orc, p_learn):
     acc, acc_l, bad, kinds, acc_flags = orc.mc_sweep_mixed(
         ref, sp, omega, w.grid, k0=k0, n_ref=w.n_ref, local_a=a, p_learn=p_learn, params=params,
         **HEAD, bf16_mode=True, seed=w.seed, sweep=0, want_flags=True, threads=8, ambiguous=amb,
-        pos_env=env)
+        pos_env=env, self_term=s_term)
     got = m.pos.cpu().numpy()
     n_bad, unexplained, flagged, dec = explain_mismatches(got, pos, ref, acc_flags, amb, env, 32)
     allowed = math.ceil(1e-6 * pos.shape[0])
