@@ -446,7 +446,9 @@ typedef struct soma_tune {
  * (SOMA_HIST_DIRECT, and SOMA_HIST_BINNED where the grid allows it) x the
  * block size of the local, smart-MC and bond-Gibbs sweeps (128, 256, 512
  * threads; the mixed sweep always runs 256) x, for local moves, the grid (one
- * block per tile group, or 2048 persistent blocks): up to 12 candidates.
+ * block per tile group, or the persistent grid of as many blocks as the
+ * device holds at once at that block size, from the runtime's occupancy
+ * query; 2048 if it gives none): up to 12 candidates.
  * Molecule order: the grid caps {none, 256, 512, 1024, 2048}.  Batches: the
  * item order (XCD ranges or round-robin) x the grid {one block per item, 2048,
  * 8192}. */

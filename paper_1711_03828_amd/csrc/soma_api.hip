@@ -441,6 +441,30 @@ void launch_sweep_t(uint32_t kind, dim3 grid, dim3 threads, hipStream_t s,
     hipLaunchKernelGGL((soma::mc_sweep_local_kernel<C64, V2, B>), grid, threads, 0, s, a);
 }
 
+// Blocks of the local-move kernel that the whole device holds at once at
+// `threads` per block (occupancy of the kernel's registers and LDS times the
+// compute units): the persistent grid whose waves all start together.  0 if
+// the runtime cannot tell.
+template <bool C64, bool B>
+uint32_t resident_local_blocks_t(uint32_t threads) {
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0u;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0u;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void *>(&soma::mc_sweep_local_kernel<C64, true, B>),
+          (int)threads, 0) != hipSuccess)
+    return 0u;
+  return per_cu > 0 && cus > 0 ? (uint32_t)per_cu * (uint32_t)cus : 0u;
+}
+
+uint32_t resident_local_blocks(bool c64, bool binned, uint32_t threads) {
+  if (c64) return binned ? resident_local_blocks_t<true, true>(threads)
+                         : resident_local_blocks_t<true, false>(threads);
+  return binned ? resident_local_blocks_t<false, true>(threads)
+                : resident_local_blocks_t<false, false>(threads);
+}
+
 template <bool C64, bool V2>
 void launch_sweep_b(bool binned, uint32_t kind, dim3 grid, dim3 threads, hipStream_t s,
                     const soma::SweepArgs &a, const soma::MixArgs &mx) {
@@ -2087,8 +2111,10 @@ int32_t soma_autotune(soma_system *sys, uint32_t cycles, uint32_t move_kind,
   if (rc) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   // SET order: mode = histogram mode (bit 0) | block size / 64 - 1 (bits 1..3);
-  // the grid (persistent blocks) for local moves only.  Molecule order: grid
-  // caps small enough to keep its chains in L2.
+  // the grid for local moves only: one tile per wave (0), or the persistent
+  // grid of exactly the blocks the device holds at once, whose waves loop
+  // over the tiles and load the next tile's positions during the current one.
+  // Molecule order: grid caps small enough to keep its chains in L2.
   std::vector<Shape> shapes;
   const bool mol = sys->scheme == SOMA_SCHEME_MOLECULE;
   if (mol) {
@@ -2099,8 +2125,13 @@ int32_t soma_autotune(soma_system *sys, uint32_t cycles, uint32_t move_kind,
     for (uint32_t h = 0; h < n_hist; ++h)
       for (uint32_t t : {256u, 128u, 512u}) {
         if (fixed_block && t != 256u) continue;
-        for (uint32_t g : {0u, 2048u}) {
-          if (g && move_kind != SOMA_MOVE_LOCAL) continue;
+        for (uint32_t resident : {0u, 1u}) {
+          if (resident && move_kind != SOMA_MOVE_LOCAL) continue;
+          uint32_t g = 0u;
+          if (resident) {
+            g = resident_local_blocks(sys->cfg.count_width == 32, h != 0u, t);
+            if (g == 0u) g = 2048u;
+          }
           shapes.push_back({h | ((t / 64u - 1u) << 1), g});
         }
       }

@@ -3,12 +3,12 @@
 // per update.
 //
 // The grid is cut into bricks of 16 x 16 x 8 cells.  A wave that moves beads
-// to other cells groups its +-1 updates by brick, reserves room in each
-// brick's bin with one atomic per (wave, brick) and writes the updates there
-// with plain stores; a bin that is full takes the rest as direct atomics on
-// the counts.  Afterwards `bin_apply_kernel` gives every brick one workgroup:
-// the brick's count words go to LDS, the bin's updates are added with LDS
-// atomics, and the words go back.  Integer additions are exact and
+// to other cells counts its +-1 updates per brick in a small LDS table,
+// reserves room in each brick's bin with one atomic per (wave, brick) and
+// writes the updates there with plain stores; a bin that is full takes the
+// rest as direct atomics on the counts.  Afterwards `bin_apply_kernel` gives
+// every brick one workgroup: the brick's count words go to LDS, the bin's
+// updates are added with LDS atomics, and the words go back.  Integer additions are exact and
 // order-independent, so the counts are bit-identical to direct atomics (and
 // to a recount of the final positions).
 //
@@ -111,91 +111,81 @@ __device__ __forceinline__ void apply_entry_direct(const BinArgs &b, const Grid 
   }
 }
 
-// One group of bin_append: the brick of the first lane with a pending slot.
-// Marks the lane's slots in that brick with the group index j and their rank
-// (go_s = j | rank << 3), clears them from `want`, and has the first lane
-// reserve the group's room (*gb, read only after all groups are issued).
-__device__ __forceinline__ void bin_group(uint32_t *bin_count, uint32_t sub, uint32_t j, uint32_t k0,
-                                          uint32_t k1, uint32_t k2, uint32_t k3, uint32_t &want,
-                                          uint32_t &go0, uint32_t &go1, uint32_t &go2,
-                                          uint32_t &go3, uint32_t &gk, uint32_t &gb,
-                                          uint32_t &gl) {
-  const uint64_t any = __ballot(want != 0u);
-  if (any == 0ull) return;
-  const uint32_t lane = __lane_id();
-  const uint64_t below = (1ull << lane) - 1ull;
-  const uint32_t leader = (uint32_t)__ffsll((long long)any) - 1u;
-  const uint32_t first = (want & 1u) ? k0 : (want & 2u) ? k1 : (want & 4u) ? k2 : k3;
-  const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)first, (int)leader);
-  const bool m0 = (want & 1u) && k0 == k, m1 = (want & 2u) && k1 == k;
-  const bool m2 = (want & 4u) && k2 == k, m3 = (want & 8u) && k3 == k;
-  const uint64_t b0 = __ballot(m0), b1 = __ballot(m1), b2 = __ballot(m2), b3 = __ballot(m3);
-  const uint32_t c0 = (uint32_t)__popcll(b0), c1 = (uint32_t)__popcll(b1);
-  const uint32_t c2 = (uint32_t)__popcll(b2), c3 = (uint32_t)__popcll(b3);
-  if (m0) go0 = j | ((uint32_t)__popcll(b0 & below) << 3);
-  if (m1) go1 = j | ((c0 + (uint32_t)__popcll(b1 & below)) << 3);
-  if (m2) go2 = j | ((c0 + c1 + (uint32_t)__popcll(b2 & below)) << 3);
-  if (m3) go3 = j | ((c0 + c1 + c2 + (uint32_t)__popcll(b3 & below)) << 3);
-  want &= ~((m0 ? 1u : 0u) | (m1 ? 2u : 0u) | (m2 ? 4u : 0u) | (m3 ? 8u : 0u));
-  if (lane == leader) gb = atomicAdd(bin_count + ((k << kSubShift) | sub), c0 + c1 + c2 + c3);
-  gk = k;
-  gl = leader;
+// Per-wave table of the bricks a wave's updates fall in: kTabSlots slots of
+// {brick, count} in LDS, open addressing with linear probing.  Built for one
+// bin_append call and discarded after it.
+constexpr uint32_t kTabSlots = 32u;
+constexpr uint32_t kTabEmpty = 0xFFFFFFFFu;   // no brick (brick indices are below 2^21)
+constexpr uint32_t kNoSlot = 0xFFu;
+constexpr uint32_t kMaxWaves = 8u;            // waves per block that may call bin_append
+
+__device__ __forceinline__ uint32_t tab_hash(uint32_t brick) {
+  return (__umul24(brick, 0x9E3779u) >> 11) & (kTabSlots - 1u);
 }
 
-// Stores entry v of a slot marked go (group j = go & 7 of `only`, or of any
-// of the four groups if only > 3) at its reserved place, or applies it
-// directly if the bin is full.
+// Slot of `brick` in the wave's table (claimed if new) << 16 | the entry's
+// rank among the wave's entries for that brick; kNoSlot << 16 if the table is
+// full.
+__device__ __forceinline__ uint32_t tab_insert(uint2 *tab, uint32_t brick) {
+  uint32_t h = tab_hash(brick);
+  uint32_t probe = 0;
+#pragma unroll 1
+  for (; probe < kTabSlots; ++probe) {
+    const uint32_t old = atomicCAS(&tab[h].x, kTabEmpty, brick);
+    if (old == kTabEmpty || old == brick) break;
+    h = (h + 1u) & (kTabSlots - 1u);
+  }
+  if (probe == kTabSlots) return kNoSlot << 16;
+  return (h << 16) | atomicAdd(&tab[h].y, 1u);
+}
+
+// Stores entry v (brick k, table slot and rank q) at its reserved place, or
+// applies it directly if its sub-bin is full or the wave's table was.
 template <bool COUNT64>
-__device__ __forceinline__ void bin_put(const BinArgs &b, const Grid &g, void *counts,
-                                        uint32_t sub, uint32_t go, uint32_t v, uint32_t gk0, uint32_t gk1,
-                                        uint32_t gk2, uint32_t gk3, uint32_t base0, uint32_t base1,
-                                        uint32_t base2, uint32_t base3) {
-  const uint32_t j = go & 7u;
-  if (j > 3u) return;
-  const uint32_t bk = j == 0u ? gk0 : j == 1u ? gk1 : j == 2u ? gk2 : gk3;
-  const uint32_t pos = (j == 0u ? base0 : j == 1u ? base1 : j == 2u ? base2 : base3) + (go >> 3);
-  if (pos < b.cap) b.bins[(size_t)((bk << kSubShift) | sub) * b.cap + pos] = v;
-  else apply_entry_direct<COUNT64>(b, g, counts, bk, v);
+__device__ __forceinline__ void tab_put(const BinArgs &b, const Grid &g, void *counts,
+                                        const uint2 *tab, uint32_t sub, uint32_t k, uint32_t q,
+                                        uint32_t v) {
+  const uint32_t h = q >> 16;
+  const uint32_t pos = h != kNoSlot ? tab[h].y + (q & 0xFFFFu) : 0xFFFFFFFFu;
+  if (pos < b.cap) b.bins[(size_t)((k << kSubShift) | sub) * b.cap + pos] = v;
+  else apply_entry_direct<COUNT64>(b, g, counts, k, v);
 }
 
 // Appends the entries of a wave to their bricks' bins.  Each lane offers up
 // to four entries (slot s: brick ks, value vs, wanted if bit s of `want`).
-// All lanes of the wave must call this together.  Entries are grouped by
-// brick; the first four groups reserve their room with atomics issued back
-// to back (one wait for all), further groups one at a time.
+// All lanes of the wave must call this together (wave-uniform control flow).
+// The entries are counted per brick in the wave's LDS table (the rank of an
+// entry is its place among the wave's entries for its brick), one lane per
+// brick reserves that many places in the brick's sub-bin with one atomic, and
+// every entry is stored at reserved base + rank.  LDS operations of one wave
+// execute in issue order, so the table needs no barrier between the steps.
 template <bool COUNT64>
 __device__ __forceinline__ void bin_append(const BinArgs &b, const Grid &g, void *counts,
                                            uint32_t k0, uint32_t k1, uint32_t k2, uint32_t k3,
                                            uint32_t v0, uint32_t v1, uint32_t v2, uint32_t v3,
                                            uint32_t want) {
+  __shared__ uint2 s_tab[kMaxWaves * kTabSlots];
   const uint32_t sub = wave_sub_bin();
-  uint32_t go0 = 7u, go1 = 7u, go2 = 7u, go3 = 7u;
-  uint32_t gk0 = 0u, gk1 = 0u, gk2 = 0u, gk3 = 0u;
-  uint32_t gb0 = 0u, gb1 = 0u, gb2 = 0u, gb3 = 0u;
-  uint32_t gl0 = 0u, gl1 = 0u, gl2 = 0u, gl3 = 0u;
-  bin_group(b.bin_count, sub, 0u, k0, k1, k2, k3, want, go0, go1, go2, go3, gk0, gb0, gl0);
-  bin_group(b.bin_count, sub, 1u, k0, k1, k2, k3, want, go0, go1, go2, go3, gk1, gb1, gl1);
-  bin_group(b.bin_count, sub, 2u, k0, k1, k2, k3, want, go0, go1, go2, go3, gk2, gb2, gl2);
-  bin_group(b.bin_count, sub, 3u, k0, k1, k2, k3, want, go0, go1, go2, go3, gk3, gb3, gl3);
-  const uint32_t base0 = (uint32_t)__builtin_amdgcn_readlane((int)gb0, (int)gl0);
-  const uint32_t base1 = (uint32_t)__builtin_amdgcn_readlane((int)gb1, (int)gl1);
-  const uint32_t base2 = (uint32_t)__builtin_amdgcn_readlane((int)gb2, (int)gl2);
-  const uint32_t base3 = (uint32_t)__builtin_amdgcn_readlane((int)gb3, (int)gl3);
-  bin_put<COUNT64>(b, g, counts, sub, go0, v0, gk0, gk1, gk2, gk3, base0, base1, base2, base3);
-  bin_put<COUNT64>(b, g, counts, sub, go1, v1, gk0, gk1, gk2, gk3, base0, base1, base2, base3);
-  bin_put<COUNT64>(b, g, counts, sub, go2, v2, gk0, gk1, gk2, gk3, base0, base1, base2, base3);
-  bin_put<COUNT64>(b, g, counts, sub, go3, v3, gk0, gk1, gk2, gk3, base0, base1, base2, base3);
-  // rare: more than four bricks in one wave, one group at a time
-  while (__ballot(want != 0u) != 0ull) {
-    uint32_t gk = 0u, gb = 0u, gl = 0u;
-    go0 = go1 = go2 = go3 = 7u;
-    bin_group(b.bin_count, sub, 0u, k0, k1, k2, k3, want, go0, go1, go2, go3, gk, gb, gl);
-    const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)gb, (int)gl);
-    bin_put<COUNT64>(b, g, counts, sub, go0, v0, gk, gk, gk, gk, base, base, base, base);
-    bin_put<COUNT64>(b, g, counts, sub, go1, v1, gk, gk, gk, gk, base, base, base, base);
-    bin_put<COUNT64>(b, g, counts, sub, go2, v2, gk, gk, gk, gk, base, base, base, base);
-    bin_put<COUNT64>(b, g, counts, sub, go3, v3, gk, gk, gk, gk, base, base, base, base);
+  const uint32_t lane = __lane_id();
+  uint2 *tab = s_tab + (threadIdx.x >> 6) * kTabSlots;
+  if (lane < kTabSlots) tab[lane] = make_uint2(kTabEmpty, 0u);
+  __builtin_amdgcn_wave_barrier();
+  uint32_t q0 = 0u, q1 = 0u, q2 = 0u, q3 = 0u;   // slot << 16 | rank
+  if (want & 1u) q0 = tab_insert(tab, k0);
+  if (want & 2u) q1 = tab_insert(tab, k1);
+  if (want & 4u) q2 = tab_insert(tab, k2);
+  if (want & 8u) q3 = tab_insert(tab, k3);
+  __builtin_amdgcn_wave_barrier();
+  if (lane < kTabSlots) {   // one reservation per brick; the slot keeps its base
+    const uint2 e = tab[lane];
+    if (e.x != kTabEmpty) tab[lane].y = atomicAdd(b.bin_count + ((e.x << kSubShift) | sub), e.y);
   }
+  __builtin_amdgcn_wave_barrier();
+  if (want & 1u) tab_put<COUNT64>(b, g, counts, tab, sub, k0, q0, v0);
+  if (want & 2u) tab_put<COUNT64>(b, g, counts, tab, sub, k1, q1, v1);
+  if (want & 4u) tab_put<COUNT64>(b, g, counts, tab, sub, k2, q2, v2);
+  if (want & 8u) tab_put<COUNT64>(b, g, counts, tab, sub, k3, q3, v3);
+  __builtin_amdgcn_wave_barrier();
 }
 
 // The count updates of a lane's two beads (bead e moved from the cell with

@@ -244,6 +244,11 @@ __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap
                  sz1 = shift_cell(z1, r1.z, t1.z, a.grid.nz);
   const uint32_t n0 = cell_index(a.grid, sx0, sy0, sz0);
   const uint32_t n1 = cell_index(a.grid, sx1, sy1, sz1);
+  // brick keys of the four cells now, so that the coordinates die here
+  const uint32_t kf0 = BINNED ? brick_key(a.bin, x0, y0, z0) : 0u;
+  const uint32_t kt0 = BINNED ? brick_key(a.bin, sx0, sy0, sz0) : 0u;
+  const uint32_t kf1 = BINNED ? brick_key(a.bin, x1, y1, z1) : 0u;
+  const uint32_t kt1 = BINNED ? brick_key(a.bin, sx1, sy1, sz1) : 0u;
   float wn0 = wo0, wn1 = wo1;
   if (n0 != c0) wn0 = field_at(a.omega, pl0, n0);
   if (n1 != c1) wn1 = field_at(a.omega, pl1, n1);
@@ -293,10 +298,8 @@ __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap
   store_pair<VEC2>(cp, m, sel(odd_first, rb, ra), sel(odd_first, ra, rb));
   const bool acc0 = odd_first ? acc_b : acc_a, acc1 = odd_first ? acc_a : acc_b;
   if (BINNED) {
-    bin_moves<COUNT64>(a.bin, a.grid, a.counts, brick_key(a.bin, x0, y0, z0),
-                       brick_key(a.bin, sx0, sy0, sz0), b0 ? 1u : 0u, acc0 && n0 != c0,
-                       brick_key(a.bin, x1, y1, z1), brick_key(a.bin, sx1, sy1, sz1),
-                       b1 ? 1u : 0u, acc1 && n1 != c1);
+    bin_moves<COUNT64>(a.bin, a.grid, a.counts, kf0, kt0, b0 ? 1u : 0u, acc0 && n0 != c0,
+                       kf1, kt1, b1 ? 1u : 0u, acc1 && n1 != c1);
   } else {
     if (acc0 && n0 != c0) move_count<COUNT64>(a.counts, c0, n0, b0);
     if (acc1 && n1 != c1) move_count<COUNT64>(a.counts, c1, n1, b1);
@@ -321,8 +324,12 @@ __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap
 // With fewer waves than tiles each wave loops, loading the next tile's
 // positions while it works on the current one.
 // ---------------------------------------------------------------------------
+// Registers capped for five waves per SIMD (96 VGPRs, no spills), so that the
+// persistent grid holds enough waves to cover the latency of its gathers and
+// of the bin reservations.
 template <bool COUNT64, bool VEC2, bool BINNED>
-__global__ __launch_bounds__(512) void mc_sweep_local_kernel(const SweepArgs a_in) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5)))
+void mc_sweep_local_kernel(const SweepArgs a_in) {
   const SweepArgs a = resolve_sweep(a_in, 0u);
   const uint32_t n_tiles = (a.n_sub + a.chains_per_wave - 1u) / a.chains_per_wave;
   const uint32_t blocks = gridDim.x;
