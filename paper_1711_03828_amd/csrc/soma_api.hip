@@ -77,6 +77,7 @@ struct Derived {
   uint32_t nbx = 0, nby = 0, nbz = 0, bin_cap = 0;
   uint64_t n_bricks = 0, off_bin_count = 0, off_bins = 0;
   bool bins_ok = false;
+  uint64_t off_queue = 0;   // tile counters of persistent local sweeps
 };
 
 int32_t derive(const soma_config *c, Derived *d) {
@@ -144,7 +145,8 @@ int32_t derive(const soma_config *c, Derived *d) {
   d->halo_plane = c->p_learn > 0.f ? (uint64_t)c->nz * c->ny * (c->nx + 2u) : 0u;
   if (8ull * d->halo_plane >= (1ull << 32))
     return fail(SOMA_E_UNSUPPORTED, "grid too large for the learned proposal's field copy");
-  d->ws_bytes = align_up(d->off_halo + 8ull * d->halo_plane);
+  d->off_queue = align_up(d->off_halo + 8ull * d->halo_plane);
+  d->ws_bytes = align_up(d->off_queue + 4ull * soma::kQueueParts * soma::kQueueSub * soma::kQueueStride);
   // bins: room for the updates of about half the beads of a brick per sweep
   // (entries beyond it go to the counts as direct atomics)
   d->nbx = (c->nx + 15u) / 16u;
@@ -541,6 +543,7 @@ void sweep_args(soma_system *sys, uint32_t sp, uint32_t kind, soma::SweepArgs &a
   a.gibbs_s1 = (float)(1.0 / std::sqrt((double)S.k0));
   a.bin = sys->d.bins_ok ? sys->bins() : soma::BinArgs{};
   a.self_term = sys->self_term ? self_energy(sys) : 0.0f;
+  a.queue = nullptr;   // set by launch_sweep for persistent local grids
   mx.net = sys->net(sp);
   mx.head.m_max = c->mu_max;
   mx.head.lo = c->log_sigma_min;
@@ -600,8 +603,12 @@ int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s, uint32_t of
     const uint32_t threads = kind == SOMA_MOVE_MIXED ? 256u : sys->sweep_threads;
     const uint64_t chains_per_block = (uint64_t)(threads / 64u) * a.chains_per_wave;
     uint64_t blocks = (a.n_sub + chains_per_block - 1) / chains_per_block;
-    if (kind == SOMA_MOVE_LOCAL && sys->sweep_blocks && sys->sweep_blocks < blocks)
-      blocks = sys->sweep_blocks;
+    if (kind == SOMA_MOVE_LOCAL && sys->sweep_blocks && sys->sweep_blocks < blocks) {
+      blocks = sys->sweep_blocks;   // persistent: tiles from counters zeroed here
+      a.queue = reinterpret_cast<uint32_t *>(sys->ws + sys->d.off_queue);
+      hipLaunchKernelGGL(soma::queue_reset_kernel, dim3(1), dim3(256), 0, s, a.queue);
+      LAUNCH_TRY();
+    }
     const bool v2 = species_vec2(sys, sp);
     const dim3 grid((uint32_t)blocks), block(threads);
     if (c64) {

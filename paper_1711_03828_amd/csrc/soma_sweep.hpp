@@ -61,7 +61,19 @@ struct SweepArgs {
   // energy added to every move that changes cell (0: the quasi-instantaneous
   // field alone); see soma_set_self_term
   float self_term;
+  // persistent local sweeps: kQueueParts x kQueueSub tile counters, kQueueStride
+  // words apart, zeroed before the launch (null: the static tile order)
+  uint32_t *queue;
 };
+
+constexpr uint32_t kQueueParts = 8u, kQueueSub = 16u, kQueueStride = 32u;
+
+// Zeroes the tile counters of a persistent local sweep (a kernel, not a
+// memset, so that it can sit in a captured graph).
+__global__ __launch_bounds__(256) void queue_reset_kernel(uint32_t *q) {
+  for (uint32_t i = threadIdx.x; i < kQueueParts * kQueueSub; i += blockDim.x)
+    q[i * kQueueStride] = 0u;
+}
 
 // A move from cell `from` to cell `to` that the impenetrable cells allow.
 __device__ __forceinline__ bool move_allowed(const SweepArgs &a, uint32_t from, uint32_t to) {
@@ -343,6 +355,34 @@ void mc_sweep_local_kernel(const SweepArgs a_in) {
   const uint32_t t_end = (uint32_t)(((uint64_t)n_tiles * (part + 1u)) / parts);
 
   uint32_t n_acc = 0;
+  if (a.queue) {
+    // Persistent grid: each part hands out its tiles through S = min(kQueueSub,
+    // waves of the part) counters; a wave draws from counter (wave mod S),
+    // which owns the tiles sub + S j of the part (every counter has a wave), so
+    // that the part's waves stay on one moving window of tiles however their
+    // speeds differ.  (With a fixed stride per wave, waves drift apart over
+    // their ~200 tiles and the window they cover outgrows L2: half again as
+    // many HBM reads.)  The next tile is drawn while the current one runs.
+    const uint32_t n_sq = waves_per_part < kQueueSub ? waves_per_part : kQueueSub;
+    const uint32_t sq = wave_in_part % n_sq;
+    uint32_t *q = a.queue + (part * kQueueSub + sq) * kQueueStride;
+    const bool lead = (threadIdx.x & 63u) == 0u;
+    uint32_t v = 0u;
+    if (lead) v = atomicAdd(q, 1u);
+    uint32_t t = t_begin + sq + n_sq * (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+    while (t < t_end) {
+      uint32_t vn = 0u;
+      if (lead) vn = atomicAdd(q, 1u);
+      const LaneMap m = lane_map_tile(a, t, true);
+      float *cp = a.pos + (size_t)(m.has0 ? m.chain : 0u) * a.n * 3u + 6u * m.k;
+      F3 r0, r1;
+      load_pair<VEC2>(cp, m, r0, r1);
+      n_acc += local_tile<COUNT64, VEC2, BINNED>(a, m, cp, r0, r1);
+      t = t_begin + sq + n_sq * (uint32_t)__builtin_amdgcn_readfirstlane((int)vn);
+    }
+    finish_block(a, n_acc);
+    return;
+  }
   uint32_t t = t_begin + wave_in_part;
   LaneMap m = lane_map_tile(a, t < t_end ? t : 0u, t < t_end);
   float *cp = a.pos + (size_t)(m.has0 ? m.chain : 0u) * a.n * 3u + 6u * m.k;

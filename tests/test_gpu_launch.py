@@ -50,6 +50,35 @@ def test_block_sizes_equal_default(threads):
     got.close()
 
 
+@pytest.mark.parametrize("hist", [0, 1])
+@pytest.mark.parametrize("blocks", [5, 8, 24])
+def test_persistent_grids_equal_default(hist, blocks):
+    """Persistent local sweeps (fewer blocks than tile groups) draw their tiles
+    from per-part counters; any grid gives the default trajectory bit for bit
+    (5 blocks: one part; 8 and 24: eight parts)."""
+    from paper_1711_03828_amd import soma as C
+    from paper_1711_03828_amd.melt import Melt
+    cfg, pos = _setup()
+    ref = Melt(cfg, positions=torch.from_numpy(pos))
+    got = Melt(cfg, positions=torch.from_numpy(pos))
+    for m in (ref, got):
+        m.set_histogram(C.SOMA_HIST_BINNED if hist else C.SOMA_HIST_DIRECT)
+    C.soma_set_sweep_threads(got.handle, 128)
+    C.soma_set_sweep_blocks(got.handle, blocks)
+    for m in (ref, got):
+        m.cycle(4, C.SOMA_MOVE_LOCAL)
+    got.capture_cycle(3, C.SOMA_MOVE_LOCAL)     # the counters' reset is a graph node too
+    got.run_cycle(2)
+    ref.cycle(6, C.SOMA_MOVE_LOCAL)
+    torch.cuda.synchronize()
+    assert torch.equal(ref.pos, got.pos)
+    assert torch.equal(ref.counts, got.counts)
+    assert torch.equal(ref.omega, got.omega)
+    assert list(ref.observables().accepted) == list(got.observables().accepted)
+    ref.close()
+    got.close()
+
+
 def test_sweep_threads_refused():
     from paper_1711_03828_amd import soma as C
     from paper_1711_03828_amd.melt import Melt
