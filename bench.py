@@ -340,16 +340,17 @@ def _c4_subsystem(side: int):
 # Per sampler, in the order run: (move kind, chain subsets per cycle, cycles
 # per frame, frames discarded, frames measured).  Run lengths aim at >= 3
 # tau_int discarded and >= 50 tau_int measured for the tau_int these replicas
-# show with the self term (about 560 cycles learned with 8 refreshes, 21,000
-# plain, 400 bond-Gibbs); the JSON states the ratio actually reached.  The learned
-# sampler runs first, from the common start it made; the plain run follows
-# from the learned one's end state, the bond-Gibbs run from the plain one's.
+# show with the self term (about 1,100 cycles learned with 8 refreshes, 21,000
+# to 40,000 plain depending on the start, 480 bond-Gibbs); the JSON states the
+# ratio actually reached.  The learned sampler runs first, from the common
+# start it made; the plain run follows from the learned one's end state, the
+# bond-Gibbs run from the plain one's.
 def _replica_plan(C, substeps: int, scale: float):
     def n(x):
         return max(20, int(round(x * scale)))
-    return {"learned": (C.SOMA_MOVE_MIXED, substeps, 20, n(100), n(1600)),
-            "plain": (C.SOMA_MOVE_LOCAL, 1, 400, n(160), n(2650)),
-            "gibbs": (C.SOMA_MOVE_GIBBS, substeps, 10, n(150), n(2100))}
+    return {"learned": (C.SOMA_MOVE_MIXED, substeps, 20, n(170), n(2800)),
+            "plain": (C.SOMA_MOVE_LOCAL, 1, 400, n(300), n(5000)),
+            "gibbs": (C.SOMA_MOVE_GIBBS, substeps, 10, n(150), n(2500))}
 
 
 def replica_statistics(params, substeps: int, p_learn: float, rates: dict, n_rep: int,
