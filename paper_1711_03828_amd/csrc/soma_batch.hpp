@@ -37,7 +37,8 @@ struct BatchLaunch {
 template <bool COUNT64, bool VEC2, uint32_t KIND>
 __global__ __launch_bounds__(256, 2) void batched_sweep_kernel(const BatchLaunch L) {
   __shared__ __bf16 s_act[KIND == 2 ? 4 : 1][KIND == 2 ? 64 * kActStride : 1];
-  __shared__ __bf16 s_tmp[KIND == 2 ? 4 : 1][KIND == 2 ? 64 * kActStride : 1];
+  __shared__ __bf16 s_w[KIND == 2 ? kWRows * kWStride : 1];
+  uint32_t net_sg = 0xFFFFFFFFu;   // segment whose weights s_w holds (mixed sweeps)
   uint32_t item, end, stride;
   if (L.mode == 0) {   // grid is a multiple of 8 blocks (host-checked)
     const uint32_t x = blockIdx.x & 7u;
@@ -68,9 +69,14 @@ __global__ __launch_bounds__(256, 2) void batched_sweep_kernel(const BatchLaunch
       finish_block(a, smc_wave<COUNT64, VEC2, false, true>(a, m));
     } else {
       const MixArgs mx = L.segs[sg].mx;
+      if (sg != net_sg) {   // block-uniform: a new segment's network
+        __syncthreads();
+        net_weights_to_lds(mx.net, s_w);
+        __syncthreads();
+        net_sg = sg;
+      }
       uint32_t cnt[3];
-      mixed_wave<COUNT64, VEC2, false>(a, mx, m, s_act[KIND == 2 ? m.wib : 0],
-                                       s_tmp[KIND == 2 ? m.wib : 0], cnt);
+      mixed_wave<COUNT64, VEC2, false>(a, mx, m, s_act[KIND == 2 ? m.wib : 0], s_w, cnt);
       mixed_finish(a, mx, cnt);
     }
   }

@@ -10,8 +10,11 @@
 // One wavefront evaluates the network for 64 samples (its 64 lanes) with
 // v_mfma_f32_16x16x32_bf16: activations are the B operand (K = units, N =
 // samples), weights the A operand (M = output units); BF16 inputs, FP32
-// accumulation.  Activations pass between layers through a per-wave LDS
-// tile [64 samples][72] bf16 in natural unit order.
+// accumulation.  The input features come from a per-wave LDS tile
+// [64 samples][72] bf16 in natural unit order; the hidden activations stay
+// in registers: an output tile of one layer becomes the next layer's B
+// operand through the gfx950 lane swaps (v_permlane32_swap,
+// v_permlane16_swap), without a trip through LDS.
 #pragma once
 
 #include "soma_device.hpp"
@@ -93,20 +96,62 @@ __device__ __forceinline__ bf16x8 lds_b8(const __bf16 *p) {
   return *reinterpret_cast<const bf16x8 *>(p);
 }
 
+// LDS copy of the weights a block's waves read for every network pass:
+// rows 0..63 W1' (folded), 64..127 W2, 128..143 W3 (rows >= 6 zero), kWStride
+// bf16 per row (64 + 8 padding: the 16 rows one MFMA A operand reads land in
+// different banks).
+constexpr int kWStride = 72, kWRows = 144;
+
+// Copies the network's weights to `sw` (all threads of the block; the caller
+// synchronises before the first read).
+__device__ __forceinline__ void net_weights_to_lds(const NetDev *__restrict__ net, __bf16 *sw) {
+  for (uint32_t i = threadIdx.x; i < (uint32_t)kWRows * 8u; i += blockDim.x) {
+    const uint32_t r = i >> 3, c = i & 7u;
+    const __bf16 *src = r < 64u ? net->w1f + r * 64u : (r < 128u ? net->w2 + (r - 64u) * 64u
+                                                                 : net->w3 + (r - 128u) * 64u);
+    *reinterpret_cast<uint4 *>(sw + r * kWStride + 8u * c) =
+        *reinterpret_cast<const uint4 *>(src + 8u * c);
+  }
+}
+
+// B-operand fragments of a layer's input for the wave's 64 samples: [kb][t]
+// holds units 32 kb + 8 g .. + 7 of sample 16 t + col (lane = 16 g + col).
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+struct Frag {
+  bf16x8 b[2][4];
+};
+
+// The input features of the wave's samples from LDS tile `act` (row = sample).
+__device__ __forceinline__ void frag_from_lds(const __bf16 *act, Frag &f) {
+  const int lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      f.b[kb][t] = lds_b8(act + (16 * t + col) * kActStride + 32 * kb + 8 * g);
+}
+
 // One fully connected layer of 64 outputs with ReLU for the wave's 64
-// samples: inputs from LDS tile `in`, outputs to LDS tile `out`.  Output
-// units are produced 16 at a time (one MFMA row tile), so only 16
-// accumulators per lane are live.  The accumulators start at the bias; the
-// outputs are rounded to BF16 and then clipped at zero on the BF16 bit
-// patterns (a negative BF16 is a negative 16-bit integer), which gives the
-// same values as rounding the clipped FP32 sum.
-__device__ __forceinline__ void hidden_layer(const __bf16 *__restrict__ w,
-                                             const float *__restrict__ bias,
-                                             const __bf16 *in, __bf16 *out) {
+// samples, inputs and outputs as B-operand fragments.  Output units come 16
+// at a time (one MFMA row tile: lane 16 g' + col holds units 4 g' .. + 3 of
+// sample 16 t + col).  The accumulators start at the bias; the outputs are
+// rounded to BF16 and then clipped at zero on the BF16 bit patterns (a
+// negative BF16 is a negative 16-bit integer), which gives the same values as
+// rounding the clipped FP32 sum.  The output tiles of units 32 kb .. + 15 (X)
+// and 32 kb + 16 .. + 31 (Y) hold, in lane row g' (16 lanes each), units
+// 4 g' .. + 3 of their tile; the next layer wants in lane row g units
+// 32 kb + 8 g .. + 7, i.e. rows 2 (g % 2) and 2 (g % 2) + 1 of X (g < 2) or of
+// Y (g >= 2).  v_permlane32_swap(X, Y) gives [X0 X1 Y0 Y1] and [X2 X3 Y2 Y3]
+// (rows), v_permlane16_swap of those gives [X0 X2 Y0 Y2] (the first four
+// units) and [X1 X3 Y1 Y3] (the last four).
+__device__ __forceinline__ void hidden_layer(const __bf16 *w, const float *__restrict__ bias,
+                                             const Frag &in, Frag &out) {
   const int lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
   typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
   typedef short i16x4 __attribute__((ext_vector_type(4)));
-#pragma unroll 2
+  u32x2 p[4][4];   // [output tile mt][sample tile t]: 4 BF16 units per lane
+#pragma unroll
   for (int mt = 0; mt < 4; ++mt) {
     const f32x4 b = *reinterpret_cast<const f32x4 *>(bias + 16 * mt + 4 * g);
     f32x4 acc[4];
@@ -114,44 +159,58 @@ __device__ __forceinline__ void hidden_layer(const __bf16 *__restrict__ w,
     for (int t = 0; t < 4; ++t) acc[t] = b;
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) {
-      const bf16x8 av = *reinterpret_cast<const bf16x8 *>(w + (16 * mt + col) * 64 + 32 * kb + 8 * g);
+      const bf16x8 av = lds_b8(w + (16 * mt + col) * kWStride + 32 * kb + 8 * g);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const bf16x8 bv = lds_b8(in + (16 * t + col) * kActStride + 32 * kb + 8 * g);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
-      }
+      for (int t = 0; t < 4; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, in.b[kb][t], acc[t], 0, 0, 0);
     }
-    const int unit = 16 * mt + 4 * g;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const bf16x4 v = __builtin_convertvector(acc[t], bf16x4);
       const i16x4 h = __builtin_elementwise_max(__builtin_bit_cast(i16x4, v), (i16x4)0);
-      *reinterpret_cast<i16x4 *>(out + (16 * t + col) * kActStride + unit) = h;
+      p[mt][t] = __builtin_bit_cast(u32x2, h);
     }
   }
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      u32x4 o;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const auto r = __builtin_amdgcn_permlane32_swap(p[2 * kb][t][c], p[2 * kb + 1][t][c],
+                                                        false, false);
+        const auto q = __builtin_amdgcn_permlane16_swap(r[0], r[1], false, false);
+        o[c] = q[0];       // units 8 g + 2 c, + 1
+        o[2 + c] = q[1];   // units 8 g + 4 + 2 c, + 1
+      }
+      out.b[kb][t] = __builtin_bit_cast(bf16x8, o);
+    }
 }
 
-// Network output z (6 per sample) for the 64 samples whose standardised
-// inputs are in LDS tile `act` (row = lane); `tmp` is a second tile of the
-// same size.  z of sample s lands in zout[8 s .. 8 s + 5] (zout may alias
-// `act`: it is written after the last read of `act`).
-__device__ __forceinline__ void wave_forward(const NetDev *__restrict__ net, __bf16 *act,
-                                             __bf16 *tmp, float *zout) {
-  hidden_layer(net->w1f, net->b1f, act, tmp);
-  hidden_layer(net->w2, net->b2, tmp, act);
+// Network output z (6 per sample) for the 64 samples whose raw inputs are in
+// LDS tile `act` (row = lane); weights from the block's LDS copy `sw`
+// (net_weights_to_lds), biases from `net`.  z of sample s lands in
+// zout[8 s .. 8 s + 5] (zout may alias `act`: it is written after the last
+// read of `act`).
+__device__ __forceinline__ void wave_forward(const NetDev *__restrict__ net, const __bf16 *sw,
+                                             const __bf16 *act, float *zout) {
+  Frag f0, f1;
+  frag_from_lds(act, f0);
+  hidden_layer(sw, net->b1f, f0, f1);
+  hidden_layer(sw + 64 * kWStride, net->b2, f1, f0);
   const int lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
   f32x4 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int kb = 0; kb < 2; ++kb) {
-    const bf16x8 av = *reinterpret_cast<const bf16x8 *>(net->w3 + col * 64 + 32 * kb + 8 * g);
+    const bf16x8 av = lds_b8(sw + (128 + col) * kWStride + 32 * kb + 8 * g);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const bf16x8 b = lds_b8(act + (16 * t + col) * kActStride + 32 * kb + 8 * g);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, acc[t], 0, 0, 0);
-    }
+    for (int t = 0; t < 4; ++t)
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, f0.b[kb][t], acc[t], 0, 0, 0);
   }
+  __builtin_amdgcn_wave_barrier();
   if (g < 2) {
 #pragma unroll
     for (int t = 0; t < 4; ++t)
@@ -315,7 +374,6 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const NetDev *__restri
                                                           const float *__restrict__ feat,
                                                           uint32_t n, float *__restrict__ z) {
   __shared__ __bf16 s_act[4][64 * kActStride];
-  __shared__ __bf16 s_tmp[4][64 * kActStride];
   __shared__ float s_z[4][64 * 8];
   const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   const uint32_t s = (blockIdx.x * 4u + wv) * 64u + lane;
@@ -331,7 +389,10 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const NetDev *__restri
     }
     *reinterpret_cast<bf16x8 *>(row + 8 * c) = v;
   }
-  wave_forward(net, s_act[wv], s_tmp[wv], s_z[wv]);
+  __shared__ __bf16 s_w[kWRows * kWStride];
+  net_weights_to_lds(net, s_w);
+  __syncthreads();
+  wave_forward(net, s_w, s_act[wv], s_z[wv]);
   if (s < n)
 #pragma unroll
     for (int o = 0; o < kNO; ++o) z[(size_t)s * kNO + o] = s_z[wv][lane * 8 + o];

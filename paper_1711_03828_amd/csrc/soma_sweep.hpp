@@ -632,13 +632,14 @@ struct MixArgs {
 // non-finite network output rejects it and raises error bit 2.  The network
 // needs the bond vectors, so the two sets are handled one after the other.
 // ---------------------------------------------------------------------------
-// One wave's chains; act/tmp are the wave's two LDS activation tiles (the
-// network output z reuses tmp).  Returns through cnt the wave's accepted local
-// moves, accepted learned moves and learned attempts.
+// One wave's chains; act is the wave's LDS feature tile (the network output z
+// reuses it), sw the block's LDS copy of the network's weights.  Returns
+// through cnt the wave's accepted local moves, accepted learned moves and
+// learned attempts.
 template <bool COUNT64, bool VEC2, bool BINNED>
 __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx, const LaneMap &m,
-                                           __bf16 *act, __bf16 *tmp, uint32_t cnt[3]) {
-  float *zb = reinterpret_cast<float *>(tmp);
+                                           __bf16 *act, const __bf16 *sw, uint32_t cnt[3]) {
+  float *zb = reinterpret_cast<float *>(act);
   __bf16 *row = act + m.lane * kActStride;
   const uint32_t N = a.n;
   const uint32_t i0 = 2u * m.k, i1 = i0 + 1u;
@@ -686,7 +687,7 @@ __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx
       features_to_row_halo(a.grid, mx.halo, mx.halo_plane, is_b, r, has_l ? left - r : zero3,
                            has_r ? right - r : zero3, row, co);
       w_old = field_at(a.omega, pl, co);   // energies from the field itself
-      wave_forward(mx.net, act, tmp, zb);
+      wave_forward(mx.net, sw, act, zb);
       float mu[3], sig[3], lsig[3];
       head(zb + m.lane * 8, mx.head, mu, sig, lsig);
       float xi0, xi1, xi2, xi3;
@@ -700,7 +701,7 @@ __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx
       features_to_row_halo(a.grid, mx.halo, mx.halo_plane, is_b, rn, has_l ? left - rn : zero3,
                            has_r ? right - rn : zero3, row, cn);
       w_new = cn == co ? w_old : field_at(a.omega, pl, cn);
-      wave_forward(mx.net, act, tmp, zb);
+      wave_forward(mx.net, sw, act, zb);
       float mun[3], sign[3], lsign[3];
       head(zb + m.lane * 8, mx.head, mun, sign, lsign);
       float lq = 0.0f;
@@ -783,11 +784,13 @@ template <bool COUNT64, bool VEC2, bool BINNED>
 __global__ __launch_bounds__(256) void mc_sweep_mixed_kernel(const SweepArgs a_in,
                                                              const MixArgs mx) {
   __shared__ __bf16 s_act[4][64 * kActStride];
-  __shared__ __bf16 s_tmp[4][64 * kActStride];
+  __shared__ __bf16 s_w[kWRows * kWStride];
+  net_weights_to_lds(mx.net, s_w);
+  __syncthreads();
   const SweepArgs a = resolve_sweep(a_in, 0u);
   const LaneMap m = lane_map(a);
   uint32_t cnt[3];
-  mixed_wave<COUNT64, VEC2, BINNED>(a, mx, m, s_act[m.wib], s_tmp[m.wib], cnt);
+  mixed_wave<COUNT64, VEC2, BINNED>(a, mx, m, s_act[m.wib], s_w, cnt);
   mixed_finish(a, mx, cnt);
 }
 
