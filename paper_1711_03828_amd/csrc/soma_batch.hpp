@@ -37,6 +37,7 @@ struct BatchLaunch {
 template <bool COUNT64, bool VEC2, uint32_t KIND>
 __global__ __launch_bounds__(256, 2) void batched_sweep_kernel(const BatchLaunch L) {
   __shared__ __bf16 s_act[KIND == 2 ? 4 : 1][KIND == 2 ? 64 * kActStride : 1];
+  __shared__ float s_z[KIND == 2 ? 4 : 1][KIND == 2 ? 64 * 8 : 1];
   __shared__ __bf16 s_w[KIND == 2 ? kWRows * kWStride : 1];
   uint32_t net_sg = 0xFFFFFFFFu;   // segment whose weights s_w holds (mixed sweeps)
   uint32_t item, end, stride;
@@ -76,7 +77,8 @@ __global__ __launch_bounds__(256, 2) void batched_sweep_kernel(const BatchLaunch
         net_sg = sg;
       }
       uint32_t cnt[3];
-      mixed_wave<COUNT64, VEC2, false>(a, mx, m, s_act[KIND == 2 ? m.wib : 0], s_w, cnt);
+      mixed_wave<COUNT64, VEC2, false>(a, mx, m, s_act[KIND == 2 ? m.wib : 0],
+                                       s_z[KIND == 2 ? m.wib : 0], s_w, cnt);
       mixed_finish(a, mx, cnt);
     }
   }

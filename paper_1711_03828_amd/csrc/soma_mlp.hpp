@@ -313,6 +313,23 @@ __device__ __forceinline__ void store_row(const float (&f)[kNF], __bf16 *row) {
   }
 }
 
+// Rewrites only the bond features (54..59) of a row, whose field features are
+// current.
+__device__ __forceinline__ void bond_features_to_row(F3 bp, F3 bn, __bf16 *row) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  bf16x2 lo;
+  lo[0] = (__bf16)bp.x;
+  lo[1] = (__bf16)bp.y;
+  bf16x8 hi;
+  hi[0] = (__bf16)bp.z;
+  hi[1] = (__bf16)bn.x;
+  hi[2] = (__bf16)bn.y;
+  hi[3] = (__bf16)bn.z;
+  hi[4] = hi[5] = hi[6] = hi[7] = (__bf16)0.0f;
+  *reinterpret_cast<bf16x2 *>(row + 54) = lo;
+  *reinterpret_cast<bf16x8 *>(row + 56) = hi;
+}
+
 // Gathers the 60 features of a bead at r into one LDS row of bf16.  Returns
 // the bead's own field in its cell; `cell` receives that cell's index.
 __device__ __forceinline__ float features_to_row(const Grid &g, const float *__restrict__ omega,

@@ -632,14 +632,14 @@ struct MixArgs {
 // non-finite network output rejects it and raises error bit 2.  The network
 // needs the bond vectors, so the two sets are handled one after the other.
 // ---------------------------------------------------------------------------
-// One wave's chains; act is the wave's LDS feature tile (the network output z
-// reuses it), sw the block's LDS copy of the network's weights.  Returns
-// through cnt the wave's accepted local moves, accepted learned moves and
-// learned attempts.
+// One wave's chains; act is the wave's LDS feature tile, zb its LDS tile of
+// network outputs ([64][8] floats), sw the block's LDS copy of the network's
+// weights.  Returns through cnt the wave's accepted local moves, accepted
+// learned moves and learned attempts.
 template <bool COUNT64, bool VEC2, bool BINNED>
 __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx, const LaneMap &m,
-                                           __bf16 *act, const __bf16 *sw, uint32_t cnt[3]) {
-  float *zb = reinterpret_cast<float *>(act);
+                                           __bf16 *act, float *zb, const __bf16 *sw,
+                                           uint32_t cnt[3]) {
   __bf16 *row = act + m.lane * kActStride;
   const uint32_t N = a.n;
   const uint32_t i0 = 2u * m.k, i1 = i0 + 1u;
@@ -698,8 +698,16 @@ __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx
       const F3 tp = {fmaf(a.step, uniform11(w.x), r.x), fmaf(a.step, uniform11(w.y), r.y),
                      fmaf(a.step, uniform11(w.z), r.z)};
       rn = sel(learned, tl, tp);
-      features_to_row_halo(a.grid, mx.halo, mx.halo_plane, is_b, rn, has_l ? left - rn : zero3,
-                           has_r ? right - rn : zero3, row, cn);
+      // features at r': in the same cell the 27 field values are those at r
+      // (still in the row), so only the bond vectors change
+      cn = cell_of(a.grid, rn.x, rn.y, rn.z);
+      const F3 bpn = has_l ? left - rn : zero3, bnn = has_r ? right - rn : zero3;
+      if (cn != co) {
+        uint32_t c2;
+        features_to_row_halo(a.grid, mx.halo, mx.halo_plane, is_b, rn, bpn, bnn, row, c2);
+      } else {
+        bond_features_to_row(bpn, bnn, row);
+      }
       w_new = cn == co ? w_old : field_at(a.omega, pl, cn);
       wave_forward(mx.net, sw, act, zb);
       float mun[3], sign[3], lsign[3];
@@ -784,13 +792,14 @@ template <bool COUNT64, bool VEC2, bool BINNED>
 __global__ __launch_bounds__(256) void mc_sweep_mixed_kernel(const SweepArgs a_in,
                                                              const MixArgs mx) {
   __shared__ __bf16 s_act[4][64 * kActStride];
+  __shared__ float s_z[4][64 * 8];
   __shared__ __bf16 s_w[kWRows * kWStride];
   net_weights_to_lds(mx.net, s_w);
   __syncthreads();
   const SweepArgs a = resolve_sweep(a_in, 0u);
   const LaneMap m = lane_map(a);
   uint32_t cnt[3];
-  mixed_wave<COUNT64, VEC2, BINNED>(a, mx, m, s_act[m.wib], s_w, cnt);
+  mixed_wave<COUNT64, VEC2, BINNED>(a, mx, m, s_act[m.wib], s_z[m.wib], s_w, cnt);
   mixed_finish(a, mx, cnt);
 }
 
