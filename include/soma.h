@@ -299,11 +299,14 @@ int32_t soma_set_types(soma_system *sys, uint32_t n_types, const float *chi_n, v
  * too small. */
 int32_t soma_type_counts(soma_system *sys, uint64_t *out, uint32_t n_out, void *stream);
 
-/* Launch shape of the local-move sweep: 0 (default) runs one wave per tile
- * of chains; blocks > 0 runs that many persistent 256-thread blocks, each wave
- * looping over tiles and prefetching the next tile's positions.  Results are
- * identical for every value (they depend only on seed, sweep and chain).
- * A multiple of 8 keeps each XCD on one contiguous range of chains. */
+/* Launch shape of the SET sweeps (local, smart-MC, bond-Gibbs and mixed
+ * moves): 0 (default) runs one wave per tile of chains; blocks > 0, when
+ * fewer than the tile groups, runs that many persistent blocks whose waves
+ * draw their tiles from per-XCD counters in the workspace (zeroed by a small
+ * kernel before each launch, a graph node).  Results are identical for every
+ * value (they depend only on seed, sweep and chain).  A multiple of 8 keeps
+ * each XCD on one contiguous range of chains.  Capture graphs again after a
+ * change. */
 int32_t soma_set_sweep_blocks(soma_system *sys, uint32_t blocks);
 
 /* Threads per block (64, 128, ..., 512; default 256) of the local, smart-MC
@@ -445,10 +448,10 @@ typedef struct soma_tune {
 /* Single systems, SET order: the search space is the histogram mode
  * (SOMA_HIST_DIRECT, and SOMA_HIST_BINNED where the grid allows it) x the
  * block size of the local, smart-MC and bond-Gibbs sweeps (128, 256, 512
- * threads; the mixed sweep always runs 256) x, for local moves, the grid (one
- * block per tile group, or the persistent grid of as many blocks as the
- * device holds at once at that block size, from the runtime's occupancy
- * query; 2048 if it gives none): up to 12 candidates.
+ * threads; the mixed sweep always runs 256) x the grid (one block per tile
+ * group, or the persistent grid of as many blocks as the device holds at
+ * once for that kernel and block size, from the runtime's occupancy query;
+ * 2048 if it gives none): up to 12 candidates (4 for mixed moves).
  * Molecule order: the grid caps {none, 256, 512, 1024, 2048}.  Batches: the
  * item order (XCD ranges or round-robin) x the grid {one block per item, 2048,
  * 8192}. */

@@ -365,7 +365,7 @@ struct soma_system {
   soma::Grid grid;
   uint64_t sweep = 0;
   uint64_t attempted[4] = {0, 0, 0, 0};   // by move kind (the learned slot unused)
-  uint32_t sweep_blocks = 0;  // local-move grid: 0 = one tile per wave, else persistent blocks
+  uint32_t sweep_blocks = 0;  // SET sweep grid: 0 = one tile per wave, else persistent blocks
   uint64_t mixed_moves = 0;   // bead moves made by mixed sweeps (local or learned)
   uint32_t net_mask = 0;      // species with an installed network (bit per species)
   uint32_t arch_mask = 0;     // species with a general architecture (bit per species)
@@ -430,41 +430,57 @@ int32_t launch_hist_sys(soma_system *sys, hipStream_t s) {
 
 // The mixed kernel's LDS tiles are laid out for four waves: it always runs
 // 256-thread blocks; the others take `threads` (64..512).
+template <bool C64, bool V2, bool B, bool P>
+void launch_sweep_p(uint32_t kind, dim3 grid, dim3 threads, hipStream_t s,
+                    const soma::SweepArgs &a, const soma::MixArgs &mx) {
+  if (kind == SOMA_MOVE_MIXED)
+    hipLaunchKernelGGL((soma::mc_sweep_mixed_kernel<C64, V2, B, P>), grid, dim3(256), 0, s, a, mx);
+  else if (kind == SOMA_MOVE_SMC)
+    hipLaunchKernelGGL((soma::mc_sweep_smc_kernel<C64, V2, B, P>), grid, threads, 0, s, a);
+  else if (kind == SOMA_MOVE_GIBBS)
+    hipLaunchKernelGGL((soma::mc_sweep_gibbs_kernel<C64, V2, B, P>), grid, threads, 0, s, a);
+  else
+    hipLaunchKernelGGL((soma::mc_sweep_local_kernel<C64, V2, B, P>), grid, threads, 0, s, a);
+}
+
+// The mixed kernel's LDS tiles are laid out for four waves: it always runs
+// 256-thread blocks; the others take `threads` (64..512).  A set queue
+// selects the persistent instance.
 template <bool C64, bool V2, bool B>
 void launch_sweep_t(uint32_t kind, dim3 grid, dim3 threads, hipStream_t s,
                     const soma::SweepArgs &a, const soma::MixArgs &mx) {
-  if (kind == SOMA_MOVE_MIXED)
-    hipLaunchKernelGGL((soma::mc_sweep_mixed_kernel<C64, V2, B>), grid, dim3(256), 0, s, a, mx);
-  else if (kind == SOMA_MOVE_SMC)
-    hipLaunchKernelGGL((soma::mc_sweep_smc_kernel<C64, V2, B>), grid, threads, 0, s, a);
-  else if (kind == SOMA_MOVE_GIBBS)
-    hipLaunchKernelGGL((soma::mc_sweep_gibbs_kernel<C64, V2, B>), grid, threads, 0, s, a);
-  else
-    hipLaunchKernelGGL((soma::mc_sweep_local_kernel<C64, V2, B>), grid, threads, 0, s, a);
+  if (a.queue) launch_sweep_p<C64, V2, B, true>(kind, grid, threads, s, a, mx);
+  else launch_sweep_p<C64, V2, B, false>(kind, grid, threads, s, a, mx);
 }
 
-// Blocks of the local-move kernel that the whole device holds at once at
-// `threads` per block (occupancy of the kernel's registers and LDS times the
-// compute units): the persistent grid whose waves all start together.  0 if
-// the runtime cannot tell.
+// Blocks of a SET sweep kernel (local, smart-MC, bond-Gibbs or mixed; the
+// persistent 8-byte-pair instance that the full-size melts use) that the whole device
+// holds at once at `threads` per block: occupancy of the kernel's registers
+// and LDS times the compute units, the persistent grid whose waves all start
+// together.  0 if the runtime cannot tell.
 template <bool C64, bool B>
-uint32_t resident_local_blocks_t(uint32_t threads) {
+uint32_t resident_blocks_t(uint32_t kind, uint32_t threads) {
   int per_cu = 0, dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0u;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0u;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void *>(&soma::mc_sweep_local_kernel<C64, true, B>),
-          (int)threads, 0) != hipSuccess)
+  const void *f = kind == SOMA_MOVE_MIXED
+                      ? reinterpret_cast<const void *>(&soma::mc_sweep_mixed_kernel<C64, true, B, true>)
+                  : kind == SOMA_MOVE_SMC
+                      ? reinterpret_cast<const void *>(&soma::mc_sweep_smc_kernel<C64, true, B, true>)
+                  : kind == SOMA_MOVE_GIBBS
+                      ? reinterpret_cast<const void *>(&soma::mc_sweep_gibbs_kernel<C64, true, B, true>)
+                      : reinterpret_cast<const void *>(&soma::mc_sweep_local_kernel<C64, true, B, true>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, (int)threads, 0) != hipSuccess)
     return 0u;
   return per_cu > 0 && cus > 0 ? (uint32_t)per_cu * (uint32_t)cus : 0u;
 }
 
-uint32_t resident_local_blocks(bool c64, bool binned, uint32_t threads) {
-  if (c64) return binned ? resident_local_blocks_t<true, true>(threads)
-                         : resident_local_blocks_t<true, false>(threads);
-  return binned ? resident_local_blocks_t<false, true>(threads)
-                : resident_local_blocks_t<false, false>(threads);
+uint32_t resident_blocks(uint32_t kind, bool c64, bool binned, uint32_t threads) {
+  if (c64) return binned ? resident_blocks_t<true, true>(kind, threads)
+                         : resident_blocks_t<true, false>(kind, threads);
+  return binned ? resident_blocks_t<false, true>(kind, threads)
+                : resident_blocks_t<false, false>(kind, threads);
 }
 
 template <bool C64, bool V2>
@@ -603,7 +619,7 @@ int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s, uint32_t of
     const uint32_t threads = kind == SOMA_MOVE_MIXED ? 256u : sys->sweep_threads;
     const uint64_t chains_per_block = (uint64_t)(threads / 64u) * a.chains_per_wave;
     uint64_t blocks = (a.n_sub + chains_per_block - 1) / chains_per_block;
-    if (kind == SOMA_MOVE_LOCAL && sys->sweep_blocks && sys->sweep_blocks < blocks) {
+    if (sys->sweep_blocks && sys->sweep_blocks < blocks) {
       blocks = sys->sweep_blocks;   // persistent: tiles from counters zeroed here
       a.queue = reinterpret_cast<uint32_t *>(sys->ws + sys->d.off_queue);
       hipLaunchKernelGGL(soma::queue_reset_kernel, dim3(1), dim3(256), 0, s, a.queue);
@@ -2118,10 +2134,9 @@ int32_t soma_autotune(soma_system *sys, uint32_t cycles, uint32_t move_kind,
   if (rc) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   // SET order: mode = histogram mode (bit 0) | block size / 64 - 1 (bits 1..3);
-  // the grid for local moves only: one tile per wave (0), or the persistent
-  // grid of exactly the blocks the device holds at once, whose waves loop
-  // over the tiles and load the next tile's positions during the current one.
-  // Molecule order: grid caps small enough to keep its chains in L2.
+  // grid: one tile per wave (0), or the persistent grid of exactly the blocks
+  // the device holds at once, whose waves draw their tiles from per-XCD
+  // counters.  Molecule order: grid caps small enough to keep its chains in L2.
   std::vector<Shape> shapes;
   const bool mol = sys->scheme == SOMA_SCHEME_MOLECULE;
   if (mol) {
@@ -2133,10 +2148,9 @@ int32_t soma_autotune(soma_system *sys, uint32_t cycles, uint32_t move_kind,
       for (uint32_t t : {256u, 128u, 512u}) {
         if (fixed_block && t != 256u) continue;
         for (uint32_t resident : {0u, 1u}) {
-          if (resident && move_kind != SOMA_MOVE_LOCAL) continue;
           uint32_t g = 0u;
           if (resident) {
-            g = resident_local_blocks(sys->cfg.count_width == 32, h != 0u, t);
+            g = resident_blocks(move_kind, sys->cfg.count_width == 32, h != 0u, t);
             if (g == 0u) g = 2048u;
           }
           shapes.push_back({h | ((t / 64u - 1u) << 1), g});

@@ -68,11 +68,57 @@ struct SweepArgs {
 
 constexpr uint32_t kQueueParts = 8u, kQueueSub = 16u, kQueueStride = 32u;
 
-// Zeroes the tile counters of a persistent local sweep (a kernel, not a
-// memset, so that it can sit in a captured graph).
+// Zeroes the tile counters of a persistent sweep (a kernel, not a memset, so
+// that it can sit in a captured graph).
 __global__ __launch_bounds__(256) void queue_reset_kernel(uint32_t *q) {
   for (uint32_t i = threadIdx.x; i < kQueueParts * kQueueSub; i += blockDim.x)
     q[i * kQueueStride] = 0u;
+}
+
+// Tiles of a persistent SET sweep (PERSIST instances; SweepArgs::queue set).  The tiles (one
+// wave's chains each) are dealt XCD by XCD when the grid is a multiple of 8
+// blocks: part x owns the contiguous range [x T/8, (x+1) T/8), so the waves
+// running together on one XCD share one compact region of the grid.  Each
+// part hands out its tiles through S = min(kQueueSub, waves of the part)
+// counters; a wave draws from counter (wave mod S), which owns the tiles
+// sub + S j of the part (every counter has a wave), so that the part's waves
+// stay on one moving window of tiles however their speeds differ.  (With a
+// fixed stride per wave, waves drift apart over their ~200 tiles and the
+// window they cover outgrows L2: half again as many HBM reads.)
+struct TileIter {
+  uint32_t *q;
+  uint32_t t_begin, t_end, n_sq, sq;
+  bool lead;
+};
+
+__device__ __forceinline__ TileIter tile_iter(const SweepArgs &a) {
+  TileIter it;
+  const uint32_t n_tiles = (a.n_sub + a.chains_per_wave - 1u) / a.chains_per_wave;
+  const uint32_t blocks = gridDim.x;
+  const uint32_t parts = (blocks & 7u) == 0u ? 8u : 1u;
+  const uint32_t part = blockIdx.x % parts;
+  const uint32_t wpb = blockDim.x >> 6;
+  const uint32_t waves_per_part = (blocks / parts) * wpb;
+  const uint32_t wave_in_part = (blockIdx.x / parts) * wpb + (threadIdx.x >> 6);
+  it.t_begin = (uint32_t)(((uint64_t)n_tiles * part) / parts);
+  it.t_end = (uint32_t)(((uint64_t)n_tiles * (part + 1u)) / parts);
+  it.n_sq = waves_per_part < kQueueSub ? waves_per_part : kQueueSub;
+  it.sq = wave_in_part % it.n_sq;
+  it.q = a.queue + (part * kQueueSub + it.sq) * kQueueStride;
+  it.lead = (threadIdx.x & 63u) == 0u;
+  return it;
+}
+
+// Draws the wave's next tile index (lane 0; the value may still be in flight).
+__device__ __forceinline__ uint32_t tile_draw(const TileIter &it) {
+  uint32_t v = 0u;
+  if (it.lead) v = atomicAdd(it.q, 1u);
+  return v;
+}
+
+// The tile of a draw (>= t_end: no tiles left for this wave).
+__device__ __forceinline__ uint32_t tile_of(const TileIter &it, uint32_t v) {
+  return it.t_begin + it.sq + it.n_sq * (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
 // A move from cell `from` to cell `to` that the impenetrable cells allow.
@@ -330,76 +376,35 @@ __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap
 // the passes need no per-pass selection.  Requires a < 1 cell (host-checked):
 // a trial position is then at most one cell away along each axis.
 //
-// Tiles (one wave's chains) are dealt XCD by XCD: the tiles of XCD x are the
-// contiguous range [x T/8, (x+1) T/8), walked by that XCD's waves in order, so
-// the waves running together on one XCD share one compact region of the grid.
-// With fewer waves than tiles each wave loops, loading the next tile's
-// positions while it works on the current one.
+// Tiles (one wave's chains): one per wave, or drawn from per-XCD counters in
+// a persistent grid (TileIter).
 // ---------------------------------------------------------------------------
 // Registers capped for five waves per SIMD (96 VGPRs, no spills), so that the
 // persistent grid holds enough waves to cover the latency of its gathers and
 // of the bin reservations.
-template <bool COUNT64, bool VEC2, bool BINNED>
+template <bool COUNT64, bool VEC2, bool BINNED, bool PERSIST = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5)))
 void mc_sweep_local_kernel(const SweepArgs a_in) {
   const SweepArgs a = resolve_sweep(a_in, 0u);
-  const uint32_t n_tiles = (a.n_sub + a.chains_per_wave - 1u) / a.chains_per_wave;
-  const uint32_t blocks = gridDim.x;
-  // XCD split only when the grid is a multiple of 8 blocks
-  const uint32_t parts = (blocks & 7u) == 0u ? 8u : 1u;
-  const uint32_t part = blockIdx.x % parts;
-  const uint32_t wpb = blockDim.x >> 6;   // waves per block
-  const uint32_t waves_per_part = (blocks / parts) * wpb;
-  const uint32_t wave_in_part = (blockIdx.x / parts) * wpb + (threadIdx.x >> 6);
-  const uint32_t t_begin = (uint32_t)(((uint64_t)n_tiles * part) / parts);
-  const uint32_t t_end = (uint32_t)(((uint64_t)n_tiles * (part + 1u)) / parts);
-
-  uint32_t n_acc = 0;
-  if (a.queue) {
-    // Persistent grid: each part hands out its tiles through S = min(kQueueSub,
-    // waves of the part) counters; a wave draws from counter (wave mod S),
-    // which owns the tiles sub + S j of the part (every counter has a wave), so
-    // that the part's waves stay on one moving window of tiles however their
-    // speeds differ.  (With a fixed stride per wave, waves drift apart over
-    // their ~200 tiles and the window they cover outgrows L2: half again as
-    // many HBM reads.)  The next tile is drawn while the current one runs.
-    const uint32_t n_sq = waves_per_part < kQueueSub ? waves_per_part : kQueueSub;
-    const uint32_t sq = wave_in_part % n_sq;
-    uint32_t *q = a.queue + (part * kQueueSub + sq) * kQueueStride;
-    const bool lead = (threadIdx.x & 63u) == 0u;
-    uint32_t v = 0u;
-    if (lead) v = atomicAdd(q, 1u);
-    uint32_t t = t_begin + sq + n_sq * (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
-    while (t < t_end) {
-      uint32_t vn = 0u;
-      if (lead) vn = atomicAdd(q, 1u);
-      const LaneMap m = lane_map_tile(a, t, true);
-      float *cp = a.pos + (size_t)(m.has0 ? m.chain : 0u) * a.n * 3u + 6u * m.k;
-      F3 r0, r1;
-      load_pair<VEC2>(cp, m, r0, r1);
-      n_acc += local_tile<COUNT64, VEC2, BINNED>(a, m, cp, r0, r1);
-      t = t_begin + sq + n_sq * (uint32_t)__builtin_amdgcn_readfirstlane((int)vn);
-    }
-    finish_block(a, n_acc);
+  if (!PERSIST) {   // one tile per wave
+    const LaneMap m = lane_map(a);
+    float *cp = a.pos + (size_t)(m.has0 ? m.chain : 0u) * a.n * 3u + 6u * m.k;
+    F3 r0, r1;
+    load_pair<VEC2>(cp, m, r0, r1);
+    finish_block(a, local_tile<COUNT64, VEC2, BINNED>(a, m, cp, r0, r1));
     return;
   }
-  uint32_t t = t_begin + wave_in_part;
-  LaneMap m = lane_map_tile(a, t < t_end ? t : 0u, t < t_end);
-  float *cp = a.pos + (size_t)(m.has0 ? m.chain : 0u) * a.n * 3u + 6u * m.k;
-  F3 r0, r1;
-  load_pair<VEC2>(cp, m, r0, r1);
-  while (t < t_end) {
-    const uint32_t tn = t + waves_per_part;
-    const LaneMap mn = lane_map_tile(a, tn < t_end ? tn : 0u, tn < t_end);
-    float *cpn = a.pos + (size_t)(mn.has0 ? mn.chain : 0u) * a.n * 3u + 6u * mn.k;
-    F3 s0, s1;
-    load_pair<VEC2>(cpn, mn, s0, s1);    // next tile, in flight during this one
+  const TileIter it = tile_iter(a);
+  uint32_t n_acc = 0;
+  uint32_t t = tile_of(it, tile_draw(it));
+  while (t < it.t_end) {
+    const uint32_t vn = tile_draw(it);   // the next tile, drawn while this one runs
+    const LaneMap m = lane_map_tile(a, t, true);
+    float *cp = a.pos + (size_t)(m.has0 ? m.chain : 0u) * a.n * 3u + 6u * m.k;
+    F3 r0, r1;
+    load_pair<VEC2>(cp, m, r0, r1);
     n_acc += local_tile<COUNT64, VEC2, BINNED>(a, m, cp, r0, r1);
-    m = mn;
-    cp = cpn;
-    r0 = s0;
-    r1 = s1;
-    t = tn;
+    t = tile_of(it, vn);
   }
   finish_block(a, n_acc);
 }
@@ -594,18 +599,36 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
   return n_acc;
 }
 
-template <bool COUNT64, bool VEC2, bool BINNED>
-__global__ __launch_bounds__(512) void mc_sweep_smc_kernel(const SweepArgs a_in) {
-  const SweepArgs a = resolve_sweep(a_in, 0u);
-  const LaneMap m = lane_map(a);
-  finish_block(a, smc_wave<COUNT64, VEC2, BINNED>(a, m));
+// Smart-MC or bond-Gibbs waves over one tile each, or over the tiles of a
+// persistent grid (SweepArgs::queue).
+template <bool COUNT64, bool VEC2, bool BINNED, bool GIBBS, bool PERSIST>
+__device__ __forceinline__ void smc_tiles(const SweepArgs &a) {
+  if (!PERSIST) {   // one tile per wave
+    finish_block(a, smc_wave<COUNT64, VEC2, BINNED, GIBBS>(a, lane_map(a)));
+    return;
+  }
+  const TileIter it = tile_iter(a);
+  uint32_t n_acc = 0;
+  uint32_t t = tile_of(it, tile_draw(it));
+  while (t < it.t_end) {
+    const uint32_t vn = tile_draw(it);
+    n_acc += smc_wave<COUNT64, VEC2, BINNED, GIBBS>(a, lane_map_tile(a, t, true));
+    t = tile_of(it, vn);
+  }
+  finish_block(a, n_acc);
 }
 
-template <bool COUNT64, bool VEC2, bool BINNED>
+// PERSIST: the persistent-grid instance (SweepArgs::queue set); its loop over
+// tiles needs more registers than a single tile, so single-tile launches use
+// their own instance.
+template <bool COUNT64, bool VEC2, bool BINNED, bool PERSIST = false>
+__global__ __launch_bounds__(512) void mc_sweep_smc_kernel(const SweepArgs a_in) {
+  smc_tiles<COUNT64, VEC2, BINNED, false, PERSIST>(resolve_sweep(a_in, 0u));
+}
+
+template <bool COUNT64, bool VEC2, bool BINNED, bool PERSIST = false>
 __global__ __launch_bounds__(512) void mc_sweep_gibbs_kernel(const SweepArgs a_in) {
-  const SweepArgs a = resolve_sweep(a_in, 0u);
-  const LaneMap m = lane_map(a);
-  finish_block(a, smc_wave<COUNT64, VEC2, BINNED, true>(a, m));
+  smc_tiles<COUNT64, VEC2, BINNED, true, PERSIST>(resolve_sweep(a_in, 0u));
 }
 
 }  // namespace soma
@@ -788,7 +811,7 @@ __device__ __forceinline__ void mixed_finish(const SweepArgs &a, const MixArgs &
   __syncthreads();
 }
 
-template <bool COUNT64, bool VEC2, bool BINNED>
+template <bool COUNT64, bool VEC2, bool BINNED, bool PERSIST = false>
 __global__ __launch_bounds__(256) void mc_sweep_mixed_kernel(const SweepArgs a_in,
                                                              const MixArgs mx) {
   __shared__ __bf16 s_act[4][64 * kActStride];
@@ -797,9 +820,26 @@ __global__ __launch_bounds__(256) void mc_sweep_mixed_kernel(const SweepArgs a_i
   net_weights_to_lds(mx.net, s_w);
   __syncthreads();
   const SweepArgs a = resolve_sweep(a_in, 0u);
-  const LaneMap m = lane_map(a);
-  uint32_t cnt[3];
-  mixed_wave<COUNT64, VEC2, BINNED>(a, mx, m, s_act[m.wib], s_z[m.wib], s_w, cnt);
+  const uint32_t wib = threadIdx.x >> 6;
+  uint32_t cnt[3] = {0u, 0u, 0u};
+  if (!PERSIST) {   // one tile per wave
+    mixed_wave<COUNT64, VEC2, BINNED>(a, mx, lane_map(a), s_act[wib], s_z[wib], s_w, cnt);
+    mixed_finish(a, mx, cnt);
+    return;
+  }
+  // a persistent grid copies the weights once per block for all its tiles
+  const TileIter it = tile_iter(a);
+  uint32_t t = tile_of(it, tile_draw(it));
+  while (t < it.t_end) {
+    const uint32_t vn = tile_draw(it);
+    uint32_t c[3];
+    mixed_wave<COUNT64, VEC2, BINNED>(a, mx, lane_map_tile(a, t, true), s_act[wib], s_z[wib],
+                                      s_w, c);
+    cnt[0] += c[0];
+    cnt[1] += c[1];
+    cnt[2] += c[2];
+    t = tile_of(it, vn);
+  }
   mixed_finish(a, mx, cnt);
 }
 
