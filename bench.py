@@ -267,9 +267,13 @@ def learned_leg(p_learn: float, equil_cycles: int, substeps: int, lag: int = 64,
         "flop_per_step": flop_train, "flop_per_sample": FLOP_TRAIN_SAMPLE}
     rates = {}
     ksub = {"plain": 1, "learned": substeps, "gibbs": substeps}
+    tuned = {}
     for name, kind in (("plain", C.SOMA_MOVE_LOCAL), ("learned", C.SOMA_MOVE_MIXED),
                        ("gibbs", C.SOMA_MOVE_GIBBS)):
         melt.set_substeps(ksub[name])
+        t = melt.autotune(2, kind)     # launch shape per sampler (results do not depend on it)
+        tuned[name] = {"hist_mode": "binned" if t.hist_mode else "direct",
+                       "block_threads": t.block_threads, "grid_blocks": t.grid_blocks}
         melt.capture_cycle(10, kind)
         melt.run_cycle(2)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -280,11 +284,12 @@ def learned_leg(p_learn: float, equil_cycles: int, substeps: int, lag: int = 64,
         ms = e0.elapsed_time(e1) / 50
         rates[name] = 1e3 / ms
         out[name] = {"ms_per_cycle": ms, "bead_moves_per_s": w.n_beads * 1e3 / ms,
-                     "substeps": ksub[name]}
+                     "substeps": ksub[name], "launch": tuned[name]}
     # matrix-core roofline of the mixed sweep: every learned move evaluates the
     # network at r and at r' (2 x 16,640 flop); sweeps with the fields frozen,
     # HIP events on the launch stream
     melt.set_substeps(1)
+    melt.autotune(2, C.SOMA_MOVE_MIXED)
     melt.sweep(2, C.SOMA_MOVE_MIXED)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
