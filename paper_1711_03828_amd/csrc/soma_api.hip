@@ -221,11 +221,11 @@ int32_t launch_hist(const soma_config *c, const Derived &d, const float *pos, vo
     const uint32_t planes = (d.n_types + 1u) / 2u;
     const size_t lds = (size_t)planes * soma::kBrickCells * (c->count_width == 32 ? 8u : 4u);
     if (c->count_width == 32)
-      hipLaunchKernelGGL(soma::bin_apply_kernel<true>, dim3((uint32_t)d.n_bricks), dim3(256), lds,
-                         s, *bins, g, counts, planes);
+      hipLaunchKernelGGL(soma::bin_apply_kernel<true>, dim3((uint32_t)d.n_bricks),
+                         dim3(soma::kApplyThreads), lds, s, *bins, g, counts, planes);
     else
-      hipLaunchKernelGGL(soma::bin_apply_kernel<false>, dim3((uint32_t)d.n_bricks), dim3(256),
-                         lds, s, *bins, g, counts, planes);
+      hipLaunchKernelGGL(soma::bin_apply_kernel<false>, dim3((uint32_t)d.n_bricks),
+                         dim3(soma::kApplyThreads), lds, s, *bins, g, counts, planes);
     LAUNCH_TRY();
     return SOMA_OK;
   }
@@ -498,12 +498,13 @@ int32_t launch_bin_apply(soma_system *sys, hipStream_t s) {
   const bool c64 = sys->cfg.count_width == 32;
   const uint32_t planes = 1u;
   const size_t lds = (size_t)planes * soma::kBrickCells * (c64 ? 8u : 4u);
+  const dim3 grid((uint32_t)sys->d.n_bricks), block(soma::kApplyThreads);
   if (c64)
-    hipLaunchKernelGGL(soma::bin_apply_kernel<true>, dim3((uint32_t)sys->d.n_bricks), dim3(256),
-                       lds, s, b, sys->grid, sys->buf.counts, planes);
+    hipLaunchKernelGGL(soma::bin_apply_kernel<true>, grid, block, lds, s, b, sys->grid,
+                       sys->buf.counts, planes);
   else
-    hipLaunchKernelGGL(soma::bin_apply_kernel<false>, dim3((uint32_t)sys->d.n_bricks), dim3(256),
-                       lds, s, b, sys->grid, sys->buf.counts, planes);
+    hipLaunchKernelGGL(soma::bin_apply_kernel<false>, grid, block, lds, s, b, sys->grid,
+                       sys->buf.counts, planes);
   LAUNCH_TRY();
   return SOMA_OK;
 }

@@ -246,71 +246,118 @@ __global__ __launch_bounds__(256) void density_hist_binned_kernel(
   bin_append<COUNT64>(b, g, counts, k0 >> 11, k1 >> 11, 0u, 0u, v0, v1, 0u, 0u, want);
 }
 
-// Applies the bins to the counts: one workgroup per brick.  The brick's count
-// words (every plane) are staged in LDS, the bin's updates added with LDS
-// atomics, the words written back, and the bin emptied for the next sweep.
+// Applies the bins to the counts: one workgroup of kApplyThreads per brick.
+// The brick's count words (every plane) are staged in LDS, the bin's updates
+// added with LDS atomics, the words written back, and the bin emptied for the
+// next sweep.  The sub-bins' fill levels load together with the counts, and
+// their entries are taken as one flat index range, kApplyBatch independent
+// loads per thread at a time, so that a block waits on memory a few times
+// rather than twice per sub-bin.
 // LDS: planes x 2048 words (u16 pairs) or 2 x planes x 2048 halves (u32 pairs).
+constexpr uint32_t kApplyThreads = 256u;
+constexpr uint32_t kApplyBatch = 4u;
+constexpr uint32_t kApplyPerThread = kBrickCells / kApplyThreads;   // cells per thread and plane
+
 template <bool COUNT64>
-__global__ __launch_bounds__(256) void bin_apply_kernel(BinArgs b, Grid g, void *counts,
-                                                        uint32_t planes) {
+__device__ __forceinline__ void apply_entry_lds(uint32_t *s_cnt, uint32_t planes, uint32_t e) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const uint32_t upd = (e >> (16 * h)) & 0xFFFFu;
+    const uint32_t t = (upd >> 11) & 7u;
+    if ((upd & kUpdPresent) && (t >> 1) < planes) {
+      const uint32_t i = (t >> 1) * kBrickCells + (upd & 2047u);
+      const bool minus = (upd & kUpdMinus) != 0u;
+      if (COUNT64) {
+        atomicAdd(&s_cnt[i * 2 + (t & 1u)], minus ? 0xFFFFFFFFu : 1u);
+      } else {
+        const uint32_t inc = (t & 1u) ? (1u << 16) : 1u;
+        atomicAdd(&s_cnt[i], minus ? 0u - inc : inc);
+      }
+    }
+  }
+}
+
+template <bool COUNT64>
+__global__ __launch_bounds__(kApplyThreads) void bin_apply_kernel(BinArgs b, Grid g, void *counts,
+                                                                  uint32_t planes) {
   extern __shared__ uint32_t s_cnt[];
-  const uint32_t brick = blockIdx.x;
+  __shared__ uint32_t s_fill[kSubBins];
+  const uint32_t brick = blockIdx.x, tid = threadIdx.x;
+  uint32_t fill = 0u;
+  if (tid < kSubBins) fill = b.bin_count[(brick << kSubShift) | tid];
   const uint32_t bx = brick % b.nbx, rest = brick / b.nbx;
   const uint32_t by = rest % b.nby, bz = rest / b.nby;
   const uint32_t x0 = bx * 16u, y0 = by * 16u, z0 = bz * 8u;
-  for (uint32_t i = threadIdx.x; i < planes * kBrickCells; i += blockDim.x) {
-    const uint32_t p = i / kBrickCells, l = i % kBrickCells;
-    const uint32_t x = x0 + (l & 15u), y = y0 + ((l >> 4) & 15u), z = z0 + (l >> 8);
-    uint32_t lo = 0u, hi = 0u;
-    if (x < (uint32_t)g.nx && y < (uint32_t)g.ny && z < (uint32_t)g.nz) {
-      const size_t w = (size_t)p * g.n_cells + ((size_t)z * g.ny + y) * g.nx + x;
-      if (COUNT64) {
-        const uint2 v = reinterpret_cast<const uint2 *>(counts)[w];
-        lo = v.x;
-        hi = v.y;
-      } else {
-        lo = reinterpret_cast<const uint32_t *>(counts)[w];
-      }
-    }
-    if (COUNT64) reinterpret_cast<uint2 *>(s_cnt)[i] = make_uint2(lo, hi);
-    else s_cnt[i] = lo;
-  }
-  __syncthreads();
-  for (uint32_t sb = 0; sb < kSubBins; ++sb) {
-  const uint32_t n = min(b.bin_count[(brick << kSubShift) | sb], b.cap);
-  const uint32_t *bin = b.bins + (size_t)((brick << kSubShift) | sb) * b.cap;
-  for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
-    const uint32_t e = bin[j];
+  // cell l = tid + u * kApplyThreads of the brick: a thread keeps x = x0 + (tid & 15)
+  const uint32_t x = x0 + (tid & 15u);
+  for (uint32_t p = 0; p < planes; ++p) {
+    uint2 v[kApplyPerThread];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const uint32_t upd = (e >> (16 * h)) & 0xFFFFu;
-      const uint32_t t = (upd >> 11) & 7u;
-      if ((upd & kUpdPresent) && (t >> 1) < planes) {
-        const uint32_t i = (t >> 1) * kBrickCells + (upd & 2047u);
-        const bool minus = (upd & kUpdMinus) != 0u;
-        if (COUNT64) {
-          atomicAdd(&s_cnt[i * 2 + (t & 1u)], minus ? 0xFFFFFFFFu : 1u);
-        } else {
-          const uint32_t inc = (t & 1u) ? (1u << 16) : 1u;
-          atomicAdd(&s_cnt[i], minus ? 0u - inc : inc);
+    for (uint32_t u = 0; u < kApplyPerThread; ++u) {
+      const uint32_t l = tid + u * kApplyThreads;
+      const uint32_t y = y0 + ((l >> 4) & 15u), z = z0 + (l >> 8);
+      v[u] = make_uint2(0u, 0u);
+      if (x < (uint32_t)g.nx && y < (uint32_t)g.ny && z < (uint32_t)g.nz) {
+        const size_t w = (size_t)p * g.n_cells + ((size_t)z * g.ny + y) * g.nx + x;
+        if (COUNT64) v[u] = reinterpret_cast<const uint2 *>(counts)[w];
+        else v[u].x = reinterpret_cast<const uint32_t *>(counts)[w];
+      }
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kApplyPerThread; ++u) {
+      const uint32_t i = p * kBrickCells + tid + u * kApplyThreads;
+      if (COUNT64) reinterpret_cast<uint2 *>(s_cnt)[i] = v[u];
+      else s_cnt[i] = v[u].x;
+    }
+  }
+  if (tid < kSubBins) s_fill[tid] = min(fill, b.cap);
+  __syncthreads();
+  // sub-bin s holds the flat indices [start[s], start[s] + fill of s)
+  uint32_t start[kSubBins];
+  uint32_t total = 0u;
+#pragma unroll
+  for (uint32_t s = 0; s < kSubBins; ++s) {
+    start[s] = total;
+    total += s_fill[s];
+  }
+  const uint32_t *bins = b.bins + (size_t)(brick << kSubShift) * b.cap;
+  for (uint32_t j0 = 0; j0 < total; j0 += kApplyBatch * kApplyThreads) {
+    uint32_t e[kApplyBatch];
+#pragma unroll
+    for (uint32_t u = 0; u < kApplyBatch; ++u) {
+      const uint32_t j = j0 + u * kApplyThreads + tid;
+      e[u] = 0u;
+      if (j < total) {
+        uint32_t sb = 0u, base = 0u;
+#pragma unroll
+        for (uint32_t s = 1; s < kSubBins; ++s) {
+          const bool past = j >= start[s];
+          sb = past ? s : sb;
+          base = past ? start[s] : base;
         }
+        e[u] = bins[(size_t)sb * b.cap + (j - base)];
+      }
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kApplyBatch; ++u) apply_entry_lds<COUNT64>(s_cnt, planes, e[u]);
+  }
+  __syncthreads();
+  for (uint32_t p = 0; p < planes; ++p) {
+#pragma unroll
+    for (uint32_t u = 0; u < kApplyPerThread; ++u) {
+      const uint32_t l = tid + u * kApplyThreads;
+      const uint32_t y = y0 + ((l >> 4) & 15u), z = z0 + (l >> 8);
+      if (x < (uint32_t)g.nx && y < (uint32_t)g.ny && z < (uint32_t)g.nz) {
+        const size_t w = (size_t)p * g.n_cells + ((size_t)z * g.ny + y) * g.nx + x;
+        const uint32_t i = p * kBrickCells + l;
+        if (COUNT64)
+          reinterpret_cast<uint2 *>(counts)[w] = reinterpret_cast<const uint2 *>(s_cnt)[i];
+        else
+          reinterpret_cast<uint32_t *>(counts)[w] = s_cnt[i];
       }
     }
   }
-  }
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < planes * kBrickCells; i += blockDim.x) {
-    const uint32_t p = i / kBrickCells, l = i % kBrickCells;
-    const uint32_t x = x0 + (l & 15u), y = y0 + ((l >> 4) & 15u), z = z0 + (l >> 8);
-    if (x < (uint32_t)g.nx && y < (uint32_t)g.ny && z < (uint32_t)g.nz) {
-      const size_t w = (size_t)p * g.n_cells + ((size_t)z * g.ny + y) * g.nx + x;
-      if (COUNT64)
-        reinterpret_cast<uint2 *>(counts)[w] = reinterpret_cast<const uint2 *>(s_cnt)[i];
-      else
-        reinterpret_cast<uint32_t *>(counts)[w] = s_cnt[i];
-    }
-  }
-  if (threadIdx.x < kSubBins) b.bin_count[(brick << kSubShift) | threadIdx.x] = 0u;
+  if (tid < kSubBins) b.bin_count[(brick << kSubShift) | tid] = 0u;
 }
 
 }  // namespace soma
