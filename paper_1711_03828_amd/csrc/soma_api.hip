@@ -561,6 +561,7 @@ void sweep_args(soma_system *sys, uint32_t sp, uint32_t kind, soma::SweepArgs &a
   a.bin = sys->d.bins_ok ? sys->bins() : soma::BinArgs{};
   a.self_term = sys->self_term ? self_energy(sys) : 0.0f;
   a.queue = nullptr;   // set by launch_sweep for persistent local grids
+  a.wpb = 4u;          // 256-thread blocks unless launch_sweep picks another size
   mx.net = sys->net(sp);
   mx.head.m_max = c->mu_max;
   mx.head.lo = c->log_sigma_min;
@@ -618,6 +619,7 @@ int32_t launch_sweep(soma_system *sys, uint32_t kind, hipStream_t s, uint32_t of
       continue;
     }
     const uint32_t threads = kind == SOMA_MOVE_MIXED ? 256u : sys->sweep_threads;
+    a.wpb = threads / 64u;
     const uint64_t chains_per_block = (uint64_t)(threads / 64u) * a.chains_per_wave;
     uint64_t blocks = (a.n_sub + chains_per_block - 1) / chains_per_block;
     if (sys->sweep_blocks && sys->sweep_blocks < blocks) {

@@ -42,9 +42,9 @@ struct BinArgs {
   uint32_t nbx, nby, nbz;
 };
 
-// Sub-bin of the calling wave.
-__device__ __forceinline__ uint32_t wave_sub_bin() {
-  return ((blockIdx.x * (blockDim.x >> 6)) + (threadIdx.x >> 6)) & (kSubBins - 1u);
+// Sub-bin of the calling wave (wpb waves per block).
+__device__ __forceinline__ uint32_t wave_sub_bin(uint32_t wpb) {
+  return ((blockIdx.x * wpb) + (threadIdx.x >> 6)) & (kSubBins - 1u);
 }
 
 // Brick key of cell (x, y, z): brick index << 11 | cell inside the brick.
@@ -161,11 +161,10 @@ __device__ __forceinline__ void tab_put(const BinArgs &b, const Grid &g, void *c
 // execute in issue order, so the table needs no barrier between the steps.
 template <bool COUNT64>
 __device__ __forceinline__ void bin_append(const BinArgs &b, const Grid &g, void *counts,
-                                           uint32_t k0, uint32_t k1, uint32_t k2, uint32_t k3,
+                                           uint32_t sub, uint32_t k0, uint32_t k1, uint32_t k2, uint32_t k3,
                                            uint32_t v0, uint32_t v1, uint32_t v2, uint32_t v3,
                                            uint32_t want) {
   __shared__ uint2 s_tab[kMaxWaves * kTabSlots];
-  const uint32_t sub = wave_sub_bin();
   const uint32_t lane = __lane_id();
   uint2 *tab = s_tab + (threadIdx.x >> 6) * kTabSlots;
   if (lane < kTabSlots) tab[lane] = make_uint2(kTabEmpty, 0u);
@@ -189,19 +188,21 @@ __device__ __forceinline__ void bin_append(const BinArgs &b, const Grid &g, void
 }
 
 // The count updates of a lane's two beads (bead e moved from the cell with
-// brick key from[e] to to[e] if moved[e]; t[e] its type), as bin entries:
+// brick key from[e] to to[e] if moved[e]; t[e] its type), as bin entries of
+// sub-bin `sub`:
 // one entry when both cells lie in one brick, else one entry per brick.
 template <bool COUNT64>
 __device__ __forceinline__ void bin_moves(const BinArgs &b, const Grid &g, void *counts,
-                                          uint32_t from0, uint32_t to0, uint32_t t0, bool moved0,
-                                          uint32_t from1, uint32_t to1, uint32_t t1, bool moved1) {
+                                          uint32_t sub, uint32_t from0, uint32_t to0, uint32_t t0,
+                                          bool moved0, uint32_t from1, uint32_t to1, uint32_t t1,
+                                          bool moved1) {
   const uint32_t hm0 = kUpdPresent | kUpdMinus | (t0 << 11) | (from0 & 2047u);
   const uint32_t hp0 = kUpdPresent | (t0 << 11) | (to0 & 2047u);
   const uint32_t hm1 = kUpdPresent | kUpdMinus | (t1 << 11) | (from1 & 2047u);
   const uint32_t hp1 = kUpdPresent | (t1 << 11) | (to1 & 2047u);
   const bool same0 = (from0 >> 11) == (to0 >> 11), same1 = (from1 >> 11) == (to1 >> 11);
   const uint32_t want = (moved0 ? (same0 ? 1u : 3u) : 0u) | (moved1 ? (same1 ? 4u : 12u) : 0u);
-  bin_append<COUNT64>(b, g, counts, from0 >> 11, to0 >> 11, from1 >> 11, to1 >> 11,
+  bin_append<COUNT64>(b, g, counts, sub, from0 >> 11, to0 >> 11, from1 >> 11, to1 >> 11,
                       same0 ? (hm0 | (hp0 << 16)) : hm0, hp0 << 16,
                       same1 ? (hm1 | (hp1 << 16)) : hm1, hp1 << 16, want);
 }
@@ -243,7 +244,8 @@ __global__ __launch_bounds__(256) void density_hist_binned_kernel(
   const uint32_t v0 = (has1 && same) ? (h0 | (h1 << 16)) : h0;
   const uint32_t v1 = h1 << 16;
   // a lane without bead 2q has only bead 2q+1 absent too (n_beads is the end)
-  bin_append<COUNT64>(b, g, counts, k0 >> 11, k1 >> 11, 0u, 0u, v0, v1, 0u, 0u, want);
+  bin_append<COUNT64>(b, g, counts, wave_sub_bin(blockDim.x >> 6), k0 >> 11, k1 >> 11, 0u, 0u,
+                      v0, v1, 0u, 0u, want);
 }
 
 // Applies the bins to the counts: one workgroup of kApplyThreads per brick.

@@ -64,6 +64,10 @@ struct SweepArgs {
   // persistent local sweeps: kQueueParts x kQueueSub tile counters, kQueueStride
   // words apart, zeroed before the launch (null: the static tile order)
   uint32_t *queue;
+  // waves per block of the launch (blockDim.x / 64), as a kernel argument: it
+  // loads with the other arguments, while the block size itself is a 16-bit
+  // field that costs a vector load ahead of everything that depends on it
+  uint32_t wpb;
 };
 
 constexpr uint32_t kQueueParts = 8u, kQueueSub = 16u, kQueueStride = 32u;
@@ -97,7 +101,7 @@ __device__ __forceinline__ TileIter tile_iter(const SweepArgs &a) {
   const uint32_t blocks = gridDim.x;
   const uint32_t parts = (blocks & 7u) == 0u ? 8u : 1u;
   const uint32_t part = blockIdx.x % parts;
-  const uint32_t wpb = blockDim.x >> 6;
+  const uint32_t wpb = a.wpb;
   const uint32_t waves_per_part = (blocks / parts) * wpb;
   const uint32_t wave_in_part = (blockIdx.x / parts) * wpb + (threadIdx.x >> 6);
   it.t_begin = (uint32_t)(((uint64_t)n_tiles * part) / parts);
@@ -179,7 +183,7 @@ __device__ __forceinline__ LaneMap lane_map_tile(const SweepArgs &a, uint32_t ti
 }
 
 __device__ __forceinline__ LaneMap lane_map(const SweepArgs &a) {
-  const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x) * a.wpb + (threadIdx.x >> 6);
   return lane_map_tile(a, tile, true);
 }
 
@@ -241,7 +245,7 @@ __device__ __forceinline__ void finish_block(const SweepArgs &a, uint32_t n_acc)
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t tot = 0;
-    for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) tot += s_acc[w];
+    for (uint32_t w = 0; w < a.wpb; ++w) tot += s_acc[w];
     if (tot) atomicAdd(a.acc_slots + (blockIdx.x & (kAccSlots - 1u)), (unsigned long long)tot);
   }
   __syncthreads();
@@ -307,9 +311,16 @@ __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap
   const uint32_t kt0 = BINNED ? brick_key(a.bin, sx0, sy0, sz0) : 0u;
   const uint32_t kf1 = BINNED ? brick_key(a.bin, x1, y1, z1) : 0u;
   const uint32_t kt1 = BINNED ? brick_key(a.bin, sx1, sy1, sz1) : 0u;
-  float wn0 = wo0, wn1 = wo1;
-  if (n0 != c0) wn0 = field_at(a.omega, pl0, n0);
-  if (n1 != c1) wn1 = field_at(a.omega, pl1, n1);
+  // trial-cell values only where the trial leaves the cell, chosen afterwards.
+  // With the old-cell value as the default of the load (which the compiler
+  // makes of a plain choice unless the empty asm hides the loaded registers)
+  // every gather waits for the one before it; this way all four are in flight
+  // together.
+  float g0 = 0.0f, g1 = 0.0f;
+  if (n0 != c0) g0 = field_at(a.omega, pl0, n0);
+  if (n1 != c1) g1 = field_at(a.omega, pl1, n1);
+  asm volatile("" : "+v"(g0), "+v"(g1));
+  const float wn0 = n0 != c0 ? g0 : wo0, wn1 = n1 != c1 ? g1 : wo1;
   const bool ok0 = move_allowed(a, c0, n0), ok1 = move_allowed(a, c1, n1);
 
   // relabel by set order: a moves first, b second
@@ -356,8 +367,8 @@ __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap
   store_pair<VEC2>(cp, m, sel(odd_first, rb, ra), sel(odd_first, ra, rb));
   const bool acc0 = odd_first ? acc_b : acc_a, acc1 = odd_first ? acc_a : acc_b;
   if (BINNED) {
-    bin_moves<COUNT64>(a.bin, a.grid, a.counts, kf0, kt0, b0 ? 1u : 0u, acc0 && n0 != c0,
-                       kf1, kt1, b1 ? 1u : 0u, acc1 && n1 != c1);
+    bin_moves<COUNT64>(a.bin, a.grid, a.counts, wave_sub_bin(a.wpb), kf0, kt0, b0 ? 1u : 0u,
+                       acc0 && n0 != c0, kf1, kt1, b1 ? 1u : 0u, acc1 && n1 != c1);
   } else {
     if (acc0 && n0 != c0) move_count<COUNT64>(a.counts, c0, n0, b0);
     if (acc1 && n1 != c1) move_count<COUNT64>(a.counts, c1, n1, b1);
@@ -590,8 +601,8 @@ __device__ __forceinline__ uint32_t smc_wave(const SweepArgs &a, const LaneMap &
 
   store_pair<VEC2>(cp, m, r0, r1);
   if (BINNED) {
-    bin_moves<COUNT64>(a.bin, a.grid, a.counts, from0, to0, b0 ? 1u : 0u, moved0, from1, to1,
-                       b1 ? 1u : 0u, moved1);
+    bin_moves<COUNT64>(a.bin, a.grid, a.counts, wave_sub_bin(a.wpb), from0, to0, b0 ? 1u : 0u,
+                       moved0, from1, to1, b1 ? 1u : 0u, moved1);
   } else {
     if (moved0) move_count<COUNT64>(a.counts, from0, to0, b0);
     if (moved1) move_count<COUNT64>(a.counts, from1, to1, b1);
@@ -777,7 +788,8 @@ __device__ __forceinline__ void mixed_wave(const SweepArgs &a, const MixArgs &mx
   }
   store_pair<VEC2>(cp, m, r0, r1);
   if (BINNED) {
-    bin_moves<COUNT64>(a.bin, a.grid, a.counts, cell_brick_key(a.bin, a.grid, from0),
+    bin_moves<COUNT64>(a.bin, a.grid, a.counts, wave_sub_bin(a.wpb),
+                       cell_brick_key(a.bin, a.grid, from0),
                        cell_brick_key(a.bin, a.grid, to0), b0 ? 1u : 0u, moved0,
                        cell_brick_key(a.bin, a.grid, from1), cell_brick_key(a.bin, a.grid, to1),
                        b1 ? 1u : 0u, moved1);
