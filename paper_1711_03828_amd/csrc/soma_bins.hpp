@@ -151,39 +151,72 @@ __device__ __forceinline__ void tab_put(const BinArgs &b, const Grid &g, void *c
   else apply_entry_direct<COUNT64>(b, g, counts, k, v);
 }
 
+// Set bits of mask m in the lanes below the calling one.
+__device__ __forceinline__ uint32_t mbcnt64(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // Appends the entries of a wave to their bricks' bins.  Each lane offers up
 // to four entries (slot s: brick ks, value vs, wanted if bit s of `want`).
 // All lanes of the wave must call this together (wave-uniform control flow).
-// The entries are counted per brick in the wave's LDS table (the rank of an
-// entry is its place among the wave's entries for its brick), one lane per
-// brick reserves that many places in the brick's sub-bin with one atomic, and
-// every entry is stored at reserved base + rank.  LDS operations of one wave
-// execute in issue order, so the table needs no barrier between the steps.
+// The wanted entries are first packed into a wave-private LDS list (slot 0 of
+// every lane, then slot 1, ...), so that the steps below run once per 64
+// entries with every lane busy, rather than once per slot with the few lanes
+// whose bead changed cell.  The entries are counted per brick in the wave's
+// LDS table (the rank of an entry is its place among the wave's entries for
+// its brick), one lane per brick reserves that many places in the brick's
+// sub-bin `sub` with one atomic, and every entry is stored at reserved base +
+// rank.  LDS operations of one wave execute in issue order, so neither the
+// list nor the table needs a barrier between the steps.
+constexpr uint32_t kListSlots = 4u * 64u;
+
 template <bool COUNT64>
 __device__ __forceinline__ void bin_append(const BinArgs &b, const Grid &g, void *counts,
-                                           uint32_t sub, uint32_t k0, uint32_t k1, uint32_t k2, uint32_t k3,
-                                           uint32_t v0, uint32_t v1, uint32_t v2, uint32_t v3,
-                                           uint32_t want) {
+                                           uint32_t sub, uint32_t k0, uint32_t k1, uint32_t k2,
+                                           uint32_t k3, uint32_t v0, uint32_t v1, uint32_t v2,
+                                           uint32_t v3, uint32_t want) {
   __shared__ uint2 s_tab[kMaxWaves * kTabSlots];
+  __shared__ uint2 s_list[kMaxWaves * kListSlots];
   const uint32_t lane = __lane_id();
   uint2 *tab = s_tab + (threadIdx.x >> 6) * kTabSlots;
+  uint2 *list = s_list + (threadIdx.x >> 6) * kListSlots;
   if (lane < kTabSlots) tab[lane] = make_uint2(kTabEmpty, 0u);
+  const uint64_t m0 = __ballot((want & 1u) != 0u), m1 = __ballot((want & 2u) != 0u);
+  const uint64_t m2 = __ballot((want & 4u) != 0u), m3 = __ballot((want & 8u) != 0u);
+  const uint32_t o1 = (uint32_t)__popcll(m0), o2 = o1 + (uint32_t)__popcll(m1);
+  const uint32_t o3 = o2 + (uint32_t)__popcll(m2), n = o3 + (uint32_t)__popcll(m3);
+  if (want & 1u) list[mbcnt64(m0)] = make_uint2(k0, v0);
+  if (want & 2u) list[o1 + mbcnt64(m1)] = make_uint2(k1, v1);
+  if (want & 4u) list[o2 + mbcnt64(m2)] = make_uint2(k2, v2);
+  if (want & 8u) list[o3 + mbcnt64(m3)] = make_uint2(k3, v3);
   __builtin_amdgcn_wave_barrier();
-  uint32_t q0 = 0u, q1 = 0u, q2 = 0u, q3 = 0u;   // slot << 16 | rank
-  if (want & 1u) q0 = tab_insert(tab, k0);
-  if (want & 2u) q1 = tab_insert(tab, k1);
-  if (want & 4u) q2 = tab_insert(tab, k2);
-  if (want & 8u) q3 = tab_insert(tab, k3);
-  __builtin_amdgcn_wave_barrier();
-  if (lane < kTabSlots) {   // one reservation per brick; the slot keeps its base
-    const uint2 e = tab[lane];
-    if (e.x != kTabEmpty) tab[lane].y = atomicAdd(b.bin_count + ((e.x << kSubShift) | sub), e.y);
+  // entry lane + 64 p of the list in pass p (n is wave-uniform)
+  uint2 e[4];
+  uint32_t q[4];   // slot << 16 | rank
+#pragma unroll
+  for (uint32_t p = 0; p < 4u; ++p) {
+    e[p] = make_uint2(0u, 0u);
+    q[p] = 0u;
+    if (64u * p < n) {
+      const uint32_t j = 64u * p + lane;
+      if (j < n) {
+        e[p] = list[j];
+        q[p] = tab_insert(tab, e[p].x);
+      }
+    }
   }
   __builtin_amdgcn_wave_barrier();
-  if (want & 1u) tab_put<COUNT64>(b, g, counts, tab, sub, k0, q0, v0);
-  if (want & 2u) tab_put<COUNT64>(b, g, counts, tab, sub, k1, q1, v1);
-  if (want & 4u) tab_put<COUNT64>(b, g, counts, tab, sub, k2, q2, v2);
-  if (want & 8u) tab_put<COUNT64>(b, g, counts, tab, sub, k3, q3, v3);
+  if (lane < kTabSlots) {   // one reservation per brick; the slot keeps its base
+    const uint2 t = tab[lane];
+    if (t.x != kTabEmpty) tab[lane].y = atomicAdd(b.bin_count + ((t.x << kSubShift) | sub), t.y);
+  }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (uint32_t p = 0; p < 4u; ++p) {
+    if (64u * p < n && 64u * p + lane < n)
+      tab_put<COUNT64>(b, g, counts, tab, sub, e[p].x, q[p], e[p].y);
+  }
   __builtin_amdgcn_wave_barrier();
 }
 
