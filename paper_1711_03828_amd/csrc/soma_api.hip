@@ -538,6 +538,7 @@ void sweep_args(soma_system *sys, uint32_t sp, uint32_t kind, soma::SweepArgs &a
   a.n_a = S.n_a;
   a.lanes_per_chain = (S.n + 1) / 2;
   a.chains_per_wave = 64u / a.lanes_per_chain;
+  a.lpc_magic = (65536u + a.lanes_per_chain - 1u) / a.lanes_per_chain;
   a.chain_base = (uint32_t)sys->d.chain_off[sp];
   a.k0 = S.k0;
   a.half_k0 = 0.5f * S.k0;

@@ -74,20 +74,18 @@ __device__ __forceinline__ uint32_t wrap_cell(float x, int n, float inv_n) {
   const float f = fminf(fmaxf(floorf(x), -kMaxCoord), kMaxCoord);
   const float q = floorf(f * inv_n);
   const int r = (int)fmaf(-q, (float)n, f);  // exact: integers below 2^24
-  uint32_t u = (uint32_t)r;
-  u = min(u, u + (uint32_t)n);               // r in [-n, 0)  -> r + n
-  u = min(u, u - (uint32_t)n);               // r in [n, 2n)  -> r - n
-  return u;
+  // r in [-n, 0) -> r + n, r in [n, 2n) -> r - n: as unsigned words the one
+  // candidate in [0, n) is the smallest of the three
+  const uint32_t u = (uint32_t)r;
+  return min(u, min(u + (uint32_t)n, u - (uint32_t)n));
 }
 
 // Cell coordinate of x' given the cell coordinate c of x and |x' - x| < 1:
 // floor moves by -1, 0 or +1, then wraps at the box faces.
 __device__ __forceinline__ uint32_t shift_cell(uint32_t c, float x, float xn, int n) {
   const int d = (int)(floorf(xn) - floorf(x));
-  uint32_t u = c + (uint32_t)d;
-  u = min(u, u + (uint32_t)n);  // -1 -> n-1
-  u = min(u, u - (uint32_t)n);  // n  -> 0
-  return u;
+  const uint32_t u = c + (uint32_t)d;   // -1 -> n-1 and n -> 0 as in wrap_cell
+  return min(u, min(u + (uint32_t)n, u - (uint32_t)n));
 }
 
 struct Grid {

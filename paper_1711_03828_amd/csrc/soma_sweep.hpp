@@ -68,6 +68,9 @@ struct SweepArgs {
   // loads with the other arguments, while the block size itself is a 16-bit
   // field that costs a vector load ahead of everything that depends on it
   uint32_t wpb;
+  // ceil(2^16 / lanes_per_chain): lane / lanes_per_chain = (lane lpc_magic) >> 16
+  // for every lane < 64 (exact while lanes_per_chain < 1024)
+  uint32_t lpc_magic;
 };
 
 constexpr uint32_t kQueueParts = 8u, kQueueSub = 16u, kQueueStride = 32u;
@@ -172,7 +175,7 @@ __device__ __forceinline__ LaneMap lane_map_tile(const SweepArgs &a, uint32_t ti
   m.wib = threadIdx.x >> 6;
   m.tile = tile;
   const uint32_t L = a.lanes_per_chain;
-  const uint32_t slot = (uint32_t)m.lane / L;
+  const uint32_t slot = __umul24((uint32_t)m.lane, a.lpc_magic) >> 16;
   m.k = (uint32_t)m.lane - slot * L;
   const uint32_t cl = tile * a.chains_per_wave + slot;   // index within the subset
   m.chain = cl * a.sub_k + a.sub_j;
