@@ -497,7 +497,10 @@ def batched_leg(cycles: int):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / (cycles // 10 * 10)
-    # the same cycles melt by melt (one launch per melt and kernel)
+    # the same cycles melt by melt (one launch per melt and kernel), in the
+    # histogram mode the batch was tuned to
+    for m in melts:
+        m.set_histogram(tune.hist_mode)
     e0.record(stream)
     for m in melts:
         m.cycle(10)
@@ -515,6 +518,7 @@ def batched_leg(cycles: int):
             "ms_per_cycle_unbatched": ms_single,
             "speedup_vs_unbatched": ms_single / ms,
             "tuned": {"mode": tune.mode, "grid_blocks": tune.grid_blocks,
+                      "hist_mode": "binned" if tune.hist_mode else "direct",
                       "candidates": tune.candidates, "cycles_run": tune.cycles_run},
             "acceptance": acc}
 

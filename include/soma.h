@@ -453,8 +453,9 @@ typedef struct soma_tune {
  * once for that kernel and block size, from the runtime's occupancy query;
  * 2048 if it gives none): up to 12 candidates (4 for mixed moves).
  * Molecule order: the grid caps {none, 256, 512, 1024, 2048}.  Batches: the
- * item order (XCD ranges or round-robin) x the grid {one block per item, 2048,
- * 8192}. */
+ * histogram mode (direct, and binned where every system allows it; hist_mode)
+ * x the item order (XCD ranges or round-robin; mode) x the grid {one block per
+ * item, 2048, 8192}: up to 12 candidates. */
 int32_t soma_autotune(soma_system *sys, uint32_t cycles, uint32_t move_kind,
                       const char *cache_path, void *stream, soma_tune *out);
 
@@ -477,6 +478,13 @@ int32_t soma_batch_create(soma_system *const *systems, uint32_t n, void *workspa
 /* Launch shape: mode 0 (XCD ranges, default) or 1 (round-robin items);
  * grid_blocks 0 (one block per item, default) or a persistent grid. */
 int32_t soma_batch_set_launch(soma_batch *b, uint32_t mode, uint32_t grid_blocks);
+/* Count updates of batched sweeps (Eq. (4), Sec. 3.1.1), as soma_set_histogram
+ * for one system: SOMA_HIST_DIRECT (default) or SOMA_HIST_BINNED, where each
+ * sweep appends to the bins of every system's own workspace and one more launch
+ * applies all of them brick by brick.  Counts, fields and trajectories are the
+ * same bits either way.  SOMA_E_UNSUPPORTED for SOMA_HIST_BINNED unless every
+ * system has bins (see soma_set_histogram) and at most two bead types. */
+int32_t soma_batch_set_histogram(soma_batch *b, uint32_t mode);
 /* n_sweeps sweeps of every system with fields fixed (asynchronous). */
 int32_t soma_batch_sweep(soma_batch *b, uint32_t n_sweeps, uint32_t move_kind, void *stream);
 /* Field refresh of every system (asynchronous). */

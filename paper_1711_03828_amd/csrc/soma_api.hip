@@ -1688,6 +1688,13 @@ struct soma_batch {
   uint32_t **d_ctrs = nullptr;
   uint32_t n_items = 0, c64 = 0, v2 = 1;
   uint32_t mode = 0, grid_blocks = 0;  // launch shape (results do not depend on it)
+  // binned count updates: every system's own bins, one apply launch for all
+  uint32_t hist = 0;                    // soma::kHistDirect or soma::kHistBinned
+  bool bins_ok = false;                 // every system has bins and two bead types
+  std::vector<soma::BinApplySeg> apply;
+  std::vector<uint32_t> brick_first;
+  soma::BinApplySeg *d_apply = nullptr;
+  uint32_t *d_brick_first = nullptr;
   uint32_t substeps = 1;                // chain subsets per cycle (field refresh after each)
   CycleGraph graph;
   ~soma_batch() { graph.release(); }
@@ -1696,7 +1703,7 @@ struct soma_batch {
 namespace {
 
 struct BatchLayout {
-  uint64_t segs[4], seg_first, fargs, fb_first, ctrs, total;
+  uint64_t segs[4], seg_first, fargs, fb_first, ctrs, apply, brick_first, total;
 };
 
 BatchLayout batch_layout(uint64_t n_segs, uint64_t n_sys) {
@@ -1714,6 +1721,10 @@ BatchLayout batch_layout(uint64_t n_segs, uint64_t n_sys) {
   o = align_up(o + (n_sys + 1) * 4);
   L.ctrs = o;
   o = align_up(o + n_sys * 8);
+  L.apply = o;
+  o = align_up(o + n_sys * sizeof(soma::BinApplySeg));
+  L.brick_first = o;
+  o = align_up(o + (n_sys + 1) * 4);
   L.total = o;
   return L;
 }
@@ -1753,16 +1764,23 @@ int32_t batch_items(soma_batch *b) {
   return SOMA_OK;
 }
 
-template <bool C64, bool V2>
-void launch_batch_t(uint32_t kind, dim3 grid, hipStream_t s, const soma::BatchLaunch &L) {
+template <bool C64, bool V2, bool B>
+void launch_batch_k(uint32_t kind, dim3 grid, hipStream_t s, const soma::BatchLaunch &L) {
   if (kind == SOMA_MOVE_MIXED)
-    hipLaunchKernelGGL((soma::batched_sweep_kernel<C64, V2, 2>), grid, dim3(256), 0, s, L);
+    hipLaunchKernelGGL((soma::batched_sweep_kernel<C64, V2, 2, B>), grid, dim3(256), 0, s, L);
   else if (kind == SOMA_MOVE_GIBBS)
-    hipLaunchKernelGGL((soma::batched_sweep_kernel<C64, V2, 3>), grid, dim3(256), 0, s, L);
+    hipLaunchKernelGGL((soma::batched_sweep_kernel<C64, V2, 3, B>), grid, dim3(256), 0, s, L);
   else if (kind == SOMA_MOVE_SMC)
-    hipLaunchKernelGGL((soma::batched_sweep_kernel<C64, V2, 1>), grid, dim3(256), 0, s, L);
+    hipLaunchKernelGGL((soma::batched_sweep_kernel<C64, V2, 1, B>), grid, dim3(256), 0, s, L);
   else
-    hipLaunchKernelGGL((soma::batched_sweep_kernel<C64, V2, 0>), grid, dim3(256), 0, s, L);
+    hipLaunchKernelGGL((soma::batched_sweep_kernel<C64, V2, 0, B>), grid, dim3(256), 0, s, L);
+}
+
+template <bool C64, bool V2>
+void launch_batch_t(bool binned, uint32_t kind, dim3 grid, hipStream_t s,
+                    const soma::BatchLaunch &L) {
+  if (binned) launch_batch_k<C64, V2, true>(kind, grid, s, L);
+  else launch_batch_k<C64, V2, false>(kind, grid, s, L);
 }
 
 int32_t launch_batch_sweep(soma_batch *b, uint32_t kind, hipStream_t s, uint32_t off,
@@ -1786,13 +1804,26 @@ int32_t launch_batch_sweep(soma_batch *b, uint32_t kind, hipStream_t s, uint32_t
     if (b->grid_blocks && b->grid_blocks < blocks) blocks = b->grid_blocks;
   }
   const dim3 grid(blocks);
+  const bool binned = b->hist == soma::kHistBinned;
   if (b->c64) {
-    if (b->v2) launch_batch_t<true, true>(kind, grid, s, L);
-    else launch_batch_t<true, false>(kind, grid, s, L);
+    if (b->v2) launch_batch_t<true, true>(binned, kind, grid, s, L);
+    else launch_batch_t<true, false>(binned, kind, grid, s, L);
   } else {
-    if (b->v2) launch_batch_t<false, true>(kind, grid, s, L);
-    else launch_batch_t<false, false>(kind, grid, s, L);
+    if (b->v2) launch_batch_t<false, true>(binned, kind, grid, s, L);
+    else launch_batch_t<false, false>(binned, kind, grid, s, L);
   }
+  LAUNCH_TRY();
+  if (!binned) return SOMA_OK;
+  // every system's bins into its counts: one workgroup per brick of the batch
+  const uint32_t n_sys = (uint32_t)b->sys.size();
+  const dim3 agrid(b->brick_first[n_sys]), ablock(soma::kApplyThreads);
+  const size_t lds = (size_t)soma::kBrickCells * (b->c64 ? 8u : 4u);
+  if (b->c64)
+    hipLaunchKernelGGL(soma::batched_bin_apply_kernel<true>, agrid, ablock, lds, s, b->d_apply,
+                       b->d_brick_first, n_sys);
+  else
+    hipLaunchKernelGGL(soma::batched_bin_apply_kernel<false>, agrid, ablock, lds, s, b->d_apply,
+                       b->d_brick_first, n_sys);
   LAUNCH_TRY();
   return SOMA_OK;
 }
@@ -1898,12 +1929,28 @@ int32_t soma_batch_create(soma_system *const *systems, uint32_t n, void *workspa
     b->fb_first.push_back(b->fb_first.back() + x->d.field_blocks);
     b->ctrs.push_back(x->sweep_ctr());
   }
+  b->bins_ok = true;
+  b->brick_first.push_back(0);
+  for (uint32_t i = 0; i < n; ++i) {
+    soma_system *x = systems[i];
+    b->bins_ok = b->bins_ok && x->d.bins_ok && x->d.n_types <= 2;
+    soma::BinApplySeg a{};
+    if (x->d.bins_ok) a.b = x->bins();
+    a.g = x->grid;
+    a.counts = x->buf.counts;
+    b->apply.push_back(a);
+    const uint64_t next = (uint64_t)b->brick_first.back() + (x->d.bins_ok ? x->d.n_bricks : 0u);
+    b->bins_ok = b->bins_ok && next < (1ull << 31);
+    b->brick_first.push_back((uint32_t)std::min<uint64_t>(next, 1ull << 31));
+  }
   unsigned char *ws = reinterpret_cast<unsigned char *>(workspace);
   for (int k = 0; k < 4; ++k) b->d_segs[k] = reinterpret_cast<soma::BatchSeg *>(ws + lay.segs[k]);
   b->d_seg_first = reinterpret_cast<uint32_t *>(ws + lay.seg_first);
   b->d_fargs = reinterpret_cast<soma::FieldArgs *>(ws + lay.fargs);
   b->d_fb_first = reinterpret_cast<uint32_t *>(ws + lay.fb_first);
   b->d_ctrs = reinterpret_cast<uint32_t **>(ws + lay.ctrs);
+  b->d_apply = reinterpret_cast<soma::BinApplySeg *>(ws + lay.apply);
+  b->d_brick_first = reinterpret_cast<uint32_t *>(ws + lay.brick_first);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   auto put = [&](void *dst, const void *src, size_t bytes) -> int32_t {
     HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
@@ -1915,6 +1962,8 @@ int32_t soma_batch_create(soma_system *const *systems, uint32_t n, void *workspa
   if (!rc) rc = put(b->d_fargs, b->fargs.data(), b->fargs.size() * sizeof(soma::FieldArgs));
   if (!rc) rc = put(b->d_fb_first, b->fb_first.data(), b->fb_first.size() * 4);
   if (!rc) rc = put(b->d_ctrs, b->ctrs.data(), b->ctrs.size() * 8);
+  if (!rc) rc = put(b->d_apply, b->apply.data(), b->apply.size() * sizeof(soma::BinApplySeg));
+  if (!rc) rc = put(b->d_brick_first, b->brick_first.data(), b->brick_first.size() * 4);
   if (!rc) {  // the host tables must outlive the copies
     const hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) rc = fail(SOMA_E_HIP, "batch tables: %s", hipGetErrorString(e));
@@ -1924,6 +1973,17 @@ int32_t soma_batch_create(soma_system *const *systems, uint32_t n, void *workspa
     return rc;
   }
   *out = b;
+  return SOMA_OK;
+}
+
+int32_t soma_batch_set_histogram(soma_batch *b, uint32_t mode) {
+  if (!b) return fail(SOMA_E_INVAL, "batch is NULL");
+  if (mode != SOMA_HIST_DIRECT && mode != SOMA_HIST_BINNED)
+    return fail(SOMA_E_INVAL, "histogram mode %u", mode);
+  if (mode == SOMA_HIST_BINNED && !b->bins_ok)
+    return fail(SOMA_E_UNSUPPORTED,
+                "binned count updates need bins in every system and two bead types");
+  b->hist = mode == SOMA_HIST_BINNED ? soma::kHistBinned : soma::kHistDirect;
   return SOMA_OK;
 }
 
@@ -2219,18 +2279,29 @@ int32_t soma_batch_autotune(soma_batch *b, uint32_t cycles, uint32_t move_kind,
   const int32_t rc = batch_check_kind(b, move_kind);
   if (rc) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  static const Shape shapes[] = {{0, 0}, {1, 0}, {0, 2048}, {1, 2048}, {0, 8192}, {1, 8192}};
+  // mode: item order (bit 0) | binned count updates (bit 1)
+  std::vector<Shape> shapes;
+  for (uint32_t h = 0; h < (b->bins_ok ? 2u : 1u); ++h)
+    for (uint32_t g : {0u, 2048u, 8192u})
+      for (uint32_t order : {0u, 1u}) shapes.push_back({order | (h << 1), g});
   char kind_s[16];
   std::snprintf(kind_s, sizeof kind_s, "batch/k%u", move_kind);
   std::string key = kind_s;
   for (soma_system *x : b->sys) key += "/" + system_key(x);
-  return tune(shapes, 6u, cycles, cache_path, key, s,
-              [&](uint32_t mode, uint32_t grid) {
-                b->mode = mode;
-                b->grid_blocks = grid;
-              },
-              [&]() -> int32_t { return soma_batch_cycle(b, 1, move_kind, stream); },
-              out);
+  const int32_t r = tune(shapes.data(), (uint32_t)shapes.size(), cycles, cache_path, key, s,
+                         [&](uint32_t mode, uint32_t grid) {
+                           b->mode = mode & 1u;
+                           b->hist = (mode >> 1) ? soma::kHistBinned : soma::kHistDirect;
+                           b->grid_blocks = grid;
+                         },
+                         [&]() -> int32_t { return soma_batch_cycle(b, 1, move_kind, stream); },
+                         out);
+  if (!r) {
+    out->mode = b->mode;
+    out->hist_mode = b->hist == soma::kHistBinned ? SOMA_HIST_BINNED : SOMA_HIST_DIRECT;
+    out->block_threads = 256u;
+  }
+  return r;
 }
 
 void soma_batch_destroy(soma_batch *b) { delete b; }

@@ -34,7 +34,10 @@ struct BatchLaunch {
   uint32_t sub_k, sub_j;       // chain subset of this launch (see SweepArgs)
 };
 
-template <bool COUNT64, bool VEC2, uint32_t KIND>
+// BINNED: count updates through the melts' own per-brick bins (each segment's
+// SweepArgs carry its melt's BinArgs), applied afterwards by
+// batched_bin_apply_kernel; else direct atomics.
+template <bool COUNT64, bool VEC2, uint32_t KIND, bool BINNED>
 __global__ __launch_bounds__(256, 2) void batched_sweep_kernel(const BatchLaunch L) {
   __shared__ __bf16 s_act[KIND == 2 ? 4 : 1][KIND == 2 ? 64 * kActStride : 1];
   __shared__ float s_z[KIND == 2 ? 4 : 1][KIND == 2 ? 64 * 8 : 1];
@@ -63,11 +66,11 @@ __global__ __launch_bounds__(256, 2) void batched_sweep_kernel(const BatchLaunch
       float *cp = a.pos + (size_t)(m.has0 ? m.chain : 0u) * a.n * 3u + 6u * m.k;
       F3 r0, r1;
       load_pair<VEC2>(cp, m, r0, r1);
-      finish_block(a, local_tile<COUNT64, VEC2, false>(a, m, cp, r0, r1));
+      finish_block(a, local_tile<COUNT64, VEC2, BINNED>(a, m, cp, r0, r1));
     } else if (KIND == 1) {
-      finish_block(a, smc_wave<COUNT64, VEC2, false>(a, m));
+      finish_block(a, smc_wave<COUNT64, VEC2, BINNED>(a, m));
     } else if (KIND == 3) {
-      finish_block(a, smc_wave<COUNT64, VEC2, false, true>(a, m));
+      finish_block(a, smc_wave<COUNT64, VEC2, BINNED, true>(a, m));
     } else {
       const MixArgs mx = L.segs[sg].mx;
       if (sg != net_sg) {   // block-uniform: a new segment's network
@@ -77,11 +80,30 @@ __global__ __launch_bounds__(256, 2) void batched_sweep_kernel(const BatchLaunch
         net_sg = sg;
       }
       uint32_t cnt[3];
-      mixed_wave<COUNT64, VEC2, false>(a, mx, m, s_act[KIND == 2 ? m.wib : 0],
+      mixed_wave<COUNT64, VEC2, BINNED>(a, mx, m, s_act[KIND == 2 ? m.wib : 0],
                                        s_z[KIND == 2 ? m.wib : 0], s_w, cnt);
       mixed_finish(a, mx, cnt);
     }
   }
+}
+
+// The bins of every melt of a batch applied in one launch: one workgroup per
+// brick of every melt (melt s owns the blocks [brick_first[s],
+// brick_first[s + 1])), each the brick workgroup of bin_apply_kernel.
+struct BinApplySeg {
+  BinArgs b;
+  Grid g;
+  void *counts;
+};
+
+template <bool COUNT64>
+__global__ __launch_bounds__(kApplyThreads) void batched_bin_apply_kernel(
+    const BinApplySeg *__restrict__ segs, const uint32_t *__restrict__ brick_first,
+    uint32_t n_sys) {
+  extern __shared__ uint32_t s_cnt[];
+  const uint32_t s = range_of(brick_first, n_sys, blockIdx.x);
+  const BinApplySeg x = segs[s];
+  bin_apply_brick<COUNT64>(x.b, x.g, x.counts, 1u, blockIdx.x - brick_first[s], s_cnt);
 }
 
 }  // namespace soma

@@ -312,12 +312,12 @@ __device__ __forceinline__ void apply_entry_lds(uint32_t *s_cnt, uint32_t planes
   }
 }
 
+// The body of one brick's workgroup (s_cnt: the dynamic LDS of the counts).
 template <bool COUNT64>
-__global__ __launch_bounds__(kApplyThreads) void bin_apply_kernel(BinArgs b, Grid g, void *counts,
-                                                                  uint32_t planes) {
-  extern __shared__ uint32_t s_cnt[];
+__device__ __forceinline__ void bin_apply_brick(const BinArgs &b, const Grid &g, void *counts,
+                                                uint32_t planes, uint32_t brick, uint32_t *s_cnt) {
   __shared__ uint32_t s_fill[kSubBins];
-  const uint32_t brick = blockIdx.x, tid = threadIdx.x;
+  const uint32_t tid = threadIdx.x;
   uint32_t fill = 0u;
   if (tid < kSubBins) fill = b.bin_count[(brick << kSubShift) | tid];
   const uint32_t bx = brick % b.nbx, rest = brick / b.nbx;
@@ -393,6 +393,13 @@ __global__ __launch_bounds__(kApplyThreads) void bin_apply_kernel(BinArgs b, Gri
     }
   }
   if (tid < kSubBins) b.bin_count[(brick << kSubShift) | tid] = 0u;
+}
+
+template <bool COUNT64>
+__global__ __launch_bounds__(kApplyThreads) void bin_apply_kernel(BinArgs b, Grid g, void *counts,
+                                                                  uint32_t planes) {
+  extern __shared__ uint32_t s_cnt[];
+  bin_apply_brick<COUNT64>(b, g, counts, planes, blockIdx.x, s_cnt);
 }
 
 }  // namespace soma

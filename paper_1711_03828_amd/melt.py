@@ -226,6 +226,9 @@ class Batch:
     def set_launch(self, mode: int, grid_blocks: int = 0):
         C.soma_batch_set_launch(self.handle, mode, grid_blocks)
 
+    def set_histogram(self, mode: int):
+        C.soma_batch_set_histogram(self.handle, mode)
+
     def sweep(self, n_sweeps=1, move_kind=C.SOMA_MOVE_LOCAL, stream=None):
         C.soma_batch_sweep(self.handle, n_sweeps, move_kind, _stream(stream))
 

@@ -141,6 +141,7 @@ _SIGS = {
     "soma_batch_workspace_size": ([ctypes.POINTER(_P), _u32, _pu64], _i32),
     "soma_batch_create": ([ctypes.POINTER(_P), _u32, _P, _u64, _P, ctypes.POINTER(_P)], _i32),
     "soma_batch_set_launch": ([_P, _u32, _u32], _i32),
+    "soma_batch_set_histogram": ([_P, _u32], _i32),
     "soma_batch_sweep": ([_P, _u32, _u32, _P], _i32),
     "soma_batch_update_fields": ([_P, _P], _i32),
     "soma_batch_capture_cycle": ([_P, _u32, _u32], _i32),
@@ -374,6 +375,10 @@ def soma_batch_create(handles, ws_ptr: int, ws_bytes: int, stream: int):
 
 def soma_batch_set_launch(b, mode: int, grid_blocks: int) -> None:
     _check(_lib.soma_batch_set_launch(b, mode, grid_blocks))
+
+
+def soma_batch_set_histogram(b, mode: int) -> None:
+    _check(_lib.soma_batch_set_histogram(b, mode))
 
 
 def soma_batch_sweep(b, n_sweeps: int, move_kind: int, stream: int) -> None:

@@ -5,7 +5,7 @@ Bars (all bit-exact -- launch shapes and batching never change results):
     of each melt, position for position;
   * batched cycles (sweep + field refresh, every move kind) equal the same
     cycles of each melt alone: positions, counts, fields, acceptance counters
-    and the FP64 field energy;
+    and the FP64 field energy -- with direct and with binned count updates;
   * replays of a captured graph equal the same cycles called one by one,
     checked after every replay with eager work in between;
   * an autotuned run equals an untuned run of the same number of cycles, and
@@ -115,6 +115,37 @@ def test_batched_cycles_equal_single(kind):
     batch.close()
 
 
+@pytest.mark.parametrize("kind", ["local", "smc", "mixed", "gibbs"])
+def test_batched_binned_cycles_equal_single(kind):
+    """Binned batched sweeps (every melt's own bins, one apply launch for all
+    bricks of the batch) against each melt alone with direct atomics, in two
+    launch shapes (one block per item, and a persistent round-robin grid)."""
+    from paper_1711_03828_amd import soma as C
+    from paper_1711_03828_amd.melt import Batch
+    move = {"local": C.SOMA_MOVE_LOCAL, "smc": C.SOMA_MOVE_SMC, "mixed": C.SOMA_MOVE_MIXED,
+            "gibbs": C.SOMA_MOVE_GIBBS}[kind]
+    reps = _replicas()
+    p_learn = 0.5 if kind == "mixed" else 0.0
+    ma, mb = _melts(reps, p_learn), _melts(reps, p_learn)
+    if kind == "mixed":
+        for mset in (ma, mb):
+            for m in mset:
+                for sp in range(m.cfg.n_species):
+                    params = synth.mlp_params(50 + sp, out_gain=0.1)
+                    m.set_proposal(torch.from_numpy(params).cuda(), species=sp)
+    batch = Batch(ma)
+    batch.set_histogram(C.SOMA_HIST_BINNED)
+    flush("binned batch", kind)
+    for rep_, (mode, grid) in enumerate([(0, 0), (1, 24)]):
+        batch.set_launch(mode, grid)
+        batch.cycle(3, move)
+        for m in mb:
+            m.cycle(3, move)
+        torch.cuda.synchronize()
+        _assert_same(ma, mb, f"binned {kind} shape {mode} {grid}")
+    batch.close()
+
+
 def test_graph_replays_equal_eager_cycles():
     from paper_1711_03828_amd import soma as C
     from paper_1711_03828_amd.melt import Batch, Melt
@@ -167,8 +198,9 @@ def test_autotune_keeps_results(tmp_path):
     batch = Batch(ma)
     tb = batch.autotune(2, C.SOMA_MOVE_LOCAL, cache)
     flush("batch tune", tb.mode, tb.grid_blocks, tb.ms_per_cycle, tb.candidates, tb.cycles_run)
-    # item order {XCD ranges, round-robin} x grid {one block per item, 2048, 8192}
-    assert tb.candidates == 6 and tb.cycles_run == 18
+    # histogram {direct, binned} x item order {XCD ranges, round-robin} x grid
+    # {one block per item, 2048, 8192}
+    assert tb.candidates == 12 and tb.cycles_run == 36
     for m in mb:
         m.cycle(tb.cycles_run)
     batch.cycle(3)
