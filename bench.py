@@ -353,10 +353,11 @@ def _c4_subsystem(side: int):
 def _replica_plan(C, substeps: int, scale: float):
     def n(x):
         return max(20, int(round(x * scale)))
-    # transients of more than 3 tau_int and runs of more than 50 tau_int at the
-    # tau_int these samplers show on this melt (about 1,500, 57,000 and 540 cycles)
-    return {"learned": (C.SOMA_MOVE_MIXED, substeps, 20, n(240), n(3900)),
-            "plain": (C.SOMA_MOVE_LOCAL, 1, 400, n(450), n(7600)),
+    # transients of more than 3 tau_int at the tau_int these samplers show on
+    # this melt (about 1,700, 72,000 and 550 cycles; the plain and learned
+    # estimates still grow with the run length), runs of 40-55 tau_int
+    return {"learned": (C.SOMA_MOVE_MIXED, substeps, 20, n(280), n(3900)),
+            "plain": (C.SOMA_MOVE_LOCAL, 1, 400, n(580), n(7600)),
             "gibbs": (C.SOMA_MOVE_GIBBS, substeps, 10, n(180), n(2900))}
 
 
