@@ -146,6 +146,18 @@ def test_batched_binned_cycles_equal_single(kind):
     batch.close()
 
 
+def test_batch_histogram_refusals():
+    from paper_1711_03828_amd import soma as C
+    from paper_1711_03828_amd.melt import Batch
+    reps = _replicas()[:2]
+    batch = Batch(_melts(reps))
+    with pytest.raises(C.SomaError):
+        batch.set_histogram(7)
+    batch.set_histogram(C.SOMA_HIST_BINNED)
+    batch.set_histogram(C.SOMA_HIST_DIRECT)
+    batch.close()
+
+
 def test_graph_replays_equal_eager_cycles():
     from paper_1711_03828_amd import soma as C
     from paper_1711_03828_amd.melt import Batch, Melt
