@@ -439,6 +439,8 @@ void launch_sweep_p(uint32_t kind, dim3 grid, dim3 threads, hipStream_t s,
     hipLaunchKernelGGL((soma::mc_sweep_smc_kernel<C64, V2, B, P>), grid, threads, 0, s, a);
   else if (kind == SOMA_MOVE_GIBBS)
     hipLaunchKernelGGL((soma::mc_sweep_gibbs_kernel<C64, V2, B, P>), grid, threads, 0, s, a);
+  else if (B && a.stream_pos)   // measured: no gain with direct atomics
+    hipLaunchKernelGGL((soma::mc_sweep_local_kernel<C64, V2, B, P, true>), grid, threads, 0, s, a);
   else
     hipLaunchKernelGGL((soma::mc_sweep_local_kernel<C64, V2, B, P>), grid, threads, 0, s, a);
 }
@@ -563,6 +565,8 @@ void sweep_args(soma_system *sys, uint32_t sp, uint32_t kind, soma::SweepArgs &a
   a.self_term = sys->self_term ? self_energy(sys) : 0.0f;
   a.queue = nullptr;   // set by launch_sweep for persistent local grids
   a.wpb = 4u;          // 256-thread blocks unless launch_sweep picks another size
+  // positions larger than the last-level cache (256 MB) stream past it
+  a.stream_pos = 12ull * sys->d.n_beads > (256ull << 20) ? 1u : 0u;
   mx.net = sys->net(sp);
   mx.head.m_max = c->mu_max;
   mx.head.lo = c->log_sigma_min;
@@ -1766,8 +1770,9 @@ int32_t batch_items(soma_batch *b) {
 
 template <bool C64, bool V2, bool B>
 void launch_batch_k(uint32_t kind, dim3 grid, hipStream_t s, const soma::BatchLaunch &L) {
-  if (kind == SOMA_MOVE_MIXED)
-    hipLaunchKernelGGL((soma::batched_sweep_kernel<C64, V2, 2, B>), grid, dim3(256), 0, s, L);
+  if (kind == SOMA_MOVE_MIXED)   // direct atomics only (see launch_batch_sweep)
+    hipLaunchKernelGGL((soma::batched_sweep_kernel<C64, V2, 2, false>), grid, dim3(256), 0, s,
+                       L);
   else if (kind == SOMA_MOVE_GIBBS)
     hipLaunchKernelGGL((soma::batched_sweep_kernel<C64, V2, 3, B>), grid, dim3(256), 0, s, L);
   else if (kind == SOMA_MOVE_SMC)
@@ -1779,7 +1784,7 @@ void launch_batch_k(uint32_t kind, dim3 grid, hipStream_t s, const soma::BatchLa
 template <bool C64, bool V2>
 void launch_batch_t(bool binned, uint32_t kind, dim3 grid, hipStream_t s,
                     const soma::BatchLaunch &L) {
-  if (binned) launch_batch_k<C64, V2, true>(kind, grid, s, L);
+  if (binned && kind != SOMA_MOVE_MIXED) launch_batch_k<C64, V2, true>(kind, grid, s, L);
   else launch_batch_k<C64, V2, false>(kind, grid, s, L);
 }
 
@@ -1804,7 +1809,9 @@ int32_t launch_batch_sweep(soma_batch *b, uint32_t kind, hipStream_t s, uint32_t
     if (b->grid_blocks && b->grid_blocks < blocks) blocks = b->grid_blocks;
   }
   const dim3 grid(blocks);
-  const bool binned = b->hist == soma::kHistBinned;
+  // mixed sweeps keep direct atomics: their LDS tiles leave no room for the
+  // bin tables at two blocks per compute unit
+  const bool binned = b->hist == soma::kHistBinned && kind != SOMA_MOVE_MIXED;
   if (b->c64) {
     if (b->v2) launch_batch_t<true, true>(binned, kind, grid, s, L);
     else launch_batch_t<true, false>(binned, kind, grid, s, L);

@@ -71,6 +71,10 @@ struct SweepArgs {
   // ceil(2^16 / lanes_per_chain): lane / lanes_per_chain = (lane lpc_magic) >> 16
   // for every lane < 64 (exact while lanes_per_chain < 1024)
   uint32_t lpc_magic;
+  // binned local sweeps read and write positions with the non-temporal hint
+  // (1: melts whose positions outgrow the last-level cache; each is touched
+  // once per sweep, and the hint keeps the field and count lines cached instead)
+  uint32_t stream_pos;
 };
 
 constexpr uint32_t kQueueParts = 8u, kQueueSub = 16u, kQueueStride = 32u;
@@ -190,15 +194,27 @@ __device__ __forceinline__ LaneMap lane_map(const SweepArgs &a) {
   return lane_map_tile(a, tile, true);
 }
 
-template <bool VEC2>
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// NT: the non-temporal hint (a compile-time choice: loads that differ only in
+// the hint would be merged by the compiler, dropping it).
+template <bool VEC2, bool NT = false>
 __device__ __forceinline__ void load_pair(const float *cp, const LaneMap &m, F3 &r0, F3 &r1) {
   r0 = F3{0.f, 0.f, 0.f};
   r1 = F3{0.f, 0.f, 0.f};
   if (VEC2) {
     if (m.has0) {
-      const float2 p0 = reinterpret_cast<const float2 *>(cp)[0];
-      const float2 p1 = reinterpret_cast<const float2 *>(cp)[1];
-      const float2 p2 = reinterpret_cast<const float2 *>(cp)[2];
+      const f32x2 *q = reinterpret_cast<const f32x2 *>(cp);
+      f32x2 p0, p1, p2;
+      if (NT) {
+        p0 = __builtin_nontemporal_load(q);
+        p1 = __builtin_nontemporal_load(q + 1);
+        p2 = __builtin_nontemporal_load(q + 2);
+      } else {
+        p0 = q[0];
+        p1 = q[1];
+        p2 = q[2];
+      }
       r0 = F3{p0.x, p0.y, p1.x};
       r1 = F3{p1.y, p2.x, p2.y};
     }
@@ -208,13 +224,21 @@ __device__ __forceinline__ void load_pair(const float *cp, const LaneMap &m, F3 
   }
 }
 
-template <bool VEC2>
+template <bool VEC2, bool NT = false>
 __device__ __forceinline__ void store_pair(float *cp, const LaneMap &m, F3 r0, F3 r1) {
   if (VEC2) {
     if (m.has0) {
-      reinterpret_cast<float2 *>(cp)[0] = make_float2(r0.x, r0.y);
-      reinterpret_cast<float2 *>(cp)[1] = make_float2(r0.z, r1.x);
-      reinterpret_cast<float2 *>(cp)[2] = make_float2(r1.y, r1.z);
+      f32x2 *q = reinterpret_cast<f32x2 *>(cp);
+      const f32x2 p0 = {r0.x, r0.y}, p1 = {r0.z, r1.x}, p2 = {r1.y, r1.z};
+      if (NT) {
+        __builtin_nontemporal_store(p0, q);
+        __builtin_nontemporal_store(p1, q + 1);
+        __builtin_nontemporal_store(p2, q + 2);
+      } else {
+        q[0] = p0;
+        q[1] = p1;
+        q[2] = p2;
+      }
     }
   } else {
     if (m.has0) { cp[0] = r0.x; cp[1] = r0.y; cp[2] = r0.z; }
@@ -276,7 +300,7 @@ __device__ __forceinline__ uint32_t set_order_bit(const SweepArgs &a, const Lane
 // a trial position is then at most one cell away along each axis.
 // ---------------------------------------------------------------------------
 // One wave's tile of local moves: positions r0/r1 already loaded for lane map m.
-template <bool COUNT64, bool VEC2, bool BINNED>
+template <bool COUNT64, bool VEC2, bool BINNED, bool NT = false>
 __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap &m, float *cp,
                                                F3 r0, F3 r1) {
   const uint32_t N = a.n;
@@ -367,7 +391,7 @@ __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap
     acc_b = has_b && ok_b && (d_e <= 0.0f || uniform01(wb.w) < __expf(-d_e));
     rb = acc_b ? tb : rb;
   }
-  store_pair<VEC2>(cp, m, sel(odd_first, rb, ra), sel(odd_first, ra, rb));
+  store_pair<VEC2, NT>(cp, m, sel(odd_first, rb, ra), sel(odd_first, ra, rb));
   const bool acc0 = odd_first ? acc_b : acc_a, acc1 = odd_first ? acc_a : acc_b;
   if (BINNED) {
     bin_moves<COUNT64>(a.bin, a.grid, a.counts, wave_sub_bin(a.wpb), kf0, kt0, b0 ? 1u : 0u,
@@ -396,7 +420,7 @@ __device__ __forceinline__ uint32_t local_tile(const SweepArgs &a, const LaneMap
 // Registers capped for five waves per SIMD (96 VGPRs, no spills), so that the
 // persistent grid holds enough waves to cover the latency of its gathers and
 // of the bin reservations.
-template <bool COUNT64, bool VEC2, bool BINNED, bool PERSIST = false>
+template <bool COUNT64, bool VEC2, bool BINNED, bool PERSIST = false, bool NT = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5)))
 void mc_sweep_local_kernel(const SweepArgs a_in) {
   const SweepArgs a = resolve_sweep(a_in, 0u);
@@ -404,8 +428,8 @@ void mc_sweep_local_kernel(const SweepArgs a_in) {
     const LaneMap m = lane_map(a);
     float *cp = a.pos + (size_t)(m.has0 ? m.chain : 0u) * a.n * 3u + 6u * m.k;
     F3 r0, r1;
-    load_pair<VEC2>(cp, m, r0, r1);
-    finish_block(a, local_tile<COUNT64, VEC2, BINNED>(a, m, cp, r0, r1));
+    load_pair<VEC2, NT>(cp, m, r0, r1);
+    finish_block(a, local_tile<COUNT64, VEC2, BINNED, NT>(a, m, cp, r0, r1));
     return;
   }
   const TileIter it = tile_iter(a);
@@ -416,8 +440,8 @@ void mc_sweep_local_kernel(const SweepArgs a_in) {
     const LaneMap m = lane_map_tile(a, t, true);
     float *cp = a.pos + (size_t)(m.has0 ? m.chain : 0u) * a.n * 3u + 6u * m.k;
     F3 r0, r1;
-    load_pair<VEC2>(cp, m, r0, r1);
-    n_acc += local_tile<COUNT64, VEC2, BINNED>(a, m, cp, r0, r1);
+    load_pair<VEC2, NT>(cp, m, r0, r1);
+    n_acc += local_tile<COUNT64, VEC2, BINNED, NT>(a, m, cp, r0, r1);
     t = tile_of(it, vn);
   }
   finish_block(a, n_acc);
