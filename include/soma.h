@@ -481,8 +481,8 @@ int32_t soma_batch_set_launch(soma_batch *b, uint32_t mode, uint32_t grid_blocks
 /* Count updates of batched sweeps (Eq. (4), Sec. 3.1.1), as soma_set_histogram
  * for one system: SOMA_HIST_DIRECT (default) or SOMA_HIST_BINNED, where each
  * sweep appends to the bins of every system's own workspace and one more launch
- * applies all of them brick by brick.  Counts, fields and trajectories are the
- * same bits either way.  SOMA_E_UNSUPPORTED for SOMA_HIST_BINNED unless every
+ * applies all of them brick by brick (mixed sweeps of a batch keep direct
+ * atomics).  Counts, fields and trajectories are the same bits either way.  SOMA_E_UNSUPPORTED for SOMA_HIST_BINNED unless every
  * system has bins (see soma_set_histogram) and at most two bead types. */
 int32_t soma_batch_set_histogram(soma_batch *b, uint32_t mode);
 /* n_sweeps sweeps of every system with fields fixed (asynchronous). */
