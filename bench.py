@@ -271,7 +271,9 @@ def learned_leg(p_learn: float, equil_cycles: int, substeps: int, lag: int = 64,
     for name, kind in (("plain", C.SOMA_MOVE_LOCAL), ("learned", C.SOMA_MOVE_MIXED),
                        ("gibbs", C.SOMA_MOVE_GIBBS)):
         melt.set_substeps(ksub[name])
-        t = melt.autotune(2, kind)     # launch shape per sampler (results do not depend on it)
+        # launch shape per sampler (results do not depend on it); 4 cycles per
+        # candidate, as their times lie within a few per cent of each other
+        t = melt.autotune(4, kind)
         tuned[name] = {"hist_mode": "binned" if t.hist_mode else "direct",
                        "block_threads": t.block_threads, "grid_blocks": t.grid_blocks}
         melt.capture_cycle(10, kind)
@@ -289,7 +291,7 @@ def learned_leg(p_learn: float, equil_cycles: int, substeps: int, lag: int = 64,
     # network at r and at r' (2 x 16,640 flop); sweeps with the fields frozen,
     # HIP events on the launch stream
     melt.set_substeps(1)
-    melt.autotune(2, C.SOMA_MOVE_MIXED)
+    melt.autotune(4, C.SOMA_MOVE_MIXED)
     melt.sweep(2, C.SOMA_MOVE_MIXED)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
