@@ -54,6 +54,11 @@ def test_fullsize_histogram_fields_and_sampled_sweep(orc, big, big_fields):
     np.testing.assert_array_equal(melt.counts_planes(), counts)
     np.testing.assert_array_equal(melt.omega.cpu().numpy(), omega)
 
+    # the launch shape the bench's autotuner picks at this size (binned count
+    # updates, 512-thread blocks, one tile per wave; positions streamed with the
+    # non-temporal hint)
+    melt.set_histogram(C.SOMA_HIST_BINNED)
+    C.soma_set_sweep_threads(melt.handle, 512)
     flush("device sweep")
     melt.sweep(1, C.SOMA_MOVE_LOCAL)
     torch.cuda.synchronize()
@@ -92,6 +97,8 @@ def test_fullsize_smc_sweep_sampled(orc, big, big_fields):
     k0, a, A, inv_rho = constants(w)
     _, omega = big_fields
     melt = Melt(device_config(w), positions=torch.from_numpy(pos))
+    melt.set_histogram(C.SOMA_HIST_BINNED)   # as the bench's smart-MC leg
+    C.soma_set_sweep_threads(melt.handle, 512)
     flush("device smart-MC sweep")
     melt.sweep(1, C.SOMA_MOVE_SMC)
     torch.cuda.synchronize()
