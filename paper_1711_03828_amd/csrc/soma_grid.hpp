@@ -160,17 +160,31 @@ __device__ __forceinline__ double hnb_cell(uint32_t na, uint32_t nb,
   return 0.5 * a.kappa_n_d * dev * dev + inter;
 }
 
-template <bool COUNT64>
+// NT: the counts are read with the non-temporal hint (grids whose counts
+// outgrow the caches: the fields written here, which the next sweep gathers,
+// then keep their place in the last-level cache).  A compile-time choice:
+// loads that differ only in the hint would be merged, dropping it.
+template <bool COUNT64, bool NT = false>
 __device__ __forceinline__ void load4(const void *counts, uint32_t q,
                                       uint32_t na[4], uint32_t nb[4]) {
   if (COUNT64) {
-    const ulonglong2 *c = reinterpret_cast<const ulonglong2 *>(counts) + 2 * (size_t)q;
-    const ulonglong2 v0 = c[0], v1 = c[1];
+    typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+    const u64x2 *c = reinterpret_cast<const u64x2 *>(counts) + 2 * (size_t)q;
+    u64x2 v0, v1;
+    if (NT) {
+      v0 = __builtin_nontemporal_load(c);
+      v1 = __builtin_nontemporal_load(c + 1);
+    } else {
+      v0 = c[0];
+      v1 = c[1];
+    }
     const unsigned long long w[4] = {v0.x, v0.y, v1.x, v1.y};
 #pragma unroll
     for (int j = 0; j < 4; ++j) { na[j] = (uint32_t)w[j]; nb[j] = (uint32_t)(w[j] >> 32); }
   } else {
-    const uint4 v = reinterpret_cast<const uint4 *>(counts)[q];
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 *c = reinterpret_cast<const u32x4 *>(counts) + q;
+    const u32x4 v = NT ? __builtin_nontemporal_load(c) : c[0];
     const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int j = 0; j < 4; ++j) { na[j] = w[j] & 0xFFFFu; nb[j] = w[j] >> 16; }
@@ -179,7 +193,7 @@ __device__ __forceinline__ void load4(const void *counts, uint32_t q,
 
 // Block `blk` of the `nblk` blocks that serve one grid: a grid-stride loop
 // over groups of four cells, then the block's partial sums (FP64 H_nb).
-template <bool COUNT64>
+template <bool COUNT64, bool NT = false>
 __device__ __forceinline__ void field_body(const FieldArgs &a, uint32_t blk, uint32_t nblk) {
   __shared__ unsigned long long s_a[4], s_b[4];
   __shared__ double s_h[4];
@@ -194,7 +208,7 @@ __device__ __forceinline__ void field_body(const FieldArgs &a, uint32_t blk, uin
   float4 *ob4 = reinterpret_cast<float4 *>(a.omega + (b_aligned ? a.n_cells : 0u));
   for (uint32_t q = tid; q < n4; q += stride) {
     uint32_t na[4], nb[4];
-    load4<COUNT64>(a.counts, q, na, nb);
+    load4<COUNT64, NT>(a.counts, q, na, nb);
     // the four cells 4q..4q+3 share one mask word
     const uint32_t fb = a.forbid ? (a.forbid[q >> 3] >> ((4u * q) & 31u)) & 0xFu : 0u;
     float va[4], vb[4];
@@ -281,9 +295,9 @@ __device__ __forceinline__ void field_body(const FieldArgs &a, uint32_t blk, uin
   }
 }
 
-template <bool COUNT64>
+template <bool COUNT64, bool NT = false>
 __global__ __launch_bounds__(256) void field_update_kernel(const FieldArgs a) {
-  field_body<COUNT64>(a, blockIdx.x, gridDim.x);
+  field_body<COUNT64, NT>(a, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
